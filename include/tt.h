@@ -1,0 +1,186 @@
+/*
+ * tt.h — C ABI of the additive two-level DMRG hot path on one AMD MI355X (gfx950).
+ *
+ * The library computes, for a Hamiltonian given as a matrix product operator
+ * (eq. MPO, Appendix A) and a tensor-train iterate (Definitions "tensor train
+ * parameter space" and "tensor train contraction mapping", Section 2.1):
+ *   - the two-site effective-Hamiltonian product (the two-site form of
+ *     eq. mat_vec built from the environments eq. env_L / eq. env_R),
+ *   - the local eigenproblems of the two-site micro-iteration
+ *     (eq. MALS_Micro, Lemma "DMRG micro-iterations for eigenvalue problems"),
+ *     run over groups of adjoining sites (Extension Two of Algorithm 2),
+ *   - the coarse-space minimisation (eq. d_optim, eq. d_opt_lin_3/4,
+ *     eq. A_reduced, rank-deficient branch eq. aux_eig_final_sym) and the
+ *     compression back to a left-orthogonal TT (Step 4 of Algorithm 2),
+ *   - one global iteration of Algorithm 2 (two-site branch),
+ *   - the classical two-site sweep (Algorithm 1, two-site branch).
+ *
+ * Conventions
+ *   sites k = 0..L-1, local dimension 4 (|0>,|up>,|dn>,|updn>), bonds 0..L.
+ *   TT core k:  U[a][s][b], row-major, a < r_k, b < r_{k+1}, r_0 = r_L = 1.
+ *   MPO core k: W[A][s_out][s_in][B], given sparsely as nnz entries
+ *               (A, B, op[4][4]) with op row-major [s_out][s_in].
+ *   Environments: E[K][bra][ket] (operator channel outermost).
+ *   Quantum-number labels are (N, 2Sz) int32 pairs.
+ *   Two-site tensor: x[a][s1][s2][b].
+ *
+ * Ownership: host arrays are read during the call and copied; the caller keeps
+ * them.  Device pointers passed to the *_dev entry points are borrowed for the
+ * duration of the call and used on the context's stream (the call returns
+ * after the stream is synchronised).  The context owns all other device memory
+ * (allocated with hipMalloc on the context's device, released by tt_destroy).
+ *
+ * Errors: no exception crosses the ABI.  Return value 0 = success, > 0 =
+ * warning (result usable), < 0 = error; tt_last_error() gives a message.
+ * Sizes and quantum-number structure are validated on the host before any
+ * device work.
+ */
+#ifndef TT_H
+#define TT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_OK 0
+#define TT_WNOCONV 1      /* a local or coarse eigensolve hit its iteration limit */
+#define TT_WRANKDEF 2     /* the coarse overlap matrix was rank-deficient (eps branch) */
+#define TT_EINVAL (-1)    /* shape / quantum-number mismatch, bad argument */
+#define TT_ESTATE (-2)    /* wrong call order */
+#define TT_ENOMEM (-3)    /* device allocation failed */
+#define TT_EHIP (-4)      /* HIP / rocSOLVER runtime error */
+#define TT_EINTERNAL (-5) /* unexpected internal failure */
+
+typedef enum { TT_F64 = 0, TT_F32 = 1, TT_BF16 = 2 } tt_prec;
+
+typedef struct tt_opts {
+  int chi_max;        /* maximal TT rank kept by every truncation */
+  double svd_cutoff;  /* drop singular values below svd_cutoff * s_max (1e-12) */
+  double tie_rel;     /* tie group |s_i - s_chi| <= tie_rel * s_max dropped if it straddles the cut */
+  double dav_tol;     /* residual 2-norm tolerance of the local eigensolver (unit Ritz vector) */
+  int dav_maxiter;    /* matvec limit per local eigensolve */
+  int dav_maxsub;     /* subspace size before a restart */
+  double coarse_eps;  /* keep overlap eigenvalues >= coarse_eps * max (rank-deficient branch) */
+  int matvec_prec;    /* tt_prec of the effective-Hamiltonian product */
+  int refine_fp64;    /* 1: after a low-precision solve, continue with FP64 products to dav_tol */
+  double lowprec_tol; /* residual tolerance of the low-precision phase before FP64 refinement */
+  int device;         /* HIP device ordinal */
+} tt_opts;
+
+#define TT_MAX_SUB 64
+
+typedef struct tt_sweep_report {
+  int nsub;
+  double E_before;                 /* <U|H|U> of the input iterate */
+  double E_local[TT_MAX_SUB];      /* last Ritz value of each subdomain sweep */
+  int matvecs[TT_MAX_SUB];         /* effective-Hamiltonian products per subdomain */
+  double S[(TT_MAX_SUB + 1) * (TT_MAX_SUB + 1)]; /* coarse overlap, row-major (nsub+1)^2 */
+  double A[(TT_MAX_SUB + 1) * (TT_MAX_SUB + 1)]; /* coarse Hamiltonian, row-major */
+  double coef[TT_MAX_SUB + 1];     /* coarse coefficients, c^T S c = 1 */
+  double lambda;                   /* lowest coarse eigenvalue */
+  int rankS;                       /* numerical rank of S */
+  double E_after;                  /* <U|H|U> of the compressed next iterate */
+  double discarded;                /* total discarded weight of Step 4 */
+  double seconds[4];               /* wall time of Steps 1..4 */
+  double flops_heff;               /* dense-bond flops of all effective-Hamiltonian products */
+  double seconds_heff;             /* device time of those products (HIP events) */
+} tt_sweep_report;
+
+void tt_default_opts(tt_opts* o);
+int tt_create(const tt_opts* opts, void** ctx_out);
+void tt_destroy(void* ctx);
+const char* tt_last_error(const void* ctx);
+
+/* Operator A as an MPO (eq. MPO).  R[0..L] bond dimensions with R[0] = R[L] = 1;
+ * per site k: nnz[k] entries A[k][e], B[k][e], ops[k][16*e..]; chan_q[k] holds
+ * R[k] (dN, d2Sz) pairs (charge of the left operator of each channel).
+ * block[4*k..4*k+3] = (p0, p1, q0, q1) marks an optional coefficient block of
+ * site k: every entry with A in [p0,p1) and B in [q0,q1) must have an
+ * identity local operator (times a coefficient); such blocks are applied as
+ * dense channel transforms of the environments.  Use -1 for none. */
+int tt_set_mpo(void* ctx, int L, const int* R, const int* nnz, const int32_t* const* A, const int32_t* const* B,
+               const double* const* ops, const int32_t* const* chan_q, const int* block);
+
+/* TT iterate (Definition "tensor train parameter space").  r[0..L], cores
+ * U[k] host [r_k][4][r_{k+1}], labels q[k] host int32 [r_k][2].  Every core
+ * must respect the labels (q(a) + q(s) = q(b)); the library brings the TT to
+ * left-orthogonal form (sector-wise QR on the device) and normalises it. */
+int tt_set_mps(void* ctx, int L, const int* r, const double* const* U, const int32_t* const* q);
+
+/* Copy the current (left-orthogonal) iterate out.  If U is NULL only r[0..L] is
+ * written; otherwise U[k] and q[k] must have room for the sizes in r. */
+int tt_get_mps(void* ctx, int* r, double* const* U, int32_t* const* q);
+
+/* <U|H|U> / <U|U> of the current iterate. */
+int tt_energy(void* ctx, double* E);
+
+/* Steps 1-2 of Algorithm 2: LQ sweep with saved orthogonal copies and
+ * environment caches, then the local solves of nsub subdomains of lengths[]
+ * sites (sum = L); subdomain j sweeps its bonds left to right, the last one
+ * stopping at bond (L-2, L-1). */
+int tt_local_solve(void* ctx, int nsub, const int* lengths, double* E_local, int* matvecs);
+
+/* Steps 3-4: coarse matrices over {current, subdomain updates}, coarse
+ * eigenpair, compression of the combination to chi_max; the result becomes
+ * the current iterate.  S_out/A_out are row-major (nsub+1)^2. */
+int tt_coarse_correct(void* ctx, double* S_out, double* A_out, double* coef_out, double* lambda_out,
+                      double* E_out, int* rankS_out);
+
+/* One global iteration of Algorithm 2 (Steps 1-4). */
+int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out);
+
+/* nsweeps full sweeps of classical two-site DMRG (Algorithm 1); energies[2*nsweeps]
+ * receive the last Ritz value of every half sweep. */
+int tt_dmrg2(void* ctx, int nsweeps, double* energies);
+
+/* Kernel-level entry points (device pointers, borrowed).
+ * Two-site product y = H_eff x with left environment Lenv[RA][rl][rl],
+ * right environment Renv[RC][rr][rr], MPO cores W1 (RA -> RB) and W2 (RB -> RC)
+ * given sparsely on the host, x, y [rl][4][4][rr].  Element type by prec:
+ * TT_F64 double, TT_F32 float, TT_BF16 uint16 bfloat16 for Lenv/Renv/x with
+ * float y.  rl and rr must be multiples of 32. */
+int tt_heff_apply_dev(void* ctx, int prec, int rl, int rr, int RA, int RB, int RC, const void* Lenv,
+                      const void* Renv, int nnz1, const int32_t* A1, const int32_t* B1, const double* ops1, int nnz2,
+                      const int32_t* A2, const int32_t* B2, const double* ops2, const void* x, void* y);
+
+/* One environment update (double precision).  side 0: left update
+ * out[B][rb2][rk2] = sum E[A][rb][rk] Ubra[rb][4][rb2] W[A,s',s,B] Uket[rk][4][rk2];
+ * side 1: right update out[A][rb][rk] = sum Ubra[rb][4][rb2] W Uket[rk][4][rk2] E[B][rb2][rk2].
+ * RA/RB are the channel counts at the left/right bond of the site.  All bond
+ * dimensions must be multiples of 32. */
+int tt_env_update_dev(void* ctx, int side, int rb, int rk, int rb2, int rk2, int RA, int RB, const double* E,
+                      const double* Ubra, const double* Uket, int nnz, const int32_t* A, const int32_t* B,
+                      const double* ops, double* out);
+
+/* Strided batched GEMM on MFMA (the building block of every contraction
+ * above), C[b] = alpha * op(A[b]) op(B[b]) + beta * C[b] with
+ * A(m,k) = A + b*sAb + m*sAm + (k/kin)*sAkb + (k%kin)*sAkk,
+ * B(k,n) = B + b*sBb + (k/kin)*sBkb + (k%kin)*sBkk + n*sBn,
+ * C(m,n) = C + b*sCb + m*sCm + n (element strides).  a_kcontig: sAkk == 1
+ * (else sAm == 1); b_ncontig: sBn == 1 (else sBkk == 1).  kin must be a
+ * multiple of 16 (32 for TT_BF16, which reads uint16 bfloat16 A/B and writes
+ * float C).  strides[10] = {sAb,sAm,sAkb,sAkk, sBb,sBkb,sBkk,sBn, sCb,sCm, ...}. */
+int tt_gemm_dev(void* ctx, int prec, int M, int N, int K, int batch, int kin, const long long* strides, int a_kcontig,
+                int b_ncontig, double alpha, double beta, const void* A, const void* B, void* C);
+
+/* Energy E = <x|H_eff|x> (FP64) and its gradients with respect to x, the two
+ * environments and the two MPO cores (dense gradient of each sparse entry's
+ * 4x4 operator).  Shapes as in tt_heff_apply_dev; gx [rl][4][4][rr],
+ * gL [RA][rl][rl], gR [RC][rr][rr] device; gops1/gops2 host [nnz][16]. */
+int tt_heff_energy_grad_dev(void* ctx, int rl, int rr, int RA, int RB, int RC, const double* Lenv,
+                            const double* Renv, int nnz1, const int32_t* A1, const int32_t* B1, const double* ops1,
+                            int nnz2, const int32_t* A2, const int32_t* B2, const double* ops2, const double* x,
+                            double* E, double* gx, double* gL, double* gR, double* gops1, double* gops2);
+
+/* Gradient of E = <U|H|U> (current normalised iterate, fixed) with respect to
+ * every entry of every MPO core: gops[k] host [nnz_k][16].  Environments are
+ * recomputed, not stored, outside the active chain. */
+int tt_energy_mpo_grad(void* ctx, double* E, double* const* gops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_H */

@@ -79,10 +79,21 @@ def heff_grads(Lenv, W1, W2, Renv, x):
     W1T = W1.transpose(0, 2, 1, 3)
     W2T = W2.transpose(0, 2, 1, 3)
     gx = y + heff_apply(LT, W1T, W2T, RT, x)
-    gL = np.einsum("puvq,AuwB,BvtC,qCb,awtb->pAa", x, W1, W2, Renv, x, optimize=True)
-    gR = np.einsum("puvq,pAa,AuwB,BvtC,awtb->qCb", x, Lenv, W1, W2, x, optimize=True)
-    gW1 = np.einsum("puvq,pAa,BvtC,qCb,awtb->AuwB", x, Lenv, W2, Renv, x, optimize=True)
-    gW2 = np.einsum("puvq,pAa,AuwB,qCb,awtb->BvtC", x, Lenv, W1, Renv, x, optimize=True)
+    # every gradient is the contraction with one operand removed, taken in
+    # pairwise steps
+    Rx = np.einsum("qCb,awtb->qCawt", Renv, x)
+    W2Rx = np.einsum("BvtC,qCawt->qBvaw", W2, Rx)
+    W1W2Rx = np.einsum("AuwB,qBvaw->qAuva", W1, W2Rx)
+    gL = np.einsum("puvq,qAuva->pAa", x, W1W2Rx)
+    Lx = np.einsum("pAa,awtb->pAwtb", Lenv, x)
+    W1Lx = np.einsum("AuwB,pAwtb->puBtb", W1, Lx)
+    W2W1Lx = np.einsum("BvtC,puBtb->puvCb", W2, W1Lx)
+    gR = np.einsum("puvq,puvCb->qCb", x, W2W1Lx)
+    W2R = np.einsum("BvtC,qCb->Bvtqb", W2, Renv)
+    xW2R = np.einsum("puvq,Bvtqb->puBtb", x, W2R)
+    gW1 = np.einsum("puBtb,pAwtb->AuwB", xW2R, Lx)
+    xR = np.einsum("puvq,qCb->puvCb", x, Renv)
+    gW2 = np.einsum("puvCb,puBtb->BvtC", xR, W1Lx)
     return E, gx, gL, gW1, gW2, gR
 
 

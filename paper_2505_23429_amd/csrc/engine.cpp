@@ -1,0 +1,1896 @@
+// Host orchestration of the additive two-level DMRG hot path on one GPU.
+// All tensor arithmetic runs in the kernels of kernels.hip or in rocSOLVER on
+// the device; the host only takes decisions on small data (Rayleigh-Ritz
+// matrices of the local solver, singular values for truncation, the coarse
+// (P+1)x(P+1) pencil).
+#include "engine.h"
+
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+
+namespace tt {
+
+#define HC(x)                                                                                       \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x); \
+  } while (0)
+#define RC(x)                                                                                      \
+  do {                                                                                             \
+    rocblas_status s_ = (x);                                                                       \
+    if (s_ != rocblas_status_success)                                                              \
+      throw std::runtime_error(std::string("rocSOLVER/rocBLAS status ") + std::to_string((int)s_) + " at " #x); \
+  } while (0)
+
+static const Q2 SITE_Q[4] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};
+static inline Q2 qadd(Q2 a, Q2 b) { return {a[0] + b[0], a[1] + b[1]}; }
+static inline Q2 qsub(Q2 a, Q2 b) { return {a[0] - b[0], a[1] - b[1]}; }
+
+// ---------------------------------------------------------------------------
+// memory helpers
+// ---------------------------------------------------------------------------
+void DevMem::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  n = 0;
+}
+void DevMem::ensure(size_t bytes) {
+  if (bytes <= n) return;
+  release();
+  if (bytes == 0) return;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  n = bytes;
+}
+void DevMem::resize_zero(size_t bytes, hipStream_t s) {
+  if (bytes != n) {
+    release();
+    if (bytes) {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        p = nullptr;
+        throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+      }
+      n = bytes;
+    }
+  }
+  if (bytes) fill(p, bytes, s);
+}
+void upload(DevMem& m, const void* h, size_t bytes, hipStream_t s) {
+  m.ensure(bytes);
+  if (bytes) HC(hipMemcpyAsync(m.p, h, bytes, hipMemcpyHostToDevice, s));
+  HC(hipStreamSynchronize(s));
+}
+void download(void* h, const DevMem& m, size_t bytes, hipStream_t s) {
+  if (bytes) HC(hipMemcpyAsync(h, m.p, bytes, hipMemcpyDeviceToHost, s));
+  HC(hipStreamSynchronize(s));
+}
+static void d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
+  if (bytes) HC(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+  HC(hipStreamSynchronize(s));
+}
+static DevMem upload_ints(const std::vector<int>& v, hipStream_t s) {
+  DevMem m;
+  upload(m, v.data(), v.size() * sizeof(int), s);
+  return m;
+}
+static DevMem upload_dbl(const std::vector<double>& v, hipStream_t s) {
+  DevMem m;
+  upload(m, v.data(), v.size() * sizeof(double), s);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// small dense symmetric eigensolver (cyclic Jacobi), host FP64
+// ---------------------------------------------------------------------------
+static void jacobi_eig(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (i != j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+      }
+    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[(size_t)p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        double theta = (aqq - app) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = c * akp - s * akq;
+          A[(size_t)k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = c * apk - s * aqk;
+          A[(size_t)q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - s * vkq;
+          V[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  // sort ascending
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[(size_t)a * n + a] < A[(size_t)b * n + b]; });
+  w.resize(n);
+  std::vector<double> V2((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = A[(size_t)idx[j] * n + idx[j]];
+    for (int k = 0; k < n; ++k) V2[(size_t)k * n + j] = V[(size_t)k * n + idx[j]];
+  }
+  V.swap(V2);
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+Engine::Engine(const tt_opts& o) : opts(o) {
+  HC(hipSetDevice(o.device));
+  HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  RC(rocblas_create_handle(&blas));
+  RC(rocblas_set_stream(blas, stream));
+  HC(hipEventCreate(&ev0));
+  HC(hipEventCreate(&ev1));
+}
+Engine::~Engine() {
+  if (blas) rocblas_destroy_handle(blas);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+void Engine::free_caches() {
+  Vc.clear();
+  Wc.clear();
+  Lenv.clear();
+  Renv.clear();
+  subs.clear();
+  have_local = false;
+}
+
+void Engine::build_siteop(SiteOp& so, int nout, const std::vector<int>& out_idx, const std::vector<int>& in_idx,
+                          const std::vector<double>& ops, hipStream_t s) {
+  const int nnz = (int)out_idx.size();
+  std::vector<int> order(nnz);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return out_idx[a] < out_idx[b]; });
+  std::vector<int> ptr(nout + 1, 0), src(std::max(nnz, 1), 0);
+  std::vector<double> op64((size_t)std::max(nnz, 1) * 16, 0.0);
+  std::vector<float> op32((size_t)std::max(nnz, 1) * 16, 0.f);
+  for (int e = 0; e < nnz; ++e) {
+    if (out_idx[e] < 0 || out_idx[e] >= nout) throw std::runtime_error("MPO entry channel out of range");
+    ptr[out_idx[e] + 1]++;
+  }
+  for (int c = 0; c < nout; ++c) ptr[c + 1] += ptr[c];
+  for (int k = 0; k < nnz; ++k) {
+    int e = order[k];
+    src[k] = in_idx[e];
+    for (int j = 0; j < 16; ++j) {
+      op64[(size_t)k * 16 + j] = ops[(size_t)e * 16 + j];
+      op32[(size_t)k * 16 + j] = (float)ops[(size_t)e * 16 + j];
+    }
+  }
+  so.nout = nout;
+  so.nnz = nnz;
+  upload(so.ptr, ptr.data(), ptr.size() * sizeof(int), s);
+  upload(so.src, src.data(), src.size() * sizeof(int), s);
+  upload(so.op64, op64.data(), op64.size() * sizeof(double), s);
+  upload(so.op32, op32.data(), op32.size() * sizeof(float), s);
+}
+
+void Engine::set_mpo(int L_, const int* R, const int* nnz, const int32_t* const* A, const int32_t* const* B,
+                     const double* const* ops, const int32_t* const* cq, const int* block) {
+  if (L_ < 2) throw std::invalid_argument("L must be >= 2");
+  if (R[0] != 1 || R[L_] != 1) throw std::invalid_argument("MPO boundary bond dimensions must be 1");
+  for (int k = 0; k <= L_; ++k)
+    if (R[k] <= 0) throw std::invalid_argument("MPO bond dimension must be positive");
+  std::vector<SiteMPO> m(L_);
+  std::vector<Labels> q(L_ + 1);
+  for (int k = 0; k <= L_; ++k) {
+    q[k].resize(R[k]);
+    for (int c = 0; c < R[k]; ++c) q[k][c] = {cq[k][2 * c], cq[k][2 * c + 1]};
+  }
+  for (int k = 0; k < L_; ++k) {
+    SiteMPO& s = m[k];
+    s.Rl = R[k];
+    s.Rr = R[k + 1];
+    s.A.assign(A[k], A[k] + nnz[k]);
+    s.B.assign(B[k], B[k] + nnz[k]);
+    s.ops.assign(ops[k], ops[k] + (size_t)nnz[k] * 16);
+    for (int e = 0; e < nnz[k]; ++e) {
+      if (s.A[e] < 0 || s.A[e] >= s.Rl || s.B[e] < 0 || s.B[e] >= s.Rr)
+        throw std::invalid_argument("MPO entry index out of range at site " + std::to_string(k));
+      // charge conservation: q(A) + q(s') - q(s) == q(B) for every nonzero op element
+      for (int sp = 0; sp < 4; ++sp)
+        for (int sn = 0; sn < 4; ++sn)
+          if (s.ops[(size_t)e * 16 + sp * 4 + sn] != 0.0) {
+            Q2 lhs = qsub(qadd(q[k][s.A[e]], SITE_Q[sp]), SITE_Q[sn]);
+            if (lhs != q[k + 1][s.B[e]])
+              throw std::invalid_argument("MPO entry violates channel charges at site " + std::to_string(k));
+          }
+    }
+    int p0 = block ? block[4 * k] : -1, p1 = block ? block[4 * k + 1] : -1;
+    int q0 = block ? block[4 * k + 2] : -1, q1 = block ? block[4 * k + 3] : -1;
+    std::vector<int> rA, rB, nA, nB, vA, vB, xA, xB;
+    std::vector<double> rO, nO, vO, xO;
+    if (p0 >= 0 && p1 > p0 && q0 >= 0 && q1 > q0) {
+      if (p1 > s.Rl || q1 > s.Rr) throw std::invalid_argument("coefficient block out of range");
+      s.has_block = true;
+      s.p0 = p0; s.p1 = p1; s.q0 = q0; s.q1 = q1;
+      const int nP = p1 - p0, nQ = q1 - q0;
+      std::vector<double> Vh((size_t)nQ * nP, 0.0);
+      for (int e = 0; e < nnz[k]; ++e) {
+        const double* o = &s.ops[(size_t)e * 16];
+        bool in_blk = s.A[e] >= p0 && s.A[e] < p1 && s.B[e] >= q0 && s.B[e] < q1;
+        if (in_blk) {
+          double c = o[0];
+          for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+              if (std::fabs(o[i * 4 + j] - (i == j ? c : 0.0)) > 1e-15 * std::max(1.0, std::fabs(c)))
+                throw std::invalid_argument("coefficient block entry without identity local operator");
+          Vh[(size_t)(s.B[e] - q0) * nP + (s.A[e] - p0)] += c;
+        } else {
+          nA.push_back(s.A[e]); nB.push_back(s.B[e]);
+          nO.insert(nO.end(), o, o + 16);
+        }
+      }
+      upload(s.V, Vh.data(), Vh.size() * sizeof(double), stream);
+      static const double Id[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+      // left use: output q gathers from virtual input Rl + (q - q0)
+      vA = nA; vB = nB; vO = nO;
+      for (int qq = q0; qq < q1; ++qq) {
+        vA.push_back(s.Rl + (qq - q0)); vB.push_back(qq);
+        vO.insert(vO.end(), Id, Id + 16);
+      }
+      build_siteop(s.byB_left, s.Rr, vB, vA, vO, stream);
+      build_siteop(s.byB_noblk, s.Rr, nB, nA, nO, stream);
+      // right use: output p (left bond) gathers from virtual input Rr + (p - p0)
+      xA = nA; xB = nB; xO = nO;
+      for (int pp = p0; pp < p1; ++pp) {
+        xA.push_back(pp); xB.push_back(s.Rr + (pp - p0));
+        xO.insert(xO.end(), Id, Id + 16);
+      }
+      build_siteop(s.byA_right, s.Rl, xA, xB, xO, stream);
+    }
+    build_siteop(s.byB, s.Rr, s.B, s.A, s.ops, stream);
+    build_siteop(s.byA, s.Rl, s.A, s.B, s.ops, stream);
+  }
+  mpo = std::move(m);
+  chan_q = std::move(q);
+  Rb.assign(R, R + L_ + 1);
+  if (have_mps && L != L_) have_mps = false;
+  L = L_;
+  have_mpo = true;
+  free_caches();
+}
+
+// ---------------------------------------------------------------------------
+// effective Hamiltonian product (K1)
+//   T1[A][a'][s1 s2 b] = L_A x               batched MFMA GEMM
+//   T2[B][a'][s1'][s2 b] = W1 mix over s1    sparse, memory bound
+//   T3[C][a' s1'][s2'][b] = W2 mix over s2
+//   y[(a' s1' s2')][b'] = sum_C T3[C] R_C^T  MFMA GEMM with K = (C, b)
+// ---------------------------------------------------------------------------
+template <class T>
+static const T* siteop_ops(const SiteOp& so);
+template <>
+const double* siteop_ops<double>(const SiteOp& so) { return so.op64.as<double>(); }
+template <>
+const float* siteop_ops<float>(const SiteOp& so) { return so.op32.as<float>(); }
+
+template <class T>
+void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
+                  const T* Rv, const T* x, T* y, const T* Rtil, int P0, int nP) {
+  const long long slab = (long long)rl * 16 * rr;
+  ws0.ensure(sizeof(T) * slab * std::max(RA, RC));
+  ws1.ensure(sizeof(T) * slab * RB);
+  T* T1 = ws0.as<T>();
+  T* T2 = ws1.as<T>();
+  GemmArgs g{};
+  g.M = rl; g.N = 16 * rr; g.K = rl; g.batch = RA; g.kin = rl;
+  g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkb = 0; g.sAkk = 1;
+  g.sBb = 0; g.sBkb = 0; g.sBkk = 16LL * rr; g.sBn = 1;
+  g.sCb = slab; g.sCm = 16LL * rr; g.alpha = 1.0; g.beta = 0.0;
+  gemm<T>(g, Lv, x, T1, true, true, stream);
+  mix<T>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), siteop_ops<T>(w1), T1, slab, T2, slab, rl, 4 * rr, stream);
+  T* T3 = ws0.as<T>();
+  mix<T>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), siteop_ops<T>(w2), T2, slab, T3, slab, 4 * rl, rr, stream);
+  GemmArgs h{};
+  h.M = 16 * rl; h.N = rr; h.K = RC * rr; h.batch = 1; h.kin = rr;
+  h.sAb = 0; h.sAm = rr; h.sAkb = slab; h.sAkk = 1;
+  h.sBb = 0; h.sBkb = (long long)rr * rr; h.sBkk = 1; h.sBn = rr;
+  h.sCb = 0; h.sCm = rr; h.alpha = 1.0; h.beta = 0.0;
+  gemm<T>(h, T3, Rv, y, true, false, stream);
+  if (Rtil && nP > 0) {
+    h.K = nP * rr;
+    h.beta = 1.0;
+    gemm<T>(h, T2 + (long long)P0 * slab, Rtil, y, true, false, stream);
+  }
+}
+template void Engine::heff<double>(int, int, int, const double*, const SiteOp&, int, const SiteOp&, int, const double*,
+                                   const double*, double*, const double*, int, int);
+template void Engine::heff<float>(int, int, int, const float*, const SiteOp&, int, const SiteOp&, int, const float*,
+                                  const float*, float*, const float*, int, int);
+
+// BF16 operands, FP32 accumulation and FP32 intermediates.  The second mix writes
+// FP32; T3 is rounded to BF16 for the last GEMM.
+__global__ void round_bf16_kernel(const float* a, uint16_t* b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t u = __float_as_uint(a[i]);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    b[i] = (uint16_t)(u >> 16);
+  }
+}
+static void round_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 1u << 20);
+  hipLaunchKernelGGL(round_bf16_kernel, dim3(nb), dim3(256), 0, s, a, b, n);
+  HC(hipGetLastError());
+}
+
+void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
+                       const uint16_t* Rv, const uint16_t* x, float* y, const uint16_t* Rtil, int P0, int nP) {
+  const long long slab = (long long)rl * 16 * rr;
+  ws0.ensure(sizeof(float) * slab * std::max(RA, RC));
+  ws1.ensure(sizeof(float) * slab * RB);
+  float* T1 = ws0.as<float>();
+  float* T2 = ws1.as<float>();
+  GemmArgs g{};
+  g.M = rl; g.N = 16 * rr; g.K = rl; g.batch = RA; g.kin = rl;
+  g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkb = 0; g.sAkk = 1;
+  g.sBb = 0; g.sBkb = 0; g.sBkk = 16LL * rr; g.sBn = 1;
+  g.sCb = slab; g.sCm = 16LL * rr; g.alpha = 1.0; g.beta = 0.0;
+  gemm_bf16(g, Lv, x, T1, true, true, stream);
+  mix<float>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), w1.op32.as<float>(), T1, slab, T2, slab, rl, 4 * rr, stream);
+  float* T3 = ws0.as<float>();
+  mix<float>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), w2.op32.as<float>(), T2, slab, T3, slab, 4 * rl, rr, stream);
+  ws2.ensure(sizeof(uint16_t) * slab * std::max(RC, nP));
+  uint16_t* T3b = ws2.as<uint16_t>();
+  round_bf16(T3, T3b, (size_t)slab * RC, stream);
+  GemmArgs h{};
+  h.M = 16 * rl; h.N = rr; h.K = RC * rr; h.batch = 1; h.kin = rr;
+  h.sAb = 0; h.sAm = rr; h.sAkb = slab; h.sAkk = 1;
+  h.sBb = 0; h.sBkb = (long long)rr * rr; h.sBkk = 1; h.sBn = rr;
+  h.sCb = 0; h.sCm = rr; h.alpha = 1.0; h.beta = 0.0;
+  gemm_bf16(h, T3b, Rv, y, true, false, stream);
+  if (Rtil && nP > 0) {
+    round_bf16(T2 + (long long)P0 * slab, T3b, (size_t)slab * nP, stream);
+    h.K = nP * rr;
+    h.beta = 1.0;
+    gemm_bf16(h, T3b, Rtil, y, true, false, stream);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// environment updates (K2 / K3), FP64, padded dims
+// ---------------------------------------------------------------------------
+void Engine::env_left_raw(int rb, int rk, int rb2, int rk2, int RA, const double* E, const double* Ubra,
+                          const double* Uket, const SiteOp& w, int RB, double* out) {
+  const long long sl = (long long)rb * 4 * rk2;
+  ws2.ensure(sizeof(double) * sl * RA);
+  ws3.ensure(sizeof(double) * sl * RB);
+  double* T = ws2.as<double>();
+  double* Tp = ws3.as<double>();
+  GemmArgs g{};
+  g.M = rb; g.N = 4 * rk2; g.K = rk; g.batch = RA; g.kin = rk;
+  g.sAb = (long long)rb * rk; g.sAm = rk; g.sAkb = 0; g.sAkk = 1;
+  g.sBb = 0; g.sBkb = 0; g.sBkk = 4LL * rk2; g.sBn = 1;
+  g.sCb = sl; g.sCm = 4LL * rk2; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, E, Uket, T, true, true, stream);
+  mix<double>(w.nout, w.ptr.as<int>(), w.src.as<int>(), w.op64.as<double>(), T, sl, Tp, sl, rb, rk2, stream);
+  GemmArgs h{};
+  h.M = rb2; h.N = rk2; h.K = 4 * rb; h.batch = RB; h.kin = 4 * rb;
+  h.sAb = 0; h.sAm = 1; h.sAkb = 0; h.sAkk = rb2;
+  h.sBb = sl; h.sBkb = 0; h.sBkk = rk2; h.sBn = 1;
+  h.sCb = (long long)rb2 * rk2; h.sCm = rk2; h.alpha = 1.0; h.beta = 0.0;
+  gemm<double>(h, Ubra, Tp, out, false, true, stream);
+}
+
+void Engine::env_right_raw(int rb, int rk, int rb2, int rk2, int RB, const double* E, const double* Ubra,
+                           const double* Uket, const SiteOp& w, int RA, double* out) {
+  const long long sl = (long long)rk * 4 * rb2;
+  ws2.ensure(sizeof(double) * sl * RB);
+  ws3.ensure(sizeof(double) * sl * RA);
+  double* T = ws2.as<double>();
+  double* Tp = ws3.as<double>();
+  GemmArgs g{};
+  g.M = 4 * rk; g.N = rb2; g.K = rk2; g.batch = RB; g.kin = rk2;
+  g.sAb = 0; g.sAm = rk2; g.sAkb = 0; g.sAkk = 1;
+  g.sBb = (long long)rb2 * rk2; g.sBkb = 0; g.sBkk = 1; g.sBn = rk2;
+  g.sCb = sl; g.sCm = rb2; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, Uket, E, T, true, false, stream);
+  mix<double>(w.nout, w.ptr.as<int>(), w.src.as<int>(), w.op64.as<double>(), T, sl, Tp, sl, rk, rb2, stream);
+  GemmArgs h{};
+  h.M = rb; h.N = rk; h.K = 4 * rb2; h.batch = RA; h.kin = 4 * rb2;
+  h.sAb = 0; h.sAm = 4LL * rb2; h.sAkb = 0; h.sAkk = 1;
+  h.sBb = sl; h.sBkb = 0; h.sBkk = 1; h.sBn = 4LL * rb2;
+  h.sCb = (long long)rb * rk; h.sCm = rk; h.alpha = 1.0; h.beta = 0.0;
+  gemm<double>(h, Ubra, Tp, out, true, false, stream);
+}
+
+static inline int kin16(int K) { return ((K + 15) / 16) * 16; }
+
+// channel transform: out[q][:] = sum_p V[q][p] in[p][:]  (transpose=false)
+//                    out[p][:] = sum_q V[q][p] in[q][:]  (transpose=true)
+static void channel_transform(const double* V, int nQ, int nP, const double* in, long long slab, double* out,
+                              bool transpose, hipStream_t s) {
+  GemmArgs g{};
+  g.batch = 1; g.N = (int)slab; g.alpha = 1.0; g.beta = 0.0;
+  g.sBb = 0; g.sBkb = 0; g.sBkk = slab; g.sBn = 1; g.sCb = 0; g.sCm = slab;
+  if (!transpose) {
+    g.M = nQ; g.K = nP; g.kin = kin16(nP);
+    g.sAb = 0; g.sAm = nP; g.sAkb = 0; g.sAkk = 1;
+    gemm<double>(g, V, in, out, true, true, s);
+  } else {
+    g.M = nP; g.K = nQ; g.kin = kin16(nQ);
+    g.sAb = 0; g.sAm = 1; g.sAkb = 0; g.sAkk = nP;
+    gemm<double>(g, V, in, out, false, true, s);
+  }
+}
+
+void Engine::env_unit(Env& e, int R) {
+  e.R = R;
+  e.rb = 1;
+  e.rk = 1;
+  e.d.resize_zero(sizeof(double) * e.elems(), stream);
+  double one = 1.0;
+  HC(hipMemcpyAsync(e.d.p, &one, sizeof(double), hipMemcpyHostToDevice, stream));
+  HC(hipStreamSynchronize(stream));
+}
+
+void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site, Env& out) {
+  const SiteMPO& s = mpo[site];
+  if (in.R != s.Rl || in.rb != bra.rl || in.rk != ket.rl) throw std::runtime_error("env_left: shape mismatch");
+  const int rb = padr(in.rb), rk = padr(in.rk), rb2 = bra.rrp(), rk2 = ket.rrp();
+  Env o;
+  o.R = s.Rr; o.rb = bra.rr; o.rk = ket.rr;
+  o.d.ensure(sizeof(double) * o.elems());
+  if (s.has_block) {
+    const long long slab = (long long)rb * rk;
+    const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
+    wsd.ensure(sizeof(double) * slab * (s.Rl + nQ));
+    HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rl, hipMemcpyDeviceToDevice, stream));
+    channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.p0 * slab, slab,
+                      wsd.as<double>() + (long long)s.Rl * slab, false, stream);
+    env_left_raw(rb, rk, rb2, rk2, s.Rl + nQ, wsd.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byB_left,
+                 s.Rr, o.d.as<double>());
+  } else {
+    env_left_raw(rb, rk, rb2, rk2, s.Rl, in.d.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byB, s.Rr,
+                 o.d.as<double>());
+  }
+  out = std::move(o);
+}
+
+void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site, Env& out) {
+  const SiteMPO& s = mpo[site];
+  if (in.R != s.Rr || in.rb != bra.rr || in.rk != ket.rr) throw std::runtime_error("env_right: shape mismatch");
+  const int rb = bra.rlp(), rk = ket.rlp(), rb2 = padr(in.rb), rk2 = padr(in.rk);
+  Env o;
+  o.R = s.Rl; o.rb = bra.rl; o.rk = ket.rl;
+  o.d.ensure(sizeof(double) * o.elems());
+  if (s.has_block) {
+    const long long slab = (long long)rb2 * rk2;
+    const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
+    wsd.ensure(sizeof(double) * slab * (s.Rr + nP));
+    HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rr, hipMemcpyDeviceToDevice, stream));
+    channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.q0 * slab, slab,
+                      wsd.as<double>() + (long long)s.Rr * slab, true, stream);
+    env_right_raw(rb, rk, rb2, rk2, s.Rr + nP, wsd.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byA_right,
+                  s.Rl, o.d.as<double>());
+  } else {
+    env_right_raw(rb, rk, rb2, rk2, s.Rr, in.d.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byA, s.Rl,
+                  o.d.as<double>());
+  }
+  out = std::move(o);
+}
+
+double Engine::env_close(const Env& Lb, const Env& Rb_) {
+  if (Lb.R != Rb_.R || Lb.rb != Rb_.rb || Lb.rk != Rb_.rk) throw std::runtime_error("env_close: shape mismatch");
+  const size_t n = Lb.elems();
+  wsp.ensure(sizeof(double) * (256 + 8));
+  const int nblk = 128;
+  DevMem part;
+  part.ensure(sizeof(double) * nblk);
+  multi_dot(Lb.d.as<double>(), n, 1, Rb_.d.as<double>(), n, wsp.as<double>(), part.as<double>(), nblk, stream);
+  double v = 0.0;
+  d2h(&v, wsp.p, sizeof(double), stream);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// sector-wise linear algebra (rocSOLVER per charge block)
+// ---------------------------------------------------------------------------
+struct Sector {
+  Q2 g;
+  std::vector<int> rows, cols;
+};
+
+static std::vector<Sector> make_sectors(const std::vector<int>& rows, const Labels& rq, const std::vector<int>& cols,
+                                        const Labels& cq) {
+  std::map<Q2, Sector> m;
+  for (size_t i = 0; i < rows.size(); ++i) {
+    auto& s = m[rq[i]];
+    s.g = rq[i];
+    s.rows.push_back(rows[i]);
+  }
+  std::map<Q2, std::vector<int>> cm;
+  for (size_t j = 0; j < cols.size(); ++j) cm[cq[j]].push_back(cols[j]);
+  std::vector<Sector> out;
+  for (auto& kv : m) {
+    auto it = cm.find(kv.first);
+    if (it == cm.end()) continue;
+    kv.second.cols = it->second;
+    out.push_back(kv.second);
+  }
+  return out;
+}
+
+static int truncation_keep(const std::vector<double>& sv, int chi, double cutoff, double tau) {
+  if (sv.empty() || sv[0] <= 0.0) return 0;
+  const double smax = sv[0];
+  int n = 0;
+  for (double s : sv)
+    if (s >= cutoff * smax) ++n;
+  if (n <= chi) return n;
+  const double ref = sv[chi - 1];
+  int gmin = -1, gmax = -1;
+  for (int i = 0; i < n; ++i)
+    if (std::fabs(sv[i] - ref) <= tau * smax) {
+      if (gmin < 0) gmin = i;
+      gmax = i;
+    }
+  if (gmin >= 0 && gmin < chi && gmax >= chi) return gmin;
+  return chi;
+}
+
+struct SvdOut {
+  int k = 0;
+  Labels q;
+  double discarded = 0.0;
+  std::vector<double> s;
+};
+
+// Truncated SVD of the matrix M (device, element (r,c) at M[r*ldm + c]) restricted
+// to the listed rows/cols, block-diagonal by charge.  Writes the left factor
+// into left[r*ldl + j] and the right factor into right[j*ldr + c] (both
+// pre-zeroed by the caller after the first pass, see two-phase use below).
+// mode 0: right factor carries the singular values; mode 1: left factor.
+class SectorSVD {
+ public:
+  SectorSVD(Engine& e) : E(e) {}
+  SvdOut run(const double* M, long long ldm, const std::vector<int>& rows, const Labels& rq,
+             const std::vector<int>& cols, const Labels& cq, int chi, bool truncate) {
+    secs = make_sectors(rows, rq, cols, cq);
+    blocks.clear();
+    blocks.resize(secs.size());
+    struct Trip {
+      double s;
+      Q2 g;
+      int sec, i;
+    };
+    std::vector<Trip> trip;
+    DevMem info, E_;
+    info.ensure(sizeof(int));
+    for (size_t t = 0; t < secs.size(); ++t) {
+      Sector& sc = secs[t];
+      const int m = (int)sc.rows.size(), n = (int)sc.cols.size(), k = std::min(m, n);
+      Blk& b = blocks[t];
+      b.m = m; b.n = n; b.k = k;
+      DevMem Ablk, rdev, cdev;
+      Ablk.ensure(sizeof(double) * m * n);
+      rdev = upload_ints(sc.rows, E.stream);
+      cdev = upload_ints(sc.cols, E.stream);
+      gather2d(M, ldm, rdev.as<int>(), m, cdev.as<int>(), n, Ablk.as<double>(), true, E.stream);
+      b.U.ensure(sizeof(double) * m * k);
+      b.Vt.ensure(sizeof(double) * k * n);
+      b.S.ensure(sizeof(double) * k);
+      E_.ensure(sizeof(double) * std::max(k, 1));
+      RC(rocsolver_dgesvd(E.blas, rocblas_svect_singular, rocblas_svect_singular, m, n, Ablk.as<double>(), m,
+                          b.S.as<double>(), b.U.as<double>(), m, b.Vt.as<double>(), k, E_.as<double>(),
+                          rocblas_outofplace, info.as<int>()));
+      int inf = 0;
+      d2h(&inf, info.p, sizeof(int), E.stream);
+      if (inf != 0) throw std::runtime_error("gesvd did not converge");
+      b.hs.resize(k);
+      d2h(b.hs.data(), b.S.p, sizeof(double) * k, E.stream);
+      for (int i = 0; i < k; ++i) trip.push_back({b.hs[i], sc.g, (int)t, i});
+    }
+    std::sort(trip.begin(), trip.end(), [](const Trip& a, const Trip& b) {
+      if (a.s != b.s) return a.s > b.s;
+      if (a.g != b.g) return a.g < b.g;
+      return a.i < b.i;
+    });
+    std::vector<double> all(trip.size());
+    for (size_t i = 0; i < trip.size(); ++i) all[i] = trip[i].s;
+    int keep = truncate ? truncation_keep(all, chi, E.opts.svd_cutoff, E.opts.tie_rel) : (int)all.size();
+    if (!truncate) {
+      // still drop exact zeros
+      keep = 0;
+      for (double s : all)
+        if (s > 0.0) ++keep;
+    }
+    SvdOut out;
+    for (size_t i = keep; i < all.size(); ++i) out.discarded += all[i] * all[i];
+    std::vector<int> cnt(secs.size(), 0);
+    for (int i = 0; i < keep; ++i) cnt[trip[i].sec]++;
+    // new bond order: sectors in charge order (make_sectors returns sorted), then decreasing s
+    int off = 0;
+    for (size_t t = 0; t < secs.size(); ++t) {
+      blocks[t].t = cnt[t];
+      blocks[t].off = off;
+      for (int i = 0; i < cnt[t]; ++i) {
+        out.q.push_back(secs[t].g);
+        out.s.push_back(blocks[t].hs[i]);
+      }
+      off += cnt[t];
+    }
+    out.k = off;
+    return out;
+  }
+  // scatter the kept factors (destination arrays must be zero initialised)
+  void scatter(double* left, long long ldl, double* right, long long ldr, int mode) {
+    for (size_t t = 0; t < secs.size(); ++t) {
+      Blk& b = blocks[t];
+      if (b.t == 0) continue;
+      std::vector<int> newidx(b.t);
+      std::iota(newidx.begin(), newidx.end(), b.off);
+      DevMem rdev = upload_ints(secs[t].rows, E.stream);
+      DevMem cdev = upload_ints(secs[t].cols, E.stream);
+      DevMem ndev = upload_ints(newidx, E.stream);
+      // left: (row i of block, new j) <- U[j*m + i]
+      scatter2d(b.U.as<double>(), 1, b.m, rdev.as<int>(), b.m, ndev.as<int>(), b.t, left, ldl, 1.0, nullptr,
+                mode == 1 ? b.S.as<double>() : nullptr, 0, E.stream);
+      // right: (new j, col c) <- Vt[c*k + j]
+      scatter2d(b.Vt.as<double>(), 1, b.k, ndev.as<int>(), b.t, cdev.as<int>(), b.n, right, ldr, 1.0,
+                mode == 0 ? b.S.as<double>() : nullptr, nullptr, 0, E.stream);
+    }
+    HC(hipStreamSynchronize(E.stream));
+  }
+
+ private:
+  Engine& E;
+  struct Blk {
+    int m = 0, n = 0, k = 0, t = 0, off = 0;
+    DevMem U, Vt, S;
+    std::vector<double> hs;
+  };
+  std::vector<Sector> secs;
+  std::vector<Blk> blocks;
+};
+
+// QR of core A viewed as [(a s)][b]; A <- Q (left-orthogonal), next <- R next.
+static void qr_left(Engine& E, Core& A, Core& next) {
+  const int rlp = A.rlp(), rrp = A.rrp();
+  std::vector<int> rows, cols;
+  Labels rq, cq;
+  for (int a = 0; a < A.rl; ++a)
+    for (int s = 0; s < 4; ++s) {
+      rows.push_back(a * 4 + s);
+      rq.push_back(qadd(A.ql[a], SITE_Q[s]));
+    }
+  for (int b = 0; b < A.rr; ++b) {
+    cols.push_back(b);
+    cq.push_back(A.qr[b]);
+  }
+  // every column must belong to a sector with at least as many rows
+  auto secs = make_sectors(rows, rq, cols, cq);
+  size_t ncov = 0;
+  for (auto& s : secs) {
+    if (s.rows.size() < s.cols.size()) throw std::runtime_error("rank-deficient QN block in QR");
+    ncov += s.cols.size();
+  }
+  if (ncov != cols.size()) throw std::runtime_error("TT core has a bond state with no compatible rows");
+  DevMem Qd, Rm;
+  Qd.resize_zero(sizeof(double) * (size_t)rlp * 4 * rrp, E.stream);
+  Rm.resize_zero(sizeof(double) * (size_t)rrp * rrp, E.stream);
+  DevMem info, tau;
+  info.ensure(sizeof(int));
+  for (auto& sc : secs) {
+    const int m = (int)sc.rows.size(), n = (int)sc.cols.size();
+    DevMem blk, rdev = upload_ints(sc.rows, E.stream), cdev = upload_ints(sc.cols, E.stream);
+    blk.ensure(sizeof(double) * m * n);
+    tau.ensure(sizeof(double) * n);
+    gather2d(A.d.as<double>(), rrp, rdev.as<int>(), m, cdev.as<int>(), n, blk.as<double>(), true, E.stream);
+    RC(rocsolver_dgeqrf(E.blas, m, n, blk.as<double>(), m, tau.as<double>()));
+    // R (upper n x n) -> Rm[cols][cols]
+    scatter2d(blk.as<double>(), 1, m, cdev.as<int>(), n, cdev.as<int>(), n, Rm.as<double>(), rrp, 1.0, nullptr,
+              nullptr, 1, E.stream);
+    RC(rocsolver_dorgqr(E.blas, m, n, n, blk.as<double>(), m, tau.as<double>()));
+    scatter2d(blk.as<double>(), 1, m, rdev.as<int>(), m, cdev.as<int>(), n, Qd.as<double>(), rrp, 1.0, nullptr,
+              nullptr, 0, E.stream);
+    HC(hipStreamSynchronize(E.stream));
+  }
+  A.d = std::move(Qd);
+  // next <- Rm * next : [rrp][rrp] x [rrp][4*nrp]
+  const int nrp = next.rrp();
+  DevMem nd;
+  nd.ensure(sizeof(double) * (size_t)rrp * 4 * nrp);
+  GemmArgs g{};
+  g.M = rrp; g.N = 4 * nrp; g.K = rrp; g.batch = 1; g.kin = rrp;
+  g.sAm = rrp; g.sAkk = 1; g.sBkk = 4LL * nrp; g.sBn = 1; g.sCm = 4LL * nrp; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, Rm.as<double>(), next.d.as<double>(), nd.as<double>(), true, true, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+  next.d = std::move(nd);
+}
+
+// LQ of core W viewed as [a][(s b)]: W <- Q (right-orthogonal, possibly smaller
+// left bond), prev <- prev Lmat.  Returns the new left labels.
+static void lq_right(Engine& E, Core& W, Core& prev) {
+  const int rlp = W.rlp(), rrp = W.rrp();
+  std::vector<int> rows, cols;
+  Labels rq, cq;
+  for (int a = 0; a < W.rl; ++a) {
+    rows.push_back(a);
+    rq.push_back(W.ql[a]);
+  }
+  for (int s = 0; s < 4; ++s)
+    for (int b = 0; b < W.rr; ++b) {
+      cols.push_back(s * rrp + b);
+      cq.push_back(qsub(W.qr[b], SITE_Q[s]));
+    }
+  auto secs = make_sectors(rows, rq, cols, cq);
+  // new left bond: k_g = min(m_g, n_g) per sector, in charge order
+  int knew = 0;
+  Labels qn;
+  std::vector<int> offs;
+  for (auto& sc : secs) {
+    int k = (int)std::min(sc.rows.size(), sc.cols.size());
+    offs.push_back(knew);
+    for (int i = 0; i < k; ++i) qn.push_back(sc.g);
+    knew += k;
+  }
+  const int kp = padr(knew);
+  DevMem Qd, Lm;
+  Qd.resize_zero(sizeof(double) * (size_t)kp * 4 * rrp, E.stream);
+  Lm.resize_zero(sizeof(double) * (size_t)rlp * kp, E.stream);
+  DevMem tau;
+  for (size_t t = 0; t < secs.size(); ++t) {
+    auto& sc = secs[t];
+    const int m = (int)sc.rows.size(), n = (int)sc.cols.size(), k = std::min(m, n);
+    DevMem blk, rdev = upload_ints(sc.rows, E.stream), cdev = upload_ints(sc.cols, E.stream);
+    std::vector<int> nidx(k);
+    std::iota(nidx.begin(), nidx.end(), offs[t]);
+    DevMem ndev = upload_ints(nidx, E.stream);
+    blk.ensure(sizeof(double) * m * n);
+    tau.ensure(sizeof(double) * k);
+    gather2d(W.d.as<double>(), 4LL * rrp, rdev.as<int>(), m, cdev.as<int>(), n, blk.as<double>(), true, E.stream);
+    RC(rocsolver_dgelqf(E.blas, m, n, blk.as<double>(), m, tau.as<double>()));
+    // L: lower trapezoid m x k -> Lm[rows][new]
+    scatter2d(blk.as<double>(), 1, m, rdev.as<int>(), m, ndev.as<int>(), k, Lm.as<double>(), kp, 1.0, nullptr,
+              nullptr, 2, E.stream);
+    RC(rocsolver_dorglq(E.blas, k, n, k, blk.as<double>(), m, tau.as<double>()));
+    // Q: k x n (leading k rows of the m x n array, ld m) -> Qd[new][cols]
+    scatter2d(blk.as<double>(), 1, m, ndev.as<int>(), k, cdev.as<int>(), n, Qd.as<double>(), 4LL * rrp, 1.0,
+              nullptr, nullptr, 0, E.stream);
+    HC(hipStreamSynchronize(E.stream));
+  }
+  W.d = std::move(Qd);
+  W.rl = knew;
+  W.ql = qn;
+  // prev [prlp][4][rlp] x Lm [rlp][kp] -> [prlp][4][kp]
+  const int prlp = prev.rlp();
+  DevMem nd;
+  nd.ensure(sizeof(double) * (size_t)prlp * 4 * kp);
+  GemmArgs g{};
+  g.M = prlp * 4; g.N = kp; g.K = rlp; g.batch = 1; g.kin = rlp;
+  g.sAm = rlp; g.sAkk = 1; g.sBkk = kp; g.sBn = 1; g.sCm = kp; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, prev.d.as<double>(), Lm.as<double>(), nd.as<double>(), true, true, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+  prev.d = std::move(nd);
+  prev.rr = knew;
+  prev.qr = qn;
+}
+
+// two-site tensor x[a][s1][s2][b] = sum_k C[a][s1][k] D[k][s2][b]
+static void two_site(Engine& E, const Core& C, const Core& D, DevMem& x) {
+  const int rlp = C.rlp(), kp = C.rrp(), rrp = D.rrp();
+  if (C.rr != D.rl) throw std::runtime_error("two_site: bond mismatch");
+  x.ensure(sizeof(double) * (size_t)rlp * 16 * rrp);
+  GemmArgs g{};
+  g.M = 4 * rlp; g.N = 4 * rrp; g.K = kp; g.batch = 1; g.kin = kp;
+  g.sAm = kp; g.sAkk = 1; g.sBkk = 4LL * rrp; g.sBn = 1; g.sCm = 4LL * rrp; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, C.d.as<double>(), D.d.as<double>(), x.as<double>(), true, true, E.stream);
+}
+
+// split x (padded [rlp][4][4][rrp]) by the truncated block SVD into (N, C) with
+// labels; left_normal: N left-orthogonal, C = S V^T; else N = U S, C = V^T.
+static double split_two_site(Engine& E, const double* x, int rl, const Labels& ql, int rr, const Labels& qr, int chi,
+                             bool left_normal, Core& N, Core& C) {
+  const int rlp = padr(rl), rrp = padr(rr);
+  std::vector<int> rows, cols;
+  Labels rq, cq;
+  for (int a = 0; a < rl; ++a)
+    for (int s = 0; s < 4; ++s) {
+      rows.push_back(a * 4 + s);
+      rq.push_back(qadd(ql[a], SITE_Q[s]));
+    }
+  for (int s = 0; s < 4; ++s)
+    for (int b = 0; b < rr; ++b) {
+      cols.push_back(s * rrp + b);
+      cq.push_back(qsub(qr[b], SITE_Q[s]));
+    }
+  SectorSVD svd(E);
+  SvdOut o = svd.run(x, 4LL * rrp, rows, rq, cols, cq, chi, true);
+  const int k = o.k, kp = padr(std::max(k, 1));
+  N.rl = rl; N.ql = ql; N.rr = k; N.qr = o.q;
+  C.rl = k; C.ql = o.q; C.rr = rr; C.qr = qr;
+  N.d.resize_zero(sizeof(double) * (size_t)rlp * 4 * kp, E.stream);
+  C.d.resize_zero(sizeof(double) * (size_t)kp * 4 * rrp, E.stream);
+  svd.scatter(N.d.as<double>(), kp, C.d.as<double>(), 4LL * rrp, left_normal ? 0 : 1);
+  return o.discarded;
+}
+
+static double norm_dev(Engine& E, const double* x, size_t n) {
+  DevMem out, part;
+  out.ensure(sizeof(double));
+  part.ensure(sizeof(double) * 128);
+  multi_dot(x, n, 1, x, n, out.as<double>(), part.as<double>(), 128, E.stream);
+  double v;
+  d2h(&v, out.p, sizeof(double), E.stream);
+  return std::sqrt(std::max(v, 0.0));
+}
+
+// ---------------------------------------------------------------------------
+// MPS handling
+// ---------------------------------------------------------------------------
+void Engine::set_mps(int L_, const int* r, const double* const* Uh, const int32_t* const* q) {
+  if (!have_mpo) throw std::logic_error("set the MPO before the TT iterate");
+  if (L_ != L) throw std::invalid_argument("TT length differs from the MPO length");
+  if (r[0] != 1 || r[L] != 1) throw std::invalid_argument("TT boundary ranks must be 1");
+  std::vector<Labels> lab(L + 1);
+  for (int k = 0; k <= L; ++k) {
+    if (r[k] <= 0) throw std::invalid_argument("TT rank must be positive");
+    lab[k].resize(r[k]);
+    for (int a = 0; a < r[k]; ++a) lab[k][a] = {q[k][2 * a], q[k][2 * a + 1]};
+  }
+  if (lab[0][0] != Q2{0, 0}) throw std::invalid_argument("left boundary label must be (0,0)");
+  std::vector<Core> cores(L);
+  for (int k = 0; k < L; ++k) {
+    Core& c = cores[k];
+    c.rl = r[k]; c.rr = r[k + 1]; c.ql = lab[k]; c.qr = lab[k + 1];
+    const int rlp = c.rlp(), rrp = c.rrp();
+    std::vector<double> h((size_t)rlp * 4 * rrp, 0.0);
+    for (int a = 0; a < c.rl; ++a)
+      for (int s = 0; s < 4; ++s)
+        for (int b = 0; b < c.rr; ++b) {
+          double v = Uh[k][((size_t)a * 4 + s) * c.rr + b];
+          if (v != 0.0 && qadd(c.ql[a], SITE_Q[s]) != c.qr[b])
+            throw std::invalid_argument("TT core " + std::to_string(k) + " violates its quantum-number labels");
+          h[((size_t)a * 4 + s) * rrp + b] = v;
+        }
+    upload(c.d, h.data(), h.size() * sizeof(double), stream);
+  }
+  for (int k = 0; k + 1 < L; ++k) qr_left(*this, cores[k], cores[k + 1]);
+  double nrm = norm_dev(*this, cores[L - 1].d.as<double>(), cores[L - 1].elems());
+  if (!(nrm > 0.0)) throw std::invalid_argument("TT iterate has zero norm");
+  scale(cores[L - 1].d.as<double>(), 1.0 / nrm, cores[L - 1].elems(), stream);
+  HC(hipStreamSynchronize(stream));
+  U = std::move(cores);
+  have_mps = true;
+  free_caches();
+}
+
+void Engine::get_mps(int* r, double* const* Uh, int32_t* const* q) {
+  if (!have_mps) throw std::logic_error("no TT iterate");
+  r[0] = U[0].rl;
+  for (int k = 0; k < L; ++k) r[k + 1] = U[k].rr;
+  if (!Uh) return;
+  for (int k = 0; k < L; ++k) {
+    const Core& c = U[k];
+    std::vector<double> h(c.elems());
+    download(h.data(), c.d, h.size() * sizeof(double), stream);
+    const int rrp = c.rrp();
+    for (int a = 0; a < c.rl; ++a)
+      for (int s = 0; s < 4; ++s)
+        for (int b = 0; b < c.rr; ++b) Uh[k][((size_t)a * 4 + s) * c.rr + b] = h[((size_t)a * 4 + s) * rrp + b];
+  }
+  if (q)
+    for (int k = 0; k <= L; ++k) {
+      const Labels& lab = k < L ? U[k].ql : U[L - 1].qr;
+      for (size_t a = 0; a < lab.size(); ++a) {
+        q[k][2 * a] = lab[a][0];
+        q[k][2 * a + 1] = lab[a][1];
+      }
+    }
+}
+
+double Engine::energy() {
+  if (!have_mps || !have_mpo) throw std::logic_error("energy needs MPO and TT");
+  Env e;
+  env_unit(e, 1);
+  for (int k = 0; k < L; ++k) {
+    Env o;
+    env_left(e, U[k], U[k], k, o);
+    e = std::move(o);
+  }
+  double v;
+  d2h(&v, e.d.p, sizeof(double), stream);
+  double n = norm_dev(*this, U[L - 1].d.as<double>(), U[L - 1].elems());
+  return v / (n * n);
+}
+
+// ---------------------------------------------------------------------------
+// local eigensolver (Davidson with FP64 Rayleigh-Ritz on the host)
+// ---------------------------------------------------------------------------
+struct Window {
+  int rl = 0, rr = 0, rlp = 0, rrp = 0;
+  int RA = 0, RAx = 0, RB = 0, RC = 0;
+  const SiteOp* w1 = nullptr;
+  const SiteOp* w2 = nullptr;
+  DevMem Lx;            // FP64 left env incl. virtual channels [RAx][rlp][rlp]
+  const double* R64 = nullptr;
+  DevMem Rt;            // FP64 transformed right env [nP][rrp][rrp]
+  int P0 = 0, nP = 0;
+  int prec = 0;
+  DevMem L32, R32, Rt32;  // low-precision copies
+  double flops = 0.0;
+};
+
+static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env& Re, int prec) {
+  const SiteMPO& s1 = E.mpo[b];
+  const SiteMPO& s2 = E.mpo[b + 1];
+  w.rl = Le.rb; w.rr = Re.rb;
+  w.rlp = padr(w.rl); w.rrp = padr(w.rr);
+  w.RA = s1.Rl; w.RB = s1.Rr; w.RC = s2.Rr;
+  const long long sl = (long long)w.rlp * w.rlp, sr = (long long)w.rrp * w.rrp;
+  if (s1.has_block) {
+    const int nQ = s1.q1 - s1.q0;
+    w.RAx = w.RA + nQ;
+    w.Lx.ensure(sizeof(double) * sl * w.RAx);
+    HC(hipMemcpyAsync(w.Lx.p, Le.d.p, sizeof(double) * sl * w.RA, hipMemcpyDeviceToDevice, E.stream));
+    channel_transform(s1.V.as<double>(), nQ, s1.p1 - s1.p0, Le.d.as<double>() + (long long)s1.p0 * sl, sl,
+                      w.Lx.as<double>() + (long long)w.RA * sl, false, E.stream);
+    w.w1 = &s1.byB_left;
+  } else {
+    w.RAx = w.RA;
+    w.Lx.ensure(sizeof(double) * sl * w.RA);
+    HC(hipMemcpyAsync(w.Lx.p, Le.d.p, sizeof(double) * sl * w.RA, hipMemcpyDeviceToDevice, E.stream));
+    w.w1 = &s1.byB;
+  }
+  w.R64 = Re.d.as<double>();
+  if (s2.has_block) {
+    w.P0 = s2.p0;
+    w.nP = s2.p1 - s2.p0;
+    w.Rt.ensure(sizeof(double) * sr * w.nP);
+    channel_transform(s2.V.as<double>(), s2.q1 - s2.q0, w.nP, Re.d.as<double>() + (long long)s2.q0 * sr, sr,
+                      w.Rt.as<double>(), true, E.stream);
+    w.w2 = &s2.byB_noblk;
+  } else {
+    w.nP = 0;
+    w.w2 = &s2.byB;
+  }
+  w.prec = prec;
+  if (prec == TT_F32) {
+    w.L32.ensure(sizeof(float) * sl * w.RAx);
+    convert_f64_f32(w.Lx.as<double>(), w.L32.as<float>(), sl * w.RAx, E.stream);
+    w.R32.ensure(sizeof(float) * sr * w.RC);
+    convert_f64_f32(w.R64, w.R32.as<float>(), sr * w.RC, E.stream);
+    if (w.nP) {
+      w.Rt32.ensure(sizeof(float) * sr * w.nP);
+      convert_f64_f32(w.Rt.as<double>(), w.Rt32.as<float>(), sr * w.nP, E.stream);
+    }
+  } else if (prec == TT_BF16) {
+    w.L32.ensure(sizeof(uint16_t) * sl * w.RAx);
+    convert_f64_bf16(w.Lx.as<double>(), w.L32.as<uint16_t>(), sl * w.RAx, E.stream);
+    w.R32.ensure(sizeof(uint16_t) * sr * w.RC);
+    convert_f64_bf16(w.R64, w.R32.as<uint16_t>(), sr * w.RC, E.stream);
+    if (w.nP) {
+      w.Rt32.ensure(sizeof(uint16_t) * sr * w.nP);
+      convert_f64_bf16(w.Rt.as<double>(), w.Rt32.as<uint16_t>(), sr * w.nP, E.stream);
+    }
+  }
+  // dense-bond algorithmic flops of one product (true sizes, no virtual channels)
+  w.flops = 2.0 * 16.0 * w.rl * w.rr * ((double)w.RA * w.rl + (double)w.RC * w.rr);
+  HC(hipStreamSynchronize(E.stream));
+}
+
+static void window_matvec(Engine& E, Window& w, const double* x, double* y, int prec) {
+  const size_t n = (size_t)w.rlp * 16 * w.rrp;
+  HC(hipEventRecord(E.ev0, E.stream));
+  if (prec == TT_F64) {
+    E.heff<double>(w.rlp, w.rrp, w.RAx, w.Lx.as<double>(), *w.w1, w.RB, *w.w2, w.RC, w.R64, x, y,
+                   w.nP ? w.Rt.as<double>() : nullptr, w.P0, w.nP);
+  } else if (prec == TT_F32) {
+    E.wlow_x.ensure(sizeof(float) * n);
+    E.wlow_y.ensure(sizeof(float) * n);
+    convert_f64_f32(x, E.wlow_x.as<float>(), n, E.stream);
+    E.heff<float>(w.rlp, w.rrp, w.RAx, w.L32.as<float>(), *w.w1, w.RB, *w.w2, w.RC, w.R32.as<float>(),
+                  E.wlow_x.as<float>(), E.wlow_y.as<float>(), w.nP ? w.Rt32.as<float>() : nullptr, w.P0, w.nP);
+    convert_f32_f64(E.wlow_y.as<float>(), y, n, E.stream);
+  } else {
+    E.wlow_x.ensure(sizeof(uint16_t) * n);
+    E.wlow_y.ensure(sizeof(float) * n);
+    convert_f64_bf16(x, E.wlow_x.as<uint16_t>(), n, E.stream);
+    E.heff_bf16(w.rlp, w.rrp, w.RAx, w.L32.as<uint16_t>(), *w.w1, w.RB, *w.w2, w.RC, w.R32.as<uint16_t>(),
+                E.wlow_x.as<uint16_t>(), E.wlow_y.as<float>(), w.nP ? w.Rt32.as<uint16_t>() : nullptr, w.P0, w.nP);
+    convert_f32_f64(E.wlow_y.as<float>(), y, n, E.stream);
+  }
+  HC(hipEventRecord(E.ev1, E.stream));
+  HC(hipEventSynchronize(E.ev1));
+  float ms = 0.f;
+  HC(hipEventElapsedTime(&ms, E.ev0, E.ev1));
+  E.sec_heff += ms * 1e-3;
+  E.flops_heff += w.flops;
+}
+
+static DevMem build_mask(Engine& E, int rl, const Labels& ql, int rr, const Labels& qr) {
+  const int rlp = padr(rl), rrp = padr(rr);
+  std::vector<uint8_t> m((size_t)rlp * 16 * rrp, 0);
+  for (int a = 0; a < rl; ++a)
+    for (int s1 = 0; s1 < 4; ++s1)
+      for (int s2 = 0; s2 < 4; ++s2) {
+        Q2 q = qadd(qadd(ql[a], SITE_Q[s1]), SITE_Q[s2]);
+        for (int b = 0; b < rr; ++b)
+          if (qr[b] == q) m[(((size_t)a * 4 + s1) * 4 + s2) * rrp + b] = 1;
+      }
+  DevMem d;
+  upload(d, m.data(), m.size(), E.stream);
+  return d;
+}
+
+// Davidson for the lowest eigenpair of the window operator restricted to the
+// QN-allowed entries.  x is the warm start on entry and the eigenvector on exit.
+static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, int prec, double tol, int maxiter) {
+  Davidson res;
+  const size_t n = (size_t)w.rlp * 16 * w.rrp;
+  const int maxsub = std::max(4, std::min(E.opts.dav_maxsub, 64));
+  E.dav_V.ensure(sizeof(double) * n * maxsub);
+  E.dav_AV.ensure(sizeof(double) * n * maxsub);
+  E.dav_t.ensure(sizeof(double) * n);
+  E.dav_u.ensure(sizeof(double) * n);
+  E.dav_Au.ensure(sizeof(double) * n);
+  E.dav_c.ensure(sizeof(double) * 2 * maxsub);
+  const int nblk = 256;
+  E.wsp.ensure(sizeof(double) * (size_t)nblk * maxsub);
+  double* V = E.dav_V.as<double>();
+  double* AV = E.dav_AV.as<double>();
+  double* t = E.dav_t.as<double>();
+  double* u = E.dav_u.as<double>();
+  double* Au = E.dav_Au.as<double>();
+  double* cdev = E.dav_c.as<double>();
+  double* part = E.wsp.as<double>();
+  auto dots = [&](const double* Vb, int m, const double* vec, std::vector<double>& out) {
+    multi_dot(Vb, n, m, vec, n, cdev, part, nblk, E.stream);
+    out.resize(m);
+    d2h(out.data(), cdev, sizeof(double) * m, E.stream);
+  };
+  auto lcomb = [&](const double* Vb, int m, const std::vector<double>& c, double* out) {
+    HC(hipMemcpyAsync(cdev, c.data(), sizeof(double) * m, hipMemcpyHostToDevice, E.stream));
+    lincomb(Vb, n, m, cdev, out, n, E.stream);
+  };
+  // start vector
+  mask_apply(x, mask.as<uint8_t>(), n, E.stream);
+  double nx = norm_dev(E, x, n);
+  if (!(nx > 0.0)) {
+    // fall back to a deterministic QN-allowed start: all allowed entries equal
+    std::vector<uint8_t> hm(n);
+    d2h(hm.data(), mask.p, n, E.stream);
+    std::vector<double> h(n);
+    for (size_t i = 0; i < n; ++i) h[i] = hm[i] ? 1.0 : 0.0;
+    HC(hipMemcpyAsync(x, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, E.stream));
+    nx = norm_dev(E, x, n);
+    if (!(nx > 0.0)) throw std::runtime_error("empty QN-allowed space in a local problem");
+  }
+  HC(hipMemcpyAsync(V, x, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+  scale(V, 1.0 / nx, n, E.stream);
+  window_matvec(E, w, V, AV, prec);
+  mask_apply(AV, mask.as<uint8_t>(), n, E.stream);
+  res.matvecs = 1;
+  int m = 1;
+  std::vector<double> Hs(1);
+  {
+    std::vector<double> d;
+    dots(V, 1, AV, d);
+    Hs[0] = d[0];
+  }
+  std::vector<double> evals, evecs, c;
+  for (int it = 0;; ++it) {
+    // Rayleigh-Ritz
+    std::vector<double> Hm((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Hm[(size_t)i * m + j] = 0.5 * (Hs[(size_t)i * maxsub + j] + Hs[(size_t)j * maxsub + i]);
+    jacobi_eig(m, Hm, evals, evecs);
+    res.theta = evals[0];
+    c.resize(m);
+    for (int i = 0; i < m; ++i) c[i] = evecs[(size_t)i * m];
+    lcomb(V, m, c, u);
+    lcomb(AV, m, c, Au);
+    axpby(t, 1.0, Au, -res.theta, u, n, E.stream);
+    res.resid = norm_dev(E, t, n);
+    res.iters = it + 1;
+    if (res.resid <= tol) {
+      res.converged = true;
+      break;
+    }
+    if (res.matvecs >= maxiter) break;
+    if (m >= maxsub) {
+      // restart with the Ritz vector
+      HC(hipMemcpyAsync(V, u, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+      HC(hipMemcpyAsync(AV, Au, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+      double nu = norm_dev(E, V, n);
+      scale(V, 1.0 / nu, n, E.stream);
+      scale(AV, 1.0 / nu, n, E.stream);
+      m = 1;
+      std::vector<double> d;
+      dots(V, 1, AV, d);
+      Hs.assign((size_t)maxsub * maxsub, 0.0);
+      Hs[0] = d[0];
+      continue;
+    }
+    // new direction: residual, projected out of the subspace twice
+    mask_apply(t, mask.as<uint8_t>(), n, E.stream);
+    double tn0 = norm_dev(E, t, n);
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<double> d;
+      dots(V, m, t, d);
+      for (double& v : d) v = -v;
+      lcomb(V, m, d, u);  // u is free now
+      axpy(t, 1.0, u, n, E.stream);
+    }
+    double tn = norm_dev(E, t, n);
+    if (!(tn > 1e-10 * tn0) || !(tn > 0.0)) {
+      res.converged = res.resid <= tol;
+      break;
+    }
+    double* vm = V + (size_t)m * n;
+    HC(hipMemcpyAsync(vm, t, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+    scale(vm, 1.0 / tn, n, E.stream);
+    double* avm = AV + (size_t)m * n;
+    window_matvec(E, w, vm, avm, prec);
+    mask_apply(avm, mask.as<uint8_t>(), n, E.stream);
+    res.matvecs++;
+    std::vector<double> d;
+    dots(V, m + 1, avm, d);
+    if ((int)Hs.size() < maxsub * maxsub) {
+      std::vector<double> H2((size_t)maxsub * maxsub, 0.0);
+      H2[0] = Hs[0];
+      Hs.swap(H2);
+    }
+    for (int i = 0; i <= m; ++i) {
+      Hs[(size_t)i * maxsub + m] = d[i];
+      Hs[(size_t)m * maxsub + i] = d[i];
+    }
+    ++m;
+  }
+  // eigenvector -> x (unit norm)
+  double nu = norm_dev(E, u, n);
+  HC(hipMemcpyAsync(x, u, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+  scale(x, 1.0 / nu, n, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+  return res;
+}
+
+// one micro-iteration: lowest eigenpair of the window; returns theta
+static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem& x, const Core& C, const Core& D) {
+  const Labels& ql = C.ql;
+  const Labels& qr = D.qr;
+  DevMem mask = build_mask(E, C.rl, ql, D.rr, qr);
+  Window w;
+  const int prec = E.opts.matvec_prec;
+  Davidson r;
+  if (prec != TT_F64) {
+    prepare_window(E, w, Le, b, Re, prec);
+    const double tol_low = E.opts.refine_fp64 ? std::max(E.opts.lowprec_tol, E.opts.dav_tol) : E.opts.dav_tol;
+    r = davidson(E, w, mask, x.as<double>(), prec, tol_low, E.opts.dav_maxiter);
+    if (E.opts.refine_fp64) {
+      w.L32.release();
+      w.R32.release();
+      w.Rt32.release();
+      Davidson r2 = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter);
+      r2.matvecs += r.matvecs;
+      r = r2;
+    }
+  } else {
+    prepare_window(E, w, Le, b, Re, TT_F64);
+    r = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter);
+  }
+  if (!r.converged) E.warn = std::max(E.warn, (int)TT_WNOCONV);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 + Step 2
+// ---------------------------------------------------------------------------
+void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
+  if (!have_mpo || !have_mps) throw std::logic_error("local_solve needs the MPO and the TT iterate");
+  if (nsub <= 0 || nsub > TT_MAX_SUB) throw std::invalid_argument("bad number of subdomains");
+  int tot = 0;
+  for (int j = 0; j < nsub; ++j) {
+    if (lengths[j] <= 0) throw std::invalid_argument("subdomain lengths must be positive");
+    tot += lengths[j];
+  }
+  if (tot != L) throw std::invalid_argument("subdomain lengths must sum to L");
+  free_caches();
+  // Step 1: LQ sweep; W[k] centres, V[k] right-orthogonal cores
+  Vc.clear(); Vc.resize(L);
+  Wc.clear(); Wc.resize(L);
+  {
+    Core cur;  // W_{L-1}
+    cur.rl = U[L - 1].rl; cur.rr = U[L - 1].rr; cur.ql = U[L - 1].ql; cur.qr = U[L - 1].qr;
+    cur.d.ensure(U[L - 1].d.n);
+    HC(hipMemcpyAsync(cur.d.p, U[L - 1].d.p, U[L - 1].d.n, hipMemcpyDeviceToDevice, stream));
+    auto copy_core = [&](const Core& a, Core& b) {
+      b.rl = a.rl; b.rr = a.rr; b.ql = a.ql; b.qr = a.qr;
+      b.d.ensure(a.d.n);
+      HC(hipMemcpyAsync(b.d.p, a.d.p, a.d.n, hipMemcpyDeviceToDevice, stream));
+    };
+    copy_core(cur, Wc[L - 1]);
+    for (int k = L - 1; k >= 1; --k) {
+      Core prev;
+      copy_core(U[k - 1], prev);
+      Core w;
+      copy_core(Wc[k], w);
+      lq_right(*this, w, prev);
+      Vc[k] = std::move(w);
+      Wc[k - 1] = std::move(prev);
+      if (Vc[k].rl != U[k - 1].rr) throw std::runtime_error("LQ sweep changed a bond dimension (rank-deficient iterate)");
+    }
+    HC(hipStreamSynchronize(stream));
+  }
+  // environment caches: Lenv[k] at bond k from U (k = 0..L-1), Renv[k] from V (k = 2..L)
+  Lenv.clear(); Lenv.resize(L + 1);
+  Renv.clear(); Renv.resize(L + 1);
+  env_unit(Lenv[0], 1);
+  for (int k = 0; k + 1 < L; ++k) env_left(Lenv[k], U[k], U[k], k, Lenv[k + 1]);
+  env_unit(Renv[L], 1);
+  for (int k = L - 1; k >= 2; --k) env_right(Renv[k + 1], Vc[k], Vc[k], k, Renv[k]);
+  // Step 2: subdomain sweeps
+  subs.clear(); subs.resize(nsub);
+  int start = 0;
+  for (int j = 0; j < nsub; ++j) {
+    Sub& S = subs[j];
+    const int s = start, e = start + lengths[j] - 1;
+    start += lengths[j];
+    const int blast = std::min(e, L - 2);
+    S.s = s;
+    S.t = blast + 1;
+    if (s > L - 2) {
+      // a one-site last subdomain has no bond of its own
+      S.t = s;
+      S.mod.clear();
+      Core c;
+      c.rl = Wc[s].rl; c.rr = Wc[s].rr; c.ql = Wc[s].ql; c.qr = Wc[s].qr;
+      c.d.ensure(Wc[s].d.n);
+      HC(hipMemcpyAsync(c.d.p, Wc[s].d.p, Wc[s].d.n, hipMemcpyDeviceToDevice, stream));
+      S.mod.push_back(std::move(c));
+      S.E = 0.0;
+      continue;
+    }
+    Core center;
+    center.rl = Wc[s].rl; center.rr = Wc[s].rr; center.ql = Wc[s].ql; center.qr = Wc[s].qr;
+    center.d.ensure(Wc[s].d.n);
+    HC(hipMemcpyAsync(center.d.p, Wc[s].d.p, Wc[s].d.n, hipMemcpyDeviceToDevice, stream));
+    Env Lrun;
+    const Env* Lcur = &Lenv[s];
+    DevMem x;
+    for (int b = s; b <= blast; ++b) {
+      const Core& next = Vc[b + 1];
+      two_site(*this, center, next, x);
+      Davidson r = local_eig(*this, *Lcur, b, Renv[b + 2], x, center, next);
+      S.matvecs += r.matvecs;
+      S.E = r.theta;
+      S.converged = S.converged && r.converged;
+      Core N, C;
+      split_two_site(*this, x.as<double>(), center.rl, center.ql, next.rr, next.qr, opts.chi_max, true, N, C);
+      if (b < blast) {
+        Env nl;
+        env_left(*Lcur, N, N, b, nl);
+        Lrun = std::move(nl);
+        Lcur = &Lrun;
+      } else {
+        double nc = norm_dev(*this, C.d.as<double>(), C.elems());
+        scale(C.d.as<double>(), 1.0 / nc, C.elems(), stream);
+      }
+      S.mod.push_back(std::move(N));
+      center = std::move(C);
+    }
+    S.mod.push_back(std::move(center));
+    HC(hipStreamSynchronize(stream));
+    if (Eloc) Eloc[j] = S.E;
+    if (mv) mv[j] = S.matvecs;
+  }
+  have_local = true;
+}
+
+// ---------------------------------------------------------------------------
+// Step 3 + Step 4
+// ---------------------------------------------------------------------------
+static const Core& core_of(const Engine& E, int j, int k, bool V_suffix) {
+  // Ũ^j (j >= 1): U_k for k < s_j, mod for s_j..t_j, V_k beyond
+  const Engine::Sub& S = E.subs[j - 1];
+  if (k < S.s) return E.U[k];
+  if (k <= S.t) return S.mod[k - S.s];
+  (void)V_suffix;
+  return E.Vc[k];
+}
+
+int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam, double* Eout, int* rank,
+                           double* disc) {
+  if (!have_local) throw std::logic_error("coarse_correct needs a preceding local_solve");
+  const int P = (int)subs.size();
+  const int n = P + 1;
+  std::vector<double> S((size_t)n * n, 0.0), A((size_t)n * n, 0.0);
+  // <U0|H|U0> and <U0|U0> = 1 (normalised iterate)
+  {
+    Env e;
+    env_left(Lenv[L - 1], U[L - 1], U[L - 1], L - 1, e);
+    double v;
+    d2h(&v, e.d.p, sizeof(double), stream);
+    A[0] = v;
+    S[0] = 1.0;
+  }
+  auto overlap_start = [&](int rb, int rk, Env& e) {
+    // identity on the bra/ket bond (both left-orthonormal prefixes of U)
+    e.R = 1; e.rb = rb; e.rk = rk;
+    const int p = padr(rb), q = padr(rk);
+    std::vector<double> h((size_t)p * q, 0.0);
+    for (int i = 0; i < std::min(rb, rk); ++i) h[(size_t)i * q + i] = 1.0;
+    upload(e.d, h.data(), h.size() * sizeof(double), stream);
+  };
+  // overlap chains use a one-channel identity "MPO" through the same kernels
+  SiteOp ident;
+  {
+    std::vector<int> o{0}, i{0};
+    std::vector<double> op{1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    build_siteop(ident, 1, o, i, op, stream);
+  }
+  auto ov_left = [&](const Env& in, const Core& bra, const Core& ket, Env& out) {
+    Env o;
+    o.R = 1; o.rb = bra.rr; o.rk = ket.rr;
+    o.d.ensure(sizeof(double) * o.elems());
+    env_left_raw(padr(in.rb), padr(in.rk), bra.rrp(), ket.rrp(), 1, in.d.as<double>(), bra.d.as<double>(),
+                 ket.d.as<double>(), ident, 1, o.d.as<double>());
+    out = std::move(o);
+  };
+  auto ov_close = [&](const Env& e) {
+    // trace over the bond (the V suffix is right-orthonormal)
+    const int p = padr(e.rb), q = padr(e.rk);
+    std::vector<double> h((size_t)p * q);
+    download(h.data(), e.d, h.size() * sizeof(double), stream);
+    double t = 0.0;
+    for (int i = 0; i < std::min(e.rb, e.rk); ++i) t += h[(size_t)i * q + i];
+    return t;
+  };
+  // entries (0, j) and (j, j)
+  for (int j = 1; j <= P; ++j) {
+    const Sub& Sj = subs[j - 1];
+    // bra U^0 in the s_j-orthogonal gauge: W_{s_j}, V_{s_j+1}, ...
+    Env eH, eS, tH, tS;
+    const Env* cH = &Lenv[Sj.s];
+    overlap_start(Wc[Sj.s].rl, Sj.mod[0].rl, eS);
+    for (int k = Sj.s; k <= Sj.t; ++k) {
+      const Core& bra = (k == Sj.s) ? Wc[k] : Vc[k];
+      const Core& ket = Sj.mod[k - Sj.s];
+      env_left(*cH, bra, ket, k, tH);
+      eH = std::move(tH);
+      cH = &eH;
+      ov_left(eS, bra, ket, tS);
+      eS = std::move(tS);
+    }
+    A[j] = A[(size_t)j * n] = env_close(eH, Renv[Sj.t + 1]);
+    S[j] = S[(size_t)j * n] = ov_close(eS);
+    // diagonal
+    cH = &Lenv[Sj.s];
+    overlap_start(Sj.mod[0].rl, Sj.mod[0].rl, eS);
+    for (int k = Sj.s; k <= Sj.t; ++k) {
+      const Core& c = Sj.mod[k - Sj.s];
+      env_left(*cH, c, c, k, tH);
+      eH = std::move(tH);
+      cH = &eH;
+      ov_left(eS, c, c, tS);
+      eS = std::move(tS);
+    }
+    A[(size_t)j * n + j] = env_close(eH, Renv[Sj.t + 1]);
+    S[(size_t)j * n + j] = ov_close(eS);
+  }
+  // entries (i, j), 1 <= i < j
+  for (int i = 1; i <= P; ++i) {
+    const Sub& Si = subs[i - 1];
+    // common chain: bra = Ũ^i, ket = U, from bond s_i
+    Env cH, cS, tH, tS;
+    bool first = true;
+    int k = Si.s;
+    for (int j = i + 1; j <= P; ++j) {
+      const Sub& Sj = subs[j - 1];
+      // advance common chain to bond s_j
+      for (; k < Sj.s; ++k) {
+        const Core& bra = core_of(*this, i, k, true);
+        const Core& ket = U[k];
+        if (first) {
+          env_left(Lenv[Si.s], bra, ket, k, tH);
+          Env s0;
+          overlap_start(bra.rl, ket.rl, s0);
+          ov_left(s0, bra, ket, tS);
+          first = false;
+        } else {
+          env_left(cH, bra, ket, k, tH);
+          ov_left(cS, bra, ket, tS);
+        }
+        cH = std::move(tH);
+        cS = std::move(tS);
+      }
+      // branch: sites s_j..t_j with ket = Ũ^j
+      Env bH, bS;
+      const Env* pH = &cH;
+      const Env* pS = &cS;
+      for (int kk = Sj.s; kk <= Sj.t; ++kk) {
+        const Core& bra = core_of(*this, i, kk, true);
+        const Core& ket = Sj.mod[kk - Sj.s];
+        env_left(*pH, bra, ket, kk, tH);
+        ov_left(*pS, bra, ket, tS);
+        bH = std::move(tH);
+        bS = std::move(tS);
+        pH = &bH;
+        pS = &bS;
+      }
+      A[(size_t)i * n + j] = A[(size_t)j * n + i] = env_close(bH, Renv[Sj.t + 1]);
+      S[(size_t)i * n + j] = S[(size_t)j * n + i] = ov_close(bS);
+    }
+  }
+  // coarse eigenproblem (host FP64): canonical orthogonalisation of S
+  std::vector<double> ws, Vs;
+  jacobi_eig(n, S, ws, Vs);
+  const double smax = ws[n - 1];
+  std::vector<int> keep;
+  for (int i = 0; i < n; ++i)
+    if (ws[i] >= opts.coarse_eps * smax) keep.push_back(i);
+  const int p = (int)keep.size();
+  std::vector<double> X((size_t)n * p);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < p; ++a) X[(size_t)i * p + a] = Vs[(size_t)i * n + keep[a]] / std::sqrt(ws[keep[a]]);
+  std::vector<double> At((size_t)p * p, 0.0);
+  for (int a = 0; a < p; ++a)
+    for (int b = 0; b < p; ++b) {
+      double v = 0.0;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) v += X[(size_t)i * p + a] * A[(size_t)i * n + j] * X[(size_t)j * p + b];
+      At[(size_t)a * p + b] = v;
+    }
+  for (int a = 0; a < p; ++a)
+    for (int b = a + 1; b < p; ++b) {
+      double v = 0.5 * (At[(size_t)a * p + b] + At[(size_t)b * p + a]);
+      At[(size_t)a * p + b] = At[(size_t)b * p + a] = v;
+    }
+  std::vector<double> wa, Va;
+  jacobi_eig(p, At, wa, Va);
+  std::vector<double> c(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * Va[(size_t)a * p];
+  int imax = 0;
+  for (int i = 1; i < n; ++i)
+    if (std::fabs(c[i]) > std::fabs(c[imax])) imax = i;
+  if (c[imax] < 0)
+    for (double& v : c) v = -v;
+  int status = (p < n) ? TT_WRANKDEF : TT_OK;
+  if (Sout) std::copy(S.begin(), S.end(), Sout);
+  if (Aout) std::copy(A.begin(), A.end(), Aout);
+  if (cout) std::copy(c.begin(), c.end(), cout);
+  if (lam) *lam = wa[0];
+  if (rank) *rank = p;
+
+  // ---- Step 4: block TT of sum_j c_j Ũ^j and TT rounding ----
+  // bond k (1..L-1) blocks: U (r_k), V (r_k, if some subdomain ended before site k), straddle (one subdomain)
+  struct BondLayout {
+    int offU = -1, offV = -1, offS = -1, sub = -1, dim = 0;
+    int rU = 0, rV = 0, rS = 0;
+    Labels q;
+  };
+  std::vector<BondLayout> bl(L + 1);
+  bl[0].dim = 1;
+  bl[0].q = {Q2{0, 0}};
+  bl[L].dim = 1;
+  bl[L].q = {U[L - 1].qr[0]};
+  for (int k = 1; k < L; ++k) {
+    BondLayout& B = bl[k];
+    int d = 0;
+    B.offU = d; B.rU = U[k].rl; d += B.rU;
+    B.q.insert(B.q.end(), U[k].ql.begin(), U[k].ql.end());
+    bool anyV = false;
+    for (int j = 1; j <= P; ++j)
+      if (subs[j - 1].t <= k - 1) anyV = true;
+    if (anyV) {
+      B.offV = d; B.rV = Vc[k].rl; d += B.rV;
+      B.q.insert(B.q.end(), Vc[k].ql.begin(), Vc[k].ql.end());
+    }
+    for (int j = 1; j <= P; ++j) {
+      const Sub& Sj = subs[j - 1];
+      if (Sj.s <= k - 1 && k <= Sj.t) {
+        B.sub = j;
+        B.offS = d;
+        B.rS = Sj.mod[k - Sj.s].rl;
+        d += B.rS;
+        B.q.insert(B.q.end(), Sj.mod[k - Sj.s].ql.begin(), Sj.mod[k - Sj.s].ql.end());
+      }
+    }
+    B.dim = d;
+  }
+  double c0 = c[0];
+  for (int j = 1; j <= P; ++j)
+    if (subs[j - 1].s == L - 1) c0 += c[j];
+  std::vector<Core> T(L);
+  for (int k = 0; k < L; ++k) {
+    Core& C = T[k];
+    C.rl = bl[k].dim; C.rr = bl[k + 1].dim; C.ql = bl[k].q; C.qr = bl[k + 1].q;
+    C.d.resize_zero(sizeof(double) * C.elems(), stream);
+    const int Crrp = C.rrp();
+    auto put = [&](const Core& src, int row_off, int col_off, double alpha) {
+      // C[row_off + a][s][col_off + b] = alpha * src[a][s][b]
+      double* dst = C.d.as<double>() + (long long)row_off * 4 * Crrp + col_off;
+      copy3d(src.d.as<double>(), 4LL * src.rrp(), src.rrp(), dst, 4LL * Crrp, Crrp, src.rl, 4, src.rr, alpha, stream);
+    };
+    const BondLayout& Bl = bl[k];
+    const BondLayout& Br = bl[k + 1];
+    if (k == 0) {
+      put(U[0], 0, (k + 1 < L) ? Br.offU : 0, (k + 1 < L) ? 1.0 : c0);
+      if (k + 1 < L) {
+        const Sub& S1 = subs[0];
+        if (S1.s == 0) {
+          if (S1.t == 0) put(S1.mod[0], 0, Br.offV >= 0 ? Br.offV : 0, c[1]);
+          else put(S1.mod[0], 0, Br.offS, 1.0);
+        }
+      }
+      continue;
+    }
+    if (k == L - 1) {
+      put(U[L - 1], Bl.offU, 0, c0);
+      if (Bl.offV >= 0) put(Vc[L - 1], Bl.offV, 0, 1.0);
+      if (Bl.sub >= 1) {
+        const Sub& Sj = subs[Bl.sub - 1];
+        put(Sj.mod[k - Sj.s], Bl.offS, 0, c[Bl.sub]);
+      }
+      continue;
+    }
+    // interior site
+    put(U[k], Bl.offU, Br.offU, 1.0);
+    if (Bl.offV >= 0) put(Vc[k], Bl.offV, Br.offV, 1.0);
+    if (Bl.sub >= 1) {
+      const Sub& Sj = subs[Bl.sub - 1];
+      const Core& mc = Sj.mod[k - Sj.s];
+      if (k < Sj.t) put(mc, Bl.offS, Br.offS, 1.0);
+      else put(mc, Bl.offS, Br.offV, c[Bl.sub]);  // k == t_j : close into the V chain
+    }
+    for (int j = 1; j <= P; ++j) {
+      const Sub& Sj = subs[j - 1];
+      if (Sj.s == k) put(Sj.mod[0], Bl.offU, Br.offS, 1.0);
+    }
+  }
+  HC(hipStreamSynchronize(stream));
+  // right-to-left orthogonalisation
+  for (int k = L - 1; k >= 1; --k) lq_right(*this, T[k], T[k - 1]);
+  // left-to-right truncated SVD
+  double discarded = 0.0;
+  for (int k = 0; k + 1 < L; ++k) {
+    Core& C = T[k];
+    std::vector<int> rows, cols;
+    Labels rq, cq;
+    for (int a = 0; a < C.rl; ++a)
+      for (int s = 0; s < 4; ++s) {
+        rows.push_back(a * 4 + s);
+        rq.push_back(qadd(C.ql[a], SITE_Q[s]));
+      }
+    for (int b = 0; b < C.rr; ++b) {
+      cols.push_back(b);
+      cq.push_back(C.qr[b]);
+    }
+    SectorSVD svd(*this);
+    SvdOut o = svd.run(C.d.as<double>(), C.rrp(), rows, rq, cols, cq, opts.chi_max, true);
+    discarded += o.discarded;
+    const int kk = o.k, kp = padr(std::max(kk, 1));
+    Core N;
+    N.rl = C.rl; N.ql = C.ql; N.rr = kk; N.qr = o.q;
+    N.d.resize_zero(sizeof(double) * (size_t)C.rlp() * 4 * kp, stream);
+    DevMem SV;
+    SV.resize_zero(sizeof(double) * (size_t)kp * C.rrp(), stream);
+    svd.scatter(N.d.as<double>(), kp, SV.as<double>(), C.rrp(), 0);
+    // next <- SV * next
+    Core& Nx = T[k + 1];
+    const int nrp = Nx.rrp();
+    DevMem nd;
+    nd.ensure(sizeof(double) * (size_t)kp * 4 * nrp);
+    GemmArgs g{};
+    g.M = kp; g.N = 4 * nrp; g.K = C.rrp(); g.batch = 1; g.kin = C.rrp();
+    g.sAm = C.rrp(); g.sAkk = 1; g.sBkk = 4LL * nrp; g.sBn = 1; g.sCm = 4LL * nrp; g.alpha = 1.0; g.beta = 0.0;
+    gemm<double>(g, SV.as<double>(), Nx.d.as<double>(), nd.as<double>(), true, true, stream);
+    HC(hipStreamSynchronize(stream));
+    Nx.d = std::move(nd);
+    Nx.rl = kk;
+    Nx.ql = o.q;
+    T[k] = std::move(N);
+  }
+  double nr = norm_dev(*this, T[L - 1].d.as<double>(), T[L - 1].elems());
+  if (!(nr > 0.0)) throw std::runtime_error("compressed iterate vanished");
+  scale(T[L - 1].d.as<double>(), 1.0 / nr, T[L - 1].elems(), stream);
+  HC(hipStreamSynchronize(stream));
+  U = std::move(T);
+  free_caches();
+  double En = energy();
+  if (Eout) *Eout = En;
+  if (disc) *disc = discarded;
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// classical two-site DMRG (Algorithm 1)
+// ---------------------------------------------------------------------------
+void Engine::dmrg2(int nsweeps, double* energies) {
+  if (!have_mpo || !have_mps) throw std::logic_error("dmrg2 needs the MPO and the TT iterate");
+  // right-orthogonal start: cur = (W_0, V_1, ..., V_{L-1})
+  std::vector<Core> cur(L);
+  for (int k = 0; k < L; ++k) {
+    cur[k].rl = U[k].rl; cur[k].rr = U[k].rr; cur[k].ql = U[k].ql; cur[k].qr = U[k].qr;
+    cur[k].d.ensure(U[k].d.n);
+    HC(hipMemcpyAsync(cur[k].d.p, U[k].d.p, U[k].d.n, hipMemcpyDeviceToDevice, stream));
+  }
+  for (int k = L - 1; k >= 1; --k) lq_right(*this, cur[k], cur[k - 1]);
+  std::vector<Env> Le(L + 1), Re(L + 1);
+  env_unit(Le[0], 1);
+  env_unit(Re[L], 1);
+  for (int k = L - 1; k >= 2; --k) env_right(Re[k + 1], cur[k], cur[k], k, Re[k]);
+  DevMem x;
+  int ie = 0;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    double th = 0.0;
+    for (int b = 0; b + 1 < L; ++b) {
+      two_site(*this, cur[b], cur[b + 1], x);
+      Davidson r = local_eig(*this, Le[b], b, Re[b + 2], x, cur[b], cur[b + 1]);
+      th = r.theta;
+      Core N, C;
+      split_two_site(*this, x.as<double>(), cur[b].rl, cur[b].ql, cur[b + 1].rr, cur[b + 1].qr, opts.chi_max, true,
+                     N, C);
+      cur[b] = std::move(N);
+      cur[b + 1] = std::move(C);
+      if (b + 2 < L) env_left(Le[b], cur[b], cur[b], b, Le[b + 1]);
+    }
+    if (energies) energies[ie++] = th;
+    for (int b = L - 2; b >= 0; --b) {
+      two_site(*this, cur[b], cur[b + 1], x);
+      Davidson r = local_eig(*this, Le[b], b, Re[b + 2], x, cur[b], cur[b + 1]);
+      th = r.theta;
+      Core N, C;
+      split_two_site(*this, x.as<double>(), cur[b].rl, cur[b].ql, cur[b + 1].rr, cur[b + 1].qr, opts.chi_max, false,
+                     N, C);
+      cur[b] = std::move(N);
+      cur[b + 1] = std::move(C);
+      if (b >= 1) env_right(Re[b + 2], cur[b + 1], cur[b + 1], b + 1, Re[b + 1]);
+    }
+    if (energies) energies[ie++] = th;
+  }
+  // back to left-orthogonal form
+  for (int k = 0; k + 1 < L; ++k) qr_left(*this, cur[k], cur[k + 1]);
+  double nr = norm_dev(*this, cur[L - 1].d.as<double>(), cur[L - 1].elems());
+  scale(cur[L - 1].d.as<double>(), 1.0 / nr, cur[L - 1].elems(), stream);
+  HC(hipStreamSynchronize(stream));
+  U = std::move(cur);
+  free_caches();
+}
+
+}  // namespace tt
+
+// ---------------------------------------------------------------------------
+// backward of E = <x|H_eff|x> (K12): the forward chain
+//   T1 = L x, T2 = mix_W1(T1), T3 = mix_W2(T2), y = sum_C T3[C] R_C^T
+// is linear in each operand, so every gradient is the contraction with that
+// operand removed; the adjoint of a mix is the same gather with the entry
+// lists regrouped by input channel and the local operators transposed.
+// ---------------------------------------------------------------------------
+namespace tt {
+
+static std::vector<double> transpose_ops(const std::vector<double>& o) {
+  std::vector<double> t(o.size());
+  for (size_t e = 0; e < o.size() / 16; ++e)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) t[e * 16 + i * 4 + j] = o[e * 16 + j * 4 + i];
+  return t;
+}
+
+void Engine::heff_grad_raw(int rl, int rr, int RA, int RB, int RC, const double* Lv, const double* Rv,
+                           const std::vector<int>& A1, const std::vector<int>& B1, const std::vector<double>& o1,
+                           const std::vector<int>& A2, const std::vector<int>& B2, const std::vector<double>& o2,
+                           const double* x, double* En, double* gx, double* gL, double* gR, std::vector<double>& gop1,
+                           std::vector<double>& gop2) {
+  const long long slab = (long long)rl * 16 * rr;
+  const size_t n = (size_t)slab;
+  SiteOp w1f, w2f, w1fT, w2fT, w1a, w2a;
+  std::vector<double> o1T = transpose_ops(o1), o2T = transpose_ops(o2);
+  build_siteop(w1f, RB, B1, A1, o1, stream);
+  build_siteop(w2f, RC, B2, A2, o2, stream);
+  build_siteop(w1fT, RB, B1, A1, o1T, stream);
+  build_siteop(w2fT, RC, B2, A2, o2T, stream);
+  build_siteop(w1a, RA, A1, B1, o1T, stream);  // adjoint of mix 1: out A <- in B, op^T
+  build_siteop(w2a, RB, A2, B2, o2T, stream);  // adjoint of mix 2: out B <- in C, op^T
+  DevMem T1, T2, T3, G1, G2, G3, y, yT, LT, RT, ch1a, ch1b, ch2a, ch2b, g1d, g2d;
+  T1.ensure(sizeof(double) * slab * RA);
+  T2.ensure(sizeof(double) * slab * RB);
+  T3.ensure(sizeof(double) * slab * RC);
+  G3.ensure(sizeof(double) * slab * RC);
+  G2.ensure(sizeof(double) * slab * RB);
+  G1.ensure(sizeof(double) * slab * RA);
+  y.ensure(sizeof(double) * n);
+  yT.ensure(sizeof(double) * n);
+  // forward
+  GemmArgs g{};
+  g.M = rl; g.N = 16 * rr; g.K = rl; g.batch = RA; g.kin = rl;
+  g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkk = 1; g.sBkk = 16LL * rr; g.sBn = 1;
+  g.sCb = slab; g.sCm = 16LL * rr; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, Lv, x, T1.as<double>(), true, true, stream);
+  mix<double>(RB, w1f.ptr.as<int>(), w1f.src.as<int>(), w1f.op64.as<double>(), T1.as<double>(), slab, T2.as<double>(),
+              slab, rl, 4 * rr, stream);
+  mix<double>(RC, w2f.ptr.as<int>(), w2f.src.as<int>(), w2f.op64.as<double>(), T2.as<double>(), slab, T3.as<double>(),
+              slab, 4 * rl, rr, stream);
+  GemmArgs h{};
+  h.M = 16 * rl; h.N = rr; h.K = RC * rr; h.batch = 1; h.kin = rr;
+  h.sAm = rr; h.sAkb = slab; h.sAkk = 1; h.sBkb = (long long)rr * rr; h.sBkk = 1; h.sBn = rr;
+  h.sCm = rr; h.alpha = 1.0; h.beta = 0.0;
+  gemm<double>(h, T3.as<double>(), Rv, y.as<double>(), true, false, stream);
+  // E = x . y
+  wsp.ensure(sizeof(double) * 264);
+  DevMem part;
+  part.ensure(sizeof(double) * 128);
+  multi_dot(x, n, 1, y.as<double>(), n, wsp.as<double>(), part.as<double>(), 128, stream);
+  d2h(En, wsp.p, sizeof(double), stream);
+  // H^T x with every operand transposed
+  LT.ensure(sizeof(double) * (size_t)RA * rl * rl);
+  RT.ensure(sizeof(double) * (size_t)RC * rr * rr);
+  transpose_batched(Lv, LT.as<double>(), RA, rl, rl, stream);
+  transpose_batched(Rv, RT.as<double>(), RC, rr, rr, stream);
+  heff<double>(rl, rr, RA, LT.as<double>(), w1fT, RB, w2fT, RC, RT.as<double>(), x, yT.as<double>(), nullptr, 0, 0);
+  axpby(gx, 1.0, y.as<double>(), 1.0, yT.as<double>(), n, stream);
+  // adjoint of the last GEMM: G3[C] = x R_C ; gR[C] = x^T T3[C]
+  GemmArgs a{};
+  a.M = 16 * rl; a.N = rr; a.K = rr; a.batch = RC; a.kin = rr;
+  a.sAb = 0; a.sAm = rr; a.sAkk = 1; a.sBb = (long long)rr * rr; a.sBkk = rr; a.sBn = 1;
+  a.sCb = slab; a.sCm = rr; a.alpha = 1.0; a.beta = 0.0;
+  gemm<double>(a, x, Rv, G3.as<double>(), true, true, stream);
+  GemmArgs b{};
+  b.M = rr; b.N = rr; b.K = 16 * rl; b.batch = RC; b.kin = 16 * rl;
+  b.sAb = 0; b.sAm = 1; b.sAkk = rr; b.sBb = slab; b.sBkk = rr; b.sBn = 1;
+  b.sCb = (long long)rr * rr; b.sCm = rr; b.alpha = 1.0; b.beta = 0.0;
+  gemm<double>(b, x, T3.as<double>(), gR, false, true, stream);
+  // entry gradients of W2 and adjoint of mix 2
+  const int nnz1 = (int)A1.size(), nnz2 = (int)A2.size();
+  g2d.resize_zero(sizeof(double) * 16 * std::max(nnz2, 1), stream);
+  g1d.resize_zero(sizeof(double) * 16 * std::max(nnz1, 1), stream);
+  if (nnz2) {
+    ch2a = upload_ints(B2, stream);  // G channel (output C)
+    ch2b = upload_ints(A2, stream);  // T channel (input B)
+    entry_grad<double>(nnz2, ch2a.as<int>(), ch2b.as<int>(), G3.as<double>(), slab, T2.as<double>(), slab, 4 * rl, rr,
+                       g2d.as<double>(), stream);
+  }
+  mix<double>(RB, w2a.ptr.as<int>(), w2a.src.as<int>(), w2a.op64.as<double>(), G3.as<double>(), slab, G2.as<double>(),
+              slab, 4 * rl, rr, stream);
+  if (nnz1) {
+    ch1a = upload_ints(B1, stream);
+    ch1b = upload_ints(A1, stream);
+    entry_grad<double>(nnz1, ch1a.as<int>(), ch1b.as<int>(), G2.as<double>(), slab, T1.as<double>(), slab, rl, 4 * rr,
+                       g1d.as<double>(), stream);
+  }
+  mix<double>(RA, w1a.ptr.as<int>(), w1a.src.as<int>(), w1a.op64.as<double>(), G2.as<double>(), slab, G1.as<double>(),
+              slab, rl, 4 * rr, stream);
+  // gL[A] = G1[A] X^T
+  GemmArgs c{};
+  c.M = rl; c.N = rl; c.K = 16 * rr; c.batch = RA; c.kin = 16 * rr;
+  c.sAb = slab; c.sAm = 16LL * rr; c.sAkk = 1; c.sBb = 0; c.sBkk = 1; c.sBn = 16LL * rr;
+  c.sCb = (long long)rl * rl; c.sCm = rl; c.alpha = 1.0; c.beta = 0.0;
+  gemm<double>(c, G1.as<double>(), x, gL, true, false, stream);
+  HC(hipStreamSynchronize(stream));
+  gop1.resize(16 * (size_t)nnz1);
+  gop2.resize(16 * (size_t)nnz2);
+  if (nnz1) d2h(gop1.data(), g1d.p, sizeof(double) * 16 * nnz1, stream);
+  if (nnz2) d2h(gop2.data(), g2d.p, sizeof(double) * 16 * nnz2, stream);
+}
+
+// Gradient of E = <U|H|U> (normalised U fixed) with respect to every MPO entry:
+//   dE/dW_k[A,s',s,B] = sum L_k[A][a'][a] U_k[a' s' b'] U_k[a s b] R_{k+1}[B][b'][b].
+// Left environments are carried along the sweep; right environments are kept
+// only at checkpoints every ~sqrt(L) sites and recomputed inside a segment.
+void Engine::mpo_grad(double* En, double* const* gops) {
+  if (!have_mpo || !have_mps) throw std::logic_error("gradient needs the MPO and the TT iterate");
+  const int cstep = std::max(1, (int)std::ceil(std::sqrt((double)L)));
+  std::map<int, Env> ckpt;  // right environments at checkpoint bonds
+  {
+    Env e;
+    env_unit(e, 1);
+    for (int k = L - 1; k >= 1; --k) {
+      Env o;
+      env_right(e, U[k], U[k], k, o);
+      e = std::move(o);
+      if (k % cstep == 0) {
+        Env keep;
+        keep.R = e.R; keep.rb = e.rb; keep.rk = e.rk;
+        keep.d.ensure(e.d.n);
+        HC(hipMemcpyAsync(keep.d.p, e.d.p, e.d.n, hipMemcpyDeviceToDevice, stream));
+        ckpt[k] = std::move(keep);
+      }
+    }
+  }
+  std::map<int, Env> seg;  // right environments of the current segment
+  auto right_env = [&](int bond) -> const Env& {
+    if (bond == L) {
+      if (!seg.count(L)) env_unit(seg[L], 1);
+      return seg[L];
+    }
+    auto it = seg.find(bond);
+    if (it != seg.end()) return it->second;
+    // recompute from the next checkpoint at or above `bond`
+    seg.clear();
+    int top = L;
+    for (auto& kv : ckpt)
+      if (kv.first >= bond) { top = kv.first; break; }
+    Env cur;
+    if (top == L) env_unit(cur, 1);
+    else {
+      cur.R = ckpt[top].R; cur.rb = ckpt[top].rb; cur.rk = ckpt[top].rk;
+      cur.d.ensure(ckpt[top].d.n);
+      HC(hipMemcpyAsync(cur.d.p, ckpt[top].d.p, ckpt[top].d.n, hipMemcpyDeviceToDevice, stream));
+    }
+    for (int k = top - 1; k >= bond; --k) {
+      Env o;
+      env_right(cur, U[k], U[k], k, o);
+      Env keep;
+      keep.R = o.R; keep.rb = o.rb; keep.rk = o.rk;
+      keep.d.ensure(o.d.n);
+      HC(hipMemcpyAsync(keep.d.p, o.d.p, o.d.n, hipMemcpyDeviceToDevice, stream));
+      seg[k] = std::move(keep);
+      cur = std::move(o);
+    }
+    return seg[bond];
+  };
+  Env Lk;
+  env_unit(Lk, 1);
+  for (int k = 0; k < L; ++k) {
+    const SiteMPO& s = mpo[k];
+    const Core& C = U[k];
+    const Env& Rk = right_env(k + 1);
+    const int rl = C.rlp(), rr = C.rrp();
+    const long long sl = (long long)rl * 4 * rr;
+    DevMem T, Rt, gd, cha, chb;
+    T.ensure(sizeof(double) * sl * s.Rl);
+    Rt.ensure(sizeof(double) * sl * s.Rr);
+    GemmArgs g{};
+    g.M = rl; g.N = 4 * rr; g.K = rl; g.batch = s.Rl; g.kin = rl;
+    g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkk = 1; g.sBkk = 4LL * rr; g.sBn = 1;
+    g.sCb = sl; g.sCm = 4LL * rr; g.alpha = 1.0; g.beta = 0.0;
+    gemm<double>(g, Lk.d.as<double>(), C.d.as<double>(), T.as<double>(), true, true, stream);
+    GemmArgs h{};
+    h.M = 4 * rl; h.N = rr; h.K = rr; h.batch = s.Rr; h.kin = rr;
+    h.sAb = 0; h.sAm = rr; h.sAkk = 1; h.sBb = (long long)rr * rr; h.sBkk = rr; h.sBn = 1;
+    h.sCb = sl; h.sCm = rr; h.alpha = 1.0; h.beta = 0.0;
+    gemm<double>(h, C.d.as<double>(), Rk.d.as<double>(), Rt.as<double>(), true, true, stream);
+    const int nnz = (int)s.A.size();
+    gd.resize_zero(sizeof(double) * 16 * std::max(nnz, 1), stream);
+    if (nnz) {
+      cha = upload_ints(s.B, stream);
+      chb = upload_ints(s.A, stream);
+      entry_grad<double>(nnz, cha.as<int>(), chb.as<int>(), Rt.as<double>(), sl, T.as<double>(), sl, rl, rr,
+                         gd.as<double>(), stream);
+      d2h(gops[k], gd.p, sizeof(double) * 16 * nnz, stream);
+    }
+    Env o;
+    env_left(Lk, C, C, k, o);
+    Lk = std::move(o);
+  }
+  d2h(En, Lk.d.p, sizeof(double), stream);
+}
+
+}  // namespace tt

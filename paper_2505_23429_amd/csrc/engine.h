@@ -1,0 +1,171 @@
+// Host-side engine of the additive two-level DMRG hot path: device tensors,
+// sparse MPO cores, environments, sector-wise linear algebra (rocSOLVER),
+// Davidson and the four steps of one global iteration.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <array>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tt.h"
+#include "kernels.h"
+
+namespace tt {
+
+constexpr int PAD = 32;  // every bond dimension is stored padded to a multiple of 32
+inline int padr(int r) { return ((r + PAD - 1) / PAD) * PAD; }
+
+using Q2 = std::array<int, 2>;
+using Labels = std::vector<Q2>;
+
+struct DevMem {
+  void* p = nullptr;
+  size_t n = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevMem() { release(); }
+  void release();
+  void ensure(size_t bytes);       // grow-only, contents not preserved
+  void resize_zero(size_t bytes, hipStream_t s);  // exact size, zero filled
+  template <class T> T* as() const { return (T*)p; }
+};
+
+// A TT core on the device: f64 [rlp][4][rrp], zero padded.
+struct Core {
+  int rl = 0, rr = 0;
+  Labels ql, qr;
+  DevMem d;
+  int rlp() const { return padr(rl); }
+  int rrp() const { return padr(rr); }
+  size_t elems() const { return (size_t)rlp() * 4 * rrp(); }
+};
+
+// One CSR form of a sparse MPO core (grouped by output channel).
+struct SiteOp {
+  int nout = 0, nnz = 0;
+  DevMem ptr, src, op64, op32;
+};
+
+struct SiteMPO {
+  int Rl = 0, Rr = 0;
+  std::vector<int> A, B;          // all entries (host)
+  std::vector<double> ops;        // [nnz][16]
+  SiteOp byB, byA;                // all entries
+  bool has_block = false;
+  int p0 = 0, p1 = 0, q0 = 0, q1 = 0;
+  DevMem V;                       // [q1-q0][p1-p0] f64 coefficient block
+  SiteOp byB_left;                // block -> virtual pass entries (inputs Rl + q - q0)
+  SiteOp byB_noblk;               // block entries removed
+  SiteOp byA_right;               // block -> virtual pass entries (inputs Rr + p - p0)
+};
+
+struct Env {
+  int R = 0, rb = 0, rk = 0;  // true sizes; storage [R][rbp][rkp]
+  DevMem d;
+  size_t elems() const { return (size_t)R * padr(rb) * padr(rk); }
+};
+
+struct Davidson {
+  int iters = 0, matvecs = 0;
+  bool converged = false;
+  double theta = 0.0, resid = 0.0;
+};
+
+class Engine {
+ public:
+  explicit Engine(const tt_opts& o);
+  ~Engine();
+  tt_opts opts;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  std::string err;
+
+  // problem
+  int L = 0;
+  std::vector<SiteMPO> mpo;
+  std::vector<int> Rb;                 // bond dims
+  std::vector<Labels> chan_q;          // per bond
+  std::vector<Core> U;                 // current left-orthogonal iterate
+  bool have_mpo = false, have_mps = false;
+
+  // Step 1 products (valid after local_solve)
+  std::vector<Core> Vc, Wc;            // right-orthogonal cores and centres
+  std::vector<Env> Lenv, Renv;         // environment caches
+  // Step 2 products
+  struct Sub {
+    int s = 0, t = 0;                  // modified sites [s, t]
+    std::vector<Core> mod;             // cores s..t
+    double E = 0.0;
+    int matvecs = 0;
+    bool converged = true;
+  };
+  std::vector<Sub> subs;
+  bool have_local = false;
+
+  // timing / accounting
+  double flops_heff = 0.0, sec_heff = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int warn = 0;
+
+  // setup
+  void set_mpo(int L, const int* R, const int* nnz, const int32_t* const* A, const int32_t* const* B,
+               const double* const* ops, const int32_t* const* cq, const int* block);
+  void set_mps(int L, const int* r, const double* const* Uh, const int32_t* const* q);
+  void get_mps(int* r, double* const* Uh, int32_t* const* q);
+  double energy();
+
+  // algorithm
+  void local_solve(int nsub, const int* lengths, double* E, int* mv);
+  int coarse_correct(double* S, double* A, double* c, double* lam, double* Eout, int* rank, double* disc);
+  void dmrg2(int nsweeps, double* energies);
+
+  // kernels on raw device pointers
+  template <class T>
+  void heff(int rl, int rr, int RA, const T* Lenv, const SiteOp& w1, int RB, const SiteOp& w2, int RC, const T* Renv,
+            const T* x, T* y, const T* Rtil, int P0, int nP);
+  void heff_bf16(int rl, int rr, int RA, const uint16_t* Lenv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
+                 const uint16_t* Renv, const uint16_t* x, float* y, const uint16_t* Rtil, int P0, int nP);
+  void env_left_raw(int rb, int rk, int rb2, int rk2, int RA, const double* E, const double* Ubra, const double* Uket,
+                    const SiteOp& w, int RB, double* out);
+  void env_right_raw(int rb, int rk, int rb2, int rk2, int RB, const double* E, const double* Ubra,
+                     const double* Uket, const SiteOp& w, int RA, double* out);
+  void heff_grad_raw(int rl, int rr, int RA, int RB, int RC, const double* Lenv, const double* Renv,
+                     const std::vector<int>& A1, const std::vector<int>& B1, const std::vector<double>& o1,
+                     const std::vector<int>& A2, const std::vector<int>& B2, const std::vector<double>& o2,
+                     const double* x, double* E, double* gx, double* gL, double* gR, std::vector<double>& gop1,
+                     std::vector<double>& gop2);
+  void mpo_grad(double* E, double* const* gops);
+
+  // environment updates through a site of the MPO (handles coefficient blocks)
+  void env_left(const Env& in, const Core& bra, const Core& ket, int site, Env& out);
+  void env_right(const Env& in, const Core& bra, const Core& ket, int site, Env& out);
+  void env_unit(Env& e, int R);
+  double env_close(const Env& Lb, const Env& Rb);  // full contraction at one bond
+  double overlap_chain(const std::vector<const Core*>& bra, const std::vector<const Core*>& ket);
+
+  static void build_siteop(SiteOp& so, int nout, const std::vector<int>& out_idx, const std::vector<int>& in_idx,
+                           const std::vector<double>& ops, hipStream_t s);
+
+  // workspace
+  DevMem ws0, ws1, ws2, ws3, wsd, wsp;
+  DevMem dav_V, dav_AV, dav_t, dav_u, dav_Au, dav_c, dav_mask;
+  DevMem wlow_x, wlow_y, wlow_L, wlow_R, wlow_Rt;
+
+ private:
+  void free_caches();
+};
+
+void upload(DevMem& m, const void* h, size_t bytes, hipStream_t s);
+void download(void* h, const DevMem& m, size_t bytes, hipStream_t s);
+
+}  // namespace tt

@@ -1,0 +1,79 @@
+// Device kernels of the additive two-level DMRG hot path (gfx950).
+// Internal interface between the kernels and the host orchestration; the
+// public C ABI is include/tt.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace tt {
+
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+// Operand addressing of the strided GEMM.  A(m,k), B(k,n) and C(m,n) are
+//   A(m,k) = A + batch*sAb + m*sAm + (k / kin)*sAkb + (k % kin)*sAkk
+//   B(k,n) = B + batch*sBb + (k / kin)*sBkb + (k % kin)*sBkk + n*sBn
+//   C(m,n) = C + batch*sCb + m*sCm + n          (row-major output)
+// The contiguous direction of each operand is a template choice:
+//   a_kcontig: sAkk == 1 (else sAm == 1);  b_ncontig: sBn == 1 (else sBkk == 1).
+// kin must be a multiple of 16 (bond dimensions are padded to 16).
+struct GemmArgs {
+  int M, N, K, batch;
+  int kin;
+  long long sAb, sAm, sAkb, sAkk;
+  long long sBb, sBkb, sBkk, sBn;
+  long long sCb, sCm;
+  double alpha, beta;
+};
+
+// C = alpha * A B + beta * C for T in {double, float}.  Accumulation in T.
+template <typename T>
+void gemm(const GemmArgs& g, const T* A, const T* B, T* C, bool a_kcontig, bool b_ncontig, hipStream_t s);
+
+// BF16 operands (uint16 storage), FP32 accumulation and FP32 output.
+void gemm_bf16(const GemmArgs& g, const uint16_t* A, const uint16_t* B, float* C, bool a_kcontig,
+               bool b_ncontig, hipStream_t s);
+
+// Sparse MPO application along one site index:
+//   out[c][o][s'][i] = sum_{e in [ptr[c], ptr[c+1])} sum_s op[e][s'][s] * in[src[e]][o][s][i]
+// in/out channel slabs have O*4*I elements; channel strides are given so the
+// same kernel serves every stage.  op is stored [e][4][4] in the compute type.
+template <typename T>
+void mix(int nout, const int* ptr, const int* src, const T* op, const T* in, long long in_cstride,
+         T* out, long long out_cstride, int O, int I, hipStream_t s);
+
+// Elementwise / reduction helpers (double unless noted).
+void fill(void* p, size_t bytes, hipStream_t s);                     // zero fill (kernel, graph-safe)
+void scale(double* x, double a, size_t n, hipStream_t s);
+void axpy(double* y, double a, const double* x, size_t n, hipStream_t s);
+void axpby(double* z, double a, const double* x, double b, const double* y, size_t n, hipStream_t s);
+void mask_apply(double* x, const uint8_t* mask, size_t n, hipStream_t s);
+// out[i] = sum_n V[i*ldv + n] * w[n] for i < m  (deterministic two-pass reduction)
+void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, double* out_dev, double* partial,
+               int nblk, hipStream_t s);
+// out[n] = sum_i c[i] V[i*ldv+n]  (c on device)
+void lincomb(const double* V, size_t ldv, int m, const double* c_dev, double* out, size_t n, hipStream_t s);
+void convert_f64_f32(const double* a, float* b, size_t n, hipStream_t s);
+void convert_f32_f64(const float* a, double* b, size_t n, hipStream_t s);
+void convert_f64_bf16(const double* a, uint16_t* b, size_t n, hipStream_t s);
+void convert_f64_f32_op(const double* a, float* b, size_t n, hipStream_t s);
+// gather / scatter of a 2-D block: dst[i*ldd + j] = src[rows[i]*lds + cols[j]] (column-major dst if colmajor)
+void gather2d(const double* src, long long lds, const int* rows, int nr, const int* cols, int nc, double* dst,
+              bool colmajor, hipStream_t s);
+// dst[rows[i]*ldd + cols[j]] = alpha * src[i*sr + j*sc] * (rs ? rs[i] : 1) * (cs ? cs[j] : 1)
+// tri: 0 full, 1 keep i <= j (upper), 2 keep j <= i (lower); other entries written as 0
+void scatter2d(const double* src, long long sr, long long sc, const int* rows, int nr, const int* cols, int nc,
+               double* dst, long long ldd, double alpha, const double* rs, const double* cs, int tri, hipStream_t s);
+// copy a strided 3-D block: dst[(i*d1 + j)*d2 + k] style with explicit strides
+void copy3d(const double* src, long long s0, long long s1, double* dst, long long d0, long long d1, int n0, int n1,
+            int n2, double alpha, hipStream_t s);
+
+// gop[e][s'][s] += sum_{o,i} G[cg(e)][o][s'][i] * T[ct(e)][o][s][i] for every entry e
+// (entries given as flat lists; one workgroup per entry, deterministic reduction)
+template <typename T>
+void entry_grad(int nnz, const int* gch, const int* tch, const T* G, long long g_cs, const T* Tin, long long t_cs,
+                int O, int I, double* gop, hipStream_t s);
+// batched transpose of [n][r][c] -> [n][c][r]
+void transpose_batched(const double* in, double* out, int n, int r, int c, hipStream_t s);
+
+}  // namespace tt

@@ -1,0 +1,639 @@
+// HIP kernels for gfx950 (CDNA4): MFMA GEMM tiles, sparse MPO mixing and the
+// bandwidth-bound vector operations of the Davidson solver.
+#include "kernels.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <stdexcept>
+
+namespace tt {
+
+#define HIPCHECK(x)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// MFMA GEMM: 128x128 output tile per workgroup (4 waves of 64x64), K step 16.
+// One 16x16x4 MFMA per (16x16 sub-tile, 4-deep K slice); lane l supplies
+// A[l%16][l/16] and B[l/16][l%16].  Accumulator register v of lane l holds
+// D[4*(l/16)+v][l%16] for FP32 and D[4*v+l/16][l%16] for FP64.
+// ---------------------------------------------------------------------------
+constexpr int BM = 128, BN = 128, BK = 16;
+
+template <typename T>
+__device__ inline void mfma_step(T a, T b, T (&acc)[4]);
+
+template <>
+__device__ inline void mfma_step<double>(double a, double b, double (&acc)[4]) {
+  d4 c = {acc[0], acc[1], acc[2], acc[3]};
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  acc[0] = c[0]; acc[1] = c[1]; acc[2] = c[2]; acc[3] = c[3];
+}
+
+template <>
+__device__ inline void mfma_step<float>(float a, float b, float (&acc)[4]) {
+  f4 c = {acc[0], acc[1], acc[2], acc[3]};
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  acc[0] = c[0]; acc[1] = c[1]; acc[2] = c[2]; acc[3] = c[3];
+}
+
+template <typename T>
+__device__ inline int acc_row(int lane, int v);
+template <>
+__device__ inline int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <>
+__device__ inline int acc_row<double>(int lane, int v) { return 4 * v + (lane >> 4); }
+
+template <typename T, bool AK, bool BNC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restrict__ A, const T* __restrict__ B,
+                                                   T* __restrict__ C) {
+  __shared__ T As[BK][BM + 4];
+  __shared__ T Bs[BK][BN + 4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int bz = blockIdx.z;
+  const T* Ab = A + (long long)bz * g.sAb;
+  const T* Bb = B + (long long)bz * g.sBb;
+  T* Cb = C + (long long)bz * g.sCb;
+
+  T acc[4][4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    const long long kbase_a = (long long)(k0 / g.kin) * g.sAkb;
+    const long long kbase_b = (long long)(k0 / g.kin) * g.sBkb;
+    const int kr = k0 % g.kin;  // offset inside the inner K block (tile never straddles)
+    // ---- A tile -> LDS (As[k][m]) ----
+    if (AK) {
+      const int m = tid >> 1, kh = (tid & 1) * 8;
+      const int gm = m0 + m;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = kh + u;
+        T v = T(0);
+        if (gm < g.M && k0 + kk < g.K) v = Ab[(long long)gm * g.sAm + kbase_a + (long long)(kr + kk) * g.sAkk];
+        As[kk][m] = v;
+      }
+    } else {
+      const int kk = tid >> 4, mc = (tid & 15) * 8;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gm = m0 + mc + u;
+        T v = T(0);
+        if (gm < g.M && k0 + kk < g.K) v = Ab[(long long)gm * g.sAm + kbase_a + (long long)(kr + kk) * g.sAkk];
+        As[kk][mc + u] = v;
+      }
+    }
+    // ---- B tile -> LDS (Bs[k][n]) ----
+    if (BNC) {
+      const int kk = tid >> 4, nc = (tid & 15) * 8;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gn = n0 + nc + u;
+        T v = T(0);
+        if (gn < g.N && k0 + kk < g.K) v = Bb[kbase_b + (long long)(kr + kk) * g.sBkk + (long long)gn * g.sBn];
+        Bs[kk][nc + u] = v;
+      }
+    } else {
+      const int n = tid >> 1, kh = (tid & 1) * 8;
+      const int gn = n0 + n;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = kh + u;
+        T v = T(0);
+        if (gn < g.N && k0 + kk < g.K) v = Bb[kbase_b + (long long)(kr + kk) * g.sBkk + (long long)gn * g.sBn];
+        Bs[kk][n] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[ks + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[ks + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mfma_step<T>(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  // ---- epilogue ----
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 64 + i * 16 + acc_row<T>(lane, v);
+        if (row >= g.M) continue;
+        T* p = Cb + (long long)row * g.sCm + col;
+        T r = T(g.alpha) * acc[i][j][v];
+        if (g.beta != 0.0) r += T(g.beta) * (*p);
+        *p = r;
+      }
+    }
+}
+
+static void check_args(const GemmArgs& g) {
+  if (g.M < 0 || g.N < 0 || g.K < 0 || g.batch < 0) throw std::runtime_error("gemm: negative size");
+  if (g.kin <= 0 || g.kin % BK != 0) throw std::runtime_error("gemm: inner K block must be a multiple of 16");
+}
+
+template <typename T>
+void gemm(const GemmArgs& g, const T* A, const T* B, T* C, bool a_kcontig, bool b_ncontig, hipStream_t s) {
+  check_args(g);
+  if (g.M == 0 || g.N == 0 || g.batch == 0) return;
+  if (g.K == 0) {
+    // C = beta*C : run the kernel anyway (loop body skipped) for uniform semantics
+  }
+  dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
+  if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm: grid too large");
+  if (a_kcontig && b_ncontig)
+    hipLaunchKernelGGL((gemm_kernel<T, true, true>), grid, dim3(256), 0, s, g, A, B, C);
+  else if (a_kcontig && !b_ncontig)
+    hipLaunchKernelGGL((gemm_kernel<T, true, false>), grid, dim3(256), 0, s, g, A, B, C);
+  else if (!a_kcontig && b_ncontig)
+    hipLaunchKernelGGL((gemm_kernel<T, false, true>), grid, dim3(256), 0, s, g, A, B, C);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, false, false>), grid, dim3(256), 0, s, g, A, B, C);
+  HIPCHECK(hipGetLastError());
+}
+
+template void gemm<double>(const GemmArgs&, const double*, const double*, double*, bool, bool, hipStream_t);
+template void gemm<float>(const GemmArgs&, const float*, const float*, float*, bool, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// BF16 operands, FP32 accumulation: 16x16x32 MFMA (gfx950).  Lane l supplies
+// A[l%16][8*(l/16)+0..7] and B[8*(l/16)+0..7][l%16].  K step 32.
+// ---------------------------------------------------------------------------
+constexpr int BK16 = 32;
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <bool AK, bool BNC>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, const uint16_t* __restrict__ A,
+                                                        const uint16_t* __restrict__ B, float* __restrict__ C) {
+  __shared__ uint16_t As[BM][BK16 + 8];  // [m][k]
+  __shared__ uint16_t Bs[BN][BK16 + 8];  // [n][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int bz = blockIdx.z;
+  const uint16_t* Ab = A + (long long)bz * g.sAb;
+  const uint16_t* Bb = B + (long long)bz * g.sBb;
+  float* Cb = C + (long long)bz * g.sCb;
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < g.K; k0 += BK16) {
+    const long long kbase_a = (long long)(k0 / g.kin) * g.sAkb;
+    const long long kbase_b = (long long)(k0 / g.kin) * g.sBkb;
+    const int kr = k0 % g.kin;
+    // A tile: 128 x 32 = 4096 elements, 16 per thread
+    if (AK) {
+      const int m = tid >> 1, kh = (tid & 1) * 16;
+      const int gm = m0 + m;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int kk = kh + u;
+        uint16_t v = 0;
+        if (gm < g.M && k0 + kk < g.K) v = Ab[(long long)gm * g.sAm + kbase_a + (long long)(kr + kk) * g.sAkk];
+        As[m][kk] = v;
+      }
+    } else {
+      const int kk = tid >> 3, mc = (tid & 7) * 16;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int gm = m0 + mc + u;
+        uint16_t v = 0;
+        if (gm < g.M && k0 + kk < g.K) v = Ab[(long long)gm * g.sAm + kbase_a + (long long)(kr + kk) * g.sAkk];
+        As[mc + u][kk] = v;
+      }
+    }
+    if (BNC) {
+      const int kk = tid >> 3, nc = (tid & 7) * 16;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int gn = n0 + nc + u;
+        uint16_t v = 0;
+        if (gn < g.N && k0 + kk < g.K) v = Bb[kbase_b + (long long)(kr + kk) * g.sBkk + (long long)gn * g.sBn];
+        Bs[nc + u][kk] = v;
+      }
+    } else {
+      const int n = tid >> 1, kh = (tid & 1) * 16;
+      const int gn = n0 + n;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int kk = kh + u;
+        uint16_t v = 0;
+        if (gn < g.N && k0 + kk < g.K) v = Bb[kbase_b + (long long)(kr + kk) * g.sBkk + (long long)gn * g.sBn];
+        Bs[n][kk] = v;
+      }
+    }
+    __syncthreads();
+    bf8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint16_t* p = &As[wm * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[i][u] = __builtin_bit_cast(__bf16, p[u]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint16_t* p = &Bs[wn * 64 + j * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[j][u] = __builtin_bit_cast(__bf16, p[u]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        if (row >= g.M) continue;
+        float* p = Cb + (long long)row * g.sCm + col;
+        float r = (float)g.alpha * acc[i][j][v];
+        if (g.beta != 0.0) r += (float)g.beta * (*p);
+        *p = r;
+      }
+    }
+}
+
+void gemm_bf16(const GemmArgs& g, const uint16_t* A, const uint16_t* B, float* C, bool a_kcontig, bool b_ncontig,
+               hipStream_t s) {
+  if (g.kin <= 0 || g.kin % BK16 != 0) throw std::runtime_error("gemm_bf16: inner K block must be a multiple of 32");
+  if (g.M == 0 || g.N == 0 || g.batch == 0) return;
+  dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
+  if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm: grid too large");
+  if (a_kcontig && b_ncontig)
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, s, g, A, B, C);
+  else if (a_kcontig && !b_ncontig)
+    hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, s, g, A, B, C);
+  else if (!a_kcontig && b_ncontig)
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, s, g, A, B, C);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, s, g, A, B, C);
+  HIPCHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Sparse MPO mixing (memory bound).  One output channel per blockIdx.x so that
+// all channels of one position chunk run back to back and share the chunk of
+// every input channel through L2.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void mix_kernel(const int* __restrict__ ptr, const int* __restrict__ src,
+                                                  const T* __restrict__ op, const T* __restrict__ in,
+                                                  long long in_cs, T* __restrict__ out, long long out_cs, int O,
+                                                  int I) {
+  const int c = blockIdx.x;
+  const long long p = (long long)blockIdx.y * blockDim.x + threadIdx.x;
+  const long long npos = (long long)O * I;
+  if (p >= npos) return;
+  const long long o = p / I, i = p % I;
+  const long long off = o * 4LL * I + i;
+  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  const int e0 = ptr[c], e1 = ptr[c + 1];
+  for (int e = e0; e < e1; ++e) {
+    const T* w = op + 16LL * e;
+    const T* x = in + (long long)src[e] * in_cs + off;
+    const T v0 = x[0], v1 = x[I], v2 = x[2LL * I], v3 = x[3LL * I];
+    acc0 += w[0] * v0 + w[1] * v1 + w[2] * v2 + w[3] * v3;
+    acc1 += w[4] * v0 + w[5] * v1 + w[6] * v2 + w[7] * v3;
+    acc2 += w[8] * v0 + w[9] * v1 + w[10] * v2 + w[11] * v3;
+    acc3 += w[12] * v0 + w[13] * v1 + w[14] * v2 + w[15] * v3;
+  }
+  T* y = out + (long long)c * out_cs + off;
+  y[0] = acc0;
+  y[I] = acc1;
+  y[2LL * I] = acc2;
+  y[3LL * I] = acc3;
+}
+
+template <typename T>
+void mix(int nout, const int* ptr, const int* src, const T* op, const T* in, long long in_cs, T* out,
+         long long out_cs, int O, int I, hipStream_t s) {
+  if (nout == 0 || O == 0 || I == 0) return;
+  const long long npos = (long long)O * I;
+  const long long chunks = (npos + 255) / 256;
+  if (chunks > 65535) throw std::runtime_error("mix: too many positions");
+  if (nout > 2147483647) throw std::runtime_error("mix: too many channels");
+  dim3 grid(nout, (unsigned)chunks);
+  hipLaunchKernelGGL((mix_kernel<T>), grid, dim3(256), 0, s, ptr, src, op, in, in_cs, out, out_cs, O, I);
+  HIPCHECK(hipGetLastError());
+}
+
+template void mix<double>(int, const int*, const int*, const double*, const double*, long long, double*, long long,
+                          int, int, hipStream_t);
+template void mix<float>(int, const int*, const int*, const float*, const float*, long long, float*, long long, int,
+                         int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// vector kernels
+// ---------------------------------------------------------------------------
+static inline unsigned nblocks(size_t n, int per = 256) {
+  size_t b = (n + per - 1) / per;
+  return (unsigned)std::min<size_t>(b, 1u << 20);
+}
+
+__global__ void fill_kernel(uint32_t* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+__global__ void fill8_kernel(uint8_t* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+void fill(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (bytes % 4 == 0 && ((uintptr_t)p % 4) == 0)
+    hipLaunchKernelGGL(fill_kernel, dim3(nblocks(bytes / 4)), dim3(256), 0, s, (uint32_t*)p, bytes / 4);
+  else
+    hipLaunchKernelGGL(fill8_kernel, dim3(nblocks(bytes)), dim3(256), 0, s, (uint8_t*)p, bytes);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void scale_kernel(double* x, double a, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] *= a;
+}
+void scale(double* x, double a, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(scale_kernel, dim3(nblocks(n)), dim3(256), 0, s, x, a, n);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void axpy_kernel(double* y, double a, const double* x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+void axpy(double* y, double a, const double* x, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(axpy_kernel, dim3(nblocks(n)), dim3(256), 0, s, y, a, x, n);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void axpby_kernel(double* z, double a, const double* x, double b, const double* y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    z[i] = a * x[i] + b * y[i];
+}
+void axpby(double* z, double a, const double* x, double b, const double* y, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3(nblocks(n)), dim3(256), 0, s, z, a, x, b, y, n);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void mask_kernel(double* x, const uint8_t* m, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!m[i]) x[i] = 0.0;
+}
+void mask_apply(double* x, const uint8_t* mask, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(mask_kernel, dim3(nblocks(n)), dim3(256), 0, s, x, mask, n);
+  HIPCHECK(hipGetLastError());
+}
+
+// two-pass deterministic multi-dot: grid (nblk, m)
+__global__ __launch_bounds__(256) void mdot_partial(const double* V, size_t ldv, const double* w, size_t n,
+                                                    double* partial, int nblk) {
+  const int i = blockIdx.y;
+  const double* v = V + (size_t)i * ldv;
+  double s = 0.0;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)nblk * blockDim.x) s += v[k] * w[k];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)i * nblk + blockIdx.x] = red[0];
+}
+__global__ void mdot_final(const double* partial, int nblk, int m, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(size_t)i * nblk + b];
+  out[i] = s;
+}
+void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, double* out_dev, double* partial,
+               int nblk, hipStream_t s) {
+  if (m <= 0) return;
+  if (m > 65535) throw std::runtime_error("multi_dot: too many vectors");
+  hipLaunchKernelGGL(mdot_partial, dim3(nblk, m), dim3(256), 0, s, V, ldv, w, n, partial, nblk);
+  HIPCHECK(hipGetLastError());
+  hipLaunchKernelGGL(mdot_final, dim3((m + 63) / 64), dim3(64), 0, s, partial, nblk, m, out_dev);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void lincomb_kernel(const double* V, size_t ldv, int m, const double* c, double* out, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += c[i] * V[(size_t)i * ldv + k];
+    out[k] = s;
+  }
+}
+void lincomb(const double* V, size_t ldv, int m, const double* c_dev, double* out, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(lincomb_kernel, dim3(nblocks(n)), dim3(256), 0, s, V, ldv, m, c_dev, out, n);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void cvt_d2f(const double* a, float* b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+__global__ void cvt_f2d(const float* a, double* b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (double)a[i];
+}
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+__global__ void cvt_d2bf(const double* a, uint16_t* b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = f32_to_bf16_rne((float)a[i]);
+}
+void convert_f64_f32(const double* a, float* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(cvt_d2f, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
+  HIPCHECK(hipGetLastError());
+}
+void convert_f64_f32_op(const double* a, float* b, size_t n, hipStream_t s) { convert_f64_f32(a, b, n, s); }
+void convert_f32_f64(const float* a, double* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(cvt_f2d, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
+  HIPCHECK(hipGetLastError());
+}
+void convert_f64_bf16(const double* a, uint16_t* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(cvt_d2bf, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void gather2d_kernel(const double* src, long long lds, const int* rows, int nr, const int* cols, int nc,
+                                double* dst, bool colmajor) {
+  const long long tot = (long long)nr * nc;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    int i, j;
+    if (colmajor) { i = (int)(t % nr); j = (int)(t / nr); }
+    else { i = (int)(t / nc); j = (int)(t % nc); }
+    const double v = src[(long long)rows[i] * lds + cols[j]];
+    if (colmajor) dst[(long long)j * nr + i] = v; else dst[(long long)i * nc + j] = v;
+  }
+}
+void gather2d(const double* src, long long lds, const int* rows, int nr, const int* cols, int nc, double* dst,
+              bool colmajor, hipStream_t s) {
+  if (nr <= 0 || nc <= 0) return;
+  hipLaunchKernelGGL(gather2d_kernel, dim3(nblocks((size_t)nr * nc)), dim3(256), 0, s, src, lds, rows, nr, cols, nc,
+                     dst, colmajor);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void scatter2d_kernel(const double* src, long long sr, long long sc, const int* rows, int nr,
+                                 const int* cols, int nc, double* dst, long long ldd, double alpha, const double* rs,
+                                 const double* cs, int tri) {
+  const long long tot = (long long)nr * nc;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t % nr);
+    const int j = (int)(t / nr);
+    double v = 0.0;
+    if (tri == 0 || (tri == 1 && i <= j) || (tri == 2 && j <= i)) {
+      v = alpha * src[i * sr + j * sc];
+      if (rs) v *= rs[i];
+      if (cs) v *= cs[j];
+    }
+    dst[(long long)rows[i] * ldd + cols[j]] = v;
+  }
+}
+void scatter2d(const double* src, long long sr, long long sc, const int* rows, int nr, const int* cols, int nc,
+               double* dst, long long ldd, double alpha, const double* rs, const double* cs, int tri, hipStream_t s) {
+  if (nr <= 0 || nc <= 0) return;
+  hipLaunchKernelGGL(scatter2d_kernel, dim3(nblocks((size_t)nr * nc)), dim3(256), 0, s, src, sr, sc, rows, nr, cols,
+                     nc, dst, ldd, alpha, rs, cs, tri);
+  HIPCHECK(hipGetLastError());
+}
+
+__global__ void copy3d_kernel(const double* src, long long s0, long long s1, double* dst, long long d0, long long d1,
+                              int n0, int n1, int n2, double alpha) {
+  const long long tot = (long long)n0 * n1 * n2;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(t % n2);
+    const long long r = t / n2;
+    const int j = (int)(r % n1);
+    const int i = (int)(r / n1);
+    dst[i * d0 + j * d1 + k] = alpha * src[i * s0 + j * s1 + k];
+  }
+}
+void copy3d(const double* src, long long s0, long long s1, double* dst, long long d0, long long d1, int n0, int n1,
+            int n2, double alpha, hipStream_t s) {
+  if (n0 <= 0 || n1 <= 0 || n2 <= 0) return;
+  hipLaunchKernelGGL(copy3d_kernel, dim3(nblocks((size_t)n0 * n1 * n2)), dim3(256), 0, s, src, s0, s1, dst, d0, d1, n0,
+                     n1, n2, alpha);
+  HIPCHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// gradient of the sparse MPO entries (backward of the mixing stages)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void entry_grad_kernel(const int* gch, const int* tch, const T* G, long long g_cs,
+                                                         const T* Tin, long long t_cs, int O, int I, double* gop) {
+  const int e = blockIdx.x;
+  const T* g = G + (long long)gch[e] * g_cs;
+  const T* t = Tin + (long long)tch[e] * t_cs;
+  const long long npos = (long long)O * I;
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  for (long long p = threadIdx.x; p < npos; p += blockDim.x) {
+    const long long o = p / I, i = p % I;
+    const long long off = o * 4LL * I + i;
+    double gv[4], tv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      gv[s] = (double)g[off + s * (long long)I];
+      tv[s] = (double)t[off + s * (long long)I];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a * 4 + b] += gv[a] * tv[b];
+  }
+  __shared__ double red[256];
+  for (int j = 0; j < 16; ++j) {
+    red[threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) gop[16LL * e + j] += red[0];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void entry_grad(int nnz, const int* gch, const int* tch, const T* G, long long g_cs, const T* Tin, long long t_cs,
+                int O, int I, double* gop, hipStream_t s) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL((entry_grad_kernel<T>), dim3(nnz), dim3(256), 0, s, gch, tch, G, g_cs, Tin, t_cs, O, I, gop);
+  HIPCHECK(hipGetLastError());
+}
+template void entry_grad<double>(int, const int*, const int*, const double*, long long, const double*, long long, int,
+                                 int, double*, hipStream_t);
+
+__global__ void transpose_kernel(const double* in, double* out, int n, int r, int c) {
+  const long long tot = (long long)n * r * c;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(t % c);
+    const long long q = t / c;
+    const int i = (int)(q % r);
+    const long long b = q / r;
+    out[(b * c + j) * r + i] = in[t];
+  }
+}
+void transpose_batched(const double* in, double* out, int n, int r, int c, hipStream_t s) {
+  if ((long long)n * r * c == 0) return;
+  hipLaunchKernelGGL(transpose_kernel, dim3(nblocks((size_t)n * r * c)), dim3(256), 0, s, in, out, n, r, c);
+  HIPCHECK(hipGetLastError());
+}
+
+}  // namespace tt

@@ -84,7 +84,7 @@ def _terms(h, B, tol=0.0):
     coef = h[p, q]
     keep = np.abs(coef) > tol
     codes = np.stack([4 * p + s, 4 * q + 2 + s], axis=1)[keep]
-    out.append((codes, coef[keep]))
+    out.append((codes, coef[keep], (p * L + q)[keep]))
     # two-body: a+_{p s} a+_{r t} a_{u t} a_{q s}, coefficient (pq|ru)/2
     eri = np.einsum("kpq,krs->pqrs", B, B)
     idx = np.nonzero(np.abs(eri) > tol)
@@ -94,7 +94,7 @@ def _terms(h, B, tol=0.0):
         for sb in range(2):
             ok = ~(((pp == rr) & (sa == sb)) | ((uu == qq) & (sa == sb)))
             c = np.stack([4 * pp + sa, 4 * rr + sb, 4 * uu + 2 + sb, 4 * qq + 2 + sa], axis=1)[ok]
-            out.append((c, vals[ok]))
+            out.append((c, vals[ok], np.full(int(ok.sum()), -1)))
     return out
 
 
@@ -110,7 +110,7 @@ def _canonical(codes, coef):
         for j in range(i + 1, n):
             inv += key[:, i] > key[:, j]
     sign = np.where(inv % 2 == 0, 1.0, -1.0)
-    return np.take_along_axis(codes, order, axis=1), coef * sign
+    return np.take_along_axis(codes, order, axis=1), coef * sign, sign
 
 
 class _Coder:
@@ -177,11 +177,12 @@ def build_mpo(h, B, switch=None, tol=0.0) -> MPO:
     ev_site, ev_b, ev_a, ev_loc, ev_coef, ev_sw = [], [], [], [], [], []
     seg_code, seg_lo, seg_hi = [], [], []
 
-    for codes, coef in _terms(h, B, tol):
+    dh_site, dh_b, dh_a, dh_loc, dh_sign, dh_tag = [], [], [], [], [], []
+    for codes, coef, tag in _terms(h, B, tol):
         if len(codes) == 0:
             continue
         nops = codes.shape[1]
-        o, cf = _canonical(codes, coef)
+        o, cf, sgn = _canonical(codes, coef)
         site = o // 4
         typ = o % 4
         T = len(o)
@@ -236,6 +237,9 @@ def build_mpo(h, B, switch=None, tol=0.0) -> MPO:
             sw = np.isin(chb // cd.big, _NORMAL) & ~np.isin(cha // cd.big, _NORMAL)
             ev_site.append(t); ev_b.append(chb); ev_a.append(cha); ev_loc.append(loc)
             ev_coef.append(np.where(sw, cf[sel], 0.0)); ev_sw.append(sw)
+            if nops == 2 and np.any(sw):
+                dh_site.append(t[sw]); dh_b.append(chb[sw]); dh_a.append(cha[sw]); dh_loc.append(loc[sw])
+                dh_sign.append(sgn[sel][sw]); dh_tag.append(tag[sel][sw])
             # the channel after the event lives on bonds t+1 .. (next event site)
             seg_code.append(cha); seg_lo.append(t + 1)
         # segment upper ends: next event site per term, computed by sorting events
@@ -278,6 +282,7 @@ def build_mpo(h, B, switch=None, tol=0.0) -> MPO:
         chan_q.append(_channel_charge(cd, cc))
 
     As, Bs, Ops = [], [], []
+    key_index, idx_maps = [], []
     for k in range(L):
         idx_b = {int(c): i for i, c in enumerate(chan_codes[k])}
         idx_a = {int(c): i for i, c in enumerate(chan_codes[k + 1])}
@@ -315,10 +320,54 @@ def build_mpo(h, B, switch=None, tol=0.0) -> MPO:
                 else:
                     ent[kk] = M
         keys = sorted(ent)
+        key_index.append({kk: i for i, kk in enumerate(keys)})
+        idx_maps.append((idx_b, idx_a))
         As.append(np.array([k_[0] for k_ in keys], dtype=np.int32))
         Bs.append(np.array([k_[1] for k_ in keys], dtype=np.int32))
         Ops.append(np.array([ent[k_] for k_ in keys]).reshape(-1, 4, 4))
-    return MPO(L, m, R, As, Bs, Ops, chan_q, chan_codes)
+    mpo = MPO(L, m, R, As, Bs, Ops, chan_q, chan_codes)
+    # derivative of every entry with respect to h_pq (one-body switch transitions)
+    dh = []
+    if dh_site:
+        ds = np.concatenate(dh_site); db = np.concatenate(dh_b); da = np.concatenate(dh_a)
+        dl = np.concatenate(dh_loc); dg = np.concatenate(dh_sign); dt = np.concatenate(dh_tag)
+        for t_, b_, a_, l_, g_, tg in zip(ds, db, da, dl, dg, dt):
+            ib, ia = idx_maps[int(t_)]
+            e = key_index[int(t_)][(ib[int(b_)], ia[int(a_)])]
+            dh.append((int(t_), e, int(tg) // L, int(tg) % L, g_ * _local_matrix(int(l_))))
+    mpo.dh = dh
+    mpo.blocks = _switch_blocks(mpo, cd)
+    return mpo
+
+
+def _switch_blocks(mpo, cd):
+    """Per site ``(p0, p1, q0, q1)``: the coefficient block P(bond m) -> Q(bond m+1)
+    at the switch site (identity local operator times the integral), else -1s."""
+    out = []
+    for k in range(mpo.L):
+        tb = mpo.chan_codes[k] // cd.big
+        ta = mpo.chan_codes[k + 1] // cd.big
+        pidx = np.nonzero(tb == T_P)[0]
+        qidx = np.nonzero(ta == T_Q)[0]
+        if len(pidx) and len(qidx):
+            p0, p1, q0, q1 = int(pidx[0]), int(pidx[-1]) + 1, int(qidx[0]), int(qidx[-1]) + 1
+            assert p1 - p0 == len(pidx) and q1 - q0 == len(qidx)
+            inblk = (mpo.A[k] >= p0) & (mpo.A[k] < p1) & (mpo.B[k] >= q0) & (mpo.B[k] < q1)
+            ops = mpo.ops[k][inblk]
+            eye = ops[:, 0, 0][:, None, None] * np.eye(4)[None]
+            assert np.abs(ops - eye).max(initial=0.0) <= 1e-14 * max(1.0, np.abs(ops).max(initial=0.0))
+            out.append((p0, p1, q0, q1))
+        else:
+            out.append((-1, -1, -1, -1))
+    return out
+
+
+def h_gradient(mpo, gops):
+    """dE/dh_pq from per-entry gradients ``gops[k][e][4][4]`` of every MPO entry."""
+    g = np.zeros((mpo.L, mpo.L))
+    for k, e, p, q, D in mpo.dh:
+        g[p, q] += float(np.sum(np.asarray(gops[k][e]).reshape(4, 4) * D))
+    return g
 
 
 def _channel_charge(cd, codes):
