@@ -179,6 +179,13 @@ int tt_heff_energy_grad_dev(void* ctx, int rl, int rr, int RA, int RB, int RC, c
  * recomputed, not stored, outside the active chain. */
 int tt_energy_mpo_grad(void* ctx, double* E, double* const* gops);
 
+/* Per-kernel timing of the effective-Hamiltonian products (HIP events on the
+ * library stream).  enable != 0 turns recording on for subsequent products.
+ * stats (may be NULL) receives 4 rows [ms, launches, algorithmic flops,
+ * algorithmic bytes] for: L.x GEMM, site-1 mix, site-2 mix, R GEMM, with true
+ * (unpadded) sizes; reset != 0 clears the accumulators after copying. */
+int tt_kernel_timing(void* ctx, int enable, double* stats, int reset);
+
 #ifdef __cplusplus
 }
 #endif

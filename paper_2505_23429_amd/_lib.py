@@ -20,7 +20,7 @@ TT_MAX_SUB = 64
 EXPORTS = (
     "tt_default_opts", "tt_create", "tt_destroy", "tt_last_error", "tt_set_mpo", "tt_set_mps", "tt_get_mps",
     "tt_energy", "tt_local_solve", "tt_coarse_correct", "tt_sweep", "tt_dmrg2", "tt_heff_apply_dev",
-    "tt_env_update_dev", "tt_heff_energy_grad_dev", "tt_energy_mpo_grad", "tt_gemm_dev",
+    "tt_env_update_dev", "tt_heff_energy_grad_dev", "tt_energy_mpo_grad", "tt_gemm_dev", "tt_kernel_timing",
 )
 
 
@@ -92,6 +92,8 @@ def load():
     lib.tt_heff_energy_grad_dev.restype = I
     lib.tt_gemm_dev.argtypes = [VP, I, I, I, I, I, I, P(C.c_longlong), I, I, D, D, VP, VP, VP]
     lib.tt_gemm_dev.restype = I
+    lib.tt_kernel_timing.argtypes = [VP, I, P(D), I]
+    lib.tt_kernel_timing.restype = I
     lib.tt_energy_mpo_grad.argtypes = [VP, P(D), P(P(D))]
     lib.tt_energy_mpo_grad.restype = I
     _lib = lib

@@ -165,6 +165,14 @@ class Context:
         rc = self._check(self.lib.tt_dmrg2(self.h, nsweeps, E.ctypes.data_as(C.POINTER(C.c_double))))
         return E, rc
 
+    def kernel_timing(self, enable=True, reset=False):
+        """Per-kernel stats of the products: rows (Lx GEMM, mix 1, mix 2, R GEMM),
+        columns (ms, launches, algorithmic flops, algorithmic bytes)."""
+        st = np.zeros(16)
+        self._check(self.lib.tt_kernel_timing(self.h, int(enable), st.ctypes.data_as(C.POINTER(C.c_double)),
+                                              int(reset)))
+        return st.reshape(4, 4)
+
     def mpo_gradient(self, mpo):
         """dE/dW for every MPO entry of E = <U|H|U> (normalised current iterate)."""
         g = [np.zeros((len(a), 16)) for a in mpo.A]

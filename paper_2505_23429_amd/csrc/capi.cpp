@@ -292,6 +292,19 @@ int tt_heff_energy_grad_dev(void* ctx, int rl, int rr, int RA, int RB, int RC, c
   });
 }
 
+int tt_kernel_timing(void* ctx, int enable, double* stats, int reset) {
+  return guard(ctx, [&](Engine& E) {
+    if (stats)
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) stats[i * 4 + j] = E.kstat[i][j];
+    if (reset)
+      for (auto& r : E.kstat)
+        for (double& v : r) v = 0.0;
+    E.kt_on = enable != 0;
+    return TT_OK;
+  });
+}
+
 int tt_energy_mpo_grad(void* ctx, double* En, double* const* gops) {
   return guard(ctx, [&](Engine& E) {
     if (!En || !gops) throw std::invalid_argument("NULL pointer");

@@ -285,6 +285,36 @@ void Engine::set_mpo(int L_, const int* R, const int* nnz, const int32_t* const*
 }
 
 // ---------------------------------------------------------------------------
+// per-kernel timing of the effective-Hamiltonian product (HIP events on the
+// library stream; enabled by tt_kernel_timing)
+// ---------------------------------------------------------------------------
+void Engine::kt_mark(int i) {
+  if (!kt_on) return;
+  if (!kt_ev[i]) HC(hipEventCreate(&kt_ev[i]));
+  HC(hipEventRecord(kt_ev[i], stream));
+}
+void Engine::kt_finish(int elem, int RB) {
+  if (!kt_on) return;
+  HC(hipEventSynchronize(kt_ev[4]));
+  float ms[4];
+  for (int i = 0; i < 4; ++i) HC(hipEventElapsedTime(&ms[i], kt_ev[i], kt_ev[i + 1]));
+  // algorithmic work with the true (unpadded) sizes of the current window
+  const double rl = cur_rl, rr = cur_rr, slab = rl * 16.0 * rr;
+  const double f1 = 2.0 * cur_RA * rl * rl * 16.0 * rr;
+  const double f4 = 2.0 * 16.0 * rl * rr * rr * cur_RC;
+  const double b1 = (double)elem * slab * (cur_RA + RB);
+  const double b2 = (double)elem * slab * (RB + cur_RC);
+  const double fl[4] = {f1, 0.0, 0.0, f4};
+  const double by[4] = {0.0, b1, b2, 0.0};
+  for (int i = 0; i < 4; ++i) {
+    kstat[i][0] += ms[i];
+    kstat[i][1] += 1.0;
+    kstat[i][2] += fl[i];
+    kstat[i][3] += by[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // effective Hamiltonian product (K1)
 //   T1[A][a'][s1 s2 b] = L_A x               batched MFMA GEMM
 //   T2[B][a'][s1'][s2 b] = W1 mix over s1    sparse, memory bound
@@ -311,10 +341,14 @@ void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB,
   g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkb = 0; g.sAkk = 1;
   g.sBb = 0; g.sBkb = 0; g.sBkk = 16LL * rr; g.sBn = 1;
   g.sCb = slab; g.sCm = 16LL * rr; g.alpha = 1.0; g.beta = 0.0;
+  kt_mark(0);
   gemm<T>(g, Lv, x, T1, true, true, stream);
+  kt_mark(1);
   mix<T>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), siteop_ops<T>(w1), T1, slab, T2, slab, rl, 4 * rr, stream);
+  kt_mark(2);
   T* T3 = ws0.as<T>();
   mix<T>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), siteop_ops<T>(w2), T2, slab, T3, slab, 4 * rl, rr, stream);
+  kt_mark(3);
   GemmArgs h{};
   h.M = 16 * rl; h.N = rr; h.K = RC * rr; h.batch = 1; h.kin = rr;
   h.sAb = 0; h.sAm = rr; h.sAkb = slab; h.sAkk = 1;
@@ -326,6 +360,8 @@ void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB,
     h.beta = 1.0;
     gemm<T>(h, T2 + (long long)P0 * slab, Rtil, y, true, false, stream);
   }
+  kt_mark(4);
+  kt_finish(sizeof(T), RB);
 }
 template void Engine::heff<double>(int, int, int, const double*, const SiteOp&, int, const SiteOp&, int, const double*,
                                    const double*, double*, const double*, int, int);
@@ -361,10 +397,14 @@ void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp&
   g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkb = 0; g.sAkk = 1;
   g.sBb = 0; g.sBkb = 0; g.sBkk = 16LL * rr; g.sBn = 1;
   g.sCb = slab; g.sCm = 16LL * rr; g.alpha = 1.0; g.beta = 0.0;
+  kt_mark(0);
   gemm_bf16(g, Lv, x, T1, true, true, stream);
+  kt_mark(1);
   mix<float>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), w1.op32.as<float>(), T1, slab, T2, slab, rl, 4 * rr, stream);
+  kt_mark(2);
   float* T3 = ws0.as<float>();
   mix<float>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), w2.op32.as<float>(), T2, slab, T3, slab, 4 * rl, rr, stream);
+  kt_mark(3);
   ws2.ensure(sizeof(uint16_t) * slab * std::max(RC, nP));
   uint16_t* T3b = ws2.as<uint16_t>();
   round_bf16(T3, T3b, (size_t)slab * RC, stream);
@@ -380,6 +420,8 @@ void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp&
     h.beta = 1.0;
     gemm_bf16(h, T3b, Rtil, y, true, false, stream);
   }
+  kt_mark(4);
+  kt_finish(4, RB);
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,6 +1049,7 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
 
 static void window_matvec(Engine& E, Window& w, const double* x, double* y, int prec) {
   const size_t n = (size_t)w.rlp * 16 * w.rrp;
+  E.cur_rl = w.rl; E.cur_rr = w.rr; E.cur_RA = w.RA; E.cur_RC = w.RC;
   HC(hipEventRecord(E.ev0, E.stream));
   if (prec == TT_F64) {
     E.heff<double>(w.rlp, w.rrp, w.RAx, w.Lx.as<double>(), *w.w1, w.RB, *w.w2, w.RC, w.R64, x, y,
@@ -1251,8 +1294,30 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   // environment caches: Lenv[k] at bond k from U (k = 0..L-1), Renv[k] from V (k = 2..L)
   Lenv.clear(); Lenv.resize(L + 1);
   Renv.clear(); Renv.resize(L + 1);
-  env_unit(Lenv[0], 1);
-  for (int k = 0; k + 1 < L; ++k) env_left(Lenv[k], U[k], U[k], k, Lenv[k + 1]);
+  {
+    // keep left environments only where they are read: subdomain starts and bond L-1
+    std::vector<char> need(L + 1, 0);
+    int st = 0;
+    for (int j = 0; j < nsub; ++j) {
+      need[st] = 1;
+      st += lengths[j];
+    }
+    need[L - 1] = 1;
+    Env cur;
+    env_unit(cur, 1);
+    for (int k = 0; k + 1 < L; ++k) {
+      if (need[k]) {
+        Lenv[k].R = cur.R; Lenv[k].rb = cur.rb; Lenv[k].rk = cur.rk;
+        Lenv[k].d.ensure(cur.d.n);
+        HC(hipMemcpyAsync(Lenv[k].d.p, cur.d.p, cur.d.n, hipMemcpyDeviceToDevice, stream));
+      }
+      Env nx;
+      env_left(cur, U[k], U[k], k, nx);
+      cur = std::move(nx);
+    }
+    Lenv[L - 1] = std::move(cur);
+    HC(hipStreamSynchronize(stream));
+  }
   env_unit(Renv[L], 1);
   for (int k = L - 1; k >= 2; --k) env_right(Renv[k + 1], Vc[k], Vc[k], k, Renv[k]);
   // Step 2: subdomain sweeps
@@ -1832,6 +1897,8 @@ void Engine::mpo_grad(double* En, double* const* gops) {
     }
     auto it = seg.find(bond);
     if (it != seg.end()) return it->second;
+    auto ck = ckpt.find(bond);
+    if (ck != ckpt.end()) return ck->second;
     // recompute from the next checkpoint at or above `bond`
     seg.clear();
     int top = L;
@@ -1854,7 +1921,9 @@ void Engine::mpo_grad(double* En, double* const* gops) {
       seg[k] = std::move(keep);
       cur = std::move(o);
     }
-    return seg[bond];
+    auto fin = seg.find(bond);
+    if (fin == seg.end() || fin->second.d.p == nullptr) throw std::runtime_error("right environment missing");
+    return fin->second;
   };
   Env Lk;
   env_unit(Lk, 1);

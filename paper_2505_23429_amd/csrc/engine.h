@@ -116,6 +116,15 @@ class Engine {
   double flops_heff = 0.0, sec_heff = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
+  // per-kernel statistics of the effective-Hamiltonian product:
+  // [stage][ms, launches, algorithmic flops, algorithmic bytes]
+  // stage 0 = L.x GEMM, 1 = site-1 mix, 2 = site-2 mix, 3 = R GEMM
+  bool kt_on = false;
+  hipEvent_t kt_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double kstat[4][4] = {};
+  int cur_rl = 0, cur_rr = 0, cur_RA = 0, cur_RC = 0;
+  void kt_mark(int i);
+  void kt_finish(int elem, int RB);
 
   // setup
   void set_mpo(int L, const int* R, const int* nnz, const int32_t* const* A, const int32_t* const* B,

@@ -163,6 +163,7 @@ template <typename T>
 void gemm(const GemmArgs& g, const T* A, const T* B, T* C, bool a_kcontig, bool b_ncontig, hipStream_t s) {
   check_args(g);
   if (g.M == 0 || g.N == 0 || g.batch == 0) return;
+  if (!C || (g.K > 0 && (!A || !B))) throw std::runtime_error("gemm: null operand");
   if (g.K == 0) {
     // C = beta*C : run the kernel anyway (loop body skipped) for uniform semantics
   }
@@ -298,6 +299,7 @@ void gemm_bf16(const GemmArgs& g, const uint16_t* A, const uint16_t* B, float* C
                hipStream_t s) {
   if (g.kin <= 0 || g.kin % BK16 != 0) throw std::runtime_error("gemm_bf16: inner K block must be a multiple of 32");
   if (g.M == 0 || g.N == 0 || g.batch == 0) return;
+  if (!C || (g.K > 0 && (!A || !B))) throw std::runtime_error("gemm: null operand");
   dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
   if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm: grid too large");
   if (a_kcontig && b_ncontig)
@@ -349,6 +351,7 @@ template <typename T>
 void mix(int nout, const int* ptr, const int* src, const T* op, const T* in, long long in_cs, T* out,
          long long out_cs, int O, int I, hipStream_t s) {
   if (nout == 0 || O == 0 || I == 0) return;
+  if (!ptr || !src || !op || !in || !out) throw std::runtime_error("mix: null operand");
   const long long npos = (long long)O * I;
   const long long chunks = (npos + 255) / 256;
   if (chunks > 65535) throw std::runtime_error("mix: too many positions");
@@ -614,6 +617,7 @@ template <typename T>
 void entry_grad(int nnz, const int* gch, const int* tch, const T* G, long long g_cs, const T* Tin, long long t_cs,
                 int O, int I, double* gop, hipStream_t s) {
   if (nnz <= 0) return;
+  if (!gch || !tch || !G || !Tin || !gop) throw std::runtime_error("entry_grad: null operand");
   hipLaunchKernelGGL((entry_grad_kernel<T>), dim3(nnz), dim3(256), 0, s, gch, tch, G, g_cs, Tin, t_cs, O, I, gop);
   HIPCHECK(hipGetLastError());
 }

@@ -156,7 +156,7 @@ def _local_code(types, parity):
     return c + 625 * parity
 
 
-def _local_matrix(code):
+def _local_matrix_uncached(code):
     par = code // 625
     c = code % 625
     M = np.eye(4)
@@ -167,6 +167,13 @@ def _local_matrix(code):
     if par:
         M = M @ PARITY
     return M
+
+
+_LOCAL_TABLE = np.stack([_local_matrix_uncached(c).reshape(16) for c in range(1250)])
+
+
+def _local_matrix(code):
+    return _LOCAL_TABLE[code].reshape(4, 4)
 
 
 def build_mpo(h, B, switch=None, tol=0.0) -> MPO:
@@ -281,50 +288,44 @@ def build_mpo(h, B, switch=None, tol=0.0) -> MPO:
         R.append(len(cc))
         chan_q.append(_channel_charge(cd, cc))
 
-    As, Bs, Ops = [], [], []
-    key_index, idx_maps = [], []
+    table = _LOCAL_TABLE
+    order = np.argsort(ev_site, kind="stable")
+    ev_site, ev_b, ev_a, ev_loc, ev_coef, ev_sw = (ev_site[order], ev_b[order], ev_a[order], ev_loc[order],
+                                                    ev_coef[order], ev_sw[order])
+    bounds = np.searchsorted(ev_site, np.arange(L + 1))
+    As, Bs, Ops, Keys = [], [], [], []
+    loc_I, loc_P = 0, 625
     for k in range(L):
-        idx_b = {int(c): i for i, c in enumerate(chan_codes[k])}
-        idx_a = {int(c): i for i, c in enumerate(chan_codes[k + 1])}
-        ent = {}
+        cb, ca = chan_codes[k], chan_codes[k + 1]
+        Ra = len(ca)
         # pass-through entries
-        both = np.intersect1d(chan_codes[k], chan_codes[k + 1])
-        for c in both:
-            t = int(c // cd.big)
-            M = PARITY if t in (T_S, T_C) else np.eye(4)
-            ent[(idx_b[int(c)], idx_a[int(c)])] = M.copy()
-        sel = ev_site == k
-        b_, a_, l_, c_, s_ = ev_b[sel], ev_a[sel], ev_loc[sel], ev_coef[sel], ev_sw[sel]
-        # non-switch events: unique (b, a) with a fixed local operator
+        both = np.intersect1d(cb, ca)
+        tb = both // cd.big
+        pb = np.searchsorted(cb, both)
+        pa = np.searchsorted(ca, both)
+        ploc = np.where((tb == T_S) | (tb == T_C), loc_P, loc_I)
+        sl = slice(bounds[k], bounds[k + 1])
+        b_, a_, l_, c_, s_ = ev_b[sl], ev_a[sl], ev_loc[sl], ev_coef[sl], ev_sw[sl]
+        ib = np.searchsorted(cb, b_)
+        ia = np.searchsorted(ca, a_)
+        # non-switch events: one fixed local operator per (b, a)
         ns = ~s_
-        if np.any(ns):
-            key = np.stack([b_[ns], a_[ns], l_[ns]], axis=1)
-            uk = np.unique(key, axis=0)
-            for bb, aa, ll in uk:
-                kk = (idx_b[int(bb)], idx_a[int(aa)])
-                if kk in ent:
-                    raise RuntimeError("conflicting MPO transition")
-                ent[kk] = _local_matrix(int(ll))
-        if np.any(s_):
-            key = np.stack([b_[s_], a_[s_], l_[s_]], axis=1)
-            uk, inv2 = np.unique(key, axis=0, return_inverse=True)
-            csum = np.zeros(len(uk))
-            np.add.at(csum, inv2.ravel(), c_[s_])
-            for (bb, aa, ll), cv in zip(uk, csum):
-                if cv == 0.0:
-                    continue
-                kk = (idx_b[int(bb)], idx_a[int(aa)])
-                M = cv * _local_matrix(int(ll))
-                if kk in ent:
-                    ent[kk] = ent[kk] + M
-                else:
-                    ent[kk] = M
-        keys = sorted(ent)
-        key_index.append({kk: i for i, kk in enumerate(keys)})
-        idx_maps.append((idx_b, idx_a))
-        As.append(np.array([k_[0] for k_ in keys], dtype=np.int32))
-        Bs.append(np.array([k_[1] for k_ in keys], dtype=np.int32))
-        Ops.append(np.array([ent[k_] for k_ in keys]).reshape(-1, 4, 4))
+        key_ns = np.unique((ib[ns].astype(np.int64) * Ra + ia[ns]) * 1250 + l_[ns])
+        kb_ns = key_ns // 1250
+        if len(np.unique(kb_ns)) != len(kb_ns):
+            raise RuntimeError("conflicting MPO transition")
+        all_key = np.concatenate([pb.astype(np.int64) * Ra + pa, kb_ns, ib[s_].astype(np.int64) * Ra + ia[s_]])
+        all_loc = np.concatenate([ploc, key_ns % 1250, l_[s_]])
+        all_cf = np.concatenate([np.ones(len(pb)), np.ones(len(kb_ns)), c_[s_]])
+        keep = all_cf != 0.0
+        all_key, all_loc, all_cf = all_key[keep], all_loc[keep], all_cf[keep]
+        uk, inv = np.unique(all_key, return_inverse=True)
+        ops = np.zeros((len(uk), 16))
+        np.add.at(ops, inv.ravel(), all_cf[:, None] * table[all_loc])
+        Keys.append(uk)
+        As.append((uk // Ra).astype(np.int32))
+        Bs.append((uk % Ra).astype(np.int32))
+        Ops.append(ops.reshape(-1, 4, 4))
     mpo = MPO(L, m, R, As, Bs, Ops, chan_q, chan_codes)
     # derivative of every entry with respect to h_pq (one-body switch transitions)
     dh = []
@@ -332,9 +333,12 @@ def build_mpo(h, B, switch=None, tol=0.0) -> MPO:
         ds = np.concatenate(dh_site); db = np.concatenate(dh_b); da = np.concatenate(dh_a)
         dl = np.concatenate(dh_loc); dg = np.concatenate(dh_sign); dt = np.concatenate(dh_tag)
         for t_, b_, a_, l_, g_, tg in zip(ds, db, da, dl, dg, dt):
-            ib, ia = idx_maps[int(t_)]
-            e = key_index[int(t_)][(ib[int(b_)], ia[int(a_)])]
-            dh.append((int(t_), e, int(tg) // L, int(tg) % L, g_ * _local_matrix(int(l_))))
+            t_ = int(t_)
+            ib = np.searchsorted(chan_codes[t_], b_)
+            ia = np.searchsorted(chan_codes[t_ + 1], a_)
+            key = int(ib) * len(chan_codes[t_ + 1]) + int(ia)
+            e = int(np.searchsorted(Keys[t_], key))
+            dh.append((t_, e, int(tg) // L, int(tg) % L, g_ * _local_matrix(int(l_))))
     mpo.dh = dh
     mpo.blocks = _switch_blocks(mpo, cd)
     return mpo
