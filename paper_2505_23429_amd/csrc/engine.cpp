@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -145,6 +147,8 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double>& w, std
 // Engine
 // ---------------------------------------------------------------------------
 Engine::Engine(const tt_opts& o) : opts(o) {
+  const char* v = std::getenv("TT_VERBOSE");
+  verbose = v && std::atoi(v) > 0;
   HC(hipSetDevice(o.device));
   HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   RC(rocblas_create_handle(&blas));
@@ -1320,6 +1324,7 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   }
   env_unit(Renv[L], 1);
   for (int k = L - 1; k >= 2; --k) env_right(Renv[k + 1], Vc[k], Vc[k], k, Renv[k]);
+  if (verbose) std::fprintf(stderr, "[tt] step 1 done (LQ sweep + environments)\n");
   // Step 2: subdomain sweeps
   subs.clear(); subs.resize(nsub);
   int start = 0;
@@ -1372,6 +1377,9 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
     }
     S.mod.push_back(std::move(center));
     HC(hipStreamSynchronize(stream));
+    if (verbose)
+      std::fprintf(stderr, "[tt] subdomain %d sites %d..%d: E=%.10f matvecs=%d heff %.2fs/%.3g flop\n", j, s, e, S.E,
+                   S.matvecs, sec_heff, flops_heff);
     if (Eloc) Eloc[j] = S.E;
     if (mv) mv[j] = S.matvecs;
   }
@@ -1513,6 +1521,7 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
       S[(size_t)i * n + j] = S[(size_t)j * n + i] = ov_close(bS);
     }
   }
+  if (verbose) std::fprintf(stderr, "[tt] step 3: coarse matrices done\n");
   // coarse eigenproblem (host FP64): canonical orthogonalisation of S
   std::vector<double> ws, Vs;
   jacobi_eig(n, S, ws, Vs);
@@ -1690,6 +1699,7 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   U = std::move(T);
   free_caches();
   double En = energy();
+  if (verbose) std::fprintf(stderr, "[tt] step 4: compressed, E=%.10f discarded=%.3g\n", En, discarded);
   if (Eout) *Eout = En;
   if (disc) *disc = discarded;
   return status;

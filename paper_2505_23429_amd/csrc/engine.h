@@ -116,6 +116,7 @@ class Engine {
   double flops_heff = 0.0, sec_heff = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
+  bool verbose = false;
   // per-kernel statistics of the effective-Hamiltonian product:
   // [stage][ms, launches, algorithmic flops, algorithmic bytes]
   // stage 0 = L.x GEMM, 1 = site-1 mix, 2 = site-2 mix, 3 = R GEMM
