@@ -67,6 +67,8 @@ typedef struct tt_opts {
   int refine_fp64;    /* 1: after a low-precision solve, continue with FP64 products to dav_tol */
   double lowprec_tol; /* residual tolerance of the low-precision phase before FP64 refinement */
   int device;         /* HIP device ordinal */
+  int qn_skip;        /* 1: skip the exact zeros of the quantum-number blocks in the
+                         effective-Hamiltonian product and environment updates */
 } tt_opts;
 
 #define TT_MAX_SUB 64

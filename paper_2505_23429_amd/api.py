@@ -36,7 +36,7 @@ class Context:
     """One device context: MPO, current TT iterate, environment caches."""
 
     def __init__(self, chi=64, dav_tol=1e-8, dav_maxiter=200, dav_maxsub=24, coarse_eps=1e-8, svd_cutoff=1e-12,
-                 tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0):
+                 tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True):
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -51,6 +51,7 @@ class Context:
         o.refine_fp64 = int(bool(refine_fp64))
         o.lowprec_tol = lowprec_tol
         o.device = device
+        o.qn_skip = int(bool(qn_skip))
         self.opts = o
         h = C.c_void_p()
         rc = self.lib.tt_create(C.byref(o), C.byref(h))

@@ -70,6 +70,7 @@ void tt_default_opts(tt_opts* o) {
   o->refine_fp64 = 0;
   o->lowprec_tol = 1e-5;
   o->device = 0;
+  o->qn_skip = 1;
 }
 
 int tt_create(const tt_opts* opts, void** out) {

@@ -34,6 +34,22 @@ static const Q2 SITE_Q[4] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};
 static inline Q2 qadd(Q2 a, Q2 b) { return {a[0] + b[0], a[1] + b[1]}; }
 static inline Q2 qsub(Q2 a, Q2 b) { return {a[0] - b[0], a[1] - b[1]}; }
 
+static constexpr int QSENT = 1 << 20;  // charge of padding rows/columns: matches no rule
+
+static void upload_q2(DevMem& d, const std::vector<Q2>& v, hipStream_t s) {
+  std::vector<int> f(2 * v.size());
+  for (size_t i = 0; i < v.size(); ++i) { f[2 * i] = v[i][0]; f[2 * i + 1] = v[i][1]; }
+  upload(d, f.data(), f.size() * sizeof(int), s);
+}
+
+// charges of a padded label list (sentinel sign: +1 for output-side, -1 for input-side arrays)
+static std::vector<Q2> padded_q(const Labels& q, int n, int sent) {
+  std::vector<Q2> v(n, Q2{sent * QSENT, 0});
+  for (int i = 0; i < (int)q.size() && i < n; ++i) v[i] = q[i];
+  return v;
+}
+
+
 // ---------------------------------------------------------------------------
 // memory helpers
 // ---------------------------------------------------------------------------
@@ -279,6 +295,13 @@ void Engine::set_mpo(int L_, const int* R, const int* nnz, const int32_t* const*
     build_siteop(s.byB, s.Rr, s.B, s.A, s.ops, stream);
     build_siteop(s.byA, s.Rl, s.A, s.B, s.ops, stream);
   }
+  chan_q_dev.clear();
+  chan_q_dev.resize(L_ + 1);
+  for (int k = 0; k <= L_; ++k) {
+    std::vector<int> flat;
+    for (auto& x : q[k]) { flat.push_back(x[0]); flat.push_back(x[1]); }
+    upload(chan_q_dev[k], flat.data(), flat.size() * sizeof(int), stream);
+  }
   mpo = std::move(m);
   chan_q = std::move(q);
   Rb.assign(R, R + L_ + 1);
@@ -334,7 +357,7 @@ const float* siteop_ops<float>(const SiteOp& so) { return so.op32.as<float>(); }
 
 template <class T>
 void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
-                  const T* Rv, const T* x, T* y, const T* Rtil, int P0, int nP) {
+                  const T* Rv, const T* x, T* y, const T* Rtil, int P0, int nP, const WinTabs* tabs) {
   const long long slab = (long long)rl * 16 * rr;
   ws0.ensure(sizeof(T) * slab * std::max(RA, RC));
   ws1.ensure(sizeof(T) * slab * RB);
@@ -345,32 +368,45 @@ void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB,
   g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkb = 0; g.sAkk = 1;
   g.sBb = 0; g.sBkb = 0; g.sBkk = 16LL * rr; g.sBn = 1;
   g.sCb = slab; g.sCm = 16LL * rr; g.alpha = 1.0; g.beta = 0.0;
+  MixQ q1, q2;
+  if (tabs) {
+    g.kmode = 1; g.mtiles = tabs->m1tiles; g.ntiles = tabs->n1tiles;
+    g.ktab = tabs->k1tab.as<int>(); g.skip = tabs->k1skip.as<unsigned char>();
+    q1.qo = tabs->qo1.as<int2>(); q1.qi = tabs->qi1.as<int2>(); q1.qc = tabs->qcB;
+    q2.qo = tabs->qo2.as<int2>(); q2.qi = tabs->qi2.as<int2>(); q2.qc = tabs->qcC;
+  }
   kt_mark(0);
   gemm<T>(g, Lv, x, T1, true, true, stream);
   kt_mark(1);
-  mix<T>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), siteop_ops<T>(w1), T1, slab, T2, slab, rl, 4 * rr, stream);
+  mix<T>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), siteop_ops<T>(w1), T1, slab, T2, slab, rl, 4 * rr, stream,
+         tabs ? &q1 : nullptr);
   kt_mark(2);
   T* T3 = ws0.as<T>();
-  mix<T>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), siteop_ops<T>(w2), T2, slab, T3, slab, 4 * rl, rr, stream);
+  mix<T>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), siteop_ops<T>(w2), T2, slab, T3, slab, 4 * rl, rr, stream,
+         tabs ? &q2 : nullptr);
   kt_mark(3);
   GemmArgs h{};
   h.M = 16 * rl; h.N = rr; h.K = RC * rr; h.batch = 1; h.kin = rr;
   h.sAb = 0; h.sAm = rr; h.sAkb = slab; h.sAkk = 1;
   h.sBb = 0; h.sBkb = (long long)rr * rr; h.sBkk = 1; h.sBn = rr;
   h.sCb = 0; h.sCm = rr; h.alpha = 1.0; h.beta = 0.0;
+  if (tabs) {
+    h.kmode = 2; h.nkb = RC; h.ntiles = tabs->n4tiles; h.ktab = tabs->k4tab.as<int>();
+  }
   gemm<T>(h, T3, Rv, y, true, false, stream);
   if (Rtil && nP > 0) {
     h.K = nP * rr;
     h.beta = 1.0;
+    if (tabs) { h.nkb = nP; h.ktab = tabs->k4tabP.as<int>(); }
     gemm<T>(h, T2 + (long long)P0 * slab, Rtil, y, true, false, stream);
   }
   kt_mark(4);
   kt_finish(sizeof(T), RB);
 }
 template void Engine::heff<double>(int, int, int, const double*, const SiteOp&, int, const SiteOp&, int, const double*,
-                                   const double*, double*, const double*, int, int);
+                                   const double*, double*, const double*, int, int, const WinTabs*);
 template void Engine::heff<float>(int, int, int, const float*, const SiteOp&, int, const SiteOp&, int, const float*,
-                                  const float*, float*, const float*, int, int);
+                                  const float*, float*, const float*, int, int, const WinTabs*);
 
 // BF16 operands, FP32 accumulation and FP32 intermediates.  The second mix writes
 // FP32; T3 is rounded to BF16 for the last GEMM.
@@ -390,7 +426,8 @@ static void round_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s) {
 }
 
 void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
-                       const uint16_t* Rv, const uint16_t* x, float* y, const uint16_t* Rtil, int P0, int nP) {
+                       const uint16_t* Rv, const uint16_t* x, float* y, const uint16_t* Rtil, int P0, int nP,
+                       const WinTabs* tabs) {
   const long long slab = (long long)rl * 16 * rr;
   ws0.ensure(sizeof(float) * slab * std::max(RA, RC));
   ws1.ensure(sizeof(float) * slab * RB);
@@ -401,13 +438,22 @@ void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp&
   g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkb = 0; g.sAkk = 1;
   g.sBb = 0; g.sBkb = 0; g.sBkk = 16LL * rr; g.sBn = 1;
   g.sCb = slab; g.sCm = 16LL * rr; g.alpha = 1.0; g.beta = 0.0;
+  MixQ q1, q2;
+  if (tabs) {
+    g.kmode = 1; g.mtiles = tabs->m1tiles; g.ntiles = tabs->n1tiles;
+    g.ktab = tabs->k1tab.as<int>(); g.skip = tabs->k1skip.as<unsigned char>();
+    q1.qo = tabs->qo1.as<int2>(); q1.qi = tabs->qi1.as<int2>(); q1.qc = tabs->qcB;
+    q2.qo = tabs->qo2.as<int2>(); q2.qi = tabs->qi2.as<int2>(); q2.qc = tabs->qcC;
+  }
   kt_mark(0);
   gemm_bf16(g, Lv, x, T1, true, true, stream);
   kt_mark(1);
-  mix<float>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), w1.op32.as<float>(), T1, slab, T2, slab, rl, 4 * rr, stream);
+  mix<float>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), w1.op32.as<float>(), T1, slab, T2, slab, rl, 4 * rr, stream,
+             tabs ? &q1 : nullptr);
   kt_mark(2);
   float* T3 = ws0.as<float>();
-  mix<float>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), w2.op32.as<float>(), T2, slab, T3, slab, 4 * rl, rr, stream);
+  mix<float>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), w2.op32.as<float>(), T2, slab, T3, slab, 4 * rl, rr, stream,
+             tabs ? &q2 : nullptr);
   kt_mark(3);
   ws2.ensure(sizeof(uint16_t) * slab * std::max(RC, nP));
   uint16_t* T3b = ws2.as<uint16_t>();
@@ -417,11 +463,15 @@ void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp&
   h.sAb = 0; h.sAm = rr; h.sAkb = slab; h.sAkk = 1;
   h.sBb = 0; h.sBkb = (long long)rr * rr; h.sBkk = 1; h.sBn = rr;
   h.sCb = 0; h.sCm = rr; h.alpha = 1.0; h.beta = 0.0;
+  if (tabs) {
+    h.kmode = 2; h.nkb = RC; h.ntiles = tabs->n4tiles; h.ktab = tabs->k4tab.as<int>();
+  }
   gemm_bf16(h, T3b, Rv, y, true, false, stream);
   if (Rtil && nP > 0) {
     round_bf16(T2 + (long long)P0 * slab, T3b, (size_t)slab * nP, stream);
     h.K = nP * rr;
     h.beta = 1.0;
+    if (tabs) { h.nkb = nP; h.ktab = tabs->k4tabP.as<int>(); }
     gemm_bf16(h, T3b, Rtil, y, true, false, stream);
   }
   kt_mark(4);
@@ -432,7 +482,7 @@ void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp&
 // environment updates (K2 / K3), FP64, padded dims
 // ---------------------------------------------------------------------------
 void Engine::env_left_raw(int rb, int rk, int rb2, int rk2, int RA, const double* E, const double* Ubra,
-                          const double* Uket, const SiteOp& w, int RB, double* out) {
+                          const double* Uket, const SiteOp& w, int RB, double* out, const MixQ* q) {
   const long long sl = (long long)rb * 4 * rk2;
   ws2.ensure(sizeof(double) * sl * RA);
   ws3.ensure(sizeof(double) * sl * RB);
@@ -444,7 +494,7 @@ void Engine::env_left_raw(int rb, int rk, int rb2, int rk2, int RA, const double
   g.sBb = 0; g.sBkb = 0; g.sBkk = 4LL * rk2; g.sBn = 1;
   g.sCb = sl; g.sCm = 4LL * rk2; g.alpha = 1.0; g.beta = 0.0;
   gemm<double>(g, E, Uket, T, true, true, stream);
-  mix<double>(w.nout, w.ptr.as<int>(), w.src.as<int>(), w.op64.as<double>(), T, sl, Tp, sl, rb, rk2, stream);
+  mix<double>(w.nout, w.ptr.as<int>(), w.src.as<int>(), w.op64.as<double>(), T, sl, Tp, sl, rb, rk2, stream, q);
   GemmArgs h{};
   h.M = rb2; h.N = rk2; h.K = 4 * rb; h.batch = RB; h.kin = 4 * rb;
   h.sAb = 0; h.sAm = 1; h.sAkb = 0; h.sAkk = rb2;
@@ -454,7 +504,7 @@ void Engine::env_left_raw(int rb, int rk, int rb2, int rk2, int RA, const double
 }
 
 void Engine::env_right_raw(int rb, int rk, int rb2, int rk2, int RB, const double* E, const double* Ubra,
-                           const double* Uket, const SiteOp& w, int RA, double* out) {
+                           const double* Uket, const SiteOp& w, int RA, double* out, const MixQ* q) {
   const long long sl = (long long)rk * 4 * rb2;
   ws2.ensure(sizeof(double) * sl * RB);
   ws3.ensure(sizeof(double) * sl * RA);
@@ -466,7 +516,7 @@ void Engine::env_right_raw(int rb, int rk, int rb2, int rk2, int RB, const doubl
   g.sBb = (long long)rb2 * rk2; g.sBkb = 0; g.sBkk = 1; g.sBn = rk2;
   g.sCb = sl; g.sCm = rb2; g.alpha = 1.0; g.beta = 0.0;
   gemm<double>(g, Uket, E, T, true, false, stream);
-  mix<double>(w.nout, w.ptr.as<int>(), w.src.as<int>(), w.op64.as<double>(), T, sl, Tp, sl, rk, rb2, stream);
+  mix<double>(w.nout, w.ptr.as<int>(), w.src.as<int>(), w.op64.as<double>(), T, sl, Tp, sl, rk, rb2, stream, q);
   GemmArgs h{};
   h.M = rb; h.N = rk; h.K = 4 * rb2; h.batch = RA; h.kin = 4 * rb2;
   h.sAb = 0; h.sAm = 4LL * rb2; h.sAkb = 0; h.sAkk = 1;
@@ -512,6 +562,14 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
   Env o;
   o.R = s.Rr; o.rb = bra.rr; o.rk = ket.rr;
   o.d.ensure(sizeof(double) * o.elems());
+  // mix output (B, a', s', b) can be non-zero only if q(s') = d_B - q(a') + q(b)
+  MixQ q, *qp = nullptr;
+  if (opts.qn_skip && (int)bra.ql.size() == bra.rl && (int)ket.qr.size() == ket.rr) {
+    upload_q2(envq_o, padded_q(bra.ql, rb, 1), stream);
+    upload_q2(envq_i, padded_q(ket.qr, rk2, -1), stream);
+    q.qo = envq_o.as<int2>(); q.qi = envq_i.as<int2>(); q.qc = chan_q_dev[site + 1].as<int2>(); q.sgn = 1;
+    qp = &q;
+  }
   if (s.has_block) {
     const long long slab = (long long)rb * rk;
     const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
@@ -520,10 +578,10 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
     channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.p0 * slab, slab,
                       wsd.as<double>() + (long long)s.Rl * slab, false, stream);
     env_left_raw(rb, rk, rb2, rk2, s.Rl + nQ, wsd.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byB_left,
-                 s.Rr, o.d.as<double>());
+                 s.Rr, o.d.as<double>(), qp);
   } else {
     env_left_raw(rb, rk, rb2, rk2, s.Rl, in.d.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byB, s.Rr,
-                 o.d.as<double>());
+                 o.d.as<double>(), qp);
   }
   out = std::move(o);
 }
@@ -535,6 +593,14 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
   Env o;
   o.R = s.Rl; o.rb = bra.rl; o.rk = ket.rl;
   o.d.ensure(sizeof(double) * o.elems());
+  // mix output (A, a, s', b') can be non-zero only if q(s') = q(b') - q(a) - d_A
+  MixQ q, *qp = nullptr;
+  if (opts.qn_skip && (int)ket.ql.size() == ket.rl && (int)bra.qr.size() == bra.rr) {
+    upload_q2(envq_o, padded_q(ket.ql, rk, 1), stream);
+    upload_q2(envq_i, padded_q(bra.qr, rb2, -1), stream);
+    q.qo = envq_o.as<int2>(); q.qi = envq_i.as<int2>(); q.qc = chan_q_dev[site].as<int2>(); q.sgn = -1;
+    qp = &q;
+  }
   if (s.has_block) {
     const long long slab = (long long)rb2 * rk2;
     const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
@@ -543,10 +609,10 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
     channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.q0 * slab, slab,
                       wsd.as<double>() + (long long)s.Rr * slab, true, stream);
     env_right_raw(rb, rk, rb2, rk2, s.Rr + nP, wsd.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byA_right,
-                  s.Rl, o.d.as<double>());
+                  s.Rl, o.d.as<double>(), qp);
   } else {
     env_right_raw(rb, rk, rb2, rk2, s.Rr, in.d.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byA, s.Rl,
-                  o.d.as<double>());
+                  o.d.as<double>(), qp);
   }
   out = std::move(o);
 }
@@ -990,10 +1056,208 @@ struct Window {
   int P0 = 0, nP = 0;
   int prec = 0;
   DevMem L32, R32, Rt32;  // low-precision copies
+  DevMem diag;            // FP64 diagonal of the window operator [rlp][4][4][rrp]
   double flops = 0.0;
+  bool use_tabs = false;
+  WinTabs tabs;           // structural-zero tables of the quantum-number blocks
 };
 
-static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env& Re, int prec) {
+// diag[a][s1][s2][b] = sum_B (sum_A W1[A,s1,s1,B] L_A[a][a]) (sum_C W2[B,s2,s2,C] R_C[b][b])
+static void window_diag(Engine& E, Window& w, const Env& Le, int b, const Env& Re) {
+  const SiteMPO& s1 = E.mpo[b];
+  const SiteMPO& s2 = E.mpo[b + 1];
+  DevMem Ld, Rd, LW, WR;
+  Ld.ensure(sizeof(double) * (size_t)s1.Rl * w.rlp);
+  Rd.ensure(sizeof(double) * (size_t)s2.Rr * w.rrp);
+  LW.ensure(sizeof(double) * (size_t)s1.Rr * 4 * w.rlp);
+  WR.ensure(sizeof(double) * (size_t)s1.Rr * 4 * w.rrp);
+  diag_extract(Le.d.as<double>(), s1.Rl, w.rlp, Ld.as<double>(), E.stream);
+  diag_extract(Re.d.as<double>(), s2.Rr, w.rrp, Rd.as<double>(), E.stream);
+  diag_mix(s1.Rr, s1.byB.ptr.as<int>(), s1.byB.src.as<int>(), s1.byB.op64.as<double>(), Ld.as<double>(), w.rlp,
+           LW.as<double>(), true, E.stream);
+  diag_mix(s2.Rl, s2.byA.ptr.as<int>(), s2.byA.src.as<int>(), s2.byA.op64.as<double>(), Rd.as<double>(), w.rrp,
+           WR.as<double>(), false, E.stream);
+  w.diag.ensure(sizeof(double) * (size_t)w.rlp * 16 * w.rrp);
+  GemmArgs g{};
+  g.M = 4 * w.rlp; g.N = 4 * w.rrp; g.K = s1.Rr; g.batch = 1; g.kin = kin16(s1.Rr);
+  g.sAm = 1; g.sAkk = 4LL * w.rlp; g.sBkk = 4LL * w.rrp; g.sBn = 1; g.sCm = 4LL * w.rrp; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, LW.as<double>(), WR.as<double>(), w.diag.as<double>(), false, true, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+}
+
+// ---------------------------------------------------------------------------
+// structural zeros of the quantum-number blocks (tables read by the GEMM and
+// mix kernels; every skipped product term is an exact zero)
+// ---------------------------------------------------------------------------
+
+// first and one-past-last index of every charge of a label list
+static std::map<Q2, std::pair<int, int>> qspans(const Labels& q) {
+  std::map<Q2, std::pair<int, int>> m;
+  for (int i = 0; i < (int)q.size(); ++i) {
+    auto it = m.find(q[i]);
+    if (it == m.end()) m[q[i]] = {i, i + 1};
+    else it->second.second = i + 1;
+  }
+  return m;
+}
+
+// distinct charges of the valid labels inside each tile of T consecutive indices
+static std::vector<std::set<Q2>> tile_charges(const std::vector<Q2>& q, const std::vector<char>& valid, int n, int T) {
+  const int nt = (n + T - 1) / T;
+  std::vector<std::set<Q2>> out(nt);
+  for (int i = 0; i < n; ++i)
+    if (valid[i]) out[i / T].insert(q[i]);
+  return out;
+}
+
+// K-range table of a batched product C_A = E_A X where E_A[m][k] can be non-zero
+// only if q_m(m) - q_k(k) = d_A (kmode 1), plus the zero-tile map from the charges
+// that X's columns need of k (colk[nt]).
+static void kmode1_tables(const Labels& qm, int M, const Labels& qk, const std::vector<Q2>& dA,
+                          const std::vector<std::set<Q2>>& colk, std::vector<int>& ktab, std::vector<uint8_t>& skip,
+                          int& mtiles) {
+  std::vector<Q2> qmv(M, Q2{QSENT, 0});
+  std::vector<char> val(M, 0);
+  for (int i = 0; i < (int)qm.size() && i < M; ++i) { qmv[i] = qm[i]; val[i] = 1; }
+  const auto rowq = tile_charges(qmv, val, M, GEMM_TILE);
+  mtiles = (int)rowq.size();
+  const int ntiles = (int)colk.size();
+  const auto spans = qspans(qk);
+  const int nb = (int)dA.size();
+  ktab.assign((size_t)nb * mtiles * 2, 0);
+  skip.assign((size_t)nb * mtiles * ntiles, 1);
+  std::map<Q2, int> seen;  // batches with equal channel charge share their rows
+  for (int A = 0; A < nb; ++A) {
+    auto it = seen.find(dA[A]);
+    if (it != seen.end()) {
+      const int B0 = it->second;
+      std::copy(ktab.begin() + (size_t)B0 * mtiles * 2, ktab.begin() + (size_t)(B0 + 1) * mtiles * 2,
+                ktab.begin() + (size_t)A * mtiles * 2);
+      std::copy(skip.begin() + (size_t)B0 * mtiles * ntiles, skip.begin() + (size_t)(B0 + 1) * mtiles * ntiles,
+                skip.begin() + (size_t)A * mtiles * ntiles);
+      continue;
+    }
+    seen[dA[A]] = A;
+    for (int mt = 0; mt < mtiles; ++mt) {
+      std::set<Q2> need;  // charges of k that meet some row of the tile
+      int lo = INT32_MAX, hi = 0;
+      for (const Q2& r : rowq[mt]) {
+        Q2 c = qsub(r, dA[A]);
+        auto s = spans.find(c);
+        if (s == spans.end()) continue;
+        need.insert(c);
+        lo = std::min(lo, s->second.first);
+        hi = std::max(hi, s->second.second);
+      }
+      if (need.empty()) lo = hi = 0;
+      ktab[((size_t)A * mtiles + mt) * 2] = lo;
+      ktab[((size_t)A * mtiles + mt) * 2 + 1] = hi;
+      for (int nt = 0; nt < ntiles; ++nt) {
+        bool live = false;
+        for (const Q2& c : need)
+          if (colk[nt].count(c)) { live = true; break; }
+        skip[((size_t)A * mtiles + mt) * ntiles + nt] = live ? 0 : 1;
+      }
+    }
+  }
+}
+
+// inner K-range table of y = sum_C T_C R_C^T with R_C[n][k] non-zero only if
+// q_n(n) - q_k(k) = d_C (kmode 2): ktab[(nt*nC + C)*2]
+static void kmode2_tables(const Labels& qn, int N, const Labels& qk, const std::vector<Q2>& dC, std::vector<int>& ktab,
+                          int& ntiles) {
+  std::vector<Q2> qv(N, Q2{QSENT, 0});
+  std::vector<char> val(N, 0);
+  for (int i = 0; i < (int)qn.size() && i < N; ++i) { qv[i] = qn[i]; val[i] = 1; }
+  const auto colq = tile_charges(qv, val, N, GEMM_TILE);
+  ntiles = (int)colq.size();
+  const auto spans = qspans(qk);
+  const int nC = (int)dC.size();
+  ktab.assign((size_t)ntiles * nC * 2, 0);
+  std::map<Q2, std::vector<std::pair<int, int>>> memo;
+  for (int C = 0; C < nC; ++C) {
+    auto it = memo.find(dC[C]);
+    if (it == memo.end()) {
+      std::vector<std::pair<int, int>> r(ntiles, {0, 0});
+      for (int nt = 0; nt < ntiles; ++nt) {
+        int lo = INT32_MAX, hi = 0;
+        for (const Q2& q : colq[nt]) {
+          auto s = spans.find(qsub(q, dC[C]));
+          if (s == spans.end()) continue;
+          lo = std::min(lo, s->second.first);
+          hi = std::max(hi, s->second.second);
+        }
+        if (hi == 0) lo = 0;
+        r[nt] = {lo, hi};
+      }
+      it = memo.emplace(dC[C], std::move(r)).first;
+    }
+    for (int nt = 0; nt < ntiles; ++nt) {
+      ktab[((size_t)nt * nC + C) * 2] = it->second[nt].first;
+      ktab[((size_t)nt * nC + C) * 2 + 1] = it->second[nt].second;
+    }
+  }
+}
+
+// Tables of the two-site product at sites (b, b+1) with left labels ql (bond b)
+// and right labels qr (bond b+2).
+static void build_window_tabs(Engine& E, WinTabs& t, int b, const Labels& ql, const Labels& qr, int rlp, int rrp,
+                              int RAx, int P0, int nP) {
+  const SiteMPO& s1 = E.mpo[b];
+  const SiteMPO& s2 = E.mpo[b + 1];
+  // stage 1: T1[A] = L_A x over the left bond; channel A (or the virtual channel of
+  // block row q) carries charge d_A with q(a') - q(a) = d_A
+  std::vector<Q2> dA(RAx);
+  for (int A = 0; A < s1.Rl; ++A) dA[A] = E.chan_q[b][A];
+  for (int A = s1.Rl; A < RAx; ++A) dA[A] = E.chan_q[b + 1][s1.q0 + (A - s1.Rl)];
+  // columns (s1, s2, b) of x need q(a) = q(b) - q(s1) - q(s2)
+  const int N1 = 16 * rrp;
+  std::vector<Q2> colq(N1, Q2{QSENT, 0});
+  std::vector<char> colv(N1, 0);
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v)
+      for (int j = 0; j < (int)qr.size(); ++j) {
+        const int n = (u * 4 + v) * rrp + j;
+        colq[n] = qsub(qsub(qr[j], SITE_Q[u]), SITE_Q[v]);
+        colv[n] = 1;
+      }
+  const auto colk = tile_charges(colq, colv, N1, GEMM_TILE);
+  t.n1tiles = (int)colk.size();
+  std::vector<int> k1;
+  std::vector<uint8_t> sk;
+  kmode1_tables(ql, rlp, ql, dA, colk, k1, sk, t.m1tiles);
+  upload(t.k1tab, k1.data(), k1.size() * sizeof(int), E.stream);
+  upload(t.k1skip, sk.data(), sk.size(), E.stream);
+  // stage 4: y = sum_C T3[C] R_C^T, R_C[b'][b] non-zero only if q(b') - q(b) = d_C
+  std::vector<Q2> dC(E.chan_q[b + 2].begin(), E.chan_q[b + 2].end());
+  std::vector<int> k4;
+  kmode2_tables(qr, rrp, qr, dC, k4, t.n4tiles);
+  upload(t.k4tab, k4.data(), k4.size() * sizeof(int), E.stream);
+  if (nP > 0) {
+    std::vector<Q2> dP(E.chan_q[b + 1].begin() + P0, E.chan_q[b + 1].begin() + P0 + nP);
+    std::vector<int> kp;
+    int nt = 0;
+    kmode2_tables(qr, rrp, qr, dP, kp, nt);
+    upload(t.k4tabP, kp.data(), kp.size() * sizeof(int), E.stream);
+  }
+  // mix charges: site 1 (O = a', I = (s2, b)), site 2 (O = (a', s1'), I = b)
+  upload_q2(t.qo1, padded_q(ql, rlp, 1), E.stream);
+  std::vector<Q2> qi1(4 * rrp, Q2{-QSENT, 0});
+  for (int v = 0; v < 4; ++v)
+    for (int j = 0; j < (int)qr.size(); ++j) qi1[v * rrp + j] = qsub(qr[j], SITE_Q[v]);
+  upload_q2(t.qi1, qi1, E.stream);
+  std::vector<Q2> qo2(4 * rlp, Q2{QSENT, 0});
+  for (int a = 0; a < (int)ql.size(); ++a)
+    for (int u = 0; u < 4; ++u) qo2[a * 4 + u] = qadd(ql[a], SITE_Q[u]);
+  upload_q2(t.qo2, qo2, E.stream);
+  upload_q2(t.qi2, padded_q(qr, rrp, -1), E.stream);
+  t.qcB = E.chan_q_dev[b + 1].as<int2>();
+  t.qcC = E.chan_q_dev[b + 2].as<int2>();
+  (void)s2;
+}
+
+static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env& Re, int prec, const Labels& ql,
+                           const Labels& qr) {
   const SiteMPO& s1 = E.mpo[b];
   const SiteMPO& s2 = E.mpo[b + 1];
   w.rl = Le.rb; w.rr = Re.rb;
@@ -1048,29 +1312,33 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
   }
   // dense-bond algorithmic flops of one product (true sizes, no virtual channels)
   w.flops = 2.0 * 16.0 * w.rl * w.rr * ((double)w.RA * w.rl + (double)w.RC * w.rr);
-  HC(hipStreamSynchronize(E.stream));
+  w.use_tabs = E.opts.qn_skip != 0;
+  if (w.use_tabs) build_window_tabs(E, w.tabs, b, ql, qr, w.rlp, w.rrp, w.RAx, w.P0, w.nP);
+  window_diag(E, w, Le, b, Re);
 }
 
 static void window_matvec(Engine& E, Window& w, const double* x, double* y, int prec) {
   const size_t n = (size_t)w.rlp * 16 * w.rrp;
   E.cur_rl = w.rl; E.cur_rr = w.rr; E.cur_RA = w.RA; E.cur_RC = w.RC;
+  const WinTabs* tabs = w.use_tabs ? &w.tabs : nullptr;
   HC(hipEventRecord(E.ev0, E.stream));
   if (prec == TT_F64) {
     E.heff<double>(w.rlp, w.rrp, w.RAx, w.Lx.as<double>(), *w.w1, w.RB, *w.w2, w.RC, w.R64, x, y,
-                   w.nP ? w.Rt.as<double>() : nullptr, w.P0, w.nP);
+                   w.nP ? w.Rt.as<double>() : nullptr, w.P0, w.nP, tabs);
   } else if (prec == TT_F32) {
     E.wlow_x.ensure(sizeof(float) * n);
     E.wlow_y.ensure(sizeof(float) * n);
     convert_f64_f32(x, E.wlow_x.as<float>(), n, E.stream);
     E.heff<float>(w.rlp, w.rrp, w.RAx, w.L32.as<float>(), *w.w1, w.RB, *w.w2, w.RC, w.R32.as<float>(),
-                  E.wlow_x.as<float>(), E.wlow_y.as<float>(), w.nP ? w.Rt32.as<float>() : nullptr, w.P0, w.nP);
+                  E.wlow_x.as<float>(), E.wlow_y.as<float>(), w.nP ? w.Rt32.as<float>() : nullptr, w.P0, w.nP, tabs);
     convert_f32_f64(E.wlow_y.as<float>(), y, n, E.stream);
   } else {
     E.wlow_x.ensure(sizeof(uint16_t) * n);
     E.wlow_y.ensure(sizeof(float) * n);
     convert_f64_bf16(x, E.wlow_x.as<uint16_t>(), n, E.stream);
     E.heff_bf16(w.rlp, w.rrp, w.RAx, w.L32.as<uint16_t>(), *w.w1, w.RB, *w.w2, w.RC, w.R32.as<uint16_t>(),
-                E.wlow_x.as<uint16_t>(), E.wlow_y.as<float>(), w.nP ? w.Rt32.as<uint16_t>() : nullptr, w.P0, w.nP);
+                E.wlow_x.as<uint16_t>(), E.wlow_y.as<float>(), w.nP ? w.Rt32.as<uint16_t>() : nullptr, w.P0, w.nP,
+                tabs);
     convert_f32_f64(E.wlow_y.as<float>(), y, n, E.stream);
   }
   HC(hipEventRecord(E.ev1, E.stream));
@@ -1172,21 +1440,25 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     }
     if (res.matvecs >= maxiter) break;
     if (m >= maxsub) {
-      // restart with the Ritz vector
-      HC(hipMemcpyAsync(V, u, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
-      HC(hipMemcpyAsync(AV, Au, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
-      double nu = norm_dev(E, V, n);
-      scale(V, 1.0 / nu, n, E.stream);
-      scale(AV, 1.0 / nu, n, E.stream);
-      m = 1;
-      std::vector<double> d;
-      dots(V, 1, AV, d);
+      // thick restart: keep the lowest Ritz vectors of the current subspace
+      const int keep = std::min(3, m);
+      E.dav_t2.ensure(sizeof(double) * n * keep);
+      E.dav_t3.ensure(sizeof(double) * n * keep);
+      for (int q = 0; q < keep; ++q) {
+        std::vector<double> cq(m);
+        for (int i = 0; i < m; ++i) cq[i] = evecs[(size_t)i * m + q];
+        lcomb(V, m, cq, E.dav_t2.as<double>() + (size_t)q * n);
+        lcomb(AV, m, cq, E.dav_t3.as<double>() + (size_t)q * n);
+      }
+      HC(hipMemcpyAsync(V, E.dav_t2.p, sizeof(double) * n * keep, hipMemcpyDeviceToDevice, E.stream));
+      HC(hipMemcpyAsync(AV, E.dav_t3.p, sizeof(double) * n * keep, hipMemcpyDeviceToDevice, E.stream));
       Hs.assign((size_t)maxsub * maxsub, 0.0);
-      Hs[0] = d[0];
+      for (int q = 0; q < keep; ++q) Hs[(size_t)q * maxsub + q] = evals[q];
+      m = keep;
       continue;
     }
-    // new direction: residual, projected out of the subspace twice
-    mask_apply(t, mask.as<uint8_t>(), n, E.stream);
+    // new direction: diagonally preconditioned residual, projected out of the subspace twice
+    precond(t, t, w.diag.as<double>(), res.theta, mask.as<uint8_t>(), n, E.stream);
     double tn0 = norm_dev(E, t, n);
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<double> d;
@@ -1237,7 +1509,7 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
   const int prec = E.opts.matvec_prec;
   Davidson r;
   if (prec != TT_F64) {
-    prepare_window(E, w, Le, b, Re, prec);
+    prepare_window(E, w, Le, b, Re, prec, ql, qr);
     const double tol_low = E.opts.refine_fp64 ? std::max(E.opts.lowprec_tol, E.opts.dav_tol) : E.opts.dav_tol;
     r = davidson(E, w, mask, x.as<double>(), prec, tol_low, E.opts.dav_maxiter);
     if (E.opts.refine_fp64) {
@@ -1249,7 +1521,7 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
       r = r2;
     }
   } else {
-    prepare_window(E, w, Le, b, Re, TT_F64);
+    prepare_window(E, w, Le, b, Re, TT_F64, ql, qr);
     r = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter);
   }
   if (!r.converged) E.warn = std::max(E.warn, (int)TT_WNOCONV);

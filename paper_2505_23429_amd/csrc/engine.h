@@ -6,8 +6,10 @@
 #include <rocblas/rocblas.h>
 
 #include <array>
+#include <climits>
 #include <map>
 #include <memory>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -69,6 +71,18 @@ struct SiteMPO {
   SiteOp byA_right;               // block -> virtual pass entries (inputs Rr + p - p0)
 };
 
+// Structural-zero tables of one two-site window (device arrays).
+struct WinTabs {
+  DevMem k1tab, k1skip;   // stage 1: [RAx][mtiles][2] K ranges, [RAx][mtiles][ntiles] zero tiles
+  int m1tiles = 0, n1tiles = 0;
+  DevMem k4tab;           // stage 4: [ntiles][RC][2] inner K ranges
+  DevMem k4tabP;          // extra stage-4 GEMM of the second-site block: [ntiles][nP][2]
+  int n4tiles = 0;
+  DevMem qo1, qi1, qo2, qi2;            // int2 charge arrays of the two mixes
+  const int2* qcB = nullptr;            // channel charges of the middle bond (not owned)
+  const int2* qcC = nullptr;            // channel charges of the right bond (not owned)
+};
+
 struct Env {
   int R = 0, rb = 0, rk = 0;  // true sizes; storage [R][rbp][rkp]
   DevMem d;
@@ -95,6 +109,7 @@ class Engine {
   std::vector<SiteMPO> mpo;
   std::vector<int> Rb;                 // bond dims
   std::vector<Labels> chan_q;          // per bond
+  std::vector<DevMem> chan_q_dev;      // per bond, int2
   std::vector<Core> U;                 // current left-orthogonal iterate
   bool have_mpo = false, have_mps = false;
 
@@ -142,13 +157,14 @@ class Engine {
   // kernels on raw device pointers
   template <class T>
   void heff(int rl, int rr, int RA, const T* Lenv, const SiteOp& w1, int RB, const SiteOp& w2, int RC, const T* Renv,
-            const T* x, T* y, const T* Rtil, int P0, int nP);
+            const T* x, T* y, const T* Rtil, int P0, int nP, const WinTabs* tabs = nullptr);
   void heff_bf16(int rl, int rr, int RA, const uint16_t* Lenv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
-                 const uint16_t* Renv, const uint16_t* x, float* y, const uint16_t* Rtil, int P0, int nP);
+                 const uint16_t* Renv, const uint16_t* x, float* y, const uint16_t* Rtil, int P0, int nP,
+                 const WinTabs* tabs = nullptr);
   void env_left_raw(int rb, int rk, int rb2, int rk2, int RA, const double* E, const double* Ubra, const double* Uket,
-                    const SiteOp& w, int RB, double* out);
+                    const SiteOp& w, int RB, double* out, const MixQ* q = nullptr);
   void env_right_raw(int rb, int rk, int rb2, int rk2, int RB, const double* E, const double* Ubra,
-                     const double* Uket, const SiteOp& w, int RA, double* out);
+                     const double* Uket, const SiteOp& w, int RA, double* out, const MixQ* q = nullptr);
   void heff_grad_raw(int rl, int rr, int RA, int RB, int RC, const double* Lenv, const double* Renv,
                      const std::vector<int>& A1, const std::vector<int>& B1, const std::vector<double>& o1,
                      const std::vector<int>& A2, const std::vector<int>& B2, const std::vector<double>& o2,
@@ -168,8 +184,9 @@ class Engine {
 
   // workspace
   DevMem ws0, ws1, ws2, ws3, wsd, wsp;
-  DevMem dav_V, dav_AV, dav_t, dav_u, dav_Au, dav_c, dav_mask;
+  DevMem dav_V, dav_AV, dav_t, dav_u, dav_Au, dav_c, dav_mask, dav_t2, dav_t3;
   DevMem wlow_x, wlow_y, wlow_L, wlow_R, wlow_Rt;
+  DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
 
  private:
   void free_caches();

@@ -24,7 +24,17 @@ struct GemmArgs {
   long long sBb, sBkb, sBkk, sBn;
   long long sCb, sCm;
   double alpha, beta;
+  // structural-zero skipping (optional; all zero = dense):
+  //  kmode 0: full K.
+  //  kmode 1: ktab[(batch*mtiles + mtile)*2 + {0,1}] = [lo, hi) range of K.
+  //  kmode 2: K = (kb, inner) with nkb outer blocks of kin; ktab[(ntile*nkb + kb)*2 + {0,1}]
+  //           = [lo, hi) inner range of block kb for output column tile ntile.
+  //  skip: skip[(batch*mtiles + mtile)*ntiles + ntile] != 0 -> the output tile is zero.
+  int kmode, nkb, mtiles, ntiles;
+  const int* ktab;
+  const unsigned char* skip;
 };
+constexpr int GEMM_TILE = 128;
 
 // C = alpha * A B + beta * C for T in {double, float}.  Accumulation in T.
 template <typename T>
@@ -38,9 +48,18 @@ void gemm_bf16(const GemmArgs& g, const uint16_t* A, const uint16_t* B, float* C
 //   out[c][o][s'][i] = sum_{e in [ptr[c], ptr[c+1])} sum_s op[e][s'][s] * in[src[e]][o][s][i]
 // in/out channel slabs have O*4*I elements; channel strides are given so the
 // same kernel serves every stage.  op is stored [e][4][4] in the compute type.
+// Optional charge tables for structural-zero skipping of the mix: an output
+// element (c, o, *, i) can be non-zero only if qi[i] - qo[o] + sgn*qc[c] is the
+// charge of a local state; otherwise it is written as zero without gathering.
+struct MixQ {
+  const int2* qo = nullptr;
+  const int2* qi = nullptr;
+  const int2* qc = nullptr;
+  int sgn = 1;
+};
 template <typename T>
 void mix(int nout, const int* ptr, const int* src, const T* op, const T* in, long long in_cstride,
-         T* out, long long out_cstride, int O, int I, hipStream_t s);
+         T* out, long long out_cstride, int O, int I, hipStream_t s, const MixQ* q = nullptr);
 
 // Elementwise / reduction helpers (double unless noted).
 void fill(void* p, size_t bytes, hipStream_t s);                     // zero fill (kernel, graph-safe)
@@ -75,5 +94,12 @@ void entry_grad(int nnz, const int* gch, const int* tch, const T* G, long long g
                 int O, int I, double* gop, hipStream_t s);
 // batched transpose of [n][r][c] -> [n][c][r]
 void transpose_batched(const double* in, double* out, int n, int r, int c, hipStream_t s);
+
+// diagonal of the effective Hamiltonian: env diagonals, channel mixes of the
+// diagonal local-operator elements, preconditioner application
+void diag_extract(const double* E, int R, int r, double* out, hipStream_t s);
+void diag_mix(int nout, const int* ptr, const int* src, const double* op, const double* in, int n, double* out,
+              bool state_inner, hipStream_t s);
+void precond(double* t, const double* r, const double* d, double theta, const uint8_t* m, size_t n, hipStream_t s);
 
 }  // namespace tt

@@ -50,11 +50,88 @@ __device__ inline int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) +
 template <>
 __device__ inline int acc_row<double>(int lane, int v) { return 4 * v + (lane >> 4); }
 
-template <typename T, bool AK, bool BNC>
+// Software-pipelined tile loop: the next K tile is fetched from global memory
+// into registers while the MFMAs of the current tile run out of one of two
+// LDS buffers.  Global loads move runs of RUN consecutive elements along the
+// contiguous direction of each operand (16-byte vector loads when VEC).
+template <typename T>
+struct GemmCfg {
+  static constexpr int BK = sizeof(T) == 4 ? 32 : 16;
+  static constexpr int RUN = BM * BK / 256;  // elements per thread per operand tile
+};
+
+// Iterates the K tiles (start indices, multiples of BKT inside a segment) that
+// a workgroup has to process, following the structural-zero tables.
+template <int BKT>
+struct KIter {
+  const GemmArgs& g;
+  int seg = 0, nseg = 1, mt, nt, bz;
+  bool empty = false;
+  __device__ KIter(const GemmArgs& g_, int mt_, int nt_, int bz_) : g(g_), mt(mt_), nt(nt_), bz(bz_) {
+    if (g.skip && g.skip[((long long)bz * g.mtiles + mt) * g.ntiles + nt]) empty = true;
+    if (g.kmode == 2) nseg = g.nkb;
+  }
+  __device__ void bounds(int s, int& lo, int& hi) const {
+    if (g.kmode == 0) { lo = 0; hi = g.K; }
+    else if (g.kmode == 1) {
+      const int* t = g.ktab + ((long long)bz * g.mtiles + mt) * 2;
+      lo = t[0]; hi = t[1];
+    } else {
+      const int* t = g.ktab + ((long long)nt * g.nkb + s) * 2;
+      lo = s * g.kin + t[0]; hi = s * g.kin + t[1];
+    }
+    if (hi > g.K) hi = g.K;
+    lo = (lo / BKT) * BKT;  // tiles start on the BKT grid (inner blocks are multiples of BKT)
+  }
+  __device__ int start_from(int s) {
+    for (; s < nseg; ++s) {
+      int lo, hi;
+      bounds(s, lo, hi);
+      if (lo < hi) { seg = s; return lo; }
+    }
+    return -1;
+  }
+  __device__ int first() { return empty ? -1 : start_from(0); }
+  __device__ int next(int k0) {
+    int lo, hi;
+    bounds(seg, lo, hi);
+    if (k0 + BKT < hi) return k0 + BKT;
+    return start_from(seg + 1);
+  }
+};
+
+template <typename T, bool VEC>
+__device__ inline void load_run(const T* __restrict__ p, long long stride, bool full, int nvalid, T* r) {
+  constexpr int RUN = GemmCfg<T>::RUN;
+  if (VEC && full && stride == 1) {
+    if constexpr (sizeof(T) == 4) {
+      const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+      for (int u = 0; u < RUN / 4; ++u) {
+        float4 v = q[u];
+        r[4 * u] = v.x; r[4 * u + 1] = v.y; r[4 * u + 2] = v.z; r[4 * u + 3] = v.w;
+      }
+    } else {
+      const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+      for (int u = 0; u < RUN / 2; ++u) {
+        double2 v = q[u];
+        r[2 * u] = v.x; r[2 * u + 1] = v.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < RUN; ++u) r[u] = (u < nvalid) ? p[u * stride] : T(0);
+  }
+}
+
+template <typename T, bool AK, bool BNC, bool VEC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restrict__ A, const T* __restrict__ B,
                                                    T* __restrict__ C) {
-  __shared__ T As[BK][BM + 4];
-  __shared__ T Bs[BK][BN + 4];
+  constexpr int BKc = GemmCfg<T>::BK;
+  constexpr int RUN = GemmCfg<T>::RUN;
+  __shared__ T As[2][BKc][BM + 4];
+  __shared__ T Bs[2][BKc][BN + 4];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -66,6 +143,59 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restri
   const T* Bb = B + (long long)bz * g.sBb;
   T* Cb = C + (long long)bz * g.sCb;
 
+  // thread -> run assignment
+  // k-contiguous operand: row = tid/2, k offset = (tid%2)*RUN
+  // m/n-contiguous operand: k = tid/(BM/RUN), offset = (tid%(BM/RUN))*RUN
+  constexpr int TPR = BM / RUN;
+  const int kc_row = tid >> 1, kc_k = (tid & 1) * RUN;
+  const int mc_k = tid / TPR, mc_off = (tid % TPR) * RUN;
+
+  T ra[RUN], rb[RUN];
+  auto fetch = [&](int k0) {
+    if (AK) {
+      const int gm = m0 + kc_row;
+      const int kk = k0 + kc_k;
+      const int nv = (gm < g.M) ? max(0, min(RUN, g.K - kk)) : 0;
+      const T* p = Ab + (long long)gm * g.sAm + (long long)(kk / g.kin) * g.sAkb + (long long)(kk % g.kin) * g.sAkk;
+      load_run<T, VEC>(nv > 0 ? p : Ab, g.sAkk, nv == RUN, nv, ra);
+    } else {
+      const int kk = k0 + mc_k;
+      const int gm = m0 + mc_off;
+      const int nv = (kk < g.K) ? max(0, min(RUN, g.M - gm)) : 0;
+      const T* p = Ab + (long long)gm * g.sAm + (long long)(kk / g.kin) * g.sAkb + (long long)(kk % g.kin) * g.sAkk;
+      load_run<T, VEC>(nv > 0 ? p : Ab, g.sAm, nv == RUN, nv, ra);
+    }
+    if (BNC) {
+      const int kk = k0 + mc_k;
+      const int gn = n0 + mc_off;
+      const int nv = (kk < g.K) ? max(0, min(RUN, g.N - gn)) : 0;
+      const T* p = Bb + (long long)(kk / g.kin) * g.sBkb + (long long)(kk % g.kin) * g.sBkk + (long long)gn * g.sBn;
+      load_run<T, VEC>(nv > 0 ? p : Bb, g.sBn, nv == RUN, nv, rb);
+    } else {
+      const int gn = n0 + kc_row;
+      const int kk = k0 + kc_k;
+      const int nv = (gn < g.N) ? max(0, min(RUN, g.K - kk)) : 0;
+      const T* p = Bb + (long long)(kk / g.kin) * g.sBkb + (long long)(kk % g.kin) * g.sBkk + (long long)gn * g.sBn;
+      load_run<T, VEC>(nv > 0 ? p : Bb, g.sBkk, nv == RUN, nv, rb);
+    }
+  };
+  auto stash = [&](int buf) {
+    if (AK) {
+#pragma unroll
+      for (int u = 0; u < RUN; ++u) As[buf][kc_k + u][kc_row] = ra[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < RUN; ++u) As[buf][mc_k][mc_off + u] = ra[u];
+    }
+    if (BNC) {
+#pragma unroll
+      for (int u = 0; u < RUN; ++u) Bs[buf][mc_k][mc_off + u] = rb[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < RUN; ++u) Bs[buf][kc_k + u][kc_row] = rb[u];
+    }
+  };
+
   T acc[4][4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -74,66 +204,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restri
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    const long long kbase_a = (long long)(k0 / g.kin) * g.sAkb;
-    const long long kbase_b = (long long)(k0 / g.kin) * g.sBkb;
-    const int kr = k0 % g.kin;  // offset inside the inner K block (tile never straddles)
-    // ---- A tile -> LDS (As[k][m]) ----
-    if (AK) {
-      const int m = tid >> 1, kh = (tid & 1) * 8;
-      const int gm = m0 + m;
+  KIter<BKc> it(g, blockIdx.x, blockIdx.y, bz);
+  int buf = 0;
+  int kcur = it.first();
+  if (kcur >= 0) {
+    fetch(kcur);
+    stash(0);
+  }
+  __syncthreads();
+  while (kcur >= 0) {
+    const int knext = it.next(kcur);
+    const bool more = knext >= 0;
+    if (more) fetch(knext);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int kk = kh + u;
-        T v = T(0);
-        if (gm < g.M && k0 + kk < g.K) v = Ab[(long long)gm * g.sAm + kbase_a + (long long)(kr + kk) * g.sAkk];
-        As[kk][m] = v;
-      }
-    } else {
-      const int kk = tid >> 4, mc = (tid & 15) * 8;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int gm = m0 + mc + u;
-        T v = T(0);
-        if (gm < g.M && k0 + kk < g.K) v = Ab[(long long)gm * g.sAm + kbase_a + (long long)(kr + kk) * g.sAkk];
-        As[kk][mc + u] = v;
-      }
-    }
-    // ---- B tile -> LDS (Bs[k][n]) ----
-    if (BNC) {
-      const int kk = tid >> 4, nc = (tid & 15) * 8;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int gn = n0 + nc + u;
-        T v = T(0);
-        if (gn < g.N && k0 + kk < g.K) v = Bb[kbase_b + (long long)(kr + kk) * g.sBkk + (long long)gn * g.sBn];
-        Bs[kk][nc + u] = v;
-      }
-    } else {
-      const int n = tid >> 1, kh = (tid & 1) * 8;
-      const int gn = n0 + n;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int kk = kh + u;
-        T v = T(0);
-        if (gn < g.N && k0 + kk < g.K) v = Bb[kbase_b + (long long)(kr + kk) * g.sBkk + (long long)gn * g.sBn];
-        Bs[kk][n] = v;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
+    for (int ks = 0; ks < BKc; ks += 4) {
       T a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[ks + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 4; ++i) a[i] = As[buf][ks + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[ks + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][ks + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) mfma_step<T>(a[i], b[j], acc[i][j]);
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
+    kcur = knext;
   }
   // ---- epilogue ----
 #pragma unroll
@@ -169,14 +267,26 @@ void gemm(const GemmArgs& g, const T* A, const T* B, T* C, bool a_kcontig, bool 
   }
   dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
   if (grid.y > 65535 || grid.z > 65535) throw std::runtime_error("gemm: grid too large");
-  if (a_kcontig && b_ncontig)
-    hipLaunchKernelGGL((gemm_kernel<T, true, true>), grid, dim3(256), 0, s, g, A, B, C);
-  else if (a_kcontig && !b_ncontig)
-    hipLaunchKernelGGL((gemm_kernel<T, true, false>), grid, dim3(256), 0, s, g, A, B, C);
-  else if (!a_kcontig && b_ncontig)
-    hipLaunchKernelGGL((gemm_kernel<T, false, true>), grid, dim3(256), 0, s, g, A, B, C);
-  else
-    hipLaunchKernelGGL((gemm_kernel<T, false, false>), grid, dim3(256), 0, s, g, A, B, C);
+  // 16-byte vector loads need every stride that moves a run start, and the base
+  // pointers, to be aligned to 16 bytes
+  constexpr long long VW = 16 / sizeof(T);
+  const bool vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && g.sAb % VW == 0 && g.sBb % VW == 0 &&
+                   g.sAkb % VW == 0 && g.sBkb % VW == 0 && (a_kcontig ? g.sAm % VW == 0 : g.sAkk % VW == 0) &&
+                   (b_ncontig ? g.sBkk % VW == 0 : g.sBn % VW == 0) && g.kin % GemmCfg<T>::RUN == 0;
+#define LAUNCH(AKc, BNc, V) \
+  hipLaunchKernelGGL((gemm_kernel<T, AKc, BNc, V>), grid, dim3(256), 0, s, g, A, B, C)
+  if (vec) {
+    if (a_kcontig && b_ncontig) LAUNCH(true, true, true);
+    else if (a_kcontig) LAUNCH(true, false, true);
+    else if (b_ncontig) LAUNCH(false, true, true);
+    else LAUNCH(false, false, true);
+  } else {
+    if (a_kcontig && b_ncontig) LAUNCH(true, true, false);
+    else if (a_kcontig) LAUNCH(true, false, false);
+    else if (b_ncontig) LAUNCH(false, true, false);
+    else LAUNCH(false, false, false);
+  }
+#undef LAUNCH
   HIPCHECK(hipGetLastError());
 }
 
@@ -212,7 +322,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, const uint16
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK16) {
+  KIter<BK16> it(g, blockIdx.x, blockIdx.y, bz);
+  for (int k0 = it.first(); k0 >= 0; k0 = it.next(k0)) {
     const long long kbase_a = (long long)(k0 / g.kin) * g.sAkb;
     const long long kbase_b = (long long)(k0 / g.kin) * g.sBkb;
     const int kr = k0 % g.kin;
@@ -314,33 +425,55 @@ void gemm_bf16(const GemmArgs& g, const uint16_t* A, const uint16_t* B, float* C
 }
 
 // ---------------------------------------------------------------------------
-// Sparse MPO mixing (memory bound).  One output channel per blockIdx.x so that
-// all channels of one position chunk run back to back and share the chunk of
-// every input channel through L2.
+// Sparse MPO mixing (memory bound).  One wave per (output channel, chunk of 64
+// positions).  Workgroups are dispatched round-robin over the 8 XCDs, so the
+// linear workgroup id is mapped such that XCD x owns the chunks c = x mod 8 and
+// walks through every output channel of one chunk before the next: the input
+// slabs of that chunk (all channels, 64 positions x 4 states) stay resident in
+// the XCD's own L2 while the fan-in gathers re-read them.
 // ---------------------------------------------------------------------------
+constexpr int MIX_CHUNK = 64;
+constexpr int NXCD = 8;
+
+__device__ inline bool site_charge(int dn, int ds) {
+  return (dn == 0 && ds == 0) || (dn == 1 && (ds == 1 || ds == -1)) || (dn == 2 && ds == 0);
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void mix_kernel(const int* __restrict__ ptr, const int* __restrict__ src,
-                                                  const T* __restrict__ op, const T* __restrict__ in,
-                                                  long long in_cs, T* __restrict__ out, long long out_cs, int O,
-                                                  int I) {
-  const int c = blockIdx.x;
-  const long long p = (long long)blockIdx.y * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(MIX_CHUNK) void mix_kernel(const int* __restrict__ ptr, const int* __restrict__ src,
+                                                        const T* __restrict__ op, const T* __restrict__ in,
+                                                        long long in_cs, T* __restrict__ out, long long out_cs,
+                                                        int O, int I, int nout, long long nchunks, MixQ q) {
+  const long long w = blockIdx.x;
+  const long long xcd = w % NXCD;
+  const long long j = w / NXCD;
+  const long long c = (j / nout) * NXCD + xcd;  // chunk owned by this XCD
+  const int ch = (int)(j % nout);
+  if (c >= nchunks) return;
+  const long long p = c * MIX_CHUNK + threadIdx.x;
   const long long npos = (long long)O * I;
   if (p >= npos) return;
   const long long o = p / I, i = p % I;
   const long long off = o * 4LL * I + i;
   T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  const int e0 = ptr[c], e1 = ptr[c + 1];
-  for (int e = e0; e < e1; ++e) {
-    const T* w = op + 16LL * e;
-    const T* x = in + (long long)src[e] * in_cs + off;
-    const T v0 = x[0], v1 = x[I], v2 = x[2LL * I], v3 = x[3LL * I];
-    acc0 += w[0] * v0 + w[1] * v1 + w[2] * v2 + w[3] * v3;
-    acc1 += w[4] * v0 + w[5] * v1 + w[6] * v2 + w[7] * v3;
-    acc2 += w[8] * v0 + w[9] * v1 + w[10] * v2 + w[11] * v3;
-    acc3 += w[12] * v0 + w[13] * v1 + w[14] * v2 + w[15] * v3;
+  bool live = true;
+  if (q.qo) {
+    const int2 a = q.qo[o], b = q.qi[i], cc = q.qc[ch];
+    live = site_charge(b.x - a.x + q.sgn * cc.x, b.y - a.y + q.sgn * cc.y);
   }
-  T* y = out + (long long)c * out_cs + off;
+  if (live) {
+    const int e0 = ptr[ch], e1 = ptr[ch + 1];
+    for (int e = e0; e < e1; ++e) {
+      const T* wt = op + 16LL * e;
+      const T* x = in + (long long)src[e] * in_cs + off;
+      const T v0 = x[0], v1 = x[I], v2 = x[2LL * I], v3 = x[3LL * I];
+      acc0 += wt[0] * v0 + wt[1] * v1 + wt[2] * v2 + wt[3] * v3;
+      acc1 += wt[4] * v0 + wt[5] * v1 + wt[6] * v2 + wt[7] * v3;
+      acc2 += wt[8] * v0 + wt[9] * v1 + wt[10] * v2 + wt[11] * v3;
+      acc3 += wt[12] * v0 + wt[13] * v1 + wt[14] * v2 + wt[15] * v3;
+    }
+  }
+  T* y = out + (long long)ch * out_cs + off;
   y[0] = acc0;
   y[I] = acc1;
   y[2LL * I] = acc2;
@@ -349,22 +482,25 @@ __global__ __launch_bounds__(256) void mix_kernel(const int* __restrict__ ptr, c
 
 template <typename T>
 void mix(int nout, const int* ptr, const int* src, const T* op, const T* in, long long in_cs, T* out,
-         long long out_cs, int O, int I, hipStream_t s) {
+         long long out_cs, int O, int I, hipStream_t s, const MixQ* q) {
   if (nout == 0 || O == 0 || I == 0) return;
   if (!ptr || !src || !op || !in || !out) throw std::runtime_error("mix: null operand");
   const long long npos = (long long)O * I;
-  const long long chunks = (npos + 255) / 256;
-  if (chunks > 65535) throw std::runtime_error("mix: too many positions");
-  if (nout > 2147483647) throw std::runtime_error("mix: too many channels");
-  dim3 grid(nout, (unsigned)chunks);
-  hipLaunchKernelGGL((mix_kernel<T>), grid, dim3(256), 0, s, ptr, src, op, in, in_cs, out, out_cs, O, I);
+  const long long nchunks = (npos + MIX_CHUNK - 1) / MIX_CHUNK;
+  const long long nchunks_pad = ((nchunks + NXCD - 1) / NXCD) * NXCD;
+  const long long nblk = nchunks_pad * nout;
+  if (nblk > 2147483647LL) throw std::runtime_error("mix: grid too large");
+  MixQ qq;
+  if (q && q->qo && q->qi && q->qc) qq = *q;
+  hipLaunchKernelGGL((mix_kernel<T>), dim3((unsigned)nblk), dim3(MIX_CHUNK), 0, s, ptr, src, op, in, in_cs, out,
+                     out_cs, O, I, nout, nchunks, qq);
   HIPCHECK(hipGetLastError());
 }
 
 template void mix<double>(int, const int*, const int*, const double*, const double*, long long, double*, long long,
-                          int, int, hipStream_t);
+                          int, int, hipStream_t, const MixQ*);
 template void mix<float>(int, const int*, const int*, const float*, const float*, long long, float*, long long, int,
-                         int, hipStream_t);
+                         int, hipStream_t, const MixQ*);
 
 // ---------------------------------------------------------------------------
 // vector kernels
@@ -637,6 +773,63 @@ __global__ void transpose_kernel(const double* in, double* out, int n, int r, in
 void transpose_batched(const double* in, double* out, int n, int r, int c, hipStream_t s) {
   if ((long long)n * r * c == 0) return;
   hipLaunchKernelGGL(transpose_kernel, dim3(nblocks((size_t)n * r * c)), dim3(256), 0, s, in, out, n, r, c);
+  HIPCHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// diagonal of the effective Hamiltonian (Davidson preconditioner)
+// ---------------------------------------------------------------------------
+__global__ void diag_extract_kernel(const double* E, int R, int r, double* out) {
+  const long long tot = (long long)R * r;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    const long long c = t / r, a = t % r;
+    out[t] = E[(c * r + a) * r + a];
+  }
+}
+void diag_extract(const double* E, int R, int r, double* out, hipStream_t s) {
+  if ((long long)R * r == 0) return;
+  hipLaunchKernelGGL(diag_extract_kernel, dim3(nblocks((size_t)R * r)), dim3(256), 0, s, E, R, r, out);
+  HIPCHECK(hipGetLastError());
+}
+
+// out[c][n][s] (state_inner) or out[c][s][n]: sum over entries of op[e][s][s] * in[src[e]][n]
+__global__ void diag_mix_kernel(int nout, const int* ptr, const int* src, const double* op, const double* in, int n,
+                                double* out, bool state_inner) {
+  const long long tot = (long long)nout * n;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(t / n), a = (int)(t % n);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int e = ptr[c]; e < ptr[c + 1]; ++e) {
+      const double v = in[(long long)src[e] * n + a];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] += op[16LL * e + 5 * s] * v;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (state_inner) out[((long long)c * n + a) * 4 + s] = acc[s];
+      else out[((long long)c * 4 + s) * n + a] = acc[s];
+    }
+  }
+}
+void diag_mix(int nout, const int* ptr, const int* src, const double* op, const double* in, int n, double* out,
+              bool state_inner, hipStream_t s) {
+  if ((long long)nout * n == 0) return;
+  hipLaunchKernelGGL(diag_mix_kernel, dim3(nblocks((size_t)nout * n)), dim3(256), 0, s, nout, ptr, src, op, in, n, out,
+                     state_inner);
+  HIPCHECK(hipGetLastError());
+}
+
+// t = mask ? r / (theta - d) : 0, with |theta - d| clamped from below
+__global__ void precond_kernel(double* t, const double* r, const double* d, double theta, const uint8_t* m, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double den = theta - d[i];
+    if (fabs(den) < 1e-3) den = den < 0 ? -1e-3 : 1e-3;
+    t[i] = m[i] ? r[i] / den : 0.0;
+  }
+}
+void precond(double* t, const double* r, const double* d, double theta, const uint8_t* m, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(precond_kernel, dim3(nblocks(n)), dim3(256), 0, s, t, r, d, theta, m, n);
   HIPCHECK(hipGetLastError());
 }
 
