@@ -147,6 +147,21 @@ int tt_heff_apply_dev(void* ctx, int prec, int rl, int rr, int RA, int RB, int R
                       const void* Renv, int nnz1, const int32_t* A1, const int32_t* B1, const double* ops1, int nnz2,
                       const int32_t* A2, const int32_t* B2, const double* ops2, const void* x, void* y);
 
+/* Two-site product of the context's MPO at sites (b, b+1), y = H_eff x
+ * (eq. mat_vec with the two-site contraction of Section 3), through the same
+ * quantum-number block-sparse kernels the local solves use.  rl, rr: bond
+ * dimensions at bonds b and b+2; ql [rl][2], qr [rr][2]: host (N, 2Sz) labels
+ * of those bonds, equal labels contiguous (otherwise the dense product with
+ * zero-block skipping is used).  Lenv: device FP64 [R_b][rlp][rlp] (bra, ket),
+ * Renv: device FP64 [R_{b+2}][rrp][rrp], x, y: device FP64 [rlp][4][4][rrp],
+ * with rlp, rrp = rl, rr rounded up to multiples of 32 (padding zero).
+ * Entries of Lenv, Renv, x outside their charge blocks must be zero; prec
+ * selects the arithmetic (TT_F64, TT_F32, or FP32 on bfloat16-rounded
+ * operands for TT_BF16).  y is overwritten.  TT_EINVAL on bad arguments,
+ * TT_ESTATE without an MPO. */
+int tt_window_apply_dev(void* ctx, int b, int rl, int rr, const int32_t* ql, const int32_t* qr, const double* Lenv,
+                        const double* Renv, int prec, const double* x, double* y);
+
 /* One environment update (double precision).  side 0: left update
  * out[B][rb2][rk2] = sum E[A][rb][rk] Ubra[rb][4][rb2] W[A,s',s,B] Uket[rk][4][rk2];
  * side 1: right update out[A][rb][rk] = sum Ubra[rb][4][rb2] W Uket[rk][4][rk2] E[B][rb2][rk2].

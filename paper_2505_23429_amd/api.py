@@ -249,6 +249,24 @@ def heff_apply_rb(ctx, prec, Lenv, W1, W2, Renv, x, RB, y=None):
     return y
 
 
+def window_apply(ctx, b, ql, qr, Lenv, Renv, x, prec="f64", y=None):
+    """y = H_eff x of the context's MPO at sites (b, b+1) with the given FP64
+    device environments and bond labels (tt_window_apply_dev)."""
+    import torch
+
+    ql = np.ascontiguousarray(ql, dtype=np.int32)
+    qr = np.ascontiguousarray(qr, dtype=np.int32)
+    if y is None:
+        y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    I32 = C.POINTER(C.c_int32)
+    rc = ctx.lib.tt_window_apply_dev(ctx.h, int(b), len(ql), len(qr), ql.ctypes.data_as(I32), qr.ctypes.data_as(I32),
+                                     C.c_void_p(Lenv.data_ptr()), C.c_void_p(Renv.data_ptr()), PREC[prec],
+                                     C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()))
+    ctx._check(rc)
+    return y
+
+
 def gemm(ctx, prec, M, N, K, batch, kin, strides, a_kcontig, b_ncontig, A, B, Cout, alpha=1.0, beta=0.0):
     """Strided batched MFMA GEMM on device tensors (see tt_gemm_dev)."""
     import torch

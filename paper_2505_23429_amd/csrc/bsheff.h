@@ -1,0 +1,65 @@
+// Quantum-number block-sparse form of the two-site effective-Hamiltonian
+// product of one window (sites k, k+1).
+//
+// Bond labels are grouped by charge into sectors (alpha on the left bond,
+// beta on the right bond).  The channel index and one site index of every
+// intermediate combine into a row (K, s) whose charge Gamma = q(s) - d_K is
+// conserved by each MPO site tensor; the remaining indices form a spectator
+// block (alpha', s_other, beta) of shape n_alpha' x n_beta, and a spectator
+// belongs to the group Gamma = Q_beta - Q_alpha' - q(s_other).  Per group an
+// intermediate is one dense row-major matrix [rows x spectator elements], so
+//   stage 1  T1 = L_A x           grouped GEMM per left sector alpha
+//   mix 1    T2 = W1 T1           sparse x dense product per group (site k)
+//   mix 2    T3 = W2 T2           sparse x dense product per group (site k+1)
+//   stage 4  y  = sum_C T3 R_C^T  grouped split-K GEMM per right sector beta'
+// store and touch only the structurally non-zero entries.  The environments
+// stay dense; x and y are the dense padded vectors [rlp][4][4][rrp].
+#pragma once
+#include "engine.h"
+
+namespace tt {
+
+struct BsAlpha { int M, N, K, row0, col0, oal; };
+struct BsGroup { long long in_base; int ncols, spec0, nspec, pad; };
+struct BsS4Tile { long long abase, bbase; int M, N, K, m0, n0, k0, k1, slot; };
+struct BsRedTile { int M, N, m0, n0, slot0, nsplit, row0, pad; };
+struct BsPair { int C, beta, koff, bprime; };
+
+struct BsMix {
+  int ntiles = 0;
+  double flops = 0.0, nin = 0.0, nout = 0.0;  // 2 nnz cols; elements read and written once
+  DevMem tiles, groups, optr, ocol, oval64, oval32, orow, spec;
+};
+
+struct BsPlan {
+  bool ok = false;
+  long long serial = 0;
+  int rlp = 0, rrp = 0, nal = 0, nbe = 0, RAx = 0, RB = 0, RC = 0, RCx = 0, ndcls = 0;
+  long long n1 = 0, n2 = 0, n3 = 0, nrs = 0;  // elements of T1, T2, T3 and the stacked R
+  double flops1 = 0.0, flops4 = 0.0;          // block-sparse flops of stages 1 and 4
+  double bytes1 = 0.0, bytes4 = 0.0;          // element counts moved once by stages 1 and 4
+  // stage 1
+  int ntiles1 = 0;
+  DevMem tiles1, alpha, rsrc, rinfo, cinfo, rowpart1, specoff, nbeta, boff;
+  // mixes
+  BsMix m1, m2;
+  DevMem rowbase2, ccls, bshift, pbase, kbeta, koff;
+  // stage 4
+  int ntiles4 = 0, nred = 0, nslots = 0, npairs = 0;
+  DevMem tiles4, red, rowdst, pairs, rbase;
+  DevMem rstack64, rstack32;
+  bool have64 = false, have32 = false;
+  DevMem err;  // set by a kernel when an index would leave its buffer (the access is skipped)
+};
+
+// Builds the plan of the window at sites (b, b+1).  Returns false (no plan)
+// when the labels of a bond are not grouped by charge.
+bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, int rlp, int rrp, int RAx, int nP);
+
+// y = H_eff x.  L: [RAx][rlp][rlp] (virtual channels included), R: [RC][rrp][rrp],
+// Rt: [RCx - RC][rrp][rrp] (second-site block channels), x, y: [rlp][4][4][rrp].
+// bf16_t3 rounds the mix-2 output to bfloat16 before the last contraction.
+template <typename T>
+void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3);
+
+}  // namespace tt

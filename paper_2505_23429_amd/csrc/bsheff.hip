@@ -1,0 +1,685 @@
+// Quantum-number block-sparse two-site effective-Hamiltonian product:
+// per-window plan (host) and the four device stages.  The layout is described
+// in bsheff.h.
+#include "bsheff.h"
+
+#include <algorithm>
+#include <map>
+#include <stdexcept>
+
+namespace tt {
+
+#define BSCHECK(x)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+const Q2 kSiteQ[4] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};  // |0>, |up>, |dn>, |up dn>: (N, 2Sz)
+inline Q2 add(Q2 a, Q2 b) { return {a[0] + b[0], a[1] + b[1]}; }
+inline Q2 sub(Q2 a, Q2 b) { return {a[0] - b[0], a[1] - b[1]}; }
+
+constexpr int TILE = 64;       // output tile edge of the stage-1 and stage-4 kernels
+constexpr int KT = 32;         // K slice staged in LDS
+constexpr int MIX_COLS = 256;  // spectator columns per mix workgroup (one per thread)
+constexpr int MIX_ROWS = 64;   // output rows per mix workgroup
+constexpr int KSPLIT = 2048;   // K chunk of one stage-4 workgroup
+
+struct Sectors {
+  std::vector<Q2> q;
+  std::vector<int> off, n;
+  std::map<Q2, int> id;
+  int find(Q2 c) const {
+    auto it = id.find(c);
+    return it == id.end() ? -1 : it->second;
+  }
+};
+
+// sectors of a label list; false if equal charges are not contiguous
+bool make_sectors(const Labels& lab, Sectors& s) {
+  for (int i = 0; i < (int)lab.size(); ++i) {
+    if (i == 0 || lab[i] != lab[i - 1]) {
+      if (s.id.count(lab[i])) return false;
+      s.id[lab[i]] = (int)s.q.size();
+      s.q.push_back(lab[i]);
+      s.off.push_back(i);
+      s.n.push_back(0);
+    }
+    s.n.back()++;
+  }
+  return true;
+}
+
+template <class V>
+void up(DevMem& d, const std::vector<V>& v, hipStream_t s) {
+  upload(d, v.data(), v.size() * sizeof(V), s);
+}
+
+__device__ inline float bf16_round(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+// ---------------------------------------------------------------------------
+// stage 1: T1[(A, s1)][spec(a', s2, b) + i' n_b + j] = sum_a L_A[a'][a] x[a][s1][s2][b]
+// for each left sector alpha (rows (A, i') with a' in alpha + d_A, columns
+// (s1, s2, j) with b in alpha + q(s1) + q(s2)).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void stage1_kernel(const int4* __restrict__ tiles, const BsAlpha* __restrict__ al,
+                                                     const long long* __restrict__ rsrc, const int4* __restrict__ rinfo,
+                                                     const int4* __restrict__ cinfo,
+                                                     const long long* __restrict__ rowpart,
+                                                     const long long* __restrict__ specoff,
+                                                     const int* __restrict__ nbeta, int nbe, const T* __restrict__ L,
+                                                     long long nL, const T* __restrict__ x, long long nx,
+                                                     long long xld, T* __restrict__ out, long long nout,
+                                                     int* __restrict__ err) {
+  const int4 t = tiles[blockIdx.x];
+  const BsAlpha a = al[t.x];
+  const int m0 = t.y, c0 = t.z;
+  __shared__ T Ls[KT][TILE + 1];
+  __shared__ T Xs[KT][TILE + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  for (int k0 = 0; k0 < a.K; k0 += KT) {
+    for (int e = tid; e < TILE * KT; e += 256) {
+      const int r = e / KT, kk = e % KT;
+      T v = T(0);
+      if (m0 + r < a.M && k0 + kk < a.K) {
+        const long long q = rsrc[a.row0 + m0 + r] + k0 + kk;
+        if (q >= 0 && q < nL) v = L[q]; else err[0] = 1;
+      }
+      Ls[kk][r] = v;
+    }
+    for (int e = tid; e < TILE * KT; e += 256) {
+      const int kk = e / TILE, c = e % TILE;
+      T v = T(0);
+      if (c0 + c < a.N && k0 + kk < a.K) {
+        const long long q = (long long)(a.oal + k0 + kk) * xld + cinfo[a.col0 + c0 + c].x;
+        if (q >= 0 && q < nx) v = x[q]; else err[0] = 2;
+      }
+      Xs[kk][c] = v;
+    }
+    __syncthreads();
+    const int kn = min(KT, a.K - k0);
+    for (int kk = 0; kk < kn; ++kk) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = Ls[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Xs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = m0 + ty * 4 + i;
+    if (r >= a.M) continue;
+    const int4 ri = rinfo[a.row0 + r];  // {A, i', alpha', -}
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tx + 16 * j;
+      if (c >= a.N) continue;
+      const int4 ci = cinfo[a.col0 + c];  // {x column, s1*4+s2, beta, j}
+      const long long rp = rowpart[ri.x * 4 + (ci.y >> 2)];
+      const long long so = specoff[((long long)ri.z * 4 + (ci.y & 3)) * nbe + ci.z];
+      const long long d = rp + so + (long long)ri.y * nbeta[ci.z] + ci.w;
+      if (rp < 0 || so < 0 || d >= nout) { err[0] = 3; continue; }
+      out[d] = acc[i][j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// mixes: out row r of a group = sum_e val_e * in row col_e of the same group,
+// one spectator column per thread.  MODE 1 scatters into the T2 layout
+// (rows (B, s2)), MODE 2 into the stage-4 panels (rows (a', s1', s2', i'),
+// columns (C, j)).
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(MIX_COLS) void mix_kernel(
+    const int4* __restrict__ tiles, const BsGroup* __restrict__ groups, const int* __restrict__ optr,
+    const int* __restrict__ ocol, const T* __restrict__ oval, const int2* __restrict__ orow,
+    const int4* __restrict__ spec, const T* __restrict__ in, long long nin, T* __restrict__ out, long long nout,
+    int* __restrict__ err, int nbe,
+    const long long* __restrict__ rowbase2, const long long* __restrict__ specoff, const int* __restrict__ ccls,
+    const int* __restrict__ bshift, const long long* __restrict__ pbase, const int* __restrict__ kbeta,
+    const int* __restrict__ koff, int RCx, const int* __restrict__ nbeta, int round_bf16) {
+  const int4 t = tiles[blockIdx.x];
+  const BsGroup G = groups[t.x];
+  const int col = t.y + (int)threadIdx.x;
+  if (col >= G.ncols) return;
+  int lo = 0, hi = G.nspec - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (spec[G.spec0 + mid].x <= col) lo = mid; else hi = mid - 1;
+  }
+  const int4 sp = spec[G.spec0 + lo];  // {start, alpha', s, beta}
+  const int within = col - sp.x;
+  int wi = 0, wj = within;
+  if (MODE == 2) {
+    const int nb = nbeta[sp.w];
+    wi = within / nb;
+    wj = within - wi * nb;
+  }
+  const T* src = in + G.in_base + col;
+  const long long ld = G.ncols;
+  const long long lim = nin - G.in_base - col;  // src[q] valid for 0 <= q < lim
+  for (int r = t.z; r < t.w; ++r) {
+    T acc = T(0);
+    const int e1 = optr[r + 1];
+    for (int e = optr[r]; e < e1; ++e) {
+      const long long q = (long long)ocol[e] * ld;
+      if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 4;
+    }
+    const int2 ro = orow[r];  // {channel, site state}
+    long long d;
+    if (MODE == 1) {
+      const long long rb = rowbase2[ro.x * 4 + sp.z];
+      const long long so = specoff[((long long)sp.y * 4 + ro.y) * nbe + sp.w];
+      if (rb < 0 || so < 0) { err[0] = 5; continue; }
+      d = rb + so + within;
+    } else {
+      const int bp = bshift[ccls[ro.x] * nbe + sp.w];
+      if (bp < 0) continue;
+      const long long pb = pbase[(((long long)sp.y * 4 + sp.z) * 4 + ro.y) * nbe + bp];
+      const int ko = koff[(long long)bp * RCx + ro.x];
+      if (pb < 0 || ko < 0) { err[0] = 6; continue; }
+      d = pb + (long long)wi * kbeta[bp] + ko + wj;
+      if (round_bf16) acc = (T)bf16_round((float)acc);
+    }
+    if (d < 0 || d >= nout) { err[0] = 7; continue; }
+    out[d] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 4: partial[slot] = panel rows [m0, m0+64) x stacked R columns [n0, n0+64)
+// over K in [k0, k1); the reduction sums the K chunks and writes rows of y.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void stage4_kernel(const BsS4Tile* __restrict__ tiles, const T* __restrict__ A,
+                                                     long long nA, const T* __restrict__ B, long long nB,
+                                                     T* __restrict__ part, int* __restrict__ err) {
+  const BsS4Tile t = tiles[blockIdx.x];
+  if (t.abase < 0 || t.abase + (long long)t.M * t.K > nA || t.bbase < 0 || t.bbase + (long long)t.K * t.N > nB) {
+    if (threadIdx.x == 0) err[0] = 8;
+    return;
+  }
+  __shared__ T As[KT][TILE + 1];
+  __shared__ T Bs[KT][TILE + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  for (int k0 = t.k0; k0 < t.k1; k0 += KT) {
+    for (int e = tid; e < TILE * KT; e += 256) {
+      const int r = e / KT, kk = e % KT;
+      T v = T(0);
+      if (t.m0 + r < t.M && k0 + kk < t.k1) v = A[t.abase + (long long)(t.m0 + r) * t.K + k0 + kk];
+      As[kk][r] = v;
+    }
+    for (int e = tid; e < TILE * KT; e += 256) {
+      const int kk = e / TILE, c = e % TILE;
+      T v = T(0);
+      if (t.n0 + c < t.N && k0 + kk < t.k1) v = B[t.bbase + (long long)(k0 + kk) * t.N + t.n0 + c];
+      Bs[kk][c] = v;
+    }
+    __syncthreads();
+    const int kn = min(KT, t.k1 - k0);
+    for (int kk = 0; kk < kn; ++kk) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+  T* P = part + (long long)t.slot * (TILE * TILE);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) P[(ty * 4 + i) * TILE + tx + 16 * j] = acc[i][j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void reduce4_kernel(const BsRedTile* __restrict__ red, const T* __restrict__ part,
+                                                      const long long* __restrict__ rowdst, T* __restrict__ y,
+                                                      long long ny, int* __restrict__ err) {
+  const BsRedTile t = red[blockIdx.x];
+  for (int e = threadIdx.x; e < TILE * TILE; e += 256) {
+    const int r = e / TILE, c = e % TILE;
+    if (t.m0 + r >= t.M || t.n0 + c >= t.N) continue;
+    T s = T(0);
+    for (int q = 0; q < t.nsplit; ++q) s += part[(long long)(t.slot0 + q) * (TILE * TILE) + e];
+    const long long d = rowdst[t.row0 + t.m0 + r] + t.n0 + c;
+    if (d < 0 || d >= ny) { err[0] = 9; continue; }
+    y[d] = s;
+  }
+}
+
+// stacked R of sector beta': rows (C, j) with b = off(beta) + j, columns j' with b' = off(beta') + j'
+template <typename T>
+__global__ __launch_bounds__(256) void rstack_kernel(const BsPair* __restrict__ pairs, const int* __restrict__ boff,
+                                                     const int* __restrict__ nbeta,
+                                                     const long long* __restrict__ rbase, int RC, int RCx, int rrp,
+                                                     const T* __restrict__ R, const T* __restrict__ Rt,
+                                                     T* __restrict__ rs, long long nrs, int* __restrict__ err) {
+  const BsPair p = pairs[blockIdx.x];
+  const int nb = nbeta[p.beta], nbp = nbeta[p.bprime], ob = boff[p.beta], obp = boff[p.bprime];
+  const long long rr2 = (long long)rrp * rrp;
+  const T* src = p.C < RC ? R + (long long)p.C * rr2 : Rt + (long long)(p.C - RC) * rr2;
+  T* dst = rs + rbase[p.bprime] + (long long)p.koff * nbp;
+  if (p.C < 0 || p.C >= RCx || ob < 0 || obp < 0 || ob + nb > rrp || obp + nbp > rrp ||
+      rbase[p.bprime] + (long long)(p.koff + nb) * nbp > nrs) {
+    if (threadIdx.x == 0) err[0] = 10;
+    return;
+  }
+  for (int e = threadIdx.x; e < nb * nbp; e += 256) {
+    const int j = e / nbp, jp = e - j * nbp;
+    dst[(long long)j * nbp + jp] = src[(long long)(obp + jp) * rrp + ob + j];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q2>& dout, int nout_ch,
+                      const std::vector<int>& rowidx_in, const std::vector<int>& grp_in, const std::map<Q2, int>& gid,
+                      const std::vector<Q2>& gq, const std::vector<int>& cols, const std::vector<long long>& in_off,
+                      const std::vector<int>& nrows_in, const std::vector<int>& spec0,
+                      const std::vector<int>& nspec) {
+  const int ng = (int)gq.size();
+  std::vector<std::vector<int2>> rows_by_g(ng);
+  for (int K = 0; K < nout_ch; ++K)
+    for (int s = 0; s < 4; ++s) {
+      auto it = gid.find(sub(kSiteQ[s], dout[K]));
+      if (it != gid.end()) rows_by_g[it->second].push_back(make_int2(K, s));
+    }
+  std::vector<int> optr(1, 0), ocol;
+  std::vector<double> oval;
+  std::vector<int2> orow;
+  std::vector<int4> tiles;
+  std::vector<BsGroup> groups(ng);
+  m.flops = m.nin = m.nout = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    groups[g] = BsGroup{in_off[g], cols[g], spec0[g], nspec[g], 0};
+    const int r0 = (int)orow.size();
+    long long nnz_g = 0;
+    for (const int2& ro : rows_by_g[g]) {
+      const int K = ro.x, sp = ro.y;
+      for (int e = so.hptr[K]; e < so.hptr[K + 1]; ++e) {
+        const int A = so.hsrc[e];
+        for (int s = 0; s < 4; ++s) {
+          const double v = so.hop[(size_t)e * 16 + sp * 4 + s];
+          if (v == 0.0) continue;
+          const int ri = rowidx_in[A * 4 + s];
+          if (ri < 0 || grp_in[A * 4 + s] != g)
+            throw std::runtime_error("block-sparse plan: MPO entry breaks the charge grouping");
+          ocol.push_back(ri);
+          oval.push_back(v);
+          ++nnz_g;
+        }
+      }
+      optr.push_back((int)ocol.size());
+      orow.push_back(ro);
+    }
+    const int r1 = (int)orow.size();
+    if (cols[g] == 0 || r1 == r0) continue;
+    m.flops += 2.0 * (double)nnz_g * cols[g];
+    m.nin += (double)nrows_in[g] * cols[g];
+    m.nout += (double)(r1 - r0) * cols[g];
+    for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
+      for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
+  }
+  if (ocol.empty()) { ocol.push_back(0); oval.push_back(0.0); }
+  std::vector<float> oval32(oval.begin(), oval.end());
+  m.ntiles = (int)tiles.size();
+  hipStream_t s = E.stream;
+  up(m.tiles, tiles, s);
+  up(m.groups, groups, s);
+  up(m.optr, optr, s);
+  up(m.ocol, ocol, s);
+  up(m.oval64, oval, s);
+  up(m.oval32, oval32, s);
+  up(m.orow, orow, s);
+}
+
+bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, int rlp, int rrp, int RAx, int nP) {
+  p.ok = false;
+  Sectors SA, SB;
+  if (!make_sectors(ql, SA) || !make_sectors(qr, SB)) return false;
+  const SiteMPO& s1 = E.mpo[b];
+  const SiteMPO& s2 = E.mpo[b + 1];
+  const SiteOp& w1 = s1.has_block ? s1.byB_left : s1.byB;
+  const SiteOp& w2 = s2.has_block ? s2.byB_rightv : s2.byB;
+  const int nal = (int)SA.q.size(), nbe = (int)SB.q.size();
+  const int RB = s1.Rr, RC = s2.Rr, RCx = RC + (s2.has_block ? nP : 0);
+  if (w1.nout != RB || w2.nout != RCx) throw std::runtime_error("block-sparse plan: channel count mismatch");
+  p.rlp = rlp; p.rrp = rrp; p.nal = nal; p.nbe = nbe; p.RAx = RAx; p.RB = RB; p.RC = RC; p.RCx = RCx;
+  // channel charges (virtual channels carry the charge of the block channel they stand for)
+  std::vector<Q2> dA(RAx), dB(RB), dC(RCx);
+  for (int A = 0; A < RAx; ++A) dA[A] = A < s1.Rl ? E.chan_q[b][A] : E.chan_q[b + 1][s1.q0 + (A - s1.Rl)];
+  for (int B = 0; B < RB; ++B) dB[B] = E.chan_q[b + 1][B];
+  for (int C = 0; C < RCx; ++C) dC[C] = C < RC ? E.chan_q[b + 2][C] : E.chan_q[b + 1][s2.p0 + (C - RC)];
+
+  // spectator groups
+  std::map<Q2, int> gid;
+  std::vector<Q2> gq;
+  std::vector<int> cols;
+  std::vector<std::vector<int4>> spec_g;
+  std::vector<long long> specoff((size_t)nal * 4 * nbe, -1);
+  for (int a = 0; a < nal; ++a)
+    for (int s = 0; s < 4; ++s)
+      for (int be = 0; be < nbe; ++be) {
+        const Q2 G = sub(sub(SB.q[be], SA.q[a]), kSiteQ[s]);
+        auto it = gid.find(G);
+        int g;
+        if (it == gid.end()) {
+          g = (int)gq.size();
+          gid[G] = g;
+          gq.push_back(G);
+          cols.push_back(0);
+          spec_g.emplace_back();
+        } else {
+          g = it->second;
+        }
+        specoff[((size_t)a * 4 + s) * nbe + be] = cols[g];
+        spec_g[g].push_back(make_int4(cols[g], a, s, be));
+        cols[g] += SA.n[a] * SB.n[be];
+      }
+  const int ng = (int)gq.size();
+  std::vector<int4> spec;
+  std::vector<int> spec0(ng), nspec(ng);
+  for (int g = 0; g < ng; ++g) {
+    spec0[g] = (int)spec.size();
+    nspec[g] = (int)spec_g[g].size();
+    spec.insert(spec.end(), spec_g[g].begin(), spec_g[g].end());
+  }
+
+  // row grouping of T1 (rows (A, s1)) and T2 (rows (B, s2))
+  auto rows_of = [&](const std::vector<Q2>& d, int n, std::vector<int>& idx, std::vector<int>& grp,
+                     std::vector<int>& nrows) {
+    idx.assign((size_t)n * 4, -1);
+    grp.assign((size_t)n * 4, -1);
+    nrows.assign(ng, 0);
+    for (int K = 0; K < n; ++K)
+      for (int s = 0; s < 4; ++s) {
+        auto it = gid.find(sub(kSiteQ[s], d[K]));
+        if (it == gid.end()) continue;
+        grp[K * 4 + s] = it->second;
+        idx[K * 4 + s] = nrows[it->second]++;
+      }
+  };
+  std::vector<int> idx1, grp1, nr1, idx2, grp2, nr2;
+  rows_of(dA, RAx, idx1, grp1, nr1);
+  rows_of(dB, RB, idx2, grp2, nr2);
+  std::vector<long long> off1(ng), off2(ng);
+  long long n1 = 0, n2 = 0;
+  for (int g = 0; g < ng; ++g) {
+    off1[g] = n1; n1 += (long long)nr1[g] * cols[g];
+    off2[g] = n2; n2 += (long long)nr2[g] * cols[g];
+  }
+  std::vector<long long> rowpart1((size_t)RAx * 4, -1), rowbase2((size_t)RB * 4, -1);
+  for (int i = 0; i < RAx * 4; ++i)
+    if (idx1[i] >= 0) rowpart1[i] = off1[grp1[i]] + (long long)idx1[i] * cols[grp1[i]];
+  for (int i = 0; i < RB * 4; ++i)
+    if (idx2[i] >= 0) rowbase2[i] = off2[grp2[i]] + (long long)idx2[i] * cols[grp2[i]];
+  p.n1 = n1;
+  p.n2 = n2;
+
+  // stage 1 tables
+  std::vector<BsAlpha> alpha(nal);
+  std::vector<long long> rsrc;
+  std::vector<int4> rinfo, cinfo, tiles1;
+  const long long rl2 = (long long)rlp * rlp;
+  p.flops1 = 0.0;
+  p.bytes1 = 0.0;
+  for (int a = 0; a < nal; ++a) {
+    BsAlpha& A_ = alpha[a];
+    A_.row0 = (int)rinfo.size();
+    A_.col0 = (int)cinfo.size();
+    A_.K = SA.n[a];
+    A_.oal = SA.off[a];
+    for (int A = 0; A < RAx; ++A) {
+      const int ap = SA.find(add(SA.q[a], dA[A]));
+      if (ap < 0) continue;
+      for (int i = 0; i < SA.n[ap]; ++i) {
+        rsrc.push_back((long long)A * rl2 + (long long)(SA.off[ap] + i) * rlp + SA.off[a]);
+        rinfo.push_back(make_int4(A, i, ap, 0));
+      }
+    }
+    for (int s1_ = 0; s1_ < 4; ++s1_)
+      for (int s2_ = 0; s2_ < 4; ++s2_) {
+        const int be = SB.find(add(add(SA.q[a], kSiteQ[s1_]), kSiteQ[s2_]));
+        if (be < 0) continue;
+        for (int j = 0; j < SB.n[be]; ++j)
+          cinfo.push_back(make_int4((s1_ * 4 + s2_) * rrp + SB.off[be] + j, s1_ * 4 + s2_, be, j));
+      }
+    A_.M = (int)rinfo.size() - A_.row0;
+    A_.N = (int)cinfo.size() - A_.col0;
+    p.flops1 += 2.0 * A_.M * (double)A_.N * A_.K;
+    p.bytes1 += (double)A_.M * A_.K + (double)A_.K * A_.N + (double)A_.M * A_.N;
+    for (int m0 = 0; m0 < A_.M; m0 += TILE)
+      for (int c0 = 0; c0 < A_.N; c0 += TILE) tiles1.push_back(make_int4(a, m0, c0, 0));
+  }
+  p.ntiles1 = (int)tiles1.size();
+
+  // stage 4 tables: delta classes of the output channels
+  std::map<Q2, int> dcls;
+  std::vector<int> ccls(RCx);
+  for (int C = 0; C < RCx; ++C) {
+    auto it = dcls.find(dC[C]);
+    if (it == dcls.end()) it = dcls.emplace(dC[C], (int)dcls.size()).first;
+    ccls[C] = it->second;
+  }
+  p.ndcls = (int)dcls.size();
+  std::vector<int> bshift((size_t)p.ndcls * nbe, -1);
+  for (auto& kv : dcls)
+    for (int be = 0; be < nbe; ++be) bshift[(size_t)kv.second * nbe + be] = SB.find(add(SB.q[be], kv.first));
+  std::vector<int> koff((size_t)nbe * RCx, -1), kbeta(nbe, 0);
+  std::vector<BsPair> pairs;
+  std::vector<long long> rbase(nbe, 0);
+  long long nrs = 0;
+  for (int bp = 0; bp < nbe; ++bp) {
+    rbase[bp] = nrs;
+    for (int C = 0; C < RCx; ++C) {
+      const int be = SB.find(sub(SB.q[bp], dC[C]));
+      if (be < 0) continue;
+      koff[(size_t)bp * RCx + C] = kbeta[bp];
+      pairs.push_back(BsPair{C, be, kbeta[bp], bp});
+      kbeta[bp] += SB.n[be];
+    }
+    nrs += (long long)kbeta[bp] * SB.n[bp];
+  }
+  p.nrs = nrs;
+  p.npairs = (int)pairs.size();
+  std::vector<long long> pbase((size_t)nal * 16 * nbe, -1), rowdst;
+  std::vector<BsS4Tile> tiles4;
+  std::vector<BsRedTile> red;
+  long long n3 = 0;
+  int slots = 0;
+  p.flops4 = 0.0;
+  p.bytes4 = 0.0;
+  for (int bp = 0; bp < nbe; ++bp) {
+    const int row0 = (int)rowdst.size();
+    int M = 0;
+    for (int a = 0; a < nal; ++a)
+      for (int s1_ = 0; s1_ < 4; ++s1_)
+        for (int s2_ = 0; s2_ < 4; ++s2_) {
+          if (add(add(SA.q[a], kSiteQ[s1_]), kSiteQ[s2_]) != SB.q[bp]) continue;
+          pbase[(((size_t)a * 4 + s1_) * 4 + s2_) * nbe + bp] = n3 + (long long)M * kbeta[bp];
+          for (int i = 0; i < SA.n[a]; ++i)
+            rowdst.push_back((long long)(SA.off[a] + i) * 16 * rrp + (long long)(s1_ * 4 + s2_) * rrp + SB.off[bp]);
+          M += SA.n[a];
+        }
+    const int K = kbeta[bp], N = SB.n[bp];
+    if (M > 0 && K > 0) {
+      p.flops4 += 2.0 * M * (double)K * N;
+      p.bytes4 += (double)M * K + (double)K * N + (double)M * N;
+      for (int m0 = 0; m0 < M; m0 += TILE)
+        for (int n0 = 0; n0 < N; n0 += TILE) {
+          BsRedTile r{M, N, m0, n0, slots, 0, row0, 0};
+          for (int k0 = 0; k0 < K; k0 += KSPLIT) {
+            tiles4.push_back(BsS4Tile{n3, rbase[bp], M, N, K, m0, n0, k0, std::min(K, k0 + KSPLIT), slots});
+            ++slots;
+            ++r.nsplit;
+          }
+          red.push_back(r);
+        }
+    }
+    n3 += (long long)M * K;
+  }
+  p.n3 = n3;
+  p.ntiles4 = (int)tiles4.size();
+  p.nred = (int)red.size();
+  p.nslots = slots;
+
+  hipStream_t s = E.stream;
+  up(p.tiles1, tiles1, s);
+  up(p.alpha, alpha, s);
+  up(p.rsrc, rsrc, s);
+  up(p.rinfo, rinfo, s);
+  up(p.cinfo, cinfo, s);
+  up(p.rowpart1, rowpart1, s);
+  up(p.specoff, specoff, s);
+  up(p.nbeta, SB.n, s);
+  up(p.boff, SB.off, s);
+  up(p.rowbase2, rowbase2, s);
+  up(p.ccls, ccls, s);
+  up(p.bshift, bshift, s);
+  up(p.pbase, pbase, s);
+  up(p.kbeta, kbeta, s);
+  up(p.koff, koff, s);
+  up(p.tiles4, tiles4, s);
+  up(p.red, red, s);
+  up(p.rowdst, rowdst, s);
+  up(p.pairs, pairs, s);
+  up(p.rbase, rbase, s);
+  // mixes: site k (inputs T1 rows, outputs into T2) and site k+1 (inputs T2 rows, outputs into panels)
+  build_mix(E, p.m1, w1, dB, RB, idx1, grp1, gid, gq, cols, off1, nr1, spec0, nspec);
+  build_mix(E, p.m2, w2, dC, RCx, idx2, grp2, gid, gq, cols, off2, nr2, spec0, nspec);
+  up(p.m1.spec, spec, s);
+  up(p.m2.spec, spec, s);
+  p.have64 = p.have32 = false;
+  p.serial = ++E.bs_serial;
+  p.ok = true;
+  return true;
+}
+
+template <typename T>
+static const DevMem& mix_vals(const BsMix& m);
+template <>
+const DevMem& mix_vals<double>(const BsMix& m) { return m.oval64; }
+template <>
+const DevMem& mix_vals<float>(const BsMix& m) { return m.oval32; }
+
+template <typename T>
+void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3) {
+  if (!p.ok) throw std::runtime_error("block-sparse plan not built");
+  hipStream_t s = E.stream;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const size_t ny = (size_t)p.rlp * 16 * p.rrp;
+  if (!p.err.p) p.err.resize_zero(sizeof(int), s);
+  int* err = p.err.as<int>();
+  E.bs_t1.ensure(sizeof(T) * std::max<long long>(p.n1, 1));
+  E.bs_t2.ensure(sizeof(T) * std::max<long long>(p.n2, 1));
+  E.bs_t3.ensure(sizeof(T) * std::max<long long>(p.n3, 1));
+  E.bs_part.ensure(sizeof(T) * (size_t)std::max(p.nslots, 1) * TILE * TILE);
+  if (E.bs_zero_serial != p.serial || E.bs_zero_prec != prec) {
+    // T1 entries whose left sector alpha' - d_A does not exist are never written
+    fill(E.bs_t1.p, sizeof(T) * p.n1, s);
+    E.bs_zero_serial = p.serial;
+    E.bs_zero_prec = prec;
+  }
+  DevMem& rs = prec == 0 ? p.rstack64 : p.rstack32;
+  bool& have = prec == 0 ? p.have64 : p.have32;
+  if (!have) {
+    rs.ensure(sizeof(T) * std::max<long long>(p.nrs, 1));
+    if (p.npairs > 0) {
+      if (p.RCx > p.RC && !Rt) throw std::runtime_error("block-sparse product: missing block environment");
+      hipLaunchKernelGGL((rstack_kernel<T>), dim3(p.npairs), dim3(256), 0, s, p.pairs.as<BsPair>(), p.boff.as<int>(),
+                         p.nbeta.as<int>(), p.rbase.as<long long>(), p.RC, p.RCx, p.rrp, R, Rt, rs.as<T>(), p.nrs,
+                         err);
+      BSCHECK(hipGetLastError());
+    }
+    have = true;
+  }
+  fill(y, sizeof(T) * ny, s);
+  E.kt_mark(0);
+  if (p.ntiles1 > 0) {
+    hipLaunchKernelGGL((stage1_kernel<T>), dim3(p.ntiles1), dim3(256), 0, s, p.tiles1.as<int4>(),
+                       p.alpha.as<BsAlpha>(), p.rsrc.as<long long>(), p.rinfo.as<int4>(), p.cinfo.as<int4>(),
+                       p.rowpart1.as<long long>(), p.specoff.as<long long>(), p.nbeta.as<int>(), p.nbe, L,
+                       (long long)p.RAx * p.rlp * p.rlp, x, (long long)ny, (long long)16 * p.rrp, E.bs_t1.as<T>(),
+                       p.n1, err);
+    BSCHECK(hipGetLastError());
+  }
+  E.kt_mark(1);
+  if (p.m1.ntiles > 0) {
+    hipLaunchKernelGGL((mix_kernel<T, 1>), dim3(p.m1.ntiles), dim3(MIX_COLS), 0, s, p.m1.tiles.as<int4>(),
+                       p.m1.groups.as<BsGroup>(), p.m1.optr.as<int>(), p.m1.ocol.as<int>(), mix_vals<T>(p.m1).template as<T>(),
+                       p.m1.orow.as<int2>(), p.m1.spec.as<int4>(), E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2,
+                       err, p.nbe,
+                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
+                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(), 0);
+    BSCHECK(hipGetLastError());
+  }
+  E.kt_mark(2);
+  if (p.m2.ntiles > 0) {
+    hipLaunchKernelGGL((mix_kernel<T, 2>), dim3(p.m2.ntiles), dim3(MIX_COLS), 0, s, p.m2.tiles.as<int4>(),
+                       p.m2.groups.as<BsGroup>(), p.m2.optr.as<int>(), p.m2.ocol.as<int>(), mix_vals<T>(p.m2).template as<T>(),
+                       p.m2.orow.as<int2>(), p.m2.spec.as<int4>(), E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3,
+                       err, p.nbe,
+                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
+                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
+                       bf16_t3 ? 1 : 0);
+    BSCHECK(hipGetLastError());
+  }
+  E.kt_mark(3);
+  if (p.ntiles4 > 0) {
+    hipLaunchKernelGGL((stage4_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
+                       E.bs_t3.as<T>(), p.n3, rs.as<T>(), p.nrs, E.bs_part.as<T>(), err);
+    BSCHECK(hipGetLastError());
+    hipLaunchKernelGGL((reduce4_kernel<T>), dim3(p.nred), dim3(256), 0, s, p.red.as<BsRedTile>(),
+                       E.bs_part.as<T>(), p.rowdst.as<long long>(), y, (long long)ny, err);
+    BSCHECK(hipGetLastError());
+  }
+  E.kt_mark(4);
+  int herr = 0;
+  BSCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  BSCHECK(hipStreamSynchronize(s));
+  if (herr != 0)
+    throw std::runtime_error("block-sparse product: index outside its buffer (check " + std::to_string(herr) + ")");
+  const double el = (double)sizeof(T);
+  const double fl[4] = {p.flops1, p.m1.flops, p.m2.flops, p.flops4};
+  const double by[4] = {el * p.bytes1, el * (p.m1.nin + p.m1.nout), el * (p.m2.nin + p.m2.nout), el * p.bytes4};
+  E.kt_add(fl, by);
+}
+
+template void bs_apply<double>(Engine&, BsPlan&, const double*, const double*, const double*, const double*, double*,
+                               bool);
+template void bs_apply<float>(Engine&, BsPlan&, const float*, const float*, const float*, const float*, float*, bool);
+
+}  // namespace tt

@@ -189,6 +189,14 @@ int tt_dmrg2(void* ctx, int nsweeps, double* energies) {
   });
 }
 
+int tt_window_apply_dev(void* ctx, int b, int rl, int rr, const int32_t* ql, const int32_t* qr, const double* Lenv,
+                        const double* Renv, int prec, const double* x, double* y) {
+  return guard(ctx, [&](Engine& E) {
+    E.window_apply(b, rl, rr, ql, qr, Lenv, Renv, prec, x, y);
+    return TT_OK;
+  });
+}
+
 int tt_heff_apply_dev(void* ctx, int prec, int rl, int rr, int RA, int RB, int RC, const void* Lenv, const void* Renv,
                       int nnz1, const int32_t* A1, const int32_t* B1, const double* ops1, int nnz2, const int32_t* A2,
                       const int32_t* B2, const double* ops2, const void* x, void* y) {

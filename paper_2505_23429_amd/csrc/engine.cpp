@@ -4,6 +4,7 @@
 // matrices of the local solver, singular values for truncation, the coarse
 // (P+1)x(P+1) pencil).
 #include "engine.h"
+#include "bsheff.h"
 
 #include <rocsolver/rocsolver.h>
 
@@ -54,9 +55,10 @@ static std::vector<Q2> padded_q(const Labels& q, int n, int sent) {
 // memory helpers
 // ---------------------------------------------------------------------------
 void DevMem::release() {
-  if (p) (void)hipFree(p);
+  if (p && own) (void)hipFree(p);
   p = nullptr;
   n = 0;
+  own = true;
 }
 void DevMem::ensure(size_t bytes) {
   if (bytes <= n) return;
@@ -212,6 +214,9 @@ void Engine::build_siteop(SiteOp& so, int nout, const std::vector<int>& out_idx,
   }
   so.nout = nout;
   so.nnz = nnz;
+  so.hptr = ptr;
+  so.hsrc.assign(src.begin(), src.begin() + nnz);
+  so.hop.assign(op64.begin(), op64.begin() + (size_t)nnz * 16);
   upload(so.ptr, ptr.data(), ptr.size() * sizeof(int), s);
   upload(so.src, src.data(), src.size() * sizeof(int), s);
   upload(so.op64, op64.data(), op64.size() * sizeof(double), s);
@@ -291,6 +296,14 @@ void Engine::set_mpo(int L_, const int* R, const int* nnz, const int32_t* const*
         xO.insert(xO.end(), Id, Id + 16);
       }
       build_siteop(s.byA_right, s.Rl, xA, xB, xO, stream);
+      // second site of a window: block row p feeds the virtual output Rr + (p - p0)
+      std::vector<int> yA = nA, yB = nB;
+      std::vector<double> yO = nO;
+      for (int pp = p0; pp < p1; ++pp) {
+        yA.push_back(pp); yB.push_back(s.Rr + (pp - p0));
+        yO.insert(yO.end(), Id, Id + 16);
+      }
+      build_siteop(s.byB_rightv, s.Rr + nP, yB, yA, yO, stream);
     }
     build_siteop(s.byB, s.Rr, s.B, s.A, s.ops, stream);
     build_siteop(s.byA, s.Rl, s.A, s.B, s.ops, stream);
@@ -320,6 +333,19 @@ void Engine::kt_mark(int i) {
   if (!kt_ev[i]) HC(hipEventCreate(&kt_ev[i]));
   HC(hipEventRecord(kt_ev[i], stream));
 }
+void Engine::kt_add(const double fl[4], const double by[4]) {
+  if (!kt_on) return;
+  HC(hipEventSynchronize(kt_ev[4]));
+  float ms[4];
+  for (int i = 0; i < 4; ++i) HC(hipEventElapsedTime(&ms[i], kt_ev[i], kt_ev[i + 1]));
+  for (int i = 0; i < 4; ++i) {
+    kstat[i][0] += ms[i];
+    kstat[i][1] += 1.0;
+    kstat[i][2] += fl[i];
+    kstat[i][3] += by[i];
+  }
+}
+
 void Engine::kt_finish(int elem, int RB) {
   if (!kt_on) return;
   HC(hipEventSynchronize(kt_ev[4]));
@@ -1059,7 +1085,9 @@ struct Window {
   DevMem diag;            // FP64 diagonal of the window operator [rlp][4][4][rrp]
   double flops = 0.0;
   bool use_tabs = false;
-  WinTabs tabs;           // structural-zero tables of the quantum-number blocks
+  WinTabs tabs;           // structural-zero tables of the quantum-number blocks (dense product)
+  bool use_bs = false;
+  BsPlan bs;              // block-sparse product plan
 };
 
 // diag[a][s1][s2][b] = sum_B (sum_A W1[A,s1,s1,B] L_A[a][a]) (sum_C W2[B,s2,s2,C] R_C[b][b])
@@ -1291,7 +1319,19 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
     w.w2 = &s2.byB;
   }
   w.prec = prec;
-  if (prec == TT_F32) {
+  w.use_bs = E.opts.qn_skip != 0 && bs_build(E, w.bs, b, ql, qr, w.rlp, w.rrp, w.RAx, w.nP);
+  w.use_tabs = E.opts.qn_skip != 0 && !w.use_bs;
+  if (prec == TT_BF16 && w.use_bs) {
+    // block-sparse product in FP32 arithmetic on operands rounded to bfloat16
+    w.L32.ensure(sizeof(float) * sl * w.RAx);
+    convert_f64_bf16f32(w.Lx.as<double>(), w.L32.as<float>(), sl * w.RAx, E.stream);
+    w.R32.ensure(sizeof(float) * sr * w.RC);
+    convert_f64_bf16f32(w.R64, w.R32.as<float>(), sr * w.RC, E.stream);
+    if (w.nP) {
+      w.Rt32.ensure(sizeof(float) * sr * w.nP);
+      convert_f64_bf16f32(w.Rt.as<double>(), w.Rt32.as<float>(), sr * w.nP, E.stream);
+    }
+  } else if (prec == TT_F32) {
     w.L32.ensure(sizeof(float) * sl * w.RAx);
     convert_f64_f32(w.Lx.as<double>(), w.L32.as<float>(), sl * w.RAx, E.stream);
     w.R32.ensure(sizeof(float) * sr * w.RC);
@@ -1312,7 +1352,6 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
   }
   // dense-bond algorithmic flops of one product (true sizes, no virtual channels)
   w.flops = 2.0 * 16.0 * w.rl * w.rr * ((double)w.RA * w.rl + (double)w.RC * w.rr);
-  w.use_tabs = E.opts.qn_skip != 0;
   if (w.use_tabs) build_window_tabs(E, w.tabs, b, ql, qr, w.rlp, w.rrp, w.RAx, w.P0, w.nP);
   window_diag(E, w, Le, b, Re);
 }
@@ -1322,7 +1361,19 @@ static void window_matvec(Engine& E, Window& w, const double* x, double* y, int 
   E.cur_rl = w.rl; E.cur_rr = w.rr; E.cur_RA = w.RA; E.cur_RC = w.RC;
   const WinTabs* tabs = w.use_tabs ? &w.tabs : nullptr;
   HC(hipEventRecord(E.ev0, E.stream));
-  if (prec == TT_F64) {
+  if (w.use_bs) {
+    if (prec == TT_F64) {
+      bs_apply<double>(E, w.bs, w.Lx.as<double>(), w.R64, w.nP ? w.Rt.as<double>() : nullptr, x, y, false);
+    } else {
+      E.wlow_x.ensure(sizeof(float) * n);
+      E.wlow_y.ensure(sizeof(float) * n);
+      if (prec == TT_BF16) convert_f64_bf16f32(x, E.wlow_x.as<float>(), n, E.stream);
+      else convert_f64_f32(x, E.wlow_x.as<float>(), n, E.stream);
+      bs_apply<float>(E, w.bs, w.L32.as<float>(), w.R32.as<float>(), w.nP ? w.Rt32.as<float>() : nullptr,
+                      E.wlow_x.as<float>(), E.wlow_y.as<float>(), prec == TT_BF16);
+      convert_f32_f64(E.wlow_y.as<float>(), y, n, E.stream);
+    }
+  } else if (prec == TT_F64) {
     E.heff<double>(w.rlp, w.rrp, w.RAx, w.Lx.as<double>(), *w.w1, w.RB, *w.w2, w.RC, w.R64, x, y,
                    w.nP ? w.Rt.as<double>() : nullptr, w.P0, w.nP, tabs);
   } else if (prec == TT_F32) {
@@ -2242,6 +2293,29 @@ void Engine::mpo_grad(double* En, double* const* gops) {
     Lk = std::move(o);
   }
   d2h(En, Lk.d.p, sizeof(double), stream);
+}
+
+// ---------------------------------------------------------------------------
+// window operator with caller environments (the product used inside the local solves)
+// ---------------------------------------------------------------------------
+void Engine::window_apply(int b, int rl, int rr, const int32_t* ql, const int32_t* qr, const double* Lenv,
+                          const double* Renv, int prec, const double* x, double* y) {
+  if (!have_mpo) throw std::logic_error("window_apply needs the MPO");
+  if (b < 0 || b + 1 >= L) throw std::invalid_argument("window site out of range");
+  if (rl <= 0 || rr <= 0 || !ql || !qr || !Lenv || !Renv || !x || !y) throw std::invalid_argument("bad window operand");
+  if (prec != TT_F64 && prec != TT_F32 && prec != TT_BF16) throw std::invalid_argument("bad precision");
+  Labels lq(rl), rq(rr);
+  for (int i = 0; i < rl; ++i) lq[i] = {ql[2 * i], ql[2 * i + 1]};
+  for (int i = 0; i < rr; ++i) rq[i] = {qr[2 * i], qr[2 * i + 1]};
+  Env Le, Re;
+  Le.R = mpo[b].Rl; Le.rb = Le.rk = rl;
+  Re.R = mpo[b + 1].Rr; Re.rb = Re.rk = rr;
+  Le.d.borrow(const_cast<double*>(Lenv), sizeof(double) * Le.elems());
+  Re.d.borrow(const_cast<double*>(Renv), sizeof(double) * Re.elems());
+  Window w;
+  prepare_window(*this, w, Le, b, Re, prec, lq, rq);
+  window_matvec(*this, w, x, y, prec);
+  HC(hipStreamSynchronize(stream));
 }
 
 }  // namespace tt

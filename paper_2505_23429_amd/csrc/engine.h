@@ -27,14 +27,16 @@ using Labels = std::vector<Q2>;
 struct DevMem {
   void* p = nullptr;
   size_t n = 0;
+  bool own = true;  // false: a caller's buffer, never freed here
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n), own(o.own) { o.p = nullptr; o.n = 0; o.own = true; }
   DevMem& operator=(DevMem&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; own = o.own; o.p = nullptr; o.n = 0; o.own = true; }
     return *this;
   }
+  void borrow(void* q, size_t bytes) { release(); p = q; n = bytes; own = false; }
   ~DevMem() { release(); }
   void release();
   void ensure(size_t bytes);       // grow-only, contents not preserved
@@ -56,6 +58,8 @@ struct Core {
 struct SiteOp {
   int nout = 0, nnz = 0;
   DevMem ptr, src, op64, op32;
+  std::vector<int> hptr, hsrc;   // host copy of the CSR (grouped by output channel)
+  std::vector<double> hop;       // [nnz][4][4]
 };
 
 struct SiteMPO {
@@ -69,6 +73,7 @@ struct SiteMPO {
   SiteOp byB_left;                // block -> virtual pass entries (inputs Rl + q - q0)
   SiteOp byB_noblk;               // block entries removed
   SiteOp byA_right;               // block -> virtual pass entries (inputs Rr + p - p0)
+  SiteOp byB_rightv;              // block entries replaced by outputs Rr + (p - p0) (second site of a window)
 };
 
 // Structural-zero tables of one two-site window (device arrays).
@@ -141,6 +146,7 @@ class Engine {
   int cur_rl = 0, cur_rr = 0, cur_RA = 0, cur_RC = 0;
   void kt_mark(int i);
   void kt_finish(int elem, int RB);
+  void kt_add(const double fl[4], const double by[4]);  // explicit per-stage work of one product
 
   // setup
   void set_mpo(int L, const int* R, const int* nnz, const int32_t* const* A, const int32_t* const* B,
@@ -171,6 +177,9 @@ class Engine {
                      const double* x, double* E, double* gx, double* gL, double* gR, std::vector<double>& gop1,
                      std::vector<double>& gop2);
   void mpo_grad(double* E, double* const* gops);
+  // window operator of the MPO at sites (b, b+1) applied with caller environments
+  void window_apply(int b, int rl, int rr, const int32_t* ql, const int32_t* qr, const double* Lenv,
+                    const double* Renv, int prec, const double* x, double* y);
 
   // environment updates through a site of the MPO (handles coefficient blocks)
   void env_left(const Env& in, const Core& bra, const Core& ket, int site, Env& out);
@@ -187,6 +196,10 @@ class Engine {
   DevMem dav_V, dav_AV, dav_t, dav_u, dav_Au, dav_c, dav_mask, dav_t2, dav_t3;
   DevMem wlow_x, wlow_y, wlow_L, wlow_R, wlow_Rt;
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
+  // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)
+  DevMem bs_t1, bs_t2, bs_t3, bs_part;
+  long long bs_serial = 0, bs_zero_serial = -1;
+  int bs_zero_prec = -1;
 
  private:
   void free_caches();

@@ -75,6 +75,8 @@ void lincomb(const double* V, size_t ldv, int m, const double* c_dev, double* ou
 void convert_f64_f32(const double* a, float* b, size_t n, hipStream_t s);
 void convert_f32_f64(const float* a, double* b, size_t n, hipStream_t s);
 void convert_f64_bf16(const double* a, uint16_t* b, size_t n, hipStream_t s);
+// FP32 copy holding the bfloat16 rounding (round to nearest even) of each value
+void convert_f64_bf16f32(const double* a, float* b, size_t n, hipStream_t s);
 void convert_f64_f32_op(const double* a, float* b, size_t n, hipStream_t s);
 // gather / scatter of a 2-D block: dst[i*ldd + j] = src[rows[i]*lds + cols[j]] (column-major dst if colmajor)
 void gather2d(const double* src, long long lds, const int* rows, int nr, const int* cols, int nc, double* dst,

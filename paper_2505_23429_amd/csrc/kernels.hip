@@ -646,6 +646,15 @@ void convert_f64_bf16(const double* a, uint16_t* b, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(cvt_d2bf, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
   HIPCHECK(hipGetLastError());
 }
+__global__ void cvt_d2bff(const double* a, float* b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = __uint_as_float((uint32_t)f32_to_bf16_rne((float)a[i]) << 16);
+}
+void convert_f64_bf16f32(const double* a, float* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(cvt_d2bff, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
+  HIPCHECK(hipGetLastError());
+}
 
 __global__ void gather2d_kernel(const double* src, long long lds, const int* rows, int nr, const int* cols, int nc,
                                 double* dst, bool colmajor) {
