@@ -176,6 +176,8 @@ def main():
         "matvecs_per_sweep": int(sum(int(np.sum(r["matvecs"])) for r in reps) / args.steps),
         "E_after": reps[-1]["E_after"], "lambda": reps[-1]["lambda"], "E_before": reps[-1]["E_before"],
         "roofline": roof, "kernels": breakdown,
+        "phases_s": {k: round(sum(r["phase_seconds"][i] for r in reps) / args.steps, 3) for i, k in enumerate(
+            ("lq", "env_step1", "window_setup", "davidson", "split", "env_sweep", "coarse", "compress"))},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mpo, w, fl / args.steps, args.cpu_seconds)

@@ -88,6 +88,9 @@ typedef struct tt_sweep_report {
   double seconds[4];               /* wall time of Steps 1..4 */
   double flops_heff;               /* dense-bond flops of all effective-Hamiltonian products */
   double seconds_heff;             /* device time of those products (HIP events) */
+  double phase_seconds[8];         /* wall time: LQ sweep, step-1 environments, window set-up,
+                                      Davidson, two-site splits, subdomain environment updates,
+                                      coarse matrices, coarse solve + compression */
 } tt_sweep_report;
 
 void tt_default_opts(tt_opts* o);

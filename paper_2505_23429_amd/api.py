@@ -159,6 +159,7 @@ class Context:
             "matvecs": np.array(rep.matvecs[:n]), "S": S, "A": A, "c": np.array(rep.coef[:m]),
             "lambda": rep.lambda_, "rankS": rep.rankS, "E_after": rep.E_after, "discarded": rep.discarded,
             "seconds": list(rep.seconds), "flops_heff": rep.flops_heff, "seconds_heff": rep.seconds_heff,
+            "phase_seconds": list(rep.phase_seconds),
         }
 
     def dmrg2(self, nsweeps):

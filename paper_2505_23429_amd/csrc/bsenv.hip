@@ -1,0 +1,585 @@
+// Quantum-number block-sparse environment update through one site (FP64).
+// Layout and index conventions are described in bsheff.h.
+//
+// Bond roles: P = bra at the input bond, Q = ket at the input bond,
+// R = ket at the output bond, T = bra at the output bond.  With sigma = +1
+// (left update) the cores are read as ket[q][s][r], bra[p][s'][t]; with
+// sigma = -1 (right update) as ket[r][s][q], bra[t][s'][p].
+//   stage 1  T1[(K, s)][spec(pi, rho)] = sum_q E_K[p][q] ket(q, s, r)   grouped GEMM per (class, kappa)
+//   mix      panel_tau[(pi, s', i_p)][(K', i_r)] = sum W T1                sparse x dense per group
+//   stage 3  out[K'][t][r] = sum_k bra(p, s', t) panel_tau                 grouped GEMM per (tau, class)
+#include "bsheff.h"
+
+#include <algorithm>
+#include <map>
+#include <stdexcept>
+
+namespace tt {
+
+#define BECHECK(x)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+const Q2 kQ[4] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};  // (N, 2Sz) of |0>, |up>, |dn>, |up dn>
+inline Q2 add(Q2 a, Q2 b) { return {a[0] + b[0], a[1] + b[1]}; }
+inline Q2 sub(Q2 a, Q2 b) { return {a[0] - b[0], a[1] - b[1]}; }
+inline Q2 mul(int s, Q2 a) { return {s * a[0], s * a[1]}; }
+
+constexpr int TL = 64;   // GEMM output tile edge
+constexpr int KS = 32;   // K slice in LDS
+constexpr int MC = 256;  // mix: spectator columns per workgroup
+constexpr int MR = 64;   // mix: output rows per workgroup
+
+struct Sec {
+  std::vector<Q2> q;
+  std::vector<int> off, n;
+  std::map<Q2, int> id;
+  int find(Q2 c) const {
+    auto it = id.find(c);
+    return it == id.end() ? -1 : it->second;
+  }
+};
+
+bool sectors(const Labels& lab, Sec& s) {
+  for (int i = 0; i < (int)lab.size(); ++i) {
+    if (i == 0 || lab[i] != lab[i - 1]) {
+      if (s.id.count(lab[i])) return false;
+      s.id[lab[i]] = (int)s.q.size();
+      s.q.push_back(lab[i]);
+      s.off.push_back(i);
+      s.n.push_back(0);
+    }
+    s.n.back()++;
+  }
+  return true;
+}
+
+template <class V>
+void up(DevMem& d, const std::vector<V>& v, hipStream_t s) {
+  if (v.empty()) {
+    const V z{};
+    upload(d, &z, sizeof(V), s);
+  } else {
+    upload(d, v.data(), v.size() * sizeof(V), s);
+  }
+}
+
+struct EnvS1 { int M, N, K, cls0, np, op, oq, col0, pi, pad; };
+struct EnvGrp { long long in_base; int ncols, spec0, nspec, pad; };
+struct EnvS3 { long long upoff, pbase; int M, N, K, ld, pcol, cls0, nrho, orho, otau, pad; };
+struct EnvUP { long long upoff; int tau, pi, s, koff, K, pad; };
+
+// stage 1: rows (K in the input class, i_p), columns (s, rho, i_r), sum over the ket sector kappa
+__global__ __launch_bounds__(256) void env_s1_kernel(
+    const int4* __restrict__ tiles, const EnvS1* __restrict__ desc, const int* __restrict__ clist_in,
+    const int4* __restrict__ cinfo, const int* __restrict__ gidx, const int* __restrict__ rin,
+    const long long* __restrict__ goff, const int* __restrict__ gcols, const long long* __restrict__ specoff,
+    const int* __restrict__ nR, int nRsec, const double* __restrict__ Ein, long long PQ, int Qp, long long nE,
+    const double* __restrict__ ket, long long nket, long long bks, double* __restrict__ T1, long long n1,
+    int* __restrict__ err) {
+  const int4 t = tiles[blockIdx.x];
+  const EnvS1 d = desc[t.x];
+  const int m0 = t.y, c0 = t.z;
+  __shared__ double As[KS][TL + 1];
+  __shared__ double Bs[KS][TL + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < d.K; k0 += KS) {
+    for (int e = tid; e < TL * KS; e += 256) {
+      const int r = e / KS, kk = e % KS;
+      double v = 0.0;
+      if (m0 + r < d.M && k0 + kk < d.K) {
+        const int m = m0 + r;
+        const int K = clist_in[d.cls0 + m / d.np];
+        const long long q = (long long)K * PQ + (long long)(d.op + m % d.np) * Qp + d.oq + k0 + kk;
+        if (q >= 0 && q < nE) v = Ein[q]; else err[0] = 11;
+      }
+      As[kk][r] = v;
+    }
+    for (int e = tid; e < TL * KS; e += 256) {
+      const int kk = e / TL, c = e % TL;
+      double v = 0.0;
+      if (c0 + c < d.N && k0 + kk < d.K) {
+        const long long q = (long long)(d.oq + k0 + kk) * bks + cinfo[d.col0 + c0 + c].x;
+        if (q >= 0 && q < nket) v = ket[q]; else err[0] = 12;
+      }
+      Bs[kk][c] = v;
+    }
+    __syncthreads();
+    const int kn = min(KS, d.K - k0);
+    for (int kk = 0; kk < kn; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty * 4 + i;
+    if (m >= d.M) continue;
+    const int K = clist_in[d.cls0 + m / d.np], ip = m % d.np;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tx + 16 * j;
+      if (c >= d.N) continue;
+      const int4 ci = cinfo[d.col0 + c];  // {ket column, s, rho, i_r}
+      const int g = gidx[K * 4 + ci.y];
+      const long long so = specoff[(long long)d.pi * nRsec + ci.z];
+      if (g < 0 || so < 0) { err[0] = 13; continue; }
+      const long long dst = goff[g] + (long long)rin[K * 4 + ci.y] * gcols[g] + so + (long long)ip * nR[ci.z] + ci.w;
+      if (dst < 0 || dst >= n1) { err[0] = 14; continue; }
+      T1[dst] = acc[i][j];
+    }
+  }
+}
+
+// mix: output row (K', s') of a group, one spectator column per thread, written into the panel of tau
+__global__ __launch_bounds__(MC) void env_mix_kernel(
+    const int4* __restrict__ tiles, const EnvGrp* __restrict__ grp, const int* __restrict__ optr,
+    const int* __restrict__ ocol, const double* __restrict__ oval, const int2* __restrict__ orow,
+    const int4* __restrict__ spec, const double* __restrict__ T1, long long n1, double* __restrict__ panel,
+    long long npan, const int* __restrict__ t3tau, const long long* __restrict__ t3base, const int* __restrict__ Ntau,
+    const int* __restrict__ pcol, int ncout, const int* __restrict__ cls_out, const int* __restrict__ pos_out,
+    const int* __restrict__ nR, int* __restrict__ err) {
+  const int4 t = tiles[blockIdx.x];
+  const EnvGrp G = grp[t.x];
+  const int col = t.y + (int)threadIdx.x;
+  if (col >= G.ncols) return;
+  int lo = 0, hi = G.nspec - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (spec[G.spec0 + mid].x <= col) lo = mid; else hi = mid - 1;
+  }
+  const int4 sp = spec[G.spec0 + lo];  // {start, pi, rho, -}
+  const int within = col - sp.x;
+  const int nr = nR[sp.z];
+  const int ip = within / nr, ir = within - ip * nr;
+  const long long lim = n1 - G.in_base - col;
+  const double* src = T1 + G.in_base + col;
+  for (int r = t.z; r < t.w; ++r) {
+    double acc = 0.0;
+    const int e1 = optr[r + 1];
+    for (int e = optr[r]; e < e1; ++e) {
+      const long long q = (long long)ocol[e] * G.ncols;
+      if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 15;
+    }
+    const int2 ro = orow[r];  // {K', s'}
+    const int ts = sp.y * 4 + ro.y;
+    const int tau = t3tau[ts];
+    if (tau < 0) continue;
+    const long long dst = t3base[ts] + (long long)ip * Ntau[tau] + pcol[tau * ncout + cls_out[ro.x]] +
+                          (long long)pos_out[ro.x] * nr + ir;
+    if (dst < 0 || dst >= npan) { err[0] = 16; continue; }
+    panel[dst] = acc;
+  }
+}
+
+// bra panel of tau: UP[m][koff + i_p] = bra(p = o_pi + i_p, s', t = o_tau + m)
+__global__ __launch_bounds__(256) void env_up_kernel(const EnvUP* __restrict__ ups, const double* __restrict__ bra,
+                                                     long long nbra, long long ps, long long ss, long long ts,
+                                                     const int* __restrict__ oP, const int* __restrict__ nP,
+                                                     const int* __restrict__ oT, const int* __restrict__ nT,
+                                                     double* __restrict__ UP, long long nup, int* __restrict__ err) {
+  const EnvUP u = ups[blockIdx.x];
+  const int np = nP[u.pi], nt = nT[u.tau];
+  for (int e = threadIdx.x; e < np * nt; e += 256) {
+    const int m = e / np, ip = e - m * np;
+    const long long q = (long long)(oP[u.pi] + ip) * ps + (long long)u.s * ss + (long long)(oT[u.tau] + m) * ts;
+    const long long dst = u.upoff + (long long)m * u.K + u.koff + ip;
+    if (q < 0 || q >= nbra || dst < 0 || dst >= nup) { err[0] = 17; continue; }
+    UP[dst] = bra[q];
+  }
+}
+
+// stage 3: out[K'][o_tau + m][o_rho + i_r] = sum_k UP[m][k] panel[k][pcol + (K' position, i_r)]
+__global__ __launch_bounds__(256) void env_s3_kernel(const int4* __restrict__ tiles, const EnvS3* __restrict__ desc,
+                                                     const double* __restrict__ UP, long long nup,
+                                                     const double* __restrict__ panel, long long npan,
+                                                     const int* __restrict__ clist_out, double* __restrict__ out,
+                                                     long long nout, long long TR, int Rp, int* __restrict__ err) {
+  const int4 t = tiles[blockIdx.x];
+  const EnvS3 d = desc[t.x];
+  const int m0 = t.y, n0 = t.z;
+  __shared__ double As[KS][TL + 1];
+  __shared__ double Bs[KS][TL + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < d.K; k0 += KS) {
+    for (int e = tid; e < TL * KS; e += 256) {
+      const int r = e / KS, kk = e % KS;
+      double v = 0.0;
+      if (m0 + r < d.M && k0 + kk < d.K) {
+        const long long q = d.upoff + (long long)(m0 + r) * d.K + k0 + kk;
+        if (q >= 0 && q < nup) v = UP[q]; else err[0] = 18;
+      }
+      As[kk][r] = v;
+    }
+    for (int e = tid; e < TL * KS; e += 256) {
+      const int kk = e / TL, c = e % TL;
+      double v = 0.0;
+      if (n0 + c < d.N && k0 + kk < d.K) {
+        const long long q = d.pbase + (long long)(k0 + kk) * d.ld + d.pcol + n0 + c;
+        if (q >= 0 && q < npan) v = panel[q]; else err[0] = 19;
+      }
+      Bs[kk][c] = v;
+    }
+    __syncthreads();
+    const int kn = min(KS, d.K - k0);
+    for (int kk = 0; kk < kn; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty * 4 + i;
+    if (m >= d.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx + 16 * j;
+      if (n >= d.N) continue;
+      const int K = clist_out[d.cls0 + n / d.nrho], ir = n % d.nrho;
+      const long long dst = (long long)K * TR + (long long)(d.otau + m) * Rp + d.orho + ir;
+      if (dst < 0 || dst >= nout) { err[0] = 20; continue; }
+      out[dst] = acc[i][j];
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// site tables
+// ---------------------------------------------------------------------------
+void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2>& din,
+                 const std::vector<Q2>& dout, int sigma) {
+  u = BsSiteUse();
+  u.sigma = sigma;
+  u.nin = (int)din.size();
+  u.nout = (int)dout.size();
+  if (op.nout != u.nout) throw std::runtime_error("block-sparse site tables: channel count mismatch");
+  auto classes = [](const std::vector<Q2>& d, std::vector<Q2>& cq, std::vector<int>& cls, std::vector<int>& cstart,
+                    std::vector<int>& clist, std::vector<int>& pos) {
+    std::map<Q2, int> m;
+    for (const Q2& q : d) m.emplace(q, 0);
+    int c = 0;
+    for (auto& kv : m) { kv.second = c++; cq.push_back(kv.first); }
+    cls.resize(d.size());
+    std::vector<int> cnt(c, 0);
+    for (size_t k = 0; k < d.size(); ++k) { cls[k] = m[d[k]]; cnt[cls[k]]++; }
+    cstart.assign(c + 1, 0);
+    for (int i = 0; i < c; ++i) cstart[i + 1] = cstart[i] + cnt[i];
+    clist.resize(d.size());
+    pos.resize(d.size());
+    std::vector<int> fill = cstart;
+    for (size_t k = 0; k < d.size(); ++k) {
+      pos[k] = fill[cls[k]] - cstart[cls[k]];
+      clist[fill[cls[k]]++] = (int)k;
+    }
+    return c;
+  };
+  std::vector<int> clist_in, clist_out, pos_in, pos_out;
+  u.ncin = classes(din, u.cq_in, u.cls_in, u.cstart_in, clist_in, pos_in);
+  u.ncout = classes(dout, u.cq_out, u.cls_out, u.cstart_out, clist_out, pos_out);
+  auto group = [&](Q2 G) {
+    auto it = u.gid.find(G);
+    if (it != u.gid.end()) return it->second;
+    const int g = (int)u.gq.size();
+    u.gid[G] = g;
+    u.gq.push_back(G);
+    return g;
+  };
+  std::vector<int> rin(u.nin * 4), nrows;
+  u.gidx_in.assign(u.nin * 4, -1);
+  for (int K = 0; K < u.nin; ++K)
+    for (int s = 0; s < 4; ++s) {
+      const int g = group(sub(mul(sigma, kQ[s]), din[K]));
+      if ((int)nrows.size() <= g) nrows.resize(g + 1, 0);
+      u.gidx_in[K * 4 + s] = g;
+      rin[K * 4 + s] = nrows[g]++;
+    }
+  std::vector<std::vector<int2>> rows_by_g;
+  for (int K = 0; K < u.nout; ++K)
+    for (int s = 0; s < 4; ++s) {
+      const int g = group(sub(mul(sigma, kQ[s]), dout[K]));
+      if ((int)rows_by_g.size() <= g) rows_by_g.resize(g + 1);
+      rows_by_g[g].push_back(make_int2(K, s));
+    }
+  u.ngrp = (int)u.gq.size();
+  rows_by_g.resize(u.ngrp);
+  nrows.resize(u.ngrp, 0);
+  std::vector<int> optr(1, 0), ocol;
+  std::vector<double> oval;
+  std::vector<int2> orow;
+  u.orow0.assign(u.ngrp + 1, 0);
+  for (int g = 0; g < u.ngrp; ++g) {
+    u.orow0[g] = (int)orow.size();
+    for (const int2& ro : rows_by_g[g]) {
+      for (int e = op.hptr[ro.x]; e < op.hptr[ro.x + 1]; ++e) {
+        const int Kin = op.hsrc[e];
+        if (Kin < 0 || Kin >= u.nin) throw std::runtime_error("block-sparse site tables: input channel out of range");
+        for (int s = 0; s < 4; ++s) {
+          const double v = op.hop[(size_t)e * 16 + ro.y * 4 + s];
+          if (v == 0.0) continue;
+          if (u.gidx_in[Kin * 4 + s] != g)
+            throw std::runtime_error("block-sparse site tables: operator entry breaks the charge grouping");
+          ocol.push_back(rin[Kin * 4 + s]);
+          oval.push_back(v);
+        }
+      }
+      optr.push_back((int)ocol.size());
+      orow.push_back(ro);
+    }
+  }
+  u.orow0[u.ngrp] = (int)orow.size();
+  u.nnz = (double)ocol.size();
+  u.nrows_in = nrows;
+  hipStream_t st = E.stream;
+  up(u.clist_in, clist_in, st);
+  up(u.clist_out, clist_out, st);
+  up(u.pos_out, pos_out, st);
+  up(u.d_cls_out, u.cls_out, st);
+  up(u.d_gidx_in, u.gidx_in, st);
+  up(u.rin, rin, st);
+  up(u.optr, optr, st);
+  up(u.ocol, ocol, st);
+  up(u.oval, oval, st);
+  up(u.orow, orow, st);
+}
+
+// ---------------------------------------------------------------------------
+// one update
+// ---------------------------------------------------------------------------
+bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, const Core& ket, double* out) {
+  const bool left = u.sigma > 0;
+  const int sg = u.sigma;
+  const Labels& lP = left ? bra.ql : bra.qr;
+  const Labels& lQ = left ? ket.ql : ket.qr;
+  const Labels& lR = left ? ket.qr : ket.ql;
+  const Labels& lT = left ? bra.qr : bra.ql;
+  if ((int)bra.ql.size() != bra.rl || (int)bra.qr.size() != bra.rr || (int)ket.ql.size() != ket.rl ||
+      (int)ket.qr.size() != ket.rr)
+    return false;
+  Sec SP, SQ, SR, ST;
+  if (!sectors(lP, SP) || !sectors(lQ, SQ) || !sectors(lR, SR) || !sectors(lT, ST)) return false;
+  const int Pp = left ? bra.rlp() : bra.rrp(), Qp = left ? ket.rlp() : ket.rrp();
+  const int Rp = left ? ket.rrp() : ket.rlp(), Tp = left ? bra.rrp() : bra.rlp();
+  const int nPs = (int)SP.q.size(), nQs = (int)SQ.q.size(), nRs = (int)SR.q.size(), nTs = (int)ST.q.size();
+  const int ng = u.ngrp;
+
+  // spectators (pi, rho) grouped by Gamma = Q_rho - Q_pi
+  std::vector<int> gcols(ng, 0);
+  std::vector<std::vector<int4>> spec_g(ng);
+  std::vector<long long> specoff((size_t)std::max(nPs * nRs, 1), -1);
+  for (int pi = 0; pi < nPs; ++pi)
+    for (int rho = 0; rho < nRs; ++rho) {
+      auto it = u.gid.find(sub(SR.q[rho], SP.q[pi]));
+      if (it == u.gid.end()) continue;
+      const int g = it->second;
+      specoff[(size_t)pi * nRs + rho] = gcols[g];
+      spec_g[g].push_back(make_int4(gcols[g], pi, rho, 0));
+      gcols[g] += SP.n[pi] * SR.n[rho];
+    }
+  std::vector<long long> goff(ng, 0);
+  long long n1 = 0;
+  std::vector<int4> spec;
+  std::vector<EnvGrp> grp(ng);
+  for (int g = 0; g < ng; ++g) {
+    goff[g] = n1;
+    n1 += (long long)u.nrows_in[g] * gcols[g];
+    grp[g] = EnvGrp{goff[g], gcols[g], (int)spec.size(), (int)spec_g[g].size(), 0};
+    spec.insert(spec.end(), spec_g[g].begin(), spec_g[g].end());
+  }
+
+  // stage 1: per (input class c, ket sector kappa)
+  const long long bks = left ? 4LL * ket.rrp() : 1LL;
+  std::vector<int4> cinfo;
+  std::vector<int> col0(nQs), ncol(nQs);
+  for (int ka = 0; ka < nQs; ++ka) {
+    col0[ka] = (int)cinfo.size();
+    for (int s = 0; s < 4; ++s) {
+      const int rho = SR.find(add(SQ.q[ka], mul(sg, kQ[s])));
+      if (rho < 0) continue;
+      for (int ir = 0; ir < SR.n[rho]; ++ir) {
+        const int cx = left ? s * ket.rrp() + SR.off[rho] + ir : (SR.off[rho] + ir) * 4 * ket.rrp() + s * ket.rrp();
+        cinfo.push_back(make_int4(cx, s, rho, ir));
+      }
+    }
+    ncol[ka] = (int)cinfo.size() - col0[ka];
+  }
+  std::vector<EnvS1> s1;
+  std::vector<int4> t1;
+  for (int c = 0; c < u.ncin; ++c) {
+    const int cnt = u.cstart_in[c + 1] - u.cstart_in[c];
+    for (int ka = 0; ka < nQs; ++ka) {
+      const int pi = SP.find(add(SQ.q[ka], u.cq_in[c]));
+      if (pi < 0 || ncol[ka] == 0 || cnt == 0) continue;
+      EnvS1 d{cnt * SP.n[pi], ncol[ka], SQ.n[ka], u.cstart_in[c], SP.n[pi], SP.off[pi], SQ.off[ka], col0[ka], pi, 0};
+      const int id = (int)s1.size();
+      s1.push_back(d);
+      for (int m0 = 0; m0 < d.M; m0 += TL)
+        for (int c0 = 0; c0 < d.N; c0 += TL) t1.push_back(make_int4(id, m0, c0, 0));
+    }
+  }
+
+  // panels: tau rows (pi, s', i_p) with Q_tau = Q_pi + sigma q(s'); columns (class c', K', i_r)
+  std::vector<int> Ntau(nTs, 0), Ktau(nTs, 0), pcol((size_t)std::max(nTs * u.ncout, 1), -1);
+  for (int ta = 0; ta < nTs; ++ta)
+    for (int c = 0; c < u.ncout; ++c) {
+      const int rho = SR.find(sub(ST.q[ta], u.cq_out[c]));
+      if (rho < 0) continue;
+      pcol[(size_t)ta * u.ncout + c] = Ntau[ta];
+      Ntau[ta] += (u.cstart_out[c + 1] - u.cstart_out[c]) * SR.n[rho];
+    }
+  std::vector<int> t3tau((size_t)std::max(nPs * 4, 1), -1), koff((size_t)std::max(nPs * 4, 1), 0);
+  for (int ta = 0; ta < nTs; ++ta)
+    for (int pi = 0; pi < nPs; ++pi)
+      for (int s = 0; s < 4; ++s)
+        if (add(SP.q[pi], mul(sg, kQ[s])) == ST.q[ta]) {
+          t3tau[pi * 4 + s] = ta;
+          koff[pi * 4 + s] = Ktau[ta];
+          Ktau[ta] += SP.n[pi];
+        }
+  std::vector<long long> pbase(nTs, 0), upoff(nTs, 0);
+  long long npan = 0, nup = 0;
+  for (int ta = 0; ta < nTs; ++ta) {
+    pbase[ta] = npan;
+    npan += (long long)Ktau[ta] * Ntau[ta];
+    upoff[ta] = nup;
+    nup += (long long)ST.n[ta] * Ktau[ta];
+  }
+  std::vector<long long> t3base((size_t)std::max(nPs * 4, 1), -1);
+  std::vector<EnvUP> ups;
+  for (int pi = 0; pi < nPs; ++pi)
+    for (int s = 0; s < 4; ++s) {
+      const int ta = t3tau[pi * 4 + s];
+      if (ta < 0) continue;
+      t3base[pi * 4 + s] = pbase[ta] + (long long)koff[pi * 4 + s] * Ntau[ta];
+      ups.push_back(EnvUP{upoff[ta], ta, pi, s, koff[pi * 4 + s], Ktau[ta], 0});
+    }
+
+  // mix tiles
+  std::vector<int4> tm;
+  for (int g = 0; g < ng; ++g) {
+    if (gcols[g] == 0) continue;
+    for (int c0 = 0; c0 < gcols[g]; c0 += MC)
+      for (int r0 = u.orow0[g]; r0 < u.orow0[g + 1]; r0 += MR)
+        tm.push_back(make_int4(g, c0, r0, std::min(r0 + MR, u.orow0[g + 1])));
+  }
+
+  // stage 3: per (tau, output class c')
+  std::vector<EnvS3> s3;
+  std::vector<int4> t3;
+  for (int ta = 0; ta < nTs; ++ta) {
+    if (Ktau[ta] == 0) continue;
+    for (int c = 0; c < u.ncout; ++c) {
+      const int pc = pcol[(size_t)ta * u.ncout + c];
+      if (pc < 0) continue;
+      const int rho = SR.find(sub(ST.q[ta], u.cq_out[c]));
+      const int cnt = u.cstart_out[c + 1] - u.cstart_out[c];
+      EnvS3 d{upoff[ta], pbase[ta], ST.n[ta], cnt * SR.n[rho], Ktau[ta], Ntau[ta], pc, u.cstart_out[c],
+              SR.n[rho], SR.off[rho], ST.off[ta], 0};
+      const int id = (int)s3.size();
+      s3.push_back(d);
+      for (int m0 = 0; m0 < d.M; m0 += TL)
+        for (int n0 = 0; n0 < d.N; n0 += TL) t3.push_back(make_int4(id, m0, n0, 0));
+    }
+  }
+
+  // device tables of this update
+  hipStream_t st = E.stream;
+  DevMem d_s1, d_t1, d_cinfo, d_goff, d_gcols, d_specoff, d_nR, d_grp, d_spec, d_tm, d_t3tau, d_t3base, d_Ntau,
+      d_pcol, d_ups, d_oP, d_nP, d_oT, d_nT, d_s3, d_t3, d_err;
+  up(d_s1, s1, st);
+  up(d_t1, t1, st);
+  up(d_cinfo, cinfo, st);
+  up(d_goff, goff, st);
+  up(d_gcols, gcols, st);
+  up(d_specoff, specoff, st);
+  up(d_nR, SR.n, st);
+  up(d_grp, grp, st);
+  up(d_spec, spec, st);
+  up(d_tm, tm, st);
+  up(d_t3tau, t3tau, st);
+  up(d_t3base, t3base, st);
+  up(d_Ntau, Ntau, st);
+  up(d_pcol, pcol, st);
+  up(d_ups, ups, st);
+  up(d_oP, SP.off, st);
+  up(d_nP, SP.n, st);
+  up(d_oT, ST.off, st);
+  up(d_nT, ST.n, st);
+  up(d_s3, s3, st);
+  up(d_t3, t3, st);
+  d_err.resize_zero(sizeof(int), st);
+  int* err = d_err.as<int>();
+
+  E.be_t1.ensure(sizeof(double) * std::max<long long>(n1, 1));
+  E.be_panel.ensure(sizeof(double) * std::max<long long>(npan, 1));
+  E.be_up.ensure(sizeof(double) * std::max<long long>(nup, 1));
+  const long long nE = (long long)u.nin * Pp * Qp;
+  const long long nout = (long long)u.nout * Tp * Rp;
+  const long long nket = (long long)ket.rlp() * 4 * ket.rrp();
+  const long long nbra = (long long)bra.rlp() * 4 * bra.rrp();
+  fill(out, sizeof(double) * nout, st);
+  // T1 entries whose ket sector Q_pi - d_K does not exist are never written
+  fill(E.be_t1.p, sizeof(double) * n1, st);
+  if (!t1.empty()) {
+    hipLaunchKernelGGL(env_s1_kernel, dim3((unsigned)t1.size()), dim3(256), 0, st, d_t1.as<int4>(), d_s1.as<EnvS1>(),
+                       u.clist_in.as<int>(), d_cinfo.as<int4>(), u.d_gidx_in.as<int>(), u.rin.as<int>(),
+                       d_goff.as<long long>(), d_gcols.as<int>(), d_specoff.as<long long>(), d_nR.as<int>(), nRs,
+                       Ein, (long long)Pp * Qp, Qp, nE, ket.d.as<double>(), nket, bks, E.be_t1.as<double>(), n1, err);
+    BECHECK(hipGetLastError());
+  }
+  if (!tm.empty()) {
+    hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)tm.size()), dim3(MC), 0, st, d_tm.as<int4>(),
+                       d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
+                       u.orow.as<int2>(), d_spec.as<int4>(), E.be_t1.as<double>(), n1, E.be_panel.as<double>(), npan,
+                       d_t3tau.as<int>(), d_t3base.as<long long>(), d_Ntau.as<int>(), d_pcol.as<int>(), u.ncout,
+                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), d_nR.as<int>(), err);
+    BECHECK(hipGetLastError());
+  }
+  if (!ups.empty()) {
+    const long long rbp = bra.rrp();
+    const long long ps = left ? 4 * rbp : 1, ss = rbp, ts = left ? 1 : 4 * rbp;
+    hipLaunchKernelGGL(env_up_kernel, dim3((unsigned)ups.size()), dim3(256), 0, st, d_ups.as<EnvUP>(),
+                       bra.d.as<double>(), nbra, ps, ss, ts, d_oP.as<int>(), d_nP.as<int>(), d_oT.as<int>(),
+                       d_nT.as<int>(), E.be_up.as<double>(), nup, err);
+    BECHECK(hipGetLastError());
+  }
+  if (!t3.empty()) {
+    hipLaunchKernelGGL(env_s3_kernel, dim3((unsigned)t3.size()), dim3(256), 0, st, d_t3.as<int4>(),
+                       d_s3.as<EnvS3>(), E.be_up.as<double>(), nup, E.be_panel.as<double>(), npan,
+                       u.clist_out.as<int>(), out, nout, (long long)Tp * Rp, Rp, err);
+    BECHECK(hipGetLastError());
+  }
+  int herr = 0;
+  BECHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  BECHECK(hipStreamSynchronize(st));
+  if (herr != 0)
+    throw std::runtime_error("block-sparse environment update: index outside its buffer (check " +
+                             std::to_string(herr) + ")");
+  (void)nQs;
+  return true;
+}
+
+}  // namespace tt

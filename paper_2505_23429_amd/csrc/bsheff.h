@@ -62,4 +62,38 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
 template <typename T>
 void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3);
 
+// ---------------------------------------------------------------------------
+// Block-sparse environment update through one site (FP64).
+//   left  (sigma = +1): out[B][b'][b] = sum E[A][a'][a] Ubra[a'][s'][b'] W[A,s',s,B] Uket[a][s][b]
+//   right (sigma = -1): out[A][a'][a] = sum Ubra[a'][s'][b'] W[A,s',s,B] Uket[a][s][b] E[B][b'][b]
+// Rows (channel, s) of the intermediates are grouped by Gamma = sigma q(s) - d,
+// conserved by the site operator; spectators are (bra sector at the input
+// bond, ket sector at the output bond).  The charge-grouped operator tables
+// depend only on the site and are built once per MPO.
+// ---------------------------------------------------------------------------
+struct BsSiteUse {
+  int sigma = 1, nin = 0, nout = 0, ncin = 0, ncout = 0, ngrp = 0;
+  std::vector<Q2> cq_in, cq_out;           // class charges
+  std::vector<int> cls_in, cls_out;        // class of every channel
+  std::vector<int> cstart_in, cstart_out;  // class -> first entry of clist (size nc + 1)
+  std::vector<int> gidx_in;                // [nin*4] row group of (channel, s), -1 if none
+  std::vector<Q2> gq;                      // group charges
+  std::map<Q2, int> gid;
+  std::vector<int> orow0;                  // group -> first output row (size ngrp + 1)
+  std::vector<int> nrows_in;               // input rows per group
+  double nnz = 0.0;                        // operator non-zeros (for flop counts)
+  DevMem clist_in, clist_out, pos_out, d_cls_out, d_gidx_in, rin, optr, ocol, oval, orow;
+};
+
+// Builds the site tables: op grouped by output channel (nout outputs, inputs
+// < nin) with channel charges din/dout; sigma as above.
+void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2>& din,
+                 const std::vector<Q2>& dout, int sigma);
+
+// One update.  Ein: [nin][Pp][Qp] at the input bond (bra rows P, ket columns Q);
+// bra/ket: the two cores; out: [nout][Tp][Rp] (bra T, ket R) at the output bond,
+// overwritten.  Returns false when a bond's labels are not grouped by charge
+// (the caller then uses the dense update).
+bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, const Core& ket, double* out);
+
 }  // namespace tt

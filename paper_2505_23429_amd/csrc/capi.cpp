@@ -153,6 +153,7 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
     E.warn = 0;
     E.flops_heff = 0.0;
     E.sec_heff = 0.0;
+    for (double& v : E.ph) v = 0.0;
     auto t0 = std::chrono::steady_clock::now();
     out->E_before = E.energy();
     auto t1 = std::chrono::steady_clock::now();
@@ -176,6 +177,7 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
     out->seconds[3] = 0.0;
     out->flops_heff = E.flops_heff;
     out->seconds_heff = E.sec_heff;
+    for (int i = 0; i < 8; ++i) out->phase_seconds[i] = E.ph[i];
     return std::max(st, E.warn);
   });
 }

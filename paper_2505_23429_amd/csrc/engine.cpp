@@ -328,6 +328,11 @@ void Engine::set_mpo(int L_, const int* R, const int* nnz, const int32_t* const*
 // per-kernel timing of the effective-Hamiltonian product (HIP events on the
 // library stream; enabled by tt_kernel_timing)
 // ---------------------------------------------------------------------------
+double Engine::now() {
+  HC(hipStreamSynchronize(stream));
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 void Engine::kt_mark(int i) {
   if (!kt_on) return;
   if (!kt_ev[i]) HC(hipEventCreate(&kt_ev[i]));
@@ -596,6 +601,32 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
     q.qo = envq_o.as<int2>(); q.qi = envq_i.as<int2>(); q.qc = chan_q_dev[site + 1].as<int2>(); q.sgn = 1;
     qp = &q;
   }
+  if (opts.qn_skip) {
+    // block-sparse update (coefficient block handled through virtual input channels)
+    SiteMPO& sm = mpo[site];
+    if (!sm.bs_left) {
+      std::vector<Q2> din(chan_q[site].begin(), chan_q[site].end());
+      if (sm.has_block)
+        for (int q = sm.q0; q < sm.q1; ++q) din.push_back(chan_q[site + 1][q]);
+      std::vector<Q2> dout(chan_q[site + 1].begin(), chan_q[site + 1].end());
+      sm.bs_left = std::make_shared<BsSiteUse>();
+      bs_site_use(*this, *sm.bs_left, sm.has_block ? sm.byB_left : sm.byB, din, dout, +1);
+    }
+    const double* Ein = in.d.as<double>();
+    if (s.has_block) {
+      const long long slab = (long long)rb * rk;
+      const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
+      wsd.ensure(sizeof(double) * slab * (s.Rl + nQ));
+      HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rl, hipMemcpyDeviceToDevice, stream));
+      channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.p0 * slab, slab,
+                        wsd.as<double>() + (long long)s.Rl * slab, false, stream);
+      Ein = wsd.as<double>();
+    }
+    if (bs_env(*this, *sm.bs_left, Ein, bra, ket, o.d.as<double>())) {
+      out = std::move(o);
+      return;
+    }
+  }
   if (s.has_block) {
     const long long slab = (long long)rb * rk;
     const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
@@ -626,6 +657,31 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
     upload_q2(envq_i, padded_q(bra.qr, rb2, -1), stream);
     q.qo = envq_o.as<int2>(); q.qi = envq_i.as<int2>(); q.qc = chan_q_dev[site].as<int2>(); q.sgn = -1;
     qp = &q;
+  }
+  if (opts.qn_skip) {
+    SiteMPO& sm = mpo[site];
+    if (!sm.bs_right) {
+      std::vector<Q2> din(chan_q[site + 1].begin(), chan_q[site + 1].end());
+      if (sm.has_block)
+        for (int p = sm.p0; p < sm.p1; ++p) din.push_back(chan_q[site][p]);
+      std::vector<Q2> dout(chan_q[site].begin(), chan_q[site].end());
+      sm.bs_right = std::make_shared<BsSiteUse>();
+      bs_site_use(*this, *sm.bs_right, sm.has_block ? sm.byA_right : sm.byA, din, dout, -1);
+    }
+    const double* Ein = in.d.as<double>();
+    if (s.has_block) {
+      const long long slab = (long long)rb2 * rk2;
+      const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
+      wsd.ensure(sizeof(double) * slab * (s.Rr + nP));
+      HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rr, hipMemcpyDeviceToDevice, stream));
+      channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.q0 * slab, slab,
+                        wsd.as<double>() + (long long)s.Rr * slab, true, stream);
+      Ein = wsd.as<double>();
+    }
+    if (bs_env(*this, *sm.bs_right, Ein, bra, ket, o.d.as<double>())) {
+      out = std::move(o);
+      return;
+    }
   }
   if (s.has_block) {
     const long long slab = (long long)rb2 * rk2;
@@ -1559,8 +1615,11 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
   Window w;
   const int prec = E.opts.matvec_prec;
   Davidson r;
+  double tph = E.now();
   if (prec != TT_F64) {
     prepare_window(E, w, Le, b, Re, prec, ql, qr);
+    E.ph[2] += E.now() - tph;
+    tph = E.now();
     const double tol_low = E.opts.refine_fp64 ? std::max(E.opts.lowprec_tol, E.opts.dav_tol) : E.opts.dav_tol;
     r = davidson(E, w, mask, x.as<double>(), prec, tol_low, E.opts.dav_maxiter);
     if (E.opts.refine_fp64) {
@@ -1573,8 +1632,11 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
     }
   } else {
     prepare_window(E, w, Le, b, Re, TT_F64, ql, qr);
+    E.ph[2] += E.now() - tph;
+    tph = E.now();
     r = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter);
   }
+  E.ph[3] += E.now() - tph;
   if (!r.converged) E.warn = std::max(E.warn, (int)TT_WNOCONV);
   return r;
 }
@@ -1592,6 +1654,7 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   }
   if (tot != L) throw std::invalid_argument("subdomain lengths must sum to L");
   free_caches();
+  double tph = now();
   // Step 1: LQ sweep; W[k] centres, V[k] right-orthogonal cores
   Vc.clear(); Vc.resize(L);
   Wc.clear(); Wc.resize(L);
@@ -1618,6 +1681,8 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
     }
     HC(hipStreamSynchronize(stream));
   }
+  ph[0] += now() - tph;
+  tph = now();
   // environment caches: Lenv[k] at bond k from U (k = 0..L-1), Renv[k] from V (k = 2..L)
   Lenv.clear(); Lenv.resize(L + 1);
   Renv.clear(); Renv.resize(L + 1);
@@ -1647,7 +1712,9 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   }
   env_unit(Renv[L], 1);
   for (int k = L - 1; k >= 2; --k) env_right(Renv[k + 1], Vc[k], Vc[k], k, Renv[k]);
-  if (verbose) std::fprintf(stderr, "[tt] step 1 done (LQ sweep + environments)\n");
+  ph[1] += now() - tph;
+  if (verbose)
+    std::fprintf(stderr, "[tt] step 1 done: LQ sweep %.2fs, environments %.2fs\n", ph[0], ph[1]);
   // Step 2: subdomain sweeps
   subs.clear(); subs.resize(nsub);
   int start = 0;
@@ -1685,12 +1752,16 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
       S.E = r.theta;
       S.converged = S.converged && r.converged;
       Core N, C;
+      tph = now();
       split_two_site(*this, x.as<double>(), center.rl, center.ql, next.rr, next.qr, opts.chi_max, true, N, C);
+      ph[4] += now() - tph;
       if (b < blast) {
+        tph = now();
         Env nl;
         env_left(*Lcur, N, N, b, nl);
         Lrun = std::move(nl);
         Lcur = &Lrun;
+        ph[5] += now() - tph;
       } else {
         double nc = norm_dev(*this, C.d.as<double>(), C.elems());
         scale(C.d.as<double>(), 1.0 / nc, C.elems(), stream);
@@ -1701,8 +1772,10 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
     S.mod.push_back(std::move(center));
     HC(hipStreamSynchronize(stream));
     if (verbose)
-      std::fprintf(stderr, "[tt] subdomain %d sites %d..%d: E=%.10f matvecs=%d heff %.2fs/%.3g flop\n", j, s, e, S.E,
-                   S.matvecs, sec_heff, flops_heff);
+      std::fprintf(stderr,
+                   "[tt] subdomain %d sites %d..%d: E=%.10f matvecs=%d | products %.2fs, set-up %.2fs, Davidson "
+                   "%.2fs, splits %.2fs, env %.2fs\n",
+                   j, s, e, S.E, S.matvecs, sec_heff, ph[2], ph[3], ph[4], ph[5]);
     if (Eloc) Eloc[j] = S.E;
     if (mv) mv[j] = S.matvecs;
   }
@@ -1724,6 +1797,7 @@ static const Core& core_of(const Engine& E, int j, int k, bool V_suffix) {
 int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam, double* Eout, int* rank,
                            double* disc) {
   if (!have_local) throw std::logic_error("coarse_correct needs a preceding local_solve");
+  double tph = now();
   const int P = (int)subs.size();
   const int n = P + 1;
   std::vector<double> S((size_t)n * n, 0.0), A((size_t)n * n, 0.0);
@@ -1844,7 +1918,9 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
       S[(size_t)i * n + j] = S[(size_t)j * n + i] = ov_close(bS);
     }
   }
-  if (verbose) std::fprintf(stderr, "[tt] step 3: coarse matrices done\n");
+  ph[6] += now() - tph;
+  tph = now();
+  if (verbose) std::fprintf(stderr, "[tt] step 3: coarse matrices %.2fs\n", ph[6]);
   // coarse eigenproblem (host FP64): canonical orthogonalisation of S
   std::vector<double> ws, Vs;
   jacobi_eig(n, S, ws, Vs);
@@ -2022,7 +2098,8 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   U = std::move(T);
   free_caches();
   double En = energy();
-  if (verbose) std::fprintf(stderr, "[tt] step 4: compressed, E=%.10f discarded=%.3g\n", En, discarded);
+  ph[7] += now() - tph;
+  if (verbose) std::fprintf(stderr, "[tt] step 4: compressed in %.2fs, E=%.10f discarded=%.3g\n", ph[7], En, discarded);
   if (Eout) *Eout = En;
   if (disc) *disc = discarded;
   return status;

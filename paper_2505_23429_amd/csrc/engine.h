@@ -62,6 +62,8 @@ struct SiteOp {
   std::vector<double> hop;       // [nnz][4][4]
 };
 
+struct BsSiteUse;  // block-sparse environment-update tables of one site (bsheff.h)
+
 struct SiteMPO {
   int Rl = 0, Rr = 0;
   std::vector<int> A, B;          // all entries (host)
@@ -74,6 +76,7 @@ struct SiteMPO {
   SiteOp byB_noblk;               // block entries removed
   SiteOp byA_right;               // block -> virtual pass entries (inputs Rr + p - p0)
   SiteOp byB_rightv;              // block entries replaced by outputs Rr + (p - p0) (second site of a window)
+  std::shared_ptr<BsSiteUse> bs_left, bs_right;  // built on first block-sparse environment update
 };
 
 // Structural-zero tables of one two-site window (device arrays).
@@ -134,6 +137,12 @@ class Engine {
 
   // timing / accounting
   double flops_heff = 0.0, sec_heff = 0.0;
+  // wall-clock phases of a sweep (seconds, stream synchronised at each boundary):
+  // 0 LQ sweep, 1 step-1 environments, 2 window set-up, 3 Davidson, 4 two-site
+  // splits, 5 environment updates of the subdomain sweeps, 6 coarse matrices,
+  // 7 coarse eigenproblem and compression
+  double ph[8] = {};
+  double now();
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;
@@ -198,6 +207,7 @@ class Engine {
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)
   DevMem bs_t1, bs_t2, bs_t3, bs_part;
+  DevMem be_t1, be_panel, be_up;  // block-sparse environment-update workspaces
   long long bs_serial = 0, bs_zero_serial = -1;
   int bs_zero_prec = -1;
 
