@@ -15,6 +15,8 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <mutex>
+#include <map>
 #include <stdexcept>
 
 namespace tt {
@@ -54,35 +56,114 @@ static std::vector<Q2> padded_q(const Labels& q, int n, int sent) {
 // ---------------------------------------------------------------------------
 // memory helpers
 // ---------------------------------------------------------------------------
+// Caching device allocator behind DevMem: released blocks are kept in a
+// size-keyed free list and reused, so the many short-lived multi-GB
+// environment buffers of a sweep do not go through hipMalloc/hipFree each time.
+namespace {
+class BlockPool {
+ public:
+  void* get(size_t bytes, size_t& cap) {
+    const size_t r = round(bytes);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto it = free_.lower_bound(r);
+      if (it != free_.end() && it->first <= r + r / 4) {
+        cap = it->first;
+        void* p = it->second;
+        cached_ -= cap;
+        free_.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      trim(0);
+      if (hipMalloc(&p, r) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    cap = r;
+    return p;
+  }
+  void put(void* p, size_t cap) {
+    // work queued on any stream may still read the block
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> g(mu_);
+    free_.emplace(cap, p);
+    cached_ += cap;
+    if (cached_ > kMaxCached) trim_locked(kMaxCached / 2);
+  }
+  void trim(size_t target) {
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> g(mu_);
+    trim_locked(target);
+  }
+
+ private:
+  static constexpr size_t kMaxCached = size_t(48) << 30;
+  static size_t round(size_t b) {
+    if (b <= (size_t(1) << 20)) {
+      size_t r = 256;
+      while (r < b) r <<= 1;
+      return r;
+    }
+    const size_t g = size_t(2) << 20;
+    return (b + g - 1) / g * g;
+  }
+  void trim_locked(size_t target) {
+    while (cached_ > target && !free_.empty()) {
+      auto it = std::prev(free_.end());
+      (void)hipFree(it->second);
+      cached_ -= it->first;
+      free_.erase(it);
+    }
+  }
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  size_t cached_ = 0;
+};
+BlockPool& pool() {
+  static BlockPool* p = new BlockPool;  // lives until process exit
+  return *p;
+}
+}  // namespace
+
 void DevMem::release() {
-  if (p && own) (void)hipFree(p);
+  if (p && own) pool().put(p, cap);
   p = nullptr;
   n = 0;
+  cap = 0;
   own = true;
 }
 void DevMem::ensure(size_t bytes) {
+  if (own && p && bytes <= cap) {
+    if (bytes > n) n = bytes;
+    return;
+  }
   if (bytes <= n) return;
   release();
   if (bytes == 0) return;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    p = nullptr;
+  p = pool().get(bytes, cap);
+  if (!p) {
+    cap = 0;
     throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
   }
   n = bytes;
 }
 void DevMem::resize_zero(size_t bytes, hipStream_t s) {
-  if (bytes != n) {
+  if (!(own && p && bytes <= cap)) {
     release();
     if (bytes) {
-      hipError_t e = hipMalloc(&p, bytes);
-      if (e != hipSuccess) {
-        p = nullptr;
+      p = pool().get(bytes, cap);
+      if (!p) {
+        cap = 0;
         throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
       }
-      n = bytes;
     }
   }
+  n = bytes;
   if (bytes) fill(p, bytes, s);
 }
 void upload(DevMem& m, const void* h, size_t bytes, hipStream_t s) {
@@ -332,6 +413,27 @@ double Engine::now() {
   HC(hipStreamSynchronize(stream));
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+namespace {
+// accumulates wall time (stream synchronised) of a scope in verbose mode
+struct ScopeTimer {
+  Engine& E;
+  double& acc;
+  int& cnt;
+  double t0 = 0.0;
+  ScopeTimer(Engine& e, double& a, int& c) : E(e), acc(a), cnt(c) {
+    if (E.verbose) t0 = E.now();
+  }
+  ~ScopeTimer() {
+    if (!E.verbose) return;
+    try {
+      acc += E.now() - t0;
+      ++cnt;
+    } catch (...) {
+    }
+  }
+};
+}  // namespace
 
 void Engine::kt_mark(int i) {
   if (!kt_on) return;
@@ -622,11 +724,17 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
                         wsd.as<double>() + (long long)s.Rl * slab, false, stream);
       Ein = wsd.as<double>();
     }
-    if (bs_env(*this, *sm.bs_left, Ein, bra, ket, o.d.as<double>())) {
+    bool done;
+    {
+      ScopeTimer tm(*this, t_env_bs, n_env_bs);
+      done = bs_env(*this, *sm.bs_left, Ein, bra, ket, o.d.as<double>());
+    }
+    if (done) {
       out = std::move(o);
       return;
     }
   }
+  ScopeTimer tmd(*this, t_env_dense, n_env_dense);
   if (s.has_block) {
     const long long slab = (long long)rb * rk;
     const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
@@ -678,11 +786,17 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
                         wsd.as<double>() + (long long)s.Rr * slab, true, stream);
       Ein = wsd.as<double>();
     }
-    if (bs_env(*this, *sm.bs_right, Ein, bra, ket, o.d.as<double>())) {
+    bool done;
+    {
+      ScopeTimer tm(*this, t_env_bs, n_env_bs);
+      done = bs_env(*this, *sm.bs_right, Ein, bra, ket, o.d.as<double>());
+    }
+    if (done) {
       out = std::move(o);
       return;
     }
   }
+  ScopeTimer tmd(*this, t_env_dense, n_env_dense);
   if (s.has_block) {
     const long long slab = (long long)rb2 * rk2;
     const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
@@ -1826,6 +1940,7 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
     build_siteop(ident, 1, o, i, op, stream);
   }
   auto ov_left = [&](const Env& in, const Core& bra, const Core& ket, Env& out) {
+    ScopeTimer tm(*this, t_ov, n_ov);
     Env o;
     o.R = 1; o.rb = bra.rr; o.rk = ket.rr;
     o.d.ensure(sizeof(double) * o.elems());
@@ -1920,7 +2035,11 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   }
   ph[6] += now() - tph;
   tph = now();
-  if (verbose) std::fprintf(stderr, "[tt] step 3: coarse matrices %.2fs\n", ph[6]);
+  if (verbose)
+    std::fprintf(stderr,
+                 "[tt] step 3: coarse matrices %.2fs (so far: %d block-sparse env updates %.2fs, %d dense %.2fs, "
+                 "%d overlap updates %.2fs)\n",
+                 ph[6], n_env_bs, t_env_bs, n_env_dense, t_env_dense, n_ov, t_ov);
   // coarse eigenproblem (host FP64): canonical orthogonalisation of S
   std::vector<double> ws, Vs;
   jacobi_eig(n, S, ws, Vs);

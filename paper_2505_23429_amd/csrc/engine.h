@@ -26,17 +26,24 @@ using Labels = std::vector<Q2>;
 
 struct DevMem {
   void* p = nullptr;
-  size_t n = 0;
-  bool own = true;  // false: a caller's buffer, never freed here
+  size_t n = 0;      // bytes in use
+  size_t cap = 0;    // bytes allocated (pooled block)
+  bool own = true;   // false: a caller's buffer, never freed here
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n), own(o.own) { o.p = nullptr; o.n = 0; o.own = true; }
+  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n), cap(o.cap), own(o.own) {
+    o.p = nullptr; o.n = 0; o.cap = 0; o.own = true;
+  }
   DevMem& operator=(DevMem&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; own = o.own; o.p = nullptr; o.n = 0; o.own = true; }
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; cap = o.cap; own = o.own;
+      o.p = nullptr; o.n = 0; o.cap = 0; o.own = true;
+    }
     return *this;
   }
-  void borrow(void* q, size_t bytes) { release(); p = q; n = bytes; own = false; }
+  void borrow(void* q, size_t bytes) { release(); p = q; n = bytes; cap = bytes; own = false; }
   ~DevMem() { release(); }
   void release();
   void ensure(size_t bytes);       // grow-only, contents not preserved
@@ -143,6 +150,9 @@ class Engine {
   // 7 coarse eigenproblem and compression
   double ph[8] = {};
   double now();
+  // verbose-mode counters: environment updates (block-sparse, dense) and overlap updates
+  double t_env_bs = 0.0, t_env_dense = 0.0, t_ov = 0.0;
+  int n_env_bs = 0, n_env_dense = 0, n_ov = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;
