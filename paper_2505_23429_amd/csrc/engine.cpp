@@ -890,39 +890,81 @@ class SectorSVD {
   SvdOut run(const double* M, long long ldm, const std::vector<int>& rows, const Labels& rq,
              const std::vector<int>& cols, const Labels& cq, int chi, bool truncate) {
     secs = make_sectors(rows, rq, cols, cq);
+    const int ns = (int)secs.size();
     blocks.clear();
-    blocks.resize(secs.size());
+    blocks.resize(ns);
+    bins.clear();
+    // all sector indices in one upload; blocks binned by size and padded with zeros to the
+    // bin's largest block: one batched SVD per bin (the top min(m, n) singular triplets of a
+    // zero-padded block are those of the block, the padding rows/columns of its vectors zero)
+    std::vector<int> allr, allc;
+    std::map<int, std::vector<int>> bykey;
+    for (int t = 0; t < ns; ++t) {
+      Blk& b = blocks[t];
+      b.m = (int)secs[t].rows.size();
+      b.n = (int)secs[t].cols.size();
+      b.k = std::min(b.m, b.n);
+      b.roff = (int)allr.size();
+      b.coff = (int)allc.size();
+      allr.insert(allr.end(), secs[t].rows.begin(), secs[t].rows.end());
+      allc.insert(allc.end(), secs[t].cols.begin(), secs[t].cols.end());
+      int key = 16;
+      while (key < std::max(b.m, b.n)) key *= 2;
+      bykey[key].push_back(t);
+    }
+    rdev = upload_ints(allr, E.stream);
+    cdev = upload_ints(allc, E.stream);
     struct Trip {
       double s;
       Q2 g;
       int sec, i;
     };
     std::vector<Trip> trip;
-    DevMem info, E_;
-    info.ensure(sizeof(int));
-    for (size_t t = 0; t < secs.size(); ++t) {
-      Sector& sc = secs[t];
-      const int m = (int)sc.rows.size(), n = (int)sc.cols.size(), k = std::min(m, n);
-      Blk& b = blocks[t];
-      b.m = m; b.n = n; b.k = k;
-      DevMem Ablk, rdev, cdev;
-      Ablk.ensure(sizeof(double) * m * n);
-      rdev = upload_ints(sc.rows, E.stream);
-      cdev = upload_ints(sc.cols, E.stream);
-      gather2d(M, ldm, rdev.as<int>(), m, cdev.as<int>(), n, Ablk.as<double>(), true, E.stream);
-      b.U.ensure(sizeof(double) * m * k);
-      b.Vt.ensure(sizeof(double) * k * n);
-      b.S.ensure(sizeof(double) * k);
-      E_.ensure(sizeof(double) * std::max(k, 1));
-      RC(rocsolver_dgesvd(E.blas, rocblas_svect_singular, rocblas_svect_singular, m, n, Ablk.as<double>(), m,
-                          b.S.as<double>(), b.U.as<double>(), m, b.Vt.as<double>(), k, E_.as<double>(),
-                          rocblas_outofplace, info.as<int>()));
-      int inf = 0;
-      d2h(&inf, info.p, sizeof(int), E.stream);
-      if (inf != 0) throw std::runtime_error("gesvd did not converge");
-      b.hs.resize(k);
-      d2h(b.hs.data(), b.S.p, sizeof(double) * k, E.stream);
-      for (int i = 0; i < k; ++i) trip.push_back({b.hs[i], sc.g, (int)t, i});
+    for (auto& kv : bykey) {
+      bins.emplace_back();
+      Bin& B = bins.back();
+      const std::vector<int>& mem = kv.second;
+      B.cnt = (int)mem.size();
+      for (int t : mem) { B.M = std::max(B.M, blocks[t].m); B.N = std::max(B.N, blocks[t].n); }
+      B.K = std::min(B.M, B.N);
+      const long long MN = (long long)B.M * B.N;
+      B.A.ensure(sizeof(double) * MN * B.cnt);
+      fill(B.A.p, sizeof(double) * MN * B.cnt, E.stream);
+      std::vector<GatherBlk> gb(B.cnt);
+      for (int i = 0; i < B.cnt; ++i) {
+        const Blk& b = blocks[mem[i]];
+        gb[i] = GatherBlk{MN * i, B.M, b.roff, b.coff, b.m, b.n, 0};
+      }
+      DevMem gdev;
+      upload(gdev, gb.data(), gb.size() * sizeof(GatherBlk), E.stream);
+      gather_blocks(M, ldm, rdev.as<int>(), cdev.as<int>(), gdev.as<GatherBlk>(), B.cnt, B.A.as<double>(), E.stream);
+      B.U.ensure(sizeof(double) * (size_t)B.M * B.K * B.cnt);
+      B.Vt.ensure(sizeof(double) * (size_t)B.K * B.N * B.cnt);
+      B.S.ensure(sizeof(double) * (size_t)B.K * B.cnt);
+      DevMem Ew, info;
+      Ew.ensure(sizeof(double) * (size_t)B.K * B.cnt);
+      info.ensure(sizeof(int) * B.cnt);
+      RC(rocsolver_dgesvd_strided_batched(E.blas, rocblas_svect_singular, rocblas_svect_singular, B.M, B.N,
+                                          B.A.as<double>(), B.M, MN, B.S.as<double>(), B.K, B.U.as<double>(), B.M,
+                                          (rocblas_stride)B.M * B.K, B.Vt.as<double>(), B.K, (rocblas_stride)B.K * B.N,
+                                          Ew.as<double>(), B.K, rocblas_outofplace, info.as<int>(), B.cnt));
+      std::vector<int> inf(B.cnt);
+      d2h(inf.data(), info.p, sizeof(int) * B.cnt, E.stream);
+      for (int v : inf)
+        if (v != 0) throw std::runtime_error("gesvd did not converge");
+      std::vector<double> hs((size_t)B.K * B.cnt);
+      d2h(hs.data(), B.S.p, sizeof(double) * hs.size(), E.stream);
+      for (int i = 0; i < B.cnt; ++i) {
+        const int t = mem[i];
+        Blk& b = blocks[t];
+        b.U = B.U.as<double>() + (size_t)B.M * B.K * i;
+        b.Vt = B.Vt.as<double>() + (size_t)B.K * B.N * i;
+        b.S = B.S.as<double>() + (size_t)B.K * i;
+        b.ldU = B.M;
+        b.ldV = B.K;
+        b.hs.assign(hs.begin() + (size_t)B.K * i, hs.begin() + (size_t)B.K * i + b.k);
+        for (int q = 0; q < b.k; ++q) trip.push_back({b.hs[q], secs[t].g, t, q});
+      }
     }
     std::sort(trip.begin(), trip.end(), [](const Trip& a, const Trip& b) {
       if (a.s != b.s) return a.s > b.s;
@@ -958,20 +1000,14 @@ class SectorSVD {
   }
   // scatter the kept factors (destination arrays must be zero initialised)
   void scatter(double* left, long long ldl, double* right, long long ldr, int mode) {
-    for (size_t t = 0; t < secs.size(); ++t) {
-      Blk& b = blocks[t];
-      if (b.t == 0) continue;
-      std::vector<int> newidx(b.t);
-      std::iota(newidx.begin(), newidx.end(), b.off);
-      DevMem rdev = upload_ints(secs[t].rows, E.stream);
-      DevMem cdev = upload_ints(secs[t].cols, E.stream);
-      DevMem ndev = upload_ints(newidx, E.stream);
-      // left: (row i of block, new j) <- U[j*m + i]
-      scatter2d(b.U.as<double>(), 1, b.m, rdev.as<int>(), b.m, ndev.as<int>(), b.t, left, ldl, 1.0, nullptr,
-                mode == 1 ? b.S.as<double>() : nullptr, 0, E.stream);
-      // right: (new j, col c) <- Vt[c*k + j]
-      scatter2d(b.Vt.as<double>(), 1, b.k, ndev.as<int>(), b.t, cdev.as<int>(), b.n, right, ldr, 1.0,
-                mode == 0 ? b.S.as<double>() : nullptr, nullptr, 0, E.stream);
+    std::vector<ScatterBlk> sb;
+    for (const Blk& b : blocks)
+      if (b.t > 0) sb.push_back(ScatterBlk{b.U, b.Vt, b.S, b.ldU, b.ldV, b.roff, b.coff, b.m, b.n, b.t, b.off});
+    if (!sb.empty()) {
+      DevMem sdev;
+      upload(sdev, sb.data(), sb.size() * sizeof(ScatterBlk), E.stream);
+      scatter_factors(sdev.as<ScatterBlk>(), (int)sb.size(), rdev.as<int>(), cdev.as<int>(), left, ldl, right, ldr,
+                      mode, E.stream);
     }
     HC(hipStreamSynchronize(E.stream));
   }
@@ -979,12 +1015,20 @@ class SectorSVD {
  private:
   Engine& E;
   struct Blk {
-    int m = 0, n = 0, k = 0, t = 0, off = 0;
-    DevMem U, Vt, S;
+    int m = 0, n = 0, k = 0, t = 0, off = 0, roff = 0, coff = 0, ldU = 0, ldV = 0;
+    const double* U = nullptr;
+    const double* Vt = nullptr;
+    const double* S = nullptr;
     std::vector<double> hs;
+  };
+  struct Bin {
+    int M = 0, N = 0, K = 0, cnt = 0;
+    DevMem A, U, Vt, S;
   };
   std::vector<Sector> secs;
   std::vector<Blk> blocks;
+  std::vector<Bin> bins;
+  DevMem rdev, cdev;
 };
 
 // QR of core A viewed as [(a s)][b]; A <- Q (left-orthogonal), next <- R next.

@@ -656,6 +656,50 @@ void convert_f64_bf16f32(const double* a, float* b, size_t n, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
+__global__ void gather_blocks_kernel(const double* __restrict__ M, long long ldm, const int* __restrict__ rows,
+                                     const int* __restrict__ cols, const GatherBlk* __restrict__ blks,
+                                     double* __restrict__ dst) {
+  const GatherBlk b = blks[blockIdx.x];
+  for (int e = threadIdx.x; e < b.m * b.n; e += blockDim.x) {
+    const int j = e / b.m, i = e - j * b.m;
+    dst[b.dst + (long long)j * b.ld + i] = M[(long long)rows[b.roff + i] * ldm + cols[b.coff + j]];
+  }
+}
+void gather_blocks(const double* M, long long ldm, const int* rows, const int* cols, const GatherBlk* blks, int nblk,
+                   double* dst, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(gather_blocks_kernel, dim3(nblk), dim3(256), 0, s, M, ldm, rows, cols, blks, dst);
+  HIPCHECK(hipGetLastError());
+}
+__global__ void scatter_left_kernel(const ScatterBlk* __restrict__ blks, const int* __restrict__ rows,
+                                    double* __restrict__ left, long long ldl, int mode) {
+  const ScatterBlk b = blks[blockIdx.x];
+  for (int e = threadIdx.x; e < b.m * b.t; e += blockDim.x) {
+    const int j = e / b.m, i = e - j * b.m;
+    double v = b.U[i + (long long)j * b.ldU];
+    if (mode == 1) v *= b.S[j];
+    left[(long long)rows[b.roff + i] * ldl + b.off + j] = v;
+  }
+}
+__global__ void scatter_right_kernel(const ScatterBlk* __restrict__ blks, const int* __restrict__ cols,
+                                     double* __restrict__ right, long long ldr, int mode) {
+  const ScatterBlk b = blks[blockIdx.x];
+  for (int e = threadIdx.x; e < b.t * b.n; e += blockDim.x) {
+    const int c = e / b.t, j = e - c * b.t;
+    double v = b.Vt[j + (long long)c * b.ldV];
+    if (mode == 0) v *= b.S[j];
+    right[(long long)(b.off + j) * ldr + cols[b.coff + c]] = v;
+  }
+}
+void scatter_factors(const ScatterBlk* blks, int nblk, const int* rows, const int* cols, double* left, long long ldl,
+                     double* right, long long ldr, int mode, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(scatter_left_kernel, dim3(nblk), dim3(256), 0, s, blks, rows, left, ldl, mode);
+  HIPCHECK(hipGetLastError());
+  hipLaunchKernelGGL(scatter_right_kernel, dim3(nblk), dim3(256), 0, s, blks, cols, right, ldr, mode);
+  HIPCHECK(hipGetLastError());
+}
+
 __global__ void gather2d_kernel(const double* src, long long lds, const int* rows, int nr, const int* cols, int nc,
                                 double* dst, bool colmajor) {
   const long long tot = (long long)nr * nc;
