@@ -25,10 +25,19 @@ struct BsS4Tile { long long abase, bbase; int M, N, K, m0, n0, k0, k1, slot; };
 struct BsRedTile { int M, N, m0, n0, slot0, nsplit, row0, pad; };
 struct BsPair { int C, beta, koff, bprime; };
 
+// One sparse x dense mix.  Output rows with few operator entries ("light",
+// nearly all of them) are gathered entry by entry; the few rows with many
+// entries ("heavy": the accumulating channels, whose rows are almost dense
+// within their group) form a dense [H x rows_in] matrix per group applied by
+// the MFMA GEMM into a staging buffer, then scattered like the light rows.
+struct BsHeavy { int g, H, Nin, cols; long long in_base, w_off, tmp_off; };
 struct BsMix {
-  int ntiles = 0;
-  double flops = 0.0, nin = 0.0, nout = 0.0;  // 2 nnz cols; elements read and written once
+  int ntiles = 0, nhtiles = 0;
+  double flops = 0.0, nin = 0.0, nout = 0.0;  // algorithmic flops; elements read and written once
+  long long ntmp = 0;                         // staging elements of the heavy rows
+  std::vector<BsHeavy> heavy;
   DevMem tiles, groups, optr, ocol, oval64, oval32, orow, spec;
+  DevMem htiles, horow, hbase, hw64, hw32;
 };
 
 struct BsPlan {

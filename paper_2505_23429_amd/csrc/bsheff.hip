@@ -26,6 +26,7 @@ constexpr int KT = 32;         // K slice staged in LDS
 constexpr int MIX_COLS = 256;  // spectator columns per mix workgroup (one per thread)
 constexpr int MIX_ROWS = 64;   // output rows per mix workgroup
 constexpr int KSPLIT = 2048;   // K chunk of one stage-4 workgroup
+constexpr int HEAVY_MIN = 32;  // output rows with more operator entries go through the dense GEMM
 
 struct Sectors {
   std::vector<Q2> q;
@@ -156,7 +157,8 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
     int* __restrict__ err, int nbe,
     const long long* __restrict__ rowbase2, const long long* __restrict__ specoff, const int* __restrict__ ccls,
     const int* __restrict__ bshift, const long long* __restrict__ pbase, const int* __restrict__ kbeta,
-    const int* __restrict__ koff, int RCx, const int* __restrict__ nbeta, int round_bf16) {
+    const int* __restrict__ koff, int RCx, const int* __restrict__ nbeta, int round_bf16,
+    const long long* __restrict__ hbase, const T* __restrict__ tmp) {
   const int4 t = tiles[blockIdx.x];
   const BsGroup G = groups[t.x];
   const int col = t.y + (int)threadIdx.x;
@@ -179,10 +181,14 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
   const long long lim = nin - G.in_base - col;  // src[q] valid for 0 <= q < lim
   for (int r = t.z; r < t.w; ++r) {
     T acc = T(0);
-    const int e1 = optr[r + 1];
-    for (int e = optr[r]; e < e1; ++e) {
-      const long long q = (long long)ocol[e] * ld;
-      if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 4;
+    if (hbase) {
+      acc = tmp[hbase[r] + col];  // heavy row: sum formed by the GEMM
+    } else {
+      const int e1 = optr[r + 1];
+      for (int e = optr[r]; e < e1; ++e) {
+        const long long q = (long long)ocol[e] * ld;
+        if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 4;
+      }
     }
     const int2 ro = orow[r];  // {channel, site state}
     long long d;
@@ -322,13 +328,24 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
   std::vector<int2> orow;
   std::vector<int4> tiles;
   std::vector<BsGroup> groups(ng);
+  std::vector<int2> horow;
+  std::vector<long long> hbase;
+  std::vector<int4> htiles;
+  std::vector<double> hw;
+  m.heavy.clear();
+  m.ntmp = 0;
   m.flops = m.nin = m.nout = 0.0;
   for (int g = 0; g < ng; ++g) {
     groups[g] = BsGroup{in_off[g], cols[g], spec0[g], nspec[g], 0};
     const int r0 = (int)orow.size();
+    const int h0 = (int)horow.size();
     long long nnz_g = 0;
+    std::vector<std::pair<int, double>> ent;
+    std::vector<std::vector<std::pair<int, double>>> hrows;
+    std::vector<int2> hro;
     for (const int2& ro : rows_by_g[g]) {
       const int K = ro.x, sp = ro.y;
+      ent.clear();
       for (int e = so.hptr[K]; e < so.hptr[K + 1]; ++e) {
         const int A = so.hsrc[e];
         for (int s = 0; s < 4; ++s) {
@@ -337,25 +354,51 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
           const int ri = rowidx_in[A * 4 + s];
           if (ri < 0 || grp_in[A * 4 + s] != g)
             throw std::runtime_error("block-sparse plan: MPO entry breaks the charge grouping");
-          ocol.push_back(ri);
-          oval.push_back(v);
-          ++nnz_g;
+          ent.emplace_back(ri, v);
         }
       }
+      if ((int)ent.size() > HEAVY_MIN) {
+        hrows.push_back(ent);
+        hro.push_back(ro);
+        continue;
+      }
+      for (auto& pv : ent) { ocol.push_back(pv.first); oval.push_back(pv.second); }
+      nnz_g += (long long)ent.size();
       optr.push_back((int)ocol.size());
       orow.push_back(ro);
     }
     const int r1 = (int)orow.size();
-    if (cols[g] == 0 || r1 == r0) continue;
-    m.flops += 2.0 * (double)nnz_g * cols[g];
+    if (cols[g] == 0) continue;
     m.nin += (double)nrows_in[g] * cols[g];
-    m.nout += (double)(r1 - r0) * cols[g];
-    for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
-      for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
+    m.nout += (double)(r1 - r0 + (int)hro.size()) * cols[g];
+    m.flops += 2.0 * (double)nnz_g * cols[g];
+    if (r1 > r0)
+      for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
+        for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
+    if (!hro.empty()) {
+      const int H = (int)hro.size(), Nin = nrows_in[g];
+      BsHeavy hv{g, H, Nin, cols[g], in_off[g], (long long)hw.size(), m.ntmp};
+      hw.resize(hw.size() + (size_t)H * Nin, 0.0);
+      for (int i = 0; i < H; ++i) {
+        for (auto& pv : hrows[i]) hw[(size_t)hv.w_off + (size_t)i * Nin + pv.first] += pv.second;
+        horow.push_back(hro[i]);
+        hbase.push_back(m.ntmp + (long long)i * cols[g]);
+      }
+      m.ntmp += (long long)H * cols[g];
+      m.flops += 2.0 * (double)H * Nin * cols[g];
+      m.heavy.push_back(hv);
+      const int q1 = (int)horow.size();
+      for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
+        for (int q0 = h0; q0 < q1; q0 += MIX_ROWS) htiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, q1)));
+    }
   }
   if (ocol.empty()) { ocol.push_back(0); oval.push_back(0.0); }
+  if (horow.empty()) { horow.push_back(make_int2(0, 0)); hbase.push_back(0); }
+  if (hw.empty()) hw.push_back(0.0);
   std::vector<float> oval32(oval.begin(), oval.end());
+  std::vector<float> hw32(hw.begin(), hw.end());
   m.ntiles = (int)tiles.size();
+  m.nhtiles = (int)htiles.size();
   hipStream_t s = E.stream;
   up(m.tiles, tiles, s);
   up(m.groups, groups, s);
@@ -364,6 +407,11 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
   up(m.oval64, oval, s);
   up(m.oval32, oval32, s);
   up(m.orow, orow, s);
+  if (!htiles.empty()) up(m.htiles, htiles, s);
+  up(m.horow, horow, s);
+  up(m.hbase, hbase, s);
+  up(m.hw64, hw, s);
+  up(m.hw32, hw32, s);
 }
 
 bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, int rlp, int rrp, int RAx, int nP) {
@@ -596,6 +644,51 @@ template <>
 const DevMem& mix_vals<float>(const BsMix& m) { return m.oval32; }
 
 template <typename T>
+static const DevMem& heavy_vals(const BsMix& m);
+template <>
+const DevMem& heavy_vals<double>(const BsMix& m) { return m.hw64; }
+template <>
+const DevMem& heavy_vals<float>(const BsMix& m) { return m.hw32; }
+
+// light rows gathered, heavy rows through the GEMM and a scatter pass
+template <typename T, int MODE>
+static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, long long nin, T* out, long long nout,
+                    int* err, bool rnd) {
+  hipStream_t s = E.stream;
+  if (m.ntiles > 0) {
+    hipLaunchKernelGGL((mix_kernel<T, MODE>), dim3(m.ntiles), dim3(MIX_COLS), 0, s, m.tiles.as<int4>(),
+                       m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
+                       m.orow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,
+                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
+                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
+                       rnd ? 1 : 0, (const long long*)nullptr, (const T*)nullptr);
+    BSCHECK(hipGetLastError());
+  }
+  if (m.nhtiles > 0) {
+    E.bs_tmp.ensure(sizeof(T) * std::max<long long>(m.ntmp, 1));
+    T* tmp = E.bs_tmp.as<T>();
+    const T* W = heavy_vals<T>(m).template as<T>();
+    for (const BsHeavy& h : m.heavy) {
+      if (h.in_base < 0 || h.in_base + (long long)h.Nin * h.cols > nin)
+        throw std::runtime_error("block-sparse product: heavy rows read outside their group");
+      GemmArgs g{};
+      g.M = h.H; g.N = h.cols; g.K = h.Nin; g.batch = 1; g.kin = ((h.Nin + 15) / 16) * 16;
+      g.sAm = h.Nin; g.sAkk = 1;
+      g.sBkk = h.cols; g.sBn = 1;
+      g.sCm = h.cols; g.alpha = 1.0; g.beta = 0.0;
+      gemm<T>(g, W + h.w_off, in + h.in_base, tmp + h.tmp_off, true, true, s);
+    }
+    hipLaunchKernelGGL((mix_kernel<T, MODE>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<int4>(),
+                       m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
+                       m.horow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,
+                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
+                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
+                       rnd ? 1 : 0, m.hbase.as<long long>(), (const T*)tmp);
+    BSCHECK(hipGetLastError());
+  }
+}
+
+template <typename T>
 void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3) {
   if (!p.ok) throw std::runtime_error("block-sparse plan not built");
   hipStream_t s = E.stream;
@@ -637,26 +730,9 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
     BSCHECK(hipGetLastError());
   }
   E.kt_mark(1);
-  if (p.m1.ntiles > 0) {
-    hipLaunchKernelGGL((mix_kernel<T, 1>), dim3(p.m1.ntiles), dim3(MIX_COLS), 0, s, p.m1.tiles.as<int4>(),
-                       p.m1.groups.as<BsGroup>(), p.m1.optr.as<int>(), p.m1.ocol.as<int>(), mix_vals<T>(p.m1).template as<T>(),
-                       p.m1.orow.as<int2>(), p.m1.spec.as<int4>(), E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2,
-                       err, p.nbe,
-                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
-                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(), 0);
-    BSCHECK(hipGetLastError());
-  }
+  run_mix<T, 1>(E, p, p.m1, E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2, err, false);
   E.kt_mark(2);
-  if (p.m2.ntiles > 0) {
-    hipLaunchKernelGGL((mix_kernel<T, 2>), dim3(p.m2.ntiles), dim3(MIX_COLS), 0, s, p.m2.tiles.as<int4>(),
-                       p.m2.groups.as<BsGroup>(), p.m2.optr.as<int>(), p.m2.ocol.as<int>(), mix_vals<T>(p.m2).template as<T>(),
-                       p.m2.orow.as<int2>(), p.m2.spec.as<int4>(), E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3,
-                       err, p.nbe,
-                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
-                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
-                       bf16_t3 ? 1 : 0);
-    BSCHECK(hipGetLastError());
-  }
+  run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3);
   E.kt_mark(3);
   if (p.ntiles4 > 0) {
     hipLaunchKernelGGL((stage4_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
