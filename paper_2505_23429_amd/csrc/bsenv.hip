@@ -33,6 +33,7 @@ constexpr int TL = 64;   // GEMM output tile edge
 constexpr int KS = 32;   // K slice in LDS
 constexpr int MC = 256;  // mix: spectator columns per workgroup
 constexpr int MR = 64;   // mix: output rows per workgroup
+constexpr int HEAVY = 32;  // output rows with more operator entries go through the dense GEMM
 
 struct Sec {
   std::vector<Q2> q;
@@ -69,7 +70,7 @@ void up(DevMem& d, const std::vector<V>& v, hipStream_t s) {
 }
 
 struct EnvS1 { int M, N, K, cls0, np, op, oq, col0, pi, pad; };
-struct EnvGrp { long long in_base; int ncols, spec0, nspec, pad; };
+struct EnvGrp { long long in_base; int ncols, spec0, nspec, ld; };  // ld: row stride of T1 (multiple of 4)
 struct EnvS3 { long long upoff, pbase; int M, N, K, ld, pcol, cls0, nrho, orho, otau, pad; };
 struct EnvUP { long long upoff; int tau, pi, s, koff, K, pad; };
 
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(MC) void env_mix_kernel(
     const int4* __restrict__ spec, const double* __restrict__ T1, long long n1, double* __restrict__ panel,
     long long npan, const int* __restrict__ t3tau, const long long* __restrict__ t3base, const int* __restrict__ Ntau,
     const int* __restrict__ pcol, int ncout, const int* __restrict__ cls_out, const int* __restrict__ pos_out,
-    const int* __restrict__ nR, int* __restrict__ err) {
+    const int* __restrict__ nR, int* __restrict__ err, const long long* __restrict__ hbase,
+    const double* __restrict__ tmp) {
   const int4 t = tiles[blockIdx.x];
   const EnvGrp G = grp[t.x];
   const int col = t.y + (int)threadIdx.x;
@@ -169,10 +171,14 @@ __global__ __launch_bounds__(MC) void env_mix_kernel(
   const double* src = T1 + G.in_base + col;
   for (int r = t.z; r < t.w; ++r) {
     double acc = 0.0;
-    const int e1 = optr[r + 1];
-    for (int e = optr[r]; e < e1; ++e) {
-      const long long q = (long long)ocol[e] * G.ncols;
-      if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 15;
+    if (hbase) {
+      acc = tmp[hbase[r] + col];  // heavy row: sum formed by the GEMM
+    } else {
+      const int e1 = optr[r + 1];
+      for (int e = optr[r]; e < e1; ++e) {
+        const long long q = (long long)ocol[e] * G.ld;
+        if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 15;
+      }
     }
     const int2 ro = orow[r];  // {K', s'}
     const int ts = sp.y * 4 + ro.y;
@@ -328,12 +334,22 @@ void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2
   rows_by_g.resize(u.ngrp);
   nrows.resize(u.ngrp, 0);
   std::vector<int> optr(1, 0), ocol;
-  std::vector<double> oval;
-  std::vector<int2> orow;
+  std::vector<double> oval, hw;
+  std::vector<int2> orow, hrow;
   u.orow0.assign(u.ngrp + 1, 0);
+  u.hrow0.assign(u.ngrp + 1, 0);
+  u.nin4.assign(u.ngrp, 0);
+  u.hw_off.assign(u.ngrp, 0);
+  u.nnz = 0.0;
+  nrows.resize(u.ngrp, 0);
+  std::vector<std::pair<int, double>> ent;
   for (int g = 0; g < u.ngrp; ++g) {
     u.orow0[g] = (int)orow.size();
+    u.hrow0[g] = (int)hrow.size();
+    u.nin4[g] = (nrows[g] + 3) / 4 * 4;
+    u.hw_off[g] = (long long)hw.size();
     for (const int2& ro : rows_by_g[g]) {
+      ent.clear();
       for (int e = op.hptr[ro.x]; e < op.hptr[ro.x + 1]; ++e) {
         const int Kin = op.hsrc[e];
         if (Kin < 0 || Kin >= u.nin) throw std::runtime_error("block-sparse site tables: input channel out of range");
@@ -342,17 +358,27 @@ void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2
           if (v == 0.0) continue;
           if (u.gidx_in[Kin * 4 + s] != g)
             throw std::runtime_error("block-sparse site tables: operator entry breaks the charge grouping");
-          ocol.push_back(rin[Kin * 4 + s]);
-          oval.push_back(v);
+          ent.emplace_back(rin[Kin * 4 + s], v);
         }
       }
+      u.nnz += (double)ent.size();
+      if ((int)ent.size() > HEAVY) {
+        const size_t base = hw.size();
+        hw.resize(base + u.nin4[g], 0.0);
+        for (auto& pv : ent) hw[base + pv.first] += pv.second;
+        hrow.push_back(ro);
+        continue;
+      }
+      for (auto& pv : ent) { ocol.push_back(pv.first); oval.push_back(pv.second); }
       optr.push_back((int)ocol.size());
       orow.push_back(ro);
     }
   }
   u.orow0[u.ngrp] = (int)orow.size();
-  u.nnz = (double)ocol.size();
+  u.hrow0[u.ngrp] = (int)hrow.size();
   u.nrows_in = nrows;
+  up(u.hrow, hrow, E.stream);
+  up(u.hw, hw, E.stream);
   hipStream_t st = E.stream;
   up(u.clist_in, clist_in, st);
   up(u.clist_out, clist_out, st);
@@ -399,14 +425,17 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
       spec_g[g].push_back(make_int4(gcols[g], pi, rho, 0));
       gcols[g] += SP.n[pi] * SR.n[rho];
     }
+  // T1 rows of a group are stored with a stride rounded up to 4 elements
   std::vector<long long> goff(ng, 0);
+  std::vector<int> gld(ng, 0);
   long long n1 = 0;
   std::vector<int4> spec;
   std::vector<EnvGrp> grp(ng);
   for (int g = 0; g < ng; ++g) {
+    gld[g] = (gcols[g] + 3) / 4 * 4;
     goff[g] = n1;
-    n1 += (long long)u.nrows_in[g] * gcols[g];
-    grp[g] = EnvGrp{goff[g], gcols[g], (int)spec.size(), (int)spec_g[g].size(), 0};
+    n1 += (long long)u.nrows_in[g] * gld[g];
+    grp[g] = EnvGrp{goff[g], gcols[g], (int)spec.size(), (int)spec_g[g].size(), gld[g]};
     spec.insert(spec.end(), spec_g[g].begin(), spec_g[g].end());
   }
 
@@ -477,13 +506,23 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
       ups.push_back(EnvUP{upoff[ta], ta, pi, s, koff[pi * 4 + s], Ktau[ta], 0});
     }
 
-  // mix tiles
-  std::vector<int4> tm;
+  // mix tiles: light rows, and heavy rows (staged by the GEMM) with their staging offsets
+  std::vector<int4> tm, th;
+  std::vector<long long> hbase((size_t)std::max(u.hrow0[ng], 1), 0), htmp(ng, 0);
+  long long ntmp = 0;
   for (int g = 0; g < ng; ++g) {
     if (gcols[g] == 0) continue;
     for (int c0 = 0; c0 < gcols[g]; c0 += MC)
       for (int r0 = u.orow0[g]; r0 < u.orow0[g + 1]; r0 += MR)
         tm.push_back(make_int4(g, c0, r0, std::min(r0 + MR, u.orow0[g + 1])));
+    if (u.hrow0[g + 1] > u.hrow0[g]) {
+      htmp[g] = ntmp;
+      for (int r = u.hrow0[g]; r < u.hrow0[g + 1]; ++r) hbase[r] = ntmp + (long long)(r - u.hrow0[g]) * gld[g];
+      ntmp += (long long)(u.hrow0[g + 1] - u.hrow0[g]) * gld[g];
+      for (int c0 = 0; c0 < gcols[g]; c0 += MC)
+        for (int r0 = u.hrow0[g]; r0 < u.hrow0[g + 1]; r0 += MR)
+          th.push_back(make_int4(g, c0, r0, std::min(r0 + MR, u.hrow0[g + 1])));
+    }
   }
 
   // stage 3: per (tau, output class c')
@@ -507,13 +546,15 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
 
   // device tables of this update
   hipStream_t st = E.stream;
-  DevMem d_s1, d_t1, d_cinfo, d_goff, d_gcols, d_specoff, d_nR, d_grp, d_spec, d_tm, d_t3tau, d_t3base, d_Ntau,
+  DevMem d_s1, d_t1, d_cinfo, d_goff, d_gcols, d_specoff, d_th, d_hbase, d_nR, d_grp, d_spec, d_tm, d_t3tau, d_t3base, d_Ntau,
       d_pcol, d_ups, d_oP, d_nP, d_oT, d_nT, d_s3, d_t3, d_err;
   up(d_s1, s1, st);
   up(d_t1, t1, st);
   up(d_cinfo, cinfo, st);
   up(d_goff, goff, st);
-  up(d_gcols, gcols, st);
+  up(d_gcols, gld, st);
+  up(d_th, th, st);
+  up(d_hbase, hbase, st);
   up(d_specoff, specoff, st);
   up(d_nR, SR.n, st);
   up(d_grp, grp, st);
@@ -555,7 +596,36 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
                        d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
                        u.orow.as<int2>(), d_spec.as<int4>(), E.be_t1.as<double>(), n1, E.be_panel.as<double>(), npan,
                        d_t3tau.as<int>(), d_t3base.as<long long>(), d_Ntau.as<int>(), d_pcol.as<int>(), u.ncout,
-                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), d_nR.as<int>(), err);
+                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), d_nR.as<int>(), err,
+                       (const long long*)nullptr, (const double*)nullptr);
+    BECHECK(hipGetLastError());
+  }
+  if (!th.empty()) {
+    E.be_tmp.ensure(sizeof(double) * std::max<long long>(ntmp, 1));
+    std::vector<GemmGroup<double>> gg;
+    for (int g = 0; g < ng; ++g) {
+      const int H = u.hrow0[g + 1] - u.hrow0[g];
+      if (H == 0 || gcols[g] == 0) continue;
+      GemmGroup<double> G{};
+      G.g.M = H; G.g.N = gcols[g]; G.g.K = u.nrows_in[g]; G.g.batch = 1;
+      G.g.kin = std::max(16, (u.nrows_in[g] + 15) / 16 * 16);
+      G.g.sAm = u.nin4[g]; G.g.sAkk = 1;
+      G.g.sBkk = gld[g]; G.g.sBn = 1;
+      G.g.sCm = gld[g]; G.g.alpha = 1.0; G.g.beta = 0.0;
+      G.A = u.hw.as<double>() + u.hw_off[g];
+      G.B = E.be_t1.as<double>() + goff[g];
+      G.C = E.be_tmp.as<double>() + htmp[g];
+      gg.push_back(G);
+    }
+    DevMem gdev;
+    upload(gdev, gg.data(), gg.size() * sizeof(GemmGroup<double>), st);
+    gemm_grouped<double>(gdev.as<GemmGroup<double>>(), gg, st);
+    hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)th.size()), dim3(MC), 0, st, d_th.as<int4>(),
+                       d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
+                       u.hrow.as<int2>(), d_spec.as<int4>(), E.be_t1.as<double>(), n1, E.be_panel.as<double>(), npan,
+                       d_t3tau.as<int>(), d_t3base.as<long long>(), d_Ntau.as<int>(), d_pcol.as<int>(), u.ncout,
+                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), d_nR.as<int>(), err, d_hbase.as<long long>(),
+                       (const double*)E.be_tmp.as<double>());
     BECHECK(hipGetLastError());
   }
   if (!ups.empty()) {

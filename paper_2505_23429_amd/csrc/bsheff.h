@@ -20,7 +20,7 @@
 namespace tt {
 
 struct BsAlpha { int M, N, K, row0, col0, oal; };
-struct BsGroup { long long in_base; int ncols, spec0, nspec, pad; };
+struct BsGroup { long long in_base; int ncols, spec0, nspec, ld; };  // ld: row stride (ncols rounded up to 4)
 struct BsS4Tile { long long abase, bbase; int M, N, K, m0, n0, k0, k1, slot; };
 struct BsRedTile { int M, N, m0, n0, slot0, nsplit, row0, pad; };
 struct BsPair { int C, beta, koff, bprime; };
@@ -30,7 +30,7 @@ struct BsPair { int C, beta, koff, bprime; };
 // entries ("heavy": the accumulating channels, whose rows are almost dense
 // within their group) form a dense [H x rows_in] matrix per group applied by
 // the MFMA GEMM into a staging buffer, then scattered like the light rows.
-struct BsHeavy { int g, H, Nin, cols; long long in_base, w_off, tmp_off; };
+struct BsHeavy { int g, H, Nin, Nin4, cols, ld; long long in_base, w_off, tmp_off; };
 struct BsMix {
   int ntiles = 0, nhtiles = 0;
   double flops = 0.0, nin = 0.0, nout = 0.0;  // algorithmic flops; elements read and written once
@@ -92,6 +92,11 @@ struct BsSiteUse {
   std::vector<int> nrows_in;               // input rows per group
   double nnz = 0.0;                        // operator non-zeros (for flop counts)
   DevMem clist_in, clist_out, pos_out, d_cls_out, d_gidx_in, rin, optr, ocol, oval, orow;
+  // heavy output rows (many entries) as a dense [H x rows_in] matrix per group
+  std::vector<int> hrow0;                  // group -> first heavy row (size ngrp + 1)
+  std::vector<int> nin4;                   // rows_in rounded up to 4 (row stride of the dense matrix)
+  std::vector<long long> hw_off;           // group -> offset of its dense matrix
+  DevMem hrow, hw;
 };
 
 // Builds the site tables: op grouped by output channel (nout outputs, inputs

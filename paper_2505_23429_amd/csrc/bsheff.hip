@@ -177,7 +177,7 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
     wj = within - wi * nb;
   }
   const T* src = in + G.in_base + col;
-  const long long ld = G.ncols;
+  const long long ld = G.ld;
   const long long lim = nin - G.in_base - col;  // src[q] valid for 0 <= q < lim
   for (int r = t.z; r < t.w; ++r) {
     T acc = T(0);
@@ -313,7 +313,8 @@ __global__ __launch_bounds__(256) void rstack_kernel(const BsPair* __restrict__ 
 // ---------------------------------------------------------------------------
 static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q2>& dout, int nout_ch,
                       const std::vector<int>& rowidx_in, const std::vector<int>& grp_in, const std::map<Q2, int>& gid,
-                      const std::vector<Q2>& gq, const std::vector<int>& cols, const std::vector<long long>& in_off,
+                      const std::vector<Q2>& gq, const std::vector<int>& cols, const std::vector<int>& ldg,
+                      const std::vector<long long>& in_off,
                       const std::vector<int>& nrows_in, const std::vector<int>& spec0,
                       const std::vector<int>& nspec) {
   const int ng = (int)gq.size();
@@ -336,7 +337,7 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
   m.ntmp = 0;
   m.flops = m.nin = m.nout = 0.0;
   for (int g = 0; g < ng; ++g) {
-    groups[g] = BsGroup{in_off[g], cols[g], spec0[g], nspec[g], 0};
+    groups[g] = BsGroup{in_off[g], cols[g], spec0[g], nspec[g], ldg[g]};
     const int r0 = (int)orow.size();
     const int h0 = (int)horow.size();
     long long nnz_g = 0;
@@ -376,15 +377,15 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
         for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
     if (!hro.empty()) {
-      const int H = (int)hro.size(), Nin = nrows_in[g];
-      BsHeavy hv{g, H, Nin, cols[g], in_off[g], (long long)hw.size(), m.ntmp};
-      hw.resize(hw.size() + (size_t)H * Nin, 0.0);
+      const int H = (int)hro.size(), Nin = nrows_in[g], Nin4 = (Nin + 3) / 4 * 4;
+      BsHeavy hv{g, H, Nin, Nin4, cols[g], ldg[g], in_off[g], (long long)hw.size(), m.ntmp};
+      hw.resize(hw.size() + (size_t)H * Nin4, 0.0);
       for (int i = 0; i < H; ++i) {
-        for (auto& pv : hrows[i]) hw[(size_t)hv.w_off + (size_t)i * Nin + pv.first] += pv.second;
+        for (auto& pv : hrows[i]) hw[(size_t)hv.w_off + (size_t)i * Nin4 + pv.first] += pv.second;
         horow.push_back(hro[i]);
-        hbase.push_back(m.ntmp + (long long)i * cols[g]);
+        hbase.push_back(m.ntmp + (long long)i * ldg[g]);
       }
-      m.ntmp += (long long)H * cols[g];
+      m.ntmp += (long long)H * ldg[g];
       m.flops += 2.0 * (double)H * Nin * cols[g];
       m.heavy.push_back(hv);
       const int q1 = (int)horow.size();
@@ -483,17 +484,20 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   std::vector<int> idx1, grp1, nr1, idx2, grp2, nr2;
   rows_of(dA, RAx, idx1, grp1, nr1);
   rows_of(dB, RB, idx2, grp2, nr2);
+  // group rows are stored with a stride rounded up to 4 elements (16-byte aligned rows)
+  std::vector<int> ldg(ng);
+  for (int g = 0; g < ng; ++g) ldg[g] = (cols[g] + 3) / 4 * 4;
   std::vector<long long> off1(ng), off2(ng);
   long long n1 = 0, n2 = 0;
   for (int g = 0; g < ng; ++g) {
-    off1[g] = n1; n1 += (long long)nr1[g] * cols[g];
-    off2[g] = n2; n2 += (long long)nr2[g] * cols[g];
+    off1[g] = n1; n1 += (long long)nr1[g] * ldg[g];
+    off2[g] = n2; n2 += (long long)nr2[g] * ldg[g];
   }
   std::vector<long long> rowpart1((size_t)RAx * 4, -1), rowbase2((size_t)RB * 4, -1);
   for (int i = 0; i < RAx * 4; ++i)
-    if (idx1[i] >= 0) rowpart1[i] = off1[grp1[i]] + (long long)idx1[i] * cols[grp1[i]];
+    if (idx1[i] >= 0) rowpart1[i] = off1[grp1[i]] + (long long)idx1[i] * ldg[grp1[i]];
   for (int i = 0; i < RB * 4; ++i)
-    if (idx2[i] >= 0) rowbase2[i] = off2[grp2[i]] + (long long)idx2[i] * cols[grp2[i]];
+    if (idx2[i] >= 0) rowbase2[i] = off2[grp2[i]] + (long long)idx2[i] * ldg[grp2[i]];
   p.n1 = n1;
   p.n2 = n2;
 
@@ -626,8 +630,8 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   up(p.pairs, pairs, s);
   up(p.rbase, rbase, s);
   // mixes: site k (inputs T1 rows, outputs into T2) and site k+1 (inputs T2 rows, outputs into panels)
-  build_mix(E, p.m1, w1, dB, RB, idx1, grp1, gid, gq, cols, off1, nr1, spec0, nspec);
-  build_mix(E, p.m2, w2, dC, RCx, idx2, grp2, gid, gq, cols, off2, nr2, spec0, nspec);
+  build_mix(E, p.m1, w1, dB, RB, idx1, grp1, gid, gq, cols, ldg, off1, nr1, spec0, nspec);
+  build_mix(E, p.m2, w2, dC, RCx, idx2, grp2, gid, gq, cols, ldg, off2, nr2, spec0, nspec);
   up(p.m1.spec, spec, s);
   up(p.m2.spec, spec, s);
   p.have64 = p.have32 = false;
@@ -668,16 +672,23 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
     E.bs_tmp.ensure(sizeof(T) * std::max<long long>(m.ntmp, 1));
     T* tmp = E.bs_tmp.as<T>();
     const T* W = heavy_vals<T>(m).template as<T>();
+    std::vector<GemmGroup<T>> gg;
     for (const BsHeavy& h : m.heavy) {
-      if (h.in_base < 0 || h.in_base + (long long)h.Nin * h.cols > nin)
+      if (h.in_base < 0 || h.in_base + (long long)h.Nin * h.ld > nin)
         throw std::runtime_error("block-sparse product: heavy rows read outside their group");
-      GemmArgs g{};
-      g.M = h.H; g.N = h.cols; g.K = h.Nin; g.batch = 1; g.kin = ((h.Nin + 15) / 16) * 16;
-      g.sAm = h.Nin; g.sAkk = 1;
-      g.sBkk = h.cols; g.sBn = 1;
-      g.sCm = h.cols; g.alpha = 1.0; g.beta = 0.0;
-      gemm<T>(g, W + h.w_off, in + h.in_base, tmp + h.tmp_off, true, true, s);
+      GemmGroup<T> G{};
+      G.g.M = h.H; G.g.N = h.cols; G.g.K = h.Nin; G.g.batch = 1; G.g.kin = ((h.Nin + 15) / 16) * 16;
+      G.g.sAm = h.Nin4; G.g.sAkk = 1;
+      G.g.sBkk = h.ld; G.g.sBn = 1;
+      G.g.sCm = h.ld; G.g.alpha = 1.0; G.g.beta = 0.0;
+      G.A = W + h.w_off;
+      G.B = in + h.in_base;
+      G.C = tmp + h.tmp_off;
+      gg.push_back(G);
     }
+    DevMem gdev;
+    upload(gdev, gg.data(), gg.size() * sizeof(GemmGroup<T>), s);
+    gemm_grouped<T>(gdev.as<GemmGroup<T>>(), gg, s);
     hipLaunchKernelGGL((mix_kernel<T, MODE>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<int4>(),
                        m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
                        m.horow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,

@@ -217,7 +217,7 @@ class Engine {
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)
   DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp;
-  DevMem be_t1, be_panel, be_up;  // block-sparse environment-update workspaces
+  DevMem be_t1, be_panel, be_up, be_tmp;  // block-sparse environment-update workspaces
   long long bs_serial = 0, bs_zero_serial = -1;
   int bs_zero_prec = -1;
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace tt {
 
@@ -39,6 +40,18 @@ constexpr int GEMM_TILE = 128;
 // C = alpha * A B + beta * C for T in {double, float}.  Accumulation in T.
 template <typename T>
 void gemm(const GemmArgs& g, const T* A, const T* B, T* C, bool a_kcontig, bool b_ncontig, hipStream_t s);
+
+// Independent row-major GEMMs (a_kcontig, b_ncontig, batch 1) in one launch.
+// dev_groups is the device copy of host_groups (used for the launch shape).
+template <typename T>
+struct GemmGroup {
+  GemmArgs g;
+  const T* A;
+  const T* B;
+  T* C;
+};
+template <typename T>
+void gemm_grouped(const GemmGroup<T>* dev_groups, const std::vector<GemmGroup<T>>& host_groups, hipStream_t s);
 
 // BF16 operands (uint16 storage), FP32 accumulation and FP32 output.
 void gemm_bf16(const GemmArgs& g, const uint16_t* A, const uint16_t* B, float* C, bool a_kcontig,

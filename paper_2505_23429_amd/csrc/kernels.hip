@@ -126,8 +126,8 @@ __device__ inline void load_run(const T* __restrict__ p, long long stride, bool 
 }
 
 template <typename T, bool AK, bool BNC, bool VEC>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restrict__ A, const T* __restrict__ B,
-                                                   T* __restrict__ C) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, const T* __restrict__ A, const T* __restrict__ B,
+                                          T* __restrict__ C, const int mtile, const int ntile, const int bz) {
   constexpr int BKc = GemmCfg<T>::BK;
   constexpr int RUN = GemmCfg<T>::RUN;
   __shared__ T As[2][BKc][BM + 4];
@@ -136,10 +136,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restri
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
-  const int bz = blockIdx.z;
-  const T* Ab = A + (long long)bz * g.sAb;
+  const int m0 = mtile * BM;
+  const int n0 = ntile * BN;
+    const T* Ab = A + (long long)bz * g.sAb;
   const T* Bb = B + (long long)bz * g.sBb;
   T* Cb = C + (long long)bz * g.sCb;
 
@@ -204,7 +203,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restri
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
 
-  KIter<BKc> it(g, blockIdx.x, blockIdx.y, bz);
+  KIter<BKc> it(g, mtile, ntile, bz);
   int buf = 0;
   int kcur = it.first();
   if (kcur >= 0) {
@@ -252,6 +251,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restri
     }
 }
 
+template <typename T, bool AK, bool BNC, bool VEC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, const T* __restrict__ A, const T* __restrict__ B,
+                                                   T* __restrict__ C) {
+  gemm_tile<T, AK, BNC, VEC>(g, A, B, C, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// one launch for a list of independent GEMMs: blockIdx.z selects the problem,
+// tiles outside it return at once
+template <typename T, bool AK, bool BNC, bool VEC>
+__global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmGroup<T>* __restrict__ grp) {
+  const GemmGroup<T> G = grp[blockIdx.z];
+  if ((int)blockIdx.x * BM >= G.g.M || (int)blockIdx.y * BN >= G.g.N) return;
+  gemm_tile<T, AK, BNC, VEC>(G.g, G.A, G.B, G.C, blockIdx.x, blockIdx.y, 0);
+}
+
 static void check_args(const GemmArgs& g) {
   if (g.M < 0 || g.N < 0 || g.K < 0 || g.batch < 0) throw std::runtime_error("gemm: negative size");
   if (g.kin <= 0 || g.kin % BK != 0) throw std::runtime_error("gemm: inner K block must be a multiple of 16");
@@ -289,6 +303,36 @@ void gemm(const GemmArgs& g, const T* A, const T* B, T* C, bool a_kcontig, bool 
 #undef LAUNCH
   HIPCHECK(hipGetLastError());
 }
+
+template <typename T>
+void gemm_grouped(const GemmGroup<T>* dev_groups, const std::vector<GemmGroup<T>>& host_groups, hipStream_t s) {
+  if (host_groups.empty()) return;
+  constexpr long long VW = 16 / sizeof(T);
+  int mt = 0, nt = 0;
+  bool vec = true;
+  for (const GemmGroup<T>& G : host_groups) {
+    const GemmArgs& g = G.g;
+    check_args(g);
+    if (g.batch != 1) throw std::runtime_error("gemm_grouped: one batch per problem");
+    if (g.kmode != 0 || g.skip) throw std::runtime_error("gemm_grouped: dense problems only");
+    if (g.M > 0 && g.N > 0 && g.K > 0 && (!G.A || !G.B || !G.C)) throw std::runtime_error("gemm_grouped: null operand");
+    mt = std::max(mt, (g.M + BM - 1) / BM);
+    nt = std::max(nt, (g.N + BN - 1) / BN);
+    vec = vec && ((uintptr_t)G.A % 16 == 0) && ((uintptr_t)G.B % 16 == 0) && g.sAm % VW == 0 && g.sBkk % VW == 0 &&
+          g.kin % GemmCfg<T>::RUN == 0 && g.sAkk == 1 && g.sBn == 1;
+    if (g.sAkk != 1 || g.sBn != 1) throw std::runtime_error("gemm_grouped: row-major operands only");
+  }
+  if (mt == 0 || nt == 0) return;
+  if (nt > 65535 || host_groups.size() > 65535) throw std::runtime_error("gemm_grouped: grid too large");
+  dim3 grid(mt, nt, (unsigned)host_groups.size());
+  if (vec)
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, true, true, true>), grid, dim3(256), 0, s, dev_groups);
+  else
+    hipLaunchKernelGGL((gemm_grouped_kernel<T, true, true, false>), grid, dim3(256), 0, s, dev_groups);
+  HIPCHECK(hipGetLastError());
+}
+template void gemm_grouped<double>(const GemmGroup<double>*, const std::vector<GemmGroup<double>>&, hipStream_t);
+template void gemm_grouped<float>(const GemmGroup<float>*, const std::vector<GemmGroup<float>>&, hipStream_t);
 
 template void gemm<double>(const GemmArgs&, const double*, const double*, double*, bool, bool, hipStream_t);
 template void gemm<float>(const GemmArgs&, const float*, const float*, float*, bool, bool, hipStream_t);
