@@ -121,6 +121,12 @@ int tt_get_mps(void* ctx, int* r, double* const* U, int32_t* const* q);
 /* <U|H|U> / <U|U> of the current iterate. */
 int tt_energy(void* ctx, double* E);
 
+/* Keeps a device copy of the current iterate (op 0) or makes the kept copy the
+ * current iterate again (op 1), without a host round trip: repeated global
+ * iterations from one state.  TT_ESTATE if there is nothing to keep/restore
+ * or the kept iterate does not fit the MPO; TT_EINVAL for another op. */
+int tt_mps_checkpoint(void* ctx, int op);
+
 /* Steps 1-2 of Algorithm 2: LQ sweep with saved orthogonal copies and
  * environment caches, then the local solves of nsub subdomains of lengths[]
  * sites (sum = L); subdomain j sweeps its bonds left to right, the last one
@@ -201,9 +207,14 @@ int tt_energy_mpo_grad(void* ctx, double* E, double* const* gops);
 
 /* Per-kernel timing of the effective-Hamiltonian products (HIP events on the
  * library stream).  enable != 0 turns recording on for subsequent products.
- * stats (may be NULL) receives 4 rows [ms, launches, algorithmic flops,
- * algorithmic bytes] for: L.x GEMM, site-1 mix, site-2 mix, R GEMM, with true
- * (unpadded) sizes; reset != 0 clears the accumulators after copying. */
+ * stats (may be NULL) receives TT_KT_SLOTS rows [ms, launches, algorithmic
+ * flops, algorithmic bytes] for the kernels: 0 L.x GEMM; 1, 2, 3 site-1 mix
+ * (gather of the rows with few operator entries, GEMM of the rows with many,
+ * scatter of those); 4, 5, 6 the same for site 2; 7 R GEMM; 8 its K-split
+ * reduction.  Algorithmic work counts only the quantum-number-allowed blocks
+ * (block-sparse product) and each operand element moved once.  reset != 0
+ * clears the accumulators after copying. */
+#define TT_KT_SLOTS 9
 int tt_kernel_timing(void* ctx, int enable, double* stats, int reset);
 
 #ifdef __cplusplus

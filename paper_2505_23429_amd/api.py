@@ -162,18 +162,26 @@ class Context:
             "phase_seconds": list(rep.phase_seconds),
         }
 
+    def checkpoint(self, restore=False):
+        """Keep a device copy of the current iterate, or make the kept copy current again."""
+        self._check(self.lib.tt_mps_checkpoint(self.h, 1 if restore else 0))
+
     def dmrg2(self, nsweeps):
         E = np.zeros(2 * nsweeps)
         rc = self._check(self.lib.tt_dmrg2(self.h, nsweeps, E.ctypes.data_as(C.POINTER(C.c_double))))
         return E, rc
 
+    KERNELS = ("gemm_Lx", "mix1_gather", "mix1_heavy_gemm", "mix1_heavy_scatter", "mix2_gather",
+               "mix2_heavy_gemm", "mix2_heavy_scatter", "gemm_R", "gemm_R_reduce")
+
     def kernel_timing(self, enable=True, reset=False):
-        """Per-kernel stats of the products: rows (Lx GEMM, mix 1, mix 2, R GEMM),
+        """Per-kernel stats of the products: one row per entry of KERNELS,
         columns (ms, launches, algorithmic flops, algorithmic bytes)."""
-        st = np.zeros(16)
+        n = len(self.KERNELS)
+        st = np.zeros(4 * n)
         self._check(self.lib.tt_kernel_timing(self.h, int(enable), st.ctypes.data_as(C.POINTER(C.c_double)),
                                               int(reset)))
-        return st.reshape(4, 4)
+        return st.reshape(n, 4)
 
     def mpo_gradient(self, mpo):
         """dE/dW for every MPO entry of E = <U|H|U> (normalised current iterate)."""

@@ -34,6 +34,8 @@ struct BsHeavy { int g, H, Nin, Nin4, cols, ld; long long in_base, w_off, tmp_of
 struct BsMix {
   int ntiles = 0, nhtiles = 0;
   double flops = 0.0, nin = 0.0, nout = 0.0;  // algorithmic flops; elements read and written once
+  // per kernel: gather of the light rows, GEMM and scatter of the heavy rows (flops, elements)
+  double fl_light = 0.0, el_light = 0.0, fl_heavy = 0.0, el_heavy = 0.0, el_scatter = 0.0;
   long long ntmp = 0;                         // staging elements of the heavy rows
   std::vector<BsHeavy> heavy;
   DevMem tiles, groups, optr, ocol, oval64, oval32, orow, spec;
@@ -47,6 +49,7 @@ struct BsPlan {
   long long n1 = 0, n2 = 0, n3 = 0, nrs = 0;  // elements of T1, T2, T3 and the stacked R
   double flops1 = 0.0, flops4 = 0.0;          // block-sparse flops of stages 1 and 4
   double bytes1 = 0.0, bytes4 = 0.0;          // element counts moved once by stages 1 and 4
+  double el_red = 0.0;                        // elements moved by the stage-4 reduction
   // stage 1
   int ntiles1 = 0;
   DevMem tiles1, alpha, rsrc, rinfo, cinfo, rowpart1, specoff, nbeta, boff;

@@ -336,6 +336,7 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
   m.heavy.clear();
   m.ntmp = 0;
   m.flops = m.nin = m.nout = 0.0;
+  m.fl_light = m.el_light = m.fl_heavy = m.el_heavy = m.el_scatter = 0.0;
   for (int g = 0; g < ng; ++g) {
     groups[g] = BsGroup{in_off[g], cols[g], spec0[g], nspec[g], ldg[g]};
     const int r0 = (int)orow.size();
@@ -373,6 +374,10 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
     m.nin += (double)nrows_in[g] * cols[g];
     m.nout += (double)(r1 - r0 + (int)hro.size()) * cols[g];
     m.flops += 2.0 * (double)nnz_g * cols[g];
+    if (r1 > r0) {
+      m.fl_light += 2.0 * (double)nnz_g * cols[g];
+      m.el_light += (double)(nrows_in[g] + (r1 - r0)) * cols[g];
+    }
     if (r1 > r0)
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
         for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
@@ -387,6 +392,9 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
       }
       m.ntmp += (long long)H * ldg[g];
       m.flops += 2.0 * (double)H * Nin * cols[g];
+      m.fl_heavy += 2.0 * (double)H * Nin * cols[g];
+      m.el_heavy += (double)H * Nin + (double)Nin * cols[g] + (double)H * cols[g];
+      m.el_scatter += 2.0 * (double)H * cols[g];
       m.heavy.push_back(hv);
       const int q1 = (int)horow.size();
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
@@ -574,6 +582,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   int slots = 0;
   p.flops4 = 0.0;
   p.bytes4 = 0.0;
+  p.el_red = 0.0;
   for (int bp = 0; bp < nbe; ++bp) {
     const int row0 = (int)rowdst.size();
     int M = 0;
@@ -598,6 +607,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
             ++slots;
             ++r.nsplit;
           }
+          p.el_red += (double)(r.nsplit + 1) * std::min(TILE, M - m0) * std::min(TILE, N - n0);
           red.push_back(r);
         }
     }
@@ -655,10 +665,33 @@ template <>
 const DevMem& heavy_vals<float>(const BsMix& m) { return m.hw32; }
 
 // light rows gathered, heavy rows through the GEMM and a scatter pass
+// descriptors of the heavy-row GEMMs of one mix (staging buffer E.bs_tmp, sized beforehand)
+template <typename T>
+static std::vector<GemmGroup<T>> heavy_groups(Engine& E, const BsMix& m, const T* in, long long nin) {
+  std::vector<GemmGroup<T>> gg;
+  const T* W = heavy_vals<T>(m).template as<T>();
+  T* tmp = E.bs_tmp.as<T>();
+  for (const BsHeavy& h : m.heavy) {
+    if (h.in_base < 0 || h.in_base + (long long)h.Nin * h.ld > nin)
+      throw std::runtime_error("block-sparse product: heavy rows read outside their group");
+    GemmGroup<T> G{};
+    G.g.M = h.H; G.g.N = h.cols; G.g.K = h.Nin; G.g.batch = 1; G.g.kin = ((h.Nin + 15) / 16) * 16;
+    G.g.sAm = h.Nin4; G.g.sAkk = 1;
+    G.g.sBkk = h.ld; G.g.sBn = 1;
+    G.g.sCm = h.ld; G.g.alpha = 1.0; G.g.beta = 0.0;
+    G.A = W + h.w_off;
+    G.B = in + h.in_base;
+    G.C = tmp + h.tmp_off;
+    gg.push_back(G);
+  }
+  return gg;
+}
+
 template <typename T, int MODE>
 static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, long long nin, T* out, long long nout,
-                    int* err, bool rnd) {
+                    int* err, bool rnd, const std::vector<GemmGroup<T>>& gg, const DevMem& gdev) {
   hipStream_t s = E.stream;
+  const int slot0 = MODE == 1 ? 1 : 4;
   if (m.ntiles > 0) {
     hipLaunchKernelGGL((mix_kernel<T, MODE>), dim3(m.ntiles), dim3(MIX_COLS), 0, s, m.tiles.as<int4>(),
                        m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
@@ -668,27 +701,11 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
                        rnd ? 1 : 0, (const long long*)nullptr, (const T*)nullptr);
     BSCHECK(hipGetLastError());
   }
+  E.kt_mark(slot0);
   if (m.nhtiles > 0) {
-    E.bs_tmp.ensure(sizeof(T) * std::max<long long>(m.ntmp, 1));
     T* tmp = E.bs_tmp.as<T>();
-    const T* W = heavy_vals<T>(m).template as<T>();
-    std::vector<GemmGroup<T>> gg;
-    for (const BsHeavy& h : m.heavy) {
-      if (h.in_base < 0 || h.in_base + (long long)h.Nin * h.ld > nin)
-        throw std::runtime_error("block-sparse product: heavy rows read outside their group");
-      GemmGroup<T> G{};
-      G.g.M = h.H; G.g.N = h.cols; G.g.K = h.Nin; G.g.batch = 1; G.g.kin = ((h.Nin + 15) / 16) * 16;
-      G.g.sAm = h.Nin4; G.g.sAkk = 1;
-      G.g.sBkk = h.ld; G.g.sBn = 1;
-      G.g.sCm = h.ld; G.g.alpha = 1.0; G.g.beta = 0.0;
-      G.A = W + h.w_off;
-      G.B = in + h.in_base;
-      G.C = tmp + h.tmp_off;
-      gg.push_back(G);
-    }
-    DevMem gdev;
-    upload(gdev, gg.data(), gg.size() * sizeof(GemmGroup<T>), s);
-    gemm_grouped<T>(gdev.as<GemmGroup<T>>(), gg, s);
+    gemm_grouped<T>(gdev.template as<GemmGroup<T>>(), gg, s);
+    E.kt_mark(slot0 + 1);
     hipLaunchKernelGGL((mix_kernel<T, MODE>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<int4>(),
                        m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
                        m.horow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,
@@ -696,6 +713,7 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
                        p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
                        rnd ? 1 : 0, m.hbase.as<long long>(), (const T*)tmp);
     BSCHECK(hipGetLastError());
+    E.kt_mark(slot0 + 2);
   }
 }
 
@@ -731,7 +749,13 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
     have = true;
   }
   fill(y, sizeof(T) * ny, s);
-  E.kt_mark(0);
+  // heavy-row GEMM descriptors uploaded before the timed kernels
+  E.bs_tmp.ensure(sizeof(T) * std::max<long long>(std::max(p.m1.ntmp, p.m2.ntmp), 1));
+  const std::vector<GemmGroup<T>> gg1 = heavy_groups<T>(E, p.m1, E.bs_t1.as<T>(), p.n1);
+  const std::vector<GemmGroup<T>> gg2 = heavy_groups<T>(E, p.m2, E.bs_t2.as<T>(), p.n2);
+  if (!gg1.empty()) upload(E.bs_gg1, gg1.data(), gg1.size() * sizeof(GemmGroup<T>), s);
+  if (!gg2.empty()) upload(E.bs_gg2, gg2.data(), gg2.size() * sizeof(GemmGroup<T>), s);
+  E.kt_begin();
   if (p.ntiles1 > 0) {
     hipLaunchKernelGGL((stage1_kernel<T>), dim3(p.ntiles1), dim3(256), 0, s, p.tiles1.as<int4>(),
                        p.alpha.as<BsAlpha>(), p.rsrc.as<long long>(), p.rinfo.as<int4>(), p.cinfo.as<int4>(),
@@ -740,29 +764,31 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
                        p.n1, err);
     BSCHECK(hipGetLastError());
   }
-  E.kt_mark(1);
-  run_mix<T, 1>(E, p, p.m1, E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2, err, false);
-  E.kt_mark(2);
-  run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3);
-  E.kt_mark(3);
+  E.kt_mark(0);
+  run_mix<T, 1>(E, p, p.m1, E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2, err, false, gg1, E.bs_gg1);
+  run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3, gg2, E.bs_gg2);
   if (p.ntiles4 > 0) {
     hipLaunchKernelGGL((stage4_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
                        E.bs_t3.as<T>(), p.n3, rs.as<T>(), p.nrs, E.bs_part.as<T>(), err);
     BSCHECK(hipGetLastError());
+    E.kt_mark(7);
     hipLaunchKernelGGL((reduce4_kernel<T>), dim3(p.nred), dim3(256), 0, s, p.red.as<BsRedTile>(),
                        E.bs_part.as<T>(), p.rowdst.as<long long>(), y, (long long)ny, err);
     BSCHECK(hipGetLastError());
+    E.kt_mark(8);
   }
-  E.kt_mark(4);
   int herr = 0;
   BSCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
   BSCHECK(hipStreamSynchronize(s));
   if (herr != 0)
     throw std::runtime_error("block-sparse product: index outside its buffer (check " + std::to_string(herr) + ")");
   const double el = (double)sizeof(T);
-  const double fl[4] = {p.flops1, p.m1.flops, p.m2.flops, p.flops4};
-  const double by[4] = {el * p.bytes1, el * (p.m1.nin + p.m1.nout), el * (p.m2.nin + p.m2.nout), el * p.bytes4};
-  E.kt_add(fl, by);
+  const double fl[Engine::KT_SLOTS] = {p.flops1, p.m1.fl_light, p.m1.fl_heavy, 0.0, p.m2.fl_light, p.m2.fl_heavy,
+                                       0.0, p.flops4, 0.0};
+  const double by[Engine::KT_SLOTS] = {el * p.bytes1, el * p.m1.el_light, el * p.m1.el_heavy, el * p.m1.el_scatter,
+                                       el * p.m2.el_light, el * p.m2.el_heavy, el * p.m2.el_scatter, el * p.bytes4,
+                                       el * p.el_red};
+  E.kt_end(fl, by);
 }
 
 template void bs_apply<double>(Engine&, BsPlan&, const double*, const double*, const double*, const double*, double*,

@@ -144,6 +144,13 @@ int tt_coarse_correct(void* ctx, double* S_out, double* A_out, double* coef_out,
   });
 }
 
+int tt_mps_checkpoint(void* ctx, int op) {
+  return guard(ctx, [&](Engine& E) {
+    E.checkpoint(op);
+    return TT_OK;
+  });
+}
+
 int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
   return guard(ctx, [&](Engine& E) {
     if (!lengths || !out) throw std::invalid_argument("NULL argument");
@@ -306,7 +313,7 @@ int tt_heff_energy_grad_dev(void* ctx, int rl, int rr, int RA, int RB, int RC, c
 int tt_kernel_timing(void* ctx, int enable, double* stats, int reset) {
   return guard(ctx, [&](Engine& E) {
     if (stats)
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < TT_KT_SLOTS; ++i)
         for (int j = 0; j < 4; ++j) stats[i * 4 + j] = E.kstat[i][j];
     if (reset)
       for (auto& r : E.kstat)

@@ -435,43 +435,47 @@ struct ScopeTimer {
 };
 }  // namespace
 
-void Engine::kt_mark(int i) {
+void Engine::kt_begin() {
   if (!kt_on) return;
-  if (!kt_ev[i]) HC(hipEventCreate(&kt_ev[i]));
-  HC(hipEventRecord(kt_ev[i], stream));
+  if (!kt_ev[0]) HC(hipEventCreate(&kt_ev[0]));
+  HC(hipEventRecord(kt_ev[0], stream));
+  kt_n = 1;
 }
-void Engine::kt_add(const double fl[4], const double by[4]) {
-  if (!kt_on) return;
-  HC(hipEventSynchronize(kt_ev[4]));
-  float ms[4];
-  for (int i = 0; i < 4; ++i) HC(hipEventElapsedTime(&ms[i], kt_ev[i], kt_ev[i + 1]));
-  for (int i = 0; i < 4; ++i) {
-    kstat[i][0] += ms[i];
-    kstat[i][1] += 1.0;
-    kstat[i][2] += fl[i];
-    kstat[i][3] += by[i];
+void Engine::kt_mark(int slot) {
+  if (!kt_on || kt_n <= 0 || kt_n > KT_SLOTS) return;
+  if (!kt_ev[kt_n]) HC(hipEventCreate(&kt_ev[kt_n]));
+  HC(hipEventRecord(kt_ev[kt_n], stream));
+  kt_slot[kt_n] = slot;
+  ++kt_n;
+}
+void Engine::kt_end(const double* fl, const double* by) {
+  if (!kt_on || kt_n <= 1) return;
+  HC(hipEventSynchronize(kt_ev[kt_n - 1]));
+  bool seen[KT_SLOTS] = {};
+  for (int i = 1; i < kt_n; ++i) {
+    float ms = 0.f;
+    HC(hipEventElapsedTime(&ms, kt_ev[i - 1], kt_ev[i]));
+    const int sl = kt_slot[i];
+    kstat[sl][0] += ms;
+    seen[sl] = true;
   }
+  for (int sl = 0; sl < KT_SLOTS; ++sl)
+    if (seen[sl]) {
+      kstat[sl][1] += 1.0;
+      kstat[sl][2] += fl[sl];
+      kstat[sl][3] += by[sl];
+    }
+  kt_n = 0;
 }
 
-void Engine::kt_finish(int elem, int RB) {
-  if (!kt_on) return;
-  HC(hipEventSynchronize(kt_ev[4]));
-  float ms[4];
-  for (int i = 0; i < 4; ++i) HC(hipEventElapsedTime(&ms[i], kt_ev[i], kt_ev[i + 1]));
-  // algorithmic work with the true (unpadded) sizes of the current window
-  const double rl = cur_rl, rr = cur_rr, slab = rl * 16.0 * rr;
-  const double f1 = 2.0 * cur_RA * rl * rl * 16.0 * rr;
-  const double f4 = 2.0 * 16.0 * rl * rr * rr * cur_RC;
-  const double b1 = (double)elem * slab * (cur_RA + RB);
-  const double b2 = (double)elem * slab * (RB + cur_RC);
-  const double fl[4] = {f1, 0.0, 0.0, f4};
-  const double by[4] = {0.0, b1, b2, 0.0};
-  for (int i = 0; i < 4; ++i) {
-    kstat[i][0] += ms[i];
-    kstat[i][1] += 1.0;
-    kstat[i][2] += fl[i];
-    kstat[i][3] += by[i];
-  }
+// dense-bond work of the dense product (all channels, true sizes)
+static void dense_work(const Engine& E, int elem, int RB, double* fl, double* by) {
+  const double rl = E.cur_rl, rr = E.cur_rr, slab = rl * 16.0 * rr;
+  for (int i = 0; i < Engine::KT_SLOTS; ++i) fl[i] = by[i] = 0.0;
+  fl[0] = 2.0 * E.cur_RA * rl * rl * 16.0 * rr;
+  fl[7] = 2.0 * 16.0 * rl * rr * rr * E.cur_RC;
+  by[1] = (double)elem * slab * (E.cur_RA + RB);
+  by[4] = (double)elem * slab * (RB + E.cur_RC);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,16 +512,16 @@ void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB,
     q1.qo = tabs->qo1.as<int2>(); q1.qi = tabs->qi1.as<int2>(); q1.qc = tabs->qcB;
     q2.qo = tabs->qo2.as<int2>(); q2.qi = tabs->qi2.as<int2>(); q2.qc = tabs->qcC;
   }
-  kt_mark(0);
+  kt_begin();
   gemm<T>(g, Lv, x, T1, true, true, stream);
-  kt_mark(1);
+  kt_mark(0);
   mix<T>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), siteop_ops<T>(w1), T1, slab, T2, slab, rl, 4 * rr, stream,
          tabs ? &q1 : nullptr);
-  kt_mark(2);
+  kt_mark(1);
   T* T3 = ws0.as<T>();
   mix<T>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), siteop_ops<T>(w2), T2, slab, T3, slab, 4 * rl, rr, stream,
          tabs ? &q2 : nullptr);
-  kt_mark(3);
+  kt_mark(4);
   GemmArgs h{};
   h.M = 16 * rl; h.N = rr; h.K = RC * rr; h.batch = 1; h.kin = rr;
   h.sAb = 0; h.sAm = rr; h.sAkb = slab; h.sAkk = 1;
@@ -533,8 +537,12 @@ void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB,
     if (tabs) { h.nkb = nP; h.ktab = tabs->k4tabP.as<int>(); }
     gemm<T>(h, T2 + (long long)P0 * slab, Rtil, y, true, false, stream);
   }
-  kt_mark(4);
-  kt_finish(sizeof(T), RB);
+  kt_mark(7);
+  {
+    double fl[KT_SLOTS], by[KT_SLOTS];
+    dense_work(*this, sizeof(T), RB, fl, by);
+    kt_end(fl, by);
+  }
 }
 template void Engine::heff<double>(int, int, int, const double*, const SiteOp&, int, const SiteOp&, int, const double*,
                                    const double*, double*, const double*, int, int, const WinTabs*);
@@ -578,16 +586,16 @@ void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp&
     q1.qo = tabs->qo1.as<int2>(); q1.qi = tabs->qi1.as<int2>(); q1.qc = tabs->qcB;
     q2.qo = tabs->qo2.as<int2>(); q2.qi = tabs->qi2.as<int2>(); q2.qc = tabs->qcC;
   }
-  kt_mark(0);
+  kt_begin();
   gemm_bf16(g, Lv, x, T1, true, true, stream);
-  kt_mark(1);
+  kt_mark(0);
   mix<float>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), w1.op32.as<float>(), T1, slab, T2, slab, rl, 4 * rr, stream,
              tabs ? &q1 : nullptr);
-  kt_mark(2);
+  kt_mark(1);
   float* T3 = ws0.as<float>();
   mix<float>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), w2.op32.as<float>(), T2, slab, T3, slab, 4 * rl, rr, stream,
              tabs ? &q2 : nullptr);
-  kt_mark(3);
+  kt_mark(4);
   ws2.ensure(sizeof(uint16_t) * slab * std::max(RC, nP));
   uint16_t* T3b = ws2.as<uint16_t>();
   round_bf16(T3, T3b, (size_t)slab * RC, stream);
@@ -607,8 +615,12 @@ void Engine::heff_bf16(int rl, int rr, int RA, const uint16_t* Lv, const SiteOp&
     if (tabs) { h.nkb = nP; h.ktab = tabs->k4tabP.as<int>(); }
     gemm_bf16(h, T3b, Rtil, y, true, false, stream);
   }
-  kt_mark(4);
-  kt_finish(4, RB);
+  kt_mark(7);
+  {
+    double fl[KT_SLOTS], by[KT_SLOTS];
+    dense_work(*this, 4, RB, fl, by);
+    kt_end(fl, by);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1265,6 +1277,33 @@ void Engine::get_mps(int* r, double* const* Uh, int32_t* const* q) {
         q[k][2 * a + 1] = lab[a][1];
       }
     }
+}
+
+void Engine::checkpoint(int op) {
+  auto copy = [&](const std::vector<Core>& from, std::vector<Core>& to) {
+    to.clear();
+    to.resize(from.size());
+    for (size_t k = 0; k < from.size(); ++k) {
+      Core& d = to[k];
+      const Core& s = from[k];
+      d.rl = s.rl; d.rr = s.rr; d.ql = s.ql; d.qr = s.qr;
+      d.d.ensure(s.d.n);
+      HC(hipMemcpyAsync(d.d.p, s.d.p, s.d.n, hipMemcpyDeviceToDevice, stream));
+    }
+    HC(hipStreamSynchronize(stream));
+  };
+  if (op == 0) {
+    if (!have_mps) throw std::logic_error("checkpoint: no iterate to keep");
+    copy(U, Usaved);
+  } else if (op == 1) {
+    if (Usaved.empty()) throw std::logic_error("checkpoint: nothing kept");
+    if ((int)Usaved.size() != L) throw std::logic_error("checkpoint: kept iterate does not fit the MPO");
+    copy(Usaved, U);
+    free_caches();
+    have_mps = true;
+  } else {
+    throw std::invalid_argument("checkpoint: op must be 0 (keep) or 1 (restore)");
+  }
 }
 
 double Engine::energy() {

@@ -126,6 +126,7 @@ class Engine {
   std::vector<Labels> chan_q;          // per bond
   std::vector<DevMem> chan_q_dev;      // per bond, int2
   std::vector<Core> U;                 // current left-orthogonal iterate
+  std::vector<Core> Usaved;            // device copy kept by tt_mps_checkpoint
   bool have_mpo = false, have_mps = false;
 
   // Step 1 products (valid after local_solve)
@@ -156,16 +157,20 @@ class Engine {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;
-  // per-kernel statistics of the effective-Hamiltonian product:
-  // [stage][ms, launches, algorithmic flops, algorithmic bytes]
-  // stage 0 = L.x GEMM, 1 = site-1 mix, 2 = site-2 mix, 3 = R GEMM
+  // per-kernel statistics of the effective-Hamiltonian products (tt_kernel_timing):
+  // kstat[slot] = {ms, launches, algorithmic flops, algorithmic bytes}; slots
+  // 0 L.x GEMM, 1/2/3 site-1 mix (gather, heavy-row GEMM, heavy-row scatter),
+  // 4/5/6 site-2 mix (same), 7 R GEMM, 8 R GEMM K-split reduction
+  static constexpr int KT_SLOTS = TT_KT_SLOTS;
   bool kt_on = false;
-  hipEvent_t kt_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  double kstat[4][4] = {};
+  hipEvent_t kt_ev[KT_SLOTS + 1] = {};
+  int kt_slot[KT_SLOTS + 1] = {};
+  int kt_n = 0;
+  double kstat[KT_SLOTS][4] = {};
   int cur_rl = 0, cur_rr = 0, cur_RA = 0, cur_RC = 0;
-  void kt_mark(int i);
-  void kt_finish(int elem, int RB);
-  void kt_add(const double fl[4], const double by[4]);  // explicit per-stage work of one product
+  void kt_begin();           // start event of one product
+  void kt_mark(int slot);    // closes the interval since the previous event, attributed to slot
+  void kt_end(const double* fl, const double* by);  // per-slot algorithmic work of the product
 
   // setup
   void set_mpo(int L, const int* R, const int* nnz, const int32_t* const* A, const int32_t* const* B,
@@ -173,6 +178,7 @@ class Engine {
   void set_mps(int L, const int* r, const double* const* Uh, const int32_t* const* q);
   void get_mps(int* r, double* const* Uh, int32_t* const* q);
   double energy();
+  void checkpoint(int op);  // 0: keep a device copy of the iterate, 1: make it current again
 
   // algorithm
   void local_solve(int nsub, const int* lengths, double* E, int* mv);
@@ -216,7 +222,7 @@ class Engine {
   DevMem wlow_x, wlow_y, wlow_L, wlow_R, wlow_Rt;
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)
-  DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp;
+  DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp, bs_gg1, bs_gg2;
   DevMem be_t1, be_panel, be_up, be_tmp;  // block-sparse environment-update workspaces
   long long bs_serial = 0, bs_zero_serial = -1;
   int bs_zero_prec = -1;
