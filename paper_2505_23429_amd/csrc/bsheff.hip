@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void stage1_kernel(const int4* __restrict__ ti
 // (rows (B, s2)), MODE 2 into the stage-4 panels (rows (a', s1', s2', i'),
 // columns (C, j)).
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int MODE, bool HEAVY>
 __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
     const int4* __restrict__ tiles, const BsGroup* __restrict__ groups, const int* __restrict__ optr,
     const int* __restrict__ ocol, const T* __restrict__ oval, const int2* __restrict__ orow,
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
   const long long lim = nin - G.in_base - col;  // src[q] valid for 0 <= q < lim
   for (int r = t.z; r < t.w; ++r) {
     T acc = T(0);
-    if (hbase) {
+    if (HEAVY) {
       acc = tmp[hbase[r] + col];  // heavy row: sum formed by the GEMM
     } else {
       const int e1 = optr[r + 1];
@@ -693,20 +693,20 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
   hipStream_t s = E.stream;
   const int slot0 = MODE == 1 ? 1 : 4;
   if (m.ntiles > 0) {
-    hipLaunchKernelGGL((mix_kernel<T, MODE>), dim3(m.ntiles), dim3(MIX_COLS), 0, s, m.tiles.as<int4>(),
+    hipLaunchKernelGGL((mix_kernel<T, MODE, false>), dim3(m.ntiles), dim3(MIX_COLS), 0, s, m.tiles.as<int4>(),
                        m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
                        m.orow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,
                        p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
                        p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
                        rnd ? 1 : 0, (const long long*)nullptr, (const T*)nullptr);
     BSCHECK(hipGetLastError());
+    E.kt_mark(slot0);
   }
-  E.kt_mark(slot0);
   if (m.nhtiles > 0) {
     T* tmp = E.bs_tmp.as<T>();
     gemm_grouped<T>(gdev.template as<GemmGroup<T>>(), gg, s);
     E.kt_mark(slot0 + 1);
-    hipLaunchKernelGGL((mix_kernel<T, MODE>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<int4>(),
+    hipLaunchKernelGGL((mix_kernel<T, MODE, true>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<int4>(),
                        m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
                        m.horow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,
                        p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
@@ -764,7 +764,7 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
                        p.n1, err);
     BSCHECK(hipGetLastError());
   }
-  E.kt_mark(0);
+  if (p.ntiles1 > 0) E.kt_mark(0);
   run_mix<T, 1>(E, p, p.m1, E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2, err, false, gg1, E.bs_gg1);
   run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3, gg2, E.bs_gg2);
   if (p.ntiles4 > 0) {

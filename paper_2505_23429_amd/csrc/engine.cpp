@@ -962,8 +962,56 @@ class SectorSVD {
                                           Ew.as<double>(), B.K, rocblas_outofplace, info.as<int>(), B.cnt));
       std::vector<int> inf(B.cnt);
       d2h(inf.data(), info.p, sizeof(int) * B.cnt, E.stream);
-      for (int v : inf)
-        if (v != 0) throw std::runtime_error("gesvd did not converge");
+      for (int i = 0; i < B.cnt; ++i) {
+        if (inf[i] == 0) continue;
+        // the zero padding can stall the batched bidiagonal QR on some blocks: factor
+        // such a block again at its own size, into its slots of the bin
+        const Blk& bb = blocks[mem[i]];
+        {
+          const int kk = std::min(bb.m, bb.n);
+          DevMem a1, e1, i1;
+          a1.ensure(sizeof(double) * (size_t)bb.m * bb.n);
+          e1.ensure(sizeof(double) * std::max(kk, 1));
+          i1.ensure(sizeof(int));
+          GatherBlk one{0, bb.m, bb.roff, bb.coff, bb.m, bb.n, 0};
+          DevMem odev;
+          upload(odev, &one, sizeof(one), E.stream);
+          gather_blocks(M, ldm, rdev.as<int>(), cdev.as<int>(), odev.as<GatherBlk>(), 1, a1.as<double>(), E.stream);
+          RC(rocsolver_dgesvd(E.blas, rocblas_svect_singular, rocblas_svect_singular, bb.m, bb.n, a1.as<double>(),
+                              bb.m, B.S.as<double>() + (size_t)B.K * i, B.U.as<double>() + (size_t)B.M * B.K * i, B.M,
+                              B.Vt.as<double>() + (size_t)B.K * B.N * i, B.K, e1.as<double>(), rocblas_outofplace,
+                              i1.as<int>()));
+          d2h(&inf[i], i1.p, sizeof(int), E.stream);
+        }
+        if (inf[i] != 0) {
+          const Blk& b = blocks[mem[i]];
+          // describe the input block (the gathered copy was overwritten by the factorisation)
+          std::vector<double> hb((size_t)b.m * b.n);
+          {
+            DevMem tmp;
+            tmp.ensure(sizeof(double) * hb.size());
+            GatherBlk one{0, b.m, b.roff, b.coff, b.m, b.n, 0};
+            DevMem odev;
+            upload(odev, &one, sizeof(one), E.stream);
+            gather_blocks(M, ldm, rdev.as<int>(), cdev.as<int>(), odev.as<GatherBlk>(), 1, tmp.as<double>(),
+                          E.stream);
+            d2h(hb.data(), tmp.p, sizeof(double) * hb.size(), E.stream);
+          }
+          double mx = 0.0;
+          int nonfinite = 0;
+          for (double v : hb) {
+            if (!std::isfinite(v)) ++nonfinite;
+            else mx = std::max(mx, std::fabs(v));
+          }
+          std::string vals;
+          for (size_t q = 0; q < std::min<size_t>(hb.size(), 8); ++q) vals += " " + std::to_string(hb[q]);
+          throw std::runtime_error("gesvd did not converge (info " + std::to_string(inf[i]) + ", block " +
+                                   std::to_string(b.m) + "x" + std::to_string(b.n) + " padded to " +
+                                   std::to_string(B.M) + "x" + std::to_string(B.N) + ", batch " +
+                                   std::to_string(B.cnt) + ", max|a| " + std::to_string(mx) + ", non-finite " +
+                                   std::to_string(nonfinite) + ", first:" + vals + ")");
+        }
+      }
       std::vector<double> hs((size_t)B.K * B.cnt);
       d2h(hs.data(), B.S.p, sizeof(double) * hs.size(), E.stream);
       for (int i = 0; i < B.cnt; ++i) {
