@@ -38,7 +38,7 @@ def workload(idx):
     return w, lengths
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_a2dmrg_L32_chi512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mix2_gather_a2dmrg_L32_chi512.txt")
 KERNEL_SOURCES = ("paper_2505_23429_amd/csrc/bsheff.hip", "paper_2505_23429_amd/csrc/kernels.hip")
 
 

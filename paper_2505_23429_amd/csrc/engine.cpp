@@ -906,11 +906,13 @@ class SectorSVD {
     blocks.clear();
     blocks.resize(ns);
     bins.clear();
-    // all sector indices in one upload; blocks binned by size and padded with zeros to the
-    // bin's largest block: one batched SVD per bin (the top min(m, n) singular triplets of a
-    // zero-padded block are those of the block, the padding rows/columns of its vectors zero)
+    // all sector indices in one upload; blocks binned by size and zero-padded to the bin's
+    // largest block: one batched SVD per bin.  The top min(m, n) singular triplets of a
+    // zero-padded block are those of the block.  Wide blocks (m < n) are factorised
+    // transposed so that every padded matrix is tall: padded wide matrices with few rows
+    // have made the batched bidiagonal QR fail to converge.
     std::vector<int> allr, allc;
-    std::map<int, std::vector<int>> bykey;
+    std::map<long long, std::vector<int>> bykey;
     for (int t = 0; t < ns; ++t) {
       Blk& b = blocks[t];
       b.m = (int)secs[t].rows.size();
@@ -920,6 +922,7 @@ class SectorSVD {
       b.coff = (int)allc.size();
       allr.insert(allr.end(), secs[t].rows.begin(), secs[t].rows.end());
       allc.insert(allc.end(), secs[t].cols.begin(), secs[t].cols.end());
+      b.tr = b.m < b.n;
       int key = 16;
       while (key < std::max(b.m, b.n)) key *= 2;
       bykey[key].push_back(t);
@@ -937,15 +940,18 @@ class SectorSVD {
       Bin& B = bins.back();
       const std::vector<int>& mem = kv.second;
       B.cnt = (int)mem.size();
-      for (int t : mem) { B.M = std::max(B.M, blocks[t].m); B.N = std::max(B.N, blocks[t].n); }
-      B.K = std::min(B.M, B.N);
+      for (int t : mem) {
+        B.M = std::max(B.M, std::max(blocks[t].m, blocks[t].n));
+        B.N = std::max(B.N, std::min(blocks[t].m, blocks[t].n));
+      }
+      B.K = B.N;
       const long long MN = (long long)B.M * B.N;
       B.A.ensure(sizeof(double) * MN * B.cnt);
       fill(B.A.p, sizeof(double) * MN * B.cnt, E.stream);
       std::vector<GatherBlk> gb(B.cnt);
       for (int i = 0; i < B.cnt; ++i) {
         const Blk& b = blocks[mem[i]];
-        gb[i] = GatherBlk{MN * i, B.M, b.roff, b.coff, b.m, b.n, 0};
+        gb[i] = GatherBlk{MN * i, B.M, b.roff, b.coff, b.m, b.n, b.tr ? 1 : 0};
       }
       DevMem gdev;
       upload(gdev, gb.data(), gb.size() * sizeof(GatherBlk), E.stream);
@@ -968,17 +974,17 @@ class SectorSVD {
         // such a block again at its own size, into its slots of the bin
         const Blk& bb = blocks[mem[i]];
         {
-          const int kk = std::min(bb.m, bb.n);
+          const int mm = std::max(bb.m, bb.n), nn = std::min(bb.m, bb.n);
           DevMem a1, e1, i1;
-          a1.ensure(sizeof(double) * (size_t)bb.m * bb.n);
-          e1.ensure(sizeof(double) * std::max(kk, 1));
+          a1.ensure(sizeof(double) * (size_t)mm * nn);
+          e1.ensure(sizeof(double) * std::max(nn, 1));
           i1.ensure(sizeof(int));
-          GatherBlk one{0, bb.m, bb.roff, bb.coff, bb.m, bb.n, 0};
+          GatherBlk one{0, mm, bb.roff, bb.coff, bb.m, bb.n, bb.tr ? 1 : 0};
           DevMem odev;
           upload(odev, &one, sizeof(one), E.stream);
           gather_blocks(M, ldm, rdev.as<int>(), cdev.as<int>(), odev.as<GatherBlk>(), 1, a1.as<double>(), E.stream);
-          RC(rocsolver_dgesvd(E.blas, rocblas_svect_singular, rocblas_svect_singular, bb.m, bb.n, a1.as<double>(),
-                              bb.m, B.S.as<double>() + (size_t)B.K * i, B.U.as<double>() + (size_t)B.M * B.K * i, B.M,
+          RC(rocsolver_dgesvd(E.blas, rocblas_svect_singular, rocblas_svect_singular, mm, nn, a1.as<double>(), mm,
+                              B.S.as<double>() + (size_t)B.K * i, B.U.as<double>() + (size_t)B.M * B.K * i, B.M,
                               B.Vt.as<double>() + (size_t)B.K * B.N * i, B.K, e1.as<double>(), rocblas_outofplace,
                               i1.as<int>()));
           d2h(&inf[i], i1.p, sizeof(int), E.stream);
@@ -1017,11 +1023,18 @@ class SectorSVD {
       for (int i = 0; i < B.cnt; ++i) {
         const int t = mem[i];
         Blk& b = blocks[t];
-        b.U = B.U.as<double>() + (size_t)B.M * B.K * i;
-        b.Vt = B.Vt.as<double>() + (size_t)B.K * B.N * i;
+        const double* Ub = B.U.as<double>() + (size_t)B.M * B.K * i;   // B.M x B.K, column-major
+        const double* Vb = B.Vt.as<double>() + (size_t)B.K * B.N * i;  // B.K x B.N, column-major
         b.S = B.S.as<double>() + (size_t)B.K * i;
-        b.ldU = B.M;
-        b.ldV = B.K;
+        if (!b.tr) {
+          // A = U S V^T: U[i][j] = Ub[i + j*M], V^T[j][c] = Vb[j + c*K]
+          b.U = Ub; b.us_i = 1; b.us_j = B.M;
+          b.Vt = Vb; b.vs_j = 1; b.vs_c = B.K;
+        } else {
+          // A^T = U' S V'^T, so A = V' S U'^T: U[i][j] = V'^T[j][i], V^T[j][c] = U'[c][j]
+          b.U = Vb; b.us_i = B.K; b.us_j = 1;
+          b.Vt = Ub; b.vs_j = B.M; b.vs_c = 1;
+        }
         b.hs.assign(hs.begin() + (size_t)B.K * i, hs.begin() + (size_t)B.K * i + b.k);
         for (int q = 0; q < b.k; ++q) trip.push_back({b.hs[q], secs[t].g, t, q});
       }
@@ -1033,13 +1046,8 @@ class SectorSVD {
     });
     std::vector<double> all(trip.size());
     for (size_t i = 0; i < trip.size(); ++i) all[i] = trip[i].s;
-    int keep = truncate ? truncation_keep(all, chi, E.opts.svd_cutoff, E.opts.tie_rel) : (int)all.size();
-    if (!truncate) {
-      // still drop exact zeros
-      keep = 0;
-      for (double s : all)
-        if (s > 0.0) ++keep;
-    }
+    // truncate: R7 rule; otherwise every singular triplet is kept (orthogonal factorisations)
+    const int keep = truncate ? truncation_keep(all, chi, E.opts.svd_cutoff, E.opts.tie_rel) : (int)all.size();
     SvdOut out;
     for (size_t i = keep; i < all.size(); ++i) out.discarded += all[i] * all[i];
     std::vector<int> cnt(secs.size(), 0);
@@ -1062,7 +1070,8 @@ class SectorSVD {
   void scatter(double* left, long long ldl, double* right, long long ldr, int mode) {
     std::vector<ScatterBlk> sb;
     for (const Blk& b : blocks)
-      if (b.t > 0) sb.push_back(ScatterBlk{b.U, b.Vt, b.S, b.ldU, b.ldV, b.roff, b.coff, b.m, b.n, b.t, b.off});
+      if (b.t > 0)
+        sb.push_back(ScatterBlk{b.U, b.Vt, b.S, b.us_i, b.us_j, b.vs_j, b.vs_c, b.roff, b.coff, b.m, b.n, b.t, b.off});
     if (!sb.empty()) {
       DevMem sdev;
       upload(sdev, sb.data(), sb.size() * sizeof(ScatterBlk), E.stream);
@@ -1075,7 +1084,9 @@ class SectorSVD {
  private:
   Engine& E;
   struct Blk {
-    int m = 0, n = 0, k = 0, t = 0, off = 0, roff = 0, coff = 0, ldU = 0, ldV = 0;
+    int m = 0, n = 0, k = 0, t = 0, off = 0, roff = 0, coff = 0;
+    bool tr = false;                  // factorised transposed (wide block)
+    long long us_i = 0, us_j = 0, vs_j = 0, vs_c = 0;  // element strides of U and V^T
     const double* U = nullptr;
     const double* Vt = nullptr;
     const double* S = nullptr;
@@ -2070,11 +2081,19 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
     std::vector<double> op{1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
     build_siteop(ident, 1, o, i, op, stream);
   }
+  // the same chain through the block-sparse update (one neutral channel)
+  BsSiteUse ident_use;
+  if (opts.qn_skip) bs_site_use(*this, ident_use, ident, {Q2{0, 0}}, {Q2{0, 0}}, +1);
   auto ov_left = [&](const Env& in, const Core& bra, const Core& ket, Env& out) {
     ScopeTimer tm(*this, t_ov, n_ov);
     Env o;
     o.R = 1; o.rb = bra.rr; o.rk = ket.rr;
     o.d.ensure(sizeof(double) * o.elems());
+    if (opts.qn_skip && in.rb == bra.rl && in.rk == ket.rl &&
+        bs_env(*this, ident_use, in.d.as<double>(), bra, ket, o.d.as<double>())) {
+      out = std::move(o);
+      return;
+    }
     env_left_raw(padr(in.rb), padr(in.rk), bra.rrp(), ket.rrp(), 1, in.d.as<double>(), bra.d.as<double>(),
                  ket.d.as<double>(), ident, 1, o.d.as<double>());
     out = std::move(o);

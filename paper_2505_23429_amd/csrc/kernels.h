@@ -103,14 +103,21 @@ void copy3d(const double* src, long long s0, long long s1, double* dst, long lon
             int n2, double alpha, hipStream_t s);
 
 // Batched block gather / scatter of the sector-wise factorisations.
-// gather: dst[b.dst + j*b.ld + i] = M[rows[b.roff+i]*ldm + cols[b.coff+j]]  (column-major blocks)
-struct GatherBlk { long long dst; int ld, roff, coff, m, n, pad; };
+// gather: dst[b.dst + j*b.ld + i] = M[rows[b.roff+i]*ldm + cols[b.coff+j]]  (column-major blocks);
+// with b.trans the block is stored transposed: dst[b.dst + i*b.ld + j] for i < m, j < n
+struct GatherBlk { long long dst; int ld, roff, coff, m, n, trans; };
 void gather_blocks(const double* M, long long ldm, const int* rows, const int* cols, const GatherBlk* blks, int nblk,
                    double* dst, hipStream_t s);
 // scatter of kept factors: for block b with t kept vectors starting at bond index off,
-//   left [rows[roff+i]*ldl + off + j] = U[i + j*ldU] * (mode == 1 ? S[j] : 1)      i < m, j < t
-//   right[(off + j)*ldr + cols[coff+c]] = Vt[j + c*ldV] * (mode == 0 ? S[j] : 1)   j < t, c < n
-struct ScatterBlk { const double* U; const double* Vt; const double* S; int ldU, ldV, roff, coff, m, n, t, off; };
+//   left [rows[roff+i]*ldl + off + j] = U[i*us_i + j*us_j] * (mode == 1 ? S[j] : 1)      i < m, j < t
+//   right[(off + j)*ldr + cols[coff+c]] = Vt[j*vs_j + c*vs_c] * (mode == 0 ? S[j] : 1)   j < t, c < n
+struct ScatterBlk {
+  const double* U;
+  const double* Vt;
+  const double* S;
+  long long us_i, us_j, vs_j, vs_c;
+  int roff, coff, m, n, t, off;
+};
 void scatter_factors(const ScatterBlk* blks, int nblk, const int* rows, const int* cols, double* left, long long ldl,
                      double* right, long long ldr, int mode, hipStream_t s);
 

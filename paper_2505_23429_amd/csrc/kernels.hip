@@ -706,7 +706,8 @@ __global__ void gather_blocks_kernel(const double* __restrict__ M, long long ldm
   const GatherBlk b = blks[blockIdx.x];
   for (int e = threadIdx.x; e < b.m * b.n; e += blockDim.x) {
     const int j = e / b.m, i = e - j * b.m;
-    dst[b.dst + (long long)j * b.ld + i] = M[(long long)rows[b.roff + i] * ldm + cols[b.coff + j]];
+    const long long d = b.trans ? b.dst + (long long)i * b.ld + j : b.dst + (long long)j * b.ld + i;
+    dst[d] = M[(long long)rows[b.roff + i] * ldm + cols[b.coff + j]];
   }
 }
 void gather_blocks(const double* M, long long ldm, const int* rows, const int* cols, const GatherBlk* blks, int nblk,
@@ -720,7 +721,7 @@ __global__ void scatter_left_kernel(const ScatterBlk* __restrict__ blks, const i
   const ScatterBlk b = blks[blockIdx.x];
   for (int e = threadIdx.x; e < b.m * b.t; e += blockDim.x) {
     const int j = e / b.m, i = e - j * b.m;
-    double v = b.U[i + (long long)j * b.ldU];
+    double v = b.U[i * b.us_i + j * b.us_j];
     if (mode == 1) v *= b.S[j];
     left[(long long)rows[b.roff + i] * ldl + b.off + j] = v;
   }
@@ -730,7 +731,7 @@ __global__ void scatter_right_kernel(const ScatterBlk* __restrict__ blks, const 
   const ScatterBlk b = blks[blockIdx.x];
   for (int e = threadIdx.x; e < b.t * b.n; e += blockDim.x) {
     const int c = e / b.t, j = e - c * b.t;
-    double v = b.Vt[j + (long long)c * b.ldV];
+    double v = b.Vt[j * b.vs_j + c * b.vs_c];
     if (mode == 0) v *= b.S[j];
     right[(long long)(b.off + j) * ldr + cols[b.coff + c]] = v;
   }
