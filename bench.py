@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dav-maxiter", type=int, default=0)
     ap.add_argument("--chi", type=int, default=0)
+    ap.add_argument("--sub-workers", type=int, default=0,
+                    help="concurrent subdomain solves (0: the library default of 4; 1: one after another)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the sweep, run a plain elementwise copy of 1 GiB (FP32) three times: the known-size "
                          "kernel that calibrates the HBM byte counters")
@@ -152,7 +154,8 @@ def main():
     prec = w.matvec_prec
     tol = w.dav_tol if prec == "f64" else 1e-5
     ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=args.dav_maxiter or 40, dav_maxsub=24, matvec_prec=prec,
-                  refine_fp64=False)
+                  refine_fp64=False, sub_workers=args.sub_workers)
+    workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
     # host -> device hand-over (PCIe) and device left-orthogonalisation: outside the timed region
     torch.cuda.synchronize()
@@ -218,7 +221,8 @@ def main():
         "dtype": prec, "data": "synthetic",
         "config": {"workload": w.name, "L": w.L, "n_elec": w.n_elec, "chi": chi, "subdomains": lengths,
                    "matvec": prec, "rayleigh_ritz": "f64", "coarse": "f64", "dav_tol": tol,
-                   "integrals_seed": w.seed, "mps_seed": w.seed + 1, "parallelism": "single-gpu"},
+                   "integrals_seed": w.seed, "mps_seed": w.seed + 1, "parallelism": "single-gpu",
+                   "concurrent_subdomain_solves": workers},
         "heff_tflops_dense_equiv": round(fl / max(sh, 1e-12) / 1e12, 3),
         "heff_dense_flops_per_sweep": fl / args.steps,
         "heff_tflops_block_sparse": round(float(stats[:, 2].sum()) / max(heff_ms * 1e-3, 1e-12) / 1e12, 3),
@@ -228,13 +232,14 @@ def main():
         "E_after": reps[-1]["E_after"], "lambda": reps[-1]["lambda"], "E_before": reps[-1]["E_before"],
         "roofline": roof, "kernels": breakdown,
         "phases_s": {k: round(sum(r["phase_seconds"][i] for r in reps) / args.steps, 3) for i, k in enumerate(
-            ("lq", "env_step1", "window_setup", "davidson", "split", "env_sweep", "coarse", "compress"))},
+            ("lq", "env_step1", "window_setup", "davidson", "split", "env_sweep", "coarse", "compress",
+             "step2_wall"))},
     }
     out["set_mps_s"] = round(t_upload, 3)
     if args.fp64_compare and prec != "f64":
         # the same sweep with FP64 products on the same GPU (same input, same solver settings)
         ctx64 = Context(chi=chi, dav_tol=tol, dav_maxiter=args.dav_maxiter or 40, dav_maxsub=24,
-                        matvec_prec="f64", refine_fp64=False)
+                        matvec_prec="f64", refine_fp64=False, sub_workers=args.sub_workers)
         ctx64.set_mpo(mpo)
         ctx64.set_mps(cores, labels)
         torch.cuda.synchronize()

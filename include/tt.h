@@ -69,6 +69,10 @@ typedef struct tt_opts {
   int device;         /* HIP device ordinal */
   int qn_skip;        /* 1: skip the exact zeros of the quantum-number blocks in the
                          effective-Hamiltonian product and environment updates */
+  int sub_workers;    /* Step 2 (Algorithm 2): the subdomain solves are independent and run
+                         concurrently on this many workers, each a host thread with its own
+                         HIP stream, rocBLAS handle and workspaces; 0 = 4, 1 = one after
+                         another on the context's stream.  Results do not depend on it. */
 } tt_opts;
 
 #define TT_MAX_SUB 64
@@ -88,9 +92,11 @@ typedef struct tt_sweep_report {
   double seconds[4];               /* wall time of Steps 1..4 */
   double flops_heff;               /* dense-bond flops of all effective-Hamiltonian products */
   double seconds_heff;             /* device time of those products (HIP events) */
-  double phase_seconds[8];         /* wall time: LQ sweep, step-1 environments, window set-up,
+  double phase_seconds[9];         /* wall time: LQ sweep, step-1 environments, window set-up,
                                       Davidson, two-site splits, subdomain environment updates,
-                                      coarse matrices, coarse solve + compression */
+                                      coarse matrices, coarse solve + compression, all subdomain
+                                      solves; with concurrent solves entries 2-5 are summed over
+                                      the workers */
 } tt_sweep_report;
 
 void tt_default_opts(tt_opts* o);

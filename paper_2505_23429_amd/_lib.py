@@ -30,6 +30,7 @@ class Opts(C.Structure):
         ("chi_max", C.c_int), ("svd_cutoff", C.c_double), ("tie_rel", C.c_double), ("dav_tol", C.c_double),
         ("dav_maxiter", C.c_int), ("dav_maxsub", C.c_int), ("coarse_eps", C.c_double), ("matvec_prec", C.c_int),
         ("refine_fp64", C.c_int), ("lowprec_tol", C.c_double), ("device", C.c_int), ("qn_skip", C.c_int),
+        ("sub_workers", C.c_int),
     ]
 
 
@@ -42,7 +43,7 @@ class SweepReport(C.Structure):
         ("matvecs", C.c_int * TT_MAX_SUB), ("S", C.c_double * _N), ("A", C.c_double * _N),
         ("coef", C.c_double * (TT_MAX_SUB + 1)), ("lambda_", C.c_double), ("rankS", C.c_int),
         ("E_after", C.c_double), ("discarded", C.c_double), ("seconds", C.c_double * 4),
-        ("flops_heff", C.c_double), ("seconds_heff", C.c_double), ("phase_seconds", C.c_double * 8),
+        ("flops_heff", C.c_double), ("seconds_heff", C.c_double), ("phase_seconds", C.c_double * 9),
     ]
 
 

@@ -71,13 +71,14 @@ void tt_default_opts(tt_opts* o) {
   o->lowprec_tol = 1e-5;
   o->device = 0;
   o->qn_skip = 1;
+  o->sub_workers = 0;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
   if (!opts || !out) return TT_EINVAL;
   *out = nullptr;
   if (opts->chi_max <= 0 || opts->dav_maxiter <= 0 || opts->dav_maxsub < 4 || opts->matvec_prec < 0 ||
-      opts->matvec_prec > 2)
+      opts->matvec_prec > 2 || opts->sub_workers < 0 || opts->sub_workers > TT_MAX_SUB)
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);
@@ -184,7 +185,7 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
     out->seconds[3] = 0.0;
     out->flops_heff = E.flops_heff;
     out->seconds_heff = E.sec_heff;
-    for (int i = 0; i < 8; ++i) out->phase_seconds[i] = E.ph[i];
+    for (int i = 0; i < Engine::NPH; ++i) out->phase_seconds[i] = E.ph[i];
     return std::max(st, E.warn);
   });
 }

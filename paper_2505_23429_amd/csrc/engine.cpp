@@ -15,7 +15,10 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <atomic>
+#include <exception>
 #include <mutex>
+#include <thread>
 #include <map>
 #include <stdexcept>
 
@@ -60,6 +63,9 @@ static std::vector<Q2> padded_q(const Labels& q, int n, int sent) {
 // size-keyed free list and reused, so the many short-lived multi-GB
 // environment buffers of a sweep do not go through hipMalloc/hipFree each time.
 namespace {
+// stream of the worker engine driven by this host thread (null: the main thread)
+thread_local hipStream_t tl_stream = nullptr;
+
 class BlockPool {
  public:
   void* get(size_t bytes, size_t& cap) {
@@ -88,8 +94,11 @@ class BlockPool {
     return p;
   }
   void put(void* p, size_t cap) {
-    // work queued on any stream may still read the block
-    (void)hipDeviceSynchronize();
+    // work queued on the releasing thread's stream may still read the block (a
+    // worker thread's blocks are used on its own stream only; other threads wait
+    // for the whole device)
+    if (tl_stream) (void)hipStreamSynchronize(tl_stream);
+    else (void)hipDeviceSynchronize();
     std::lock_guard<std::mutex> g(mu_);
     free_.emplace(cap, p);
     cached_ += cap;
@@ -245,7 +254,9 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double>& w, std
 // ---------------------------------------------------------------------------
 // Engine
 // ---------------------------------------------------------------------------
-Engine::Engine(const tt_opts& o) : opts(o) {
+Engine::Engine(const tt_opts& o)
+    : opts(o), prob(std::make_shared<Problem>()), L(prob->L), mpo(prob->mpo), Rb(prob->Rb), chan_q(prob->chan_q),
+      chan_q_dev(prob->chan_q_dev) {
   const char* v = std::getenv("TT_VERBOSE");
   verbose = v && std::atoi(v) > 0;
   HC(hipSetDevice(o.device));
@@ -255,10 +266,26 @@ Engine::Engine(const tt_opts& o) : opts(o) {
   HC(hipEventCreate(&ev0));
   HC(hipEventCreate(&ev1));
 }
+Engine::Engine(const Engine& parent, int)
+    : opts(parent.opts), prob(parent.prob), L(prob->L), mpo(prob->mpo), Rb(prob->Rb), chan_q(prob->chan_q),
+      chan_q_dev(prob->chan_q_dev) {
+  verbose = parent.verbose;
+  have_mpo = parent.have_mpo;
+  HC(hipSetDevice(opts.device));
+  HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  RC(rocblas_create_handle(&blas));
+  RC(rocblas_set_stream(blas, stream));
+  HC(hipEventCreate(&ev0));
+  HC(hipEventCreate(&ev1));
+}
 Engine::~Engine() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  workers.clear();
   if (blas) rocblas_destroy_handle(blas);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  for (hipEvent_t& ev : kt_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -718,13 +745,19 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
   if (opts.qn_skip) {
     // block-sparse update (coefficient block handled through virtual input channels)
     SiteMPO& sm = mpo[site];
-    if (!sm.bs_left) {
-      std::vector<Q2> din(chan_q[site].begin(), chan_q[site].end());
-      if (sm.has_block)
-        for (int q = sm.q0; q < sm.q1; ++q) din.push_back(chan_q[site + 1][q]);
-      std::vector<Q2> dout(chan_q[site + 1].begin(), chan_q[site + 1].end());
-      sm.bs_left = std::make_shared<BsSiteUse>();
-      bs_site_use(*this, *sm.bs_left, sm.has_block ? sm.byB_left : sm.byB, din, dout, +1);
+    std::shared_ptr<BsSiteUse> use;
+    {
+      std::lock_guard<std::mutex> g(prob->mu);
+      if (!sm.bs_left) {
+        std::vector<Q2> din(chan_q[site].begin(), chan_q[site].end());
+        if (sm.has_block)
+          for (int q = sm.q0; q < sm.q1; ++q) din.push_back(chan_q[site + 1][q]);
+        std::vector<Q2> dout(chan_q[site + 1].begin(), chan_q[site + 1].end());
+        auto u = std::make_shared<BsSiteUse>();
+        bs_site_use(*this, *u, sm.has_block ? sm.byB_left : sm.byB, din, dout, +1);
+        sm.bs_left = u;
+      }
+      use = sm.bs_left;
     }
     const double* Ein = in.d.as<double>();
     if (s.has_block) {
@@ -739,7 +772,7 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
     bool done;
     {
       ScopeTimer tm(*this, t_env_bs, n_env_bs);
-      done = bs_env(*this, *sm.bs_left, Ein, bra, ket, o.d.as<double>());
+      done = bs_env(*this, *use, Ein, bra, ket, o.d.as<double>());
     }
     if (done) {
       out = std::move(o);
@@ -780,13 +813,19 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
   }
   if (opts.qn_skip) {
     SiteMPO& sm = mpo[site];
-    if (!sm.bs_right) {
-      std::vector<Q2> din(chan_q[site + 1].begin(), chan_q[site + 1].end());
-      if (sm.has_block)
-        for (int p = sm.p0; p < sm.p1; ++p) din.push_back(chan_q[site][p]);
-      std::vector<Q2> dout(chan_q[site].begin(), chan_q[site].end());
-      sm.bs_right = std::make_shared<BsSiteUse>();
-      bs_site_use(*this, *sm.bs_right, sm.has_block ? sm.byA_right : sm.byA, din, dout, -1);
+    std::shared_ptr<BsSiteUse> use;
+    {
+      std::lock_guard<std::mutex> g(prob->mu);
+      if (!sm.bs_right) {
+        std::vector<Q2> din(chan_q[site + 1].begin(), chan_q[site + 1].end());
+        if (sm.has_block)
+          for (int p = sm.p0; p < sm.p1; ++p) din.push_back(chan_q[site][p]);
+        std::vector<Q2> dout(chan_q[site].begin(), chan_q[site].end());
+        auto u = std::make_shared<BsSiteUse>();
+        bs_site_use(*this, *u, sm.has_block ? sm.byA_right : sm.byA, din, dout, -1);
+        sm.bs_right = u;
+      }
+      use = sm.bs_right;
     }
     const double* Ein = in.d.as<double>();
     if (s.has_block) {
@@ -801,7 +840,7 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
     bool done;
     {
       ScopeTimer tm(*this, t_env_bs, n_env_bs);
-      done = bs_env(*this, *sm.bs_right, Ein, bra, ket, o.d.as<double>());
+      done = bs_env(*this, *use, Ein, bra, ket, o.d.as<double>());
     }
     if (done) {
       out = std::move(o);
@@ -1900,6 +1939,91 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
 // ---------------------------------------------------------------------------
 // Step 1 + Step 2
 // ---------------------------------------------------------------------------
+void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
+  double tph = 0.0;
+  const int blast = std::min(e, L - 2);
+  S = Sub();
+  S.s = s;
+  S.t = blast + 1;
+  if (s > L - 2) {
+    // a one-site last subdomain has no bond of its own
+    S.t = s;
+    S.mod.clear();
+    Core c;
+    c.rl = src.Wc[s].rl; c.rr = src.Wc[s].rr; c.ql = src.Wc[s].ql; c.qr = src.Wc[s].qr;
+    c.d.ensure(src.Wc[s].d.n);
+    HC(hipMemcpyAsync(c.d.p, src.Wc[s].d.p, src.Wc[s].d.n, hipMemcpyDeviceToDevice, stream));
+    S.mod.push_back(std::move(c));
+    S.E = 0.0;
+    HC(hipStreamSynchronize(stream));
+    return;
+  }
+  Core center;
+  center.rl = src.Wc[s].rl; center.rr = src.Wc[s].rr; center.ql = src.Wc[s].ql; center.qr = src.Wc[s].qr;
+  center.d.ensure(src.Wc[s].d.n);
+  HC(hipMemcpyAsync(center.d.p, src.Wc[s].d.p, src.Wc[s].d.n, hipMemcpyDeviceToDevice, stream));
+  Env Lrun;
+  const Env* Lcur = &src.Lenv[s];
+  DevMem x;
+  for (int b = s; b <= blast; ++b) {
+    const Core& next = src.Vc[b + 1];
+    two_site(*this, center, next, x);
+    Davidson r = local_eig(*this, *Lcur, b, src.Renv[b + 2], x, center, next);
+    S.matvecs += r.matvecs;
+    S.E = r.theta;
+    S.converged = S.converged && r.converged;
+    Core N, C;
+    tph = now();
+    split_two_site(*this, x.as<double>(), center.rl, center.ql, next.rr, next.qr, opts.chi_max, true, N, C);
+    ph[4] += now() - tph;
+    if (b < blast) {
+      tph = now();
+      Env nl;
+      env_left(*Lcur, N, N, b, nl);
+      Lrun = std::move(nl);
+      Lcur = &Lrun;
+      ph[5] += now() - tph;
+    } else {
+      double nc = norm_dev(*this, C.d.as<double>(), C.elems());
+      scale(C.d.as<double>(), 1.0 / nc, C.elems(), stream);
+    }
+    S.mod.push_back(std::move(N));
+    center = std::move(C);
+  }
+  S.mod.push_back(std::move(center));
+  HC(hipStreamSynchronize(stream));
+  if (verbose)
+    std::fprintf(stderr,
+                 "[tt] subdomain %d sites %d..%d: E=%.10f matvecs=%d | products %.2fs, set-up %.2fs, Davidson "
+                 "%.2fs, splits %.2fs, env %.2fs\n",
+                 j, s, e, S.E, S.matvecs, sec_heff, ph[2], ph[3], ph[4], ph[5]);
+}
+
+void Engine::absorb_counters(Engine& w) {
+  for (int i = 0; i < NPH; ++i) {
+    ph[i] += w.ph[i];
+    w.ph[i] = 0.0;
+  }
+  flops_heff += w.flops_heff;
+  sec_heff += w.sec_heff;
+  w.flops_heff = w.sec_heff = 0.0;
+  t_env_bs += w.t_env_bs;
+  t_env_dense += w.t_env_dense;
+  t_ov += w.t_ov;
+  n_env_bs += w.n_env_bs;
+  n_env_dense += w.n_env_dense;
+  n_ov += w.n_ov;
+  w.t_env_bs = w.t_env_dense = w.t_ov = 0.0;
+  w.n_env_bs = w.n_env_dense = w.n_ov = 0;
+  for (int k = 0; k < KT_SLOTS; ++k)
+    for (int c = 0; c < 4; ++c) {
+      kstat[k][c] += w.kstat[k][c];
+      w.kstat[k][c] = 0.0;
+    }
+  warn = std::max(warn, w.warn);
+  w.warn = 0;
+}
+
 void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   if (!have_mpo || !have_mps) throw std::logic_error("local_solve needs the MPO and the TT iterate");
   if (nsub <= 0 || nsub > TT_MAX_SUB) throw std::invalid_argument("bad number of subdomains");
@@ -1971,69 +2095,74 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   ph[1] += now() - tph;
   if (verbose)
     std::fprintf(stderr, "[tt] step 1 done: LQ sweep %.2fs, environments %.2fs\n", ph[0], ph[1]);
-  // Step 2: subdomain sweeps
-  subs.clear(); subs.resize(nsub);
-  int start = 0;
-  for (int j = 0; j < nsub; ++j) {
-    Sub& S = subs[j];
-    const int s = start, e = start + lengths[j] - 1;
-    start += lengths[j];
-    const int blast = std::min(e, L - 2);
-    S.s = s;
-    S.t = blast + 1;
-    if (s > L - 2) {
-      // a one-site last subdomain has no bond of its own
-      S.t = s;
-      S.mod.clear();
-      Core c;
-      c.rl = Wc[s].rl; c.rr = Wc[s].rr; c.ql = Wc[s].ql; c.qr = Wc[s].qr;
-      c.d.ensure(Wc[s].d.n);
-      HC(hipMemcpyAsync(c.d.p, Wc[s].d.p, Wc[s].d.n, hipMemcpyDeviceToDevice, stream));
-      S.mod.push_back(std::move(c));
-      S.E = 0.0;
-      continue;
-    }
-    Core center;
-    center.rl = Wc[s].rl; center.rr = Wc[s].rr; center.ql = Wc[s].ql; center.qr = Wc[s].qr;
-    center.d.ensure(Wc[s].d.n);
-    HC(hipMemcpyAsync(center.d.p, Wc[s].d.p, Wc[s].d.n, hipMemcpyDeviceToDevice, stream));
-    Env Lrun;
-    const Env* Lcur = &Lenv[s];
-    DevMem x;
-    for (int b = s; b <= blast; ++b) {
-      const Core& next = Vc[b + 1];
-      two_site(*this, center, next, x);
-      Davidson r = local_eig(*this, *Lcur, b, Renv[b + 2], x, center, next);
-      S.matvecs += r.matvecs;
-      S.E = r.theta;
-      S.converged = S.converged && r.converged;
-      Core N, C;
-      tph = now();
-      split_two_site(*this, x.as<double>(), center.rl, center.ql, next.rr, next.qr, opts.chi_max, true, N, C);
-      ph[4] += now() - tph;
-      if (b < blast) {
-        tph = now();
-        Env nl;
-        env_left(*Lcur, N, N, b, nl);
-        Lrun = std::move(nl);
-        Lcur = &Lrun;
-        ph[5] += now() - tph;
-      } else {
-        double nc = norm_dev(*this, C.d.as<double>(), C.elems());
-        scale(C.d.as<double>(), 1.0 / nc, C.elems(), stream);
+  // Step 2: the subdomain sweeps are independent of one another (they read the
+  // Step-1 cores and environments only); with several workers each runs on a
+  // worker engine of its own (a host thread and a HIP stream), longest first
+  HC(hipStreamSynchronize(stream));
+  subs.clear();
+  subs.resize(nsub);
+  std::vector<int> first(nsub);
+  for (int j = 0, st = 0; j < nsub; ++j) {
+    first[j] = st;
+    st += lengths[j];
+  }
+  int nw = opts.sub_workers > 0 ? opts.sub_workers : 4;
+  nw = std::max(1, std::min(nw, nsub));
+  const double t2 = now();
+  if (nw == 1) {
+    for (int j = 0; j < nsub; ++j) solve_subdomain(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
+  } else {
+    while ((int)workers.size() < nw) workers.emplace_back(new Engine(*this, (int)workers.size()));
+    // work estimate: sum over the subdomain's bonds of r_left * r_right * (r_left + r_right)
+    std::vector<double> cost(nsub, 0.0);
+    for (int j = 0; j < nsub; ++j)
+      for (int k = first[j]; k < first[j] + lengths[j] && k + 1 < L; ++k) {
+        const double rl = U[k].rl, rr = U[k + 1].rr;
+        cost[j] += rl * rr * (rl + rr);
       }
-      S.mod.push_back(std::move(N));
-      center = std::move(C);
+    std::vector<int> order(nsub);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> errs(nw);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w) {
+      Engine* W = workers[w].get();
+      W->opts = opts;
+      W->kt_on = kt_on;
+      W->verbose = verbose;
+      W->warn = 0;
     }
-    S.mod.push_back(std::move(center));
-    HC(hipStreamSynchronize(stream));
-    if (verbose)
-      std::fprintf(stderr,
-                   "[tt] subdomain %d sites %d..%d: E=%.10f matvecs=%d | products %.2fs, set-up %.2fs, Davidson "
-                   "%.2fs, splits %.2fs, env %.2fs\n",
-                   j, s, e, S.E, S.matvecs, sec_heff, ph[2], ph[3], ph[4], ph[5]);
-    if (Eloc) Eloc[j] = S.E;
-    if (mv) mv[j] = S.matvecs;
+    for (int w = 0; w < nw; ++w) {
+      Engine* W = workers[w].get();
+      th.emplace_back([&, W, w]() {
+        try {
+          HC(hipSetDevice(opts.device));
+          tl_stream = W->stream;
+          for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= nsub) break;
+            const int j = order[i];
+            W->solve_subdomain(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
+          }
+          HC(hipStreamSynchronize(W->stream));
+        } catch (...) {
+          errs[w] = std::current_exception();
+          next.store(nsub);  // the other workers stop after their current subdomain
+          (void)hipStreamSynchronize(W->stream);
+        }
+        tl_stream = nullptr;
+      });
+    }
+    for (auto& t : th) t.join();
+    for (int w = 0; w < nw; ++w) absorb_counters(*workers[w]);
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
+  }
+  ph[8] += now() - t2;
+  for (int j = 0; j < nsub; ++j) {
+    if (Eloc) Eloc[j] = subs[j].E;
+    if (mv) mv[j] = subs[j].matvecs;
   }
   have_local = true;
 }

@@ -9,6 +9,7 @@
 #include <climits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -110,9 +111,23 @@ struct Davidson {
   double theta = 0.0, resid = 0.0;
 };
 
+// The operator and its device tables: shared (read-only during the local solves)
+// between a context and the worker engines that run subdomain solves concurrently.
+struct Problem {
+  int L = 0;
+  std::vector<SiteMPO> mpo;
+  std::vector<int> Rb;                 // bond dims
+  std::vector<Labels> chan_q;          // per bond
+  std::vector<DevMem> chan_q_dev;      // per bond, int2
+  std::mutex mu;                       // guards the lazily built per-site tables
+};
+
 class Engine {
  public:
   explicit Engine(const tt_opts& o);
+  // worker engine: own stream, rocBLAS handle, workspaces and counters; the
+  // problem is the parent's
+  Engine(const Engine& parent, int worker);
   ~Engine();
   tt_opts opts;
   hipStream_t stream = nullptr;
@@ -120,11 +135,12 @@ class Engine {
   std::string err;
 
   // problem
-  int L = 0;
-  std::vector<SiteMPO> mpo;
-  std::vector<int> Rb;                 // bond dims
-  std::vector<Labels> chan_q;          // per bond
-  std::vector<DevMem> chan_q_dev;      // per bond, int2
+  std::shared_ptr<Problem> prob;
+  int& L;
+  std::vector<SiteMPO>& mpo;
+  std::vector<int>& Rb;
+  std::vector<Labels>& chan_q;
+  std::vector<DevMem>& chan_q_dev;
   std::vector<Core> U;                 // current left-orthogonal iterate
   std::vector<Core> Usaved;            // device copy kept by tt_mps_checkpoint
   bool have_mpo = false, have_mps = false;
@@ -142,14 +158,18 @@ class Engine {
   };
   std::vector<Sub> subs;
   bool have_local = false;
+  // worker engines of the concurrent subdomain solves (created on first use)
+  std::vector<std::unique_ptr<Engine>> workers;
 
   // timing / accounting
   double flops_heff = 0.0, sec_heff = 0.0;
   // wall-clock phases of a sweep (seconds, stream synchronised at each boundary):
   // 0 LQ sweep, 1 step-1 environments, 2 window set-up, 3 Davidson, 4 two-site
   // splits, 5 environment updates of the subdomain sweeps, 6 coarse matrices,
-  // 7 coarse eigenproblem and compression
-  double ph[8] = {};
+  // 7 coarse eigenproblem and compression, 8 all subdomain solves (wall clock).
+  // With concurrent solves, 2-5 are summed over the workers.
+  static constexpr int NPH = 9;
+  double ph[NPH] = {};
   double now();
   // verbose-mode counters: environment updates (block-sparse, dense) and overlap updates
   double t_env_bs = 0.0, t_env_dense = 0.0, t_ov = 0.0;
@@ -182,6 +202,10 @@ class Engine {
 
   // algorithm
   void local_solve(int nsub, const int* lengths, double* E, int* mv);
+  // Step 2 for one subdomain (sites s..e): this engine's stream and workspaces,
+  // the Step-1 cores and environments of src
+  void solve_subdomain(const Engine& src, int j, int s, int e, Sub& S);
+  void absorb_counters(Engine& w);  // add a worker's counters to this engine's, clear the worker's
   int coarse_correct(double* S, double* A, double* c, double* lam, double* Eout, int* rank, double* disc);
   void dmrg2(int nsweeps, double* energies);
 
