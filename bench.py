@@ -130,6 +130,9 @@ def main():
                          "kernel that calibrates the HBM byte counters")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="also run the sweep with FP64 products and report the energy difference")
+    ap.add_argument("--converged", action="store_true",
+                    help="local solves to the workload's tolerance with no product cap; low-precision products "
+                         "are followed by FP64 refinement (the precision-split comparison, not the timed sweep)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the additive sweep is measured on a single MI355X "
@@ -153,8 +156,12 @@ def main():
     log(f"setup: MPO R_mid={mpo.R[w.L // 2]} nnz={sum(mpo.nnz())} in {time.perf_counter() - t0:.1f}s")
     prec = w.matvec_prec
     tol = w.dav_tol if prec == "f64" else 1e-5
-    ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=args.dav_maxiter or 40, dav_maxsub=24, matvec_prec=prec,
-                  refine_fp64=False, sub_workers=args.sub_workers)
+    maxiter = args.dav_maxiter or 40
+    refine = False
+    if args.converged:
+        tol, maxiter, refine = w.dav_tol, args.dav_maxiter or 2000, prec != "f64"
+    ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
+                  refine_fp64=refine, sub_workers=args.sub_workers)
     workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
     # host -> device hand-over (PCIe) and device left-orthogonalisation: outside the timed region
@@ -221,6 +228,7 @@ def main():
         "dtype": prec, "data": "synthetic",
         "config": {"workload": w.name, "L": w.L, "n_elec": w.n_elec, "chi": chi, "subdomains": lengths,
                    "matvec": prec, "rayleigh_ritz": "f64", "coarse": "f64", "dav_tol": tol,
+                   "dav_max_products": maxiter, "fp64_refinement": refine,
                    "integrals_seed": w.seed, "mps_seed": w.seed + 1, "parallelism": "single-gpu",
                    "concurrent_subdomain_solves": workers},
         "heff_tflops_dense_equiv": round(fl / max(sh, 1e-12) / 1e12, 3),
@@ -237,8 +245,10 @@ def main():
     }
     out["set_mps_s"] = round(t_upload, 3)
     if args.fp64_compare and prec != "f64":
-        # the same sweep with FP64 products on the same GPU (same input, same solver settings)
-        ctx64 = Context(chi=chi, dav_tol=tol, dav_maxiter=args.dav_maxiter or 40, dav_maxsub=24,
+        # the same sweep with FP64 products on the same GPU (same input, same solver settings);
+        # the measured context's device memory is released first
+        ctx.close()
+        ctx64 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24,
                         matvec_prec="f64", refine_fp64=False, sub_workers=args.sub_workers)
         ctx64.set_mpo(mpo)
         ctx64.set_mps(cores, labels)
@@ -250,6 +260,8 @@ def main():
         log(f"fp64 sweep: {t64:.2f}s E_after={r64['E_after']:.8f}")
         out["fp64_path"] = {"s_per_sweep": round(t64, 4), "speedup": round(t64 / sec, 3),
                             "E_after": r64["E_after"], "dE_after": abs(r64["E_after"] - reps[-1]["E_after"]),
+                            "dlambda": abs(r64["lambda"] - reps[-1]["lambda"]),
+                            "matvecs": int(np.sum(r64["matvecs"])),
                             "dE_local_max": float(np.abs(np.asarray(r64["E_local"]) -
                                                          np.asarray(reps[-1]["E_local"])).max())}
         ctx64.close()

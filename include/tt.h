@@ -65,7 +65,9 @@ typedef struct tt_opts {
   double coarse_eps;  /* keep overlap eigenvalues >= coarse_eps * max (rank-deficient branch) */
   int matvec_prec;    /* tt_prec of the effective-Hamiltonian product */
   int refine_fp64;    /* 1: after a low-precision solve, continue with FP64 products to dav_tol */
-  double lowprec_tol; /* residual tolerance of the low-precision phase before FP64 refinement */
+  double lowprec_tol; /* with refine_fp64: the low-precision phase ends when the residual is
+                         <= lowprec_tol * |Ritz value| (or has stalled at the rounding floor
+                         of the low-precision product); FP64 products then reach dav_tol */
   int device;         /* HIP device ordinal */
   int qn_skip;        /* 1: skip the exact zeros of the quantum-number blocks in the
                          effective-Hamiltonian product and environment updates */

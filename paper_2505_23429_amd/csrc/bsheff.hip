@@ -3,6 +3,8 @@
 // in bsheff.h.
 #include "bsheff.h"
 
+#include <atomic>
+
 #include <algorithm>
 #include <map>
 #include <stdexcept>
@@ -645,7 +647,9 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   up(p.m1.spec, spec, s);
   up(p.m2.spec, spec, s);
   p.have64 = p.have32 = false;
-  p.serial = ++E.bs_serial;
+  // unique over all engines: a workspace is zeroed again whenever it meets a plan it has not seen
+  static std::atomic<long long> plan_serial{0};
+  p.serial = ++plan_serial;
   p.ok = true;
   return true;
 }

@@ -1001,12 +1001,19 @@ class SectorSVD {
       DevMem Ew, info;
       Ew.ensure(sizeof(double) * (size_t)B.K * B.cnt);
       info.ensure(sizeof(int) * B.cnt);
+      const double tb0 = E.verbose ? E.now() : 0.0;
       RC(rocsolver_dgesvd_strided_batched(E.blas, rocblas_svect_singular, rocblas_svect_singular, B.M, B.N,
                                           B.A.as<double>(), B.M, MN, B.S.as<double>(), B.K, B.U.as<double>(), B.M,
                                           (rocblas_stride)B.M * B.K, B.Vt.as<double>(), B.K, (rocblas_stride)B.K * B.N,
                                           Ew.as<double>(), B.K, rocblas_outofplace, info.as<int>(), B.cnt));
       std::vector<int> inf(B.cnt);
       d2h(inf.data(), info.p, sizeof(int) * B.cnt, E.stream);
+      if (E.verbose) {
+        auto& st = E.svd_bins[{B.M, B.N}];
+        st[0] += 1.0;
+        st[1] += B.cnt;
+        st[2] += E.now() - tb0;
+      }
       for (int i = 0; i < B.cnt; ++i) {
         if (inf[i] == 0) continue;
         // the zero padding can stall the batched bidiagonal QR on some blocks: factor
@@ -1768,7 +1775,11 @@ static DevMem build_mask(Engine& E, int rl, const Labels& ql, int rr, const Labe
 
 // Davidson for the lowest eigenpair of the window operator restricted to the
 // QN-allowed entries.  x is the warm start on entry and the eigenvector on exit.
-static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, int prec, double tol, int maxiter) {
+// Stops when the residual of the unit Ritz vector is <= max(tol, rel_tol * |theta|); with
+// stop_on_stall also when it has not dropped below 0.9 x its best value for 8 iterations
+// (a low-precision product has reached its rounding floor).
+static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, int prec, double tol, int maxiter,
+                         double rel_tol = 0.0, bool stop_on_stall = false) {
   Davidson res;
   const size_t n = (size_t)w.rlp * 16 * w.rrp;
   const int maxsub = std::max(4, std::min(E.opts.dav_maxsub, 64));
@@ -1822,6 +1833,8 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     Hs[0] = d[0];
   }
   std::vector<double> evals, evecs, c;
+  double best = HUGE_VAL;
+  int since_best = 0;
   for (int it = 0;; ++it) {
     // Rayleigh-Ritz
     std::vector<double> Hm((size_t)m * m);
@@ -1836,9 +1849,17 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     axpby(t, 1.0, Au, -res.theta, u, n, E.stream);
     res.resid = norm_dev(E, t, n);
     res.iters = it + 1;
-    if (res.resid <= tol) {
+    if (res.resid <= std::max(tol, rel_tol * std::fabs(res.theta))) {
       res.converged = true;
       break;
+    }
+    if (stop_on_stall) {
+      if (res.resid < 0.9 * best) {
+        best = res.resid;
+        since_best = 0;
+      } else if (++since_best >= 8) {
+        break;
+      }
     }
     if (res.matvecs >= maxiter) break;
     if (m >= maxsub) {
@@ -1915,8 +1936,10 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
     prepare_window(E, w, Le, b, Re, prec, ql, qr);
     E.ph[2] += E.now() - tph;
     tph = E.now();
-    const double tol_low = E.opts.refine_fp64 ? std::max(E.opts.lowprec_tol, E.opts.dav_tol) : E.opts.dav_tol;
-    r = davidson(E, w, mask, x.as<double>(), prec, tol_low, E.opts.dav_maxiter);
+    if (E.opts.refine_fp64)
+      r = davidson(E, w, mask, x.as<double>(), prec, E.opts.dav_tol, E.opts.dav_maxiter, E.opts.lowprec_tol, true);
+    else
+      r = davidson(E, w, mask, x.as<double>(), prec, E.opts.dav_tol, E.opts.dav_maxiter);
     if (E.opts.refine_fp64) {
       w.L32.release();
       w.R32.release();
@@ -2024,6 +2047,56 @@ void Engine::absorb_counters(Engine& w) {
   w.warn = 0;
 }
 
+void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::function<void(Engine&, int)>& fn) {
+  int nw = opts.sub_workers > 0 ? opts.sub_workers : 4;
+  nw = std::max(1, std::min(nw, ntask));
+  if (nw == 1) {
+    for (int t = 0; t < ntask; ++t) fn(*this, t);
+    HC(hipStreamSynchronize(stream));
+    return;
+  }
+  // shared inputs were produced on this engine's stream
+  HC(hipStreamSynchronize(stream));
+  while ((int)workers.size() < nw) workers.emplace_back(new Engine(*this, (int)workers.size()));
+  std::vector<int> order(ntask);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  for (int w = 0; w < nw; ++w) {
+    Engine* W = workers[w].get();
+    W->opts = opts;
+    W->kt_on = kt_on;
+    W->verbose = verbose;
+    W->warn = 0;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::exception_ptr> errs(nw);
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; ++w) {
+    Engine* W = workers[w].get();
+    th.emplace_back([&, W, w]() {
+      try {
+        HC(hipSetDevice(opts.device));
+        tl_stream = W->stream;
+        for (;;) {
+          const int i = next.fetch_add(1);
+          if (i >= ntask) break;
+          fn(*W, order[i]);
+        }
+        HC(hipStreamSynchronize(W->stream));
+      } catch (...) {
+        errs[w] = std::current_exception();
+        next.store(ntask);  // the other workers stop after their current task
+        (void)hipStreamSynchronize(W->stream);
+      }
+      tl_stream = nullptr;
+    });
+  }
+  for (auto& t : th) t.join();
+  for (int w = 0; w < nw; ++w) absorb_counters(*workers[w]);
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+}
+
 void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   if (!have_mpo || !have_mps) throw std::logic_error("local_solve needs the MPO and the TT iterate");
   if (nsub <= 0 || nsub > TT_MAX_SUB) throw std::invalid_argument("bad number of subdomains");
@@ -2106,59 +2179,17 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
     first[j] = st;
     st += lengths[j];
   }
-  int nw = opts.sub_workers > 0 ? opts.sub_workers : 4;
-  nw = std::max(1, std::min(nw, nsub));
   const double t2 = now();
-  if (nw == 1) {
-    for (int j = 0; j < nsub; ++j) solve_subdomain(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
-  } else {
-    while ((int)workers.size() < nw) workers.emplace_back(new Engine(*this, (int)workers.size()));
-    // work estimate: sum over the subdomain's bonds of r_left * r_right * (r_left + r_right)
-    std::vector<double> cost(nsub, 0.0);
-    for (int j = 0; j < nsub; ++j)
-      for (int k = first[j]; k < first[j] + lengths[j] && k + 1 < L; ++k) {
-        const double rl = U[k].rl, rr = U[k + 1].rr;
-        cost[j] += rl * rr * (rl + rr);
-      }
-    std::vector<int> order(nsub);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    std::atomic<int> next{0};
-    std::vector<std::exception_ptr> errs(nw);
-    std::vector<std::thread> th;
-    for (int w = 0; w < nw; ++w) {
-      Engine* W = workers[w].get();
-      W->opts = opts;
-      W->kt_on = kt_on;
-      W->verbose = verbose;
-      W->warn = 0;
+  // work estimate: sum over the subdomain's bonds of r_left * r_right * (r_left + r_right)
+  std::vector<double> cost(nsub, 0.0);
+  for (int j = 0; j < nsub; ++j)
+    for (int k = first[j]; k < first[j] + lengths[j] && k + 1 < L; ++k) {
+      const double rl = U[k].rl, rr = U[k + 1].rr;
+      cost[j] += rl * rr * (rl + rr);
     }
-    for (int w = 0; w < nw; ++w) {
-      Engine* W = workers[w].get();
-      th.emplace_back([&, W, w]() {
-        try {
-          HC(hipSetDevice(opts.device));
-          tl_stream = W->stream;
-          for (;;) {
-            const int i = next.fetch_add(1);
-            if (i >= nsub) break;
-            const int j = order[i];
-            W->solve_subdomain(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
-          }
-          HC(hipStreamSynchronize(W->stream));
-        } catch (...) {
-          errs[w] = std::current_exception();
-          next.store(nsub);  // the other workers stop after their current subdomain
-          (void)hipStreamSynchronize(W->stream);
-        }
-        tl_stream = nullptr;
-      });
-    }
-    for (auto& t : th) t.join();
-    for (int w = 0; w < nw; ++w) absorb_counters(*workers[w]);
-    for (auto& e : errs)
-      if (e) std::rethrow_exception(e);
-  }
+  run_tasks(nsub, cost, [&](Engine& W, int j) {
+    W.solve_subdomain(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
+  });
   ph[8] += now() - t2;
   for (int j = 0; j < nsub; ++j) {
     if (Eloc) Eloc[j] = subs[j].E;
@@ -2195,13 +2226,13 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
     A[0] = v;
     S[0] = 1.0;
   }
-  auto overlap_start = [&](int rb, int rk, Env& e) {
+  auto overlap_start = [](Engine& W, int rb, int rk, Env& e) {
     // identity on the bra/ket bond (both left-orthonormal prefixes of U)
     e.R = 1; e.rb = rb; e.rk = rk;
     const int p = padr(rb), q = padr(rk);
     std::vector<double> h((size_t)p * q, 0.0);
     for (int i = 0; i < std::min(rb, rk); ++i) h[(size_t)i * q + i] = 1.0;
-    upload(e.d, h.data(), h.size() * sizeof(double), stream);
+    upload(e.d, h.data(), h.size() * sizeof(double), W.stream);
   };
   // overlap chains use a one-channel identity "MPO" through the same kernels
   SiteOp ident;
@@ -2213,83 +2244,84 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   // the same chain through the block-sparse update (one neutral channel)
   BsSiteUse ident_use;
   if (opts.qn_skip) bs_site_use(*this, ident_use, ident, {Q2{0, 0}}, {Q2{0, 0}}, +1);
-  auto ov_left = [&](const Env& in, const Core& bra, const Core& ket, Env& out) {
-    ScopeTimer tm(*this, t_ov, n_ov);
+  HC(hipStreamSynchronize(stream));
+  auto ov_left = [&](Engine& W, const Env& in, const Core& bra, const Core& ket, Env& out) {
+    ScopeTimer tm(W, W.t_ov, W.n_ov);
     Env o;
     o.R = 1; o.rb = bra.rr; o.rk = ket.rr;
     o.d.ensure(sizeof(double) * o.elems());
     if (opts.qn_skip && in.rb == bra.rl && in.rk == ket.rl &&
-        bs_env(*this, ident_use, in.d.as<double>(), bra, ket, o.d.as<double>())) {
+        bs_env(W, ident_use, in.d.as<double>(), bra, ket, o.d.as<double>())) {
       out = std::move(o);
       return;
     }
-    env_left_raw(padr(in.rb), padr(in.rk), bra.rrp(), ket.rrp(), 1, in.d.as<double>(), bra.d.as<double>(),
-                 ket.d.as<double>(), ident, 1, o.d.as<double>());
+    W.env_left_raw(padr(in.rb), padr(in.rk), bra.rrp(), ket.rrp(), 1, in.d.as<double>(), bra.d.as<double>(),
+                   ket.d.as<double>(), ident, 1, o.d.as<double>());
     out = std::move(o);
   };
-  auto ov_close = [&](const Env& e) {
+  auto ov_close = [](Engine& W, const Env& e) {
     // trace over the bond (the V suffix is right-orthonormal)
     const int p = padr(e.rb), q = padr(e.rk);
     std::vector<double> h((size_t)p * q);
-    download(h.data(), e.d, h.size() * sizeof(double), stream);
+    download(h.data(), e.d, h.size() * sizeof(double), W.stream);
     double t = 0.0;
     for (int i = 0; i < std::min(e.rb, e.rk); ++i) t += h[(size_t)i * q + i];
     return t;
   };
-  // entries (0, j) and (j, j)
-  for (int j = 1; j <= P; ++j) {
+  // entries (0, j) and (j, j) of subdomain j
+  auto column0_and_diag = [&](Engine& W, int j) {
     const Sub& Sj = subs[j - 1];
     // bra U^0 in the s_j-orthogonal gauge: W_{s_j}, V_{s_j+1}, ...
     Env eH, eS, tH, tS;
     const Env* cH = &Lenv[Sj.s];
-    overlap_start(Wc[Sj.s].rl, Sj.mod[0].rl, eS);
+    overlap_start(W, Wc[Sj.s].rl, Sj.mod[0].rl, eS);
     for (int k = Sj.s; k <= Sj.t; ++k) {
       const Core& bra = (k == Sj.s) ? Wc[k] : Vc[k];
       const Core& ket = Sj.mod[k - Sj.s];
-      env_left(*cH, bra, ket, k, tH);
+      W.env_left(*cH, bra, ket, k, tH);
       eH = std::move(tH);
       cH = &eH;
-      ov_left(eS, bra, ket, tS);
+      ov_left(W, eS, bra, ket, tS);
       eS = std::move(tS);
     }
-    A[j] = A[(size_t)j * n] = env_close(eH, Renv[Sj.t + 1]);
-    S[j] = S[(size_t)j * n] = ov_close(eS);
+    A[j] = A[(size_t)j * n] = W.env_close(eH, Renv[Sj.t + 1]);
+    S[j] = S[(size_t)j * n] = ov_close(W, eS);
     // diagonal
     cH = &Lenv[Sj.s];
-    overlap_start(Sj.mod[0].rl, Sj.mod[0].rl, eS);
+    overlap_start(W, Sj.mod[0].rl, Sj.mod[0].rl, eS);
     for (int k = Sj.s; k <= Sj.t; ++k) {
       const Core& c = Sj.mod[k - Sj.s];
-      env_left(*cH, c, c, k, tH);
+      W.env_left(*cH, c, c, k, tH);
       eH = std::move(tH);
       cH = &eH;
-      ov_left(eS, c, c, tS);
+      ov_left(W, eS, c, c, tS);
       eS = std::move(tS);
     }
-    A[(size_t)j * n + j] = env_close(eH, Renv[Sj.t + 1]);
-    S[(size_t)j * n + j] = ov_close(eS);
-  }
-  // entries (i, j), 1 <= i < j
-  for (int i = 1; i <= P; ++i) {
+    A[(size_t)j * n + j] = W.env_close(eH, Renv[Sj.t + 1]);
+    S[(size_t)j * n + j] = ov_close(W, eS);
+  };
+  // entries (i, j), j > i: one chain with bra Ũ^i and ket U from bond s_i,
+  // branching into ket Ũ^j at every later subdomain
+  auto row = [&](Engine& W, int i) {
     const Sub& Si = subs[i - 1];
-    // common chain: bra = Ũ^i, ket = U, from bond s_i
     Env cH, cS, tH, tS;
     bool first = true;
     int k = Si.s;
     for (int j = i + 1; j <= P; ++j) {
       const Sub& Sj = subs[j - 1];
-      // advance common chain to bond s_j
+      // advance the common chain to bond s_j
       for (; k < Sj.s; ++k) {
         const Core& bra = core_of(*this, i, k, true);
         const Core& ket = U[k];
         if (first) {
-          env_left(Lenv[Si.s], bra, ket, k, tH);
+          W.env_left(Lenv[Si.s], bra, ket, k, tH);
           Env s0;
-          overlap_start(bra.rl, ket.rl, s0);
-          ov_left(s0, bra, ket, tS);
+          overlap_start(W, bra.rl, ket.rl, s0);
+          ov_left(W, s0, bra, ket, tS);
           first = false;
         } else {
-          env_left(cH, bra, ket, k, tH);
-          ov_left(cS, bra, ket, tS);
+          W.env_left(cH, bra, ket, k, tH);
+          ov_left(W, cS, bra, ket, tS);
         }
         cH = std::move(tH);
         cS = std::move(tS);
@@ -2301,17 +2333,29 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
       for (int kk = Sj.s; kk <= Sj.t; ++kk) {
         const Core& bra = core_of(*this, i, kk, true);
         const Core& ket = Sj.mod[kk - Sj.s];
-        env_left(*pH, bra, ket, kk, tH);
-        ov_left(*pS, bra, ket, tS);
+        W.env_left(*pH, bra, ket, kk, tH);
+        ov_left(W, *pS, bra, ket, tS);
         bH = std::move(tH);
         bS = std::move(tS);
         pH = &bH;
         pS = &bS;
       }
-      A[(size_t)i * n + j] = A[(size_t)j * n + i] = env_close(bH, Renv[Sj.t + 1]);
-      S[(size_t)i * n + j] = S[(size_t)j * n + i] = ov_close(bS);
+      A[(size_t)i * n + j] = A[(size_t)j * n + i] = W.env_close(bH, Renv[Sj.t + 1]);
+      S[(size_t)i * n + j] = S[(size_t)j * n + i] = ov_close(W, bS);
     }
+  };
+  // tasks: P columns/diagonals, then P - 1 rows; cost = environment updates
+  std::vector<double> cost;
+  for (int j = 1; j <= P; ++j) cost.push_back(2.0 * (subs[j - 1].t - subs[j - 1].s + 1));
+  for (int i = 1; i < P; ++i) {
+    double c = 0.0;
+    for (int j = i + 1; j <= P; ++j) c += subs[j - 1].t - subs[j - 1].s + 1;
+    cost.push_back(2.0 * (c + std::max(0, subs[P - 1].s - subs[i - 1].s)));
   }
+  run_tasks((int)cost.size(), cost, [&](Engine& W, int t) {
+    if (t < P) column0_and_diag(W, t + 1);
+    else row(W, t - P + 1);
+  });
   ph[6] += now() - tph;
   tph = now();
   if (verbose)
@@ -2447,8 +2491,10 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
     }
   }
   HC(hipStreamSynchronize(stream));
+  const double tc0 = now();
   // right-to-left orthogonalisation
   for (int k = L - 1; k >= 1; --k) lq_right(*this, T[k], T[k - 1]);
+  const double tc1 = now();
   // left-to-right truncated SVD
   double discarded = 0.0;
   for (int k = 0; k + 1 < L; ++k) {
@@ -2495,9 +2541,22 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   HC(hipStreamSynchronize(stream));
   U = std::move(T);
   free_caches();
+  const double tc2 = now();
   double En = energy();
   ph[7] += now() - tph;
-  if (verbose) std::fprintf(stderr, "[tt] step 4: compressed in %.2fs, E=%.10f discarded=%.3g\n", ph[7], En, discarded);
+  if (verbose)
+    std::fprintf(stderr,
+                 "[tt] step 4: compressed in %.2fs (block TT %.2fs, LQ pass %.2fs, SVD pass %.2fs, energy %.2fs), "
+                 "E=%.10f discarded=%.3g\n",
+                 ph[7], tc0 - tph, tc1 - tc0, tc2 - tc1, now() - tc2, En, discarded);
+  if (verbose) {
+    std::fprintf(stderr, "[tt] batched SVDs of this context (bin M x N: calls, matrices, seconds):");
+    for (auto& kv : svd_bins)
+      std::fprintf(stderr, " %dx%d:%.0f,%.0f,%.3f", kv.first.first, kv.first.second, kv.second[0], kv.second[1],
+                   kv.second[2]);
+    std::fprintf(stderr, "\n");
+    svd_bins.clear();
+  }
   if (Eout) *Eout = En;
   if (disc) *disc = discarded;
   return status;

@@ -7,6 +7,7 @@
 
 #include <array>
 #include <climits>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -174,6 +175,8 @@ class Engine {
   // verbose-mode counters: environment updates (block-sparse, dense) and overlap updates
   double t_env_bs = 0.0, t_env_dense = 0.0, t_ov = 0.0;
   int n_env_bs = 0, n_env_dense = 0, n_ov = 0;
+  // verbose mode: batched SVD calls per padded bin shape {M, N} -> {calls, matrices, seconds}
+  std::map<std::pair<int, int>, std::array<double, 3>> svd_bins;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;
@@ -206,6 +209,10 @@ class Engine {
   // the Step-1 cores and environments of src
   void solve_subdomain(const Engine& src, int j, int s, int e, Sub& S);
   void absorb_counters(Engine& w);  // add a worker's counters to this engine's, clear the worker's
+  // fn(engine, task) for every task: on this engine in order when one worker is asked
+  // for, else on worker engines (host thread + stream each), the costliest tasks first.
+  // fn reads shared state only and writes task-private outputs.
+  void run_tasks(int ntask, const std::vector<double>& cost, const std::function<void(Engine&, int)>& fn);
   int coarse_correct(double* S, double* A, double* c, double* lam, double* Eout, int* rank, double* disc);
   void dmrg2(int nsweeps, double* energies);
 
@@ -248,7 +255,7 @@ class Engine {
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)
   DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp, bs_gg1, bs_gg2;
   DevMem be_t1, be_panel, be_up, be_tmp;  // block-sparse environment-update workspaces
-  long long bs_serial = 0, bs_zero_serial = -1;
+  long long bs_zero_serial = -1;  // plan whose never-written T1 entries are zero in bs_t1
   int bs_zero_prec = -1;
 
  private:
