@@ -1149,7 +1149,7 @@ class SectorSVD {
 };
 
 // QR of core A viewed as [(a s)][b]; A <- Q (left-orthogonal), next <- R next.
-static void qr_left(Engine& E, Core& A, Core& next) {
+static void qr_left_solver(Engine& E, Core& A, Core& next) {
   const int rlp = A.rlp(), rrp = A.rrp();
   std::vector<int> rows, cols;
   Labels rq, cq;
@@ -1205,7 +1205,7 @@ static void qr_left(Engine& E, Core& A, Core& next) {
 
 // LQ of core W viewed as [a][(s b)]: W <- Q (right-orthogonal, possibly smaller
 // left bond), prev <- prev Lmat.  Returns the new left labels.
-static void lq_right(Engine& E, Core& W, Core& prev) {
+static void lq_right_solver(Engine& E, Core& W, Core& prev) {
   const int rlp = W.rlp(), rrp = W.rrp();
   std::vector<int> rows, cols;
   Labels rq, cq;
@@ -1254,6 +1254,136 @@ static void lq_right(Engine& E, Core& W, Core& prev) {
               nullptr, nullptr, 0, E.stream);
     HC(hipStreamSynchronize(E.stream));
   }
+  W.d = std::move(Qd);
+  W.rl = knew;
+  W.ql = qn;
+  // prev [prlp][4][rlp] x Lm [rlp][kp] -> [prlp][4][kp]
+  const int prlp = prev.rlp();
+  DevMem nd;
+  nd.ensure(sizeof(double) * (size_t)prlp * 4 * kp);
+  GemmArgs g{};
+  g.M = prlp * 4; g.N = kp; g.K = rlp; g.batch = 1; g.kin = rlp;
+  g.sAm = rlp; g.sAkk = 1; g.sBkk = kp; g.sBn = 1; g.sCm = kp; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, prev.d.as<double>(), Lm.as<double>(), nd.as<double>(), true, true, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+  prev.d = std::move(nd);
+  prev.rr = knew;
+  prev.qr = qn;
+}
+
+// All sector blocks of one orthogonal factorisation in one launch of the
+// Householder kernel (one workgroup per block).
+struct HhJob {
+  std::vector<int> rows, cols, nmap;
+  std::vector<HhBlk> blks;
+  long long ws = 0;
+  int maxn = 0;
+  void add(const std::vector<int>& r, const std::vector<int>& c, const std::vector<int>& nm) {
+    const int m = (int)r.size(), n = (int)c.size(), k = std::min(m, n);
+    if ((int)nm.size() != k) throw std::logic_error("Householder job: factor index map size");
+    blks.push_back(HhBlk{ws, m, n, (int)rows.size(), (int)cols.size(), (int)nmap.size(), 0});
+    rows.insert(rows.end(), r.begin(), r.end());
+    cols.insert(cols.end(), c.begin(), c.end());
+    nmap.insert(nmap.end(), nm.begin(), nm.end());
+    ws += (long long)m * n + (long long)k * n + k;
+    maxn = std::max(maxn, n);
+  }
+  void run(Engine& E, const double* W, long long sWr, long long sWc, double* L, long long sLr, long long sLc, double* Q,
+           long long sQr, long long sQc) {
+    if (blks.empty()) return;
+    DevMem dr = upload_ints(rows, E.stream), dc = upload_ints(cols, E.stream), dn = upload_ints(nmap, E.stream);
+    DevMem db, dws;
+    upload(db, blks.data(), blks.size() * sizeof(HhBlk), E.stream);
+    dws.ensure(sizeof(double) * std::max<long long>(ws, 1));
+    householder_lq(W, sWr, sWc, dr.as<int>(), dc.as<int>(), dn.as<int>(), db.as<HhBlk>(), (int)blks.size(),
+                   dws.as<double>(), L, sLr, sLc, Q, sQr, sQc, E.stream);
+    HC(hipStreamSynchronize(E.stream));
+  }
+};
+
+// QR of core A viewed as [(a s)][b] per charge sector: A <- Q (left-orthogonal, same
+// bond basis), next <- R next.  Computed as the LQ of the transposed blocks.
+static void qr_left(Engine& E, Core& A, Core& next) {
+  const int rlp = A.rlp(), rrp = A.rrp();
+  std::vector<int> rows, cols;
+  Labels rq, cq;
+  for (int a = 0; a < A.rl; ++a)
+    for (int s = 0; s < 4; ++s) {
+      rows.push_back(a * 4 + s);
+      rq.push_back(qadd(A.ql[a], SITE_Q[s]));
+    }
+  for (int b = 0; b < A.rr; ++b) {
+    cols.push_back(b);
+    cq.push_back(A.qr[b]);
+  }
+  // every column must belong to a sector with at least as many rows
+  auto secs = make_sectors(rows, rq, cols, cq);
+  size_t ncov = 0;
+  HhJob J;
+  for (auto& sc : secs) {
+    if (sc.rows.size() < sc.cols.size()) throw std::runtime_error("rank-deficient QN block in QR");
+    ncov += sc.cols.size();
+    J.add(sc.cols, sc.rows, sc.cols);
+  }
+  if (ncov != cols.size()) throw std::runtime_error("TT core has a bond state with no compatible rows");
+  if (J.maxn > HH_MAXN) {
+    qr_left_solver(E, A, next);
+    return;
+  }
+  DevMem Qd, Rm;
+  Qd.resize_zero(sizeof(double) * (size_t)rlp * 4 * rrp, E.stream);
+  Rm.resize_zero(sizeof(double) * (size_t)rrp * rrp, E.stream);
+  // transposed block [b][(a s)] = A[(a s)][b]; R[b'][b] = L^T; Q[(a s)][b'] = Q'^T
+  J.run(E, A.d.as<double>(), 1, rrp, Rm.as<double>(), 1, rrp, Qd.as<double>(), 1, rrp);
+  A.d = std::move(Qd);
+  // next <- Rm * next : [rrp][rrp] x [rrp][4*nrp]
+  const int nrp = next.rrp();
+  DevMem nd;
+  nd.ensure(sizeof(double) * (size_t)rrp * 4 * nrp);
+  GemmArgs g{};
+  g.M = rrp; g.N = 4 * nrp; g.K = rrp; g.batch = 1; g.kin = rrp;
+  g.sAm = rrp; g.sAkk = 1; g.sBkk = 4LL * nrp; g.sBn = 1; g.sCm = 4LL * nrp; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, Rm.as<double>(), next.d.as<double>(), nd.as<double>(), true, true, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+  next.d = std::move(nd);
+}
+
+// W = L Q with W viewed as [a][(s b)] per charge sector: W <- Q (right-orthogonal, left
+// bond k_g = min(m_g, n_g) per sector, in charge order), prev <- prev L.
+static void lq_right(Engine& E, Core& W, Core& prev) {
+  const int rlp = W.rlp(), rrp = W.rrp();
+  std::vector<int> rows, cols;
+  Labels rq, cq;
+  for (int a = 0; a < W.rl; ++a) {
+    rows.push_back(a);
+    rq.push_back(W.ql[a]);
+  }
+  for (int s = 0; s < 4; ++s)
+    for (int b = 0; b < W.rr; ++b) {
+      cols.push_back(s * rrp + b);
+      cq.push_back(qsub(W.qr[b], SITE_Q[s]));
+    }
+  auto secs = make_sectors(rows, rq, cols, cq);
+  int knew = 0;
+  Labels qn;
+  HhJob J;
+  for (auto& sc : secs) {
+    const int k = (int)std::min(sc.rows.size(), sc.cols.size());
+    std::vector<int> nm(k);
+    std::iota(nm.begin(), nm.end(), knew);
+    for (int i = 0; i < k; ++i) qn.push_back(sc.g);
+    knew += k;
+    J.add(sc.rows, sc.cols, nm);
+  }
+  if (J.maxn > HH_MAXN) {
+    lq_right_solver(E, W, prev);
+    return;
+  }
+  const int kp = padr(std::max(knew, 1));
+  DevMem Qd, Lm;
+  Qd.resize_zero(sizeof(double) * (size_t)kp * 4 * rrp, E.stream);
+  Lm.resize_zero(sizeof(double) * (size_t)rlp * kp, E.stream);
+  J.run(E, W.d.as<double>(), 4LL * rrp, 1, Lm.as<double>(), kp, 1, Qd.as<double>(), 4LL * rrp, 1);
   W.d = std::move(Qd);
   W.rl = knew;
   W.ql = qn;

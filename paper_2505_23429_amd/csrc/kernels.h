@@ -118,6 +118,20 @@ struct ScatterBlk {
   long long us_i, us_j, vs_j, vs_c;
   int roff, coff, m, n, t, off;
 };
+// Householder LQ of charge-sector blocks, one workgroup per block.  Block b is
+//   B[r][c] = W[rows[roff+r]*sWr + cols[coff+c]*sWc]   (m x n, k = min(m, n))
+// factored as B = L Q with reflectors applied from the right (LAPACK convention:
+// Q = first k rows of H(k-1)...H(0), H(i) = I - tau_i v_i v_i^T, v_i[i] = 1), then
+//   Lout[rows[roff+r]*sLr + nmap[noff+c]*sLc] = L[r][c]   for c <= min(r, k-1)
+//   Qout[nmap[noff+r]*sQr + cols[coff+c]*sQc] = Q[r][c]   for r < k
+// (nmap: bond index of each factor row; other destination entries untouched).
+// ws + b.ws holds the block's m x n working copy, then its k x n Q, then its k
+// reflector scales.  n <= HH_MAXN.
+struct HhBlk { long long ws; int m, n, roff, coff, noff, pad; };
+constexpr int HH_MAXN = 6144;
+void householder_lq(const double* W, long long sWr, long long sWc, const int* rows, const int* cols, const int* nmap,
+                    const HhBlk* blks, int nblk, double* ws, double* Lout, long long sLr, long long sLc, double* Qout,
+                    long long sQr, long long sQc, hipStream_t s);
 void scatter_factors(const ScatterBlk* blks, int nblk, const int* rows, const int* cols, double* left, long long ldl,
                      double* right, long long ldr, int mode, hipStream_t s);
 
