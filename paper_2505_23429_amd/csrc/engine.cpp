@@ -269,6 +269,7 @@ Engine::Engine(const tt_opts& o)
 Engine::Engine(const Engine& parent, int)
     : opts(parent.opts), prob(parent.prob), L(prob->L), mpo(prob->mpo), Rb(prob->Rb), chan_q(prob->chan_q),
       chan_q_dev(prob->chan_q_dev) {
+  is_worker = true;
   verbose = parent.verbose;
   have_mpo = parent.have_mpo;
   HC(hipSetDevice(opts.device));
@@ -278,9 +279,32 @@ Engine::Engine(const Engine& parent, int)
   HC(hipEventCreate(&ev0));
   HC(hipEventCreate(&ev1));
 }
+int Engine::aux_lanes() {
+  constexpr int kLanes = 4;
+  if (is_worker) return 0;
+  while ((int)aux_stream.size() < kLanes) {
+    hipStream_t s = nullptr;
+    HC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) {
+      (void)hipStreamDestroy(s);
+      throw std::runtime_error("rocBLAS handle creation failed");
+    }
+    RC(rocblas_set_stream(h, s));
+    aux_stream.push_back(s);
+    aux_blas.push_back(h);
+  }
+  return kLanes;
+}
+
 Engine::~Engine() {
   if (stream) (void)hipStreamSynchronize(stream);
   workers.clear();
+  for (size_t i = 0; i < aux_stream.size(); ++i) {
+    (void)hipStreamSynchronize(aux_stream[i]);
+    rocblas_destroy_handle(aux_blas[i]);
+    (void)hipStreamDestroy(aux_stream[i]);
+  }
   if (blas) rocblas_destroy_handle(blas);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
@@ -974,10 +998,13 @@ class SectorSVD {
       int sec, i;
     };
     std::vector<Trip> trip;
+    // phase 1 (context stream): padded bins gathered
+    std::vector<const std::vector<int>*> members;
     for (auto& kv : bykey) {
       bins.emplace_back();
       Bin& B = bins.back();
       const std::vector<int>& mem = kv.second;
+      members.push_back(&mem);
       B.cnt = (int)mem.size();
       for (int t : mem) {
         B.M = std::max(B.M, std::max(blocks[t].m, blocks[t].n));
@@ -992,28 +1019,75 @@ class SectorSVD {
         const Blk& b = blocks[mem[i]];
         gb[i] = GatherBlk{MN * i, B.M, b.roff, b.coff, b.m, b.n, b.tr ? 1 : 0};
       }
-      DevMem gdev;
-      upload(gdev, gb.data(), gb.size() * sizeof(GatherBlk), E.stream);
-      gather_blocks(M, ldm, rdev.as<int>(), cdev.as<int>(), gdev.as<GatherBlk>(), B.cnt, B.A.as<double>(), E.stream);
+      upload(B.gdev, gb.data(), gb.size() * sizeof(GatherBlk), E.stream);
+      gather_blocks(M, ldm, rdev.as<int>(), cdev.as<int>(), B.gdev.as<GatherBlk>(), B.cnt, B.A.as<double>(), E.stream);
       B.U.ensure(sizeof(double) * (size_t)B.M * B.K * B.cnt);
       B.Vt.ensure(sizeof(double) * (size_t)B.K * B.N * B.cnt);
       B.S.ensure(sizeof(double) * (size_t)B.K * B.cnt);
-      DevMem Ew, info;
-      Ew.ensure(sizeof(double) * (size_t)B.K * B.cnt);
-      info.ensure(sizeof(int) * B.cnt);
-      const double tb0 = E.verbose ? E.now() : 0.0;
-      RC(rocsolver_dgesvd_strided_batched(E.blas, rocblas_svect_singular, rocblas_svect_singular, B.M, B.N,
+      B.Ew.ensure(sizeof(double) * (size_t)B.K * B.cnt);
+      B.info.ensure(sizeof(int) * B.cnt);
+    }
+    HC(hipStreamSynchronize(E.stream));
+    // phase 2: one batched SVD per bin; the bins are independent and run
+    // concurrently on the context's auxiliary streams when it has them
+    auto factor = [&](Bin& B, rocblas_handle h) {
+      const long long MN = (long long)B.M * B.N;
+      RC(rocsolver_dgesvd_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, B.M, B.N,
                                           B.A.as<double>(), B.M, MN, B.S.as<double>(), B.K, B.U.as<double>(), B.M,
                                           (rocblas_stride)B.M * B.K, B.Vt.as<double>(), B.K, (rocblas_stride)B.K * B.N,
-                                          Ew.as<double>(), B.K, rocblas_outofplace, info.as<int>(), B.cnt));
-      std::vector<int> inf(B.cnt);
-      d2h(inf.data(), info.p, sizeof(int) * B.cnt, E.stream);
-      if (E.verbose) {
+                                          B.Ew.as<double>(), B.K, rocblas_outofplace, B.info.as<int>(), B.cnt));
+    };
+    const double tb0 = E.verbose ? E.now() : 0.0;
+    const int nlanes = std::min((int)bins.size(), E.aux_lanes());
+    if (nlanes <= 1) {
+      for (Bin& B : bins) factor(B, E.blas);
+      HC(hipStreamSynchronize(E.stream));
+    } else {
+      // largest bins first, each to the lane with the least work so far
+      std::vector<int> ord(bins.size());
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        return (double)bins[x].M * bins[x].N * bins[x].N > (double)bins[y].M * bins[y].N * bins[y].N;
+      });
+      std::vector<std::vector<int>> lane_bins(nlanes);
+      std::vector<double> load(nlanes, 0.0);
+      for (int i : ord) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_bins[l].push_back(i);
+        load[l] += (double)bins[i].M * bins[i].N * bins[i].N;
+      }
+      std::vector<std::exception_ptr> errs(nlanes);
+      std::vector<std::thread> th;
+      for (int l = 0; l < nlanes; ++l)
+        th.emplace_back([&, l]() {
+          try {
+            HC(hipSetDevice(E.opts.device));
+            for (int i : lane_bins[l]) factor(bins[i], E.aux_blas[l]);
+            HC(hipStreamSynchronize(E.aux_stream[l]));
+          } catch (...) {
+            errs[l] = std::current_exception();
+            (void)hipStreamSynchronize(E.aux_stream[l]);
+          }
+        });
+      for (auto& t : th) t.join();
+      for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+    }
+    if (E.verbose) {
+      const double dt = E.now() - tb0;
+      for (Bin& B : bins) {
         auto& st = E.svd_bins[{B.M, B.N}];
         st[0] += 1.0;
         st[1] += B.cnt;
-        st[2] += E.now() - tb0;
       }
+      E.svd_seconds += dt;
+    }
+    // phase 3 (context stream): convergence check, singular triplets
+    for (size_t bi = 0; bi < bins.size(); ++bi) {
+      Bin& B = bins[bi];
+      const std::vector<int>& mem = *members[bi];
+      std::vector<int> inf(B.cnt);
+      d2h(inf.data(), B.info.p, sizeof(int) * B.cnt, E.stream);
       for (int i = 0; i < B.cnt; ++i) {
         if (inf[i] == 0) continue;
         // the zero padding can stall the batched bidiagonal QR on some blocks: factor
@@ -1140,7 +1214,7 @@ class SectorSVD {
   };
   struct Bin {
     int M = 0, N = 0, K = 0, cnt = 0;
-    DevMem A, U, Vt, S;
+    DevMem A, U, Vt, S, Ew, info, gdev;
   };
   std::vector<Sector> secs;
   std::vector<Blk> blocks;
@@ -2680,12 +2754,12 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
                  "E=%.10f discarded=%.3g\n",
                  ph[7], tc0 - tph, tc1 - tc0, tc2 - tc1, now() - tc2, En, discarded);
   if (verbose) {
-    std::fprintf(stderr, "[tt] batched SVDs of this context (bin M x N: calls, matrices, seconds):");
+    std::fprintf(stderr, "[tt] batched SVDs of this context: %.3fs; bins (M x N: calls, matrices):", svd_seconds);
     for (auto& kv : svd_bins)
-      std::fprintf(stderr, " %dx%d:%.0f,%.0f,%.3f", kv.first.first, kv.first.second, kv.second[0], kv.second[1],
-                   kv.second[2]);
+      std::fprintf(stderr, " %dx%d:%.0f,%.0f", kv.first.first, kv.first.second, kv.second[0], kv.second[1]);
     std::fprintf(stderr, "\n");
     svd_bins.clear();
+    svd_seconds = 0.0;
   }
   if (Eout) *Eout = En;
   if (disc) *disc = discarded;

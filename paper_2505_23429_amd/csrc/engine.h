@@ -175,8 +175,16 @@ class Engine {
   // verbose-mode counters: environment updates (block-sparse, dense) and overlap updates
   double t_env_bs = 0.0, t_env_dense = 0.0, t_ov = 0.0;
   int n_env_bs = 0, n_env_dense = 0, n_ov = 0;
-  // verbose mode: batched SVD calls per padded bin shape {M, N} -> {calls, matrices, seconds}
+  // verbose mode: batched SVD calls per padded bin shape {M, N} -> {calls, matrices, unused},
+  // and the wall time of the batched SVD phases
   std::map<std::pair<int, int>, std::array<double, 3>> svd_bins;
+  double svd_seconds = 0.0;
+  // auxiliary streams (with rocBLAS handles) on which the independent size bins of one
+  // batched sector SVD run concurrently; created on first use, none on worker engines
+  bool is_worker = false;
+  std::vector<hipStream_t> aux_stream;
+  std::vector<rocblas_handle> aux_blas;
+  int aux_lanes();
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;
