@@ -20,7 +20,15 @@
 namespace tt {
 
 struct BsAlpha { int M, N, K, row0, col0, oal; };
-struct BsGroup { long long in_base; int ncols, spec0, nspec, ld; };  // ld: row stride (ncols rounded up to 4)
+// ld: row stride (ncols rounded up to 4); cls[s]: charge class of the output
+// channels of rows with site state s in the second mix (-1: none)
+struct BsGroup { long long in_base; int ncols, spec0, nspec, ld; int cls[4]; };
+// One output row of a mix.  First mix: b[s] is the T2 row base for spectator
+// site state s; sy is the output site state s1'.  Second mix: sy is s2' and
+// rank the position of the output channel within its charge class (its K
+// offset in a stage-4 panel is the sector start + rank * n_beta).  Light rows
+// read operator entries [e0, e1); heavy rows read the staging row at h.
+struct MixRow { long long b[4]; long long h; int e0, e1, sy, rank, pad0, pad1; };
 struct BsS4Tile { long long abase, bbase; int M, N, K, m0, n0, k0, k1, slot; };
 struct BsRedTile { int M, N, m0, n0, slot0, nsplit, row0, pad; };
 struct BsPair { int C, beta, koff, bprime; };
@@ -38,8 +46,8 @@ struct BsMix {
   double fl_light = 0.0, el_light = 0.0, fl_heavy = 0.0, el_heavy = 0.0, el_scatter = 0.0;
   long long ntmp = 0;                         // staging elements of the heavy rows
   std::vector<BsHeavy> heavy;
-  DevMem tiles, groups, optr, ocol, oval64, oval32, orow, spec;
-  DevMem htiles, horow, hbase, hw64, hw32;
+  DevMem tiles, groups, rows, ocol, oval64, oval32, spec;
+  DevMem htiles, hrows, hw64, hw32;
 };
 
 struct BsPlan {
@@ -55,7 +63,7 @@ struct BsPlan {
   DevMem tiles1, alpha, rsrc, rinfo, cinfo, rowpart1, specoff, nbeta, boff;
   // mixes
   BsMix m1, m2;
-  DevMem rowbase2, ccls, bshift, pbase, kbeta, koff;
+  DevMem bshift, pbase, kbeta, kstart;  // second-mix destinations: class x sector -> panel, panel bases, K starts
   // stage 4
   int ntiles4 = 0, nred = 0, nslots = 0, npairs = 0;
   DevMem tiles4, red, rowdst, pairs, rbase;

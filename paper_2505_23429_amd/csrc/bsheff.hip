@@ -149,18 +149,25 @@ __global__ __launch_bounds__(256) void stage1_kernel(const int4* __restrict__ ti
 // mixes: out row r of a group = sum_e val_e * in row col_e of the same group,
 // one spectator column per thread.  MODE 1 scatters into the T2 layout
 // (rows (B, s2)), MODE 2 into the stage-4 panels (rows (a', s1', s2', i'),
-// columns (C, j)).
+// columns (C, j)).  Everything that depends on the column only (its
+// destination offset for each of the four output site states) is formed once
+// per thread; a row then costs its uniform descriptor, its input loads and one
+// store.  Rows with a single operator entry (nearly all light rows) are taken
+// four at a time so that their loads are in flight together.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline long long pick4(long long a0, long long a1, long long a2, long long a3, int i) {
+  return i == 0 ? a0 : (i == 1 ? a1 : (i == 2 ? a2 : a3));
+}
+
 template <typename T, int MODE, bool HEAVY>
 __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
-    const int4* __restrict__ tiles, const BsGroup* __restrict__ groups, const int* __restrict__ optr,
-    const int* __restrict__ ocol, const T* __restrict__ oval, const int2* __restrict__ orow,
-    const int4* __restrict__ spec, const T* __restrict__ in, long long nin, T* __restrict__ out, long long nout,
-    int* __restrict__ err, int nbe,
-    const long long* __restrict__ rowbase2, const long long* __restrict__ specoff, const int* __restrict__ ccls,
-    const int* __restrict__ bshift, const long long* __restrict__ pbase, const int* __restrict__ kbeta,
-    const int* __restrict__ koff, int RCx, const int* __restrict__ nbeta, int round_bf16,
-    const long long* __restrict__ hbase, const T* __restrict__ tmp) {
+    const int4* __restrict__ tiles, const BsGroup* __restrict__ groups, const MixRow* __restrict__ rows,
+    const int* __restrict__ ocol, const T* __restrict__ oval, const int4* __restrict__ spec,
+    const T* __restrict__ in, long long nin, T* __restrict__ out, long long nout, int* __restrict__ err, int nbe,
+    const long long* __restrict__ specoff, const int* __restrict__ bshift, const long long* __restrict__ pbase,
+    const int* __restrict__ kbeta, const int* __restrict__ kstart, const int* __restrict__ nbeta, int round_bf16,
+    const T* __restrict__ tmp, long long ntmp) {
   const int4 t = tiles[blockIdx.x];
   const BsGroup G = groups[t.x];
   const int col = t.y + (int)threadIdx.x;
@@ -172,44 +179,97 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
   }
   const int4 sp = spec[G.spec0 + lo];  // {start, alpha', s, beta}
   const int within = col - sp.x;
-  int wi = 0, wj = within;
-  if (MODE == 2) {
+  // destination offset of this column for output site state 0..3
+  // (-1: no destination, -2: inconsistent tables)
+  long long c0 = -1, c1 = -1, c2 = -1, c3 = -1;
+  long long stride = 0;
+  if (MODE == 1) {
+    const long long* so = specoff + (long long)sp.y * 4 * nbe + sp.w;
+    c0 = so[0];
+    c1 = so[nbe];
+    c2 = so[2LL * nbe];
+    c3 = so[3LL * nbe];
+    c0 = c0 < 0 ? -2 : c0 + within;
+    c1 = c1 < 0 ? -2 : c1 + within;
+    c2 = c2 < 0 ? -2 : c2 + within;
+    c3 = c3 < 0 ? -2 : c3 + within;
+  } else {
     const int nb = nbeta[sp.w];
-    wi = within / nb;
-    wj = within - wi * nb;
+    const int wi = within / nb, wj = within - wi * nb;
+    stride = nb;
+    long long cz[4];
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      cz[z] = -1;
+      const int cl = G.cls[z];
+      if (cl < 0) continue;
+      const int bp = bshift[cl * nbe + sp.w];
+      if (bp < 0) continue;
+      const long long pb = pbase[(((long long)sp.y * 4 + sp.z) * 4 + z) * nbe + bp];
+      const int ks = kstart[(long long)bp * nbe + sp.w];
+      cz[z] = (pb < 0 || ks < 0) ? -2 : pb + (long long)wi * kbeta[bp] + ks + wj;
+    }
+    c0 = cz[0]; c1 = cz[1]; c2 = cz[2]; c3 = cz[3];
   }
   const T* src = in + G.in_base + col;
   const long long ld = G.ld;
   const long long lim = nin - G.in_base - col;  // src[q] valid for 0 <= q < lim
-  for (int r = t.z; r < t.w; ++r) {
+  auto store = [&](const MixRow& R, T v) {
+    long long d;
+    const long long c = pick4<T>(c0, c1, c2, c3, R.sy);
+    if (MODE == 1) {
+      const long long rb = pick4<T>(R.b[0], R.b[1], R.b[2], R.b[3], sp.z);
+      if (rb < 0 || c < 0) { err[0] = 5; return; }
+      d = rb + c;
+    } else {
+      if (c == -1) return;  // the output channel does not reach this column's right sector
+      if (c < 0 || R.rank < 0) { err[0] = 6; return; }
+      d = c + (long long)R.rank * stride;
+      if (round_bf16) v = (T)bf16_round((float)v);
+    }
+    if (d < 0 || d >= nout) { err[0] = 7; return; }
+    out[d] = v;
+  };
+  auto value = [&](const MixRow& R) {
     T acc = T(0);
     if (HEAVY) {
-      acc = tmp[hbase[r] + col];  // heavy row: sum formed by the GEMM
+      const long long q = R.h + col;  // heavy row: sum formed by the GEMM
+      if (R.h >= 0 && q < ntmp) acc = tmp[q]; else err[0] = 4;
     } else {
-      const int e1 = optr[r + 1];
-      for (int e = optr[r]; e < e1; ++e) {
+      for (int e = R.e0; e < R.e1; ++e) {
         const long long q = (long long)ocol[e] * ld;
         if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 4;
       }
     }
-    const int2 ro = orow[r];  // {channel, site state}
-    long long d;
-    if (MODE == 1) {
-      const long long rb = rowbase2[ro.x * 4 + sp.z];
-      const long long so = specoff[((long long)sp.y * 4 + ro.y) * nbe + sp.w];
-      if (rb < 0 || so < 0) { err[0] = 5; continue; }
-      d = rb + so + within;
-    } else {
-      const int bp = bshift[ccls[ro.x] * nbe + sp.w];
-      if (bp < 0) continue;
-      const long long pb = pbase[(((long long)sp.y * 4 + sp.z) * 4 + ro.y) * nbe + bp];
-      const int ko = koff[(long long)bp * RCx + ro.x];
-      if (pb < 0 || ko < 0) { err[0] = 6; continue; }
-      d = pb + (long long)wi * kbeta[bp] + ko + wj;
-      if (round_bf16) acc = (T)bf16_round((float)acc);
+    return acc;
+  };
+  int r = t.z;
+  if (!HEAVY) {
+    for (; r + 4 <= t.w; r += 4) {
+      const MixRow R0 = rows[r], R1 = rows[r + 1], R2 = rows[r + 2], R3 = rows[r + 3];
+      if (R0.e1 - R0.e0 == 1 && R1.e1 - R1.e0 == 1 && R2.e1 - R2.e0 == 1 && R3.e1 - R3.e0 == 1) {
+        const long long q0 = (long long)ocol[R0.e0] * ld, q1 = (long long)ocol[R1.e0] * ld;
+        const long long q2 = (long long)ocol[R2.e0] * ld, q3 = (long long)ocol[R3.e0] * ld;
+        if (q0 < 0 || q0 >= lim || q1 < 0 || q1 >= lim || q2 < 0 || q2 >= lim || q3 < 0 || q3 >= lim) {
+          err[0] = 4;
+          continue;
+        }
+        const T v0 = src[q0], v1 = src[q1], v2 = src[q2], v3 = src[q3];
+        store(R0, oval[R0.e0] * v0);
+        store(R1, oval[R1.e0] * v1);
+        store(R2, oval[R2.e0] * v2);
+        store(R3, oval[R3.e0] * v3);
+      } else {
+        store(R0, value(R0));
+        store(R1, value(R1));
+        store(R2, value(R2));
+        store(R3, value(R3));
+      }
     }
-    if (d < 0 || d >= nout) { err[0] = 7; continue; }
-    out[d] = acc;
+  }
+  for (; r < t.w; ++r) {
+    const MixRow R = rows[r];
+    store(R, value(R));
   }
 }
 
@@ -313,12 +373,13 @@ __global__ __launch_bounds__(256) void rstack_kernel(const BsPair* __restrict__ 
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q2>& dout, int nout_ch,
+static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std::vector<Q2>& dout, int nout_ch,
                       const std::vector<int>& rowidx_in, const std::vector<int>& grp_in, const std::map<Q2, int>& gid,
                       const std::vector<Q2>& gq, const std::vector<int>& cols, const std::vector<int>& ldg,
-                      const std::vector<long long>& in_off,
-                      const std::vector<int>& nrows_in, const std::vector<int>& spec0,
-                      const std::vector<int>& nspec) {
+                      const std::vector<long long>& in_off, const std::vector<int>& nrows_in,
+                      const std::vector<int>& spec0, const std::vector<int>& nspec,
+                      const std::vector<long long>& rowbase2, const std::vector<int>& crank,
+                      const std::vector<std::array<int, 4>>& gcls) {
   const int ng = (int)gq.size();
   std::vector<std::vector<int2>> rows_by_g(ng);
   for (int K = 0; K < nout_ch; ++K)
@@ -326,13 +387,21 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
       auto it = gid.find(sub(kSiteQ[s], dout[K]));
       if (it != gid.end()) rows_by_g[it->second].push_back(make_int2(K, s));
     }
-  std::vector<int> optr(1, 0), ocol;
+  auto descriptor = [&](int2 ro, int e0, int e1, long long h) {
+    MixRow R{};
+    R.e0 = e0;
+    R.e1 = e1;
+    R.h = h;
+    R.sy = ro.y;
+    for (int z = 0; z < 4; ++z) R.b[z] = mode == 1 ? rowbase2[(size_t)ro.x * 4 + z] : -1;
+    R.rank = mode == 2 ? crank[ro.x] : 0;
+    return R;
+  };
+  std::vector<int> ocol;
   std::vector<double> oval;
-  std::vector<int2> orow;
+  std::vector<MixRow> lrows, hrows_all;
   std::vector<int4> tiles;
   std::vector<BsGroup> groups(ng);
-  std::vector<int2> horow;
-  std::vector<long long> hbase;
   std::vector<int4> htiles;
   std::vector<double> hw;
   m.heavy.clear();
@@ -340,13 +409,12 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
   m.flops = m.nin = m.nout = 0.0;
   m.fl_light = m.el_light = m.fl_heavy = m.el_heavy = m.el_scatter = 0.0;
   for (int g = 0; g < ng; ++g) {
-    groups[g] = BsGroup{in_off[g], cols[g], spec0[g], nspec[g], ldg[g]};
-    const int r0 = (int)orow.size();
-    const int h0 = (int)horow.size();
+    groups[g] = BsGroup{in_off[g], cols[g], spec0[g], nspec[g], ldg[g], {gcls[g][0], gcls[g][1], gcls[g][2], gcls[g][3]}};
     long long nnz_g = 0;
     std::vector<std::pair<int, double>> ent;
-    std::vector<std::vector<std::pair<int, double>>> hrows;
-    std::vector<int2> hro;
+    std::vector<std::vector<std::pair<int, double>>> hrows, multi;
+    std::vector<int2> hro, mro;
+    const int r0 = (int)lrows.size();
     for (const int2& ro : rows_by_g[g]) {
       const int K = ro.x, sp = ro.y;
       ent.clear();
@@ -364,14 +432,27 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
       if ((int)ent.size() > HEAVY_MIN) {
         hrows.push_back(ent);
         hro.push_back(ro);
-        continue;
+      } else if (ent.size() != 1) {
+        // several entries, or none (the output row is written as zero)
+        multi.push_back(ent);
+        mro.push_back(ro);
+      } else {
+        // single-entry rows first: the kernel takes them four at a time
+        lrows.push_back(descriptor(ro, (int)ocol.size(), (int)ocol.size() + 1, -1));
+        ocol.push_back(ent[0].first);
+        oval.push_back(ent[0].second);
+        nnz_g += 1;
       }
-      for (auto& pv : ent) { ocol.push_back(pv.first); oval.push_back(pv.second); }
-      nnz_g += (long long)ent.size();
-      optr.push_back((int)ocol.size());
-      orow.push_back(ro);
     }
-    const int r1 = (int)orow.size();
+    for (size_t i = 0; i < multi.size(); ++i) {
+      lrows.push_back(descriptor(mro[i], (int)ocol.size(), (int)(ocol.size() + multi[i].size()), -1));
+      for (auto& pv : multi[i]) {
+        ocol.push_back(pv.first);
+        oval.push_back(pv.second);
+      }
+      nnz_g += (long long)multi[i].size();
+    }
+    const int r1 = (int)lrows.size();
     if (cols[g] == 0) continue;
     m.nin += (double)nrows_in[g] * cols[g];
     m.nout += (double)(r1 - r0 + (int)hro.size()) * cols[g];
@@ -384,13 +465,13 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
         for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
     if (!hro.empty()) {
+      const int h0 = (int)hrows_all.size();
       const int H = (int)hro.size(), Nin = nrows_in[g], Nin4 = (Nin + 3) / 4 * 4;
       BsHeavy hv{g, H, Nin, Nin4, cols[g], ldg[g], in_off[g], (long long)hw.size(), m.ntmp};
       hw.resize(hw.size() + (size_t)H * Nin4, 0.0);
       for (int i = 0; i < H; ++i) {
         for (auto& pv : hrows[i]) hw[(size_t)hv.w_off + (size_t)i * Nin4 + pv.first] += pv.second;
-        horow.push_back(hro[i]);
-        hbase.push_back(m.ntmp + (long long)i * ldg[g]);
+        hrows_all.push_back(descriptor(hro[i], 0, 0, m.ntmp + (long long)i * ldg[g]));
       }
       m.ntmp += (long long)H * ldg[g];
       m.flops += 2.0 * (double)H * Nin * cols[g];
@@ -398,13 +479,14 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
       m.el_heavy += (double)H * Nin + (double)Nin * cols[g] + (double)H * cols[g];
       m.el_scatter += 2.0 * (double)H * cols[g];
       m.heavy.push_back(hv);
-      const int q1 = (int)horow.size();
+      const int q1 = (int)hrows_all.size();
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
         for (int q0 = h0; q0 < q1; q0 += MIX_ROWS) htiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, q1)));
     }
   }
   if (ocol.empty()) { ocol.push_back(0); oval.push_back(0.0); }
-  if (horow.empty()) { horow.push_back(make_int2(0, 0)); hbase.push_back(0); }
+  if (lrows.empty()) lrows.push_back(MixRow{});
+  if (hrows_all.empty()) hrows_all.push_back(MixRow{});
   if (hw.empty()) hw.push_back(0.0);
   std::vector<float> oval32(oval.begin(), oval.end());
   std::vector<float> hw32(hw.begin(), hw.end());
@@ -413,14 +495,12 @@ static void build_mix(Engine& E, BsMix& m, const SiteOp& so, const std::vector<Q
   hipStream_t s = E.stream;
   up(m.tiles, tiles, s);
   up(m.groups, groups, s);
-  up(m.optr, optr, s);
+  up(m.rows, lrows, s);
   up(m.ocol, ocol, s);
   up(m.oval64, oval, s);
   up(m.oval32, oval32, s);
-  up(m.orow, orow, s);
   if (!htiles.empty()) up(m.htiles, htiles, s);
-  up(m.horow, horow, s);
-  up(m.hbase, hbase, s);
+  up(m.hrows, hrows_all, s);
   up(m.hw64, hw, s);
   up(m.hw32, hw32, s);
 }
@@ -548,30 +628,40 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   }
   p.ntiles1 = (int)tiles1.size();
 
-  // stage 4 tables: delta classes of the output channels
+  // stage 4 tables: charge classes of the output channels; in the panel of right
+  // sector beta' the K index runs over the source sectors beta, and within one
+  // over the channels of the class beta' - beta in channel order (rank), then j
   std::map<Q2, int> dcls;
-  std::vector<int> ccls(RCx);
+  std::vector<int> ccls(RCx), crank(RCx);
+  std::vector<std::vector<int>> members;
   for (int C = 0; C < RCx; ++C) {
     auto it = dcls.find(dC[C]);
-    if (it == dcls.end()) it = dcls.emplace(dC[C], (int)dcls.size()).first;
+    if (it == dcls.end()) {
+      it = dcls.emplace(dC[C], (int)dcls.size()).first;
+      members.emplace_back();
+    }
     ccls[C] = it->second;
+    crank[C] = (int)members[it->second].size();
+    members[it->second].push_back(C);
   }
   p.ndcls = (int)dcls.size();
   std::vector<int> bshift((size_t)p.ndcls * nbe, -1);
   for (auto& kv : dcls)
     for (int be = 0; be < nbe; ++be) bshift[(size_t)kv.second * nbe + be] = SB.find(add(SB.q[be], kv.first));
-  std::vector<int> koff((size_t)nbe * RCx, -1), kbeta(nbe, 0);
+  std::vector<int> kstart((size_t)nbe * nbe, -1), kbeta(nbe, 0);
   std::vector<BsPair> pairs;
   std::vector<long long> rbase(nbe, 0);
   long long nrs = 0;
   for (int bp = 0; bp < nbe; ++bp) {
     rbase[bp] = nrs;
-    for (int C = 0; C < RCx; ++C) {
-      const int be = SB.find(sub(SB.q[bp], dC[C]));
-      if (be < 0) continue;
-      koff[(size_t)bp * RCx + C] = kbeta[bp];
-      pairs.push_back(BsPair{C, be, kbeta[bp], bp});
-      kbeta[bp] += SB.n[be];
+    for (int be = 0; be < nbe; ++be) {
+      auto it = dcls.find(sub(SB.q[bp], SB.q[be]));
+      if (it == dcls.end()) continue;
+      kstart[(size_t)bp * nbe + be] = kbeta[bp];
+      for (int C : members[it->second]) {
+        pairs.push_back(BsPair{C, be, kbeta[bp], bp});
+        kbeta[bp] += SB.n[be];
+      }
     }
     nrs += (long long)kbeta[bp] * SB.n[bp];
   }
@@ -630,20 +720,27 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   up(p.specoff, specoff, s);
   up(p.nbeta, SB.n, s);
   up(p.boff, SB.off, s);
-  up(p.rowbase2, rowbase2, s);
-  up(p.ccls, ccls, s);
   up(p.bshift, bshift, s);
   up(p.pbase, pbase, s);
   up(p.kbeta, kbeta, s);
-  up(p.koff, koff, s);
+  up(p.kstart, kstart, s);
   up(p.tiles4, tiles4, s);
   up(p.red, red, s);
   up(p.rowdst, rowdst, s);
   up(p.pairs, pairs, s);
   up(p.rbase, rbase, s);
   // mixes: site k (inputs T1 rows, outputs into T2) and site k+1 (inputs T2 rows, outputs into panels)
-  build_mix(E, p.m1, w1, dB, RB, idx1, grp1, gid, gq, cols, ldg, off1, nr1, spec0, nspec);
-  build_mix(E, p.m2, w2, dC, RCx, idx2, grp2, gid, gq, cols, ldg, off2, nr2, spec0, nspec);
+  // charge class of the second-mix output channels per group and output site state
+  std::vector<std::array<int, 4>> gcls(ng);
+  for (int g = 0; g < ng; ++g)
+    for (int z = 0; z < 4; ++z) {
+      auto it = dcls.find(sub(kSiteQ[z], gq[g]));
+      gcls[g][z] = it == dcls.end() ? -1 : it->second;
+    }
+  std::vector<std::array<int, 4>> nocls(ng, std::array<int, 4>{-1, -1, -1, -1});
+  build_mix(E, p.m1, 1, w1, dB, RB, idx1, grp1, gid, gq, cols, ldg, off1, nr1, spec0, nspec, rowbase2, crank, nocls);
+  build_mix(E, p.m2, 2, w2, dC, RCx, idx2, grp2, gid, gq, cols, ldg, off2, nr2, spec0, nspec, rowbase2, crank,
+            gcls);
   up(p.m1.spec, spec, s);
   up(p.m2.spec, spec, s);
   p.have64 = p.have32 = false;
@@ -698,11 +795,10 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
   const int slot0 = MODE == 1 ? 1 : 4;
   if (m.ntiles > 0) {
     hipLaunchKernelGGL((mix_kernel<T, MODE, false>), dim3(m.ntiles), dim3(MIX_COLS), 0, s, m.tiles.as<int4>(),
-                       m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
-                       m.orow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,
-                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
-                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
-                       rnd ? 1 : 0, (const long long*)nullptr, (const T*)nullptr);
+                       m.groups.as<BsGroup>(), m.rows.as<MixRow>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
+                       m.spec.as<int4>(), in, nin, out, nout, err, p.nbe, p.specoff.as<long long>(),
+                       p.bshift.as<int>(), p.pbase.as<long long>(), p.kbeta.as<int>(), p.kstart.as<int>(),
+                       p.nbeta.as<int>(), rnd ? 1 : 0, (const T*)nullptr, 0LL);
     BSCHECK(hipGetLastError());
     E.kt_mark(slot0);
   }
@@ -711,11 +807,10 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
     gemm_grouped<T>(gdev.template as<GemmGroup<T>>(), gg, s);
     E.kt_mark(slot0 + 1);
     hipLaunchKernelGGL((mix_kernel<T, MODE, true>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<int4>(),
-                       m.groups.as<BsGroup>(), m.optr.as<int>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
-                       m.horow.as<int2>(), m.spec.as<int4>(), in, nin, out, nout, err, p.nbe,
-                       p.rowbase2.as<long long>(), p.specoff.as<long long>(), p.ccls.as<int>(), p.bshift.as<int>(),
-                       p.pbase.as<long long>(), p.kbeta.as<int>(), p.koff.as<int>(), p.RCx, p.nbeta.as<int>(),
-                       rnd ? 1 : 0, m.hbase.as<long long>(), (const T*)tmp);
+                       m.groups.as<BsGroup>(), m.hrows.as<MixRow>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
+                       m.spec.as<int4>(), in, nin, out, nout, err, p.nbe, p.specoff.as<long long>(),
+                       p.bshift.as<int>(), p.pbase.as<long long>(), p.kbeta.as<int>(), p.kstart.as<int>(),
+                       p.nbeta.as<int>(), rnd ? 1 : 0, (const T*)tmp, m.ntmp);
     BSCHECK(hipGetLastError());
     E.kt_mark(slot0 + 2);
   }
