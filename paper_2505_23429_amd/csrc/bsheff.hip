@@ -276,57 +276,100 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
 // ---------------------------------------------------------------------------
 // stage 4: partial[slot] = panel rows [m0, m0+64) x stacked R columns [n0, n0+64)
 // over K in [k0, k1); the reduction sums the K chunks and writes rows of y.
-// ---------------------------------------------------------------------------
+// One stage-4 tile on the matrix cores: four waves of 16 panel rows each,
+// 16 x 16 x 4 MFMA blocks over the (at most four) 16-column blocks that lie
+// inside N, K staged through two LDS buffers (the next K slice is fetched into
+// registers while the current one is multiplied).  Accumulator register v of
+// lane l holds D[4*(l/16)+v][l%16] (FP32) or D[4*v+l/16][l%16] (FP64).
 template <typename T>
-__global__ __launch_bounds__(256) void stage4_kernel(const BsS4Tile* __restrict__ tiles, const T* __restrict__ A,
-                                                     long long nA, const T* __restrict__ B, long long nB,
-                                                     T* __restrict__ part, int* __restrict__ err) {
+__device__ inline void s4_mfma(T a, T b, T (&c)[4]);
+template <>
+__device__ inline void s4_mfma<float>(float a, float b, float (&c)[4]) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 x = {c[0], c[1], c[2], c[3]};
+  x = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, x, 0, 0, 0);
+  c[0] = x[0]; c[1] = x[1]; c[2] = x[2]; c[3] = x[3];
+}
+template <>
+__device__ inline void s4_mfma<double>(double a, double b, double (&c)[4]) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  v4 x = {c[0], c[1], c[2], c[3]};
+  x = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, x, 0, 0, 0);
+  c[0] = x[0]; c[1] = x[1]; c[2] = x[2]; c[3] = x[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void stage4_mfma_kernel(const BsS4Tile* __restrict__ tiles, const T* __restrict__ A,
+                                                          long long nA, const T* __restrict__ B, long long nB,
+                                                          T* __restrict__ part, int* __restrict__ err) {
   const BsS4Tile t = tiles[blockIdx.x];
   if (t.abase < 0 || t.abase + (long long)t.M * t.K > nA || t.bbase < 0 || t.bbase + (long long)t.K * t.N > nB) {
     if (threadIdx.x == 0) err[0] = 8;
     return;
   }
-  __shared__ T As[KT][TILE + 1];
-  __shared__ T Bs[KT][TILE + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  constexpr int KS = sizeof(T) == 4 ? 32 : 16;  // K slice (two LDS buffers stay under 64 KB)
+  constexpr int RUNL = KS / 4;                   // elements per thread per operand slice
+  __shared__ T As[2][KS][TILE + 4];
+  __shared__ T Bs[2][KS][TILE + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nvalid = min(TILE, t.N - t.n0);
+  const int nblk = (nvalid + 15) >> 4;
+  // global -> register runs: A (64 rows x KS: row tid/4, RUNL consecutive k), B (KS x 64: k tid*RUNL/64, RUNL columns)
+  const int ar = tid >> 2, ak = (tid & 3) * RUNL;
+  const int bk = tid / (TILE / RUNL), bn = (tid % (TILE / RUNL)) * RUNL;
+  T ra[RUNL], rb[RUNL];
+  auto fetch = [&](int k0) {
+    const long long arow = t.abase + (long long)(t.m0 + ar) * t.K;
+    const bool rowok = t.m0 + ar < t.M;
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) {
+      const int k = k0 + ak + u;
+      ra[u] = (rowok && k < t.k1) ? A[arow + k] : T(0);
+    }
+    const int kb = k0 + bk;
+    const long long brow = t.bbase + (long long)kb * t.N + t.n0;
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) rb[u] = (kb < t.k1 && bn + u < nvalid) ? B[brow + bn + u] : T(0);
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) As[buf][ak + u][ar] = ra[u];
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) Bs[buf][bk][bn + u] = rb[u];
+  };
   T acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-  for (int k0 = t.k0; k0 < t.k1; k0 += KT) {
-    for (int e = tid; e < TILE * KT; e += 256) {
-      const int r = e / KT, kk = e % KT;
-      T v = T(0);
-      if (t.m0 + r < t.M && k0 + kk < t.k1) v = A[t.abase + (long long)(t.m0 + r) * t.K + k0 + kk];
-      As[kk][r] = v;
+    for (int v = 0; v < 4; ++v) acc[j][v] = T(0);
+  int buf = 0;
+  fetch(t.k0);
+  stash(0);
+  __syncthreads();
+  for (int k0 = t.k0; k0 < t.k1; k0 += KS) {
+    const bool more = k0 + KS < t.k1;
+    if (more) fetch(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      const T a = As[buf][kk + (lane >> 4)][wv * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < nblk) s4_mfma<T>(a, Bs[buf][kk + (lane >> 4)][j * 16 + (lane & 15)], acc[j]);
     }
-    for (int e = tid; e < TILE * KT; e += 256) {
-      const int kk = e / TILE, c = e % TILE;
-      T v = T(0);
-      if (t.n0 + c < t.N && k0 + kk < t.k1) v = B[t.bbase + (long long)(k0 + kk) * t.N + t.n0 + c];
-      Bs[kk][c] = v;
+    if (more) {
+      stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
-    __syncthreads();
-    const int kn = min(KT, t.k1 - k0);
-    for (int kk = 0; kk < kn; ++kk) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
-    }
-    __syncthreads();
   }
   T* P = part + (long long)t.slot * (TILE * TILE);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) P[(ty * 4 + i) * TILE + tx + 16 * j] = acc[i][j];
+    for (int v = 0; v < 4; ++v) {
+      const int row = sizeof(T) == 4 ? 4 * (lane >> 4) + v : 4 * v + (lane >> 4);
+      P[(wv * 16 + row) * TILE + j * 16 + (lane & 15)] = acc[j][v];
+    }
 }
 
 template <typename T>
@@ -867,7 +910,7 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   run_mix<T, 1>(E, p, p.m1, E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2, err, false, gg1, E.bs_gg1);
   run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3, gg2, E.bs_gg2);
   if (p.ntiles4 > 0) {
-    hipLaunchKernelGGL((stage4_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
+    hipLaunchKernelGGL((stage4_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
                        E.bs_t3.as<T>(), p.n3, rs.as<T>(), p.nrs, E.bs_part.as<T>(), err);
     BSCHECK(hipGetLastError());
     E.kt_mark(7);
