@@ -71,77 +71,117 @@ __device__ inline float bf16_round(float v) {
 // for each left sector alpha (rows (A, i') with a' in alpha + d_A, columns
 // (s1, s2, j) with b in alpha + q(s1) + q(s2)).
 // ---------------------------------------------------------------------------
+// One stage-1 tile on the matrix cores.  The row and column descriptors
+// of the tile are read once into LDS, the 64 x 64 product is formed with
+// 16 x 16 x 4 MFMA blocks (K is one ket sector, a few slices at most) and
+// staged in LDS, then written with consecutive threads on consecutive columns.
 template <typename T>
-__global__ __launch_bounds__(256) void stage1_kernel(const int4* __restrict__ tiles, const BsAlpha* __restrict__ al,
-                                                     const long long* __restrict__ rsrc, const int4* __restrict__ rinfo,
-                                                     const int4* __restrict__ cinfo,
-                                                     const long long* __restrict__ rowpart,
-                                                     const long long* __restrict__ specoff,
-                                                     const int* __restrict__ nbeta, int nbe, const T* __restrict__ L,
-                                                     long long nL, const T* __restrict__ x, long long nx,
-                                                     long long xld, T* __restrict__ out, long long nout,
-                                                     int* __restrict__ err) {
+__device__ inline void s1_mfma(T a, T b, T (&c)[4]);
+template <>
+__device__ inline void s1_mfma<float>(float a, float b, float (&c)[4]) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 x = {c[0], c[1], c[2], c[3]};
+  x = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, x, 0, 0, 0);
+  c[0] = x[0]; c[1] = x[1]; c[2] = x[2]; c[3] = x[3];
+}
+template <>
+__device__ inline void s1_mfma<double>(double a, double b, double (&c)[4]) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  v4 x = {c[0], c[1], c[2], c[3]};
+  x = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, x, 0, 0, 0);
+  c[0] = x[0]; c[1] = x[1]; c[2] = x[2]; c[3] = x[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void stage1_mfma_kernel(
+    const int4* __restrict__ tiles, const BsAlpha* __restrict__ al, const long long* __restrict__ rsrc,
+    const int4* __restrict__ rinfo, const int4* __restrict__ cinfo, const long long* __restrict__ rowpart,
+    const long long* __restrict__ specoff, const int* __restrict__ nbeta, int nbe, const T* __restrict__ L, long long nL,
+    const T* __restrict__ x, long long nx, long long xld, T* __restrict__ out, long long nout, int* __restrict__ err) {
+  constexpr int KS = sizeof(T) == 4 ? 32 : 16;
+  constexpr int RUNL = KS / 4;
   const int4 t = tiles[blockIdx.x];
   const BsAlpha a = al[t.x];
   const int m0 = t.y, c0 = t.z;
-  __shared__ T Ls[KT][TILE + 1];
-  __shared__ T Xs[KT][TILE + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  __shared__ T As[KS][TILE + 4];
+  __shared__ T Bs[KS][TILE + 4];
+  __shared__ T Cs[TILE][TILE + 1];
+  __shared__ long long rs[TILE];
+  __shared__ int4 ri[TILE], ci[TILE];
+  __shared__ int nb[TILE];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int mrows = min(TILE, a.M - m0), ncols = min(TILE, a.N - c0);
+  if (tid < TILE) {
+    if (tid < mrows) {
+      rs[tid] = rsrc[a.row0 + m0 + tid];
+      ri[tid] = rinfo[a.row0 + m0 + tid];  // {A, i', alpha', -}
+    }
+  } else if (tid < 2 * TILE) {
+    const int c = tid - TILE;
+    if (c < ncols) {
+      const int4 q = cinfo[a.col0 + c0 + c];  // {x column, s1*4+s2, beta, j}
+      ci[c] = q;
+      nb[c] = nbeta[q.z];
+    }
+  }
+  __syncthreads();
+  const int nblk = (ncols + 15) >> 4;
+  const int ar = tid >> 2, ak = (tid & 3) * RUNL;
+  const int bk = tid / (TILE / RUNL), bn = (tid % (TILE / RUNL)) * RUNL;
   T acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-  for (int k0 = 0; k0 < a.K; k0 += KT) {
-    for (int e = tid; e < TILE * KT; e += 256) {
-      const int r = e / KT, kk = e % KT;
+    for (int v = 0; v < 4; ++v) acc[j][v] = T(0);
+  for (int k0 = 0; k0 < a.K; k0 += KS) {
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) {
+      const int k = k0 + ak + u;
       T v = T(0);
-      if (m0 + r < a.M && k0 + kk < a.K) {
-        const long long q = rsrc[a.row0 + m0 + r] + k0 + kk;
+      if (ar < mrows && k < a.K) {
+        const long long q = rs[ar] + k;
         if (q >= 0 && q < nL) v = L[q]; else err[0] = 1;
       }
-      Ls[kk][r] = v;
+      As[ak + u][ar] = v;
     }
-    for (int e = tid; e < TILE * KT; e += 256) {
-      const int kk = e / TILE, c = e % TILE;
+    const int kb = k0 + bk;
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) {
+      const int c = bn + u;
       T v = T(0);
-      if (c0 + c < a.N && k0 + kk < a.K) {
-        const long long q = (long long)(a.oal + k0 + kk) * xld + cinfo[a.col0 + c0 + c].x;
+      if (c < ncols && kb < a.K) {
+        const long long q = (long long)(a.oal + kb) * xld + ci[c].x;
         if (q >= 0 && q < nx) v = x[q]; else err[0] = 2;
       }
-      Xs[kk][c] = v;
+      Bs[bk][c] = v;
     }
     __syncthreads();
-    const int kn = min(KT, a.K - k0);
-    for (int kk = 0; kk < kn; ++kk) {
-      T av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = Ls[kk][ty * 4 + i];
+    for (int kk = 0; kk < KS; kk += 4) {
+      const T av = As[kk + (lane >> 4)][wv * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Xs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+      for (int j = 0; j < 4; ++j)
+        if (j < nblk) s1_mfma<T>(av, Bs[kk + (lane >> 4)][j * 16 + (lane & 15)], acc[j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = m0 + ty * 4 + i;
-    if (r >= a.M) continue;
-    const int4 ri = rinfo[a.row0 + r];  // {A, i', alpha', -}
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = c0 + tx + 16 * j;
-      if (c >= a.N) continue;
-      const int4 ci = cinfo[a.col0 + c];  // {x column, s1*4+s2, beta, j}
-      const long long rp = rowpart[ri.x * 4 + (ci.y >> 2)];
-      const long long so = specoff[((long long)ri.z * 4 + (ci.y & 3)) * nbe + ci.z];
-      const long long d = rp + so + (long long)ri.y * nbeta[ci.z] + ci.w;
-      if (rp < 0 || so < 0 || d >= nout) { err[0] = 3; continue; }
-      out[d] = acc[i][j];
+    for (int v = 0; v < 4; ++v) {
+      const int row = sizeof(T) == 4 ? 4 * (lane >> 4) + v : 4 * v + (lane >> 4);
+      Cs[wv * 16 + row][j * 16 + (lane & 15)] = acc[j][v];
     }
+  __syncthreads();
+  for (int e = tid; e < TILE * TILE; e += 256) {
+    const int r = e / TILE, c = e % TILE;
+    if (r >= mrows || c >= ncols) continue;
+    const int4 R = ri[r], Cc = ci[c];
+    const long long rp = rowpart[R.x * 4 + (Cc.y >> 2)];
+    const long long so = specoff[((long long)R.z * 4 + (Cc.y & 3)) * nbe + Cc.z];
+    const long long d = rp + so + (long long)R.y * nb[c] + Cc.w;
+    if (rp < 0 || so < 0 || d >= nout) { err[0] = 3; continue; }
+    out[d] = Cs[r][c];
   }
 }
 
@@ -899,7 +939,7 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   if (!gg2.empty()) upload(E.bs_gg2, gg2.data(), gg2.size() * sizeof(GemmGroup<T>), s);
   E.kt_begin();
   if (p.ntiles1 > 0) {
-    hipLaunchKernelGGL((stage1_kernel<T>), dim3(p.ntiles1), dim3(256), 0, s, p.tiles1.as<int4>(),
+    hipLaunchKernelGGL((stage1_mfma_kernel<T>), dim3(p.ntiles1), dim3(256), 0, s, p.tiles1.as<int4>(),
                        p.alpha.as<BsAlpha>(), p.rsrc.as<long long>(), p.rinfo.as<int4>(), p.cinfo.as<int4>(),
                        p.rowpart1.as<long long>(), p.specoff.as<long long>(), p.nbeta.as<int>(), p.nbe, L,
                        (long long)p.RAx * p.rlp * p.rlp, x, (long long)ny, (long long)16 * p.rrp, E.bs_t1.as<T>(),
