@@ -6,7 +6,9 @@
 #include <atomic>
 
 #include <algorithm>
+#include <cstdio>
 #include <map>
+#include <numeric>
 #include <stdexcept>
 
 namespace tt {
@@ -192,8 +194,9 @@ __global__ __launch_bounds__(256) void stage1_mfma_kernel(
 // columns (C, j)).  Everything that depends on the column only (its
 // destination offset for each of the four output site states) is formed once
 // per thread; a row then costs its uniform descriptor, its input loads and one
-// store.  Rows with a single operator entry (nearly all light rows) are taken
-// four at a time so that their loads are in flight together.
+// store.  Rows with a single operator entry (nearly all light rows, and heavy rows
+// with one entry outside the GEMM) are taken four at a time so that their loads
+// are in flight together.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ inline long long pick4(long long a0, long long a1, long long a2, long long a3, int i) {
@@ -272,39 +275,45 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
   };
   auto value = [&](const MixRow& R) {
     T acc = T(0);
-    if (HEAVY) {
-      const long long q = R.h + col;  // heavy row: sum formed by the GEMM
-      if (R.h >= 0 && q < ntmp) acc = tmp[q]; else err[0] = 4;
-    } else {
-      for (int e = R.e0; e < R.e1; ++e) {
-        const long long q = (long long)ocol[e] * ld;
-        if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 4;
-      }
+    if (HEAVY && R.h >= 0) {
+      const long long q = R.h + col;
+      if (q < ntmp) acc = tmp[q]; else err[0] = 4;
+    }
+    for (int e = R.e0; e < R.e1; ++e) {
+      const long long q = (long long)ocol[e] * ld;
+      if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 4;
     }
     return acc;
   };
+  auto staged = [&](const MixRow& R) {
+    // heavy row: the part over the shared input rows formed by the GEMM
+    if (!HEAVY || R.h < 0) return T(0);
+    const long long q = R.h + col;
+    if (q < ntmp) return tmp[q];
+    err[0] = 4;
+    return T(0);
+  };
   int r = t.z;
-  if (!HEAVY) {
-    for (; r + 4 <= t.w; r += 4) {
-      const MixRow R0 = rows[r], R1 = rows[r + 1], R2 = rows[r + 2], R3 = rows[r + 3];
-      if (R0.e1 - R0.e0 == 1 && R1.e1 - R1.e0 == 1 && R2.e1 - R2.e0 == 1 && R3.e1 - R3.e0 == 1) {
-        const long long q0 = (long long)ocol[R0.e0] * ld, q1 = (long long)ocol[R1.e0] * ld;
-        const long long q2 = (long long)ocol[R2.e0] * ld, q3 = (long long)ocol[R3.e0] * ld;
-        if (q0 < 0 || q0 >= lim || q1 < 0 || q1 >= lim || q2 < 0 || q2 >= lim || q3 < 0 || q3 >= lim) {
-          err[0] = 4;
-          continue;
-        }
-        const T v0 = src[q0], v1 = src[q1], v2 = src[q2], v3 = src[q3];
-        store(R0, oval[R0.e0] * v0);
-        store(R1, oval[R1.e0] * v1);
-        store(R2, oval[R2.e0] * v2);
-        store(R3, oval[R3.e0] * v3);
-      } else {
-        store(R0, value(R0));
-        store(R1, value(R1));
-        store(R2, value(R2));
-        store(R3, value(R3));
+  for (; r + 4 <= t.w; r += 4) {
+    const MixRow R0 = rows[r], R1 = rows[r + 1], R2 = rows[r + 2], R3 = rows[r + 3];
+    if (R0.e1 - R0.e0 == 1 && R1.e1 - R1.e0 == 1 && R2.e1 - R2.e0 == 1 && R3.e1 - R3.e0 == 1) {
+      const long long q0 = (long long)ocol[R0.e0] * ld, q1 = (long long)ocol[R1.e0] * ld;
+      const long long q2 = (long long)ocol[R2.e0] * ld, q3 = (long long)ocol[R3.e0] * ld;
+      if (q0 < 0 || q0 >= lim || q1 < 0 || q1 >= lim || q2 < 0 || q2 >= lim || q3 < 0 || q3 >= lim) {
+        err[0] = 4;
+        continue;
       }
+      const T v0 = src[q0], v1 = src[q1], v2 = src[q2], v3 = src[q3];
+      const T h0 = staged(R0), h1 = staged(R1), h2 = staged(R2), h3 = staged(R3);
+      store(R0, h0 + oval[R0.e0] * v0);
+      store(R1, h1 + oval[R1.e0] * v1);
+      store(R2, h2 + oval[R2.e0] * v2);
+      store(R3, h3 + oval[R3.e0] * v3);
+    } else {
+      store(R0, value(R0));
+      store(R1, value(R1));
+      store(R2, value(R2));
+      store(R3, value(R3));
     }
   }
   for (; r < t.w; ++r) {
@@ -460,7 +469,7 @@ static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std
                       const std::vector<int>& rowidx_in, const std::vector<int>& grp_in, const std::map<Q2, int>& gid,
                       const std::vector<Q2>& gq, const std::vector<int>& cols, const std::vector<int>& ldg,
                       const std::vector<long long>& in_off, const std::vector<int>& nrows_in,
-                      const std::vector<int>& spec0, const std::vector<int>& nspec,
+                      const std::vector<int>& nshared, const std::vector<int>& spec0, const std::vector<int>& nspec,
                       const std::vector<long long>& rowbase2, const std::vector<int>& crank,
                       const std::vector<std::array<int, 4>>& gcls) {
   const int ng = (int)gq.size();
@@ -548,20 +557,50 @@ static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
         for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
     if (!hro.empty()) {
+      // GEMM over the group's shared input rows [0, Kd); the other entries of a heavy
+      // row are added by the scatter pass
       const int h0 = (int)hrows_all.size();
-      const int H = (int)hro.size(), Nin = nrows_in[g], Nin4 = (Nin + 3) / 4 * 4;
-      BsHeavy hv{g, H, Nin, Nin4, cols[g], ldg[g], in_off[g], (long long)hw.size(), m.ntmp};
-      hw.resize(hw.size() + (size_t)H * Nin4, 0.0);
+      const int H = (int)hro.size(), Nin = nrows_in[g];
+      // split only where it is cheaper (per spectator column: GEMM flops at ~50 TFLOP/s
+      // against gathered bytes at ~1 TB/s); else the GEMM runs over the whole group
+      long long nres_split = 0;
+      for (int i = 0; i < H; ++i)
+        for (auto& pv : hrows[i]) nres_split += pv.first >= nshared[g];
+      const double cost_full = 2.0 * H * Nin / 5e13;
+      const double cost_split = 2.0 * H * nshared[g] / 5e13 + 4.0 * (double)nres_split / 1e12;
+      const int Kd = cost_split < cost_full ? nshared[g] : Nin, Kd4 = (Kd + 3) / 4 * 4;
+      BsHeavy hv{g, H, Kd, Kd4, cols[g], ldg[g], in_off[g], (long long)hw.size(), m.ntmp};
+      hw.resize(hw.size() + (size_t)H * Kd4, 0.0);
+      long long nres = 0;
+      // rows with exactly one entry outside the GEMM first (the scatter takes them in fours)
+      std::vector<int> ord(H);
+      std::iota(ord.begin(), ord.end(), 0);
+      auto nout_of = [&](int i) {
+        int c = 0;
+        for (auto& pv : hrows[i]) c += pv.first >= Kd;
+        return c;
+      };
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return (nout_of(x) != 1) < (nout_of(y) != 1); });
       for (int i = 0; i < H; ++i) {
-        for (auto& pv : hrows[i]) hw[(size_t)hv.w_off + (size_t)i * Nin4 + pv.first] += pv.second;
-        hrows_all.push_back(descriptor(hro[i], 0, 0, m.ntmp + (long long)i * ldg[g]));
+        const int hi = ord[i];
+        const int e0 = (int)ocol.size();
+        for (auto& pv : hrows[hi]) {
+          if (pv.first < Kd) {
+            hw[(size_t)hv.w_off + (size_t)i * Kd4 + pv.first] += pv.second;
+          } else {
+            ocol.push_back(pv.first);
+            oval.push_back(pv.second);
+          }
+        }
+        nres += (long long)ocol.size() - e0;
+        hrows_all.push_back(descriptor(hro[hi], e0, (int)ocol.size(), Kd > 0 ? m.ntmp + (long long)i * ldg[g] : -1));
       }
-      m.ntmp += (long long)H * ldg[g];
-      m.flops += 2.0 * (double)H * Nin * cols[g];
-      m.fl_heavy += 2.0 * (double)H * Nin * cols[g];
-      m.el_heavy += (double)H * Nin + (double)Nin * cols[g] + (double)H * cols[g];
-      m.el_scatter += 2.0 * (double)H * cols[g];
-      m.heavy.push_back(hv);
+      if (Kd > 0) m.ntmp += (long long)H * ldg[g];
+      m.flops += 2.0 * ((double)H * Kd + (double)nres) * cols[g];
+      m.fl_heavy += 2.0 * (double)H * Kd * cols[g];
+      m.el_heavy += (double)H * Kd + (double)Kd * cols[g] + (double)H * cols[g];
+      m.el_scatter += (2.0 * H + (double)nres) * cols[g];
+      if (Kd > 0) m.heavy.push_back(hv);
       const int q1 = (int)hrows_all.size();
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
         for (int q0 = h0; q0 < q1; q0 += MIX_ROWS) htiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, q1)));
@@ -640,23 +679,55 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
     spec.insert(spec.end(), spec_g[g].begin(), spec_g[g].end());
   }
 
-  // row grouping of T1 (rows (A, s1)) and T2 (rows (B, s2))
-  auto rows_of = [&](const std::vector<Q2>& d, int n, std::vector<int>& idx, std::vector<int>& grp,
-                     std::vector<int>& nrows) {
+  // Inputs shared by the heavy rows of a mix: an output row with more than HEAVY_MIN
+  // operator entries goes through a dense GEMM, but its entries typically split into
+  // a few input rows common to most heavy rows of the group and one or two of its
+  // own.  The common input rows are stored first in their group so that the GEMM
+  // runs over them only; the remaining entries are added by the scatter pass.
+  auto shared_inputs = [&](const SiteOp& so, const std::vector<Q2>& dout, int nout_ch, int nin_ch) {
+    std::vector<int> cnt((size_t)nin_ch * 4, 0), heavy(ng, 0);
+    std::vector<int> ent;
+    for (int K = 0; K < nout_ch; ++K)
+      for (int sp = 0; sp < 4; ++sp) {
+        if (gid.find(sub(kSiteQ[sp], dout[K])) == gid.end()) continue;
+        ent.clear();
+        for (int e = so.hptr[K]; e < so.hptr[K + 1]; ++e)
+          for (int s = 0; s < 4; ++s)
+            if (so.hop[(size_t)e * 16 + sp * 4 + s] != 0.0) ent.push_back(so.hsrc[e] * 4 + s);
+        if ((int)ent.size() <= HEAVY_MIN) continue;
+        ++heavy[gid.find(sub(kSiteQ[sp], dout[K]))->second];
+        for (int id : ent) ++cnt[id];
+      }
+    return std::make_pair(cnt, heavy);
+  };
+  // row grouping of T1 (rows (A, s1)) and T2 (rows (B, s2)); shared heavy inputs first
+  auto rows_of = [&](const std::vector<Q2>& d, int n, const std::vector<int>& cnt, const std::vector<int>& heavy,
+                     std::vector<int>& idx, std::vector<int>& grp, std::vector<int>& nrows, std::vector<int>& nshared) {
     idx.assign((size_t)n * 4, -1);
     grp.assign((size_t)n * 4, -1);
     nrows.assign(ng, 0);
+    nshared.assign(ng, 0);
+    std::vector<char> sh((size_t)n * 4, 0);
     for (int K = 0; K < n; ++K)
       for (int s = 0; s < 4; ++s) {
         auto it = gid.find(sub(kSiteQ[s], d[K]));
         if (it == gid.end()) continue;
         grp[K * 4 + s] = it->second;
-        idx[K * 4 + s] = nrows[it->second]++;
+        const int H = heavy[it->second];
+        sh[K * 4 + s] = H > 0 && cnt[K * 4 + s] >= std::max(4, H / 16);
+      }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < n * 4; ++i) {
+        if (grp[i] < 0 || (sh[i] != 0) != (pass == 0)) continue;
+        idx[i] = nrows[grp[i]]++;
+        if (pass == 0) ++nshared[grp[i]];
       }
   };
-  std::vector<int> idx1, grp1, nr1, idx2, grp2, nr2;
-  rows_of(dA, RAx, idx1, grp1, nr1);
-  rows_of(dB, RB, idx2, grp2, nr2);
+  auto u1 = shared_inputs(w1, dB, RB, RAx);
+  auto u2 = shared_inputs(w2, dC, RCx, RB);
+  std::vector<int> idx1, grp1, nr1, idx2, grp2, nr2, ns1, ns2;
+  rows_of(dA, RAx, u1.first, u1.second, idx1, grp1, nr1, ns1);
+  rows_of(dB, RB, u2.first, u2.second, idx2, grp2, nr2, ns2);
   // group rows are stored with a stride rounded up to 4 elements (16-byte aligned rows)
   std::vector<int> ldg(ng);
   for (int g = 0; g < ng; ++g) ldg[g] = (cols[g] + 3) / 4 * 4;
@@ -821,11 +892,22 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
       gcls[g][z] = it == dcls.end() ? -1 : it->second;
     }
   std::vector<std::array<int, 4>> nocls(ng, std::array<int, 4>{-1, -1, -1, -1});
-  build_mix(E, p.m1, 1, w1, dB, RB, idx1, grp1, gid, gq, cols, ldg, off1, nr1, spec0, nspec, rowbase2, crank, nocls);
-  build_mix(E, p.m2, 2, w2, dC, RCx, idx2, grp2, gid, gq, cols, ldg, off2, nr2, spec0, nspec, rowbase2, crank,
+  build_mix(E, p.m1, 1, w1, dB, RB, idx1, grp1, gid, gq, cols, ldg, off1, nr1, ns1, spec0, nspec, rowbase2, crank,
+            nocls);
+  build_mix(E, p.m2, 2, w2, dC, RCx, idx2, grp2, gid, gq, cols, ldg, off2, nr2, ns2, spec0, nspec, rowbase2, crank,
             gcls);
   up(p.m1.spec, spec, s);
   up(p.m2.spec, spec, s);
+  if (E.verbose_level >= 2) {
+    std::fprintf(stderr, "[tt] window %d: rl %d rr %d groups %d stage-1 tiles %d stage-4 tiles %d; mix tiles %d/%d", b,
+                 rlp, rrp, ng, p.ntiles1, p.ntiles4, p.m1.ntiles, p.m2.ntiles);
+    for (int mi = 0; mi < 2; ++mi) {
+      const BsMix& m = mi == 0 ? p.m1 : p.m2;
+      std::fprintf(stderr, "; heavy GEMMs of mix %d (H x cols x Nin):", mi + 1);
+      for (const BsHeavy& h : m.heavy) std::fprintf(stderr, " %dx%dx%d", h.H, h.cols, h.Nin);
+    }
+    std::fprintf(stderr, "\n");
+  }
   p.have64 = p.have32 = false;
   // unique over all engines: a workspace is zeroed again whenever it meets a plan it has not seen
   static std::atomic<long long> plan_serial{0};

@@ -258,7 +258,8 @@ Engine::Engine(const tt_opts& o)
     : opts(o), prob(std::make_shared<Problem>()), L(prob->L), mpo(prob->mpo), Rb(prob->Rb), chan_q(prob->chan_q),
       chan_q_dev(prob->chan_q_dev) {
   const char* v = std::getenv("TT_VERBOSE");
-  verbose = v && std::atoi(v) > 0;
+  verbose_level = v ? std::atoi(v) : 0;
+  verbose = verbose_level > 0;
   HC(hipSetDevice(o.device));
   HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   RC(rocblas_create_handle(&blas));
@@ -271,6 +272,7 @@ Engine::Engine(const Engine& parent, int)
       chan_q_dev(prob->chan_q_dev) {
   is_worker = true;
   verbose = parent.verbose;
+  verbose_level = parent.verbose_level;
   have_mpo = parent.have_mpo;
   HC(hipSetDevice(opts.device));
   HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));

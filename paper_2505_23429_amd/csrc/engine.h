@@ -188,6 +188,7 @@ class Engine {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;
+  int verbose_level = 0;
   // per-kernel statistics of the effective-Hamiltonian products (tt_kernel_timing):
   // kstat[slot] = {ms, launches, algorithmic flops, algorithmic bytes}; slots
   // 0 L.x GEMM, 1/2/3 site-1 mix (gather, heavy-row GEMM, heavy-row scatter),

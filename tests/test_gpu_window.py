@@ -114,8 +114,10 @@ def _qn_env_dev(gen, lab, chan):
 
 
 # full-size windows: (L, integrals seed, chi, MPS seed, window, precision)
-FULL = [(32, 1003, 512, 1004, 13, "f32"), (32, 1003, 512, 1004, 15, "f32"),
-        (16, 1002, 256, 1003, 7, "f64"), (24, 1004, 1024, 1005, 12, "bf16")]
+# (windows right of the coefficient-block site have heavy output rows whose operator
+# entries split into shared inputs and private ones)
+FULL = [(32, 1003, 512, 1004, 13, "f32"), (32, 1003, 512, 1004, 15, "f32"), (32, 1003, 512, 1004, 20, "f32"),
+        (16, 1002, 256, 1003, 7, "f64"), (16, 1002, 256, 1003, 10, "f64"), (24, 1004, 1024, 1005, 12, "bf16")]
 
 
 @pytest.mark.timeout(900)
