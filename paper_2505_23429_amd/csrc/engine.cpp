@@ -282,8 +282,8 @@ Engine::Engine(const Engine& parent, int)
   HC(hipEventCreate(&ev1));
 }
 int Engine::aux_lanes() {
-  constexpr int kLanes = 4;
-  if (is_worker) return 0;
+  // context engine: 4 lanes; each worker engine: 2 (several workers already share the device)
+  const int kLanes = is_worker ? 2 : 4;
   while ((int)aux_stream.size() < kLanes) {
     hipStream_t s = nullptr;
     HC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
