@@ -414,6 +414,38 @@ void Engine::set_mpo(int L_, const int* R, const int* nnz, const int32_t* const*
         }
       }
       upload(s.V, Vh.data(), Vh.size() * sizeof(double), stream);
+      // charge classes of the block (a coupling of unequal channel charges would break
+      // charge conservation: the block entries carry the identity local operator)
+      {
+        std::map<Q2, int> cid;
+        for (int pp = 0; pp < nP; ++pp) {
+          const Q2 d = q[k][p0 + pp];
+          auto it = cid.find(d);
+          if (it == cid.end()) {
+            it = cid.emplace(d, (int)s.vcls.size()).first;
+            s.vcls.emplace_back();
+            s.vcls.back().d = d;
+          }
+          s.vcls[it->second].P.push_back(pp);
+        }
+        for (int qq = 0; qq < nQ; ++qq) {
+          auto it = cid.find(q[k + 1][q0 + qq]);
+          if (it != cid.end()) s.vcls[it->second].Q.push_back(qq);
+        }
+        for (int qq = 0; qq < nQ; ++qq)
+          for (int pp = 0; pp < nP; ++pp)
+            if (Vh[(size_t)qq * nP + pp] != 0.0 && q[k + 1][q0 + qq] != q[k][p0 + pp])
+              throw std::invalid_argument("coefficient block couples channels of different charge at site " +
+                                          std::to_string(k));
+        for (auto& c : s.vcls) {
+          std::vector<double> vc(std::max<size_t>(c.Q.size() * c.P.size(), 1), 0.0);
+          for (size_t i = 0; i < c.Q.size(); ++i)
+            for (size_t j = 0; j < c.P.size(); ++j) vc[i * c.P.size() + j] = Vh[(size_t)c.Q[i] * nP + c.P[j]];
+          c.Pd = upload_ints(c.P, stream);
+          c.Qd = upload_ints(c.Q.empty() ? std::vector<int>{0} : c.Q, stream);
+          upload(c.V, vc.data(), vc.size() * sizeof(double), stream);
+        }
+      }
       static const double Id[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
       // left use: output q gathers from virtual input Rl + (q - q0)
       vA = nA; vB = nB; vO = nO;
@@ -725,23 +757,52 @@ void Engine::env_right_raw(int rb, int rk, int rb2, int rk2, int RB, const doubl
 
 static inline int kin16(int K) { return ((K + 15) / 16) * 16; }
 
-// channel transform: out[q][:] = sum_p V[q][p] in[p][:]  (transpose=false)
-//                    out[p][:] = sum_q V[q][p] in[q][:]  (transpose=true)
-static void channel_transform(const double* V, int nQ, int nP, const double* in, long long slab, double* out,
-                              bool transpose, hipStream_t s) {
-  GemmArgs g{};
-  g.batch = 1; g.N = (int)slab; g.alpha = 1.0; g.beta = 0.0;
-  g.sBb = 0; g.sBkb = 0; g.sBkk = slab; g.sBn = 1; g.sCb = 0; g.sCm = slab;
-  if (!transpose) {
-    g.M = nQ; g.K = nP; g.kin = kin16(nP);
-    g.sAb = 0; g.sAm = nP; g.sAkb = 0; g.sAkk = 1;
-    gemm<double>(g, V, in, out, true, true, s);
-  } else {
-    g.M = nP; g.K = nQ; g.kin = kin16(nQ);
-    g.sAb = 0; g.sAm = 1; g.sAkb = 0; g.sAkk = nP;
-    gemm<double>(g, V, in, out, false, true, s);
+// The coefficient-block transform of environment slabs [bra r][ket c] (row length cp),
+// restricted by charge: channel class d is non-zero only where q(bra r) - q(ket c) = d,
+// and the block couples only channels of one class.  transpose=false:
+// out[q][:] = sum_p V[q][p] in[p][:]; transpose=true: out[p][:] = sum_q V[q][p] in[q][:]
+// (channel indices relative to the block).  Every other element of the nout output
+// slabs is zero.
+static void channel_transform_qn(Engine& E, const SiteMPO& s, const double* in, long long slab, double* out, int nout,
+                                 const Labels& rq, const Labels& cq, int cp, bool transpose) {
+  fill(out, sizeof(double) * slab * nout, E.stream);
+  std::map<Q2, std::vector<int>> cols_of;
+  for (int c = 0; c < (int)cq.size(); ++c) cols_of[cq[c]].push_back(c);
+  for (const SiteMPO::VClass& c : s.vcls) {
+    if (c.P.empty() || c.Q.empty()) continue;
+    std::vector<int> pos;
+    for (int r = 0; r < (int)rq.size(); ++r) {
+      auto it = cols_of.find(qsub(rq[r], c.d));
+      if (it == cols_of.end()) continue;
+      for (int col : it->second) pos.push_back(r * cp + col);
+    }
+    if (pos.empty()) continue;
+    if ((long long)rq.size() * cp > slab) throw std::runtime_error("channel transform: labels exceed the slab");
+    const int np = (int)pos.size();
+    const int nin = transpose ? (int)c.Q.size() : (int)c.P.size();
+    const int nou = transpose ? (int)c.P.size() : (int)c.Q.size();
+    const int* lin = transpose ? c.Qd.as<int>() : c.Pd.as<int>();
+    const int* lout = transpose ? c.Pd.as<int>() : c.Qd.as<int>();
+    DevMem pd = upload_ints(pos, E.stream);
+    DevMem ci, co;
+    ci.ensure(sizeof(double) * (size_t)nin * np);
+    co.ensure(sizeof(double) * (size_t)nou * np);
+    gather2d(in, slab, lin, nin, pd.as<int>(), np, ci.as<double>(), false, E.stream);
+    GemmArgs g{};
+    g.batch = 1; g.M = nou; g.N = np; g.K = nin; g.kin = kin16(nin); g.alpha = 1.0; g.beta = 0.0;
+    g.sBb = 0; g.sBkb = 0; g.sBkk = np; g.sBn = 1; g.sCb = 0; g.sCm = np; g.sAb = 0; g.sAkb = 0;
+    if (!transpose) {
+      g.sAm = (long long)c.P.size(); g.sAkk = 1;  // V[q][p], row-major [|Q|][|P|]
+      gemm<double>(g, c.V.as<double>(), ci.as<double>(), co.as<double>(), true, true, E.stream);
+    } else {
+      g.sAm = 1; g.sAkk = (long long)c.P.size();  // V^T
+      gemm<double>(g, c.V.as<double>(), ci.as<double>(), co.as<double>(), false, true, E.stream);
+    }
+    scatter2d(co.as<double>(), np, 1, lout, nou, pd.as<int>(), np, out, slab, 1.0, nullptr, nullptr, 0, E.stream);
+    HC(hipStreamSynchronize(E.stream));
   }
 }
+
 
 void Engine::env_unit(Env& e, int R) {
   e.R = R;
@@ -791,8 +852,9 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
       const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
       wsd.ensure(sizeof(double) * slab * (s.Rl + nQ));
       HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rl, hipMemcpyDeviceToDevice, stream));
-      channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.p0 * slab, slab,
-                        wsd.as<double>() + (long long)s.Rl * slab, false, stream);
+      (void)nP;
+      channel_transform_qn(*this, s, in.d.as<double>() + (long long)s.p0 * slab, slab,
+                           wsd.as<double>() + (long long)s.Rl * slab, nQ, bra.ql, ket.ql, rk, false);
       Ein = wsd.as<double>();
     }
     bool done;
@@ -811,8 +873,9 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
     const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
     wsd.ensure(sizeof(double) * slab * (s.Rl + nQ));
     HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rl, hipMemcpyDeviceToDevice, stream));
-    channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.p0 * slab, slab,
-                      wsd.as<double>() + (long long)s.Rl * slab, false, stream);
+    (void)nP;
+    channel_transform_qn(*this, s, in.d.as<double>() + (long long)s.p0 * slab, slab,
+                         wsd.as<double>() + (long long)s.Rl * slab, nQ, bra.ql, ket.ql, rk, false);
     env_left_raw(rb, rk, rb2, rk2, s.Rl + nQ, wsd.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byB_left,
                  s.Rr, o.d.as<double>(), qp);
   } else {
@@ -859,8 +922,9 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
       const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
       wsd.ensure(sizeof(double) * slab * (s.Rr + nP));
       HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rr, hipMemcpyDeviceToDevice, stream));
-      channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.q0 * slab, slab,
-                        wsd.as<double>() + (long long)s.Rr * slab, true, stream);
+      (void)nQ;
+      channel_transform_qn(*this, s, in.d.as<double>() + (long long)s.q0 * slab, slab,
+                           wsd.as<double>() + (long long)s.Rr * slab, nP, bra.qr, ket.qr, rk2, true);
       Ein = wsd.as<double>();
     }
     bool done;
@@ -879,8 +943,9 @@ void Engine::env_right(const Env& in, const Core& bra, const Core& ket, int site
     const int nP = s.p1 - s.p0, nQ = s.q1 - s.q0;
     wsd.ensure(sizeof(double) * slab * (s.Rr + nP));
     HC(hipMemcpyAsync(wsd.p, in.d.p, sizeof(double) * slab * s.Rr, hipMemcpyDeviceToDevice, stream));
-    channel_transform(s.V.as<double>(), nQ, nP, in.d.as<double>() + (long long)s.q0 * slab, slab,
-                      wsd.as<double>() + (long long)s.Rr * slab, true, stream);
+    (void)nQ;
+    channel_transform_qn(*this, s, in.d.as<double>() + (long long)s.q0 * slab, slab,
+                         wsd.as<double>() + (long long)s.Rr * slab, nP, bra.qr, ket.qr, rk2, true);
     env_right_raw(rb, rk, rb2, rk2, s.Rr + nP, wsd.as<double>(), bra.d.as<double>(), ket.d.as<double>(), s.byA_right,
                   s.Rl, o.d.as<double>(), qp);
   } else {
@@ -1861,8 +1926,8 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
     w.RAx = w.RA + nQ;
     w.Lx.ensure(sizeof(double) * sl * w.RAx);
     HC(hipMemcpyAsync(w.Lx.p, Le.d.p, sizeof(double) * sl * w.RA, hipMemcpyDeviceToDevice, E.stream));
-    channel_transform(s1.V.as<double>(), nQ, s1.p1 - s1.p0, Le.d.as<double>() + (long long)s1.p0 * sl, sl,
-                      w.Lx.as<double>() + (long long)w.RA * sl, false, E.stream);
+    channel_transform_qn(E, s1, Le.d.as<double>() + (long long)s1.p0 * sl, sl, w.Lx.as<double>() + (long long)w.RA * sl,
+                         nQ, ql, ql, w.rlp, false);
     w.w1 = &s1.byB_left;
   } else {
     w.RAx = w.RA;
@@ -1875,8 +1940,8 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
     w.P0 = s2.p0;
     w.nP = s2.p1 - s2.p0;
     w.Rt.ensure(sizeof(double) * sr * w.nP);
-    channel_transform(s2.V.as<double>(), s2.q1 - s2.q0, w.nP, Re.d.as<double>() + (long long)s2.q0 * sr, sr,
-                      w.Rt.as<double>(), true, E.stream);
+    channel_transform_qn(E, s2, Re.d.as<double>() + (long long)s2.q0 * sr, sr, w.Rt.as<double>(), w.nP, qr, qr, w.rrp,
+                         true);
     w.w2 = &s2.byB_noblk;
   } else {
     w.nP = 0;

@@ -81,6 +81,14 @@ struct SiteMPO {
   bool has_block = false;
   int p0 = 0, p1 = 0, q0 = 0, q1 = 0;
   DevMem V;                       // [q1-q0][p1-p0] f64 coefficient block
+  // the coefficient block per channel charge class (it only couples channels of equal
+  // charge): block-relative input channels P, output channels Q, V restricted to them
+  struct VClass {
+    Q2 d;
+    std::vector<int> P, Q;
+    DevMem Pd, Qd, V;  // ints, ints, [|Q|][|P|]
+  };
+  std::vector<VClass> vcls;
   SiteOp byB_left;                // block -> virtual pass entries (inputs Rl + q - q0)
   SiteOp byB_noblk;               // block entries removed
   SiteOp byA_right;               // block -> virtual pass entries (inputs Rr + p - p0)
