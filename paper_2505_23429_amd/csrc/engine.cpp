@@ -2151,17 +2151,22 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
       m = keep;
       continue;
     }
-    // new direction: diagonally preconditioned residual, projected out of the subspace twice
+    // new direction: diagonally preconditioned residual, projected out of the subspace
+    // (classical Gram-Schmidt, repeated once when the first pass cancels more than a
+    // factor 1/sqrt(2) of the norm: "twice is enough")
     precond(t, t, w.diag.as<double>(), res.theta, mask.as<uint8_t>(), n, E.stream);
-    double tn0 = norm_dev(E, t, n);
+    const double tn0 = norm_dev(E, t, n);
+    double tn = tn0;
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<double> d;
       dots(V, m, t, d);
       for (double& v : d) v = -v;
       lcomb(V, m, d, u);  // u is free now
       axpy(t, 1.0, u, n, E.stream);
+      const double prev = tn;
+      tn = norm_dev(E, t, n);
+      if (tn >= prev / std::sqrt(2.0)) break;
     }
-    double tn = norm_dev(E, t, n);
     if (!(tn > 1e-10 * tn0) || !(tn > 0.0)) {
       res.converged = res.resid <= tol;
       break;

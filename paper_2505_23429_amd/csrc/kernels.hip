@@ -610,35 +610,56 @@ void mask_apply(double* x, const uint8_t* mask, size_t n, hipStream_t s) {
 }
 
 // two-pass deterministic multi-dot: grid (nblk, m)
-__global__ __launch_bounds__(256) void mdot_partial(const double* V, size_t ldv, const double* w, size_t n,
-                                                    double* partial, int nblk) {
-  const int i = blockIdx.y;
-  const double* v = V + (size_t)i * ldv;
-  double s = 0.0;
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)nblk * blockDim.x) s += v[k] * w[k];
+// partial[i][blk] = sum over the block's grid-stride share of V_i . w; each block
+// takes the vectors eight at a time so that w is read once per eight vectors
+__global__ __launch_bounds__(256) void mdot_partial(const double* __restrict__ V, size_t ldv, int m,
+                                                    const double* __restrict__ w, size_t n, double* __restrict__ partial,
+                                                    int nblk) {
+  __shared__ double red[8][256];
+  for (int i0 = 0; i0 < m; i0 += 8) {
+    const int cnt = min(8, m - i0);
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)nblk * blockDim.x) {
+      const double wk = w[k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (u < cnt) s[u] += V[(size_t)(i0 + u) * ldv + k] * wk;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) red[u][threadIdx.x] = s[u];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) red[u][threadIdx.x] += red[u][threadIdx.x + st];
+      __syncthreads();
+    }
+    if ((int)threadIdx.x < cnt) partial[(size_t)(i0 + threadIdx.x) * nblk + blockIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+// out[i] = sum_blk partial[i][blk], one block per output (fixed-order tree: deterministic)
+__global__ __launch_bounds__(256) void mdot_final(const double* __restrict__ partial, int nblk,
+                                                  double* __restrict__ out) {
   __shared__ double red[256];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(size_t)i * nblk + b];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[(size_t)i * nblk + blockIdx.x] = red[0];
-}
-__global__ void mdot_final(const double* partial, int nblk, int m, double* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)i * nblk + b];
-  out[i] = s;
+  if (threadIdx.x == 0) out[i] = red[0];
 }
 void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, double* out_dev, double* partial,
                int nblk, hipStream_t s) {
   if (m <= 0) return;
   if (m > 65535) throw std::runtime_error("multi_dot: too many vectors");
-  hipLaunchKernelGGL(mdot_partial, dim3(nblk, m), dim3(256), 0, s, V, ldv, w, n, partial, nblk);
+  hipLaunchKernelGGL(mdot_partial, dim3(nblk), dim3(256), 0, s, V, ldv, m, w, n, partial, nblk);
   HIPCHECK(hipGetLastError());
-  hipLaunchKernelGGL(mdot_final, dim3((m + 63) / 64), dim3(64), 0, s, partial, nblk, m, out_dev);
+  hipLaunchKernelGGL(mdot_final, dim3(m), dim3(256), 0, s, partial, nblk, out_dev);
   HIPCHECK(hipGetLastError());
 }
 
