@@ -73,7 +73,7 @@ class BlockPool {
     {
       std::lock_guard<std::mutex> g(mu_);
       auto it = free_.lower_bound(r);
-      if (it != free_.end() && it->first <= r + r / 4) {
+      if (it != free_.end() && it->first <= r + r / 2) {
         cap = it->first;
         void* p = it->second;
         cached_ -= cap;
@@ -82,6 +82,7 @@ class BlockPool {
       }
     }
     void* p = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
     if (hipMalloc(&p, r) != hipSuccess) {
       (void)hipGetLastError();
       trim(0);
@@ -90,10 +91,22 @@ class BlockPool {
         return nullptr;
       }
     }
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      ++stats_[0];
+      stats_[1] += (double)r;
+      stats_[2] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
     cap = r;
     return p;
   }
+  // {device allocations, bytes, seconds in hipMalloc, frees, seconds in hipFree}
+  std::array<double, 5> stats() {
+    std::lock_guard<std::mutex> g(mu_);
+    return stats_;
+  }
   void put(void* p, size_t cap) {
+    const size_t limit = max_cached();
     // work queued on the releasing thread's stream may still read the block (a
     // worker thread's blocks are used on its own stream only; other threads wait
     // for the whole device)
@@ -102,7 +115,7 @@ class BlockPool {
     std::lock_guard<std::mutex> g(mu_);
     free_.emplace(cap, p);
     cached_ += cap;
-    if (cached_ > kMaxCached) trim_locked(kMaxCached / 2);
+    if (cached_ > limit) trim_locked(limit / 2);
   }
   void trim(size_t target) {
     (void)hipDeviceSynchronize();
@@ -111,7 +124,21 @@ class BlockPool {
   }
 
  private:
-  static constexpr size_t kMaxCached = size_t(48) << 30;
+  // released blocks are kept up to 60% of the device memory (a failed allocation
+  // empties the cache and retries)
+  static size_t max_cached() {
+    static const size_t lim = [] {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) {
+        (void)hipGetLastError();
+        return size_t(48) << 30;
+      }
+      return tot / 10 * 6;
+    }();
+    return lim;
+  }
+  // size classes: powers of two up to 1 MiB, then steps of about 1/8 (2 MiB minimum), so
+  // that the many slightly different sizes of a sweep's environments share blocks
   static size_t round(size_t b) {
     if (b <= (size_t(1) << 20)) {
       size_t r = 256;
@@ -119,16 +146,22 @@ class BlockPool {
       return r;
     }
     const size_t g = size_t(2) << 20;
-    return (b + g - 1) / g * g;
+    size_t r = g;
+    while (r < b) r += std::max(g, (r / 8) / g * g);
+    return r;
   }
   void trim_locked(size_t target) {
     while (cached_ > target && !free_.empty()) {
       auto it = std::prev(free_.end());
+      const auto t0 = std::chrono::steady_clock::now();
       (void)hipFree(it->second);
+      stats_[3] += 1.0;
+      stats_[4] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       cached_ -= it->first;
       free_.erase(it);
     }
   }
+  std::array<double, 5> stats_ = {};
   std::mutex mu_;
   std::multimap<size_t, void*> free_;
   size_t cached_ = 0;
@@ -2634,11 +2667,14 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   });
   ph[6] += now() - tph;
   tph = now();
-  if (verbose)
+  if (verbose) {
+    const auto ps = pool().stats();
     std::fprintf(stderr,
                  "[tt] step 3: coarse matrices %.2fs (so far: %d block-sparse env updates %.2fs, %d dense %.2fs, "
-                 "%d overlap updates %.2fs)\n",
-                 ph[6], n_env_bs, t_env_bs, n_env_dense, t_env_dense, n_ov, t_ov);
+                 "%d overlap updates %.2fs; device memory: %.0f allocations, %.1f GB, %.2fs; %.0f frees %.2fs)\n",
+                 ph[6], n_env_bs, t_env_bs, n_env_dense, t_env_dense, n_ov, t_ov, ps[0], ps[1] / 1e9, ps[2], ps[3],
+                 ps[4]);
+  }
   // coarse eigenproblem (host FP64): canonical orthogonalisation of S
   std::vector<double> ws, Vs;
   jacobi_eig(n, S, ws, Vs);
