@@ -1017,8 +1017,17 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   E.bs_tmp.ensure(sizeof(T) * std::max<long long>(std::max(p.m1.ntmp, p.m2.ntmp), 1));
   const std::vector<GemmGroup<T>> gg1 = heavy_groups<T>(E, p.m1, E.bs_t1.as<T>(), p.n1);
   const std::vector<GemmGroup<T>> gg2 = heavy_groups<T>(E, p.m2, E.bs_t2.as<T>(), p.n2);
-  if (!gg1.empty()) upload(E.bs_gg1, gg1.data(), gg1.size() * sizeof(GemmGroup<T>), s);
-  if (!gg2.empty()) upload(E.bs_gg2, gg2.data(), gg2.size() * sizeof(GemmGroup<T>), s);
+  // the descriptors change only with the plan, the precision or the workspace addresses
+  if (E.bs_gg_serial != p.serial || E.bs_gg_prec != prec || E.bs_gg_ptr[0] != E.bs_t1.p ||
+      E.bs_gg_ptr[1] != E.bs_t2.p || E.bs_gg_ptr[2] != E.bs_tmp.p) {
+    if (!gg1.empty()) upload(E.bs_gg1, gg1.data(), gg1.size() * sizeof(GemmGroup<T>), s);
+    if (!gg2.empty()) upload(E.bs_gg2, gg2.data(), gg2.size() * sizeof(GemmGroup<T>), s);
+    E.bs_gg_serial = p.serial;
+    E.bs_gg_prec = prec;
+    E.bs_gg_ptr[0] = E.bs_t1.p;
+    E.bs_gg_ptr[1] = E.bs_t2.p;
+    E.bs_gg_ptr[2] = E.bs_tmp.p;
+  }
   E.kt_begin();
   if (p.ntiles1 > 0) {
     hipLaunchKernelGGL((stage1_mfma_kernel<T>), dim3(p.ntiles1), dim3(256), 0, s, p.tiles1.as<int4>(),

@@ -2187,31 +2187,33 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     // new direction: diagonally preconditioned residual, projected out of the subspace
     // (classical Gram-Schmidt, repeated once when the first pass cancels more than a
     // factor 1/sqrt(2) of the norm: "twice is enough")
-    precond(t, t, w.diag.as<double>(), res.theta, mask.as<uint8_t>(), n, E.stream);
-    const double tn0 = norm_dev(E, t, n);
+    // The direction is formed in its basis slot V_m, so one multi-dot over V_0..V_m
+    // gives the projections and the squared norm together.
+    double* vm = V + (size_t)m * n;
+    precond(vm, t, w.diag.as<double>(), res.theta, mask.as<uint8_t>(), n, E.stream);
+    std::vector<double> d;
+    dots(V, m + 1, vm, d);
+    const double tn0 = std::sqrt(std::max(d[m], 0.0));
     double tn = tn0;
     for (int pass = 0; pass < 2; ++pass) {
-      std::vector<double> d;
-      dots(V, m, t, d);
-      for (double& v : d) v = -v;
-      lcomb(V, m, d, u);  // u is free now
-      axpy(t, 1.0, u, n, E.stream);
+      std::vector<double> c(d.begin(), d.begin() + m);
+      for (double& v : c) v = -v;
+      lcomb(V, m, c, u);  // u is free now
+      axpy(vm, 1.0, u, n, E.stream);
+      dots(V, m + 1, vm, d);
       const double prev = tn;
-      tn = norm_dev(E, t, n);
+      tn = std::sqrt(std::max(d[m], 0.0));
       if (tn >= prev / std::sqrt(2.0)) break;
     }
     if (!(tn > 1e-10 * tn0) || !(tn > 0.0)) {
       res.converged = res.resid <= tol;
       break;
     }
-    double* vm = V + (size_t)m * n;
-    HC(hipMemcpyAsync(vm, t, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
     scale(vm, 1.0 / tn, n, E.stream);
     double* avm = AV + (size_t)m * n;
     window_matvec(E, w, vm, avm, prec);
     mask_apply(avm, mask.as<uint8_t>(), n, E.stream);
     res.matvecs++;
-    std::vector<double> d;
     dots(V, m + 1, avm, d);
     if ((int)Hs.size() < maxsub * maxsub) {
       std::vector<double> H2((size_t)maxsub * maxsub, 0.0);

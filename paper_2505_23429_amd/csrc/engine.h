@@ -273,6 +273,10 @@ class Engine {
   DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp, bs_gg1, bs_gg2;
   DevMem be_t1, be_panel, be_up, be_tmp;  // block-sparse environment-update workspaces
   long long bs_zero_serial = -1;  // plan whose never-written T1 entries are zero in bs_t1
+  // plan (serial, precision, workspace addresses) whose heavy-row GEMM descriptors bs_gg1/2 hold
+  long long bs_gg_serial = -1;
+  int bs_gg_prec = -1;
+  const void* bs_gg_ptr[3] = {nullptr, nullptr, nullptr};
   int bs_zero_prec = -1;
 
  private:
