@@ -170,10 +170,140 @@ BlockPool& pool() {
   static BlockPool* p = new BlockPool;  // lives until process exit
   return *p;
 }
+
+// Large blocks (the environments and intermediates of a sweep, up to ~10 GB at
+// chi = 1024) come from chunks of device memory that are carved best-fit and
+// coalesced on release, so that requests of ever-changing sizes do not each cost
+// a hipMalloc.  A chunk goes back to the device only when a new chunk cannot be
+// obtained and the chunk is entirely free.
+class Arena {
+ public:
+  static constexpr size_t kMin = size_t(64) << 20;  // requests from this size on
+  void* get(size_t bytes, size_t& cap) {
+    const size_t r = (bytes + kAlign - 1) / kAlign * kAlign;
+    std::lock_guard<std::mutex> g(mu_);
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      auto it = by_size_.lower_bound(r);
+      if (it != by_size_.end()) {
+        char* p = it->second;
+        const size_t sz = it->first;
+        by_size_.erase(it);
+        by_addr_.erase(p);
+        if (sz > r) insert_free(p + r, sz - r);
+        used_[p] = r;
+        cap = r;
+        return p;
+      }
+      if (attempt == 0 && grow(std::max(r, kChunk))) continue;
+      if (attempt <= 1) {
+        release_free_chunks();
+        if (grow(r)) continue;
+      }
+    }
+    return nullptr;
+  }
+  bool owns(void* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    return used_.count((char*)p) != 0;
+  }
+  void put(void* p) {
+    if (tl_stream) (void)hipStreamSynchronize(tl_stream);
+    else (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = used_.find((char*)p);
+    if (it == used_.end()) return;
+    const size_t sz = it->second;
+    used_.erase(it);
+    insert_free((char*)p, sz);
+  }
+  std::array<double, 3> stats() {
+    std::lock_guard<std::mutex> g(mu_);
+    return {(double)chunks_.size(), (double)total_, grow_s_};
+  }
+
+ private:
+  static constexpr size_t kAlign = size_t(2) << 20;
+  static constexpr size_t kChunk = size_t(32) << 30;
+  bool grow(size_t size) {
+    void* p = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (hipMalloc(&p, size) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    grow_s_ += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    chunks_[(char*)p] = size;
+    total_ += size;
+    insert_free((char*)p, size);
+    return true;
+  }
+  char* chunk_of(char* p) const {
+    auto it = chunks_.upper_bound(p);
+    return it == chunks_.begin() ? nullptr : std::prev(it)->first;
+  }
+  void insert_free(char* p, size_t sz) {
+    char* c = chunk_of(p);
+    // merge with the following free segment of the same chunk
+    auto nx = by_addr_.find(p + sz);
+    if (nx != by_addr_.end() && chunk_of(nx->first) == c) {
+      erase_size(nx->first, nx->second);
+      sz += nx->second;
+      by_addr_.erase(nx);
+    }
+    // and with the preceding one
+    auto pv = by_addr_.lower_bound(p);
+    if (pv != by_addr_.begin()) {
+      --pv;
+      if (pv->first + pv->second == p && chunk_of(pv->first) == c) {
+        erase_size(pv->first, pv->second);
+        p = pv->first;
+        sz += pv->second;
+        by_addr_.erase(pv);
+      }
+    }
+    by_addr_[p] = sz;
+    by_size_.emplace(sz, p);
+  }
+  void erase_size(char* p, size_t sz) {
+    auto range = by_size_.equal_range(sz);
+    for (auto it = range.first; it != range.second; ++it)
+      if (it->second == p) {
+        by_size_.erase(it);
+        return;
+      }
+  }
+  void release_free_chunks() {
+    (void)hipDeviceSynchronize();
+    for (auto it = chunks_.begin(); it != chunks_.end();) {
+      auto f = by_addr_.find(it->first);
+      if (f != by_addr_.end() && f->second == it->second) {
+        erase_size(f->first, f->second);
+        by_addr_.erase(f);
+        (void)hipFree(it->first);
+        total_ -= it->second;
+        it = chunks_.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  std::mutex mu_;
+  std::map<char*, size_t> chunks_, by_addr_, used_;
+  std::multimap<size_t, char*> by_size_;
+  size_t total_ = 0;
+  double grow_s_ = 0.0;
+};
+Arena& arena() {
+  static Arena* a = new Arena;  // lives until process exit
+  return *a;
+}
 }  // namespace
 
 void DevMem::release() {
-  if (p && own) pool().put(p, cap);
+  if (p && own) {
+    if (cap >= Arena::kMin && arena().owns(p)) arena().put(p);
+    else pool().put(p, cap);
+  }
   p = nullptr;
   n = 0;
   cap = 0;
@@ -187,7 +317,8 @@ void DevMem::ensure(size_t bytes) {
   if (bytes <= n) return;
   release();
   if (bytes == 0) return;
-  p = pool().get(bytes, cap);
+  p = bytes >= Arena::kMin ? arena().get(bytes, cap) : nullptr;
+  if (!p) p = pool().get(bytes, cap);
   if (!p) {
     cap = 0;
     throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
@@ -198,7 +329,8 @@ void DevMem::resize_zero(size_t bytes, hipStream_t s) {
   if (!(own && p && bytes <= cap)) {
     release();
     if (bytes) {
-      p = pool().get(bytes, cap);
+      p = bytes >= Arena::kMin ? arena().get(bytes, cap) : nullptr;
+      if (!p) p = pool().get(bytes, cap);
       if (!p) {
         cap = 0;
         throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
@@ -2671,11 +2803,13 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   tph = now();
   if (verbose) {
     const auto ps = pool().stats();
+    const auto as = arena().stats();
     std::fprintf(stderr,
                  "[tt] step 3: coarse matrices %.2fs (so far: %d block-sparse env updates %.2fs, %d dense %.2fs, "
-                 "%d overlap updates %.2fs; device memory: %.0f allocations, %.1f GB, %.2fs; %.0f frees %.2fs)\n",
-                 ph[6], n_env_bs, t_env_bs, n_env_dense, t_env_dense, n_ov, t_ov, ps[0], ps[1] / 1e9, ps[2], ps[3],
-                 ps[4]);
+                 "%d overlap updates %.2fs; small blocks: %.0f allocations, %.1f GB, %.2fs; large-block chunks: "
+                 "%.0f, %.1f GB, %.2fs)\n",
+                 ph[6], n_env_bs, t_env_bs, n_env_dense, t_env_dense, n_ov, t_ov, ps[0], ps[1] / 1e9, ps[2], as[0],
+                 as[1] / 1e9, as[2]);
   }
   // coarse eigenproblem (host FP64): canonical orthogonalisation of S
   std::vector<double> ws, Vs;
