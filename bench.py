@@ -38,8 +38,18 @@ def workload(idx):
     return w, lengths
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mix2_gather_a2dmrg_L32_chi512.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_a2dmrg_L32_chi512.txt")
 KERNEL_SOURCES = ("paper_2505_23429_amd/csrc/bsheff.hip", "paper_2505_23429_amd/csrc/kernels.hip")
+# timing slots of the product and the kernel symbols they stand for (FP32 products)
+KERNEL_SYMBOLS = {
+    "gemm_Lx": "stage1_mfma_kernel<float>",
+    "mix1_gather": "mix_kernel<float, 1, false>",
+    "mix1_heavy_scatter": "mix_kernel<float, 1, true>",
+    "mix2_gather": "mix_kernel<float, 2, false>",
+    "mix2_heavy_scatter": "mix_kernel<float, 2, true>",
+    "gemm_R": "stage4_mfma_kernel<float>",
+    "gemm_R_reduce": "reduce4_kernel<float>",
+}
 
 
 def kernel_source_hash():
@@ -60,9 +70,57 @@ def measured_traffic(kernel):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel") != kernel or t.get("source_sha256_16") != kernel_source_hash():
+    if t.get("source_sha256_16") != kernel_source_hash():
         return None
-    return t.get("hbm_bytes_per_launch")
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def traffic_summary(fetch_csv, write_csv, bench_json, commands):
+    """Reduce two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+    `bench.py --copy-probe` to HBM bytes per launch of the product kernels.  Each counter
+    is scaled by what it reads for the probe, a plain elementwise copy that reads 1 GiB
+    and writes 1 GiB; the algorithmic bytes per launch come from the same run's JSON line."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        acc = defaultdict(list)
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return acc
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    probe_f = max(v for n, vals in fetch.items() if "elementwise" in n for v in vals)
+    probe_w = max(v for n, vals in write.items() if "elementwise" in n for v in vals)
+    fs, ws = (1 << 30) / (probe_f * 1024.0), (1 << 30) / (probe_w * 1024.0)
+    with open(bench_json) as f:
+        run = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    out = {"workload": run["config"]["workload"], "source_sha256_16": kernel_source_hash(), "commands": commands,
+           "note": "FETCH_SIZE and WRITE_SIZE per dispatch, averaged over the launches of each kernel, each scaled by "
+                   "the value it reads for the copy probe; algorithmic bytes per launch from the same run",
+           "copy_probe": {"kernel": "torch elementwise x * 1.0, FP32, 1 GiB read + 1 GiB write",
+                          "fetch_kib_raw": probe_f, "write_kib_raw": probe_w,
+                          "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
+           "kernels": {}}
+    for slot, sym in KERNEL_SYMBOLS.items():
+        fv = [v for n, vals in fetch.items() if sym in n for v in vals]
+        wv = [v for n, vals in write.items() if sym in n for v in vals]
+        k = run["kernels"].get(slot)
+        if not fv or not wv or not k or k["launches"] == 0:
+            continue
+        rd = sum(fv) / len(fv) * 1024.0 * fs
+        wr = sum(wv) / len(wv) * 1024.0 * ws
+        alg = k["gbs"] * 1e9 * k["ms"] * 1e-3 / k["launches"]
+        out["kernels"][slot] = {"symbol": sym, "launches_counted": len(fv),
+                                "hbm_read_bytes_per_launch": int(rd), "hbm_write_bytes_per_launch": int(wr),
+                                "hbm_bytes_per_launch": int(rd + wr),
+                                "algorithmic_bytes_per_launch": int(alg),
+                                "traffic_over_algorithmic": round((rd + wr) / max(alg, 1.0), 3)}
+    return out
 
 
 def cpu_baseline(mpo, w, gpu_flops_heff, budget_s):
@@ -130,10 +188,19 @@ def main():
                          "kernel that calibrates the HBM byte counters")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="also run the sweep with FP64 products and report the energy difference")
+    ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "RUN_JSON"),
+                    help="reduce the counter files of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "bench.py --copy-probe, and that run's JSON line, to the traffic summary this script reads; "
+                         "prints it and exits (no GPU)")
+    ap.add_argument("--traffic-commands", nargs="*", default=[],
+                    help="the rocprofv3 commands that produced the counter files (recorded in the summary)")
     ap.add_argument("--converged", action="store_true",
                     help="local solves to the workload's tolerance with no product cap; low-precision products "
                          "are followed by FP64 refinement (the precision-split comparison, not the timed sweep)")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_summary(*args.traffic_from, args.traffic_commands), indent=1))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the additive sweep is measured on a single MI355X "
               "(the multi-GPU distribution of subdomains is a design note, not built)", file=sys.stderr)

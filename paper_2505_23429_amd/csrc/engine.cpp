@@ -447,8 +447,10 @@ Engine::Engine(const Engine& parent, int)
   HC(hipEventCreate(&ev1));
 }
 int Engine::aux_lanes() {
-  // context engine: 4 lanes; each worker engine: 2 (several workers already share the device)
-  const int kLanes = is_worker ? 2 : 4;
+  // context engine only: worker engines factor their bins on their own stream (with
+  // concurrent workers, lanes on every worker put 8+ host threads into rocSOLVER at once)
+  if (is_worker) return 0;
+  const int kLanes = 4;
   while ((int)aux_stream.size() < kLanes) {
     hipStream_t s = nullptr;
     HC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));

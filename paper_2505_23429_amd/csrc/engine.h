@@ -188,7 +188,7 @@ class Engine {
   std::map<std::pair<int, int>, std::array<double, 3>> svd_bins;
   double svd_seconds = 0.0;
   // auxiliary streams (with rocBLAS handles) on which the independent size bins of one
-  // batched sector SVD run concurrently; created on first use
+  // batched sector SVD run concurrently; created on first use, context engine only
   bool is_worker = false;
   std::vector<hipStream_t> aux_stream;
   std::vector<rocblas_handle> aux_blas;
