@@ -39,7 +39,9 @@ def workload(idx):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_a2dmrg_L32_chi512.txt")
-KERNEL_SOURCES = ("paper_2505_23429_amd/csrc/bsheff.hip", "paper_2505_23429_amd/csrc/kernels.hip")
+# the product kernels whose counters the traffic summary holds are compiled from these two
+# files alone (kernels.hip holds the shared GEMM and the Davidson vector kernels)
+KERNEL_SOURCES = ("paper_2505_23429_amd/csrc/bsheff.hip", "paper_2505_23429_amd/csrc/bsheff.h")
 # timing slots of the product and the kernel symbols they stand for (FP32 products)
 KERNEL_SYMBOLS = {
     "gemm_Lx": "stage1_mfma_kernel<float>",
@@ -63,8 +65,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None
-    when there is none for this kernel or the kernel sources changed since."""
+    """Counter record of `kernel` from the committed traffic summary (HBM bytes per launch
+    and their ratio to the algorithmic bytes of the same launches), or None when there is
+    none for this kernel or its sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -72,55 +75,129 @@ def measured_traffic(kernel):
         return None
     if t.get("source_sha256_16") != kernel_source_hash():
         return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    return t.get("kernels", {}).get(kernel)
 
 
-def traffic_summary(fetch_csv, write_csv, bench_json, commands):
-    """Reduce two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
-    `bench.py --copy-probe` to HBM bytes per launch of the product kernels.  Each counter
-    is scaled by what it reads for the probe, a plain elementwise copy that reads 1 GiB
-    and writes 1 GiB; the algorithmic bytes per launch come from the same run's JSON line."""
+# On gfx950 the derived FETCH_SIZE counts a read request as 128 bytes only when it is a
+# TCC_BUBBLE; the 128-byte requests of an ordinary streaming read are counted as 64.  The
+# raw request counters give the bytes directly: 128 N128 + 64 (N - N128 - N32) + 32 N32.
+READ_COUNTERS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_BUBBLE_sum")
+
+
+def read_bytes_per_dispatch(path):
+    """Kernel name -> list of HBM read bytes per dispatch from a rocprofv3 counter file that
+    holds either the raw read-request counters (READ_COUNTERS) or FETCH_SIZE (KiB)."""
     import csv
     from collections import defaultdict
 
-    def per_kernel(path, counter):
-        acc = defaultdict(list)
-        with open(path) as f:
-            for r in csv.DictReader(f):
-                if r["Counter_Name"] == counter:
-                    acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return acc
+    per = defaultdict(dict)
+    names = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            d = int(r["Dispatch_Id"])
+            per[d][r["Counter_Name"]] = float(r["Counter_Value"])
+            names[d] = r["Kernel_Name"]
+    out = defaultdict(list)
+    for d, c in sorted(per.items()):
+        if "TCC_EA0_RDREQ_sum" in c:
+            n, n32, n128 = c["TCC_EA0_RDREQ_sum"], c["TCC_EA0_RDREQ_32B_sum"], c["TCC_EA0_RDREQ_128B_sum"]
+            b = 128.0 * n128 + 32.0 * n32 + 64.0 * (n - n128 - n32)
+        elif "FETCH_SIZE" in c:
+            b = c["FETCH_SIZE"] * 1024.0
+        else:
+            continue
+        out[names[d]].append(b)
+    return out
 
-    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
-    write = per_kernel(write_csv, "WRITE_SIZE")
-    probe_f = max(v for n, vals in fetch.items() if "elementwise" in n for v in vals)
+
+def traffic_summary(read_csv, write_csv, bench_json, commands):
+    """Reduce two rocprofv3 --pmc runs of `bench.py --copy-probe` (read requests, then
+    WRITE_SIZE in KiB per dispatch) to HBM bytes per launch of the product kernels.  Each
+    direction is scaled by what it reads for the probe, a plain elementwise copy that reads
+    1 GiB and writes 1 GiB (a scale near 1 confirms the counter arithmetic); the algorithmic
+    bytes per launch come from the same run's JSON line."""
+    import csv
+    from collections import defaultdict
+
+    reads = read_bytes_per_dispatch(read_csv)
+    write = defaultdict(list)
+    with open(write_csv) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == "WRITE_SIZE":
+                write[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
+    probe_r = max(v for n, vals in reads.items() if "elementwise" in n for v in vals)
     probe_w = max(v for n, vals in write.items() if "elementwise" in n for v in vals)
-    fs, ws = (1 << 30) / (probe_f * 1024.0), (1 << 30) / (probe_w * 1024.0)
+    rs, ws = float(1 << 30) / probe_r, float(1 << 30) / probe_w
+    with open(read_csv) as f:
+        raw = any(r["Counter_Name"] == "TCC_EA0_RDREQ_sum" for r in csv.DictReader(f))
     with open(bench_json) as f:
         run = json.loads([ln for ln in f if ln.startswith("{")][-1])
     out = {"workload": run["config"]["workload"], "source_sha256_16": kernel_source_hash(), "commands": commands,
-           "note": "FETCH_SIZE and WRITE_SIZE per dispatch, averaged over the launches of each kernel, each scaled by "
-                   "the value it reads for the copy probe; algorithmic bytes per launch from the same run",
+           "read_counters": list(READ_COUNTERS) if raw else ["FETCH_SIZE"],
+           "note": "HBM read bytes (from the read-request counters: 128 N128 + 64 N64 + 32 N32) and WRITE_SIZE per "
+                   "dispatch, averaged over the launches of each kernel, each scaled by the value it reads for the "
+                   "copy probe; algorithmic bytes per launch from the same run",
            "copy_probe": {"kernel": "torch elementwise x * 1.0, FP32, 1 GiB read + 1 GiB write",
-                          "fetch_kib_raw": probe_f, "write_kib_raw": probe_w,
-                          "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
+                          "read_bytes_raw": probe_r, "write_bytes_raw": probe_w,
+                          "read_scale": round(rs, 4), "write_scale": round(ws, 4)},
            "kernels": {}}
     for slot, sym in KERNEL_SYMBOLS.items():
-        fv = [v for n, vals in fetch.items() if sym in n for v in vals]
+        rv = [v for n, vals in reads.items() if sym in n for v in vals]
         wv = [v for n, vals in write.items() if sym in n for v in vals]
         k = run["kernels"].get(slot)
-        if not fv or not wv or not k or k["launches"] == 0:
+        if not rv or not wv or not k or k["launches"] == 0:
             continue
-        rd = sum(fv) / len(fv) * 1024.0 * fs
-        wr = sum(wv) / len(wv) * 1024.0 * ws
+        rd = sum(rv) / len(rv) * rs
+        wr = sum(wv) / len(wv) * ws
         alg = k["gbs"] * 1e9 * k["ms"] * 1e-3 / k["launches"]
-        out["kernels"][slot] = {"symbol": sym, "launches_counted": len(fv),
+        out["kernels"][slot] = {"symbol": sym, "launches_counted": len(rv),
                                 "hbm_read_bytes_per_launch": int(rd), "hbm_write_bytes_per_launch": int(wr),
                                 "hbm_bytes_per_launch": int(rd + wr),
                                 "algorithmic_bytes_per_launch": int(alg),
                                 "traffic_over_algorithmic": round((rd + wr) / max(alg, 1.0), 3)}
     return out
+
+
+def stats_summary(stats_csv, bench_json, command, top=30):
+    """Format a `rocprofv3 --kernel-trace --stats` kernel_stats.csv together with the JSON
+    line the profiled bench.py run printed: the run's configuration, bench.py's own per-slot
+    timing (HIP events) beside the profiler's per-kernel totals, and the kernel sources' hash."""
+    import csv
+
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    with open(bench_json) as f:
+        run = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    cfg = run["config"]
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    calls = sum(int(r["Calls"]) for r in rows)
+    conc = cfg.get("concurrent_subdomain_solves", 1)
+    out = ["rocprofv3 kernel statistics: additive two-level sweep %s (L=%d, chi=%d, %d subdomains), %s products, "
+           "%d concurrent subdomain solve%s" % (cfg["workload"], cfg["L"], cfg["chi"], len(cfg["subdomains"]),
+                                                cfg["matvec"].upper(), conc, "" if conc == 1 else "s"),
+           "command: " + command,
+           "product kernel source hash (bsheff.hip + bsheff.h, sha256/16): " + kernel_source_hash(),
+           "sweep under the profiler: %.3f s; products %d" % (run["value"], run["matvecs_per_sweep"]),
+           "total kernel time %.3f s over %d dispatches%s" % (
+               tot / 1e9, calls, "" if conc == 1 else " (summed over streams; kernels of different streams overlap)"),
+           "",
+           "bench.py timing of the same run (HIP events on each product's stream):"]
+    for k, v in run["kernels"].items():
+        sym = KERNEL_SYMBOLS.get(k, "")
+        prof = [r for r in rows if sym and sym in r["Name"]]
+        pavg = ("  rocprofv3 %8.1f us/launch" % (sum(float(r["TotalDurationNs"]) for r in prof) / 1e3 /
+                                                max(sum(int(r["Calls"]) for r in prof), 1))) if prof else ""
+        out.append("  %-20s %8.1f ms %5d launches %8.1f us/launch%s" % (
+            k, v["ms"], v["launches"], v["ms"] * 1e3 / max(v["launches"], 1), pavg))
+    rl = run["roofline"]
+    out.append("  roofline kernel: %s, %.1f us/launch, %s %.1f of %.1f %s (frac %.4f)" % (
+        rl["kernel"], rl["avg_launch_us"], rl["bound"], rl["achieved"], rl["peak"], rl["unit"], rl["frac"]))
+    out += ["", " total_s   calls    avg_us   pct  kernel"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        out.append("%8.3f %7s %9.1f %5.1f  %s" % (float(r["TotalDurationNs"]) / 1e9, r["Calls"],
+                                                  float(r["AverageNs"]) / 1e3,
+                                                  100 * float(r["TotalDurationNs"]) / tot, r["Name"][:100]))
+    return "\n".join(out)
 
 
 def cpu_baseline(mpo, w, gpu_flops_heff, budget_s):
@@ -188,16 +265,25 @@ def main():
                          "kernel that calibrates the HBM byte counters")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="also run the sweep with FP64 products and report the energy difference")
-    ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "RUN_JSON"),
-                    help="reduce the counter files of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+    ap.add_argument("--traffic-from", nargs=3, metavar=("READ_CSV", "WRITE_CSV", "RUN_JSON"),
+                    help="reduce the counter files of two rocprofv3 --pmc runs (the read-request counters "
+                         "TCC_EA0_RDREQ/_32B/_128B/TCC_BUBBLE or FETCH_SIZE; WRITE_SIZE) of "
                          "bench.py --copy-probe, and that run's JSON line, to the traffic summary this script reads; "
                          "prints it and exits (no GPU)")
     ap.add_argument("--traffic-commands", nargs="*", default=[],
                     help="the rocprofv3 commands that produced the counter files (recorded in the summary)")
+    ap.add_argument("--stats-from", nargs=2, metavar=("STATS_CSV", "RUN_JSON"),
+                    help="format a rocprofv3 --stats kernel_stats.csv and the JSON line of the profiled run; "
+                         "prints the summary and exits (no GPU)")
+    ap.add_argument("--stats-command", default="",
+                    help="the rocprofv3 command that produced the kernel statistics (recorded in the summary)")
     ap.add_argument("--converged", action="store_true",
                     help="local solves to the workload's tolerance with no product cap; low-precision products "
                          "are followed by FP64 refinement (the precision-split comparison, not the timed sweep)")
     args = ap.parse_args()
+    if args.stats_from:
+        print(stats_summary(*args.stats_from, args.stats_command))
+        return
     if args.traffic_from:
         print(json.dumps(traffic_summary(*args.traffic_from, args.traffic_commands), indent=1))
         return
@@ -342,9 +428,16 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 3 x (read 1 GiB + write 1 GiB), result {float(dst[0])}")
         del src, dst
-    traffic = measured_traffic(roof["kernel"])
-    if traffic is not None:
-        roof["traffic"] = traffic
+    # The counter runs sample the first products of every window (a full sweep under
+    # counter collection is too slow), so their per-launch average weights the windows
+    # differently from this run: traffic is the measured HBM/algorithmic ratio of the
+    # kernel times this run's algorithmic bytes per launch; the sample's own figure is kept.
+    rec = measured_traffic(roof["kernel"])
+    if rec is not None:
+        ratio = rec["traffic_over_algorithmic"]
+        roof["traffic"] = round(ratio * roof["algorithmic_bytes_per_launch"])
+        roof["traffic_over_algorithmic"] = ratio
+        roof["traffic_sample_bytes_per_launch"] = rec["hbm_bytes_per_launch"]
     print(json.dumps(out), flush=True)
 
 

@@ -448,8 +448,9 @@ Engine::Engine(const Engine& parent, int)
 }
 int Engine::aux_lanes() {
   // context engine only: worker engines factor their bins on their own stream (with
-  // concurrent workers, lanes on every worker put 8+ host threads into rocSOLVER at once)
-  if (is_worker) return 0;
+  // concurrent workers, lanes on every worker put 8+ host threads into rocSOLVER at once);
+  // with a single worker every launch stays on the calling thread
+  if (is_worker || opts.sub_workers == 1) return 0;
   const int kLanes = 4;
   while ((int)aux_stream.size() < kLanes) {
     hipStream_t s = nullptr;
@@ -1126,10 +1127,9 @@ double Engine::env_close(const Env& Lb, const Env& Rb_) {
   if (Lb.R != Rb_.R || Lb.rb != Rb_.rb || Lb.rk != Rb_.rk) throw std::runtime_error("env_close: shape mismatch");
   const size_t n = Lb.elems();
   wsp.ensure(sizeof(double) * (256 + 8));
-  const int nblk = 128;
   DevMem part;
-  part.ensure(sizeof(double) * nblk);
-  multi_dot(Lb.d.as<double>(), n, 1, Rb_.d.as<double>(), n, wsp.as<double>(), part.as<double>(), nblk, stream);
+  part.ensure(sizeof(double) * kDotBlocks);
+  multi_dot(Lb.d.as<double>(), n, 1, Rb_.d.as<double>(), n, wsp.as<double>(), part.as<double>(), kDotBlocks, stream);
   double v = 0.0;
   d2h(&v, wsp.p, sizeof(double), stream);
   return v;
@@ -1751,8 +1751,8 @@ static double split_two_site(Engine& E, const double* x, int rl, const Labels& q
 static double norm_dev(Engine& E, const double* x, size_t n) {
   DevMem out, part;
   out.ensure(sizeof(double));
-  part.ensure(sizeof(double) * 128);
-  multi_dot(x, n, 1, x, n, out.as<double>(), part.as<double>(), 128, E.stream);
+  part.ensure(sizeof(double) * kDotBlocks);
+  multi_dot(x, n, 1, x, n, out.as<double>(), part.as<double>(), kDotBlocks, E.stream);
   double v;
   d2h(&v, out.p, sizeof(double), E.stream);
   return std::sqrt(std::max(v, 0.0));
@@ -2227,7 +2227,7 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
   E.dav_u.ensure(sizeof(double) * n);
   E.dav_Au.ensure(sizeof(double) * n);
   E.dav_c.ensure(sizeof(double) * 2 * maxsub);
-  const int nblk = 256;
+  const int nblk = kDotBlocks;
   E.wsp.ensure(sizeof(double) * (size_t)nblk * maxsub);
   double* V = E.dav_V.as<double>();
   double* AV = E.dav_AV.as<double>();
@@ -3128,8 +3128,8 @@ void Engine::heff_grad_raw(int rl, int rr, int RA, int RB, int RC, const double*
   // E = x . y
   wsp.ensure(sizeof(double) * 264);
   DevMem part;
-  part.ensure(sizeof(double) * 128);
-  multi_dot(x, n, 1, y.as<double>(), n, wsp.as<double>(), part.as<double>(), 128, stream);
+  part.ensure(sizeof(double) * kDotBlocks);
+  multi_dot(x, n, 1, y.as<double>(), n, wsp.as<double>(), part.as<double>(), kDotBlocks, stream);
   d2h(En, wsp.p, sizeof(double), stream);
   // H^T x with every operand transposed
   LT.ensure(sizeof(double) * (size_t)RA * rl * rl);

@@ -80,9 +80,13 @@ void scale(double* x, double a, size_t n, hipStream_t s);
 void axpy(double* y, double a, const double* x, size_t n, hipStream_t s);
 void axpby(double* z, double a, const double* x, double b, const double* y, size_t n, hipStream_t s);
 void mask_apply(double* x, const uint8_t* mask, size_t n, hipStream_t s);
-// out[i] = sum_n V[i*ldv + n] * w[n] for i < m  (deterministic two-pass reduction)
+// out[i] = sum_n V[i*ldv + n] * w[n] for i < m  (deterministic two-pass reduction).
+// partial holds at least cap_blk * m doubles; the first pass uses dot_blocks(n) workgroups,
+// at most cap_blk (the summation order depends on n and cap_blk only).
+constexpr int kDotBlocks = 1024;
+int dot_blocks(size_t n);
 void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, double* out_dev, double* partial,
-               int nblk, hipStream_t s);
+               int cap_blk, hipStream_t s);
 // out[n] = sum_i c[i] V[i*ldv+n]  (c on device)
 void lincomb(const double* V, size_t ldv, int m, const double* c_dev, double* out, size_t n, hipStream_t s);
 void convert_f64_f32(const double* a, float* b, size_t n, hipStream_t s);

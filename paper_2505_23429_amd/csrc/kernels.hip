@@ -609,32 +609,68 @@ void mask_apply(double* x, const uint8_t* mask, size_t n, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
-// two-pass deterministic multi-dot: grid (nblk, m)
-// partial[i][blk] = sum over the block's grid-stride share of V_i . w; each block
-// takes the vectors eight at a time so that w is read once per eight vectors
+// Two-pass deterministic multi-dot.  First pass: partial[i][blk] = sum over the
+// block's grid-stride share of V_i . w.  A block takes the vectors CNT <= 8 at a time
+// (w is read once per pass); with VEC = 2 every load is 16 bytes.  Sums are reduced
+// within each wave by butterfly shuffles, then over the block's four waves in a fixed
+// order, so the result depends only on n and the number of blocks.
+template <int CNT, int VEC>
+__device__ __forceinline__ void mdot_pass(const double* __restrict__ V, size_t ldv, int i0,
+                                          const double* __restrict__ w, size_t nv, int nblk, double (&s)[8]) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] = 0.0;
+  for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < nv; k += (size_t)nblk * 256) {
+    if constexpr (VEC == 2) {
+      const double2 wk = reinterpret_cast<const double2*>(w)[k];
+      double2 v[CNT];
+#pragma unroll
+      for (int u = 0; u < CNT; ++u) v[u] = reinterpret_cast<const double2*>(V + (size_t)(i0 + u) * ldv)[k];
+#pragma unroll
+      for (int u = 0; u < CNT; ++u) {
+        s[u] = fma(v[u].x, wk.x, s[u]);
+        s[u] = fma(v[u].y, wk.y, s[u]);
+      }
+    } else {
+      const double wk = w[k];
+      double v[CNT];
+#pragma unroll
+      for (int u = 0; u < CNT; ++u) v[u] = V[(size_t)(i0 + u) * ldv + k];
+#pragma unroll
+      for (int u = 0; u < CNT; ++u) s[u] = fma(v[u], wk, s[u]);
+    }
+  }
+}
+template <int VEC>
 __global__ __launch_bounds__(256) void mdot_partial(const double* __restrict__ V, size_t ldv, int m,
                                                     const double* __restrict__ w, size_t n, double* __restrict__ partial,
                                                     int nblk) {
-  __shared__ double red[8][256];
+  __shared__ double red[4][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t nv = n / VEC;
   for (int i0 = 0; i0 < m; i0 += 8) {
     const int cnt = min(8, m - i0);
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)nblk * blockDim.x) {
-      const double wk = w[k];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (u < cnt) s[u] += V[(size_t)(i0 + u) * ldv + k] * wk;
+    double s[8];
+    switch (cnt) {
+      case 1: mdot_pass<1, VEC>(V, ldv, i0, w, nv, nblk, s); break;
+      case 2: mdot_pass<2, VEC>(V, ldv, i0, w, nv, nblk, s); break;
+      case 3: mdot_pass<3, VEC>(V, ldv, i0, w, nv, nblk, s); break;
+      case 4: mdot_pass<4, VEC>(V, ldv, i0, w, nv, nblk, s); break;
+      case 5: mdot_pass<5, VEC>(V, ldv, i0, w, nv, nblk, s); break;
+      case 6: mdot_pass<6, VEC>(V, ldv, i0, w, nv, nblk, s); break;
+      case 7: mdot_pass<7, VEC>(V, ldv, i0, w, nv, nblk, s); break;
+      default: mdot_pass<8, VEC>(V, ldv, i0, w, nv, nblk, s); break;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) red[u][threadIdx.x] = s[u];
+    for (int u = 0; u < 8; ++u)
+      for (int o = 32; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) red[wave][u] = s[u];
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st)
-#pragma unroll
-        for (int u = 0; u < 8; ++u) red[u][threadIdx.x] += red[u][threadIdx.x + st];
-      __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      const int u = threadIdx.x;
+      partial[(size_t)(i0 + u) * nblk + blockIdx.x] = (red[0][u] + red[1][u]) + (red[2][u] + red[3][u]);
     }
-    if ((int)threadIdx.x < cnt) partial[(size_t)(i0 + threadIdx.x) * nblk + blockIdx.x] = red[threadIdx.x][0];
     __syncthreads();
   }
 }
@@ -653,26 +689,67 @@ __global__ __launch_bounds__(256) void mdot_final(const double* __restrict__ par
   }
   if (threadIdx.x == 0) out[i] = red[0];
 }
+int dot_blocks(size_t n) {
+  // at least 2048 elements (eight 16-byte loads per thread) per block, at most kDotBlocks
+  return (int)std::min<size_t>(kDotBlocks, std::max<size_t>(1, (n + 2047) / 2048));
+}
 void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, double* out_dev, double* partial,
-               int nblk, hipStream_t s) {
+               int cap_blk, hipStream_t s) {
   if (m <= 0) return;
   if (m > 65535) throw std::runtime_error("multi_dot: too many vectors");
-  hipLaunchKernelGGL(mdot_partial, dim3(nblk), dim3(256), 0, s, V, ldv, m, w, n, partial, nblk);
+  if (cap_blk <= 0) throw std::runtime_error("multi_dot: no partial-sum buffer");
+  const int nblk = std::min(cap_blk, dot_blocks(n));
+  const bool vec2 = n % 2 == 0 && ldv % 2 == 0 && (uintptr_t)V % 16 == 0 && (uintptr_t)w % 16 == 0;
+  if (vec2)
+    hipLaunchKernelGGL(mdot_partial<2>, dim3(nblk), dim3(256), 0, s, V, ldv, m, w, n, partial, nblk);
+  else
+    hipLaunchKernelGGL(mdot_partial<1>, dim3(nblk), dim3(256), 0, s, V, ldv, m, w, n, partial, nblk);
   HIPCHECK(hipGetLastError());
   hipLaunchKernelGGL(mdot_final, dim3(m), dim3(256), 0, s, partial, nblk, out_dev);
   HIPCHECK(hipGetLastError());
 }
 
-__global__ void lincomb_kernel(const double* V, size_t ldv, int m, const double* c, double* out, size_t n) {
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) s += c[i] * V[(size_t)i * ldv + k];
-    out[k] = s;
+// out = sum_i c[i] V_i; with VEC = 2 a thread produces two adjacent entries from 16-byte
+// loads, and the vectors are taken four at a time so that four loads are in flight
+template <int VEC>
+__global__ __launch_bounds__(256) void lincomb_kernel(const double* __restrict__ V, size_t ldv, int m,
+                                                      const double* __restrict__ c, double* __restrict__ out,
+                                                      size_t n) {
+  const size_t nv = n / VEC;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nv; k += (size_t)gridDim.x * blockDim.x) {
+    if constexpr (VEC == 2) {
+      double2 s = {0.0, 0.0};
+      int i = 0;
+      for (; i + 4 <= m; i += 4) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = reinterpret_cast<const double2*>(V + (size_t)(i + u) * ldv)[k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          s.x = fma(c[i + u], v[u].x, s.x);
+          s.y = fma(c[i + u], v[u].y, s.y);
+        }
+      }
+      for (; i < m; ++i) {
+        const double2 v = reinterpret_cast<const double2*>(V + (size_t)i * ldv)[k];
+        s.x = fma(c[i], v.x, s.x);
+        s.y = fma(c[i], v.y, s.y);
+      }
+      reinterpret_cast<double2*>(out)[k] = s;
+    } else {
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s = fma(c[i], V[(size_t)i * ldv + k], s);
+      out[k] = s;
+    }
   }
 }
 void lincomb(const double* V, size_t ldv, int m, const double* c_dev, double* out, size_t n, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(lincomb_kernel, dim3(nblocks(n)), dim3(256), 0, s, V, ldv, m, c_dev, out, n);
+  const bool vec2 = n % 2 == 0 && ldv % 2 == 0 && (uintptr_t)V % 16 == 0 && (uintptr_t)out % 16 == 0;
+  if (vec2)
+    hipLaunchKernelGGL(lincomb_kernel<2>, dim3(nblocks(n / 2)), dim3(256), 0, s, V, ldv, m, c_dev, out, n);
+  else
+    hipLaunchKernelGGL(lincomb_kernel<1>, dim3(nblocks(n)), dim3(256), 0, s, V, ldv, m, c_dev, out, n);
   HIPCHECK(hipGetLastError());
 }
 
