@@ -446,35 +446,9 @@ Engine::Engine(const Engine& parent, int)
   HC(hipEventCreate(&ev0));
   HC(hipEventCreate(&ev1));
 }
-int Engine::aux_lanes() {
-  // context engine only: worker engines factor their bins on their own stream (with
-  // concurrent workers, lanes on every worker put 8+ host threads into rocSOLVER at once);
-  // with a single worker every launch stays on the calling thread
-  if (is_worker || opts.sub_workers == 1) return 0;
-  const int kLanes = 4;
-  while ((int)aux_stream.size() < kLanes) {
-    hipStream_t s = nullptr;
-    HC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) {
-      (void)hipStreamDestroy(s);
-      throw std::runtime_error("rocBLAS handle creation failed");
-    }
-    RC(rocblas_set_stream(h, s));
-    aux_stream.push_back(s);
-    aux_blas.push_back(h);
-  }
-  return kLanes;
-}
-
 Engine::~Engine() {
   if (stream) (void)hipStreamSynchronize(stream);
   workers.clear();
-  for (size_t i = 0; i < aux_stream.size(); ++i) {
-    (void)hipStreamSynchronize(aux_stream[i]);
-    rocblas_destroy_handle(aux_blas[i]);
-    (void)hipStreamDestroy(aux_stream[i]);
-  }
   if (blas) rocblas_destroy_handle(blas);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
@@ -1193,6 +1167,10 @@ struct SvdOut {
 // into left[r*ldl + j] and the right factor into right[j*ldr + c] (both
 // pre-zeroed by the caller after the first pass, see two-phase use below).
 // mode 0: right factor carries the singular values; mode 1: left factor.
+// sweep limit of the Jacobi SVD kernel (a sweep visits every column pair once; the
+// factorisations here converge in about ten)
+constexpr int kJacobiSweeps = 40;
+
 class SectorSVD {
  public:
   SectorSVD(Engine& e) : E(e) {}
@@ -1203,11 +1181,11 @@ class SectorSVD {
     blocks.clear();
     blocks.resize(ns);
     bins.clear();
-    // all sector indices in one upload; blocks binned by size and zero-padded to the bin's
-    // largest block: one batched SVD per bin.  The top min(m, n) singular triplets of a
-    // zero-padded block are those of the block.  Wide blocks (m < n) are factorised
-    // transposed so that every padded matrix is tall: padded wide matrices with few rows
-    // have made the batched bidiagonal QR fail to converge.
+    // all sector indices in one upload; blocks binned by size into zero-padded storage of
+    // the bin's largest block (the Jacobi kernel factors each block at its own size; a bin
+    // too wide for it goes to one batched rocSOLVER SVD, whose top min(m, n) triplets of a
+    // zero-padded block are those of the block).  Wide blocks (m < n) are factorised
+    // transposed so that every matrix is tall.
     std::vector<int> allr, allc;
     std::map<long long, std::vector<int>> bykey;
     for (int t = 0; t < ns; ++t) {
@@ -1262,8 +1240,9 @@ class SectorSVD {
       B.info.ensure(sizeof(int) * B.cnt);
     }
     HC(hipStreamSynchronize(E.stream));
-    // phase 2: one batched SVD per bin; the bins are independent and run
-    // concurrently on the context's auxiliary streams when it has them
+    // phase 2: every block in one launch of the Jacobi SVD kernel at its own size (tall:
+    // M = max(m, n), N = min(m, n)), in the storage of its bin, held in LDS where it fits;
+    // bins wider than the kernel takes go to rocSOLVER whole
     auto factor = [&](Bin& B, rocblas_handle h) {
       const long long MN = (long long)B.M * B.N;
       RC(rocsolver_dgesvd_strided_batched(h, rocblas_svect_singular, rocblas_svect_singular, B.M, B.N,
@@ -1272,40 +1251,42 @@ class SectorSVD {
                                           B.Ew.as<double>(), B.K, rocblas_outofplace, B.info.as<int>(), B.cnt));
     };
     const double tb0 = E.verbose ? E.now() : 0.0;
-    const int nlanes = std::min((int)bins.size(), E.aux_lanes());
-    if (nlanes <= 1) {
-      for (Bin& B : bins) factor(B, E.blas);
-      HC(hipStreamSynchronize(E.stream));
-    } else {
-      // largest bins first, each to the lane with the least work so far
-      std::vector<int> ord(bins.size());
-      std::iota(ord.begin(), ord.end(), 0);
-      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-        return (double)bins[x].M * bins[x].N * bins[x].N > (double)bins[y].M * bins[y].N * bins[y].N;
-      });
-      std::vector<std::vector<int>> lane_bins(nlanes);
-      std::vector<double> load(nlanes, 0.0);
-      for (int i : ord) {
-        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        lane_bins[l].push_back(i);
-        load[l] += (double)bins[i].M * bins[i].N * bins[i].N;
+    {
+      std::vector<SvdJob> jobs[2];
+      long long vtot = 0;
+      for (size_t bi = 0; bi < bins.size(); ++bi) {
+        if (bins[bi].N > kJacobiMaxN) continue;
+        for (int t : *members[bi]) {
+          const long long m = std::max(blocks[t].m, blocks[t].n), n = std::min(blocks[t].m, blocks[t].n);
+          if ((m + n) * n > kJacobiLds) vtot += n * n;
+        }
       }
-      std::vector<std::exception_ptr> errs(nlanes);
-      std::vector<std::thread> th;
-      for (int l = 0; l < nlanes; ++l)
-        th.emplace_back([&, l]() {
-          try {
-            HC(hipSetDevice(E.opts.device));
-            for (int i : lane_bins[l]) factor(bins[i], E.aux_blas[l]);
-            HC(hipStreamSynchronize(E.aux_stream[l]));
-          } catch (...) {
-            errs[l] = std::current_exception();
-            (void)hipStreamSynchronize(E.aux_stream[l]);
-          }
-        });
-      for (auto& t : th) t.join();
-      for (auto& e : errs)
-        if (e) std::rethrow_exception(e);
+      DevMem Vs, jdev[2];
+      Vs.ensure(sizeof(double) * (size_t)std::max<long long>(vtot, 1));
+      long long voff = 0;
+      for (size_t bi = 0; bi < bins.size(); ++bi) {
+        Bin& B = bins[bi];
+        if (B.N > kJacobiMaxN) continue;
+        const std::vector<int>& mem = *members[bi];
+        for (int i = 0; i < B.cnt; ++i) {
+          const Blk& b = blocks[mem[i]];
+          const int m = std::max(b.m, b.n), n = std::min(b.m, b.n);
+          const int in_lds = (long long)(m + n) * n <= kJacobiLds ? 1 : 0;
+          jobs[in_lds].push_back(SvdJob{B.A.as<double>() + (size_t)B.M * B.N * i, in_lds ? nullptr : Vs.as<double>() + voff,
+                                        B.U.as<double>() + (size_t)B.M * B.K * i, B.S.as<double>() + (size_t)B.K * i,
+                                        B.Vt.as<double>() + (size_t)B.K * B.N * i, B.info.as<int>() + i, m, n, B.M, B.M,
+                                        B.K, 0});
+          if (!in_lds) voff += (long long)n * n;
+        }
+      }
+      for (int v = 0; v < 2; ++v)
+        if (!jobs[v].empty()) {
+          upload(jdev[v], jobs[v].data(), jobs[v].size() * sizeof(SvdJob), E.stream);
+          jacobi_svd(jdev[v].as<SvdJob>(), (int)jobs[v].size(), kJacobiSweeps, v == 1, E.stream);
+        }
+      for (Bin& B : bins)
+        if (B.N > kJacobiMaxN) factor(B, E.blas);
+      HC(hipStreamSynchronize(E.stream));
     }
     if (E.verbose) {
       const double dt = E.now() - tb0;
@@ -1324,8 +1305,8 @@ class SectorSVD {
       d2h(inf.data(), B.info.p, sizeof(int) * B.cnt, E.stream);
       for (int i = 0; i < B.cnt; ++i) {
         if (inf[i] == 0) continue;
-        // the zero padding can stall the batched bidiagonal QR on some blocks: factor
-        // such a block again at its own size, into its slots of the bin
+        // a block whose factorisation did not converge (or a shape the Jacobi kernel does
+        // not take) is factored again by rocSOLVER at its own size, into its slots of the bin
         const Blk& bb = blocks[mem[i]];
         {
           const int mm = std::max(bb.m, bb.n), nn = std::min(bb.m, bb.n);

@@ -187,12 +187,7 @@ class Engine {
   // and the wall time of the batched SVD phases
   std::map<std::pair<int, int>, std::array<double, 3>> svd_bins;
   double svd_seconds = 0.0;
-  // auxiliary streams (with rocBLAS handles) on which the independent size bins of one
-  // batched sector SVD run concurrently; created on first use, context engine only
   bool is_worker = false;
-  std::vector<hipStream_t> aux_stream;
-  std::vector<rocblas_handle> aux_blas;
-  int aux_lanes();
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;

@@ -87,6 +87,16 @@ constexpr int kDotBlocks = 1024;
 int dot_blocks(size_t n);
 void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, double* out_dev, double* partial,
                int cap_blk, hipStream_t s);
+// Batched one-sided Jacobi SVD of tall matrices (M >= N, column-major with leading
+// dimension lda), one workgroup per matrix.  A is overwritten; V is an N x N scratch
+// (unused when the matrix is held in LDS: in_lds requires (M + N) N <= kJacobiLds).  On
+// exit S[0..N) holds the singular values in decreasing order, U (leading dimension ldu) the
+// left and Vt (leading dimension ldvt) the right singular vectors; info = 0, 1 where the
+// sweeps did not converge, -1 for a shape the kernel does not take.
+struct SvdJob { double* A; double* V; double* U; double* S; double* Vt; int* info; int M, N, lda, ldu, ldvt, pad; };
+constexpr int kJacobiMaxN = 1024;
+constexpr int kJacobiLds = 17920;  // doubles of A and V held in LDS (140 KiB)
+void jacobi_svd(const SvdJob* jobs, int njobs, int max_sweeps, bool in_lds, hipStream_t s);
 // out[n] = sum_i c[i] V[i*ldv+n]  (c on device)
 void lincomb(const double* V, size_t ldv, int m, const double* c_dev, double* out, size_t n, hipStream_t s);
 void convert_f64_f32(const double* a, float* b, size_t n, hipStream_t s);

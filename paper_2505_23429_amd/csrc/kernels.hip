@@ -709,6 +709,127 @@ void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, do
   HIPCHECK(hipGetLastError());
 }
 
+// One-sided (Hestenes) Jacobi SVD, one workgroup of JW waves per matrix.  Each sweep
+// visits every column pair once in N' - 1 rounds of a round-robin tournament (N' = N
+// rounded up to even; player N' - 1 stays, the others rotate), so the N'/2 pairs of a
+// round are disjoint and the waves take them in turn.  A pair (p, q) is rotated when
+// |a_p . a_q| > tol |a_p| |a_q|; the same rotation is applied to the columns of V.
+// After convergence sigma_j = |a_j|, u_j = a_j / sigma_j, and the triplets are written
+// in decreasing order of sigma (ties by column index).  With INLDS the matrix and V are
+// held in LDS for the whole factorisation ((M + N) N <= kJacobiLds doubles).
+constexpr int JW = 8;
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return __shfl(v, 0, 64);  // one value for the whole wave, so every lane takes the same decision
+}
+template <bool INLDS>
+__global__ __launch_bounds__(64 * JW) void jacobi_svd_kernel(const SvdJob* __restrict__ jobs, int max_sweeps) {
+  __shared__ double sig[kJacobiMaxN];
+  __shared__ int rnk[kJacobiMaxN];
+  __shared__ int rotated;
+  __shared__ double lds[INLDS ? kJacobiLds : 1];
+  const SvdJob J = jobs[blockIdx.x];
+  const int M = J.M, N = J.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NT = 64 * JW;
+  if (N <= 0 || N > kJacobiMaxN || M < N || J.lda < M || J.ldu < M || J.ldvt < N ||
+      (INLDS && (long long)(M + N) * N > kJacobiLds)) {
+    if (tid == 0) J.info[0] = -1;
+    return;
+  }
+  // column j of the working matrix starts at A + j * lda (compact in LDS)
+  const int lda = INLDS ? M : J.lda;
+  double* A = INLDS ? lds : J.A;
+  double* V = INLDS ? lds + (size_t)M * N : J.V;
+  if (INLDS)
+    for (int i = tid; i < M * N; i += NT) A[i] = J.A[(size_t)(i / M) * J.lda + i % M];
+  for (long long i = tid; i < (long long)N * N; i += NT) V[i] = (i % (N + 1) == 0) ? 1.0 : 0.0;
+  __syncthreads();
+  const double tol = 2.2e-16 * (double)M;
+  const int Np = N + (N & 1);
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < Np - 1; ++r) {
+      for (int k = wave; k < Np / 2; k += JW) {
+        int p, q;
+        if (k == 0) { p = Np - 1; q = r; }
+        else { p = (r + k) % (Np - 1); q = (r - k + Np - 1) % (Np - 1); }
+        if (p >= N || q >= N) continue;
+        double* ap = A + (size_t)p * lda;
+        double* aq = A + (size_t)q * lda;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < M; i += 64) {
+          const double x = ap[i], y = aq[i];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (!(fabs(ga) > tol * sqrt(al * be))) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        for (int i = lane; i < M; i += 64) {
+          const double x = ap[i], y = aq[i];
+          ap[i] = c * x - sn * y;
+          aq[i] = sn * x + c * y;
+        }
+        double* vp = V + (size_t)p * N;
+        double* vq = V + (size_t)q * N;
+        for (int i = lane; i < N; i += 64) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = c * x - sn * y;
+          vq[i] = sn * x + c * y;
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  // singular values and their order
+  for (int j = wave; j < N; j += JW) {
+    const double* aj = A + (size_t)j * lda;
+    double s2 = 0.0;
+    for (int i = lane; i < M; i += 64) s2 = fma(aj[i], aj[i], s2);
+    s2 = wave_sum(s2);
+    if (lane == 0) sig[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < N; j += NT) {
+    const double sj = sig[j];
+    int rk = 0;
+    for (int i = 0; i < N; ++i) rk += (sig[i] > sj) || (sig[i] == sj && i < j);
+    rnk[j] = rk;
+  }
+  __syncthreads();
+  for (int j = wave; j < N; j += JW) {
+    const int rk = rnk[j];
+    const double sj = sig[j];
+    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    const double* aj = A + (size_t)j * lda;
+    double* uo = J.U + (size_t)rk * J.ldu;
+    for (int i = lane; i < M; i += 64) uo[i] = aj[i] * inv;
+    const double* vj = V + (size_t)j * N;
+    for (int i = lane; i < N; i += 64) J.Vt[rk + (size_t)i * J.ldvt] = vj[i];
+    if (lane == 0) J.S[rk] = sj;
+  }
+  if (tid == 0) J.info[0] = sweep < max_sweeps ? 0 : 1;
+}
+void jacobi_svd(const SvdJob* jobs, int njobs, int max_sweeps, bool in_lds, hipStream_t s) {
+  if (njobs <= 0) return;
+  if (in_lds)
+    hipLaunchKernelGGL(jacobi_svd_kernel<true>, dim3(njobs), dim3(64 * JW), 0, s, jobs, max_sweeps);
+  else
+    hipLaunchKernelGGL(jacobi_svd_kernel<false>, dim3(njobs), dim3(64 * JW), 0, s, jobs, max_sweeps);
+  HIPCHECK(hipGetLastError());
+}
+
 // out = sum_i c[i] V_i; with VEC = 2 a thread produces two adjacent entries from 16-byte
 // loads, and the vectors are taken four at a time so that four loads are in flight
 template <int VEC>

@@ -164,3 +164,34 @@ def test_block_sparse_environments_match_dense(L, chi, seed):
         E.append(ctx.energy())
         ctx.close()
     assert abs(E[0] - E[1]) < 1e-11 * max(1.0, abs(E[1]))
+
+
+@pytest.mark.timeout(600)
+def test_full_size_sweep_returns_isometries():
+    """Sweep at L = 32, chi = 512 with FP32 products (six products per local solve): its
+    truncated sector SVDs reach blocks too large to be held in LDS, so both paths of the
+    Jacobi SVD kernel run.  Whichever factored a block, the cores handed back are
+    left-orthogonal to rounding, every bond respects chi, and the device energy of the
+    returned iterate is the sweep's E_after."""
+    from paper_2505_23429_amd.api import Context
+    from paper_2505_23429_amd.mpo import build_mpo
+
+    w = S.WORKLOADS[3]
+    h, B = S.integrals(w.L, w.n_factors, w.seed)
+    mpo = build_mpo(h, B)
+    cores, labels = S.random_mps(w.L, w.n_elec, w.two_sz, w.chi, w.seed + 1)
+    print(f"L={w.L} chi={w.chi} lengths={w.lengths}", flush=True)
+    ctx = Context(chi=w.chi, dav_tol=1e-5, dav_maxiter=6, dav_maxsub=24, matvec_prec="f32")
+    ctx.set_mpo(mpo)
+    ctx.set_mps(cores, labels)
+    rep = ctx.sweep(list(w.lengths))
+    c2, l2 = ctx.get_mps()
+    assert max(q.shape[0] for q in l2) <= w.chi
+    assert max(U.shape[2] for U in c2[:-1]) > 256
+    for k, U in enumerate(c2[:-1]):
+        M = U.reshape(-1, U.shape[2])
+        err = np.abs(M.T @ M - np.eye(M.shape[1])).max()
+        assert err < 1e-11, (k, M.shape, err)
+    E = ctx.energy()
+    assert abs(E - rep["E_after"]) < 1e-9 * abs(E), (E, rep["E_after"])
+    ctx.close()
