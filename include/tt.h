@@ -75,9 +75,7 @@ typedef struct tt_opts {
                          concurrently on this many workers, each a host thread with its own
                          HIP stream, rocBLAS handle and workspaces; 0 = 4.  With 1 every
                          kernel is launched from the calling thread on the context's stream
-                         (no worker threads, and the per-sector SVD bins of the compression
-                         are factored one after another instead of on four auxiliary
-                         streams).  Results do not depend on it. */
+                         (no worker threads).  Results do not depend on it. */
 } tt_opts;
 
 #define TT_MAX_SUB 64

@@ -2,9 +2,7 @@
 subdomains are independent).  Running them on several workers, each a host
 thread with its own HIP stream, must give exactly the result of running them
 one after another on the context's stream: every kernel is deterministic and a
-subdomain's solve reads only the Step-1 cores and environments.  With one worker
-the compression's SVD bins are also factored one after another instead of on
-auxiliary streams, so the comparison covers that too."""
+subdomain's solve reads only the Step-1 cores and environments."""
 import numpy as np
 import pytest
 
