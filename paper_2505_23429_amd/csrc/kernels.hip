@@ -713,11 +713,17 @@ void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, do
 // visits every column pair once in N' - 1 rounds of a round-robin tournament (N' = N
 // rounded up to even; player N' - 1 stays, the others rotate), so the N'/2 pairs of a
 // round are disjoint and the waves take them in turn.  A pair (p, q) is rotated when
-// |a_p . a_q| > tol |a_p| |a_q|; the same rotation is applied to the columns of V.
+// |a_p . a_q| > tol |a_p| |a_q| (tol = M eps) and neither column is numerically zero
+// (|a|^2 <= tol^2 |A|_F^2: rotations with larger columns keep refilling such a column with
+// rounding noise of its own size, so it never meets the relative test; its singular value
+// lies far below any truncation cutoff).  The same rotation is applied to the columns of V,
+// and columns of up to 64 JR rows stay in registers between the dot products and the
+// rotation.
 // After convergence sigma_j = |a_j|, u_j = a_j / sigma_j, and the triplets are written
 // in decreasing order of sigma (ties by column index).  With INLDS the matrix and V are
 // held in LDS for the whole factorisation ((M + N) N <= kJacobiLds doubles).
-constexpr int JW = 8;
+constexpr int JW = 16;  // waves per workgroup
+constexpr int JR = 8;   // rows per lane held in registers (columns of up to 512 rows)
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return __shfl(v, 0, 64);  // one value for the whole wave, so every lane takes the same decision
@@ -744,7 +750,19 @@ __global__ __launch_bounds__(64 * JW) void jacobi_svd_kernel(const SvdJob* __res
     for (int i = tid; i < M * N; i += NT) A[i] = J.A[(size_t)(i / M) * J.lda + i % M];
   for (long long i = tid; i < (long long)N * N; i += NT) V[i] = (i % (N + 1) == 0) ? 1.0 : 0.0;
   __syncthreads();
+  __shared__ double fro_w[JW];
+  {
+    double s2 = 0.0;
+    for (int j = wave; j < N; j += JW)
+      for (int i = lane; i < M; i += 64) s2 = fma(A[(size_t)j * lda + i], A[(size_t)j * lda + i], s2);
+    s2 = wave_sum(s2);
+    if (lane == 0) fro_w[wave] = s2;
+  }
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int w = 0; w < JW; ++w) fro2 += fro_w[w];
   const double tol = 2.2e-16 * (double)M;
+  const double zero2 = tol * tol * fro2;  // |a_j|^2 at or below this: a numerically zero column
   const int Np = N + (N & 1);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
@@ -759,30 +777,69 @@ __global__ __launch_bounds__(64 * JW) void jacobi_svd_kernel(const SvdJob* __res
         double* ap = A + (size_t)p * lda;
         double* aq = A + (size_t)q * lda;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < M; i += 64) {
-          const double x = ap[i], y = aq[i];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (!(fabs(ga) > tol * sqrt(al * be))) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-        for (int i = lane; i < M; i += 64) {
-          const double x = ap[i], y = aq[i];
-          ap[i] = c * x - sn * y;
-          aq[i] = sn * x + c * y;
-        }
-        double* vp = V + (size_t)p * N;
-        double* vq = V + (size_t)q * N;
-        for (int i = lane; i < N; i += 64) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = c * x - sn * y;
-          vq[i] = sn * x + c * y;
+        if (M <= 64 * JR) {
+          // both columns stay in registers between the dot products and the rotation
+          double x[JR], y[JR];
+#pragma unroll
+          for (int u = 0; u < JR; ++u) {
+            const int i = lane + 64 * u;
+            x[u] = i < M ? ap[i] : 0.0;
+            y[u] = i < M ? aq[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < JR; ++u) {
+            al = fma(x[u], x[u], al);
+            be = fma(y[u], y[u], be);
+            ga = fma(x[u], y[u], ga);
+          }
+          al = wave_sum(al);
+          be = wave_sum(be);
+          ga = wave_sum(ga);
+          if (!(fabs(ga) > tol * sqrt(al * be)) || !(fmin(al, be) > zero2)) continue;
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+          for (int u = 0; u < JR; ++u) {
+            const int i = lane + 64 * u;
+            if (i < M) {
+              ap[i] = c * x[u] - sn * y[u];
+              aq[i] = sn * x[u] + c * y[u];
+            }
+          }
+          double* vp = V + (size_t)p * N;
+          double* vq = V + (size_t)q * N;
+          for (int i = lane; i < N; i += 64) {
+            const double xv = vp[i], yv = vq[i];
+            vp[i] = c * xv - sn * yv;
+            vq[i] = sn * xv + c * yv;
+          }
+        } else {
+          for (int i = lane; i < M; i += 64) {
+            const double x = ap[i], y = aq[i];
+            al = fma(x, x, al);
+            be = fma(y, y, be);
+            ga = fma(x, y, ga);
+          }
+          al = wave_sum(al);
+          be = wave_sum(be);
+          ga = wave_sum(ga);
+          if (!(fabs(ga) > tol * sqrt(al * be)) || !(fmin(al, be) > zero2)) continue;
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          for (int i = lane; i < M; i += 64) {
+            const double x = ap[i], y = aq[i];
+            ap[i] = c * x - sn * y;
+            aq[i] = sn * x + c * y;
+          }
+          double* vp = V + (size_t)p * N;
+          double* vq = V + (size_t)q * N;
+          for (int i = lane; i < N; i += 64) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = c * x - sn * y;
+            vq[i] = sn * x + c * y;
+          }
         }
         if (lane == 0) rotated = 1;
       }
