@@ -29,6 +29,10 @@ struct BsGroup { long long in_base; int ncols, spec0, nspec, ld; int cls[4]; };
 // offset in a stage-4 panel is the sector start + rank * n_beta).  Light rows
 // read operator entries [e0, e1); heavy rows read the staging row at h.
 struct MixRow { long long b[4]; long long h; int e0, e1, sy, rank, pad0, pad1; };
+// One mix workgroup: group g, spectator columns [c0, c0 + 256), output rows [r0, r1).  When
+// ns > 0 the distinct input rows its rows read are stage[s0 .. s0 + ns) and are loaded once
+// into LDS; operator entry e then reads staged row oloc[e].
+struct MixTile { int g, c0, r0, r1, s0, ns, pad0, pad1; };
 struct BsS4Tile { long long abase, bbase; int M, N, K, m0, n0, k0, k1, slot; };
 struct BsRedTile { int M, N, m0, n0, slot0, nsplit, row0, pad; };
 struct BsPair { int C, beta, koff, bprime; };
@@ -40,13 +44,13 @@ struct BsPair { int C, beta, koff, bprime; };
 // the MFMA GEMM into a staging buffer, then scattered like the light rows.
 struct BsHeavy { int g, H, Nin, Nin4, cols, ld; long long in_base, w_off, tmp_off; };
 struct BsMix {
-  int ntiles = 0, nhtiles = 0;
+  int ntiles = 0, nhtiles = 0, nstage = 0, noloc = 0, nstaged = 0;  // nstaged: light tiles that stage
   double flops = 0.0, nin = 0.0, nout = 0.0;  // algorithmic flops; elements read and written once
   // per kernel: gather of the light rows, GEMM and scatter of the heavy rows (flops, elements)
   double fl_light = 0.0, el_light = 0.0, fl_heavy = 0.0, el_heavy = 0.0, el_scatter = 0.0;
   long long ntmp = 0;                         // staging elements of the heavy rows
   std::vector<BsHeavy> heavy;
-  DevMem tiles, groups, rows, ocol, oval64, oval32, spec;
+  DevMem tiles, groups, rows, ocol, oval64, oval32, spec, stage, oloc;
   DevMem htiles, hrows, hw64, hw32;
 };
 

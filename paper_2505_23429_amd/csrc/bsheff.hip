@@ -31,6 +31,7 @@ constexpr int MIX_COLS = 256;  // spectator columns per mix workgroup (one per t
 constexpr int MIX_ROWS = 64;   // output rows per mix workgroup
 constexpr int KSPLIT = 2048;   // K chunk of one stage-4 workgroup
 constexpr int HEAVY_MIN = 32;  // output rows with more operator entries go through the dense GEMM
+constexpr int MIX_STAGE = 32;  // input rows a mix workgroup stages in LDS (>= HEAVY_MIN: any light row fits)
 
 struct Sectors {
   std::vector<Q2> q;
@@ -205,16 +206,26 @@ __device__ inline long long pick4(long long a0, long long a1, long long a2, long
 
 template <typename T, int MODE, bool HEAVY>
 __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
-    const int4* __restrict__ tiles, const BsGroup* __restrict__ groups, const MixRow* __restrict__ rows,
+    const MixTile* __restrict__ tiles, const BsGroup* __restrict__ groups, const MixRow* __restrict__ rows,
     const int* __restrict__ ocol, const T* __restrict__ oval, const int4* __restrict__ spec,
     const T* __restrict__ in, long long nin, T* __restrict__ out, long long nout, int* __restrict__ err, int nbe,
     const long long* __restrict__ specoff, const int* __restrict__ bshift, const long long* __restrict__ pbase,
     const int* __restrict__ kbeta, const int* __restrict__ kstart, const int* __restrict__ nbeta, int round_bf16,
-    const T* __restrict__ tmp, long long ntmp) {
-  const int4 t = tiles[blockIdx.x];
-  const BsGroup G = groups[t.x];
-  const int col = t.y + (int)threadIdx.x;
+    const T* __restrict__ tmp, long long ntmp, const int* __restrict__ stage, int nstage,
+    const int* __restrict__ oloc, int noloc) {
+  // staged input rows [MIX_STAGE][MIX_COLS] in dynamic LDS (given only to launches that
+  // stage); every thread reads back only its own column, so no barrier is needed
+  extern __shared__ __align__(16) unsigned char mix_smem[];
+  T(*stg)[MIX_COLS] = reinterpret_cast<T(*)[MIX_COLS]>(mix_smem);
+  const MixTile t = tiles[blockIdx.x];
+  const BsGroup G = groups[t.g];
+  const int col = t.c0 + (int)threadIdx.x;
   if (col >= G.ncols) return;
+  const bool in_lds = !HEAVY && t.ns > 0;
+  if (in_lds && (t.ns > MIX_STAGE || t.s0 < 0 || t.s0 + t.ns > nstage)) {
+    err[0] = 4;
+    return;
+  }
   int lo = 0, hi = G.nspec - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -257,6 +268,36 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
   const T* src = in + G.in_base + col;
   const long long ld = G.ld;
   const long long lim = nin - G.in_base - col;  // src[q] valid for 0 <= q < lim
+  if (in_lds) {
+    // eight loads in flight before their LDS stores
+    for (int k0 = 0; k0 < t.ns; k0 += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = T(0);
+        if (k0 + u < t.ns) {
+          const long long q = (long long)stage[t.s0 + k0 + u] * ld;
+          if (q >= 0 && q < lim) v[u] = src[q]; else err[0] = 4;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < t.ns) stg[k0 + u][threadIdx.x] = v[u];
+    }
+  }
+  // input value of operator entry e for this column
+  auto in_at = [&](int e) -> T {
+    if (in_lds) {
+      const int l = e >= 0 && e < noloc ? oloc[e] : -1;
+      if (l >= 0 && l < t.ns) return stg[l][threadIdx.x];
+      err[0] = 4;
+      return T(0);
+    }
+    const long long q = (long long)ocol[e] * ld;
+    if (q >= 0 && q < lim) return src[q];
+    err[0] = 4;
+    return T(0);
+  };
   auto store = [&](const MixRow& R, T v) {
     long long d;
     const long long c = pick4<T>(c0, c1, c2, c3, R.sy);
@@ -279,10 +320,7 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
       const long long q = R.h + col;
       if (q < ntmp) acc = tmp[q]; else err[0] = 4;
     }
-    for (int e = R.e0; e < R.e1; ++e) {
-      const long long q = (long long)ocol[e] * ld;
-      if (q >= 0 && q < lim) acc += oval[e] * src[q]; else err[0] = 4;
-    }
+    for (int e = R.e0; e < R.e1; ++e) acc += oval[e] * in_at(e);
     return acc;
   };
   auto staged = [&](const MixRow& R) {
@@ -293,17 +331,11 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
     err[0] = 4;
     return T(0);
   };
-  int r = t.z;
-  for (; r + 4 <= t.w; r += 4) {
+  int r = t.r0;
+  for (; r + 4 <= t.r1; r += 4) {
     const MixRow R0 = rows[r], R1 = rows[r + 1], R2 = rows[r + 2], R3 = rows[r + 3];
     if (R0.e1 - R0.e0 == 1 && R1.e1 - R1.e0 == 1 && R2.e1 - R2.e0 == 1 && R3.e1 - R3.e0 == 1) {
-      const long long q0 = (long long)ocol[R0.e0] * ld, q1 = (long long)ocol[R1.e0] * ld;
-      const long long q2 = (long long)ocol[R2.e0] * ld, q3 = (long long)ocol[R3.e0] * ld;
-      if (q0 < 0 || q0 >= lim || q1 < 0 || q1 >= lim || q2 < 0 || q2 >= lim || q3 < 0 || q3 >= lim) {
-        err[0] = 4;
-        continue;
-      }
-      const T v0 = src[q0], v1 = src[q1], v2 = src[q2], v3 = src[q3];
+      const T v0 = in_at(R0.e0), v1 = in_at(R1.e0), v2 = in_at(R2.e0), v3 = in_at(R3.e0);
       const T h0 = staged(R0), h1 = staged(R1), h2 = staged(R2), h3 = staged(R3);
       store(R0, h0 + oval[R0.e0] * v0);
       store(R1, h1 + oval[R1.e0] * v1);
@@ -316,7 +348,7 @@ __global__ __launch_bounds__(MIX_COLS) void mix_kernel(
       store(R3, value(R3));
     }
   }
-  for (; r < t.w; ++r) {
+  for (; r < t.r1; ++r) {
     const MixRow R = rows[r];
     store(R, value(R));
   }
@@ -492,12 +524,15 @@ static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std
   std::vector<int> ocol;
   std::vector<double> oval;
   std::vector<MixRow> lrows, hrows_all;
-  std::vector<int4> tiles;
+  std::vector<MixTile> tiles;
   std::vector<BsGroup> groups(ng);
-  std::vector<int4> htiles;
+  std::vector<MixTile> htiles;
+  std::vector<int> stage;  // staged input rows of the light tiles
+  std::vector<int> oloc;   // per operator entry: its input row's position in its tile's staged list
   std::vector<double> hw;
   m.heavy.clear();
   m.ntmp = 0;
+  m.nstaged = 0;
   m.flops = m.nin = m.nout = 0.0;
   m.fl_light = m.el_light = m.fl_heavy = m.el_heavy = m.el_scatter = 0.0;
   for (int g = 0; g < ng; ++g) {
@@ -553,9 +588,57 @@ static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std
       m.fl_light += 2.0 * (double)nnz_g * cols[g];
       m.el_light += (double)(nrows_in[g] + (r1 - r0)) * cols[g];
     }
-    if (r1 > r0)
+    if (r1 > r0) {
+      // Rows whose operator entries re-read the same input rows (many more entries than
+      // distinct inputs over the group) are cut into chunks whose distinct inputs fit the
+      // LDS stage; each chunk's inputs are then read once per column instead of once per
+      // entry.  Groups without that reuse keep direct reads in chunks of MIX_ROWS rows.
+      long long nent = 0;
+      std::vector<int> dist;
+      for (int r = r0; r < r1; ++r)
+        for (int e = lrows[r].e0; e < lrows[r].e1; ++e) {
+          dist.push_back(ocol[e]);
+          ++nent;
+        }
+      std::sort(dist.begin(), dist.end());
+      dist.erase(std::unique(dist.begin(), dist.end()), dist.end());
+      const bool use_stage = (double)nent >= 1.5 * (double)dist.size();
+      oloc.resize(ocol.size(), -1);  // the group's light-row entries are all in ocol by now
+      std::vector<std::array<int, 4>> chunks;  // r0, r1, s0, ns
+      if (!use_stage) {
+        for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) chunks.push_back({q0, std::min(q0 + MIX_ROWS, r1), 0, 0});
+      } else {
+        int q = r0;
+        std::vector<int> cur, nxt;
+        while (q < r1) {
+          cur.clear();
+          int q1 = q;
+          while (q1 < r1 && q1 - q < MIX_ROWS) {
+            nxt = cur;
+            for (int e = lrows[q1].e0; e < lrows[q1].e1; ++e) nxt.push_back(ocol[e]);
+            std::sort(nxt.begin(), nxt.end());
+            nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
+            if ((int)nxt.size() > MIX_STAGE && q1 > q) break;
+            cur.swap(nxt);
+            ++q1;
+          }
+          if ((int)cur.size() > MIX_STAGE)
+            throw std::runtime_error("block-sparse plan: a light row reads more input rows than the mix stage holds");
+          const int s0 = (int)stage.size();
+          stage.insert(stage.end(), cur.begin(), cur.end());
+          for (int r = q; r < q1; ++r)
+            for (int e = lrows[r].e0; e < lrows[r].e1; ++e)
+              oloc[e] = (int)(std::lower_bound(cur.begin(), cur.end(), ocol[e]) - cur.begin());
+          chunks.push_back({q, q1, s0, (int)cur.size()});
+          q = q1;
+        }
+      }
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
-        for (int q0 = r0; q0 < r1; q0 += MIX_ROWS) tiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, r1)));
+        for (const auto& ch : chunks) {
+          tiles.push_back(MixTile{g, c0, ch[0], ch[1], ch[2], ch[3], 0, 0});
+          m.nstaged += ch[3] > 0;
+        }
+    }
     if (!hro.empty()) {
       // GEMM over the group's shared input rows [0, Kd); the other entries of a heavy
       // row are added by the scatter pass
@@ -603,10 +686,13 @@ static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std
       if (Kd > 0) m.heavy.push_back(hv);
       const int q1 = (int)hrows_all.size();
       for (int c0 = 0; c0 < cols[g]; c0 += MIX_COLS)
-        for (int q0 = h0; q0 < q1; q0 += MIX_ROWS) htiles.push_back(make_int4(g, c0, q0, std::min(q0 + MIX_ROWS, q1)));
+        for (int q0 = h0; q0 < q1; q0 += MIX_ROWS)
+          htiles.push_back(MixTile{g, c0, q0, std::min(q0 + MIX_ROWS, q1), 0, 0, 0, 0});
     }
   }
   if (ocol.empty()) { ocol.push_back(0); oval.push_back(0.0); }
+  oloc.resize(ocol.size(), -1);
+  if (stage.empty()) stage.push_back(0);
   if (lrows.empty()) lrows.push_back(MixRow{});
   if (hrows_all.empty()) hrows_all.push_back(MixRow{});
   if (hw.empty()) hw.push_back(0.0);
@@ -619,6 +705,10 @@ static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std
   up(m.groups, groups, s);
   up(m.rows, lrows, s);
   up(m.ocol, ocol, s);
+  up(m.stage, stage, s);
+  up(m.oloc, oloc, s);
+  m.nstage = (int)stage.size();
+  m.noloc = (int)oloc.size();
   up(m.oval64, oval, s);
   up(m.oval32, oval32, s);
   if (!htiles.empty()) up(m.htiles, htiles, s);
@@ -959,11 +1049,12 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
   hipStream_t s = E.stream;
   const int slot0 = MODE == 1 ? 1 : 4;
   if (m.ntiles > 0) {
-    hipLaunchKernelGGL((mix_kernel<T, MODE, false>), dim3(m.ntiles), dim3(MIX_COLS), 0, s, m.tiles.as<int4>(),
+    const size_t lds = m.nstaged > 0 ? sizeof(T) * MIX_STAGE * MIX_COLS : 0;
+    hipLaunchKernelGGL((mix_kernel<T, MODE, false>), dim3(m.ntiles), dim3(MIX_COLS), lds, s, m.tiles.as<MixTile>(),
                        m.groups.as<BsGroup>(), m.rows.as<MixRow>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
                        m.spec.as<int4>(), in, nin, out, nout, err, p.nbe, p.specoff.as<long long>(),
                        p.bshift.as<int>(), p.pbase.as<long long>(), p.kbeta.as<int>(), p.kstart.as<int>(),
-                       p.nbeta.as<int>(), rnd ? 1 : 0, (const T*)nullptr, 0LL);
+                       p.nbeta.as<int>(), rnd ? 1 : 0, (const T*)nullptr, 0LL, m.stage.as<int>(), m.nstage, m.oloc.as<int>(), m.noloc);
     BSCHECK(hipGetLastError());
     E.kt_mark(slot0);
   }
@@ -971,11 +1062,11 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
     T* tmp = E.bs_tmp.as<T>();
     gemm_grouped<T>(gdev.template as<GemmGroup<T>>(), gg, s);
     E.kt_mark(slot0 + 1);
-    hipLaunchKernelGGL((mix_kernel<T, MODE, true>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<int4>(),
+    hipLaunchKernelGGL((mix_kernel<T, MODE, true>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<MixTile>(),
                        m.groups.as<BsGroup>(), m.hrows.as<MixRow>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
                        m.spec.as<int4>(), in, nin, out, nout, err, p.nbe, p.specoff.as<long long>(),
                        p.bshift.as<int>(), p.pbase.as<long long>(), p.kbeta.as<int>(), p.kstart.as<int>(),
-                       p.nbeta.as<int>(), rnd ? 1 : 0, (const T*)tmp, m.ntmp);
+                       p.nbeta.as<int>(), rnd ? 1 : 0, (const T*)tmp, m.ntmp, m.stage.as<int>(), m.nstage, m.oloc.as<int>(), m.noloc);
     BSCHECK(hipGetLastError());
     E.kt_mark(slot0 + 2);
   }
