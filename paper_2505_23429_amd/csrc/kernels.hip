@@ -724,9 +724,28 @@ void multi_dot(const double* V, size_t ldv, int m, const double* w, size_t n, do
 // held in LDS for the whole factorisation ((M + N) N <= kJacobiLds doubles).
 constexpr int JW = 16;  // waves per workgroup
 constexpr int JR = 8;   // rows per lane held in registers (columns of up to 512 rows)
+// Sum over the 64 lanes of a wave, the same value in every lane.  Within each row of 16
+// lanes the partial sums are exchanged by DPP moves (xor 1 and xor 2 as quad permutations,
+// then the half-row and row mirrors), each step adding two values that the exchanged lanes
+// hold in swapped order, so all lanes of a row agree bit for bit; the four row sums are then
+// read into scalars and added in a fixed order.  DPP moves stay in the register file, far
+// cheaper than shuffles through the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return v + __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return __shfl(v, 0, 64);  // one value for the whole wave, so every lane takes the same decision
+  v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  v = dpp_add<0x141>(v);  // row_half_mirror: lane i <-> 7 - i within 8
+  v = dpp_add<0x140>(v);  // row_mirror: lane i <-> 15 - i within 16
+  auto row = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+  };
+  return (row(0) + row(16)) + (row(32) + row(48));
 }
 template <bool INLDS>
 __global__ __launch_bounds__(64 * JW) void jacobi_svd_kernel(const SvdJob* __restrict__ jobs, int max_sweeps) {
