@@ -1225,7 +1225,9 @@ class SectorSVD {
       B.K = B.N;
       const long long MN = (long long)B.M * B.N;
       B.A.ensure(sizeof(double) * MN * B.cnt);
-      fill(B.A.p, sizeof(double) * MN * B.cnt, E.stream);
+      // the zero padding matters only to the batched rocSOLVER path (bins wider than the
+      // Jacobi kernel takes); the kernel reads each block at its own size
+      if (B.N > kJacobiMaxN) fill(B.A.p, sizeof(double) * MN * B.cnt, E.stream);
       std::vector<GatherBlk> gb(B.cnt);
       for (int i = 0; i < B.cnt; ++i) {
         const Blk& b = blocks[mem[i]];
