@@ -76,6 +76,11 @@ typedef struct tt_opts {
                          HIP stream, rocBLAS handle and workspaces; 0 = 4.  With 1 every
                          kernel is launched from the calling thread on the context's stream
                          (no worker threads).  Results do not depend on it. */
+  int mix_stage;      /* light rows of the block-sparse product's channel mixes: 0 = stage a
+                         tile's distinct input rows in LDS where the group's operator entries
+                         outnumber its distinct input rows 1.5 times or more, 1 = stage every
+                         tile, 2 = never (read every entry's input directly).  Results do not
+                         depend on it up to the rounding of FMA contraction. */
 } tt_opts;
 
 #define TT_MAX_SUB 64

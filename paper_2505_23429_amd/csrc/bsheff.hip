@@ -602,7 +602,8 @@ static void build_mix(Engine& E, BsMix& m, int mode, const SiteOp& so, const std
         }
       std::sort(dist.begin(), dist.end());
       dist.erase(std::unique(dist.begin(), dist.end()), dist.end());
-      const bool use_stage = (double)nent >= 1.5 * (double)dist.size();
+      const int policy = E.opts.mix_stage;
+      const bool use_stage = nent > 0 && (policy == 1 || (policy == 0 && (double)nent >= 1.5 * (double)dist.size()));
       oloc.resize(ocol.size(), -1);  // the group's light-row entries are all in ocol by now
       std::vector<std::array<int, 4>> chunks;  // r0, r1, s0, ns
       if (!use_stage) {

@@ -65,10 +65,37 @@ def small():
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("b", [1, 3, 4])
 def test_window_product_matches_oracle(small, b, prec):
+    ctx, mpo, labels = small
+    _window_case(ctx, mpo, labels, b, prec)
+
+
+@pytest.fixture(scope="module")
+def small_modes(small):
+    """Contexts that force the two ways the light rows of a channel mix read their
+    inputs: every tile staged in LDS (1), or every entry read directly (2)."""
+    from paper_2505_23429_amd.api import Context
+
+    _, mpo, labels = small
+    out = {}
+    for mode in (1, 2):
+        c = Context(chi=48, mix_stage=mode)
+        c.set_mpo(mpo)
+        out[mode] = c
+    return out, mpo, labels
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("b", [1, 3, 5])
+def test_window_product_staging_modes(small_modes, b, prec, mode):
+    ctxs, mpo, labels = small_modes
+    _window_case(ctxs[mode], mpo, labels, b, prec)
+
+
+def _window_case(ctx, mpo, labels, b, prec):
     import torch
     from paper_2505_23429_amd.api import window_apply
 
-    ctx, mpo, labels = small
     ql, qr = np.asarray(labels[b]), np.asarray(labels[b + 2])
     rl, rr = len(ql), len(qr)
     rng = np.random.default_rng(100 + b)
