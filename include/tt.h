@@ -81,6 +81,8 @@ typedef struct tt_opts {
                          outnumber its distinct input rows 1.5 times or more, 1 = stage every
                          tile, 2 = never (read every entry's input directly).  Results do not
                          depend on it up to the rounding of FMA contraction. */
+  int svd_lds;        /* sector SVDs: 1 = a charge block whose factors fit in LDS is factored
+                         there, 0 = every block works in global memory (same arithmetic) */
 } tt_opts;
 
 #define TT_MAX_SUB 64

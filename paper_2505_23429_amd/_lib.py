@@ -30,7 +30,7 @@ class Opts(C.Structure):
         ("chi_max", C.c_int), ("svd_cutoff", C.c_double), ("tie_rel", C.c_double), ("dav_tol", C.c_double),
         ("dav_maxiter", C.c_int), ("dav_maxsub", C.c_int), ("coarse_eps", C.c_double), ("matvec_prec", C.c_int),
         ("refine_fp64", C.c_int), ("lowprec_tol", C.c_double), ("device", C.c_int), ("qn_skip", C.c_int),
-        ("sub_workers", C.c_int), ("mix_stage", C.c_int),
+        ("sub_workers", C.c_int), ("mix_stage", C.c_int), ("svd_lds", C.c_int),
     ]
 
 

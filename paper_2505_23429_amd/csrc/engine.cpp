@@ -1260,7 +1260,7 @@ class SectorSVD {
         if (bins[bi].N > kJacobiMaxN) continue;
         for (int t : *members[bi]) {
           const long long m = std::max(blocks[t].m, blocks[t].n), n = std::min(blocks[t].m, blocks[t].n);
-          if ((m + n) * n > kJacobiLds) vtot += n * n;
+          if (!E.opts.svd_lds || (m + n) * n > kJacobiLds) vtot += n * n;
         }
       }
       DevMem Vs, jdev[2];
@@ -1273,7 +1273,7 @@ class SectorSVD {
         for (int i = 0; i < B.cnt; ++i) {
           const Blk& b = blocks[mem[i]];
           const int m = std::max(b.m, b.n), n = std::min(b.m, b.n);
-          const int in_lds = (long long)(m + n) * n <= kJacobiLds ? 1 : 0;
+          const int in_lds = E.opts.svd_lds && (long long)(m + n) * n <= kJacobiLds ? 1 : 0;
           jobs[in_lds].push_back(SvdJob{B.A.as<double>() + (size_t)B.M * B.N * i, in_lds ? nullptr : Vs.as<double>() + voff,
                                         B.U.as<double>() + (size_t)B.M * B.K * i, B.S.as<double>() + (size_t)B.K * i,
                                         B.Vt.as<double>() + (size_t)B.K * B.N * i, B.info.as<int>() + i, m, n, B.M, B.M,

@@ -91,6 +91,24 @@ def test_a2dmrg_sweep_matches_oracle(L, seed, chi, lengths):
     assert max(q.shape[0] for q in l2) <= chi
 
 
+def test_a2dmrg_sweep_global_memory_svd_matches_oracle():
+    """The same sweep with every sector SVD block factored by the global-memory path of
+    the Jacobi kernel (at these sizes the blocks would otherwise all fit in LDS)."""
+    L, seed, chi, lengths = 8, 1008, 24, (2, 3, 3)
+    mpo, cores, labels, prob, oc = _setup(L, seed, chi, 3 + chi)
+    ctx = _ctx(mpo, cores, labels, chi=chi, dav_tol=1e-10, svd_lds=False)
+    rep = ctx.sweep(list(lengths))
+    ro = T.a2dmrg_sweep(prob, oc, labels, chi, lengths)
+    assert np.abs(rep["E_local"] - np.array(ro.E_local)).max() < 1e-8
+    assert abs(rep["lambda"] - ro.lam) < 1e-8
+    assert abs(rep["E_after"] - ro.E_new) < 1e-8
+    c2, _ = ctx.get_mps()
+    assert abs(prob.energy(c2) - ro.E_new) < 1e-8
+    for U in c2[:-1]:
+        M = U.reshape(-1, U.shape[2])
+        assert np.abs(M.T @ M - np.eye(M.shape[1])).max() < 1e-12
+
+
 def test_a2dmrg_full_rank_single_sweep_exact():
     mpo, cores, labels, prob, oc = _setup(6, 1001, 64, 2001)
     ctx = _ctx(mpo, cores, labels, chi=64, dav_tol=1e-10)
