@@ -83,6 +83,11 @@ typedef struct tt_opts {
                          depend on it up to the rounding of FMA contraction. */
   int svd_lds;        /* sector SVDs: 1 = a charge block whose factors fit in LDS is factored
                          there, 0 = every block works in global memory (same arithmetic) */
+  long long worker_alloc_limit; /* for testing the recovery from device memory exhaustion: a
+                         task on a concurrent worker whose device allocations exceed this many
+                         bytes fails as if the device were full (0 = no limit).  Such tasks,
+                         like those of a real exhaustion, are run again one after another on
+                         the context, with the same result. */
 } tt_opts;
 
 #define TT_MAX_SUB 64

@@ -31,6 +31,7 @@ class Opts(C.Structure):
         ("dav_maxiter", C.c_int), ("dav_maxsub", C.c_int), ("coarse_eps", C.c_double), ("matvec_prec", C.c_int),
         ("refine_fp64", C.c_int), ("lowprec_tol", C.c_double), ("device", C.c_int), ("qn_skip", C.c_int),
         ("sub_workers", C.c_int), ("mix_stage", C.c_int), ("svd_lds", C.c_int),
+        ("worker_alloc_limit", C.c_longlong),
     ]
 
 

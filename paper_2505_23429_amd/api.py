@@ -37,7 +37,7 @@ class Context:
 
     def __init__(self, chi=64, dav_tol=1e-8, dav_maxiter=200, dav_maxsub=24, coarse_eps=1e-8, svd_cutoff=1e-12,
                  tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True,
-                 sub_workers=0, mix_stage=0, svd_lds=True):
+                 sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0):
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -56,6 +56,7 @@ class Context:
         o.sub_workers = int(sub_workers)
         o.mix_stage = int(mix_stage)
         o.svd_lds = int(bool(svd_lds))
+        o.worker_alloc_limit = int(worker_alloc_limit)
         self.opts = o
         h = C.c_void_p()
         rc = self.lib.tt_create(C.byref(o), C.byref(h))

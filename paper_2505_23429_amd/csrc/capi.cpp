@@ -74,6 +74,7 @@ void tt_default_opts(tt_opts* o) {
   o->sub_workers = 0;
   o->mix_stage = 0;
   o->svd_lds = 1;
+  o->worker_alloc_limit = 0;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -81,7 +82,8 @@ int tt_create(const tt_opts* opts, void** out) {
   *out = nullptr;
   if (opts->chi_max <= 0 || opts->dav_maxiter <= 0 || opts->dav_maxsub < 4 || opts->matvec_prec < 0 ||
       opts->matvec_prec > 2 || opts->sub_workers < 0 || opts->sub_workers > TT_MAX_SUB ||
-      opts->mix_stage < 0 || opts->mix_stage > 2 || opts->svd_lds < 0 || opts->svd_lds > 1)
+      opts->mix_stage < 0 || opts->mix_stage > 2 || opts->svd_lds < 0 || opts->svd_lds > 1 ||
+      opts->worker_alloc_limit < 0)
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);

@@ -309,6 +309,15 @@ void DevMem::release() {
   cap = 0;
   own = true;
 }
+// allocation budget of the task running on this thread (worker_alloc_limit; -1: none)
+static thread_local long long tl_alloc_budget = -1;
+static void charge_budget(size_t bytes) {
+  if (tl_alloc_budget < 0) return;
+  if ((long long)bytes > tl_alloc_budget)
+    throw DeviceOOM("device allocation of " + std::to_string(bytes) + " bytes failed (task allocation limit)");
+  tl_alloc_budget -= (long long)bytes;
+}
+
 void DevMem::ensure(size_t bytes) {
   if (own && p && bytes <= cap) {
     if (bytes > n) n = bytes;
@@ -317,11 +326,12 @@ void DevMem::ensure(size_t bytes) {
   if (bytes <= n) return;
   release();
   if (bytes == 0) return;
+  charge_budget(bytes);
   p = bytes >= Arena::kMin ? arena().get(bytes, cap) : nullptr;
   if (!p) p = pool().get(bytes, cap);
   if (!p) {
     cap = 0;
-    throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+    throw DeviceOOM("device allocation of " + std::to_string(bytes) + " bytes failed");
   }
   n = bytes;
 }
@@ -329,11 +339,12 @@ void DevMem::resize_zero(size_t bytes, hipStream_t s) {
   if (!(own && p && bytes <= cap)) {
     release();
     if (bytes) {
+      charge_budget(bytes);
       p = bytes >= Arena::kMin ? arena().get(bytes, cap) : nullptr;
       if (!p) p = pool().get(bytes, cap);
       if (!p) {
         cap = 0;
-        throw std::runtime_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+        throw DeviceOOM("device allocation of " + std::to_string(bytes) + " bytes failed");
       }
     }
   }
@@ -455,6 +466,18 @@ Engine::~Engine() {
   for (hipEvent_t& ev : kt_ev)
     if (ev) (void)hipEventDestroy(ev);
   if (stream) (void)hipStreamDestroy(stream);
+}
+
+void Engine::release_workspaces() {
+  for (DevMem* m : {&ws0, &ws1, &ws2, &ws3, &wsd, &wsp, &dav_V, &dav_AV, &dav_t, &dav_u, &dav_Au, &dav_c, &dav_mask,
+                    &dav_t2, &dav_t3, &wlow_x, &wlow_y, &wlow_L, &wlow_R, &wlow_Rt, &envq_o, &envq_i, &bs_t1, &bs_t2,
+                    &bs_t3, &bs_part, &bs_tmp, &bs_gg1, &bs_gg2, &be_t1, &be_panel, &be_up, &be_tmp})
+    m->release();
+  bs_zero_serial = -1;
+  bs_zero_prec = -1;
+  bs_gg_serial = -1;
+  bs_gg_prec = -1;
+  for (auto& q : bs_gg_ptr) q = nullptr;
 }
 
 void Engine::free_caches() {
@@ -2477,6 +2500,7 @@ void Engine::absorb_counters(Engine& w) {
 
 void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::function<void(Engine&, int)>& fn) {
   int nw = opts.sub_workers > 0 ? opts.sub_workers : 4;
+  if (oom_cap > 0) nw = std::min(nw, oom_cap);
   nw = std::max(1, std::min(nw, ntask));
   if (nw == 1) {
     for (int t = 0; t < ntask; ++t) fn(*this, t);
@@ -2498,6 +2522,11 @@ void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::fu
   }
   std::atomic<int> next{0};
   std::vector<std::exception_ptr> errs(nw);
+  // tasks a worker gave up on when the device ran out of memory: that worker frees its
+  // workspaces and leaves, the others go on; the tasks are run again below
+  std::mutex fmu;
+  std::vector<int> failed;
+  std::vector<char> oom(nw, 0);
   std::vector<std::thread> th;
   for (int w = 0; w < nw; ++w) {
     Engine* W = workers[w].get();
@@ -2508,10 +2537,25 @@ void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::fu
         for (;;) {
           const int i = next.fetch_add(1);
           if (i >= ntask) break;
-          fn(*W, order[i]);
+          try {
+            tl_alloc_budget = opts.worker_alloc_limit > 0 ? opts.worker_alloc_limit : -1;
+            fn(*W, order[i]);
+            tl_alloc_budget = -1;
+          } catch (const DeviceOOM&) {
+            tl_alloc_budget = -1;
+            (void)hipStreamSynchronize(W->stream);
+            {
+              std::lock_guard<std::mutex> g(fmu);
+              failed.push_back(order[i]);
+            }
+            oom[w] = 1;
+            W->release_workspaces();
+            break;
+          }
         }
         HC(hipStreamSynchronize(W->stream));
       } catch (...) {
+        tl_alloc_budget = -1;
         errs[w] = std::current_exception();
         next.store(ntask);  // the other workers stop after their current task
         (void)hipStreamSynchronize(W->stream);
@@ -2523,6 +2567,24 @@ void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::fu
   for (int w = 0; w < nw; ++w) absorb_counters(*workers[w]);
   for (auto& e : errs)
     if (e) std::rethrow_exception(e);
+  // Every task is independent and writes only its own outputs, so a task that ran out of
+  // memory, or was never started because all workers left, is run again from the start,
+  // one after another on this engine once the workers have given their memory back.  The
+  // arithmetic is the same, so is the result; later calls use as many workers as fitted.
+  const int started = std::min(next.load(), ntask);
+  for (int k = started; k < ntask; ++k) failed.push_back(order[k]);
+  if (!failed.empty()) {
+    int fitted = 0;
+    for (int w = 0; w < nw; ++w) fitted += !oom[w];
+    oom_cap = std::max(1, fitted);
+    for (int w = 0; w < (int)workers.size(); ++w) workers[w]->release_workspaces();
+    if (verbose)
+      std::fprintf(stderr, "[tt] device memory ran out with %d concurrent tasks: %zu task(s) run again one after "
+                   "another; later calls use at most %d workers\n", nw, failed.size(), oom_cap);
+    std::sort(failed.begin(), failed.end());
+    for (int j : failed) fn(*this, j);
+    HC(hipStreamSynchronize(stream));
+  }
 }
 
 void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {

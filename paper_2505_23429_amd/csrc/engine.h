@@ -26,6 +26,11 @@ inline int padr(int r) { return ((r + PAD - 1) / PAD) * PAD; }
 using Q2 = std::array<int, 2>;
 using Labels = std::vector<Q2>;
 
+// a device allocation that neither the large-block arena nor the block pool could serve
+struct DeviceOOM : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
 struct DevMem {
   void* p = nullptr;
   size_t n = 0;      // bytes in use
@@ -273,6 +278,11 @@ class Engine {
   int bs_gg_prec = -1;
   const void* bs_gg_ptr[3] = {nullptr, nullptr, nullptr};
   int bs_zero_prec = -1;
+
+  // releases every workspace buffer of this engine (a worker that ran out of device memory)
+  void release_workspaces();
+  // concurrent task limit learned from a device allocation failure (0: none)
+  int oom_cap = 0;
 
  private:
   void free_caches();
