@@ -40,3 +40,23 @@ def test_default_options_and_invalid_create():
     assert lib.tt_create(C.byref(bad), C.byref(h)) == _lib.TT_EINVAL
     assert lib.tt_create(None, C.byref(h)) == _lib.TT_EINVAL
     assert lib.tt_last_error(None) == b"null context"
+
+
+@pytest.mark.parametrize("field,value", [
+    ("chi_max", 0), ("dav_maxiter", 0), ("dav_maxsub", 3), ("matvec_prec", 3), ("matvec_prec", -1),
+    ("sub_workers", -1), ("sub_workers", 65), ("mix_stage", 3), ("mix_stage", -1), ("svd_lds", 2),
+    ("worker_alloc_limit", -1),
+])
+def test_create_rejects_each_invalid_option(field, value):
+    """tt_create validates the options before it touches the device: every value outside
+    its documented range is refused with TT_EINVAL and no context."""
+    from paper_2505_23429_amd import _lib
+
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.tt_default_opts(C.byref(o))
+    assert (o.mix_stage, o.svd_lds, o.worker_alloc_limit, o.sub_workers) == (0, 1, 0, 0)
+    setattr(o, field, value)
+    h = C.c_void_p()
+    assert lib.tt_create(C.byref(o), C.byref(h)) == _lib.TT_EINVAL
+    assert not h.value
