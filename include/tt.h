@@ -75,7 +75,10 @@ typedef struct tt_opts {
                          concurrently on this many workers, each a host thread with its own
                          HIP stream, rocBLAS handle and workspaces; 0 = 4.  With 1 every
                          kernel is launched from the calling thread on the context's stream
-                         (no worker threads).  Results do not depend on it. */
+                         (no worker threads).  If a worker's task runs out of device memory,
+                         that task (and any not yet started) is run again one after another
+                         on the context, and later calls use as many workers as fitted.
+                         Results do not depend on it. */
   int mix_stage;      /* light rows of the block-sparse product's channel mixes: 0 = stage a
                          tile's distinct input rows in LDS where the group's operator entries
                          outnumber its distinct input rows 1.5 times or more, 1 = stage every
