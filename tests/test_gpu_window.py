@@ -85,7 +85,7 @@ def small_modes(small):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("b", [1, 3, 5])
 def test_window_product_staging_modes(small_modes, b, prec, mode):
     ctxs, mpo, labels = small_modes
