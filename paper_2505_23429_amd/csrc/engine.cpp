@@ -446,7 +446,6 @@ Engine::Engine(const tt_opts& o)
 Engine::Engine(const Engine& parent, int)
     : opts(parent.opts), prob(parent.prob), L(prob->L), mpo(prob->mpo), Rb(prob->Rb), chan_q(prob->chan_q),
       chan_q_dev(prob->chan_q_dev) {
-  is_worker = true;
   verbose = parent.verbose;
   verbose_level = parent.verbose_level;
   have_mpo = parent.have_mpo;

@@ -192,7 +192,6 @@ class Engine {
   // and the wall time of the batched SVD phases
   std::map<std::pair<int, int>, std::array<double, 3>> svd_bins;
   double svd_seconds = 0.0;
-  bool is_worker = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int warn = 0;
   bool verbose = false;
