@@ -25,4 +25,14 @@ Contents
               gradients of ``<x|H_eff|x>``; used for kernel-level parity at
               any size on sampled outputs.
 ``lanczos``   a plain Lanczos eigensolver with full reorthogonalisation.
+``mpo``       the oracle's own matrix product operator of the Hamiltonian
+              (eq. MPO), built from Jordan-Wigner site factors of every term;
+              independent of the library's MPO builder.
+``chain``     two-site DMRG (Algorithm 1) and the additive two-level DMRG
+              (Algorithm 2, Extension Two) through environment chains only:
+              Lanczos local solves on the effective operator, coarse matrices
+              as TT inner products and sandwiches (Appendix A.2), Step 4 as TT
+              rounding of the direct-sum TT.  No dense state vector, so it
+              reaches L = 12..16 at chi = 128..160 (minutes to hours).
+``density``   one-particle density matrix by transfer matrices.
 """
