@@ -26,9 +26,11 @@
  *
  * Ownership: host arrays are read during the call and copied; the caller keeps
  * them.  Device pointers passed to the *_dev entry points are borrowed for the
- * duration of the call and used on the context's stream (the call returns
- * after the stream is synchronised).  The context owns all other device memory
- * (allocated with hipMalloc on the context's device, released by tt_destroy).
+ * duration of the call and used on the context's stream (tt_opts.stream, or
+ * the context's own; the call returns after the stream is synchronised).  The
+ * context holds all other device memory it needs: from the caller's allocator
+ * callbacks (tt_opts.dev_alloc/dev_free) when given, otherwise from its own
+ * pools of hipMalloc'ed chunks on the context's device; tt_destroy releases it.
  *
  * Errors: no exception crosses the ABI.  Return value 0 = success, > 0 =
  * warning (result usable), < 0 = error; tt_last_error() gives a message.
@@ -38,6 +40,7 @@
 #ifndef TT_H
 #define TT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -91,6 +94,21 @@ typedef struct tt_opts {
                          bytes fails as if the device were full (0 = no limit).  Such tasks,
                          like those of a real exhaustion, are run again one after another on
                          the context, with the same result. */
+  void* stream;       /* hipStream_t of the caller (e.g. torch.cuda.current_stream), or NULL:
+                         the context's own stream.  Every call of the context runs on it and
+                         returns after it is synchronised.  Not destroyed by tt_destroy. */
+  void* (*dev_alloc)(size_t bytes, void* stream, void* user);
+                      /* caller's device allocator (e.g. the torch caching allocator), or NULL:
+                         the library's own pools.  Called on the thread that needs the block,
+                         with the stream the block will be used on; returns NULL when out of
+                         memory (the call then fails with TT_ENOMEM or, on a concurrent worker,
+                         recovers as for worker_alloc_limit).  Must be thread-safe. */
+  void (*dev_free)(void* ptr, void* stream, void* user);
+                      /* releases a block from dev_alloc (same stream argument); the library has
+                         synchronised the stream before the call.  Set both callbacks or none.
+                         Blocks live until the call that frees them or tt_destroy, so the
+                         callbacks must stay valid until tt_destroy returns. */
+  void* alloc_user;   /* passed to dev_alloc/dev_free */
 } tt_opts;
 
 #define TT_MAX_SUB 64

@@ -31,8 +31,14 @@ class Opts(C.Structure):
         ("dav_maxiter", C.c_int), ("dav_maxsub", C.c_int), ("coarse_eps", C.c_double), ("matvec_prec", C.c_int),
         ("refine_fp64", C.c_int), ("lowprec_tol", C.c_double), ("device", C.c_int), ("qn_skip", C.c_int),
         ("sub_workers", C.c_int), ("mix_stage", C.c_int), ("svd_lds", C.c_int),
-        ("worker_alloc_limit", C.c_longlong),
+        ("worker_alloc_limit", C.c_longlong), ("stream", C.c_void_p), ("dev_alloc", C.c_void_p),
+        ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p),
     ]
+
+
+# tt_opts.dev_alloc / dev_free callback types
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
 
 _N = (TT_MAX_SUB + 1) * (TT_MAX_SUB + 1)

@@ -6,6 +6,7 @@ points; the context owns its own device state.
 """
 from __future__ import annotations
 
+import copy
 import ctypes as C
 
 import numpy as np
@@ -37,7 +38,10 @@ class Context:
 
     def __init__(self, chi=64, dav_tol=1e-8, dav_maxiter=200, dav_maxsub=24, coarse_eps=1e-8, svd_cutoff=1e-12,
                  tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True,
-                 sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0):
+                 sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0, stream=None, torch_alloc=False):
+        """``stream``: a torch.cuda.Stream (or raw stream handle) every call runs on;
+        ``torch_alloc``: take every device block of the context from the torch caching
+        allocator (tt_opts.dev_alloc/dev_free) instead of the library's own pools."""
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -57,6 +61,13 @@ class Context:
         o.mix_stage = int(mix_stage)
         o.svd_lds = int(bool(svd_lds))
         o.worker_alloc_limit = int(worker_alloc_limit)
+        if stream is not None:
+            o.stream = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        self._callbacks = None
+        if torch_alloc:
+            self._callbacks = _torch_allocator(device)
+            o.dev_alloc = C.cast(self._callbacks[0], C.c_void_p)
+            o.dev_free = C.cast(self._callbacks[1], C.c_void_p)
         self.opts = o
         h = C.c_void_p()
         rc = self.lib.tt_create(C.byref(o), C.byref(h))
@@ -197,6 +208,23 @@ class Context:
         return E.value, [kg[k].reshape(-1, 4, 4) for k in range(len(g))]
 
 
+def _torch_allocator(device):
+    """ctypes callbacks that hand out and take back blocks of the torch caching
+    allocator (stream-ordered on the stream the library passes)."""
+    import torch
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except RuntimeError:  # out of memory: the library reports TT_ENOMEM
+            return None
+
+    def free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return L.ALLOC_FN(alloc), L.FREE_FN(free)
+
+
 def open_context(mpo, cores, labels, **kw):
     ctx = Context(**kw)
     ctx.set_mpo(mpo)
@@ -206,121 +234,206 @@ def open_context(mpo, cores, labels, **kw):
 
 
 # ---- kernel-level entry points (device tensors from torch) -------------------
+#
+# Every device operand is validated before its pointer crosses the ABI: the
+# library trusts the sizes implied by the other arguments, so a tensor of the
+# wrong shape, dtype or layout would be read or written out of bounds.  Shape
+# and dtype are checked before the device, so these errors are raised (as
+# ValueError) without touching a GPU.
 
-def _sparse(W):
+_DT = {"f64": "float64", "f32": "float32", "bf16": "bfloat16"}
+
+
+def _need(*specs):
+    """Each spec is (tensor, name, dtype, shape or None, element count or None).
+    Shapes, sizes, dtypes and layouts of all operands are checked first, then
+    that every operand is a device tensor."""
+    import torch
+
+    for t, name, dtype, shape, numel in specs:
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+        if shape is not None and tuple(t.shape) != tuple(int(v) for v in shape):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(int(v) for v in shape)}")
+        if numel is not None and t.numel() < numel:
+            raise ValueError(f"{name}: {t.numel()} elements, the call addresses {numel}")
+        want = getattr(torch, dtype)
+        if t.dtype != want:
+            raise ValueError(f"{name}: dtype {t.dtype}, expected {want}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+    for t, name, *_ in specs:
+        if not t.is_cuda:
+            raise ValueError(f"{name}: must be a device tensor")
+
+
+def _need_prec(prec):
+    if prec not in PREC:
+        raise ValueError(f"unknown precision {prec!r} (one of {sorted(PREC)})")
+
+
+def _need_pad(name, v):
+    if v <= 0 or v % 32:
+        raise ValueError(f"{name} = {v} must be a positive multiple of 32")
+
+
+def _sparse(W, R_in, R_out, name):
     A, B, ops = W
     A = np.ascontiguousarray(A, dtype=np.int32)
     B = np.ascontiguousarray(B, dtype=np.int32)
-    ops = np.ascontiguousarray(ops, dtype=np.float64).reshape(-1)
-    return A, B, ops
+    ops = np.ascontiguousarray(ops, dtype=np.float64)
+    if A.ndim != 1 or A.shape != B.shape or ops.shape != (len(A), 4, 4):
+        raise ValueError(f"{name}: entries (A[nnz], B[nnz], ops[nnz, 4, 4]) expected")
+    if len(A) and (A.min() < 0 or A.max() >= R_in or B.min() < 0 or B.max() >= R_out):
+        raise ValueError(f"{name}: channel index outside [0, {R_in}) x [0, {R_out})")
+    return A, B, ops.reshape(-1)
 
 
-def heff_apply(ctx, prec, Lenv, W1, W2, Renv, x, y=None):
-    """y = H_eff x with torch device tensors Lenv [RA][rl][rl], Renv [RC][rr][rr], x [rl][4][4][rr]."""
-    import torch
-
-    RA, rl, _ = Lenv.shape
-    RC, rr, _ = Renv.shape
-    A1, B1, o1 = _sparse(W1)
-    A2, B2, o2 = _sparse(W2)
-    RB = int(max(B1.max(initial=-1), A2.max(initial=-1)) + 1)
-    if y is None:
-        y = torch.empty(x.shape, dtype=torch.float32 if prec == "bf16" else x.dtype, device=x.device)
-    for t in (Lenv, Renv, x, y):
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError("operands must be contiguous device tensors")
-    torch.cuda.synchronize()
-    I32 = C.POINTER(C.c_int32)
-    DP = C.POINTER(C.c_double)
-    rc = ctx.lib.tt_heff_apply_dev(ctx.h, PREC[prec], rl, rr, RA, RB, RC, C.c_void_p(Lenv.data_ptr()),
-                                   C.c_void_p(Renv.data_ptr()), len(A1), A1.ctypes.data_as(I32),
-                                   B1.ctypes.data_as(I32), o1.ctypes.data_as(DP), len(A2), A2.ctypes.data_as(I32),
-                                   B2.ctypes.data_as(I32), o2.ctypes.data_as(DP), C.c_void_p(x.data_ptr()),
-                                   C.c_void_p(y.data_ptr()))
-    ctx._check(rc)
-    return y
+def _pointers(*ts):
+    return [C.c_void_p(t.data_ptr()) for t in ts]
 
 
 def heff_apply_rb(ctx, prec, Lenv, W1, W2, Renv, x, RB, y=None):
-    """As heff_apply with an explicit middle channel count RB."""
+    """y = H_eff x (tt_heff_apply_dev): device tensors Lenv [RA][rl][rl],
+    Renv [RC][rr][rr], x [rl][4][4][rr] in the precision's element type (bf16:
+    bfloat16 operands, float32 y), rl and rr multiples of 32; sparse cores
+    W1 (RA -> RB), W2 (RB -> RC) on the host."""
     import torch
 
-    RA, rl, _ = Lenv.shape
-    RC, rr, _ = Renv.shape
-    A1, B1, o1 = _sparse(W1)
-    A2, B2, o2 = _sparse(W2)
+    _need_prec(prec)
+    RA, rl, RC, rr = Lenv.shape[0], Lenv.shape[1], Renv.shape[0], Renv.shape[1]
+    _need_pad("rl", rl)
+    _need_pad("rr", rr)
+    A1, B1, o1 = _sparse(W1, RA, RB, "W1")
+    A2, B2, o2 = _sparse(W2, RB, RC, "W2")
+    ydt = "float32" if prec == "bf16" else _DT[prec]
+    ops = [(Lenv, "Lenv", _DT[prec], (RA, rl, rl), None), (Renv, "Renv", _DT[prec], (RC, rr, rr), None),
+           (x, "x", _DT[prec], (rl, 4, 4, rr), None)]
+    _need(*ops)
     if y is None:
-        y = torch.empty(x.shape, dtype=torch.float32 if prec == "bf16" else x.dtype, device=x.device)
+        y = torch.empty(x.shape, dtype=getattr(torch, ydt), device=x.device)
+    _need(*ops, (y, "y", ydt, (rl, 4, 4, rr), None))
     torch.cuda.synchronize()
     I32 = C.POINTER(C.c_int32)
     DP = C.POINTER(C.c_double)
-    rc = ctx.lib.tt_heff_apply_dev(ctx.h, PREC[prec], rl, rr, RA, RB, RC, C.c_void_p(Lenv.data_ptr()),
-                                   C.c_void_p(Renv.data_ptr()), len(A1), A1.ctypes.data_as(I32),
+    pL, pR, px, py = _pointers(Lenv, Renv, x, y)
+    rc = ctx.lib.tt_heff_apply_dev(ctx.h, PREC[prec], rl, rr, RA, RB, RC, pL, pR, len(A1), A1.ctypes.data_as(I32),
                                    B1.ctypes.data_as(I32), o1.ctypes.data_as(DP), len(A2), A2.ctypes.data_as(I32),
-                                   B2.ctypes.data_as(I32), o2.ctypes.data_as(DP), C.c_void_p(x.data_ptr()),
-                                   C.c_void_p(y.data_ptr()))
+                                   B2.ctypes.data_as(I32), o2.ctypes.data_as(DP), px, py)
     ctx._check(rc)
     return y
 
 
+def heff_apply(ctx, prec, Lenv, W1, W2, Renv, x, y=None):
+    """As heff_apply_rb with RB = the largest middle channel index + 1."""
+    RB = int(max(np.max(W1[1], initial=-1), np.max(W2[0], initial=-1)) + 1)
+    return heff_apply_rb(ctx, prec, Lenv, W1, W2, Renv, x, RB, y)
+
+
 def window_apply(ctx, b, ql, qr, Lenv, Renv, x, prec="f64", y=None):
-    """y = H_eff x of the context's MPO at sites (b, b+1) with the given FP64
-    device environments and bond labels (tt_window_apply_dev)."""
+    """y = H_eff x of the context's MPO at sites (b, b+1) with FP64 device
+    environments Lenv [R_b][rlp][rlp], Renv [R_{b+2}][rrp][rrp] and x
+    [rlp][4][4][rrp] (rlp, rrp: bond dimensions padded to 32), bond labels on
+    the host (tt_window_apply_dev)."""
     import torch
 
+    _need_prec(prec)
     ql = np.ascontiguousarray(ql, dtype=np.int32)
     qr = np.ascontiguousarray(qr, dtype=np.int32)
+    if ql.ndim != 2 or ql.shape[1] != 2 or qr.ndim != 2 or qr.shape[1] != 2:
+        raise ValueError("ql, qr: (N, 2Sz) label arrays of shape [r][2] expected")
+    rlp, rrp = -(-len(ql) // 32) * 32, -(-len(qr) // 32) * 32
+    if Lenv.ndim != 3 or Renv.ndim != 3:
+        raise ValueError("Lenv, Renv: [channels][bra][ket] expected")
+    ops = [(Lenv, "Lenv", "float64", (Lenv.shape[0], rlp, rlp), None),
+           (Renv, "Renv", "float64", (Renv.shape[0], rrp, rrp), None), (x, "x", "float64", (rlp, 4, 4, rrp), None)]
+    _need(*ops)
     if y is None:
         y = torch.empty_like(x)
+    _need(*ops, (y, "y", "float64", (rlp, 4, 4, rrp), None))
     torch.cuda.synchronize()
     I32 = C.POINTER(C.c_int32)
+    pL, pR, px, py = _pointers(Lenv, Renv, x, y)
     rc = ctx.lib.tt_window_apply_dev(ctx.h, int(b), len(ql), len(qr), ql.ctypes.data_as(I32), qr.ctypes.data_as(I32),
-                                     C.c_void_p(Lenv.data_ptr()), C.c_void_p(Renv.data_ptr()), PREC[prec],
-                                     C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()))
+                                     pL, pR, PREC[prec], px, py)
     ctx._check(rc)
     return y
 
 
 def gemm(ctx, prec, M, N, K, batch, kin, strides, a_kcontig, b_ncontig, A, B, Cout, alpha=1.0, beta=0.0):
-    """Strided batched MFMA GEMM on device tensors (see tt_gemm_dev)."""
+    """Strided batched MFMA GEMM on device tensors (see tt_gemm_dev).  Every
+    operand must hold the largest element offset its strides address."""
     import torch
 
-    st = (C.c_longlong * 10)(*[int(s) for s in strides])
+    _need_prec(prec)
+    st = [int(s) for s in strides]
+    if len(st) != 10 or min(st) < 0:
+        raise ValueError("strides: ten non-negative element strides expected")
+    if min(M, N, K, batch) < 0 or kin <= 0 or K % kin:
+        raise ValueError("sizes: M, N, K, batch >= 0 and K a multiple of kin expected")
+    sAb, sAm, sAkb, sAkk, sBb, sBkb, sBkk, sBn, sCb, sCm = st
+    if M * N * batch > 0:
+        kb = K // kin
+        last_a = (batch - 1) * sAb + (M - 1) * sAm + max(kb - 1, 0) * sAkb + (kin - 1) * sAkk if K else -1
+        last_b = (batch - 1) * sBb + max(kb - 1, 0) * sBkb + (kin - 1) * sBkk + (N - 1) * sBn if K else -1
+        last_c = (batch - 1) * sCb + (M - 1) * sCm + (N - 1)
+        cdt = "float32" if prec == "bf16" else _DT[prec]
+        _need((A, "A", _DT[prec], None, last_a + 1), (B, "B", _DT[prec], None, last_b + 1),
+              (Cout, "C", cdt, None, last_c + 1))
+    st = (C.c_longlong * 10)(*st)
     torch.cuda.synchronize()
+    pa, pb, pc = _pointers(A, B, Cout)
     rc = ctx.lib.tt_gemm_dev(ctx.h, PREC[prec], M, N, K, batch, kin, st, int(a_kcontig), int(b_ncontig), alpha, beta,
-                             C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()), C.c_void_p(Cout.data_ptr()))
+                             pa, pb, pc)
     ctx._check(rc)
     return Cout
 
 
 def env_update(ctx, side, Env, Ubra, Uket, W, RA, RB, out=None):
-    """One environment update (FP64 device tensors).  side 0: left, 1: right."""
+    """One environment update (FP64 device tensors; bond dimensions multiples of
+    32).  side 0: left, Env [RA][rb][rk] -> out [RB][rb2][rk2]; side 1: right,
+    Env [RB][rb2][rk2] -> out [RA][rb][rk]."""
     import torch
 
-    A, B, o = _sparse(W)
+    if side not in (0, 1):
+        raise ValueError("side must be 0 (left) or 1 (right)")
+    A, B, o = _sparse(W, RA, RB, "W")
+    if Ubra.ndim != 3 or Uket.ndim != 3:
+        raise ValueError("Ubra, Uket: cores [r][4][r'] expected")
     rb, rk = Ubra.shape[0], Uket.shape[0]
     rb2, rk2 = Ubra.shape[2], Uket.shape[2]
+    for nm, v in (("rb", rb), ("rk", rk), ("rb2", rb2), ("rk2", rk2)):
+        _need_pad(nm, v)
+    ein, eout = ((RA, rb, rk), (RB, rb2, rk2)) if side == 0 else ((RB, rb2, rk2), (RA, rb, rk))
+    ops = [(Ubra, "Ubra", "float64", (rb, 4, rb2), None), (Uket, "Uket", "float64", (rk, 4, rk2), None),
+           (Env, "Env", "float64", ein, None)]
+    _need(*ops)
     if out is None:
-        shape = (RB, rb2, rk2) if side == 0 else (RA, rb, rk)
-        out = torch.empty(shape, dtype=torch.float64, device=Env.device)
+        out = torch.empty(eout, dtype=torch.float64, device=Env.device)
+    _need(*ops, (out, "out", "float64", eout, None))
     torch.cuda.synchronize()
     I32 = C.POINTER(C.c_int32)
-    rc = ctx.lib.tt_env_update_dev(ctx.h, side, rb, rk, rb2, rk2, RA, RB, C.c_void_p(Env.data_ptr()),
-                                   C.c_void_p(Ubra.data_ptr()), C.c_void_p(Uket.data_ptr()), len(A),
-                                   A.ctypes.data_as(I32), B.ctypes.data_as(I32),
-                                   o.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(out.data_ptr()))
+    pE, pb, pk, po = _pointers(Env, Ubra, Uket, out)
+    rc = ctx.lib.tt_env_update_dev(ctx.h, side, rb, rk, rb2, rk2, RA, RB, pE, pb, pk, len(A), A.ctypes.data_as(I32),
+                                   B.ctypes.data_as(I32), o.ctypes.data_as(C.POINTER(C.c_double)), po)
     ctx._check(rc)
     return out
 
 
 def heff_energy_grad(ctx, Lenv, W1, W2, Renv, x, RB):
-    """E = <x|H_eff|x> and its gradients (FP64 device tensors; entry gradients on the host)."""
+    """E = <x|H_eff|x> and its gradients (tt_heff_energy_grad_dev): FP64 device
+    tensors Lenv [RA][rl][rl], Renv [RC][rr][rr], x [rl][4][4][rr] (rl, rr
+    multiples of 32); returns E, gx, gL, gR on the device and the per-entry
+    operator gradients of W1 and W2 on the host."""
     import torch
 
-    RA, rl, _ = Lenv.shape
-    RC, rr, _ = Renv.shape
-    A1, B1, o1 = _sparse(W1)
-    A2, B2, o2 = _sparse(W2)
+    RA, rl, RC, rr = Lenv.shape[0], Lenv.shape[1], Renv.shape[0], Renv.shape[1]
+    _need_pad("rl", rl)
+    _need_pad("rr", rr)
+    A1, B1, o1 = _sparse(W1, RA, RB, "W1")
+    A2, B2, o2 = _sparse(W2, RB, RC, "W2")
+    _need((Lenv, "Lenv", "float64", (RA, rl, rl), None), (Renv, "Renv", "float64", (RC, rr, rr), None),
+          (x, "x", "float64", (rl, 4, 4, rr), None))
     gx = torch.empty_like(x)
     gL = torch.empty_like(Lenv)
     gR = torch.empty_like(Renv)
@@ -330,37 +443,101 @@ def heff_energy_grad(ctx, Lenv, W1, W2, Renv, x, RB):
     torch.cuda.synchronize()
     I32 = C.POINTER(C.c_int32)
     DP = C.POINTER(C.c_double)
-    rc = ctx.lib.tt_heff_energy_grad_dev(ctx.h, rl, rr, RA, RB, RC, C.c_void_p(Lenv.data_ptr()),
-                                         C.c_void_p(Renv.data_ptr()), len(A1), A1.ctypes.data_as(I32),
+    pL, pR, px, pgx, pgL, pgR = _pointers(Lenv, Renv, x, gx, gL, gR)
+    rc = ctx.lib.tt_heff_energy_grad_dev(ctx.h, rl, rr, RA, RB, RC, pL, pR, len(A1), A1.ctypes.data_as(I32),
                                          B1.ctypes.data_as(I32), o1.ctypes.data_as(DP), len(A2),
-                                         A2.ctypes.data_as(I32), B2.ctypes.data_as(I32), o2.ctypes.data_as(DP),
-                                         C.c_void_p(x.data_ptr()), C.byref(E), C.c_void_p(gx.data_ptr()),
-                                         C.c_void_p(gL.data_ptr()), C.c_void_p(gR.data_ptr()),
-                                         g1.ctypes.data_as(DP), g2.ctypes.data_as(DP))
+                                         A2.ctypes.data_as(I32), B2.ctypes.data_as(I32), o2.ctypes.data_as(DP), px,
+                                         C.byref(E), pgx, pgL, pgR, g1.ctypes.data_as(DP), g2.ctypes.data_as(DP))
     ctx._check(rc)
     return E.value, gx, gL, gR, g1.reshape(-1, 4, 4), g2.reshape(-1, 4, 4)
 
 
 def make_heff_energy(ctx, W1idx, W2idx, RB):
-    """torch.autograd.Function for E = <x|H_eff|x> with the hand-written backward.
+    """torch.autograd.Function for E = <x|H_eff|x> whose backward is the
+    library's hand-written one (tt_heff_energy_grad_dev).
 
-    ``W1idx``/``W2idx`` are (A, B) index arrays of the sparse cores; the local
-    operators are differentiable inputs of shape [nnz, 4, 4]."""
+    ``W1idx``/``W2idx`` are the (A, B) index arrays of the two sparse cores; the
+    local operators are differentiable inputs ``ops1``/``ops2`` of shape
+    [nnz, 4, 4] (host or device).  ``apply(x, Lenv, Renv, ops1, ops2)`` returns
+    E as a 0-d float64 tensor on x's device; every gradient comes back on its
+    input's device in its input's dtype."""
     import torch
 
     class HeffEnergy(torch.autograd.Function):
         @staticmethod
         def forward(fctx, x, Lenv, Renv, ops1, ops2):
-            E, gx, gL, gR, g1, g2 = heff_energy_grad(ctx, Lenv.detach(), (W1idx[0], W1idx[1], ops1.detach().cpu().numpy()),
-                                                     (W2idx[0], W2idx[1], ops2.detach().cpu().numpy()), Renv.detach(),
-                                                     x.detach(), RB)
-            fctx.save_for_backward(gx, gL, gR, torch.from_numpy(g1), torch.from_numpy(g2))
-            return torch.tensor(E, dtype=torch.float64)
+            E, gx, gL, gR, g1, g2 = heff_energy_grad(
+                ctx, Lenv.detach(), (W1idx[0], W1idx[1], ops1.detach().cpu().numpy()),
+                (W2idx[0], W2idx[1], ops2.detach().cpu().numpy()), Renv.detach(), x.detach(), RB)
+            g1 = torch.from_numpy(g1).to(device=ops1.device, dtype=ops1.dtype)
+            g2 = torch.from_numpy(g2).to(device=ops2.device, dtype=ops2.dtype)
+            fctx.save_for_backward(gx, gL, gR, g1, g2)
+            return torch.tensor(E, dtype=torch.float64, device=x.device)
 
         @staticmethod
         def backward(fctx, gE):
             gx, gL, gR, g1, g2 = fctx.saved_tensors
-            s = gE.item()
-            return s * gx, s * gL, s * gR, s * g1, s * g2
+            return gE * gx, gE * gL, gE * gR, gE.to(g1.device) * g1, gE.to(g2.device) * g2
 
     return HeffEnergy
+
+
+def make_mpo_energy(ctx, mpo):
+    """torch.autograd.Function for E(ops) = <U|H(ops)|U> of the context's current
+    (normalised) iterate, where ``ops`` [sum_k nnz_k, 4, 4] are the local operators
+    of every MPO entry (sites in order, the entry structure of ``mpo``).  Forward:
+    the environment chain (tt_energy, after tt_set_mpo with these operators when
+    they differ from the context's).  Backward: the library's hand-written
+    backward through the environment chains (tt_energy_mpo_grad, environments
+    recomputed).  Composed with ``mpo_linear_map`` it gives dE/dh by autograd."""
+    import torch
+
+    nnz = [len(a) for a in mpo.A]
+    offs = np.concatenate([[0], np.cumsum(nnz)])
+    state = {"ops": np.concatenate([o.reshape(-1, 4, 4) for o in mpo.ops], axis=0)}
+
+    def _set(ops_np):
+        if ops_np.shape != state["ops"].shape:
+            raise ValueError(f"ops: shape {ops_np.shape}, expected {state['ops'].shape}")
+        if not np.array_equal(ops_np, state["ops"]):
+            m2 = copy.copy(mpo)
+            m2.ops = [ops_np[offs[k]:offs[k + 1]] for k in range(mpo.L)]
+            ctx.set_mpo(m2)
+            state["ops"] = ops_np.copy()
+
+    class MpoEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, ops):
+            _set(np.ascontiguousarray(ops.detach().cpu().numpy(), dtype=np.float64))
+            fctx.dev, fctx.dt = ops.device, ops.dtype
+            return torch.tensor(ctx.energy(), dtype=torch.float64, device=ops.device)
+
+        @staticmethod
+        def backward(fctx, gE):
+            _, gops = ctx.mpo_gradient(mpo)
+            g = torch.from_numpy(np.concatenate(gops, axis=0)).to(device=fctx.dev, dtype=fctx.dt)
+            return gE.to(g.device) * g
+
+    return MpoEnergy
+
+
+def mpo_linear_map(mpo, h0):
+    """The local operators of every MPO entry as a differentiable function of
+    the one-body integrals: ops(h) = ops(h0) + sum_pq (h - h0)_pq D_pq, exact
+    because every entry is linear in h (D from the builder's derivative map)."""
+    import torch
+
+    L = mpo.L
+    nnz = [len(a) for a in mpo.A]
+    offs = np.concatenate([[0], np.cumsum(nnz)])
+    base = torch.from_numpy(np.concatenate([o.reshape(-1, 4, 4) for o in mpo.ops], axis=0))
+    rows = torch.tensor([offs[k] + e for k, e, _, _, _ in mpo.dh], dtype=torch.long)
+    pq = torch.tensor([p * L + q for _, _, p, q, _ in mpo.dh], dtype=torch.long)
+    D = torch.from_numpy(np.stack([np.asarray(d).reshape(4, 4) for *_, d in mpo.dh]))
+    h0 = torch.as_tensor(np.asarray(h0, dtype=np.float64))
+
+    def ops_of(h):
+        dh = (h - h0).reshape(-1)[pq]
+        return base.index_add(0, rows, dh[:, None, None] * D)
+
+    return ops_of

@@ -19,7 +19,7 @@ namespace tt {
 #define BECHECK(x)                                                                   \
   do {                                                                               \
     hipError_t e_ = (x);                                                             \
-    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_)); \
+    if (e_ != hipSuccess) throw tt::HipError(std::string("HIP: ") + hipGetErrorString(e_)); \
   } while (0)
 
 namespace {

@@ -13,17 +13,17 @@ using tt::Engine;
 
 namespace {
 
-int classify(const std::exception& e) {
-  std::string m = e.what();
-  if (m.find("allocation") != std::string::npos) return TT_ENOMEM;
-  if (m.find("HIP") != std::string::npos || m.find("rocSOLVER") != std::string::npos) return TT_EHIP;
-  return TT_EINTERNAL;
-}
+// the context's allocator and stream for the blocks this thread allocates during one call
+struct CallAllocator {
+  explicit CallAllocator(Engine& E) { tt::set_thread_allocator(&E.ext, E.stream); }
+  ~CallAllocator() { tt::set_thread_allocator(nullptr, nullptr); }
+};
 
 template <class F>
 int guard(void* ctx, F&& f) {
   Engine* E = static_cast<Engine*>(ctx);
   if (!E) return TT_EINVAL;
+  CallAllocator scope(*E);
   try {
     E->err.clear();
     return f(*E);
@@ -36,9 +36,18 @@ int guard(void* ctx, F&& f) {
   } catch (const std::bad_alloc&) {
     E->err = "host allocation failed";
     return TT_ENOMEM;
+  } catch (const tt::DeviceOOM& e) {
+    E->err = e.what();
+    return TT_ENOMEM;
+  } catch (const tt::HipError& e) {
+    E->err = e.what();
+    return TT_EHIP;
+  } catch (const tt::SolverError& e) {
+    E->err = e.what();
+    return TT_EHIP;
   } catch (const std::exception& e) {
     E->err = e.what();
-    return classify(e);
+    return TT_EINTERNAL;
   } catch (...) {
     E->err = "unknown error";
     return TT_EINTERNAL;
@@ -75,6 +84,10 @@ void tt_default_opts(tt_opts* o) {
   o->mix_stage = 0;
   o->svd_lds = 1;
   o->worker_alloc_limit = 0;
+  o->stream = nullptr;
+  o->dev_alloc = nullptr;
+  o->dev_free = nullptr;
+  o->alloc_user = nullptr;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -83,7 +96,7 @@ int tt_create(const tt_opts* opts, void** out) {
   if (opts->chi_max <= 0 || opts->dav_maxiter <= 0 || opts->dav_maxsub < 4 || opts->matvec_prec < 0 ||
       opts->matvec_prec > 2 || opts->sub_workers < 0 || opts->sub_workers > TT_MAX_SUB ||
       opts->mix_stage < 0 || opts->mix_stage > 2 || opts->svd_lds < 0 || opts->svd_lds > 1 ||
-      opts->worker_alloc_limit < 0)
+      opts->worker_alloc_limit < 0 || (!opts->dev_alloc) != (!opts->dev_free))
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);
@@ -239,7 +252,7 @@ int tt_heff_apply_dev(void* ctx, int prec, int rl, int rr, int RA, int RB, int R
                   (float*)y, nullptr, 0, 0);
     else
       throw std::invalid_argument("unknown precision");
-    if (hipStreamSynchronize(E.stream) != hipSuccess) throw std::runtime_error("HIP: stream synchronisation failed");
+    if (hipStreamSynchronize(E.stream) != hipSuccess) throw tt::HipError("HIP: stream synchronisation failed");
     return TT_OK;
   });
 }
@@ -265,7 +278,7 @@ int tt_gemm_dev(void* ctx, int prec, int M, int N, int K, int batch, int kin, co
       tt::gemm_bf16(g, (const uint16_t*)A, (const uint16_t*)B, (float*)Cm, a_kcontig, b_ncontig, E.stream);
     else
       throw std::invalid_argument("unknown precision");
-    if (hipStreamSynchronize(E.stream) != hipSuccess) throw std::runtime_error("HIP: stream synchronisation failed");
+    if (hipStreamSynchronize(E.stream) != hipSuccess) throw tt::HipError("HIP: stream synchronisation failed");
     return TT_OK;
   });
 }
@@ -290,7 +303,7 @@ int tt_env_update_dev(void* ctx, int side, int rb, int rk, int rb2, int rk2, int
     } else {
       throw std::invalid_argument("side must be 0 or 1");
     }
-    if (hipStreamSynchronize(E.stream) != hipSuccess) throw std::runtime_error("HIP: stream synchronisation failed");
+    if (hipStreamSynchronize(E.stream) != hipSuccess) throw tt::HipError("HIP: stream synchronisation failed");
     return TT_OK;
   });
 }

@@ -27,13 +27,13 @@ namespace tt {
 #define HC(x)                                                                                       \
   do {                                                                                              \
     hipError_t e_ = (x);                                                                            \
-    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x); \
+    if (e_ != hipSuccess) throw HipError(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x); \
   } while (0)
 #define RC(x)                                                                                      \
   do {                                                                                             \
     rocblas_status s_ = (x);                                                                       \
     if (s_ != rocblas_status_success)                                                              \
-      throw std::runtime_error(std::string("rocSOLVER/rocBLAS status ") + std::to_string((int)s_) + " at " #x); \
+      throw SolverError(std::string("rocSOLVER/rocBLAS status ") + std::to_string((int)s_) + " at " #x); \
   } while (0)
 
 static const Q2 SITE_Q[4] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};
@@ -299,15 +299,32 @@ Arena& arena() {
 }
 }  // namespace
 
+static thread_local const ExtAlloc* tl_ext = nullptr;
+static thread_local hipStream_t tl_ext_stream = nullptr;
+void set_thread_allocator(const ExtAlloc* a, hipStream_t s) {
+  tl_ext = (a && a->alloc) ? a : nullptr;
+  tl_ext_stream = s;
+}
+
 void DevMem::release() {
   if (p && own) {
-    if (cap >= Arena::kMin && arena().owns(p)) arena().put(p);
-    else pool().put(p, cap);
+    if (ext) {
+      // work queued on the releasing thread's stream may still read the block
+      if (tl_stream) (void)hipStreamSynchronize(tl_stream);
+      else (void)hipDeviceSynchronize();
+      ext->free(p, (void*)ext_stream, ext->user);
+    } else if (cap >= Arena::kMin && arena().owns(p)) {
+      arena().put(p);
+    } else {
+      pool().put(p, cap);
+    }
   }
   p = nullptr;
   n = 0;
   cap = 0;
   own = true;
+  ext = nullptr;
+  ext_stream = nullptr;
 }
 // allocation budget of the task running on this thread (worker_alloc_limit; -1: none)
 static thread_local long long tl_alloc_budget = -1;
@@ -318,6 +335,25 @@ static void charge_budget(size_t bytes) {
   tl_alloc_budget -= (long long)bytes;
 }
 
+// a new block of at least `bytes` for m (released first): the caller's allocator of
+// this thread's call when there is one, else the arena (large) or the block pool
+static void acquire(DevMem& m, size_t bytes) {
+  charge_budget(bytes);
+  if (tl_ext) {
+    m.p = tl_ext->alloc(bytes, (void*)tl_ext_stream, tl_ext->user);
+    m.cap = m.p ? bytes : 0;
+    m.ext = m.p ? tl_ext : nullptr;
+    m.ext_stream = m.p ? tl_ext_stream : nullptr;
+  } else {
+    m.p = bytes >= Arena::kMin ? arena().get(bytes, m.cap) : nullptr;
+    if (!m.p) m.p = pool().get(bytes, m.cap);
+  }
+  if (!m.p) {
+    m.cap = 0;
+    throw DeviceOOM("device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+}
+
 void DevMem::ensure(size_t bytes) {
   if (own && p && bytes <= cap) {
     if (bytes > n) n = bytes;
@@ -326,27 +362,13 @@ void DevMem::ensure(size_t bytes) {
   if (bytes <= n) return;
   release();
   if (bytes == 0) return;
-  charge_budget(bytes);
-  p = bytes >= Arena::kMin ? arena().get(bytes, cap) : nullptr;
-  if (!p) p = pool().get(bytes, cap);
-  if (!p) {
-    cap = 0;
-    throw DeviceOOM("device allocation of " + std::to_string(bytes) + " bytes failed");
-  }
+  acquire(*this, bytes);
   n = bytes;
 }
 void DevMem::resize_zero(size_t bytes, hipStream_t s) {
   if (!(own && p && bytes <= cap)) {
     release();
-    if (bytes) {
-      charge_budget(bytes);
-      p = bytes >= Arena::kMin ? arena().get(bytes, cap) : nullptr;
-      if (!p) p = pool().get(bytes, cap);
-      if (!p) {
-        cap = 0;
-        throw DeviceOOM("device allocation of " + std::to_string(bytes) + " bytes failed");
-      }
-    }
+    if (bytes) acquire(*this, bytes);
   }
   n = bytes;
   if (bytes) fill(p, bytes, s);
@@ -437,7 +459,15 @@ Engine::Engine(const tt_opts& o)
   verbose_level = v ? std::atoi(v) : 0;
   verbose = verbose_level > 0;
   HC(hipSetDevice(o.device));
-  HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  ext.alloc = o.dev_alloc;
+  ext.free = o.dev_free;
+  ext.user = o.alloc_user;
+  if (o.stream) {
+    stream = (hipStream_t)o.stream;
+    own_stream = false;
+  } else {
+    HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  }
   RC(rocblas_create_handle(&blas));
   RC(rocblas_set_stream(blas, stream));
   HC(hipEventCreate(&ev0));
@@ -449,6 +479,7 @@ Engine::Engine(const Engine& parent, int)
   verbose = parent.verbose;
   verbose_level = parent.verbose_level;
   have_mpo = parent.have_mpo;
+  ext = parent.ext;
   HC(hipSetDevice(opts.device));
   HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   RC(rocblas_create_handle(&blas));
@@ -464,7 +495,7 @@ Engine::~Engine() {
   if (ev1) (void)hipEventDestroy(ev1);
   for (hipEvent_t& ev : kt_ev)
     if (ev) (void)hipEventDestroy(ev);
-  if (stream) (void)hipStreamDestroy(stream);
+  if (stream && own_stream) (void)hipStreamDestroy(stream);
 }
 
 void Engine::release_workspaces() {
@@ -2337,8 +2368,11 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<double> c(d.begin(), d.begin() + m);
       for (double& v : c) v = -v;
-      lcomb(V, m, c, u);  // u is free now
-      axpy(vm, 1.0, u, n, E.stream);
+      // the residual t has been consumed by the preconditioner, so it holds the
+      // projection; u stays the Ritz vector that theta and resid describe, which is
+      // what every exit below returns
+      lcomb(V, m, c, t);
+      axpy(vm, 1.0, t, n, E.stream);
       dots(V, m + 1, vm, d);
       const double prev = tn;
       tn = std::sqrt(std::max(d[m], 0.0));
@@ -2533,6 +2567,9 @@ void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::fu
       try {
         HC(hipSetDevice(opts.device));
         tl_stream = W->stream;
+        // blocks of a worker may outlive it (they move into the context's results), so
+        // they record the context's allocator, which lives as long as they do
+        set_thread_allocator(&ext, W->stream);
         for (;;) {
           const int i = next.fetch_add(1);
           if (i >= ntask) break;
@@ -2560,6 +2597,7 @@ void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::fu
         (void)hipStreamSynchronize(W->stream);
       }
       tl_stream = nullptr;
+      set_thread_allocator(nullptr, nullptr);
     });
   }
   for (auto& t : th) t.join();

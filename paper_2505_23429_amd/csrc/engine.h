@@ -31,22 +31,34 @@ struct DeviceOOM : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
 
+// Device allocator supplied by the caller (tt_opts.dev_alloc/dev_free/alloc_user).
+struct ExtAlloc {
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*free)(void*, void*, void*) = nullptr;
+  void* user = nullptr;
+};
+// Allocator (nullptr: the library's pools) and stream that new blocks of the call
+// running on this thread come from / will be used on.
+void set_thread_allocator(const ExtAlloc* a, hipStream_t s);
+
 struct DevMem {
   void* p = nullptr;
   size_t n = 0;      // bytes in use
   size_t cap = 0;    // bytes allocated (pooled block)
   bool own = true;   // false: a caller's buffer, never freed here
+  const ExtAlloc* ext = nullptr;  // the caller's allocator this block came from, if any
+  hipStream_t ext_stream = nullptr;
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n), cap(o.cap), own(o.own) {
-    o.p = nullptr; o.n = 0; o.cap = 0; o.own = true;
+  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n), cap(o.cap), own(o.own), ext(o.ext), ext_stream(o.ext_stream) {
+    o.p = nullptr; o.n = 0; o.cap = 0; o.own = true; o.ext = nullptr; o.ext_stream = nullptr;
   }
   DevMem& operator=(DevMem&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; n = o.n; cap = o.cap; own = o.own;
-      o.p = nullptr; o.n = 0; o.cap = 0; o.own = true;
+      p = o.p; n = o.n; cap = o.cap; own = o.own; ext = o.ext; ext_stream = o.ext_stream;
+      o.p = nullptr; o.n = 0; o.cap = 0; o.own = true; o.ext = nullptr; o.ext_stream = nullptr;
     }
     return *this;
   }
@@ -145,6 +157,8 @@ class Engine {
   ~Engine();
   tt_opts opts;
   hipStream_t stream = nullptr;
+  bool own_stream = true;     // false: the caller's stream (tt_opts.stream)
+  ExtAlloc ext;               // the caller's allocator (alloc == nullptr: the library's pools)
   rocblas_handle blas = nullptr;
   std::string err;
 

@@ -5,9 +5,19 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <stdexcept>
 #include <vector>
 
 namespace tt {
+
+// Failures that the C ABI reports as TT_EHIP: a HIP runtime call, and a
+// rocSOLVER/rocBLAS call that returned a bad status.
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct SolverError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
 
 enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
 

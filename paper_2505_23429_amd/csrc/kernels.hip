@@ -11,7 +11,7 @@ namespace tt {
 #define HIPCHECK(x)                                                                  \
   do {                                                                               \
     hipError_t e_ = (x);                                                             \
-    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_)); \
+    if (e_ != hipSuccess) throw tt::HipError(std::string("HIP: ") + hipGetErrorString(e_)); \
   } while (0)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
