@@ -133,6 +133,7 @@ typedef struct tt_sweep_report {
                                       coarse matrices, coarse solve + compression, all subdomain
                                       solves; with concurrent solves entries 2-5 are summed over
                                       the workers */
+  int matvecs_f64[TT_MAX_SUB];     /* of matvecs[]: the products taken in FP64 */
 } tt_sweep_report;
 
 void tt_default_opts(tt_opts* o);

@@ -118,17 +118,20 @@ def overlap_left(E, bra, ket):
 
 
 def heff_apply(Lenv, W1: SiteOps, W2: SiteOps, Renv, x):
-    """y[a', s1', s2', b'] = sum L[a', A, a] W1[A, s1', s1, B] W2[B, s2', s2, C] R[b', C, b] x[a, s1, s2, b]."""
+    """y[a', s1', s2', b'] = sum L[a', A, a] W1[A, s1', s1, B] W2[B, s2', s2, C] R[b', C, b] x[a, s1, s2, b].
+    The bra dimensions a', b' are those of the environments (a subset of bra rows of L
+    gives exactly those rows of y)."""
     rl, rr = x.shape[0], x.shape[3]
+    pl, pr = Lenv.shape[0], Renv.shape[0]
     RA, RC = W1.RA, W2.RB
-    t = (Lenv.transpose(1, 0, 2).reshape(RA * rl, rl) @ x.reshape(rl, 16 * rr)).reshape(RA, rl, 4, 4, rr)
-    t = t.transpose(0, 2, 1, 3, 4).reshape(RA * 4, rl * 4 * rr)         # [A s1, a' s2 b]
+    t = (Lenv.transpose(1, 0, 2).reshape(RA * pl, rl) @ x.reshape(rl, 16 * rr)).reshape(RA, pl, 4, 4, rr)
+    t = t.transpose(0, 2, 1, 3, 4).reshape(RA * 4, pl * 4 * rr)         # [A s1, a' s2 b]
     t = spmm(W1.fw, t)                                                  # [B s1', a' s2 b]
-    t = t.reshape(W1.RB, 4, rl, 4, rr).transpose(0, 3, 2, 1, 4).reshape(W1.RB * 4, rl * 4 * rr)
+    t = t.reshape(W1.RB, 4, pl, 4, rr).transpose(0, 3, 2, 1, 4).reshape(W1.RB * 4, pl * 4 * rr)
     t = spmm(W2.fw, t)                                                  # [C s2', a' s1' b]
-    t = t.reshape(RC, 4, rl, 4, rr).transpose(2, 3, 1, 0, 4).reshape(rl * 16, RC * rr)
-    y = t @ Renv.reshape(rr, RC * rr).T
-    return y.reshape(rl, 4, 4, rr)
+    t = t.reshape(RC, 4, pl, 4, rr).transpose(2, 3, 1, 0, 4).reshape(pl * 16, RC * rr)
+    y = t @ Renv.reshape(pr, RC * rr).T
+    return y.reshape(pl, 4, 4, pr)
 
 
 def chain_energy(mpo, ops, cores):

@@ -51,6 +51,7 @@ class SweepReport(C.Structure):
         ("coef", C.c_double * (TT_MAX_SUB + 1)), ("lambda_", C.c_double), ("rankS", C.c_int),
         ("E_after", C.c_double), ("discarded", C.c_double), ("seconds", C.c_double * 4),
         ("flops_heff", C.c_double), ("seconds_heff", C.c_double), ("phase_seconds", C.c_double * 9),
+        ("matvecs_f64", C.c_int * TT_MAX_SUB),
     ]
 
 

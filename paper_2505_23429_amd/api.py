@@ -172,7 +172,8 @@ class Context:
         A = np.array(rep.A[: m * m]).reshape(m, m)
         return {
             "status": rc, "E_before": rep.E_before, "E_local": np.array(rep.E_local[:n]),
-            "matvecs": np.array(rep.matvecs[:n]), "S": S, "A": A, "c": np.array(rep.coef[:m]),
+            "matvecs": np.array(rep.matvecs[:n]), "matvecs_f64": np.array(rep.matvecs_f64[:n]),
+            "S": S, "A": A, "c": np.array(rep.coef[:m]),
             "lambda": rep.lambda_, "rankS": rep.rankS, "E_after": rep.E_after, "discarded": rep.discarded,
             "seconds": list(rep.seconds), "flops_heff": rep.flops_heff, "seconds_heff": rep.seconds_heff,
             "phase_seconds": list(rep.phase_seconds),

@@ -64,6 +64,7 @@ std::vector<int> vec(const int32_t* p, int n) { return std::vector<int>(p, p + n
 
 }  // namespace
 
+
 extern "C" {
 
 void tt_default_opts(tt_opts* o) {
@@ -184,6 +185,7 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
     out->E_before = E.energy();
     auto t1 = std::chrono::steady_clock::now();
     E.local_solve(nsub, lengths, out->E_local, out->matvecs);
+    for (int j = 0; j < nsub; ++j) out->matvecs_f64[j] = E.subs[j].matvecs64;
     auto t2 = std::chrono::steady_clock::now();
     const int n = nsub + 1;
     std::vector<double> S((size_t)n * n), A((size_t)n * n);
@@ -256,6 +258,7 @@ int tt_heff_apply_dev(void* ctx, int prec, int rl, int rr, int RA, int RB, int R
     return TT_OK;
   });
 }
+
 
 int tt_gemm_dev(void* ctx, int prec, int M, int N, int K, int batch, int kin, const long long* st, int a_kcontig,
                 int b_ncontig, double alpha, double beta, const void* A, const void* B, void* Cm) {

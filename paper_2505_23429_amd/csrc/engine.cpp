@@ -519,15 +519,17 @@ void Engine::free_caches() {
   have_local = false;
 }
 
-void Engine::build_siteop(SiteOp& so, int nout, const std::vector<int>& out_idx, const std::vector<int>& in_idx,
-                          const std::vector<double>& ops, hipStream_t s) {
+void siteop_csr(int nout, const std::vector<int>& out_idx, const std::vector<int>& in_idx,
+                const std::vector<double>& ops, std::vector<int>& ptr, std::vector<int>& src,
+                std::vector<double>& op64, std::vector<float>& op32) {
   const int nnz = (int)out_idx.size();
   std::vector<int> order(nnz);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return out_idx[a] < out_idx[b]; });
-  std::vector<int> ptr(nout + 1, 0), src(std::max(nnz, 1), 0);
-  std::vector<double> op64((size_t)std::max(nnz, 1) * 16, 0.0);
-  std::vector<float> op32((size_t)std::max(nnz, 1) * 16, 0.f);
+  ptr.assign(nout + 1, 0);
+  src.assign(std::max(nnz, 1), 0);
+  op64.assign((size_t)std::max(nnz, 1) * 16, 0.0);
+  op32.assign((size_t)std::max(nnz, 1) * 16, 0.f);
   for (int e = 0; e < nnz; ++e) {
     if (out_idx[e] < 0 || out_idx[e] >= nout) throw std::runtime_error("MPO entry channel out of range");
     ptr[out_idx[e] + 1]++;
@@ -541,6 +543,15 @@ void Engine::build_siteop(SiteOp& so, int nout, const std::vector<int>& out_idx,
       op32[(size_t)k * 16 + j] = (float)ops[(size_t)e * 16 + j];
     }
   }
+}
+
+void Engine::build_siteop(SiteOp& so, int nout, const std::vector<int>& out_idx, const std::vector<int>& in_idx,
+                          const std::vector<double>& ops, hipStream_t s) {
+  const int nnz = (int)out_idx.size();
+  std::vector<int> ptr, src;
+  std::vector<double> op64;
+  std::vector<float> op32;
+  siteop_csr(nout, out_idx, in_idx, ops, ptr, src, op64, op32);
   so.nout = nout;
   so.nnz = nnz;
   so.hptr = ptr;
@@ -772,14 +783,19 @@ const double* siteop_ops<double>(const SiteOp& so) { return so.op64.as<double>()
 template <>
 const float* siteop_ops<float>(const SiteOp& so) { return so.op32.as<float>(); }
 
+// The dense two-site product on raw tables and workspaces:
+//   T1 = L_A x (batched GEMM over the channels A), T2 = W1 mix of T1, T3 = W2 mix of T2
+//   (in T1's space), y = sum_C T3_C R_C^T (+ the second-site coefficient block's channels).
+// Site k's entries are given grouped by output channel (ptr[nout + 1], src[nnz], ops[nnz][16]).
+// ws_a holds max(RA, RC) slabs of rl*16*rr elements, ws_b holds RB slabs.  With timed, the
+// kernels are timed into the engine's per-kernel statistics.
 template <class T>
-void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
-                  const T* Rv, const T* x, T* y, const T* Rtil, int P0, int nP, const WinTabs* tabs) {
+void heff_dense(Engine& E, int rl, int rr, int RA, const T* Lv, int RB, const int* p1, const int* s1, const T* o1,
+                int RC, const int* p2, const int* s2, const T* o2, const T* Rv, const T* x, T* y, T* ws_a, T* ws_b,
+                const T* Rtil, int P0, int nP, const WinTabs* tabs, bool timed) {
   const long long slab = (long long)rl * 16 * rr;
-  ws0.ensure(sizeof(T) * slab * std::max(RA, RC));
-  ws1.ensure(sizeof(T) * slab * RB);
-  T* T1 = ws0.as<T>();
-  T* T2 = ws1.as<T>();
+  T* T1 = ws_a;
+  T* T2 = ws_b;
   GemmArgs g{};
   g.M = rl; g.N = 16 * rr; g.K = rl; g.batch = RA; g.kin = rl;
   g.sAb = (long long)rl * rl; g.sAm = rl; g.sAkb = 0; g.sAkk = 1;
@@ -792,16 +808,14 @@ void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB,
     q1.qo = tabs->qo1.as<int2>(); q1.qi = tabs->qi1.as<int2>(); q1.qc = tabs->qcB;
     q2.qo = tabs->qo2.as<int2>(); q2.qi = tabs->qi2.as<int2>(); q2.qc = tabs->qcC;
   }
-  kt_begin();
-  gemm<T>(g, Lv, x, T1, true, true, stream);
-  kt_mark(0);
-  mix<T>(w1.nout, w1.ptr.as<int>(), w1.src.as<int>(), siteop_ops<T>(w1), T1, slab, T2, slab, rl, 4 * rr, stream,
-         tabs ? &q1 : nullptr);
-  kt_mark(1);
-  T* T3 = ws0.as<T>();
-  mix<T>(w2.nout, w2.ptr.as<int>(), w2.src.as<int>(), siteop_ops<T>(w2), T2, slab, T3, slab, 4 * rl, rr, stream,
-         tabs ? &q2 : nullptr);
-  kt_mark(4);
+  if (timed) E.kt_begin();
+  gemm<T>(g, Lv, x, T1, true, true, E.stream);
+  if (timed) E.kt_mark(0);
+  mix<T>(RB, p1, s1, o1, T1, slab, T2, slab, rl, 4 * rr, E.stream, tabs ? &q1 : nullptr);
+  if (timed) E.kt_mark(1);
+  T* T3 = ws_a;
+  mix<T>(RC, p2, s2, o2, T2, slab, T3, slab, 4 * rl, rr, E.stream, tabs ? &q2 : nullptr);
+  if (timed) E.kt_mark(4);
   GemmArgs h{};
   h.M = 16 * rl; h.N = rr; h.K = RC * rr; h.batch = 1; h.kin = rr;
   h.sAb = 0; h.sAm = rr; h.sAkb = slab; h.sAkk = 1;
@@ -810,19 +824,37 @@ void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB,
   if (tabs) {
     h.kmode = 2; h.nkb = RC; h.ntiles = tabs->n4tiles; h.ktab = tabs->k4tab.as<int>();
   }
-  gemm<T>(h, T3, Rv, y, true, false, stream);
+  gemm<T>(h, T3, Rv, y, true, false, E.stream);
   if (Rtil && nP > 0) {
     h.K = nP * rr;
     h.beta = 1.0;
     if (tabs) { h.nkb = nP; h.ktab = tabs->k4tabP.as<int>(); }
-    gemm<T>(h, T2 + (long long)P0 * slab, Rtil, y, true, false, stream);
+    gemm<T>(h, T2 + (long long)P0 * slab, Rtil, y, true, false, E.stream);
   }
-  kt_mark(7);
-  {
-    double fl[KT_SLOTS], by[KT_SLOTS];
-    dense_work(*this, sizeof(T), RB, fl, by);
-    kt_end(fl, by);
+  if (timed) {
+    E.kt_mark(7);
+    double fl[Engine::KT_SLOTS], by[Engine::KT_SLOTS];
+    dense_work(E, sizeof(T), RB, fl, by);
+    E.kt_end(fl, by);
   }
+}
+template void heff_dense<double>(Engine&, int, int, int, const double*, int, const int*, const int*, const double*,
+                                 int, const int*, const int*, const double*, const double*, const double*, double*,
+                                 double*, double*, const double*, int, int, const WinTabs*, bool);
+template void heff_dense<float>(Engine&, int, int, int, const float*, int, const int*, const int*, const float*, int,
+                                const int*, const int*, const float*, const float*, const float*, float*, float*,
+                                float*, const float*, int, int, const WinTabs*, bool);
+
+template <class T>
+void Engine::heff(int rl, int rr, int RA, const T* Lv, const SiteOp& w1, int RB, const SiteOp& w2, int RC,
+                  const T* Rv, const T* x, T* y, const T* Rtil, int P0, int nP, const WinTabs* tabs) {
+  const long long slab = (long long)rl * 16 * rr;
+  ws0.ensure(sizeof(T) * slab * std::max(RA, RC));
+  ws1.ensure(sizeof(T) * slab * RB);
+  if (w1.nout != RB || w2.nout != RC) throw std::runtime_error("heff: channel count mismatch");
+  heff_dense<T>(*this, rl, rr, RA, Lv, RB, w1.ptr.as<int>(), w1.src.as<int>(), siteop_ops<T>(w1), RC,
+                w2.ptr.as<int>(), w2.src.as<int>(), siteop_ops<T>(w2), Rv, x, y, ws0.as<T>(), ws1.as<T>(), Rtil, P0,
+                nP, tabs, true);
 }
 template void Engine::heff<double>(int, int, int, const double*, const SiteOp&, int, const SiteOp&, int, const double*,
                                    const double*, double*, const double*, int, int, const WinTabs*);
@@ -2252,8 +2284,18 @@ static DevMem build_mask(Engine& E, int rl, const Labels& ql, int rr, const Labe
 // Stops when the residual of the unit Ritz vector is <= max(tol, rel_tol * |theta|); with
 // stop_on_stall also when it has not dropped below 0.9 x its best value for 8 iterations
 // (a low-precision product has reached its rounding floor).
+//
+// anchor: the refinement of a low-precision solution (the precision split of the local
+// solve).  The first basis vector's product is an FP64 one and every later direction's is
+// in `prec`.  The Rayleigh-Ritz coupling of the first vector with the others then only
+// involves FP64 products, so the low-precision rounding enters the Ritz vector through
+// the correction directions alone, in proportion to their (small) weights.  A cycle ends
+// when the residual has fallen 1000 times below its value at the cycle's start, stalls,
+// or the basis is full; the next cycle starts from the Ritz vector alone with a fresh
+// FP64 product, whose exact residual is the only convergence test.  Each cycle thus gains
+// about three digits for one FP64 product.
 static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, int prec, double tol, int maxiter,
-                         double rel_tol = 0.0, bool stop_on_stall = false) {
+                         double rel_tol = 0.0, bool stop_on_stall = false, bool anchor = false) {
   Davidson res;
   const size_t n = (size_t)w.rlp * 16 * w.rrp;
   const int maxsub = std::max(4, std::min(E.opts.dav_maxsub, 64));
@@ -2281,6 +2323,12 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     HC(hipMemcpyAsync(cdev, c.data(), sizeof(double) * m, hipMemcpyHostToDevice, E.stream));
     lincomb(Vb, n, m, cdev, out, n, E.stream);
   };
+  auto product = [&](const double* v, double* av, int p) {
+    window_matvec(E, w, v, av, p);
+    mask_apply(av, mask.as<uint8_t>(), n, E.stream);
+    res.matvecs++;
+    if (p == TT_F64) res.matvecs64++;
+  };
   // start vector
   mask_apply(x, mask.as<uint8_t>(), n, E.stream);
   double nx = norm_dev(E, x, n);
@@ -2296,18 +2344,28 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
   }
   HC(hipMemcpyAsync(V, x, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
   scale(V, 1.0 / nx, n, E.stream);
-  window_matvec(E, w, V, AV, prec);
-  mask_apply(AV, mask.as<uint8_t>(), n, E.stream);
-  res.matvecs = 1;
+  product(V, AV, anchor ? TT_F64 : prec);
   int m = 1;
-  std::vector<double> Hs(1);
+  std::vector<double> Hs((size_t)maxsub * maxsub, 0.0);
   {
     std::vector<double> d;
     dots(V, 1, AV, d);
     Hs[0] = d[0];
   }
+  // anchored refinement: the next cycle starts from the unit Ritz vector u alone
+  auto anchor_restart = [&]() {
+    double nu = norm_dev(E, u, n);
+    HC(hipMemcpyAsync(V, u, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+    scale(V, 1.0 / nu, n, E.stream);
+    product(V, AV, TT_F64);
+    std::vector<double> d;
+    dots(V, 1, AV, d);
+    Hs.assign((size_t)maxsub * maxsub, 0.0);
+    Hs[0] = d[0];
+    m = 1;
+  };
   std::vector<double> evals, evecs, c;
-  double best = HUGE_VAL;
+  double best = HUGE_VAL, cycle0 = HUGE_VAL;
   int since_best = 0;
   for (int it = 0;; ++it) {
     // Rayleigh-Ritz
@@ -2323,16 +2381,41 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     axpby(t, 1.0, Au, -res.theta, u, n, E.stream);
     res.resid = norm_dev(E, t, n);
     res.iters = it + 1;
-    if (res.resid <= std::max(tol, rel_tol * std::fabs(res.theta))) {
-      res.converged = true;
-      break;
-    }
-    if (stop_on_stall) {
-      if (res.resid < 0.9 * best) {
-        best = res.resid;
+    if (anchor) {
+      if (m == 1) {
+        // u's product is an FP64 one: theta and the residual are exact
+        if (res.resid <= tol) {
+          res.converged = true;
+          break;
+        }
+        cycle0 = best = res.resid;
         since_best = 0;
-      } else if (++since_best >= 8) {
+      } else {
+        bool end_cycle = res.resid <= 1e-3 * cycle0 || res.resid <= 0.5 * tol || m >= maxsub;
+        if (res.resid < 0.9 * best) {
+          best = res.resid;
+          since_best = 0;
+        } else if (++since_best >= 6) {
+          end_cycle = true;
+        }
+        if (end_cycle) {
+          if (res.matvecs >= maxiter) break;
+          anchor_restart();
+          continue;
+        }
+      }
+    } else {
+      if (res.resid <= std::max(tol, rel_tol * std::fabs(res.theta))) {
+        res.converged = true;
         break;
+      }
+      if (stop_on_stall) {
+        if (res.resid < 0.9 * best) {
+          best = res.resid;
+          since_best = 0;
+        } else if (++since_best >= 8) {
+          break;
+        }
       }
     }
     if (res.matvecs >= maxiter) break;
@@ -2379,19 +2462,23 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
       if (tn >= prev / std::sqrt(2.0)) break;
     }
     if (!(tn > 1e-10 * tn0) || !(tn > 0.0)) {
-      res.converged = res.resid <= tol;
+      // the search space is exhausted
+      if (anchor && m > 1 && res.matvecs < maxiter) {
+        anchor_restart();  // confirm the Ritz vector with an exact residual
+        continue;
+      }
+      res.converged = !anchor && res.resid <= tol;
       break;
     }
     scale(vm, 1.0 / tn, n, E.stream);
     double* avm = AV + (size_t)m * n;
-    window_matvec(E, w, vm, avm, prec);
-    mask_apply(avm, mask.as<uint8_t>(), n, E.stream);
-    res.matvecs++;
+    product(vm, avm, prec);
     dots(V, m + 1, avm, d);
-    if ((int)Hs.size() < maxsub * maxsub) {
-      std::vector<double> H2((size_t)maxsub * maxsub, 0.0);
-      H2[0] = Hs[0];
-      Hs.swap(H2);
+    if (anchor) {
+      // the coupling with the first basis vector from that vector's FP64 product
+      std::vector<double> d0;
+      dots(AV, 1, vm, d0);
+      d[0] = d0[0];
     }
     for (int i = 0; i <= m; ++i) {
       Hs[(size_t)i * maxsub + m] = d[i];
@@ -2425,11 +2512,34 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
     else
       r = davidson(E, w, mask, x.as<double>(), prec, E.opts.dav_tol, E.opts.dav_maxiter);
     if (E.opts.refine_fp64) {
-      w.L32.release();
-      w.R32.release();
-      w.Rt32.release();
-      Davidson r2 = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter);
+      // refinement: FP64 residuals with FP32 correction directions.  A bfloat16 product
+      // is too coarse for the corrections (its rounding error exceeds the gap-scaled
+      // residual), so a block-sparse bfloat16 window is converted to FP32 operands (same
+      // storage), and a dense bfloat16 window continues with FP64 products.
+      int inner = prec;
+      if (prec == TT_BF16) {
+        if (w.use_bs) {
+          const long long sl = (long long)w.rlp * w.rlp, sr = (long long)w.rrp * w.rrp;
+          convert_f64_f32(w.Lx.as<double>(), w.L32.as<float>(), sl * w.RAx, E.stream);
+          convert_f64_f32(w.R64, w.R32.as<float>(), sr * w.RC, E.stream);
+          if (w.nP) convert_f64_f32(w.Rt.as<double>(), w.Rt32.as<float>(), sr * w.nP, E.stream);
+          inner = TT_F32;
+        } else {
+          inner = -1;
+        }
+      }
+      const int left = std::max(1, E.opts.dav_maxiter - r.matvecs);
+      Davidson r2;
+      if (inner >= 0) {
+        r2 = davidson(E, w, mask, x.as<double>(), inner, E.opts.dav_tol, left, 0.0, false, true);
+      } else {
+        w.L32.release();
+        w.R32.release();
+        w.Rt32.release();
+        r2 = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, left);
+      }
       r2.matvecs += r.matvecs;
+      r2.matvecs64 += r.matvecs64;
       r = r2;
     }
   } else {
@@ -2477,6 +2587,7 @@ void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
     two_site(*this, center, next, x);
     Davidson r = local_eig(*this, *Lcur, b, src.Renv[b + 2], x, center, next);
     S.matvecs += r.matvecs;
+    S.matvecs64 += r.matvecs64;
     S.E = r.theta;
     S.converged = S.converged && r.converged;
     Core N, C;

@@ -133,6 +133,7 @@ struct Env {
 
 struct Davidson {
   int iters = 0, matvecs = 0;
+  int matvecs64 = 0;  // of which FP64 products
   bool converged = false;
   double theta = 0.0, resid = 0.0;
 };
@@ -181,7 +182,7 @@ class Engine {
     int s = 0, t = 0;                  // modified sites [s, t]
     std::vector<Core> mod;             // cores s..t
     double E = 0.0;
-    int matvecs = 0;
+    int matvecs = 0, matvecs64 = 0;
     bool converged = true;
   };
   std::vector<Sub> subs;
@@ -300,6 +301,17 @@ class Engine {
  private:
   void free_caches();
 };
+
+// The entries of one sparse MPO core grouped by output channel (CSR on the host):
+// ptr[nout + 1], src[nnz] (input channel), op64/op32[nnz][16]; at least one slot each.
+void siteop_csr(int nout, const std::vector<int>& out_idx, const std::vector<int>& in_idx,
+                const std::vector<double>& ops, std::vector<int>& ptr, std::vector<int>& src,
+                std::vector<double>& op64, std::vector<float>& op32);
+// The dense two-site product on raw operands, tables and workspaces (engine.cpp).
+template <class T>
+void heff_dense(Engine& E, int rl, int rr, int RA, const T* Lv, int RB, const int* p1, const int* s1, const T* o1,
+                int RC, const int* p2, const int* s2, const T* o2, const T* Rv, const T* x, T* y, T* ws_a, T* ws_b,
+                const T* Rtil, int P0, int nP, const WinTabs* tabs, bool timed);
 
 void upload(DevMem& m, const void* h, size_t bytes, hipStream_t s);
 void download(void* h, const DevMem& m, size_t bytes, hipStream_t s);
