@@ -199,6 +199,24 @@ int tt_heff_apply_dev(void* ctx, int prec, int rl, int rr, int RA, int RB, int R
                       const void* Renv, int nnz1, const int32_t* A1, const int32_t* B1, const double* ops1, int nnz2,
                       const int32_t* A2, const int32_t* B2, const double* ops2, const void* x, void* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tt_heff_apply_dev (TT_F64 or TT_F32)
+ * without any device allocation.  Its intermediates (max(RA, RC) + RB slabs of
+ * rl*16*rr elements) and the two cores' entry tables are carved from one fixed device
+ * array of TT_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on holds
+ * until the process ends; its address is looked up once per device by tt_create.  A
+ * product that needs more scratch is refused with TT_EINVAL and a message naming the
+ * size.  Every call on one GPU shares that GPU's array and overwrites it, so calls that
+ * overlap in time on one GPU (two threads, or two contexts' streams) race: serialise
+ * them.  Operands, layouts and results as tt_heff_apply_dev; the host entry tables are
+ * copied with hipMemcpyAsync on the context's stream, and the call returns after the
+ * stream is synchronised. */
+#define TT_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int tt_heff_apply_dev_noalloc(void* ctx, int prec, int rl, int rr, int RA, int RB, int RC, const void* Lenv,
+                              const void* Renv, int nnz1, const int32_t* A1, const int32_t* B1, const double* ops1,
+                              int nnz2, const int32_t* A2, const int32_t* B2, const double* ops2, const void* x,
+                              void* y);
+
 /* Two-site product of the context's MPO at sites (b, b+1), y = H_eff x
  * (eq. mat_vec with the two-site contraction of Section 3), through the same
  * quantum-number block-sparse kernels the local solves use.  rl, rr: bond

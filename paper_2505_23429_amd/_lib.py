@@ -21,8 +21,9 @@ EXPORTS = (
     "tt_default_opts", "tt_create", "tt_destroy", "tt_last_error", "tt_set_mpo", "tt_set_mps", "tt_get_mps",
     "tt_energy", "tt_local_solve", "tt_coarse_correct", "tt_sweep", "tt_dmrg2", "tt_heff_apply_dev",
     "tt_env_update_dev", "tt_heff_energy_grad_dev", "tt_energy_mpo_grad", "tt_gemm_dev", "tt_kernel_timing",
-    "tt_window_apply_dev", "tt_mps_checkpoint",
+    "tt_window_apply_dev", "tt_mps_checkpoint", "tt_heff_apply_dev_noalloc",
 )
+TT_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class Opts(C.Structure):
@@ -95,6 +96,8 @@ def load():
     lib.tt_heff_apply_dev.argtypes = [VP, I, I, I, I, I, I, VP, VP, I, P(C.c_int32), P(C.c_int32), P(D), I,
                                       P(C.c_int32), P(C.c_int32), P(D), VP, VP]
     lib.tt_heff_apply_dev.restype = I
+    lib.tt_heff_apply_dev_noalloc.argtypes = lib.tt_heff_apply_dev.argtypes
+    lib.tt_heff_apply_dev_noalloc.restype = I
     lib.tt_mps_checkpoint.argtypes = [VP, I]
     lib.tt_mps_checkpoint.restype = I
     lib.tt_window_apply_dev.argtypes = [VP, I, I, I, P(C.c_int32), P(C.c_int32), VP, VP, I, VP, VP]

@@ -325,6 +325,34 @@ def heff_apply_rb(ctx, prec, Lenv, W1, W2, Renv, x, RB, y=None):
     return y
 
 
+def heff_apply_noalloc(ctx, prec, Lenv, W1, W2, Renv, x, RB, y):
+    """tt_heff_apply_dev_noalloc: heff_apply_rb ("f64" or "f32") without device
+    allocation; the output y is the caller's.  Intermediates live in the library's
+    fixed per-GPU scratch, so concurrent calls on one GPU must be serialised."""
+    import torch
+
+    if prec not in ("f64", "f32"):
+        raise ValueError("heff_apply_noalloc: precision must be 'f64' or 'f32'")
+    RA, rl, RC, rr = Lenv.shape[0], Lenv.shape[1], Renv.shape[0], Renv.shape[1]
+    _need_pad("rl", rl)
+    _need_pad("rr", rr)
+    A1, B1, o1 = _sparse(W1, RA, RB, "W1")
+    A2, B2, o2 = _sparse(W2, RB, RC, "W2")
+    dt = _DT[prec]
+    _need((Lenv, "Lenv", dt, (RA, rl, rl), None), (Renv, "Renv", dt, (RC, rr, rr), None),
+          (x, "x", dt, (rl, 4, 4, rr), None), (y, "y", dt, (rl, 4, 4, rr), None))
+    torch.cuda.synchronize()
+    I32 = C.POINTER(C.c_int32)
+    DP = C.POINTER(C.c_double)
+    pL, pR, px, py = _pointers(Lenv, Renv, x, y)
+    rc = ctx.lib.tt_heff_apply_dev_noalloc(ctx.h, PREC[prec], rl, rr, RA, RB, RC, pL, pR, len(A1),
+                                           A1.ctypes.data_as(I32), B1.ctypes.data_as(I32), o1.ctypes.data_as(DP),
+                                           len(A2), A2.ctypes.data_as(I32), B2.ctypes.data_as(I32),
+                                           o2.ctypes.data_as(DP), px, py)
+    ctx._check(rc)
+    return y
+
+
 def heff_apply(ctx, prec, Lenv, W1, W2, Renv, x, y=None):
     """As heff_apply_rb with RB = the largest middle channel index + 1."""
     RB = int(max(np.max(W1[1], initial=-1), np.max(W2[0], initial=-1)) + 1)

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libtt.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["kernels.hip", "bsheff.hip", "bsenv.hip", "engine.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "bsheff.hip", "bsenv.hip", "noalloc.hip", "engine.cpp", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

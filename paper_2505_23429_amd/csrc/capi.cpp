@@ -64,6 +64,68 @@ std::vector<int> vec(const int32_t* p, int n) { return std::vector<int>(p, p + n
 
 }  // namespace
 
+namespace {
+// one table or workspace carved from the no-allocation scratch (256-byte aligned)
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <class T> T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += (count * sizeof(T) + 255) / 256 * 256;
+    return p;
+  }
+};
+
+template <class T>
+int heff_noalloc(Engine& E, int rl, int rr, int RA, int RB, int RC, const T* Lenv, const T* Renv, int nnz1,
+                 const int32_t* A1, const int32_t* B1, const double* ops1, int nnz2, const int32_t* A2,
+                 const int32_t* B2, const double* ops2, const T* x, T* y) {
+  std::vector<int> p1, s1, p2, s2;
+  std::vector<double> o64a, o64b;
+  std::vector<float> o32a, o32b;
+  tt::siteop_csr(RB, vec(B1, nnz1), vec(A1, nnz1), std::vector<double>(ops1, ops1 + 16LL * nnz1), p1, s1, o64a, o32a);
+  tt::siteop_csr(RC, vec(B2, nnz2), vec(A2, nnz2), std::vector<double>(ops2, ops2 + 16LL * nnz2), p2, s2, o64b, o32b);
+  const size_t slab = (size_t)rl * 16 * rr;
+  // the byte count of the carve below, checked before anything is written
+  auto rnd = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t need = rnd(p1.size() * 4) + rnd(s1.size() * 4) + rnd(o64a.size() * sizeof(T)) + rnd(p2.size() * 4) +
+                      rnd(s2.size() * 4) + rnd(o64b.size() * sizeof(T)) +
+                      rnd(slab * std::max(RA, RC) * sizeof(T)) + rnd(slab * RB * sizeof(T));
+  if (need > tt::kNoallocScratchBytes)
+    throw std::invalid_argument("tt_heff_apply_dev_noalloc: the product needs " + std::to_string(need) +
+                                " bytes of scratch, more than its fixed " +
+                                std::to_string(tt::kNoallocScratchBytes) + " bytes (use tt_heff_apply_dev)");
+  Carve c{static_cast<char*>(E.noalloc)};
+  int* d_p1 = c.take<int>(p1.size());
+  int* d_s1 = c.take<int>(s1.size());
+  T* d_o1 = c.take<T>(o64a.size());
+  int* d_p2 = c.take<int>(p2.size());
+  int* d_s2 = c.take<int>(s2.size());
+  T* d_o2 = c.take<T>(o64b.size());
+  T* ws_a = c.take<T>(slab * std::max(RA, RC));
+  T* ws_b = c.take<T>(slab * RB);
+  auto h2d = [&](void* d, const void* h, size_t bytes) {
+    if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, E.stream) != hipSuccess)
+      throw tt::HipError("HIP: copy into the no-allocation scratch failed");
+  };
+  h2d(d_p1, p1.data(), p1.size() * 4);
+  h2d(d_s1, s1.data(), s1.size() * 4);
+  h2d(d_p2, p2.data(), p2.size() * 4);
+  h2d(d_s2, s2.data(), s2.size() * 4);
+  if (sizeof(T) == 8) {
+    h2d(d_o1, o64a.data(), o64a.size() * 8);
+    h2d(d_o2, o64b.data(), o64b.size() * 8);
+  } else {
+    h2d(d_o1, o32a.data(), o32a.size() * 4);
+    h2d(d_o2, o32b.data(), o32b.size() * 4);
+  }
+  tt::heff_dense<T>(E, rl, rr, RA, Lenv, RB, d_p1, d_s1, d_o1, RC, d_p2, d_s2, d_o2, Renv, x, y, ws_a, ws_b, nullptr,
+                    0, 0, nullptr, false);
+  // the host tables above must outlive their copies
+  if (hipStreamSynchronize(E.stream) != hipSuccess) throw tt::HipError("HIP: stream synchronisation failed");
+  return TT_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -259,6 +321,28 @@ int tt_heff_apply_dev(void* ctx, int prec, int rl, int rr, int RA, int RB, int R
   });
 }
 
+
+int tt_heff_apply_dev_noalloc(void* ctx, int prec, int rl, int rr, int RA, int RB, int RC, const void* Lenv,
+                              const void* Renv, int nnz1, const int32_t* A1, const int32_t* B1, const double* ops1,
+                              int nnz2, const int32_t* A2, const int32_t* B2, const double* ops2, const void* x,
+                              void* y) {
+  return guard(ctx, [&](Engine& E) {
+    if (rl <= 0 || rr <= 0 || rl % tt::PAD || rr % tt::PAD)
+      throw std::invalid_argument("rl and rr must be positive multiples of 32");
+    if (RA <= 0 || RB <= 0 || RC <= 0) throw std::invalid_argument("channel counts must be positive");
+    if (!Lenv || !Renv || !x || !y || (nnz1 && (!A1 || !B1 || !ops1)) || (nnz2 && (!A2 || !B2 || !ops2)))
+      throw std::invalid_argument("NULL pointer");
+    check_entries(nnz1, A1, B1, RA, RB);
+    check_entries(nnz2, A2, B2, RB, RC);
+    if (prec == TT_F64)
+      return heff_noalloc<double>(E, rl, rr, RA, RB, RC, (const double*)Lenv, (const double*)Renv, nnz1, A1, B1, ops1,
+                                  nnz2, A2, B2, ops2, (const double*)x, (double*)y);
+    if (prec == TT_F32)
+      return heff_noalloc<float>(E, rl, rr, RA, RB, RC, (const float*)Lenv, (const float*)Renv, nnz1, A1, B1, ops1,
+                                 nnz2, A2, B2, ops2, (const float*)x, (float*)y);
+    throw std::invalid_argument("tt_heff_apply_dev_noalloc: precision must be TT_F64 or TT_F32");
+  });
+}
 
 int tt_gemm_dev(void* ctx, int prec, int M, int N, int K, int batch, int kin, const long long* st, int a_kcontig,
                 int b_ncontig, double alpha, double beta, const void* A, const void* B, void* Cm) {

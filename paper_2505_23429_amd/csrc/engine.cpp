@@ -472,6 +472,7 @@ Engine::Engine(const tt_opts& o)
   RC(rocblas_set_stream(blas, stream));
   HC(hipEventCreate(&ev0));
   HC(hipEventCreate(&ev1));
+  noalloc = noalloc_scratch(o.device);  // this device is current (set above)
 }
 Engine::Engine(const Engine& parent, int)
     : opts(parent.opts), prob(parent.prob), L(prob->L), mpo(prob->mpo), Rb(prob->Rb), chan_q(prob->chan_q),

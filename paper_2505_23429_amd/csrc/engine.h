@@ -159,6 +159,7 @@ class Engine {
   tt_opts opts;
   hipStream_t stream = nullptr;
   bool own_stream = true;     // false: the caller's stream (tt_opts.stream)
+  void* noalloc = nullptr;    // device address of this device's no-allocation scratch array
   ExtAlloc ext;               // the caller's allocator (alloc == nullptr: the library's pools)
   rocblas_handle blas = nullptr;
   std::string err;
@@ -312,6 +313,10 @@ template <class T>
 void heff_dense(Engine& E, int rl, int rr, int RA, const T* Lv, int RB, const int* p1, const int* s1, const T* o1,
                 int RC, const int* p2, const int* s2, const T* o2, const T* Rv, const T* x, T* y, T* ws_a, T* ws_b,
                 const T* Rtil, int P0, int nP, const WinTabs* tabs, bool timed);
+// Device address of the fixed scratch array of the no-allocation entry point on `device`
+// (looked up once per device, with that device current; noalloc.hip).
+void* noalloc_scratch(int device);
+constexpr size_t kNoallocScratchBytes = size_t(256) << 20;
 
 void upload(DevMem& m, const void* h, size_t bytes, hipStream_t s);
 void download(void* h, const DevMem& m, size_t bytes, hipStream_t s);
