@@ -162,6 +162,43 @@ def traffic_summary(read_csv, write_csv, bench_json, commands):
     return out
 
 
+def mfma_summary(pmc_csv, bench_json, command):
+    """Reduce a rocprofv3 --pmc run with the derived counters MfmaUtil (percent of SIMD
+    cycles with the matrix cores busy while the GPU is active) and MfmaFlops (matrix-core
+    flops, 512 per MOPS) to per-kernel averages for the product kernels, beside the
+    algorithmic flops per launch of the same run."""
+    import csv
+    from collections import defaultdict
+
+    per = defaultdict(dict)
+    names = {}
+    with open(pmc_csv) as f:
+        for r in csv.DictReader(f):
+            d = int(r["Dispatch_Id"])
+            per[d][r["Counter_Name"]] = float(r["Counter_Value"])
+            names[d] = r["Kernel_Name"]
+    with open(bench_json) as f:
+        run = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    out = {"workload": run["config"]["workload"], "command": command, "source_sha256_16": kernel_source_hash(),
+           "note": "MfmaUtil: matrix-core busy cycles over (GPU active cycles x SIMDs), percent, averaged over "
+                   "dispatches; MfmaFlops: counted matrix-core flops per dispatch (including the zero padding of "
+                   "partial tiles); algorithmic flops: block-sparse flops per launch from the same run",
+           "kernels": {}}
+    for slot, sym in list(KERNEL_SYMBOLS.items()) + [("mix1_heavy_gemm", "gemm_grouped_kernel<float")]:
+        ds = [d for d, n in names.items() if sym in n and "MfmaUtil" in per[d]]
+        if not ds:
+            continue
+        util = sum(per[d]["MfmaUtil"] for d in ds) / len(ds)
+        mf = sum(per[d].get("MfmaFlops", 0.0) for d in ds) / len(ds)
+        k = run["kernels"].get(slot, {})
+        alg = k["tflops"] * 1e12 * k["ms"] * 1e-3 / k["launches"] if k.get("launches") else None
+        out["kernels"][slot if slot != "mix1_heavy_gemm" else "heavy_gemm_grouped"] = {
+            "symbol": sym, "dispatches": len(ds), "mfma_util_percent": round(util, 2),
+            "mfma_flops_per_dispatch": mf,
+            "algorithmic_flops_per_launch": alg if slot != "mix1_heavy_gemm" else None}
+    return out
+
+
 def stats_summary(stats_csv, bench_json, command, top=30):
     """Format a `rocprofv3 --kernel-trace --stats` kernel_stats.csv together with the JSON
     line the profiled bench.py run printed: the run's configuration, bench.py's own per-slot
@@ -283,6 +320,36 @@ def cpu_baseline(w, lengths, gpu_flops_heff, budget_s):
     }
 
 
+def breakdown_of(names, stats):
+    return {names[i]: {"ms": round(float(stats[i, 0]), 1), "launches": int(stats[i, 1]),
+                       "tflops": round(float(stats[i, 2] / max(stats[i, 0], 1e-9) / 1e9), 2),
+                       "gbs": round(float(stats[i, 3] / max(stats[i, 0], 1e-9) / 1e6), 1)}
+            for i in range(len(names)) if stats[i, 1] > 0}
+
+
+def roofline_of(names, stats, prec):
+    """Roofline of the dominant kernel of the product (largest total time): compute-bound
+    if its algorithmic intensity is above the ridge point of its precision, else HBM-bound."""
+    import numpy as np
+
+    dom = int(np.argmax(stats[:, 0]))
+    ms, launches, flops, nbytes = stats[dom]
+    per_launch_s = ms * 1e-3 / max(launches, 1)
+    ridge = PEAK[prec] * 1e12 / (HBM_PEAK * 1e9)
+    if nbytes > 0 and flops / nbytes > ridge:
+        achieved = flops / max(launches, 1) / per_launch_s / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[prec], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK[prec], 4)}
+    else:
+        achieved = nbytes / max(launches, 1) / per_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK, 4)}
+    roof.update({"traffic": None, "kernel": names[dom], "avg_launch_us": round(per_launch_s * 1e6, 1),
+                 "algorithmic_flops_per_launch": flops / max(launches, 1),
+                 "algorithmic_bytes_per_launch": nbytes / max(launches, 1)})
+    return roof, breakdown_of(names, stats)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +375,9 @@ def main():
     ap.add_argument("--stats-from", nargs=2, metavar=("STATS_CSV", "RUN_JSON"),
                     help="format a rocprofv3 --stats kernel_stats.csv and the JSON line of the profiled run; "
                          "prints the summary and exits (no GPU)")
+    ap.add_argument("--mfma-from", nargs=2, metavar=("PMC_CSV", "RUN_JSON"),
+                    help="reduce a rocprofv3 --pmc MfmaUtil MfmaFlops counter file of the product kernels and the "
+                         "run's JSON line to per-kernel matrix-core utilisation; prints it and exits (no GPU)")
     ap.add_argument("--stats-command", default="",
                     help="the rocprofv3 command that produced the kernel statistics (recorded in the summary)")
     ap.add_argument("--capped", action="store_true",
@@ -320,6 +390,9 @@ def main():
     args = ap.parse_args()
     if args.stats_from:
         print(stats_summary(*args.stats_from, args.stats_command))
+        return
+    if args.mfma_from:
+        print(json.dumps(mfma_summary(*args.mfma_from, args.stats_command), indent=1))
         return
     if args.traffic_from:
         print(json.dumps(traffic_summary(*args.traffic_from, args.traffic_commands), indent=1))
@@ -385,30 +458,34 @@ def main():
     stats = ctx.kernel_timing(enable=False, reset=True)
     sec = (te - ts) / args.steps
     fl = sum(r["flops_heff"] for r in reps)
-    sh = sum(r["seconds_heff"] for r in reps)
-    # dominant kernel of the product and its roofline: compute-bound if its algorithmic
-    # intensity is above the ridge point of its precision, else HBM-bound
     names = Context.KERNELS
-    dom = int(np.argmax(stats[:, 0]))
-    ms, launches, flops, nbytes = stats[dom]
-    per_launch_s = ms * 1e-3 / max(launches, 1)
-    ridge = PEAK[prec] * 1e12 / (HBM_PEAK * 1e9)
-    if nbytes > 0 and flops / nbytes > ridge:
-        achieved = flops / max(launches, 1) / per_launch_s / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[prec], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK[prec], 4)}
+    kernels_timed = breakdown_of(names, stats)
+    iso_note = "timed region (one solve at a time)"
+    if workers > 1:
+        # With concurrent solves the kernels of the other workers' streams run alongside
+        # each product kernel, so HIP-event durations of the timed region include them.
+        # The roofline comes from one more sweep, untimed, with the solves one after
+        # another (same input, same kernels): the configuration whose rocprofv3 kernel
+        # trace is committed.
+        ctx.close()
+        ctx1 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
+                       refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1)
+        ctx1.set_mpo(mpo)
+        ctx1.set_mps(cores, labels)
+        ctx1.kernel_timing(enable=True, reset=True)
+        t = time.perf_counter()
+        r1 = ctx1.sweep(lengths)
+        torch.cuda.synchronize()
+        log(f"one-solve-at-a-time pass: {time.perf_counter() - t:.2f}s E_after={r1['E_after']:.8f}")
+        stats = ctx1.kernel_timing(enable=False, reset=True)
+        ctx1.close()
+        iso_note = "one more sweep after the timed steps with the subdomain solves one after another"
+        iso_steps = 1
     else:
-        achieved = nbytes / max(launches, 1) / per_launch_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK, 4)}
-    roof.update({"traffic": None, "kernel": names[dom], "avg_launch_us": round(per_launch_s * 1e6, 1),
-                 "algorithmic_flops_per_launch": flops / max(launches, 1),
-                 "algorithmic_bytes_per_launch": nbytes / max(launches, 1)})
-    breakdown = {names[i]: {"ms": round(float(stats[i, 0]), 1), "launches": int(stats[i, 1]),
-                            "tflops": round(float(stats[i, 2] / max(stats[i, 0], 1e-9) / 1e9), 2),
-                            "gbs": round(float(stats[i, 3] / max(stats[i, 0], 1e-9) / 1e6), 1)}
-                 for i in range(len(names)) if stats[i, 1] > 0}
-    heff_ms = float(stats[:, 0].sum())
+        iso_steps = args.steps
+    roof, breakdown = roofline_of(names, stats, prec)
+    roof["measured"] = iso_note
+    heff_ms = float(stats[:, 0].sum()) / iso_steps * args.steps
     out = {
         "metric": "sec per two-level sweep + H_eff TFLOP/s at chi=512; batched/mixed vs FP64, dE<1e-6",
         "value": round(sec, 4), "unit": "s/sweep", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -426,7 +503,7 @@ def main():
         "matvecs_per_sweep": int(sum(int(np.sum(r["matvecs"])) for r in reps) / args.steps),
         "fp64_matvecs_per_sweep": int(sum(int(np.sum(r["matvecs_f64"])) for r in reps) / args.steps),
         "E_after": reps[-1]["E_after"], "lambda": reps[-1]["lambda"], "E_before": reps[-1]["E_before"],
-        "roofline": roof, "kernels": breakdown,
+        "roofline": roof, "kernels": breakdown, "kernels_timed_region": kernels_timed,
         "phases_s": {k: round(sum(r["phase_seconds"][i] for r in reps) / args.steps, 3) for i, k in enumerate(
             ("lq", "env_step1", "window_setup", "davidson", "split", "env_sweep", "coarse", "compress",
              "step2_wall"))},
