@@ -2292,9 +2292,10 @@ static DevMem build_mask(Engine& E, int rl, const Labels& ql, int rr, const Labe
 // involves FP64 products, so the low-precision rounding enters the Ritz vector through
 // the correction directions alone, in proportion to their (small) weights.  A cycle ends
 // when the residual has fallen 1000 times below its value at the cycle's start, stalls,
-// or the basis is full; the next cycle starts from the Ritz vector alone with a fresh
-// FP64 product, whose exact residual is the only convergence test.  Each cycle thus gains
-// about three digits for one FP64 product.
+// or the basis is full; the next cycle's basis is the Ritz vector, with a fresh FP64
+// product, and the next two Ritz vectors as correction directions.  The exact residual
+// of the first basis vector is the only convergence test.  Each cycle thus gains about
+// three digits for one FP64 product.
 static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, int prec, double tol, int maxiter,
                          double rel_tol = 0.0, bool stop_on_stall = false, bool anchor = false) {
   Davidson res;
@@ -2353,22 +2354,63 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     dots(V, 1, AV, d);
     Hs[0] = d[0];
   }
-  // anchored refinement: the next cycle starts from the unit Ritz vector u alone
-  auto anchor_restart = [&]() {
+  std::vector<double> evals, evecs, c;
+  // anchored refinement: the next cycle's basis is the unit Ritz vector u, whose product
+  // is taken again in FP64, and the next `more` Ritz vectors of the current basis with
+  // their products combined from the stored ones (correction directions, orthogonal to
+  // u); their couplings with u come from u's FP64 product
+  auto anchor_restart = [&](int more) {
+    more = std::max(0, std::min(more, m - 1));
+    if (more) {
+      E.dav_t2.ensure(sizeof(double) * n * more);
+      E.dav_t3.ensure(sizeof(double) * n * more);
+      for (int q = 0; q < more; ++q) {
+        std::vector<double> cq(m);
+        for (int i = 0; i < m; ++i) cq[i] = evecs[(size_t)i * m + q + 1];
+        lcomb(V, m, cq, E.dav_t2.as<double>() + (size_t)q * n);
+        lcomb(AV, m, cq, E.dav_t3.as<double>() + (size_t)q * n);
+      }
+    }
+    std::vector<double> ev(evals.begin(), evals.end());
     double nu = norm_dev(E, u, n);
     HC(hipMemcpyAsync(V, u, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
     scale(V, 1.0 / nu, n, E.stream);
+    if (more) {
+      HC(hipMemcpyAsync(V + n, E.dav_t2.p, sizeof(double) * n * more, hipMemcpyDeviceToDevice, E.stream));
+      HC(hipMemcpyAsync(AV + n, E.dav_t3.p, sizeof(double) * n * more, hipMemcpyDeviceToDevice, E.stream));
+    }
     product(V, AV, TT_F64);
     std::vector<double> d;
-    dots(V, 1, AV, d);
+    dots(V, 1 + more, AV, d);  // V_q . (A64 V_0)
     Hs.assign((size_t)maxsub * maxsub, 0.0);
     Hs[0] = d[0];
-    m = 1;
+    for (int q = 1; q <= more; ++q) {
+      Hs[(size_t)q * maxsub] = Hs[q] = d[q];
+      Hs[(size_t)q * maxsub + q] = ev[q];
+    }
+    m = 1 + more;
   };
-  std::vector<double> evals, evecs, c;
   double best = HUGE_VAL, cycle0 = HUGE_VAL;
   int since_best = 0;
+  bool fresh = anchor;  // anchored: V_0's product is an FP64 one not yet checked
   for (int it = 0;; ++it) {
+    if (fresh && m > 1) {
+      // V_0 is the only basis vector whose product is entirely FP64: its residual is
+      // exact, and it is the convergence test (the kept correction directions' products
+      // are not)
+      const double th0 = Hs[0];
+      axpby(t, 1.0, AV, -th0, V, n, E.stream);
+      const double r0 = norm_dev(E, t, n);
+      if (r0 <= tol) {
+        res.theta = th0;
+        res.resid = r0;
+        res.iters = it + 1;
+        res.converged = true;
+        HC(hipMemcpyAsync(u, V, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+        break;
+      }
+      cycle0 = r0;
+    }
     // Rayleigh-Ritz
     std::vector<double> Hm((size_t)m * m);
     for (int i = 0; i < m; ++i)
@@ -2383,13 +2425,17 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     res.resid = norm_dev(E, t, n);
     res.iters = it + 1;
     if (anchor) {
-      if (m == 1) {
-        // u's product is an FP64 one: theta and the residual are exact
-        if (res.resid <= tol) {
-          res.converged = true;
-          break;
+      if (fresh) {
+        fresh = false;
+        if (m == 1) {
+          // u = V_0: theta and the residual are exact
+          if (res.resid <= tol) {
+            res.converged = true;
+            break;
+          }
+          cycle0 = res.resid;
         }
-        cycle0 = best = res.resid;
+        best = res.resid;
         since_best = 0;
       } else {
         bool end_cycle = res.resid <= 1e-3 * cycle0 || res.resid <= 0.5 * tol || m >= maxsub;
@@ -2401,7 +2447,8 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
         }
         if (end_cycle) {
           if (res.matvecs >= maxiter) break;
-          anchor_restart();
+          anchor_restart(2);
+          fresh = true;
           continue;
         }
       }
@@ -2465,7 +2512,8 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     if (!(tn > 1e-10 * tn0) || !(tn > 0.0)) {
       // the search space is exhausted
       if (anchor && m > 1 && res.matvecs < maxiter) {
-        anchor_restart();  // confirm the Ritz vector with an exact residual
+        anchor_restart(0);  // confirm the Ritz vector with an exact residual
+        fresh = true;
         continue;
       }
       res.converged = !anchor && res.resid <= tol;
