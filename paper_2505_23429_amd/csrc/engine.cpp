@@ -500,7 +500,7 @@ Engine::~Engine() {
 }
 
 void Engine::release_workspaces() {
-  for (DevMem* m : {&ws0, &ws1, &ws2, &ws3, &wsd, &wsp, &dav_V, &dav_AV, &dav_t, &dav_u, &dav_Au, &dav_c, &dav_mask,
+  for (DevMem* m : {&ws0, &ws1, &ws2, &ws3, &wsd, &wsp, &dav_V, &dav_AV, &dav_t, &dav_u, &dav_Au, &dav_c, &dav_mask, &dav_xd, &dav_yd, &dav_dc,
                     &dav_t2, &dav_t3, &wlow_x, &wlow_y, &wlow_L, &wlow_R, &wlow_Rt, &envq_o, &envq_i, &bs_t1, &bs_t2,
                     &bs_t3, &bs_part, &bs_tmp, &bs_gg1, &bs_gg2, &be_t1, &be_panel, &be_up, &be_tmp})
     m->release();
@@ -2265,19 +2265,32 @@ static void window_matvec(Engine& E, Window& w, const double* x, double* y, int 
   E.flops_heff += w.flops;
 }
 
-static DevMem build_mask(Engine& E, int rl, const Labels& ql, int rr, const Labels& qr) {
-  const int rlp = padr(rl), rrp = padr(rr);
-  std::vector<uint8_t> m((size_t)rlp * 16 * rrp, 0);
+// The quantum-number-allowed entries of a two-site tensor (q(a) + q(s1) + q(s2) = q(b)):
+// their positions in the padded dense layout [rlp][4][4][rrp], nc of them.  The local
+// eigensolver keeps its vectors compressed to these entries, ncp = nc rounded up to 256
+// long with a zero tail; a product expands its input into a dense tensor whose other
+// entries stay zero and compresses its output, which also discards the output's
+// entries outside the allowed ones.
+struct QnIndex {
+  DevMem idx;  // int32 [nc]
+  size_t nc = 0, ncp = 0;
+};
+static QnIndex build_index(Engine& E, int rl, const Labels& ql, int rr, const Labels& qr) {
+  const int rrp = padr(rr);
+  std::vector<int> idx;
   for (int a = 0; a < rl; ++a)
     for (int s1 = 0; s1 < 4; ++s1)
       for (int s2 = 0; s2 < 4; ++s2) {
         Q2 q = qadd(qadd(ql[a], SITE_Q[s1]), SITE_Q[s2]);
         for (int b = 0; b < rr; ++b)
-          if (qr[b] == q) m[(((size_t)a * 4 + s1) * 4 + s2) * rrp + b] = 1;
+          if (qr[b] == q) idx.push_back((int)((((size_t)a * 4 + s1) * 4 + s2) * rrp + b));
       }
-  DevMem d;
-  upload(d, m.data(), m.size(), E.stream);
-  return d;
+  QnIndex r;
+  r.nc = idx.size();
+  r.ncp = std::max<size_t>(256, (r.nc + 255) / 256 * 256);
+  if (idx.empty()) idx.push_back(0);
+  upload(r.idx, idx.data(), idx.size() * sizeof(int), E.stream);
+  return r;
 }
 
 // Davidson for the lowest eigenpair of the window operator restricted to the
@@ -2296,10 +2309,12 @@ static DevMem build_mask(Engine& E, int rl, const Labels& ql, int rr, const Labe
 // product, and the next two Ritz vectors as correction directions.  The exact residual
 // of the first basis vector is the only convergence test.  Each cycle thus gains about
 // three digits for one FP64 product.
-static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, int prec, double tol, int maxiter,
+static Davidson davidson(Engine& E, Window& w, const QnIndex& qi, double* x, int prec, double tol, int maxiter,
                          double rel_tol = 0.0, bool stop_on_stall = false, bool anchor = false) {
   Davidson res;
-  const size_t n = (size_t)w.rlp * 16 * w.rrp;
+  const size_t nd = (size_t)w.rlp * 16 * w.rrp;  // dense tensor
+  const size_t n = qi.ncp;                        // compressed vectors
+  const int* idx = qi.idx.as<int>();
   const int maxsub = std::max(4, std::min(E.opts.dav_maxsub, 64));
   E.dav_V.ensure(sizeof(double) * n * maxsub);
   E.dav_AV.ensure(sizeof(double) * n * maxsub);
@@ -2307,6 +2322,9 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
   E.dav_u.ensure(sizeof(double) * n);
   E.dav_Au.ensure(sizeof(double) * n);
   E.dav_c.ensure(sizeof(double) * 2 * maxsub);
+  E.dav_xd.ensure(sizeof(double) * nd);
+  E.dav_yd.ensure(sizeof(double) * nd);
+  E.dav_dc.ensure(sizeof(double) * n);
   const int nblk = kDotBlocks;
   E.wsp.ensure(sizeof(double) * (size_t)nblk * maxsub);
   double* V = E.dav_V.as<double>();
@@ -2316,6 +2334,9 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
   double* Au = E.dav_Au.as<double>();
   double* cdev = E.dav_c.as<double>();
   double* part = E.wsp.as<double>();
+  double* xd = E.dav_xd.as<double>();
+  double* yd = E.dav_yd.as<double>();
+  double* dg = E.dav_dc.as<double>();
   auto dots = [&](const double* Vb, int m, const double* vec, std::vector<double>& out) {
     multi_dot(Vb, n, m, vec, n, cdev, part, nblk, E.stream);
     out.resize(m);
@@ -2326,25 +2347,25 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     lincomb(Vb, n, m, cdev, out, n, E.stream);
   };
   auto product = [&](const double* v, double* av, int p) {
-    window_matvec(E, w, v, av, p);
-    mask_apply(av, mask.as<uint8_t>(), n, E.stream);
+    scatter_idx(xd, v, idx, qi.nc, E.stream);   // the other entries of xd stay zero
+    window_matvec(E, w, xd, yd, p);
+    gather_idx(av, yd, idx, qi.nc, n, E.stream);
     res.matvecs++;
     if (p == TT_F64) res.matvecs64++;
   };
+  fill(xd, sizeof(double) * nd, E.stream);
+  gather_idx(dg, w.diag.as<double>(), idx, qi.nc, n, E.stream);
   // start vector
-  mask_apply(x, mask.as<uint8_t>(), n, E.stream);
-  double nx = norm_dev(E, x, n);
+  gather_idx(V, x, idx, qi.nc, n, E.stream);
+  double nx = norm_dev(E, V, n);
   if (!(nx > 0.0)) {
     // fall back to a deterministic QN-allowed start: all allowed entries equal
-    std::vector<uint8_t> hm(n);
-    d2h(hm.data(), mask.p, n, E.stream);
-    std::vector<double> h(n);
-    for (size_t i = 0; i < n; ++i) h[i] = hm[i] ? 1.0 : 0.0;
-    HC(hipMemcpyAsync(x, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, E.stream));
-    nx = norm_dev(E, x, n);
-    if (!(nx > 0.0)) throw std::runtime_error("empty QN-allowed space in a local problem");
+    if (qi.nc == 0) throw std::runtime_error("empty QN-allowed space in a local problem");
+    std::vector<double> h(n, 0.0);
+    std::fill(h.begin(), h.begin() + qi.nc, 1.0);
+    HC(hipMemcpyAsync(V, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, E.stream));
+    nx = norm_dev(E, V, n);
   }
-  HC(hipMemcpyAsync(V, x, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
   scale(V, 1.0 / nx, n, E.stream);
   product(V, AV, anchor ? TT_F64 : prec);
   int m = 1;
@@ -2491,7 +2512,7 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     // The direction is formed in its basis slot V_m, so one multi-dot over V_0..V_m
     // gives the projections and the squared norm together.
     double* vm = V + (size_t)m * n;
-    precond(vm, t, w.diag.as<double>(), res.theta, mask.as<uint8_t>(), n, E.stream);
+    precond(vm, t, dg, res.theta, nullptr, n, E.stream);
     std::vector<double> d;
     dots(V, m + 1, vm, d);
     const double tn0 = std::sqrt(std::max(d[m], 0.0));
@@ -2535,10 +2556,11 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
     }
     ++m;
   }
-  // eigenvector -> x (unit norm)
+  // eigenvector -> x (unit norm, zero outside the allowed entries)
   double nu = norm_dev(E, u, n);
-  HC(hipMemcpyAsync(x, u, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
-  scale(x, 1.0 / nu, n, E.stream);
+  scale(u, 1.0 / nu, n, E.stream);
+  fill(x, sizeof(double) * nd, E.stream);
+  scatter_idx(x, u, idx, qi.nc, E.stream);
   HC(hipStreamSynchronize(E.stream));
   return res;
 }
@@ -2547,7 +2569,7 @@ static Davidson davidson(Engine& E, Window& w, const DevMem& mask, double* x, in
 static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem& x, const Core& C, const Core& D) {
   const Labels& ql = C.ql;
   const Labels& qr = D.qr;
-  DevMem mask = build_mask(E, C.rl, ql, D.rr, qr);
+  QnIndex mask = build_index(E, C.rl, ql, D.rr, qr);
   Window w;
   const int prec = E.opts.matvec_prec;
   Davidson r;

@@ -282,6 +282,7 @@ class Engine {
   // workspace
   DevMem ws0, ws1, ws2, ws3, wsd, wsp;
   DevMem dav_V, dav_AV, dav_t, dav_u, dav_Au, dav_c, dav_mask, dav_t2, dav_t3;
+  DevMem dav_xd, dav_yd, dav_dc;  // dense product input/output, compressed diagonal
   DevMem wlow_x, wlow_y, wlow_L, wlow_R, wlow_Rt;
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)

@@ -90,6 +90,10 @@ void scale(double* x, double a, size_t n, hipStream_t s);
 void axpy(double* y, double a, const double* x, size_t n, hipStream_t s);
 void axpby(double* z, double a, const double* x, double b, const double* y, size_t n, hipStream_t s);
 void mask_apply(double* x, const uint8_t* mask, size_t n, hipStream_t s);
+// out[i] = in[idx[i]] for i < nc, 0 for nc <= i < ncp (compressed vector of a tensor's kept entries)
+void gather_idx(double* out, const double* in, const int* idx, size_t nc, size_t ncp, hipStream_t s);
+// out[idx[i]] = in[i] for i < nc (other entries of out untouched)
+void scatter_idx(double* out, const double* in, const int* idx, size_t nc, hipStream_t s);
 // out[i] = sum_n V[i*ldv + n] * w[n] for i < m  (deterministic two-pass reduction).
 // partial holds at least cap_blk * m doubles; the first pass uses dot_blocks(n) workgroups,
 // at most cap_blk (the summation order depends on n and cap_blk only).
@@ -172,6 +176,7 @@ void transpose_batched(const double* in, double* out, int n, int r, int c, hipSt
 void diag_extract(const double* E, int R, int r, double* out, hipStream_t s);
 void diag_mix(int nout, const int* ptr, const int* src, const double* op, const double* in, int n, double* out,
               bool state_inner, hipStream_t s);
+// t = r / (theta - d), |theta - d| clamped to >= 1e-3, where m (may be null: every entry) is set
 void precond(double* t, const double* r, const double* d, double theta, const uint8_t* m, size_t n, hipStream_t s);
 
 }  // namespace tt

@@ -609,6 +609,26 @@ void mask_apply(double* x, const uint8_t* mask, size_t n, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
+// compressed vector <-> dense tensor through an index list of the kept entries
+__global__ void gather_idx_kernel(double* out, const double* in, const int* idx, size_t nc, size_t ncp) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ncp; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = i < nc ? in[idx[i]] : 0.0;
+}
+__global__ void scatter_idx_kernel(double* out, const double* in, const int* idx, size_t nc) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nc; i += (size_t)gridDim.x * blockDim.x)
+    out[idx[i]] = in[i];
+}
+void gather_idx(double* out, const double* in, const int* idx, size_t nc, size_t ncp, hipStream_t s) {
+  if (!ncp) return;
+  hipLaunchKernelGGL(gather_idx_kernel, dim3(nblocks(ncp)), dim3(256), 0, s, out, in, idx, nc, ncp);
+  HIPCHECK(hipGetLastError());
+}
+void scatter_idx(double* out, const double* in, const int* idx, size_t nc, hipStream_t s) {
+  if (!nc) return;
+  hipLaunchKernelGGL(scatter_idx_kernel, dim3(nblocks(nc)), dim3(256), 0, s, out, in, idx, nc);
+  HIPCHECK(hipGetLastError());
+}
+
 // Two-pass deterministic multi-dot.  First pass: partial[i][blk] = sum over the
 // block's grid-stride share of V_i . w.  A block takes the vectors CNT <= 8 at a time
 // (w is read once per pass); with VEC = 2 every load is 16 bytes.  Sums are reduced
@@ -1329,7 +1349,7 @@ __global__ void precond_kernel(double* t, const double* r, const double* d, doub
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     double den = theta - d[i];
     if (fabs(den) < 1e-3) den = den < 0 ? -1e-3 : 1e-3;
-    t[i] = m[i] ? r[i] / den : 0.0;
+    t[i] = (!m || m[i]) ? r[i] / den : 0.0;
   }
 }
 void precond(double* t, const double* r, const double* d, double theta, const uint8_t* m, size_t n, hipStream_t s) {
