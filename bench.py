@@ -252,7 +252,7 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w, lengths, gpu_flops_heff, budget_s):
+def cpu_baseline(w, lengths, gpu_flops_heff, budget_s, coarse_k=1):
     """The oracle (oracle.chain with the oracle's own MPO, dense in the bond indices) as
     it stands, timed on the host cores for a bounded sample of this workload: blocks of
     8 output rows of its two-site product at the middle window (the product restricted to
@@ -304,7 +304,7 @@ def cpu_baseline(w, lengths, gpu_flops_heff, budget_s):
     Rm = float(np.mean(Rb[1:-1]))
     f_env = 2.0 * 4 * r * r * (2 * Rm * r)
     n_env = 2 * (L - 1) + sum(max(m - 1, 0) for m in lengths)
-    n_states = len(lengths) + 1
+    n_states = coarse_k * len(lengths) + 1
     n_env += n_states * (n_states + 1) // 2 * L + L  # coarse sandwiches + final energy chain
     total = gpu_flops_heff / rate + n_env * f_env / rate
     return {
@@ -384,6 +384,10 @@ def main():
                     help="instead of converged local solves: residual tolerance 1e-5 (FP32) and at most "
                          "--dav-maxiter (default 40) products per local solve, no refinement (fixed work per window)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-product sweep after the timed steps")
+    ap.add_argument("--matvec", choices=("f64", "f32", "bf16"), default=None,
+                    help="product precision instead of the workload's own")
+    ap.add_argument("--coarse-k", type=int, default=1,
+                    help="local eigenvectors kept per subdomain for the coarse space (Extension One)")
     ap.add_argument("--lowprec-tol", type=float, default=1e-5,
                     help="relative residual at which the low-precision Davidson phase hands over to the "
                          "FP64-anchored refinement")
@@ -417,12 +421,13 @@ def main():
     mpo = build_mpo(h, B)
     cores, labels = S.random_mps(w.L, w.n_elec, w.two_sz, chi, w.seed + 1)
     log(f"setup: MPO R_mid={mpo.R[w.L // 2]} nnz={sum(mpo.nnz())} in {time.perf_counter() - t0:.1f}s")
-    prec = w.matvec_prec
+    prec = args.matvec or w.matvec_prec
     tol, maxiter, refine = w.dav_tol, args.dav_maxiter or 4000, prec != "f64"
     if args.capped:
         tol, maxiter, refine = (w.dav_tol if prec == "f64" else 1e-5), args.dav_maxiter or 40, False
     ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
-                  refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=args.sub_workers)
+                  refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=args.sub_workers,
+                  coarse_k=args.coarse_k)
     workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
     # host -> device hand-over (PCIe) and device left-orthogonalisation: outside the timed region
@@ -469,7 +474,8 @@ def main():
         # trace is committed.
         ctx.close()
         ctx1 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
-                       refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1)
+                       refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1,
+                       coarse_k=args.coarse_k)
         ctx1.set_mpo(mpo)
         ctx1.set_mps(cores, labels)
         ctx1.kernel_timing(enable=True, reset=True)
@@ -496,7 +502,7 @@ def main():
                    "dav_max_products": maxiter, "fp64_refinement": refine,
                    "lowprec_handover": args.lowprec_tol if refine else None,
                    "integrals_seed": w.seed, "mps_seed": w.seed + 1, "parallelism": "single-gpu",
-                   "concurrent_subdomain_solves": workers},
+                   "concurrent_subdomain_solves": workers, "coarse_k": args.coarse_k},
         "heff_tflops_block_sparse": round(float(stats[:, 2].sum()) / max(heff_ms * 1e-3, 1e-12) / 1e12, 3),
         "heff_block_sparse_flops_per_sweep": float(stats[:, 2].sum()) / args.steps,
         "heff_seconds_per_sweep": round(heff_ms * 1e-3 / args.steps, 3),
@@ -515,7 +521,8 @@ def main():
         # the measured context's device memory is released first
         ctx.close()
         ctx64 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24,
-                        matvec_prec="f64", refine_fp64=False, sub_workers=args.sub_workers)
+                        matvec_prec="f64", refine_fp64=False, sub_workers=args.sub_workers,
+                        coarse_k=args.coarse_k)
         ctx64.set_mpo(mpo)
         ctx64.set_mps(cores, labels)
         ctx64.checkpoint()
@@ -536,7 +543,7 @@ def main():
                                                          np.asarray(reps[-1]["E_local"])).max())}
         ctx64.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, lengths, fl / args.steps, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, lengths, fl / args.steps, args.cpu_seconds, args.coarse_k)
     if args.copy_probe:
         n = (1 << 30) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -109,6 +109,17 @@ typedef struct tt_opts {
                          Blocks live until the call that frees them or tt_destroy, so the
                          callbacks must stay valid until tt_destroy returns. */
   void* alloc_user;   /* passed to dev_alloc/dev_free */
+  int coarse_k;       /* Extension One (Remark "Extensions of the A2DMRG algorithm"): the last
+                         micro-step of every subdomain keeps its coarse_k lowest eigenvectors
+                         (FP64 products), each giving an updated TT, so the coarse space has
+                         nsub * coarse_k + 1 states (<= TT_MAX_SUB + 1); 1 = the plain method */
+  int one_site;       /* 0: two-site micro-steps (Algorithm 2, two-site branch); 1: one-site
+                         micro-steps (Algorithm 2, one-site branch, Definition "One-site and
+                         two-site DMRG micro-iterations"): subdomain j optimises the cores of its
+                         sites s_j..e_j one after another, moving the centre right by a
+                         charge-block QR (the orthogonalization step of Algorithm 1), so bond
+                         dimensions do not change in Step 2.  Needs matvec_prec = TT_F64 and
+                         qn_skip = 1 (EINVAL otherwise). */
 } tt_opts;
 
 #define TT_MAX_SUB 64
@@ -134,6 +145,7 @@ typedef struct tt_sweep_report {
                                       solves; with concurrent solves entries 2-5 are summed over
                                       the workers */
   int matvecs_f64[TT_MAX_SUB];     /* of matvecs[]: the products taken in FP64 */
+  int nstates;                     /* coarse states n = nsub * coarse_k + 1: S, A are n x n, coef n */
 } tt_sweep_report;
 
 void tt_default_opts(tt_opts* o);
@@ -178,7 +190,9 @@ int tt_local_solve(void* ctx, int nsub, const int* lengths, double* E_local, int
 
 /* Steps 3-4: coarse matrices over {current, subdomain updates}, coarse
  * eigenpair, compression of the combination to chi_max; the result becomes
- * the current iterate.  S_out/A_out are row-major (nsub+1)^2. */
+ * the current iterate.  S_out/A_out are row-major n x n and coef_out n long,
+ * n = nsub * coarse_k + 1 (states ordered: current iterate, then per subdomain
+ * its updates from the lowest local eigenvector up). */
 int tt_coarse_correct(void* ctx, double* S_out, double* A_out, double* coef_out, double* lambda_out,
                       double* E_out, int* rankS_out);
 

@@ -24,6 +24,10 @@ contractions only, so it reaches the sizes of the bench workloads:
   left-to-right truncated SVD with the truncation rule of
   ``oracle.tt.truncation_keep``) of the textbook direct-sum tensor train of
   sum_j c_j tau(U^j);
+* Algorithm 2, one-site branch: the one-site operator (eq. mat_vec) applied as
+  L.x -> W -> R, subdomain j swept over sites s_j .. e_j with the
+  orthogonalization step of Algorithm 1 (``oracle.tt.qr_left_core``) moving the
+  centre right between micro-steps;
 * Algorithm 1 (two-site branch) with the same pieces.
 
 Every dense step is a library matrix product or factorisation on plain
@@ -134,6 +138,19 @@ def heff_apply(Lenv, W1: SiteOps, W2: SiteOps, Renv, x):
     return y.reshape(pl, 4, 4, pr)
 
 
+def heff1_apply(Lenv, W: SiteOps, Renv, x):
+    """y[a', s', b'] = sum L[a', A, a] W[A, s', s, B] R[b', B, b] x[a, s, b] (one-site form)."""
+    rl, rr = x.shape[0], x.shape[2]
+    pl, pr = Lenv.shape[0], Renv.shape[0]
+    RA, RB = W.RA, W.RB
+    t = (Lenv.transpose(1, 0, 2).reshape(RA * pl, rl) @ x.reshape(rl, 4 * rr)).reshape(RA, pl, 4, rr)
+    t = t.transpose(0, 2, 1, 3).reshape(RA * 4, pl * rr)               # [A s, a' b]
+    t = spmm(W.fw, t)                                                  # [B s', a' b]
+    t = t.reshape(RB, 4, pl, rr).transpose(2, 1, 0, 3).reshape(pl * 4, RB * rr)
+    y = t @ Renv.reshape(pr, RB * rr).T
+    return y.reshape(pl, 4, pr)
+
+
 def chain_energy(mpo, ops, cores):
     """<U|H|U> / <U|U> by one left-to-right environment chain."""
     E = np.ones((1, 1, 1))
@@ -158,18 +175,68 @@ def chain_sandwich(ops, bra, ket):
 # local eigenproblem (micro-iteration)
 # ---------------------------------------------------------------------------
 
+def local_solve_k(Lenv, W1, W2, Renv, x0, ql, qr, K, tol=1e-12):
+    """The K lowest eigenpairs of the two-site effective operator on the allowed
+    entries (Extension One), by ARPACK's implicitly restarted Lanczos
+    (scipy.sparse.linalg.eigsh), or dense eigh for small local spaces.  Returns a
+    list of (theta, x) in increasing theta, and the number of products."""
+    return _k_lowest(lambda z: heff_apply(Lenv, W1, W2, Renv, z), T.x_mask(ql, qr), x0, K, tol)
+
+
+def local_solve1_k(Lenv, W, Renv, x0, ql, qr, K, tol=1e-12):
+    """``local_solve_k`` for the one-site operator of ``heff1_apply``."""
+    return _k_lowest(lambda z: heff1_apply(Lenv, W, Renv, z), T.x1_mask(ql, qr), x0, K, tol)
+
+
+def _k_lowest(apply, m, x0, K, tol):
+    from scipy.sparse.linalg import LinearOperator, eigsh
+
+    dim = int(m.sum())
+    count = [0]
+
+    def mv(v):
+        z = np.zeros(m.shape)
+        z[m] = np.ravel(v)
+        count[0] += 1
+        return apply(z)[m]
+
+    if dim <= 400:
+        H = np.stack([mv(e) for e in np.eye(dim)], axis=1)
+        w, v = np.linalg.eigh(0.5 * (H + H.T))
+    else:
+        start = x0[m] if np.any(x0[m]) else np.ones(dim)
+        w, v = eigsh(LinearOperator((dim, dim), matvec=mv, dtype=np.float64), k=K, which="SA", v0=start, tol=tol,
+                     ncv=max(4 * K, 24))
+        o = np.argsort(w)
+        w, v = w[o], v[:, o]
+    out = []
+    for q in range(min(K, w.size)):
+        x = np.zeros(m.shape)
+        x[m] = v[:, q] / np.linalg.norm(v[:, q])
+        out.append((float(w[q]), x))
+    return out, count[0]
+
+
 def local_solve(Lenv, W1, W2, Renv, x0, ql, qr, tol=1e-11, maxiter=1000):
     """Lowest eigenpair of the two-site effective operator on the entries of x
     allowed by the bond charges (Lemma "DMRG micro-iterations for eigenvalue
     problems").  Returns (theta, x, matvecs)."""
-    m = T.x_mask(ql, qr)
+    return _lowest(lambda z: heff_apply(Lenv, W1, W2, Renv, z), T.x_mask(ql, qr), x0, tol, maxiter)
+
+
+def local_solve1(Lenv, W, Renv, x0, ql, qr, tol=1e-11, maxiter=1000):
+    """``local_solve`` for the one-site operator of ``heff1_apply`` (x0, x: one core)."""
+    return _lowest(lambda z: heff1_apply(Lenv, W, Renv, z), T.x1_mask(ql, qr), x0, tol, maxiter)
+
+
+def _lowest(apply, m, x0, tol, maxiter):
     count = [0]
 
     def mv(v):
         z = np.zeros(m.shape)
         z[m] = v
         count[0] += 1
-        return heff_apply(Lenv, W1, W2, Renv, z)[m]
+        return apply(z)[m]
 
     start = x0[m]
     if not np.any(start):
@@ -329,9 +396,12 @@ class ChainReport:
     state_labels: list
 
 
-def a2dmrg_sweep(mpo, cores, labels, chi, lengths, eps=1e-8, tol=1e-11, cutoff=1e-12, tau=1e-10, log=None):
+def a2dmrg_sweep(mpo, cores, labels, chi, lengths, eps=1e-8, tol=1e-11, cutoff=1e-12, tau=1e-10, log=None,
+                 n_eig=1, sites=2):
     """One global iteration of Algorithm 2 from a left-orthogonal TT
-    (U_0..U_{L-2}, W_{L-1}).  Same readings as ``oracle.tt.a2dmrg_sweep``."""
+    (U_0..U_{L-2}, W_{L-1}).  Same readings as ``oracle.tt.a2dmrg_sweep``,
+    including ``n_eig`` (Extension One at every subdomain's last micro-step) and
+    ``sites`` (1: one-site micro-steps)."""
     L = mpo.L
     ops = [site_ops(mpo, k) for k in range(L)]
     cores = [c.copy() for c in cores]
@@ -345,7 +415,9 @@ def a2dmrg_sweep(mpo, cores, labels, chi, lengths, eps=1e-8, tol=1e-11, cutoff=1
         Le.append(env_left(Le[k], cores[k], ops[k], cores[k]))
     Re = [None] * (L + 1)
     Re[L] = np.ones((1, 1, 1))
-    for k in range(L - 1, 1, -1):
+    # a one-site micro-step at site k reads Re[k + 1], a two-site one at (b, b + 1) Re[b + 2]
+    kmin = 1 if sites == 1 else 2
+    for k in range(L - 1, kmin - 1, -1):
         Re[k] = env_right(Re[k + 1], V[k], ops[k], V[k])
     states, state_labels = [cores], [labels]
     E_local, matvecs = [], []
@@ -356,9 +428,40 @@ def a2dmrg_sweep(mpo, cores, labels, chi, lengths, eps=1e-8, tol=1e-11, cutoff=1
         Lrun = Le[s]
         blast = min(e, L - 2)
         theta, nmv = 0.0, 0
+        alts = []
+        if sites == 1:
+            for k in range(s, e + 1):
+                if k == e and n_eig > 1:
+                    pairs, nk = local_solve1_k(Lrun, ops[k], Re[k + 1], cur[k], lab[k], lab[k + 1], n_eig)
+                    theta, x = pairs[0]
+                    for _, xq in pairs[1:]:
+                        alt = list(cur)
+                        alt[k] = xq / np.linalg.norm(xq)
+                        alts.append((alt, [q.copy() for q in lab]))
+                else:
+                    theta, x, nk = local_solve1(Lrun, ops[k], Re[k + 1], cur[k], lab[k], lab[k + 1], tol)
+                nmv += nk
+                if k < e:
+                    Q, R = T.qr_left_core(x, lab[k], lab[k + 1])
+                    cur[k], cur[k + 1] = Q, np.einsum("ab,bsc->asc", R, cur[k + 1])
+                    Lrun = env_left(Lrun, Q, ops[k], Q)
+                else:
+                    cur[k] = x / np.linalg.norm(x)
+                if log:
+                    log(f"subdomain {j} site {k}: theta={theta:.12f} products={nk}")
+            blast = -1  # no two-site micro-steps
         for b in range(s, blast + 1):
             x = np.einsum("asb,btc->astc", cur[b], cur[b + 1])
-            theta, x, k = local_solve(Lrun, ops[b], ops[b + 1], Re[b + 2], x, lab[b], lab[b + 2], tol)
+            if b == blast and n_eig > 1:
+                pairs, k = local_solve_k(Lrun, ops[b], ops[b + 1], Re[b + 2], x, lab[b], lab[b + 2], n_eig)
+                theta, x = pairs[0]
+                for _, xq in pairs[1:]:
+                    Aq, Cq, qq, _, _ = T.split_two_site(xq, lab[b], lab[b + 2], chi, True, cutoff, tau)
+                    alt, alt_lab = list(cur), [q.copy() for q in lab]
+                    alt[b], alt[b + 1], alt_lab[b + 1] = Aq, Cq / np.linalg.norm(Cq), qq
+                    alts.append((alt, alt_lab))
+            else:
+                theta, x, k = local_solve(Lrun, ops[b], ops[b + 1], Re[b + 2], x, lab[b], lab[b + 2], tol)
             nmv += k
             A, C, qn, _, _ = T.split_two_site(x, lab[b], lab[b + 2], chi, True, cutoff, tau)
             cur[b], cur[b + 1], lab[b + 1] = A, C, qn
@@ -366,10 +469,13 @@ def a2dmrg_sweep(mpo, cores, labels, chi, lengths, eps=1e-8, tol=1e-11, cutoff=1
                 Lrun = env_left(Lrun, A, ops[b], A)
             if log:
                 log(f"subdomain {j} bond {b}: theta={theta:.12f} products={k}")
-        if s <= L - 2:
+        if sites == 2 and s <= L - 2:
             cur[blast + 1] = cur[blast + 1] / np.linalg.norm(cur[blast + 1])
         states.append(cur)
         state_labels.append(lab)
+        for alt, alt_lab in alts:
+            states.append(alt)
+            state_labels.append(alt_lab)
         E_local.append(theta)
         matvecs.append(nmv)
     n = len(states)

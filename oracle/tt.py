@@ -20,6 +20,11 @@ state vectors restricted to one (N, Sz) sector, so it is limited to small
   subdomain grouping of Extension Two: subdomain j = sites [s_j, e_j] is swept
   left to right over bonds (s_j, s_j+1) .. (e_j, e_j+1), the last subdomain
   stopping at (L-2, L-1), so every bond is optimised once per global iteration.
+* Algorithm 2, one-site branch: the one-site retraction P_{U,k,1} as an explicit
+  matrix, the micro-iteration S_k as the lowest eigenpair of ``P^T A P``, and
+  subdomain j swept over sites s_j .. e_j with the orthogonalization step of
+  Algorithm 1 (charge-block QR of the new core, its R factor carried into the
+  next core) between micro-steps.
 * Second-level problem (eq. d_opt_lin_3/4, eq. A_reduced and the
   rank-deficient branch eq. aux_eig_final_sym): coarse matrices from dense
   state vectors, eigen-decomposition of the overlap with relative threshold
@@ -201,6 +206,21 @@ def x_mask(ql, qr) -> np.ndarray:
     return np.all(tot == qr[None, None, None, :, :], axis=-1)
 
 
+def x1_mask(ql, qr) -> np.ndarray:
+    """Allowed entries q(a) + q(s) = q(b) of one core."""
+    tot = ql[:, None, None, :] + SITE_Q[None, :, None, :]
+    return np.all(tot == qr[None, None, :, :], axis=-1)
+
+
+def qr_left_core(x, ql, qr):
+    """Orthogonalization step of Algorithm 1 (one-site branch): x[a, s, b] = Q R with Q
+    left-orthogonal (charge-block QR of the (a s) x b unfolding); returns (Q, R)."""
+    r, n, r2 = x.shape
+    row_q = (ql[:, None, :] + SITE_Q[None, :, :]).reshape(-1, 2)
+    Q, R = _block_qr(x.reshape(r * n, r2), row_q, qr)
+    return Q.reshape(r, n, r2), R
+
+
 class Problem:
     """Hamiltonian restricted to the target sector plus the index maps needed
     to move between dense vectors and tensor-train pieces."""
@@ -241,6 +261,39 @@ class Problem:
                 P[np.ix_(rows, cols)] = PhiL[il[rows][:, None], a_i[cols][None, :]] * PhiR[b_i[cols][None, :], ir[rows][:, None]]
         return P, m
 
+    def retraction1(self, cores, k, ql, qr):
+        """Explicit one-site retraction P_{U,k,1} (cores 0..k-1 and k+1..L-1 of
+        ``cores``) restricted to the sector rows and the allowed entries of the core."""
+        L = self.L
+        PhiL = left_block(cores, k)
+        PhiR = right_block(cores, k + 1)
+        nr = 4 ** (L - k - 1)
+        il = self.tidx // (4 * nr)
+        sv = (self.tidx // nr) % 4
+        ir = self.tidx % nr
+        m = x1_mask(ql, qr)
+        a_i, s_i, b_i = np.nonzero(m)
+        P = np.zeros((self.tidx.size, a_i.size))
+        for v in range(4):
+            rows = np.nonzero(sv == v)[0]
+            cols = np.nonzero(s_i == v)[0]
+            if rows.size and cols.size:
+                P[np.ix_(rows, cols)] = PhiL[il[rows][:, None], a_i[cols][None, :]] * PhiR[b_i[cols][None, :], ir[rows][:, None]]
+        return P, m
+
+    def local_solve1_k(self, cores, k, ql, qr, K=1):
+        """Micro-iteration S_k (one-site): the K lowest eigenpairs of P^T H P with the
+        one-site retraction (dense eigensolver); unit eigenvectors as cores."""
+        P, m = self.retraction1(cores, k, ql, qr)
+        Heff = P.T @ self.H @ P
+        w, v = np.linalg.eigh(0.5 * (Heff + Heff.T))
+        out = []
+        for q in range(min(K, w.size)):
+            x = np.zeros(m.shape)
+            x[m] = v[:, q]
+            out.append((float(w[q]), x))
+        return out
+
     def local_solve(self, cores, k, ql, qr, x0=None, tol=1e-12, dense_limit=3000):
         """Micro-iteration S_{k,k+1}: lowest eigenpair of P^T H P."""
         P, m = self.retraction(cores, k, ql, qr)
@@ -256,6 +309,18 @@ class Problem:
         x = np.zeros(m.shape)
         x[m] = u
         return float(theta), x
+
+    def local_solve_k(self, cores, k, ql, qr, K):
+        """The K lowest eigenpairs of P^T H P (Extension One); dense eigensolver."""
+        P, m = self.retraction(cores, k, ql, qr)
+        Heff = P.T @ self.H @ P
+        w, v = np.linalg.eigh(0.5 * (Heff + Heff.T))
+        out = []
+        for q in range(min(K, w.size)):
+            x = np.zeros(m.shape)
+            x[m] = v[:, q]
+            out.append((float(w[q]), x))
+        return out
 
 
 # ---------------------------------------------------------------------------
@@ -355,12 +420,23 @@ def tt_svd(prob: Problem, y_sector, chi, cutoff=1e-12, tau=1e-10):
     return cores, labels
 
 
-def a2dmrg_sweep(prob: Problem, cores, labels, chi, lengths, eps=1e-8, cutoff=1e-12, tau=1e-10):
-    """One global iteration of Algorithm 2 (two-site) with subdomains.
+def a2dmrg_sweep(prob: Problem, cores, labels, chi, lengths, eps=1e-8, cutoff=1e-12, tau=1e-10, n_eig=1, sites=2):
+    """One global iteration of Algorithm 2 (two-site, or one-site with ``sites=1``)
+    with subdomains.
 
     ``cores`` must be left-orthogonal (U_0..U_{L-2}, W_{L-1}).  Returns a
     ``SweepReport`` with the local energies, the coarse matrices, the coarse
     eigenpair and the compressed next iterate (left-orthogonal, normalised).
+
+    ``n_eig`` > 1: Extension One of the Remark on extensions of Algorithm 2, read
+    for subdomains: the last micro-step of every subdomain keeps its ``n_eig``
+    lowest eigenvectors, each giving an updated TT (coarse states ordered by
+    subdomain, the lowest eigenvector's first).
+
+    ``sites=1``: one-site micro-steps at sites s_j .. e_j of subdomain j, each followed
+    (but the last) by the orthogonalization step that moves the centre right; the
+    update is (U_0..U_{s-1}, Q_s..Q_{e-1}, x_e, V_{e+1}..V_{L-1}) with unit x_e, and
+    its bond dimensions are those of the iterate.
     """
     L = prob.L
     norm0 = np.sqrt(np.sum(contract_full(cores) ** 2))
@@ -375,13 +451,42 @@ def a2dmrg_sweep(prob: Problem, cores, labels, chi, lengths, eps=1e-8, cutoff=1e
         lab = [q.copy() for q in labels]
         cur = cores[:s] + [W[s]] + [V[k] for k in range(s + 1, L)]
         theta = None
-        for b in range(s, min(e, L - 2) + 1):
-            theta, x = prob.local_solve(cur, b, lab[b], lab[b + 2])
+        alts = []
+        if sites == 1:
+            for k in range(s, e + 1):
+                pairs = prob.local_solve1_k(cur, k, lab[k], lab[k + 1], n_eig if k == e else 1)
+                theta, x = pairs[0]
+                if k < e:
+                    cur[k], R = qr_left_core(x, lab[k], lab[k + 1])
+                    cur[k + 1] = np.einsum("ab,bsc->asc", R, cur[k + 1])
+                else:
+                    for _, xq in pairs[1:]:
+                        alt = list(cur)
+                        alt[k] = xq / np.linalg.norm(xq)
+                        alts.append(alt)
+                    cur[k] = x / np.linalg.norm(x)
+            states.append(cur)
+            states.extend(alts)
+            E_local.append(theta)
+            continue
+        blast = min(e, L - 2)
+        for b in range(s, blast + 1):
+            if b == blast and n_eig > 1:
+                pairs = prob.local_solve_k(cur, b, lab[b], lab[b + 2], n_eig)
+                theta, x = pairs[0]
+                for _, xq in pairs[1:]:
+                    A, C, qn, _, _ = split_two_site(xq, lab[b], lab[b + 2], chi, True, cutoff, tau)
+                    alt = list(cur)
+                    alt[b], alt[b + 1] = A, C / np.linalg.norm(C)
+                    alts.append(alt)
+            else:
+                theta, x = prob.local_solve(cur, b, lab[b], lab[b + 2])
             A, C, qn, _, _ = split_two_site(x, lab[b], lab[b + 2], chi, True, cutoff, tau)
             cur[b], cur[b + 1], lab[b + 1] = A, C, qn
-        last = min(e, L - 2) + 1
+        last = blast + 1
         cur[last] = cur[last] / np.linalg.norm(cur[last])
         states.append(cur)
+        states.extend(alts)
         E_local.append(theta)
     Y = np.stack([prob.to_sector(contract_full(st)) for st in states], axis=1)
     S = Y.T @ Y

@@ -33,7 +33,8 @@ class Opts(C.Structure):
         ("refine_fp64", C.c_int), ("lowprec_tol", C.c_double), ("device", C.c_int), ("qn_skip", C.c_int),
         ("sub_workers", C.c_int), ("mix_stage", C.c_int), ("svd_lds", C.c_int),
         ("worker_alloc_limit", C.c_longlong), ("stream", C.c_void_p), ("dev_alloc", C.c_void_p),
-        ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p),
+        ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p), ("coarse_k", C.c_int),
+        ("one_site", C.c_int),
     ]
 
 
@@ -52,7 +53,7 @@ class SweepReport(C.Structure):
         ("coef", C.c_double * (TT_MAX_SUB + 1)), ("lambda_", C.c_double), ("rankS", C.c_int),
         ("E_after", C.c_double), ("discarded", C.c_double), ("seconds", C.c_double * 4),
         ("flops_heff", C.c_double), ("seconds_heff", C.c_double), ("phase_seconds", C.c_double * 9),
-        ("matvecs_f64", C.c_int * TT_MAX_SUB),
+        ("matvecs_f64", C.c_int * TT_MAX_SUB), ("nstates", C.c_int),
     ]
 
 

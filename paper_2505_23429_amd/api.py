@@ -38,10 +38,12 @@ class Context:
 
     def __init__(self, chi=64, dav_tol=1e-8, dav_maxiter=200, dav_maxsub=24, coarse_eps=1e-8, svd_cutoff=1e-12,
                  tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True,
-                 sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0, stream=None, torch_alloc=False):
+                 sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0, stream=None, torch_alloc=False,
+                 coarse_k=1, one_site=False):
         """``stream``: a torch.cuda.Stream (or raw stream handle) every call runs on;
         ``torch_alloc``: take every device block of the context from the torch caching
-        allocator (tt_opts.dev_alloc/dev_free) instead of the library's own pools."""
+        allocator (tt_opts.dev_alloc/dev_free) instead of the library's own pools;
+        ``one_site``: one-site micro-steps (FP64 products) instead of two-site ones."""
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -61,6 +63,9 @@ class Context:
         o.mix_stage = int(mix_stage)
         o.svd_lds = int(bool(svd_lds))
         o.worker_alloc_limit = int(worker_alloc_limit)
+        o.coarse_k = int(coarse_k)
+        self.coarse_k = int(coarse_k)
+        o.one_site = int(bool(one_site))
         if stream is not None:
             o.stream = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
         self._callbacks = None
@@ -150,7 +155,8 @@ class Context:
         return E, mv, rc
 
     def coarse_correct(self, nsub):
-        n = nsub + 1
+        """Steps 3-4 after local_solve over nsub subdomains (nsub * coarse_k + 1 coarse states)."""
+        n = nsub * self.coarse_k + 1
         S = np.zeros((n, n))
         A = np.zeros((n, n))
         c = np.zeros(n)
@@ -167,7 +173,7 @@ class Context:
         lp, lpp = _iarr(lengths)
         rep = L.SweepReport()
         rc = self._check(self.lib.tt_sweep(self.h, n, lpp, C.byref(rep)))
-        m = n + 1
+        m = rep.nstates
         S = np.array(rep.S[: m * m]).reshape(m, m)
         A = np.array(rep.A[: m * m]).reshape(m, m)
         return {

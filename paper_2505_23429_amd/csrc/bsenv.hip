@@ -393,27 +393,45 @@ void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2
 }
 
 // ---------------------------------------------------------------------------
-// one update
+// tables of one update shape (bond labels and padded sizes), and the first two
+// stages (stage 1 and the mix, which write the panels of every output bra sector)
 // ---------------------------------------------------------------------------
-bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, const Core& ket, double* out) {
+struct EnvTab {
+  int ng = 0, nPs = 0, nQs = 0, nRs = 0, nTs = 0;
+  long long n1 = 0, npan = 0, nup = 0, ntmp = 0;
+  Sec SP, SQ, SR, ST;
+  std::vector<int> gcols, gld, Ntau, Ktau, t3tau, koff, pcol;
+  std::vector<long long> goff, htmp, t3base, pbase, upoff, hbase;
+  std::vector<EnvS1> s1;
+  std::vector<int4> t1, tm, th, t3;
+  std::vector<EnvUP> ups;
+  std::vector<EnvS3> s3;
+  DevMem d_s1, d_t1, d_cinfo, d_goff, d_gcols, d_specoff, d_th, d_hbase, d_nR, d_grp, d_spec, d_tm, d_t3tau, d_t3base,
+      d_Ntau, d_pcol, d_ups, d_oP, d_nP, d_oT, d_nT, d_s3, d_t3;
+  // heavy-row GEMMs of the mix, uploaded for the T1 and staging buffers they were built for
+  std::vector<GemmGroup<double>> gg;
+  DevMem ggdev;
+  const double* gg_t1 = nullptr;
+  const double* gg_tmp = nullptr;
+};
+
+// lP/lQ: bra/ket labels at the input bond, lR/lT: ket/bra labels at the output bond;
+// Pp..Tp their padded sizes; ket_rrp: padded right bond of the ket core (its row stride).
+static bool env_tab(Engine& E, const BsSiteUse& u, const Labels& lP, const Labels& lQ, const Labels& lR,
+                    const Labels& lT, int Pp, int Qp, int Rp, int Tp, int ket_rrp, EnvTab& t) {
+  (void)Pp; (void)Qp; (void)Rp; (void)Tp;
   const bool left = u.sigma > 0;
   const int sg = u.sigma;
-  const Labels& lP = left ? bra.ql : bra.qr;
-  const Labels& lQ = left ? ket.ql : ket.qr;
-  const Labels& lR = left ? ket.qr : ket.ql;
-  const Labels& lT = left ? bra.qr : bra.ql;
-  if ((int)bra.ql.size() != bra.rl || (int)bra.qr.size() != bra.rr || (int)ket.ql.size() != ket.rl ||
-      (int)ket.qr.size() != ket.rr)
-    return false;
-  Sec SP, SQ, SR, ST;
+  Sec &SP = t.SP, &SQ = t.SQ, &SR = t.SR, &ST = t.ST;
   if (!sectors(lP, SP) || !sectors(lQ, SQ) || !sectors(lR, SR) || !sectors(lT, ST)) return false;
-  const int Pp = left ? bra.rlp() : bra.rrp(), Qp = left ? ket.rlp() : ket.rrp();
-  const int Rp = left ? ket.rrp() : ket.rlp(), Tp = left ? bra.rrp() : bra.rlp();
   const int nPs = (int)SP.q.size(), nQs = (int)SQ.q.size(), nRs = (int)SR.q.size(), nTs = (int)ST.q.size();
+  t.nPs = nPs; t.nQs = nQs; t.nRs = nRs; t.nTs = nTs;
   const int ng = u.ngrp;
+  t.ng = ng;
 
   // spectators (pi, rho) grouped by Gamma = Q_rho - Q_pi
-  std::vector<int> gcols(ng, 0);
+  std::vector<int>& gcols = t.gcols;
+  gcols.assign(ng, 0);
   std::vector<std::vector<int4>> spec_g(ng);
   std::vector<long long> specoff((size_t)std::max(nPs * nRs, 1), -1);
   for (int pi = 0; pi < nPs; ++pi)
@@ -426,21 +444,21 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
       gcols[g] += SP.n[pi] * SR.n[rho];
     }
   // T1 rows of a group are stored with a stride rounded up to 4 elements
-  std::vector<long long> goff(ng, 0);
-  std::vector<int> gld(ng, 0);
+  t.goff.assign(ng, 0);
+  t.gld.assign(ng, 0);
   long long n1 = 0;
   std::vector<int4> spec;
   std::vector<EnvGrp> grp(ng);
   for (int g = 0; g < ng; ++g) {
-    gld[g] = (gcols[g] + 3) / 4 * 4;
-    goff[g] = n1;
-    n1 += (long long)u.nrows_in[g] * gld[g];
-    grp[g] = EnvGrp{goff[g], gcols[g], (int)spec.size(), (int)spec_g[g].size(), gld[g]};
+    t.gld[g] = (gcols[g] + 3) / 4 * 4;
+    t.goff[g] = n1;
+    n1 += (long long)u.nrows_in[g] * t.gld[g];
+    grp[g] = EnvGrp{t.goff[g], gcols[g], (int)spec.size(), (int)spec_g[g].size(), t.gld[g]};
     spec.insert(spec.end(), spec_g[g].begin(), spec_g[g].end());
   }
+  t.n1 = n1;
 
   // stage 1: per (input class c, ket sector kappa)
-  const long long bks = left ? 4LL * ket.rrp() : 1LL;
   std::vector<int4> cinfo;
   std::vector<int> col0(nQs), ncol(nQs);
   for (int ka = 0; ka < nQs; ++ka) {
@@ -449,207 +467,371 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
       const int rho = SR.find(add(SQ.q[ka], mul(sg, kQ[s])));
       if (rho < 0) continue;
       for (int ir = 0; ir < SR.n[rho]; ++ir) {
-        const int cx = left ? s * ket.rrp() + SR.off[rho] + ir : (SR.off[rho] + ir) * 4 * ket.rrp() + s * ket.rrp();
+        const int cx = left ? s * ket_rrp + SR.off[rho] + ir : (SR.off[rho] + ir) * 4 * ket_rrp + s * ket_rrp;
         cinfo.push_back(make_int4(cx, s, rho, ir));
       }
     }
     ncol[ka] = (int)cinfo.size() - col0[ka];
   }
-  std::vector<EnvS1> s1;
-  std::vector<int4> t1;
   for (int c = 0; c < u.ncin; ++c) {
     const int cnt = u.cstart_in[c + 1] - u.cstart_in[c];
     for (int ka = 0; ka < nQs; ++ka) {
       const int pi = SP.find(add(SQ.q[ka], u.cq_in[c]));
       if (pi < 0 || ncol[ka] == 0 || cnt == 0) continue;
       EnvS1 d{cnt * SP.n[pi], ncol[ka], SQ.n[ka], u.cstart_in[c], SP.n[pi], SP.off[pi], SQ.off[ka], col0[ka], pi, 0};
-      const int id = (int)s1.size();
-      s1.push_back(d);
+      const int id = (int)t.s1.size();
+      t.s1.push_back(d);
       for (int m0 = 0; m0 < d.M; m0 += TL)
-        for (int c0 = 0; c0 < d.N; c0 += TL) t1.push_back(make_int4(id, m0, c0, 0));
+        for (int c0 = 0; c0 < d.N; c0 += TL) t.t1.push_back(make_int4(id, m0, c0, 0));
     }
   }
 
   // panels: tau rows (pi, s', i_p) with Q_tau = Q_pi + sigma q(s'); columns (class c', K', i_r)
-  std::vector<int> Ntau(nTs, 0), Ktau(nTs, 0), pcol((size_t)std::max(nTs * u.ncout, 1), -1);
+  t.Ntau.assign(nTs, 0);
+  t.Ktau.assign(nTs, 0);
+  t.pcol.assign((size_t)std::max(nTs * u.ncout, 1), -1);
   for (int ta = 0; ta < nTs; ++ta)
     for (int c = 0; c < u.ncout; ++c) {
       const int rho = SR.find(sub(ST.q[ta], u.cq_out[c]));
       if (rho < 0) continue;
-      pcol[(size_t)ta * u.ncout + c] = Ntau[ta];
-      Ntau[ta] += (u.cstart_out[c + 1] - u.cstart_out[c]) * SR.n[rho];
+      t.pcol[(size_t)ta * u.ncout + c] = t.Ntau[ta];
+      t.Ntau[ta] += (u.cstart_out[c + 1] - u.cstart_out[c]) * SR.n[rho];
     }
-  std::vector<int> t3tau((size_t)std::max(nPs * 4, 1), -1), koff((size_t)std::max(nPs * 4, 1), 0);
+  t.t3tau.assign((size_t)std::max(nPs * 4, 1), -1);
+  t.koff.assign((size_t)std::max(nPs * 4, 1), 0);
   for (int ta = 0; ta < nTs; ++ta)
     for (int pi = 0; pi < nPs; ++pi)
       for (int s = 0; s < 4; ++s)
         if (add(SP.q[pi], mul(sg, kQ[s])) == ST.q[ta]) {
-          t3tau[pi * 4 + s] = ta;
-          koff[pi * 4 + s] = Ktau[ta];
-          Ktau[ta] += SP.n[pi];
+          t.t3tau[pi * 4 + s] = ta;
+          t.koff[pi * 4 + s] = t.Ktau[ta];
+          t.Ktau[ta] += SP.n[pi];
         }
-  std::vector<long long> pbase(nTs, 0), upoff(nTs, 0);
+  t.pbase.assign(nTs, 0);
+  t.upoff.assign(nTs, 0);
   long long npan = 0, nup = 0;
   for (int ta = 0; ta < nTs; ++ta) {
-    pbase[ta] = npan;
-    npan += (long long)Ktau[ta] * Ntau[ta];
-    upoff[ta] = nup;
-    nup += (long long)ST.n[ta] * Ktau[ta];
+    t.pbase[ta] = npan;
+    npan += (long long)t.Ktau[ta] * t.Ntau[ta];
+    t.upoff[ta] = nup;
+    nup += (long long)ST.n[ta] * t.Ktau[ta];
   }
-  std::vector<long long> t3base((size_t)std::max(nPs * 4, 1), -1);
-  std::vector<EnvUP> ups;
+  t.npan = npan;
+  t.nup = nup;
+  t.t3base.assign((size_t)std::max(nPs * 4, 1), -1);
   for (int pi = 0; pi < nPs; ++pi)
     for (int s = 0; s < 4; ++s) {
-      const int ta = t3tau[pi * 4 + s];
+      const int ta = t.t3tau[pi * 4 + s];
       if (ta < 0) continue;
-      t3base[pi * 4 + s] = pbase[ta] + (long long)koff[pi * 4 + s] * Ntau[ta];
-      ups.push_back(EnvUP{upoff[ta], ta, pi, s, koff[pi * 4 + s], Ktau[ta], 0});
+      t.t3base[pi * 4 + s] = t.pbase[ta] + (long long)t.koff[pi * 4 + s] * t.Ntau[ta];
+      t.ups.push_back(EnvUP{t.upoff[ta], ta, pi, s, t.koff[pi * 4 + s], t.Ktau[ta], 0});
     }
 
   // mix tiles: light rows, and heavy rows (staged by the GEMM) with their staging offsets
-  std::vector<int4> tm, th;
-  std::vector<long long> hbase((size_t)std::max(u.hrow0[ng], 1), 0), htmp(ng, 0);
+  t.hbase.assign((size_t)std::max(u.hrow0[ng], 1), 0);
+  t.htmp.assign(ng, 0);
   long long ntmp = 0;
   for (int g = 0; g < ng; ++g) {
     if (gcols[g] == 0) continue;
     for (int c0 = 0; c0 < gcols[g]; c0 += MC)
       for (int r0 = u.orow0[g]; r0 < u.orow0[g + 1]; r0 += MR)
-        tm.push_back(make_int4(g, c0, r0, std::min(r0 + MR, u.orow0[g + 1])));
+        t.tm.push_back(make_int4(g, c0, r0, std::min(r0 + MR, u.orow0[g + 1])));
     if (u.hrow0[g + 1] > u.hrow0[g]) {
-      htmp[g] = ntmp;
-      for (int r = u.hrow0[g]; r < u.hrow0[g + 1]; ++r) hbase[r] = ntmp + (long long)(r - u.hrow0[g]) * gld[g];
-      ntmp += (long long)(u.hrow0[g + 1] - u.hrow0[g]) * gld[g];
+      t.htmp[g] = ntmp;
+      for (int r = u.hrow0[g]; r < u.hrow0[g + 1]; ++r) t.hbase[r] = ntmp + (long long)(r - u.hrow0[g]) * t.gld[g];
+      ntmp += (long long)(u.hrow0[g + 1] - u.hrow0[g]) * t.gld[g];
       for (int c0 = 0; c0 < gcols[g]; c0 += MC)
         for (int r0 = u.hrow0[g]; r0 < u.hrow0[g + 1]; r0 += MR)
-          th.push_back(make_int4(g, c0, r0, std::min(r0 + MR, u.hrow0[g + 1])));
+          t.th.push_back(make_int4(g, c0, r0, std::min(r0 + MR, u.hrow0[g + 1])));
     }
   }
+  t.ntmp = ntmp;
 
   // stage 3: per (tau, output class c')
-  std::vector<EnvS3> s3;
-  std::vector<int4> t3;
   for (int ta = 0; ta < nTs; ++ta) {
-    if (Ktau[ta] == 0) continue;
+    if (t.Ktau[ta] == 0) continue;
     for (int c = 0; c < u.ncout; ++c) {
-      const int pc = pcol[(size_t)ta * u.ncout + c];
+      const int pc = t.pcol[(size_t)ta * u.ncout + c];
       if (pc < 0) continue;
       const int rho = SR.find(sub(ST.q[ta], u.cq_out[c]));
       const int cnt = u.cstart_out[c + 1] - u.cstart_out[c];
-      EnvS3 d{upoff[ta], pbase[ta], ST.n[ta], cnt * SR.n[rho], Ktau[ta], Ntau[ta], pc, u.cstart_out[c],
+      EnvS3 d{t.upoff[ta], t.pbase[ta], ST.n[ta], cnt * SR.n[rho], t.Ktau[ta], t.Ntau[ta], pc, u.cstart_out[c],
               SR.n[rho], SR.off[rho], ST.off[ta], 0};
-      const int id = (int)s3.size();
-      s3.push_back(d);
+      const int id = (int)t.s3.size();
+      t.s3.push_back(d);
       for (int m0 = 0; m0 < d.M; m0 += TL)
-        for (int n0 = 0; n0 < d.N; n0 += TL) t3.push_back(make_int4(id, m0, n0, 0));
+        for (int n0 = 0; n0 < d.N; n0 += TL) t.t3.push_back(make_int4(id, m0, n0, 0));
     }
   }
 
-  // device tables of this update
+  // device tables
   hipStream_t st = E.stream;
-  DevMem d_s1, d_t1, d_cinfo, d_goff, d_gcols, d_specoff, d_th, d_hbase, d_nR, d_grp, d_spec, d_tm, d_t3tau, d_t3base, d_Ntau,
-      d_pcol, d_ups, d_oP, d_nP, d_oT, d_nT, d_s3, d_t3, d_err;
-  up(d_s1, s1, st);
-  up(d_t1, t1, st);
-  up(d_cinfo, cinfo, st);
-  up(d_goff, goff, st);
-  up(d_gcols, gld, st);
-  up(d_th, th, st);
-  up(d_hbase, hbase, st);
-  up(d_specoff, specoff, st);
-  up(d_nR, SR.n, st);
-  up(d_grp, grp, st);
-  up(d_spec, spec, st);
-  up(d_tm, tm, st);
-  up(d_t3tau, t3tau, st);
-  up(d_t3base, t3base, st);
-  up(d_Ntau, Ntau, st);
-  up(d_pcol, pcol, st);
-  up(d_ups, ups, st);
-  up(d_oP, SP.off, st);
-  up(d_nP, SP.n, st);
-  up(d_oT, ST.off, st);
-  up(d_nT, ST.n, st);
-  up(d_s3, s3, st);
-  up(d_t3, t3, st);
+  up(t.d_s1, t.s1, st);
+  up(t.d_t1, t.t1, st);
+  up(t.d_cinfo, cinfo, st);
+  up(t.d_goff, t.goff, st);
+  up(t.d_gcols, t.gld, st);
+  up(t.d_th, t.th, st);
+  up(t.d_hbase, t.hbase, st);
+  up(t.d_specoff, specoff, st);
+  up(t.d_nR, SR.n, st);
+  up(t.d_grp, grp, st);
+  up(t.d_spec, spec, st);
+  up(t.d_tm, t.tm, st);
+  up(t.d_t3tau, t.t3tau, st);
+  up(t.d_t3base, t.t3base, st);
+  up(t.d_Ntau, t.Ntau, st);
+  up(t.d_pcol, t.pcol, st);
+  up(t.d_ups, t.ups, st);
+  up(t.d_oP, SP.off, st);
+  up(t.d_nP, SP.n, st);
+  up(t.d_oT, ST.off, st);
+  up(t.d_nT, ST.n, st);
+  up(t.d_s3, t.s3, st);
+  up(t.d_t3, t.t3, st);
+  return true;
+}
+
+// stage 1 and the mix: T1 (n1 elements, zeroed here), the panels (npan), the heavy-row
+// staging buffer tmp (ntmp).  Ein: [nin][Pp][Qp]; ket: the ket core (nket elements).
+static void env_panel(Engine& E, const BsSiteUse& u, EnvTab& t, const double* Ein, long long nE, int Qp,
+                      long long PQ, const double* ket, long long nket, long long bks, double* T1, double* panel,
+                      double* tmp, int* err) {
+  hipStream_t st = E.stream;
+  // T1 entries whose ket sector Q_pi - d_K does not exist are never written
+  fill(T1, sizeof(double) * t.n1, st);
+  if (!t.t1.empty()) {
+    hipLaunchKernelGGL(env_s1_kernel, dim3((unsigned)t.t1.size()), dim3(256), 0, st, t.d_t1.as<int4>(),
+                       t.d_s1.as<EnvS1>(), u.clist_in.as<int>(), t.d_cinfo.as<int4>(), u.d_gidx_in.as<int>(),
+                       u.rin.as<int>(), t.d_goff.as<long long>(), t.d_gcols.as<int>(), t.d_specoff.as<long long>(),
+                       t.d_nR.as<int>(), t.nRs, Ein, PQ, Qp, nE, ket, nket, bks, T1, t.n1, err);
+    BECHECK(hipGetLastError());
+  }
+  if (!t.tm.empty()) {
+    hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)t.tm.size()), dim3(MC), 0, st, t.d_tm.as<int4>(),
+                       t.d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
+                       u.orow.as<int2>(), t.d_spec.as<int4>(), T1, t.n1, panel, t.npan, t.d_t3tau.as<int>(),
+                       t.d_t3base.as<long long>(), t.d_Ntau.as<int>(), t.d_pcol.as<int>(), u.ncout,
+                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), t.d_nR.as<int>(), err,
+                       (const long long*)nullptr, (const double*)nullptr);
+    BECHECK(hipGetLastError());
+  }
+  if (!t.th.empty()) {
+    if (t.gg_t1 != T1 || t.gg_tmp != tmp) {
+      t.gg.clear();
+      for (int g = 0; g < t.ng; ++g) {
+        const int H = u.hrow0[g + 1] - u.hrow0[g];
+        if (H == 0 || t.gcols[g] == 0) continue;
+        GemmGroup<double> G{};
+        G.g.M = H; G.g.N = t.gcols[g]; G.g.K = u.nrows_in[g]; G.g.batch = 1;
+        G.g.kin = std::max(16, (u.nrows_in[g] + 15) / 16 * 16);
+        G.g.sAm = u.nin4[g]; G.g.sAkk = 1;
+        G.g.sBkk = t.gld[g]; G.g.sBn = 1;
+        G.g.sCm = t.gld[g]; G.g.alpha = 1.0; G.g.beta = 0.0;
+        G.A = u.hw.as<double>() + u.hw_off[g];
+        G.B = T1 + t.goff[g];
+        G.C = tmp + t.htmp[g];
+        t.gg.push_back(G);
+      }
+      upload(t.ggdev, t.gg.data(), t.gg.size() * sizeof(GemmGroup<double>), st);
+      t.gg_t1 = T1;
+      t.gg_tmp = tmp;
+    }
+    gemm_grouped<double>(t.ggdev.as<GemmGroup<double>>(), t.gg, st);
+    hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)t.th.size()), dim3(MC), 0, st, t.d_th.as<int4>(),
+                       t.d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
+                       u.hrow.as<int2>(), t.d_spec.as<int4>(), T1, t.n1, panel, t.npan, t.d_t3tau.as<int>(),
+                       t.d_t3base.as<long long>(), t.d_Ntau.as<int>(), t.d_pcol.as<int>(), u.ncout,
+                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), t.d_nR.as<int>(), err, t.d_hbase.as<long long>(),
+                       (const double*)tmp);
+    BECHECK(hipGetLastError());
+  }
+}
+
+static void check_err(DevMem& d_err, hipStream_t st, const char* what) {
+  int herr = 0;
+  BECHECK(hipMemcpyAsync(&herr, d_err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  BECHECK(hipStreamSynchronize(st));
+  if (herr != 0)
+    throw std::runtime_error(std::string(what) + ": index outside its buffer (check " + std::to_string(herr) + ")");
+}
+
+// ---------------------------------------------------------------------------
+// one update
+// ---------------------------------------------------------------------------
+bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, const Core& ket, double* out) {
+  const bool left = u.sigma > 0;
+  const Labels& lP = left ? bra.ql : bra.qr;
+  const Labels& lQ = left ? ket.ql : ket.qr;
+  const Labels& lR = left ? ket.qr : ket.ql;
+  const Labels& lT = left ? bra.qr : bra.ql;
+  if ((int)bra.ql.size() != bra.rl || (int)bra.qr.size() != bra.rr || (int)ket.ql.size() != ket.rl ||
+      (int)ket.qr.size() != ket.rr)
+    return false;
+  const int Pp = left ? bra.rlp() : bra.rrp(), Qp = left ? ket.rlp() : ket.rrp();
+  const int Rp = left ? ket.rrp() : ket.rlp(), Tp = left ? bra.rrp() : bra.rlp();
+  EnvTab t;
+  if (!env_tab(E, u, lP, lQ, lR, lT, Pp, Qp, Rp, Tp, ket.rrp(), t)) return false;
+  hipStream_t st = E.stream;
+  DevMem d_err;
   d_err.resize_zero(sizeof(int), st);
   int* err = d_err.as<int>();
-
-  E.be_t1.ensure(sizeof(double) * std::max<long long>(n1, 1));
-  E.be_panel.ensure(sizeof(double) * std::max<long long>(npan, 1));
-  E.be_up.ensure(sizeof(double) * std::max<long long>(nup, 1));
+  E.be_t1.ensure(sizeof(double) * std::max<long long>(t.n1, 1));
+  E.be_panel.ensure(sizeof(double) * std::max<long long>(t.npan, 1));
+  E.be_up.ensure(sizeof(double) * std::max<long long>(t.nup, 1));
+  if (!t.th.empty()) E.be_tmp.ensure(sizeof(double) * std::max<long long>(t.ntmp, 1));
   const long long nE = (long long)u.nin * Pp * Qp;
   const long long nout = (long long)u.nout * Tp * Rp;
   const long long nket = (long long)ket.rlp() * 4 * ket.rrp();
   const long long nbra = (long long)bra.rlp() * 4 * bra.rrp();
   fill(out, sizeof(double) * nout, st);
-  // T1 entries whose ket sector Q_pi - d_K does not exist are never written
-  fill(E.be_t1.p, sizeof(double) * n1, st);
-  if (!t1.empty()) {
-    hipLaunchKernelGGL(env_s1_kernel, dim3((unsigned)t1.size()), dim3(256), 0, st, d_t1.as<int4>(), d_s1.as<EnvS1>(),
-                       u.clist_in.as<int>(), d_cinfo.as<int4>(), u.d_gidx_in.as<int>(), u.rin.as<int>(),
-                       d_goff.as<long long>(), d_gcols.as<int>(), d_specoff.as<long long>(), d_nR.as<int>(), nRs,
-                       Ein, (long long)Pp * Qp, Qp, nE, ket.d.as<double>(), nket, bks, E.be_t1.as<double>(), n1, err);
-    BECHECK(hipGetLastError());
-  }
-  if (!tm.empty()) {
-    hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)tm.size()), dim3(MC), 0, st, d_tm.as<int4>(),
-                       d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
-                       u.orow.as<int2>(), d_spec.as<int4>(), E.be_t1.as<double>(), n1, E.be_panel.as<double>(), npan,
-                       d_t3tau.as<int>(), d_t3base.as<long long>(), d_Ntau.as<int>(), d_pcol.as<int>(), u.ncout,
-                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), d_nR.as<int>(), err,
-                       (const long long*)nullptr, (const double*)nullptr);
-    BECHECK(hipGetLastError());
-  }
-  if (!th.empty()) {
-    E.be_tmp.ensure(sizeof(double) * std::max<long long>(ntmp, 1));
-    std::vector<GemmGroup<double>> gg;
-    for (int g = 0; g < ng; ++g) {
-      const int H = u.hrow0[g + 1] - u.hrow0[g];
-      if (H == 0 || gcols[g] == 0) continue;
-      GemmGroup<double> G{};
-      G.g.M = H; G.g.N = gcols[g]; G.g.K = u.nrows_in[g]; G.g.batch = 1;
-      G.g.kin = std::max(16, (u.nrows_in[g] + 15) / 16 * 16);
-      G.g.sAm = u.nin4[g]; G.g.sAkk = 1;
-      G.g.sBkk = gld[g]; G.g.sBn = 1;
-      G.g.sCm = gld[g]; G.g.alpha = 1.0; G.g.beta = 0.0;
-      G.A = u.hw.as<double>() + u.hw_off[g];
-      G.B = E.be_t1.as<double>() + goff[g];
-      G.C = E.be_tmp.as<double>() + htmp[g];
-      gg.push_back(G);
-    }
-    DevMem gdev;
-    upload(gdev, gg.data(), gg.size() * sizeof(GemmGroup<double>), st);
-    gemm_grouped<double>(gdev.as<GemmGroup<double>>(), gg, st);
-    hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)th.size()), dim3(MC), 0, st, d_th.as<int4>(),
-                       d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
-                       u.hrow.as<int2>(), d_spec.as<int4>(), E.be_t1.as<double>(), n1, E.be_panel.as<double>(), npan,
-                       d_t3tau.as<int>(), d_t3base.as<long long>(), d_Ntau.as<int>(), d_pcol.as<int>(), u.ncout,
-                       u.d_cls_out.as<int>(), u.pos_out.as<int>(), d_nR.as<int>(), err, d_hbase.as<long long>(),
-                       (const double*)E.be_tmp.as<double>());
-    BECHECK(hipGetLastError());
-  }
-  if (!ups.empty()) {
+  const long long bks = left ? 4LL * ket.rrp() : 1LL;
+  env_panel(E, u, t, Ein, nE, Qp, (long long)Pp * Qp, ket.d.as<double>(), nket, bks, E.be_t1.as<double>(),
+            E.be_panel.as<double>(), t.th.empty() ? nullptr : E.be_tmp.as<double>(), err);
+  if (!t.ups.empty()) {
     const long long rbp = bra.rrp();
     const long long ps = left ? 4 * rbp : 1, ss = rbp, ts = left ? 1 : 4 * rbp;
-    hipLaunchKernelGGL(env_up_kernel, dim3((unsigned)ups.size()), dim3(256), 0, st, d_ups.as<EnvUP>(),
-                       bra.d.as<double>(), nbra, ps, ss, ts, d_oP.as<int>(), d_nP.as<int>(), d_oT.as<int>(),
-                       d_nT.as<int>(), E.be_up.as<double>(), nup, err);
+    hipLaunchKernelGGL(env_up_kernel, dim3((unsigned)t.ups.size()), dim3(256), 0, st, t.d_ups.as<EnvUP>(),
+                       bra.d.as<double>(), nbra, ps, ss, ts, t.d_oP.as<int>(), t.d_nP.as<int>(), t.d_oT.as<int>(),
+                       t.d_nT.as<int>(), E.be_up.as<double>(), t.nup, err);
     BECHECK(hipGetLastError());
   }
-  if (!t3.empty()) {
-    hipLaunchKernelGGL(env_s3_kernel, dim3((unsigned)t3.size()), dim3(256), 0, st, d_t3.as<int4>(),
-                       d_s3.as<EnvS3>(), E.be_up.as<double>(), nup, E.be_panel.as<double>(), npan,
+  if (!t.t3.empty()) {
+    hipLaunchKernelGGL(env_s3_kernel, dim3((unsigned)t.t3.size()), dim3(256), 0, st, t.d_t3.as<int4>(),
+                       t.d_s3.as<EnvS3>(), E.be_up.as<double>(), t.nup, E.be_panel.as<double>(), t.npan,
                        u.clist_out.as<int>(), out, nout, (long long)Tp * Rp, Rp, err);
     BECHECK(hipGetLastError());
   }
-  int herr = 0;
-  BECHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
-  BECHECK(hipStreamSynchronize(st));
-  if (herr != 0)
-    throw std::runtime_error("block-sparse environment update: index outside its buffer (check " +
-                             std::to_string(herr) + ")");
-  (void)nQs;
+  check_err(d_err, st, "block-sparse environment update");
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// one-site effective-Hamiltonian product (eq. mat_vec, one-site form)
+//   y[a'][s'][b'] = sum L[A][a'][a] W[A,s',s,B] x[a][s][b] R[B][b'][b]
+// Stage 1 and the mix of the left update with ket = x leave, for every output
+// bra sector tau of the right bond, the panel P_tau[(pi, s', i_p)][(B, i_r)] =
+// sum L W x.  The last stage multiplies it by the right environment stacked per
+// tau, Rs_tau[(B, i_r)][j] = R[B][o_tau + j][o_rho + i_r] (built once per local
+// problem), one GEMM per (pi, s') written straight into y.
+// ---------------------------------------------------------------------------
+namespace {
+struct R1Desc { long long dst; int cls0, cnt, nr, orho, ntau, otau, pad; };
+
+__global__ __launch_bounds__(256) void rstack1_kernel(const R1Desc* __restrict__ desc,
+                                                      const int* __restrict__ clist_out,
+                                                      const double* __restrict__ R, long long nR, int rrp,
+                                                      double* __restrict__ Rs, long long nRs, int* __restrict__ err) {
+  const R1Desc d = desc[blockIdx.x];
+  const long long tot = (long long)d.cnt * d.nr * d.ntau;
+  for (long long e = threadIdx.x; e < tot; e += 256) {
+    const int j = (int)(e % d.ntau);
+    const long long row = e / d.ntau;
+    const int ir = (int)(row % d.nr), pos = (int)(row / d.nr);
+    const int K = clist_out[d.cls0 + pos];
+    const long long q = ((long long)K * rrp + d.otau + j) * rrp + d.orho + ir;
+    const long long dst = d.dst + e;
+    if (q < 0 || q >= nR || dst < 0 || dst >= nRs) { err[0] = 21; continue; }
+    Rs[dst] = R[q];
+  }
+}
+}  // namespace
+
+struct BsHeff1Impl {
+  EnvTab t;
+  std::shared_ptr<BsSiteUse> use;
+  int rlp = 0, rrp = 0, RAx = 0;
+  DevMem t1, panel, tmp, Rs, err;
+  std::vector<long long> rsoff;
+  std::vector<GemmGroup<double>> yg;
+  DevMem ygdev;
+  double* yg_y = nullptr;
+};
+
+bool bs_heff1_build(Engine& E, BsHeff1& h, std::shared_ptr<BsSiteUse> use, const Labels& ql, const Labels& qr, int RAx,
+                    const double* R, int RB) {
+  auto p = std::make_shared<BsHeff1Impl>();
+  const BsSiteUse& u = *use;
+  if (u.sigma != 1 || u.nin != RAx || u.nout != RB)
+    throw std::runtime_error("one-site product: site tables do not match the environments");
+  p->use = use;
+  p->RAx = RAx;
+  p->rlp = padr((int)ql.size());
+  p->rrp = padr((int)qr.size());
+  // bra = ket = x: P = Q = left bond labels, R = T = right bond labels
+  if (!env_tab(E, u, ql, ql, qr, qr, p->rlp, p->rlp, p->rrp, p->rrp, p->rrp, p->t)) return false;
+  EnvTab& t = p->t;
+  hipStream_t st = E.stream;
+  p->t1.ensure(sizeof(double) * std::max<long long>(t.n1, 1));
+  p->panel.ensure(sizeof(double) * std::max<long long>(t.npan, 1));
+  if (!t.th.empty()) p->tmp.ensure(sizeof(double) * std::max<long long>(t.ntmp, 1));
+  p->err.resize_zero(sizeof(int), st);
+  // stacked right environment per tau: rows = panel columns (class, K', i_r), columns j
+  std::vector<R1Desc> rd;
+  p->rsoff.assign(t.nTs, 0);
+  long long nrs = 0;
+  for (int ta = 0; ta < t.nTs; ++ta) {
+    p->rsoff[ta] = nrs;
+    const int ntau = t.ST.n[ta];
+    for (int c = 0; c < u.ncout; ++c) {
+      const int pc = t.pcol[(size_t)ta * u.ncout + c];
+      if (pc < 0) continue;
+      const int rho = t.SR.find(sub(t.ST.q[ta], u.cq_out[c]));
+      const int cnt = u.cstart_out[c + 1] - u.cstart_out[c];
+      if (cnt == 0 || t.SR.n[rho] == 0 || ntau == 0) continue;
+      rd.push_back(R1Desc{nrs + (long long)pc * ntau, u.cstart_out[c], cnt, t.SR.n[rho], t.SR.off[rho], ntau,
+                          t.ST.off[ta], 0});
+    }
+    nrs += (long long)t.Ntau[ta] * ntau;
+  }
+  p->Rs.resize_zero(sizeof(double) * std::max<long long>(nrs, 1), st);
+  if (!rd.empty()) {
+    DevMem d_rd;
+    up(d_rd, rd, st);
+    hipLaunchKernelGGL(rstack1_kernel, dim3((unsigned)rd.size()), dim3(256), 0, st, d_rd.as<R1Desc>(),
+                       u.clist_out.as<int>(), R, (long long)RB * p->rrp * p->rrp, p->rrp, p->Rs.as<double>(),
+                       std::max<long long>(nrs, 1), p->err.as<int>());
+    BECHECK(hipGetLastError());
+    check_err(p->err, st, "one-site product set-up");
+  }
+  // block-sparse flops of one product's two contractions (stage 1 and the last
+  // stage; the sparse mix between them is not counted)
+  double fl = 0.0;
+  for (const EnvS1& d : t.s1) fl += 2.0 * d.M * (double)d.N * d.K;
+  for (const EnvUP& e : t.ups) fl += 2.0 * t.SP.n[e.pi] * (double)t.Ntau[e.tau] * t.ST.n[e.tau];
+  h.flops = fl;
+  h.p = p;
+  return true;
+}
+
+void bs_heff1_apply(Engine& E, BsHeff1& h, const double* Lx, const double* x, double* y) {
+  BsHeff1Impl& p = *h.p;
+  EnvTab& t = p.t;
+  const BsSiteUse& u = *p.use;
+  hipStream_t st = E.stream;
+  const long long nx = (long long)p.rlp * 4 * p.rrp;
+  fill(y, sizeof(double) * nx, st);
+  env_panel(E, u, t, Lx, (long long)p.RAx * p.rlp * p.rlp, p.rlp, (long long)p.rlp * p.rlp, x, nx, 4LL * p.rrp,
+            p.t1.as<double>(), p.panel.as<double>(), t.th.empty() ? nullptr : p.tmp.as<double>(), p.err.as<int>());
+  if (p.yg_y != y) {
+    p.yg.clear();
+    for (const EnvUP& e : t.ups) {
+      const int np = t.SP.n[e.pi], ntau = t.ST.n[e.tau], K = t.Ntau[e.tau];
+      if (np == 0 || ntau == 0 || K == 0) continue;
+      GemmGroup<double> G{};
+      G.g.M = np; G.g.N = ntau; G.g.K = K; G.g.batch = 1; G.g.kin = std::max(16, (K + 15) / 16 * 16);
+      G.g.sAm = K; G.g.sAkk = 1;
+      G.g.sBkk = ntau; G.g.sBn = 1;
+      G.g.sCm = 4LL * p.rrp; G.g.alpha = 1.0; G.g.beta = 0.0;
+      G.A = p.panel.as<double>() + t.t3base[e.pi * 4 + e.s];
+      G.B = p.Rs.as<double>() + p.rsoff[e.tau];
+      G.C = y + ((long long)t.SP.off[e.pi] * 4 + e.s) * p.rrp + t.ST.off[e.tau];
+      p.yg.push_back(G);
+    }
+    if (!p.yg.empty()) upload(p.ygdev, p.yg.data(), p.yg.size() * sizeof(GemmGroup<double>), st);
+    p.yg_y = y;
+  }
+  if (!p.yg.empty()) gemm_grouped<double>(p.ygdev.as<GemmGroup<double>>(), p.yg, st);
 }
 
 }  // namespace tt

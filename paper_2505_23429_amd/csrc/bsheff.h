@@ -125,4 +125,22 @@ void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2
 // (the caller then uses the dense update).
 bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, const Core& ket, double* out);
 
+// ---------------------------------------------------------------------------
+// One-site effective-Hamiltonian product (eq. mat_vec, one-site form, FP64):
+//   y[a'][s'][b'] = sum L[A][a'][a] W[A,s',s,B] x[a][s][b] R[B][b'][b]
+// through stage 1 and the mix of the left update (ket = x), then one GEMM per
+// (left sector, s') against the right environment stacked per right sector.
+// use: the left-update tables of the site (virtual input channels at a block site,
+// whose L then carries them); ql/qr: bond labels of x (grouped by charge);
+// R: [RB][rrp][rrp], read once by the build.  x, y: [rlp][4][rrp]; y is overwritten.
+// ---------------------------------------------------------------------------
+struct BsHeff1Impl;
+struct BsHeff1 {
+  std::shared_ptr<BsHeff1Impl> p;
+  double flops = 0.0;  // block-sparse flops of the two contractions of one product
+};
+bool bs_heff1_build(Engine& E, BsHeff1& h, std::shared_ptr<BsSiteUse> use, const Labels& ql, const Labels& qr, int RAx,
+                    const double* R, int RB);
+void bs_heff1_apply(Engine& E, BsHeff1& h, const double* Lx, const double* x, double* y);
+
 }  // namespace tt

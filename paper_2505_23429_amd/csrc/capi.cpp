@@ -151,6 +151,8 @@ void tt_default_opts(tt_opts* o) {
   o->dev_alloc = nullptr;
   o->dev_free = nullptr;
   o->alloc_user = nullptr;
+  o->coarse_k = 1;
+  o->one_site = 0;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -159,7 +161,9 @@ int tt_create(const tt_opts* opts, void** out) {
   if (opts->chi_max <= 0 || opts->dav_maxiter <= 0 || opts->dav_maxsub < 4 || opts->matvec_prec < 0 ||
       opts->matvec_prec > 2 || opts->sub_workers < 0 || opts->sub_workers > TT_MAX_SUB ||
       opts->mix_stage < 0 || opts->mix_stage > 2 || opts->svd_lds < 0 || opts->svd_lds > 1 ||
-      opts->worker_alloc_limit < 0 || (!opts->dev_alloc) != (!opts->dev_free))
+      opts->worker_alloc_limit < 0 || (!opts->dev_alloc) != (!opts->dev_free) || opts->coarse_k < 1 ||
+      opts->coarse_k > 8 || opts->one_site < 0 || opts->one_site > 1 ||
+      (opts->one_site && (opts->matvec_prec != TT_F64 || !opts->qn_skip)))
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);
@@ -247,9 +251,10 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
     out->E_before = E.energy();
     auto t1 = std::chrono::steady_clock::now();
     E.local_solve(nsub, lengths, out->E_local, out->matvecs);
-    for (int j = 0; j < nsub; ++j) out->matvecs_f64[j] = E.subs[j].matvecs64;
+    for (int j = 0; j < nsub; ++j) out->matvecs_f64[j] = E.subs[E.sub_base[j]].matvecs64;
     auto t2 = std::chrono::steady_clock::now();
-    const int n = nsub + 1;
+    const int n = (int)E.subs.size() + 1;
+    out->nstates = n;
     std::vector<double> S((size_t)n * n), A((size_t)n * n);
     int st = E.coarse_correct(S.data(), A.data(), out->coef, &out->lambda, &out->E_after, &out->rankS,
                               &out->discarded);

@@ -500,7 +500,7 @@ Engine::~Engine() {
 }
 
 void Engine::release_workspaces() {
-  for (DevMem* m : {&ws0, &ws1, &ws2, &ws3, &wsd, &wsp, &dav_V, &dav_AV, &dav_t, &dav_u, &dav_Au, &dav_c, &dav_mask, &dav_xd, &dav_yd, &dav_dc,
+  for (DevMem* m : {&ws0, &ws1, &ws2, &ws3, &wsd, &wsp, &dav_V, &dav_AV, &dav_t, &dav_u, &dav_Au, &dav_c, &dav_mask, &dav_xd, &dav_yd, &dav_dc, &dav_uk, &dav_tk,
                     &dav_t2, &dav_t3, &wlow_x, &wlow_y, &wlow_L, &wlow_R, &wlow_Rt, &envq_o, &envq_i, &bs_t1, &bs_t2,
                     &bs_t3, &bs_part, &bs_tmp, &bs_gg1, &bs_gg2, &be_t1, &be_panel, &be_up, &be_tmp})
     m->release();
@@ -1042,6 +1042,24 @@ void Engine::env_unit(Env& e, int R) {
   HC(hipStreamSynchronize(stream));
 }
 
+// block-sparse left-update tables of a site (inputs: the channels of the left bond, then
+// at a coefficient-block site the virtual channels standing for its block outputs);
+// built once per MPO under the problem's mutex and shared by all engines
+std::shared_ptr<BsSiteUse> Engine::left_site_use(int site) {
+  SiteMPO& sm = mpo[site];
+  std::lock_guard<std::mutex> g(prob->mu);
+  if (!sm.bs_left) {
+    std::vector<Q2> din(chan_q[site].begin(), chan_q[site].end());
+    if (sm.has_block)
+      for (int q = sm.q0; q < sm.q1; ++q) din.push_back(chan_q[site + 1][q]);
+    std::vector<Q2> dout(chan_q[site + 1].begin(), chan_q[site + 1].end());
+    auto u = std::make_shared<BsSiteUse>();
+    bs_site_use(*this, *u, sm.has_block ? sm.byB_left : sm.byB, din, dout, +1);
+    sm.bs_left = u;
+  }
+  return sm.bs_left;
+}
+
 void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site, Env& out) {
   const SiteMPO& s = mpo[site];
   if (in.R != s.Rl || in.rb != bra.rl || in.rk != ket.rl) throw std::runtime_error("env_left: shape mismatch");
@@ -1059,21 +1077,7 @@ void Engine::env_left(const Env& in, const Core& bra, const Core& ket, int site,
   }
   if (opts.qn_skip) {
     // block-sparse update (coefficient block handled through virtual input channels)
-    SiteMPO& sm = mpo[site];
-    std::shared_ptr<BsSiteUse> use;
-    {
-      std::lock_guard<std::mutex> g(prob->mu);
-      if (!sm.bs_left) {
-        std::vector<Q2> din(chan_q[site].begin(), chan_q[site].end());
-        if (sm.has_block)
-          for (int q = sm.q0; q < sm.q1; ++q) din.push_back(chan_q[site + 1][q]);
-        std::vector<Q2> dout(chan_q[site + 1].begin(), chan_q[site + 1].end());
-        auto u = std::make_shared<BsSiteUse>();
-        bs_site_use(*this, *u, sm.has_block ? sm.byB_left : sm.byB, din, dout, +1);
-        sm.bs_left = u;
-      }
-      use = sm.bs_left;
-    }
+    std::shared_ptr<BsSiteUse> use = left_site_use(site);
     const double* Ein = in.d.as<double>();
     if (s.has_block) {
       const long long slab = (long long)rb * rk;
@@ -1953,6 +1957,9 @@ struct Window {
   WinTabs tabs;           // structural-zero tables of the quantum-number blocks (dense product)
   bool use_bs = false;
   BsPlan bs;              // block-sparse product plan
+  int nphys = 16;         // local states of the window: 16 (two sites) or 4 (one site)
+  bool one = false;       // one-site window (FP64 block-sparse product bs1, L in Lx, R in R64)
+  BsHeff1 bs1;
 };
 
 // diag[a][s1][s2][b] = sum_B (sum_A W1[A,s1,s1,B] L_A[a][a]) (sum_C W2[B,s2,s2,C] R_C[b][b])
@@ -2226,7 +2233,10 @@ static void window_matvec(Engine& E, Window& w, const double* x, double* y, int 
   E.cur_rl = w.rl; E.cur_rr = w.rr; E.cur_RA = w.RA; E.cur_RC = w.RC;
   const WinTabs* tabs = w.use_tabs ? &w.tabs : nullptr;
   HC(hipEventRecord(E.ev0, E.stream));
-  if (w.use_bs) {
+  if (w.one) {
+    if (prec != TT_F64) throw std::logic_error("one-site products run in FP64 only");
+    bs_heff1_apply(E, w.bs1, w.Lx.as<double>(), x, y);
+  } else if (w.use_bs) {
     if (prec == TT_F64) {
       bs_apply<double>(E, w.bs, w.Lx.as<double>(), w.R64, w.nP ? w.Rt.as<double>() : nullptr, x, y, false);
     } else {
@@ -2309,10 +2319,15 @@ static QnIndex build_index(Engine& E, int rl, const Labels& ql, int rr, const La
 // product, and the next two Ritz vectors as correction directions.  The exact residual
 // of the first basis vector is the only convergence test.  Each cycle thus gains about
 // three digits for one FP64 product.
+//
+// nroots > 1 (Extension One): the nroots lowest eigenpairs, all to tol; the basis grows
+// by the preconditioned residual of the lowest unconverged one; roots 1.. are written
+// (dense, unit) to *extra.
 static Davidson davidson(Engine& E, Window& w, const QnIndex& qi, double* x, int prec, double tol, int maxiter,
-                         double rel_tol = 0.0, bool stop_on_stall = false, bool anchor = false) {
+                         double rel_tol = 0.0, bool stop_on_stall = false, bool anchor = false, int nroots = 1,
+                         std::vector<DevMem>* extra = nullptr) {
   Davidson res;
-  const size_t nd = (size_t)w.rlp * 16 * w.rrp;  // dense tensor
+  const size_t nd = (size_t)w.rlp * w.nphys * w.rrp;  // dense tensor
   const size_t n = qi.ncp;                        // compressed vectors
   const int* idx = qi.idx.as<int>();
   const int maxsub = std::max(4, std::min(E.opts.dav_maxsub, 64));
@@ -2445,6 +2460,42 @@ static Davidson davidson(Engine& E, Window& w, const QnIndex& qi, double* x, int
     axpby(t, 1.0, Au, -res.theta, u, n, E.stream);
     res.resid = norm_dev(E, t, n);
     res.iters = it + 1;
+    double theta_x = res.theta;  // the shift of the next direction's preconditioner
+    bool roots_done = false;
+    if (nroots > 1) {
+      // residuals of the nroots lowest Ritz pairs; t becomes that of the lowest
+      // unconverged one
+      const int nr = std::min(nroots, m);
+      E.dav_uk.ensure(sizeof(double) * n * nroots);
+      E.dav_tk.ensure(sizeof(double) * n);
+      double* tk = E.dav_tk.as<double>();
+      int pick = res.resid > tol ? 0 : -1;
+      double rmax = res.resid;
+      HC(hipMemcpyAsync(E.dav_uk.p, u, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+      for (int q = 1; q < nr; ++q) {
+        std::vector<double> cq(m);
+        for (int i = 0; i < m; ++i) cq[i] = evecs[(size_t)i * m + q];
+        double* uq = E.dav_uk.as<double>() + (size_t)q * n;
+        lcomb(V, m, cq, uq);
+        lcomb(AV, m, cq, tk);
+        axpby(tk, 1.0, tk, -evals[q], uq, n, E.stream);
+        const double rq = norm_dev(E, tk, n);
+        rmax = std::max(rmax, rq);
+        if (rq > tol && pick < 0) {
+          pick = q;
+          theta_x = evals[q];
+          HC(hipMemcpyAsync(t, tk, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+        }
+      }
+      roots_done = nr == nroots && pick < 0;
+      if (pick < 0 && nr < nroots) {
+        // fewer basis vectors than roots, all of them converged: grow from the last one
+        pick = nr - 1;
+        theta_x = evals[pick];
+        if (pick > 0) HC(hipMemcpyAsync(t, tk, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+      }
+      res.resid = rmax;
+    }
     if (anchor) {
       if (fresh) {
         fresh = false;
@@ -2474,7 +2525,7 @@ static Davidson davidson(Engine& E, Window& w, const QnIndex& qi, double* x, int
         }
       }
     } else {
-      if (res.resid <= std::max(tol, rel_tol * std::fabs(res.theta))) {
+      if (nroots > 1 ? roots_done : res.resid <= std::max(tol, rel_tol * std::fabs(res.theta))) {
         res.converged = true;
         break;
       }
@@ -2490,7 +2541,7 @@ static Davidson davidson(Engine& E, Window& w, const QnIndex& qi, double* x, int
     if (res.matvecs >= maxiter) break;
     if (m >= maxsub) {
       // thick restart: keep the lowest Ritz vectors of the current subspace
-      const int keep = std::min(3, m);
+      const int keep = std::min(std::max(3, nroots + 2), m);
       E.dav_t2.ensure(sizeof(double) * n * keep);
       E.dav_t3.ensure(sizeof(double) * n * keep);
       for (int q = 0; q < keep; ++q) {
@@ -2512,7 +2563,7 @@ static Davidson davidson(Engine& E, Window& w, const QnIndex& qi, double* x, int
     // The direction is formed in its basis slot V_m, so one multi-dot over V_0..V_m
     // gives the projections and the squared norm together.
     double* vm = V + (size_t)m * n;
-    precond(vm, t, dg, res.theta, nullptr, n, E.stream);
+    precond(vm, t, dg, theta_x, nullptr, n, E.stream);
     std::vector<double> d;
     dots(V, m + 1, vm, d);
     const double tn0 = std::sqrt(std::max(d[m], 0.0));
@@ -2561,12 +2612,29 @@ static Davidson davidson(Engine& E, Window& w, const QnIndex& qi, double* x, int
   scale(u, 1.0 / nu, n, E.stream);
   fill(x, sizeof(double) * nd, E.stream);
   scatter_idx(x, u, idx, qi.nc, E.stream);
+  if (nroots > 1 && extra) {
+    extra->resize(nroots - 1);
+    for (int q = 1; q < nroots; ++q) {
+      DevMem& X = (*extra)[q - 1];
+      X.ensure(sizeof(double) * nd);
+      fill(X.p, sizeof(double) * nd, E.stream);
+      if (q < m) {
+        double* uq = E.dav_uk.as<double>() + (size_t)q * n;
+        const double nq = norm_dev(E, uq, n);
+        scale(uq, 1.0 / nq, n, E.stream);
+        scatter_idx(X.as<double>(), uq, idx, qi.nc, E.stream);
+      }
+    }
+  }
   HC(hipStreamSynchronize(E.stream));
   return res;
 }
 
 // one micro-iteration: lowest eigenpair of the window; returns theta
-static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem& x, const Core& C, const Core& D) {
+// With more != nullptr and coarse_k > 1 (Extension One), the coarse_k lowest eigenpairs
+// with FP64 products; roots 1.. go to *more (as many as the local space allows).
+static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem& x, const Core& C, const Core& D,
+                          std::vector<DevMem>* more = nullptr) {
   const Labels& ql = C.ql;
   const Labels& qr = D.qr;
   QnIndex mask = build_index(E, C.rl, ql, D.rr, qr);
@@ -2574,6 +2642,16 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
   const int prec = E.opts.matvec_prec;
   Davidson r;
   double tph = E.now();
+  if (more && E.opts.coarse_k > 1) {
+    const int K = (int)std::min<size_t>(E.opts.coarse_k, mask.nc);
+    prepare_window(E, w, Le, b, Re, TT_F64, ql, qr);
+    E.ph[2] += E.now() - tph;
+    tph = E.now();
+    r = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter, 0.0, false, false, K, more);
+    E.ph[3] += E.now() - tph;
+    if (!r.converged) E.warn = std::max(E.warn, (int)TT_WNOCONV);
+    return r;
+  }
   if (prec != TT_F64) {
     prepare_window(E, w, Le, b, Re, prec, ql, qr);
     E.ph[2] += E.now() - tph;
@@ -2625,6 +2703,97 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
 }
 
 // ---------------------------------------------------------------------------
+// one-site local problems (Algorithm 2, one-site branch)
+// ---------------------------------------------------------------------------
+
+// The quantum-number-allowed entries q(a) + q(s) = q(b) of a core, in the padded
+// layout [rlp][4][rrp] (as build_index for two-site tensors).
+static QnIndex build_index1(Engine& E, int rl, const Labels& ql, int rr, const Labels& qr) {
+  const int rrp = padr(rr);
+  std::vector<int> idx;
+  for (int a = 0; a < rl; ++a)
+    for (int s = 0; s < 4; ++s) {
+      const Q2 q = qadd(ql[a], SITE_Q[s]);
+      for (int b = 0; b < rr; ++b)
+        if (qr[b] == q) idx.push_back((int)(((size_t)a * 4 + s) * rrp + b));
+    }
+  QnIndex r;
+  r.nc = idx.size();
+  r.ncp = std::max<size_t>(256, (r.nc + 255) / 256 * 256);
+  if (idx.empty()) idx.push_back(0);
+  upload(r.idx, idx.data(), idx.size() * sizeof(int), E.stream);
+  return r;
+}
+
+// diag[a][s][b] = sum_B (sum_A W[A,s,s,B] L_A[a][a]) R_B[b][b]
+static void window_diag1(Engine& E, Window& w, const Env& Le, int k, const Env& Re) {
+  const SiteMPO& sm = E.mpo[k];
+  DevMem Ld, Rd, LW;
+  Ld.ensure(sizeof(double) * (size_t)sm.Rl * w.rlp);
+  Rd.ensure(sizeof(double) * (size_t)sm.Rr * w.rrp);
+  LW.ensure(sizeof(double) * (size_t)sm.Rr * 4 * w.rlp);
+  diag_extract(Le.d.as<double>(), sm.Rl, w.rlp, Ld.as<double>(), E.stream);
+  diag_extract(Re.d.as<double>(), sm.Rr, w.rrp, Rd.as<double>(), E.stream);
+  diag_mix(sm.Rr, sm.byB.ptr.as<int>(), sm.byB.src.as<int>(), sm.byB.op64.as<double>(), Ld.as<double>(), w.rlp,
+           LW.as<double>(), true, E.stream);
+  w.diag.ensure(sizeof(double) * (size_t)w.rlp * 4 * w.rrp);
+  GemmArgs g{};
+  g.M = 4 * w.rlp; g.N = w.rrp; g.K = sm.Rr; g.batch = 1; g.kin = kin16(sm.Rr);
+  g.sAm = 1; g.sAkk = 4LL * w.rlp; g.sBkk = w.rrp; g.sBn = 1; g.sCm = w.rrp; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, LW.as<double>(), Rd.as<double>(), w.diag.as<double>(), false, true, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+}
+
+// One-site window of site k: Le at bond k, Re at bond k + 1 (FP64).
+static void prepare_window1(Engine& E, Window& w, const Env& Le, int k, const Env& Re, const Labels& ql,
+                            const Labels& qr) {
+  const SiteMPO& sm = E.mpo[k];
+  w.one = true;
+  w.nphys = 4;
+  w.rl = Le.rb; w.rr = Re.rb;
+  w.rlp = padr(w.rl); w.rrp = padr(w.rr);
+  if ((int)ql.size() != w.rl || (int)qr.size() != w.rr) throw std::runtime_error("one-site window: label mismatch");
+  w.RA = sm.Rl; w.RB = sm.Rr; w.RC = sm.Rr;
+  const long long sl = (long long)w.rlp * w.rlp;
+  w.RAx = w.RA + (sm.has_block ? sm.q1 - sm.q0 : 0);
+  w.Lx.ensure(sizeof(double) * sl * w.RAx);
+  HC(hipMemcpyAsync(w.Lx.p, Le.d.p, sizeof(double) * sl * w.RA, hipMemcpyDeviceToDevice, E.stream));
+  if (sm.has_block)
+    channel_transform_qn(E, sm, Le.d.as<double>() + (long long)sm.p0 * sl, sl, w.Lx.as<double>() + (long long)w.RA * sl,
+                         sm.q1 - sm.q0, ql, ql, w.rlp, false);
+  w.R64 = Re.d.as<double>();
+  w.prec = TT_F64;
+  if (!bs_heff1_build(E, w.bs1, E.left_site_use(k), ql, qr, w.RAx, w.R64, w.RB))
+    throw std::runtime_error("one-site product: bond labels are not grouped by charge");
+  // dense-bond algorithmic flops of one product (both contractions, true sizes)
+  w.flops = 2.0 * 4.0 * w.rl * w.rr * ((double)w.RA * w.rl + (double)w.RB * w.rr);
+  window_diag1(E, w, Le, k, Re);
+}
+
+// one-site micro-iteration at site k: lowest eigenpair of the one-site window (FP64
+// products), warm-started from x; with more != nullptr and coarse_k > 1 the coarse_k
+// lowest (Extension One), roots 1.. into *more.
+static Davidson local_eig1(Engine& E, const Env& Le, int k, const Env& Re, DevMem& x, const Core& C,
+                           std::vector<DevMem>* more = nullptr) {
+  QnIndex mask = build_index1(E, C.rl, C.ql, C.rr, C.qr);
+  Window w;
+  double tph = E.now();
+  prepare_window1(E, w, Le, k, Re, C.ql, C.qr);
+  E.ph[2] += E.now() - tph;
+  tph = E.now();
+  Davidson r;
+  if (more && E.opts.coarse_k > 1) {
+    const int K = (int)std::min<size_t>(E.opts.coarse_k, mask.nc);
+    r = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter, 0.0, false, false, K, more);
+  } else {
+    r = davidson(E, w, mask, x.as<double>(), TT_F64, E.opts.dav_tol, E.opts.dav_maxiter);
+  }
+  E.ph[3] += E.now() - tph;
+  if (!r.converged) E.warn = std::max(E.warn, (int)TT_WNOCONV);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
 // Step 1 + Step 2
 // ---------------------------------------------------------------------------
 void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
@@ -2656,7 +2825,9 @@ void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
   for (int b = s; b <= blast; ++b) {
     const Core& next = src.Vc[b + 1];
     two_site(*this, center, next, x);
-    Davidson r = local_eig(*this, *Lcur, b, src.Renv[b + 2], x, center, next);
+    std::vector<DevMem> more;
+    Davidson r = local_eig(*this, *Lcur, b, src.Renv[b + 2], x, center, next,
+                           b == blast && opts.coarse_k > 1 ? &more : nullptr);
     S.matvecs += r.matvecs;
     S.matvecs64 += r.matvecs64;
     S.E = r.theta;
@@ -2664,6 +2835,27 @@ void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
     Core N, C;
     tph = now();
     split_two_site(*this, x.as<double>(), center.rl, center.ql, next.rr, next.qr, opts.chi_max, true, N, C);
+    // Extension One: every further eigenvector of the last micro-step gives an update of
+    // its own, sharing cores s..b-1 with this one
+    for (size_t q = 0; q < more.size(); ++q) {
+      Sub A;
+      A.s = S.s;
+      A.t = S.t;
+      for (const Core& m0 : S.mod) {
+        Core cp;
+        cp.rl = m0.rl; cp.rr = m0.rr; cp.ql = m0.ql; cp.qr = m0.qr;
+        cp.d.ensure(m0.d.n);
+        HC(hipMemcpyAsync(cp.d.p, m0.d.p, m0.d.n, hipMemcpyDeviceToDevice, stream));
+        A.mod.push_back(std::move(cp));
+      }
+      Core Nq, Cq;
+      split_two_site(*this, more[q].as<double>(), center.rl, center.ql, next.rr, next.qr, opts.chi_max, true, Nq, Cq);
+      const double nc = norm_dev(*this, Cq.d.as<double>(), Cq.elems());
+      scale(Cq.d.as<double>(), 1.0 / nc, Cq.elems(), stream);
+      A.mod.push_back(std::move(Nq));
+      A.mod.push_back(std::move(Cq));
+      S.alt.push_back(std::move(A));
+    }
     ph[4] += now() - tph;
     if (b < blast) {
       tph = now();
@@ -2685,6 +2877,77 @@ void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
     std::fprintf(stderr,
                  "[tt] subdomain %d sites %d..%d: E=%.10f matvecs=%d | products %.2fs, set-up %.2fs, Davidson "
                  "%.2fs, splits %.2fs, env %.2fs\n",
+                 j, s, e, S.E, S.matvecs, sec_heff, ph[2], ph[3], ph[4], ph[5]);
+}
+
+// One-site subdomain sweep (Algorithm 2, one-site branch, with the subdomains of
+// Extension Two): starting from the s-orthogonal copy of the iterate, the micro-step at
+// site k replaces the centre core by the lowest eigenvector of its one-site problem; for
+// k < e a charge-block QR of it gives the left-orthogonal core N_k and moves the
+// centre into site k + 1 (R V_{k+1}).  The update is (U.., N_s..N_{e-1}, C_e, V..), C_e
+// of unit norm; bond dimensions are those of the iterate.
+void Engine::solve_subdomain1(const Engine& src, int j, int s, int e, Sub& S) {
+  double tph = 0.0;
+  S = Sub();
+  S.s = s;
+  S.t = e;
+  auto copy_core = [&](const Core& a, Core& b) {
+    b.rl = a.rl; b.rr = a.rr; b.ql = a.ql; b.qr = a.qr;
+    b.d.ensure(a.d.n);
+    HC(hipMemcpyAsync(b.d.p, a.d.p, a.d.n, hipMemcpyDeviceToDevice, stream));
+  };
+  Core center;
+  copy_core(src.Wc[s], center);
+  Env Lrun;
+  const Env* Lcur = &src.Lenv[s];
+  for (int k = s; k <= e; ++k) {
+    std::vector<DevMem> more;
+    Davidson r = local_eig1(*this, *Lcur, k, src.Renv[k + 1], center.d, center,
+                            k == e && opts.coarse_k > 1 ? &more : nullptr);
+    S.matvecs += r.matvecs;
+    S.matvecs64 += r.matvecs64;
+    S.E = r.theta;
+    S.converged = S.converged && r.converged;
+    if (k < e) {
+      tph = now();
+      Core next;
+      copy_core(src.Vc[k + 1], next);
+      qr_left(*this, center, next);
+      ph[4] += now() - tph;
+      tph = now();
+      Env nl;
+      env_left(*Lcur, center, center, k, nl);
+      Lrun = std::move(nl);
+      Lcur = &Lrun;
+      ph[5] += now() - tph;
+      S.mod.push_back(std::move(center));
+      center = std::move(next);
+    } else {
+      // Extension One: every further eigenvector of the last micro-step gives an update
+      // of its own, sharing cores s..e-1 with this one
+      for (size_t q = 0; q < more.size(); ++q) {
+        Sub A;
+        A.s = S.s;
+        A.t = S.t;
+        for (const Core& m0 : S.mod) {
+          Core cp;
+          copy_core(m0, cp);
+          A.mod.push_back(std::move(cp));
+        }
+        Core Cq;
+        Cq.rl = center.rl; Cq.rr = center.rr; Cq.ql = center.ql; Cq.qr = center.qr;
+        Cq.d = std::move(more[q]);
+        A.mod.push_back(std::move(Cq));
+        S.alt.push_back(std::move(A));
+      }
+      S.mod.push_back(std::move(center));
+    }
+  }
+  HC(hipStreamSynchronize(stream));
+  if (verbose)
+    std::fprintf(stderr,
+                 "[tt] one-site subdomain %d sites %d..%d: E=%.10f matvecs=%d | products %.2fs, set-up %.2fs, "
+                 "Davidson %.2fs, QR %.2fs, env %.2fs\n",
                  j, s, e, S.E, S.matvecs, sec_heff, ph[2], ph[3], ph[4], ph[5]);
 }
 
@@ -2809,6 +3072,8 @@ void Engine::run_tasks(int ntask, const std::vector<double>& cost, const std::fu
 void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   if (!have_mpo || !have_mps) throw std::logic_error("local_solve needs the MPO and the TT iterate");
   if (nsub <= 0 || nsub > TT_MAX_SUB) throw std::invalid_argument("bad number of subdomains");
+  if ((long long)nsub * opts.coarse_k > TT_MAX_SUB)
+    throw std::invalid_argument("nsub * coarse_k exceeds the coarse-space limit TT_MAX_SUB");
   int tot = 0;
   for (int j = 0; j < nsub; ++j) {
     if (lengths[j] <= 0) throw std::invalid_argument("subdomain lengths must be positive");
@@ -2873,7 +3138,10 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
     HC(hipStreamSynchronize(stream));
   }
   env_unit(Renv[L], 1);
-  for (int k = L - 1; k >= 2; --k) env_right(Renv[k + 1], Vc[k], Vc[k], k, Renv[k]);
+  // a one-site problem at site k reads Renv[k + 1] (k >= 0), a two-site one at bond
+  // (b, b + 1) Renv[b + 2]
+  const int kmin = opts.one_site ? 1 : 2;
+  for (int k = L - 1; k >= kmin; --k) env_right(Renv[k + 1], Vc[k], Vc[k], k, Renv[k]);
   ph[1] += now() - tph;
   if (verbose)
     std::fprintf(stderr, "[tt] step 1 done: LQ sweep %.2fs, environments %.2fs\n", ph[0], ph[1]);
@@ -2897,13 +3165,25 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
       cost[j] += rl * rr * (rl + rr);
     }
   run_tasks(nsub, cost, [&](Engine& W, int j) {
-    W.solve_subdomain(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
+    if (opts.one_site) W.solve_subdomain1(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
+    else W.solve_subdomain(*this, j, first[j], first[j] + lengths[j] - 1, subs[j]);
   });
   ph[8] += now() - t2;
   for (int j = 0; j < nsub; ++j) {
     if (Eloc) Eloc[j] = subs[j].E;
     if (mv) mv[j] = subs[j].matvecs;
   }
+  // coarse states in subdomain order, each subdomain's lowest update first
+  std::vector<Sub> states;
+  sub_base.assign(nsub, 0);
+  for (int j = 0; j < nsub; ++j) {
+    sub_base[j] = (int)states.size();
+    std::vector<Sub> alt = std::move(subs[j].alt);
+    subs[j].alt.clear();
+    states.push_back(std::move(subs[j]));
+    for (Sub& a : alt) states.push_back(std::move(a));
+  }
+  subs = std::move(states);
   have_local = true;
 }
 
@@ -3036,9 +3316,16 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
         cS = std::move(tS);
       }
       // branch: sites s_j..t_j with ket = Ũ^j
-      Env bH, bS;
+      Env bH, bS, s0;
       const Env* pH = &cH;
       const Env* pS = &cS;
+      if (first) {
+        // Ũ^j starts at the same site as Ũ^i (an alternative update of the same
+        // subdomain): the branch starts from the cached environment there
+        pH = &Lenv[Si.s];
+        overlap_start(W, core_of(*this, i, Sj.s, true).rl, Sj.mod[0].rl, s0);
+        pS = &s0;
+      }
       for (int kk = Sj.s; kk <= Sj.t; ++kk) {
         const Core& bra = core_of(*this, i, kk, true);
         const Core& ket = Sj.mod[kk - Sj.s];
@@ -3119,11 +3406,19 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   if (rank) *rank = p;
 
   // ---- Step 4: block TT of sum_j c_j Ũ^j and TT rounding ----
-  // bond k (1..L-1) blocks: U (r_k), V (r_k, if some subdomain ended before site k), straddle (one subdomain)
+  // bond k (1..L-1) blocks: U (r_k), V (r_k, if some state ended before site k), and one
+  // block per state that straddles the bond (several when Extension One keeps more than
+  // one update of a subdomain)
   struct BondLayout {
-    int offU = -1, offV = -1, offS = -1, sub = -1, dim = 0;
-    int rU = 0, rV = 0, rS = 0;
+    int offU = -1, offV = -1, dim = 0;
+    int rU = 0, rV = 0;
+    std::vector<std::pair<int, int>> str;  // (state j, block offset)
     Labels q;
+    int off_of(int j) const {
+      for (const auto& p : str)
+        if (p.first == j) return p.second;
+      return -1;
+    }
   };
   std::vector<BondLayout> bl(L + 1);
   bl[0].dim = 1;
@@ -3145,63 +3440,72 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
     for (int j = 1; j <= P; ++j) {
       const Sub& Sj = subs[j - 1];
       if (Sj.s <= k - 1 && k <= Sj.t) {
-        B.sub = j;
-        B.offS = d;
-        B.rS = Sj.mod[k - Sj.s].rl;
-        d += B.rS;
+        B.str.push_back({j, d});
+        d += Sj.mod[k - Sj.s].rl;
         B.q.insert(B.q.end(), Sj.mod[k - Sj.s].ql.begin(), Sj.mod[k - Sj.s].ql.end());
       }
     }
     B.dim = d;
   }
+  // A two-site subdomain that starts at the last site has no bond of its own and leaves
+  // the iterate unchanged (its core is the iterate's), so its coefficient adds to c_0; a
+  // one-site update of the last site is a state of its own.
   double c0 = c[0];
-  for (int j = 1; j <= P; ++j)
-    if (subs[j - 1].s == L - 1) c0 += c[j];
+  if (!opts.one_site)
+    for (int j = 1; j <= P; ++j)
+      if (subs[j - 1].s == L - 1) c0 += c[j];
   std::vector<Core> T(L);
   for (int k = 0; k < L; ++k) {
     Core& C = T[k];
     C.rl = bl[k].dim; C.rr = bl[k + 1].dim; C.ql = bl[k].q; C.qr = bl[k + 1].q;
     C.d.resize_zero(sizeof(double) * C.elems(), stream);
     const int Crrp = C.rrp();
-    auto put = [&](const Core& src, int row_off, int col_off, double alpha) {
-      // C[row_off + a][s][col_off + b] = alpha * src[a][s][b]
+    auto put = [&](const Core& src, int row_off, int col_off, double alpha, bool acc = false) {
+      // C[row_off + a][s][col_off + b] = alpha * src[a][s][b]  (acc: +=, where several
+      // one-site updates of the same site close into the same block)
       double* dst = C.d.as<double>() + (long long)row_off * 4 * Crrp + col_off;
-      copy3d(src.d.as<double>(), 4LL * src.rrp(), src.rrp(), dst, 4LL * Crrp, Crrp, src.rl, 4, src.rr, alpha, stream);
+      copy3d(src.d.as<double>(), 4LL * src.rrp(), src.rrp(), dst, 4LL * Crrp, Crrp, src.rl, 4, src.rr, alpha, stream,
+             acc);
     };
     const BondLayout& Bl = bl[k];
     const BondLayout& Br = bl[k + 1];
     if (k == 0) {
       put(U[0], 0, (k + 1 < L) ? Br.offU : 0, (k + 1 < L) ? 1.0 : c0);
-      if (k + 1 < L) {
-        const Sub& S1 = subs[0];
-        if (S1.s == 0) {
-          if (S1.t == 0) put(S1.mod[0], 0, Br.offV >= 0 ? Br.offV : 0, c[1]);
-          else put(S1.mod[0], 0, Br.offS, 1.0);
+      if (k + 1 < L)
+        for (int j = 1; j <= P; ++j) {
+          const Sub& Sj = subs[j - 1];
+          if (Sj.s != 0) continue;
+          if (Sj.t == 0) put(Sj.mod[0], 0, Br.offV >= 0 ? Br.offV : 0, c[j], true);
+          else put(Sj.mod[0], 0, Br.off_of(j), 1.0);
         }
-      }
       continue;
     }
     if (k == L - 1) {
       put(U[L - 1], Bl.offU, 0, c0);
       if (Bl.offV >= 0) put(Vc[L - 1], Bl.offV, 0, 1.0);
-      if (Bl.sub >= 1) {
-        const Sub& Sj = subs[Bl.sub - 1];
-        put(Sj.mod[k - Sj.s], Bl.offS, 0, c[Bl.sub]);
+      for (const auto& p : Bl.str) {
+        const Sub& Sj = subs[p.first - 1];
+        put(Sj.mod[k - Sj.s], p.second, 0, c[p.first]);
       }
+      if (opts.one_site)
+        for (int j = 1; j <= P; ++j)
+          if (subs[j - 1].s == L - 1) put(subs[j - 1].mod[0], Bl.offU, 0, c[j], true);
       continue;
     }
     // interior site
     put(U[k], Bl.offU, Br.offU, 1.0);
     if (Bl.offV >= 0) put(Vc[k], Bl.offV, Br.offV, 1.0);
-    if (Bl.sub >= 1) {
-      const Sub& Sj = subs[Bl.sub - 1];
+    for (const auto& p : Bl.str) {
+      const Sub& Sj = subs[p.first - 1];
       const Core& mc = Sj.mod[k - Sj.s];
-      if (k < Sj.t) put(mc, Bl.offS, Br.offS, 1.0);
-      else put(mc, Bl.offS, Br.offV, c[Bl.sub]);  // k == t_j : close into the V chain
+      if (k < Sj.t) put(mc, p.second, Br.off_of(p.first), 1.0);
+      else put(mc, p.second, Br.offV, c[p.first]);  // k == t_j : close into the V chain
     }
     for (int j = 1; j <= P; ++j) {
       const Sub& Sj = subs[j - 1];
-      if (Sj.s == k) put(Sj.mod[0], Bl.offU, Br.offS, 1.0);
+      if (Sj.s != k) continue;
+      if (Sj.t > k) put(Sj.mod[0], Bl.offU, Br.off_of(j), 1.0);
+      else put(Sj.mod[0], Bl.offU, Br.offV, c[j], true);  // a one-site update of site k alone
     }
   }
   HC(hipStreamSynchronize(stream));

@@ -185,8 +185,12 @@ class Engine {
     double E = 0.0;
     int matvecs = 0, matvecs64 = 0;
     bool converged = true;
+    // Extension One: the updates of the same subdomain from its next-lowest local
+    // eigenvectors (cores s..t, sharing all but the last two with this one)
+    std::vector<Sub> alt;
   };
-  std::vector<Sub> subs;
+  std::vector<Sub> subs;                // coarse states 1.. (per subdomain: lowest update, then alternatives)
+  std::vector<int> sub_base;            // per subdomain: index in subs of its lowest update
   bool have_local = false;
   // worker engines of the concurrent subdomain solves (created on first use)
   std::vector<std::unique_ptr<Engine>> workers;
@@ -240,6 +244,8 @@ class Engine {
   // Step 2 for one subdomain (sites s..e): this engine's stream and workspaces,
   // the Step-1 cores and environments of src
   void solve_subdomain(const Engine& src, int j, int s, int e, Sub& S);
+  void solve_subdomain1(const Engine& src, int j, int s, int e, Sub& S);  // one-site micro-steps
+  std::shared_ptr<BsSiteUse> left_site_use(int site);
   void absorb_counters(Engine& w);  // add a worker's counters to this engine's, clear the worker's
   // fn(engine, task) for every task: on this engine in order when one worker is asked
   // for, else on worker engines (host thread + stream each), the costliest tasks first.
@@ -283,6 +289,7 @@ class Engine {
   DevMem ws0, ws1, ws2, ws3, wsd, wsp;
   DevMem dav_V, dav_AV, dav_t, dav_u, dav_Au, dav_c, dav_mask, dav_t2, dav_t3;
   DevMem dav_xd, dav_yd, dav_dc;  // dense product input/output, compressed diagonal
+  DevMem dav_uk, dav_tk;          // several roots: their Ritz vectors, a residual
   DevMem wlow_x, wlow_y, wlow_L, wlow_R, wlow_Rt;
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)

@@ -1216,21 +1216,23 @@ void scatter2d(const double* src, long long sr, long long sc, const int* rows, i
 }
 
 __global__ void copy3d_kernel(const double* src, long long s0, long long s1, double* dst, long long d0, long long d1,
-                              int n0, int n1, int n2, double alpha) {
+                              int n0, int n1, int n2, double alpha, int acc) {
   const long long tot = (long long)n0 * n1 * n2;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(t % n2);
     const long long r = t / n2;
     const int j = (int)(r % n1);
     const int i = (int)(r / n1);
-    dst[i * d0 + j * d1 + k] = alpha * src[i * s0 + j * s1 + k];
+    const double v = alpha * src[i * s0 + j * s1 + k];
+    double* d = dst + (i * d0 + j * d1 + k);
+    *d = acc ? *d + v : v;
   }
 }
 void copy3d(const double* src, long long s0, long long s1, double* dst, long long d0, long long d1, int n0, int n1,
-            int n2, double alpha, hipStream_t s) {
+            int n2, double alpha, hipStream_t s, bool accumulate) {
   if (n0 <= 0 || n1 <= 0 || n2 <= 0) return;
   hipLaunchKernelGGL(copy3d_kernel, dim3(nblocks((size_t)n0 * n1 * n2)), dim3(256), 0, s, src, s0, s1, dst, d0, d1, n0,
-                     n1, n2, alpha);
+                     n1, n2, alpha, accumulate ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 

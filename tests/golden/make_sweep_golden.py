@@ -4,6 +4,8 @@ Run from the repository root:
 
     python tests/golden/make_sweep_golden.py L12_chi160
     python tests/golden/make_sweep_golden.py L16_chi128
+    python tests/golden/make_sweep_golden.py L12_chi160_k2
+    python tests/golden/make_sweep_golden.py L12_chi160_1s
 
 Every value is computed by the environment-chain oracle (``oracle.chain``,
 with the oracle's own MPO ``oracle.mpo``) from the seeded inputs of
@@ -33,12 +35,17 @@ from oracle import chain as CH  # noqa: E402
 from oracle import mpo as OM  # noqa: E402
 from oracle import tt as T  # noqa: E402
 
-# name: (L, integral seed, chi, TT seed, subdomain lengths, Lanczos tolerance)
+# name: (L, integral seed, chi, TT seed, subdomain lengths, Lanczos tolerance, kept local
+# eigenvectors per subdomain (Extension One)[, sites per micro-step (2, or 1: one-site)])
 CASES = {
-    "L12_chi160": (12, 1012, 160, 23, (4, 4, 4), 1e-11),
+    "L12_chi160": (12, 1012, 160, 23, (4, 4, 4), 1e-11, 1),
     # the L = 16 Hamiltonian of the chi = 256 FP64 workload, at chi = 128 (one oracle
     # sweep at chi = 256 takes about half a day on eight cores)
-    "L16_chi128": (16, 1002, 128, 1003, (4, 4, 4, 4), 1e-11),
+    "L16_chi128": (16, 1002, 128, 1003, (4, 4, 4, 4), 1e-11, 1),
+    # Extension One: the two lowest eigenvectors of every subdomain's last micro-step
+    "L12_chi160_k2": (12, 1012, 160, 23, (4, 4, 4), 1e-11, 2),
+    # one-site micro-steps (Algorithm 2, one-site branch)
+    "L12_chi160_1s": (12, 1012, 160, 23, (4, 4, 4), 1e-11, 1, 1),
 }
 
 
@@ -56,7 +63,8 @@ def gauge_fix(S_, A_, c):
 
 
 def run(name):
-    L, seed, chi, mps_seed, lengths, tol = CASES[name]
+    L, seed, chi, mps_seed, lengths, tol, n_eig = CASES[name][:7]
+    sites = CASES[name][7] if len(CASES[name]) > 7 else 2
     t0 = time.time()
     h, B = S.integrals(L, L, seed)
     mpo = OM.build_mpo(h, B)
@@ -66,11 +74,11 @@ def run(name):
     def log(msg):
         print(f"[{time.time() - t0:8.1f}s] {msg}", flush=True)
 
-    rep = CH.a2dmrg_sweep(mpo, oc, labels, chi, lengths, tol=tol, log=log)
+    rep = CH.a2dmrg_sweep(mpo, oc, labels, chi, lengths, tol=tol, log=log, n_eig=n_eig, sites=sites)
     Sg, Ag, cg = gauge_fix(rep.S, rep.A, rep.c)
     out = {
         "case": name, "L": L, "n_elec": L, "two_sz": 0, "integral_seed": seed, "n_factors": L, "chi": chi,
-        "mps_seed": mps_seed, "lengths": list(lengths), "lanczos_tol": tol, "coarse_eps": 1e-8,
+        "mps_seed": mps_seed, "lengths": list(lengths), "lanczos_tol": tol, "coarse_k": n_eig, "sites": sites, "coarse_eps": 1e-8,
         "svd_cutoff": 1e-12, "tie_rel": 1e-10,
         "E_before": rep.E_before, "E_local": list(map(float, rep.E_local)), "oracle_products": rep.matvecs,
         "S": rep.S.tolist(), "A": rep.A.tolist(), "S_gauge": Sg.tolist(), "A_gauge": Ag.tolist(),

@@ -45,7 +45,7 @@ def test_default_options_and_invalid_create():
 @pytest.mark.parametrize("field,value", [
     ("chi_max", 0), ("dav_maxiter", 0), ("dav_maxsub", 3), ("matvec_prec", 3), ("matvec_prec", -1),
     ("sub_workers", -1), ("sub_workers", 65), ("mix_stage", 3), ("mix_stage", -1), ("svd_lds", 2),
-    ("worker_alloc_limit", -1),
+    ("worker_alloc_limit", -1), ("coarse_k", 0), ("coarse_k", 9), ("one_site", 2), ("one_site", -1),
 ])
 def test_create_rejects_each_invalid_option(field, value):
     """tt_create validates the options before it touches the device: every value outside
@@ -56,6 +56,23 @@ def test_create_rejects_each_invalid_option(field, value):
     o = _lib.Opts()
     lib.tt_default_opts(C.byref(o))
     assert (o.mix_stage, o.svd_lds, o.worker_alloc_limit, o.sub_workers) == (0, 1, 0, 0)
+    setattr(o, field, value)
+    h = C.c_void_p()
+    assert lib.tt_create(C.byref(o), C.byref(h)) == _lib.TT_EINVAL
+    assert not h.value
+
+
+@pytest.mark.parametrize("field,value", [("matvec_prec", 1), ("matvec_prec", 2), ("qn_skip", 0)])
+def test_one_site_needs_fp64_block_sparse_products(field, value):
+    """One-site micro-steps run the FP64 block-sparse one-site product only: any other
+    product setting is refused at tt_create (before the device is touched)."""
+    from paper_2505_23429_amd import _lib
+
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.tt_default_opts(C.byref(o))
+    assert (o.one_site, o.coarse_k) == (0, 1)
+    o.one_site = 1
     setattr(o, field, value)
     h = C.c_void_p()
     assert lib.tt_create(C.byref(o), C.byref(h)) == _lib.TT_EINVAL

@@ -249,3 +249,60 @@ def test_chain_a2dmrg_full_rank_single_sweep_exact():
     oc = T.left_orthogonalize(cores, labels)
     rc = CH.a2dmrg_sweep(mpo, oc, labels, 64, (2, 2, 2))
     assert abs(rc.E_new - F.ed_ground(h, B, 6, 0)[0]) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Extension One (the K lowest eigenvectors of every subdomain's last micro-step)
+# ---------------------------------------------------------------------------
+
+def test_several_lowest_eigenpairs_match_dense_solver():
+    """The chain oracle's several-root solver (ARPACK above 400 unknowns) against eigh."""
+    from oracle import chain as CHm
+
+    L, k = 8, 3
+    h, B = S.integrals(L, L, 1008)
+    mpo = OM.build_mpo(h, B)
+    ops = [CHm.site_ops(mpo, i) for i in range(L)]
+    prob = T.Problem(h, B, L, 0)
+    cores, labels = S.random_mps(L, L, 0, 24, 27)
+    cores = T.left_orthogonalize(cores, labels)
+    V, W = T.lq_sweep(cores, labels)
+    cur = cores[:k] + [W[k]] + [V[j] for j in range(k + 1, L)]
+    Le = np.ones((1, 1, 1))
+    for i in range(k):
+        Le = CHm.env_left(Le, cur[i], ops[i], cur[i])
+    Re = np.ones((1, 1, 1))
+    for i in range(L - 1, k + 1, -1):
+        Re = CHm.env_right(Re, cur[i], ops[i], cur[i])
+    x0 = np.einsum("asb,btc->astc", cur[k], cur[k + 1])
+    pairs, _ = CHm.local_solve_k(Le, ops[k], ops[k + 1], Re, x0, labels[k], labels[k + 2], 3)
+    ref = prob.local_solve_k(cur, k, labels[k], labels[k + 2], 3)
+    assert int(T.x_mask(labels[k], labels[k + 2]).sum()) > 400  # the ARPACK branch
+    for (t1, x1), (t2, x2) in zip(pairs, ref):
+        assert abs(t1 - t2) < 1e-10
+        assert abs(abs(np.sum(x1 * x2)) - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("L,seed,chi,lengths,mps_seed", [(6, 1001, 16, (2, 2, 2), 19), (8, 1008, 24, (2, 3, 3), 27)])
+def test_extension_one_chain_equals_dense_and_lowers_the_coarse_energy(L, seed, chi, lengths, mps_seed):
+    """Two kept eigenvectors per subdomain: the environment-chain and dense-vector
+    oracles agree, the coarse space holds 2P + 1 states, and enriching it can only
+    lower the coarse eigenvalue (the plain method's states are among them)."""
+    h, B = S.integrals(L, L, seed)
+    mpo = OM.build_mpo(h, B)
+    prob = T.Problem(h, B, L, 0)
+    cores, labels = S.random_mps(L, L, 0, chi, mps_seed)
+    oc = T.left_orthogonalize(cores, labels)
+    rd = T.a2dmrg_sweep(prob, oc, labels, chi, lengths, n_eig=2)
+    rc = CH.a2dmrg_sweep(mpo, oc, labels, chi, lengths, n_eig=2)
+    r1 = T.a2dmrg_sweep(prob, oc, labels, chi, lengths)
+    assert rd.S.shape == (2 * len(lengths) + 1,) * 2
+    Sd, Ad, cd = _gauge(rd.S, rd.A, rd.c)
+    Sc, Ac, cc = _gauge(rc.S, rc.A, rc.c)
+    assert np.abs(Sd - Sc).max() < 1e-10 and np.abs(Ad - Ac).max() < 1e-9 and np.abs(cd - cc).max() < 1e-9
+    assert abs(rd.lam - rc.lam) < 1e-10 and abs(rd.E_new - rc.E_new) < 1e-10
+    assert np.abs(np.array(rd.E_local) - np.array(r1.E_local)).max() < 1e-10
+    assert rd.lam <= r1.lam + 1e-12
+    # the plain method's coarse states are the enriched space's states 0, 1, 3, 5, ...
+    sel = [0] + [1 + 2 * j for j in range(len(lengths))]
+    assert np.abs(np.abs(rd.S[np.ix_(sel, sel)]) - np.abs(r1.S)).max() < 1e-10
