@@ -252,7 +252,7 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w, lengths, gpu_flops_heff, budget_s, coarse_k=1):
+def cpu_baseline(w, lengths, gpu_flops_heff, budget_s, coarse_k=1, one_site=False):
     """The oracle (oracle.chain with the oracle's own MPO, dense in the bond indices) as
     it stands, timed on the host cores for a bounded sample of this workload: blocks of
     8 output rows of its two-site product at the middle window (the product restricted to
@@ -285,20 +285,24 @@ def cpu_baseline(w, lengths, gpu_flops_heff, budget_s, coarse_k=1):
                                          S.random_sparse_mpo_core(RB, RC, 5, 12)])
     W1, W2 = CH.site_ops(om, 0), CH.site_ops(om, 1)
     rng = np.random.default_rng(5)
-    x = rng.standard_normal((r, 4, 4, r))
-    Renv = rng.standard_normal((r, RC, r))
+    # one-site: the product of the first site alone (heff1_apply), right environment at bond b+1
+    x = rng.standard_normal((r, 4, r) if one_site else (r, 4, 4, r))
+    Renv = rng.standard_normal((r, RB if one_site else RC, r))
     rows = 8
     t0 = time.perf_counter()
     nblk = 0
     while True:
         Lrows = rng.standard_normal((rows, RA, r))
-        CH.heff_apply(Lrows, W1, W2, Renv, x)
+        if one_site:
+            CH.heff1_apply(Lrows, W1, Renv, x)
+        else:
+            CH.heff_apply(Lrows, W1, W2, Renv, x)
         nblk += 1
         if time.perf_counter() - t0 > budget_s or nblk * rows >= r:
             break
     t_blk = (time.perf_counter() - t0) / nblk
     t_mv = t_blk * r / rows
-    f_mv = 2.0 * 16.0 * r * r * (RA * r + RC * r)
+    f_mv = (2.0 * 4.0 * r * r * (RA * r + RB * r) if one_site else 2.0 * 16.0 * r * r * (RA * r + RC * r))
     rate = f_mv / t_mv  # the oracle's dense-bond flop rate on this host
     # the oracle's environment updates per sweep, dense-bond flops 4 n R r^3 each (mean R)
     Rm = float(np.mean(Rb[1:-1]))
@@ -310,7 +314,8 @@ def cpu_baseline(w, lengths, gpu_flops_heff, budget_s, coarse_k=1):
     return {
         "value": total, "unit": "s/sweep", "cores": int(threads), "kind": "oracle",
         "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
-        "sample": (f"{nblk} blocks of {rows} output rows of the oracle's two-site product (oracle.chain.heff_apply, "
+        "sample": (f"{nblk} blocks of {rows} output rows of the oracle's "
+                   f"{'one-site product (oracle.chain.heff1_apply' if one_site else 'two-site product (oracle.chain.heff_apply'}, "
                    f"its own MPO) at window ({b},{b + 1}), RA={RA}, RC={RC}, r={r}: {t_blk:.2f} s per block, "
                    f"{rate / 1e9:.1f} GFLOP/s dense-bond; extrapolated by dense-bond flops to the sweep's "
                    f"products ({gpu_flops_heff:.3e} flop) plus {n_env} oracle environment updates "
@@ -386,6 +391,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-product sweep after the timed steps")
     ap.add_argument("--matvec", choices=("f64", "f32", "bf16"), default=None,
                     help="product precision instead of the workload's own")
+    ap.add_argument("--one-site", action="store_true",
+                    help="one-site micro-steps (Algorithm 2, one-site branch; FP64 products) instead of two-site")
     ap.add_argument("--coarse-k", type=int, default=1,
                     help="local eigenvectors kept per subdomain for the coarse space (Extension One)")
     ap.add_argument("--lowprec-tol", type=float, default=1e-5,
@@ -421,13 +428,13 @@ def main():
     mpo = build_mpo(h, B)
     cores, labels = S.random_mps(w.L, w.n_elec, w.two_sz, chi, w.seed + 1)
     log(f"setup: MPO R_mid={mpo.R[w.L // 2]} nnz={sum(mpo.nnz())} in {time.perf_counter() - t0:.1f}s")
-    prec = args.matvec or w.matvec_prec
+    prec = "f64" if args.one_site else (args.matvec or w.matvec_prec)
     tol, maxiter, refine = w.dav_tol, args.dav_maxiter or 4000, prec != "f64"
     if args.capped:
         tol, maxiter, refine = (w.dav_tol if prec == "f64" else 1e-5), args.dav_maxiter or 40, False
     ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                   refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=args.sub_workers,
-                  coarse_k=args.coarse_k)
+                  coarse_k=args.coarse_k, one_site=args.one_site)
     workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
     # host -> device hand-over (PCIe) and device left-orthogonalisation: outside the timed region
@@ -463,7 +470,7 @@ def main():
     stats = ctx.kernel_timing(enable=False, reset=True)
     sec = (te - ts) / args.steps
     fl = sum(r["flops_heff"] for r in reps)
-    names = Context.KERNELS
+    names = Context.KERNELS_ONE_SITE if args.one_site else Context.KERNELS
     kernels_timed = breakdown_of(names, stats)
     iso_note = "timed region (one solve at a time)"
     if workers > 1:
@@ -475,7 +482,7 @@ def main():
         ctx.close()
         ctx1 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                        refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1,
-                       coarse_k=args.coarse_k)
+                       coarse_k=args.coarse_k, one_site=args.one_site)
         ctx1.set_mpo(mpo)
         ctx1.set_mps(cores, labels)
         ctx1.kernel_timing(enable=True, reset=True)
@@ -502,7 +509,8 @@ def main():
                    "dav_max_products": maxiter, "fp64_refinement": refine,
                    "lowprec_handover": args.lowprec_tol if refine else None,
                    "integrals_seed": w.seed, "mps_seed": w.seed + 1, "parallelism": "single-gpu",
-                   "concurrent_subdomain_solves": workers, "coarse_k": args.coarse_k},
+                   "concurrent_subdomain_solves": workers, "coarse_k": args.coarse_k,
+                   "micro_step": "one-site" if args.one_site else "two-site"},
         "heff_tflops_block_sparse": round(float(stats[:, 2].sum()) / max(heff_ms * 1e-3, 1e-12) / 1e12, 3),
         "heff_block_sparse_flops_per_sweep": float(stats[:, 2].sum()) / args.steps,
         "heff_seconds_per_sweep": round(heff_ms * 1e-3 / args.steps, 3),
@@ -543,7 +551,7 @@ def main():
                                                          np.asarray(reps[-1]["E_local"])).max())}
         ctx64.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, lengths, fl / args.steps, args.cpu_seconds, args.coarse_k)
+        out["cpu_baseline"] = cpu_baseline(w, lengths, fl / args.steps, args.cpu_seconds, args.coarse_k, args.one_site)
     if args.copy_probe:
         n = (1 << 30) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

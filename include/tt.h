@@ -286,7 +286,9 @@ int tt_energy_mpo_grad(void* ctx, double* E, double* const* gops);
  * flops, algorithmic bytes] for the kernels: 0 L.x GEMM; 1, 2, 3 site-1 mix
  * (gather of the rows with few operator entries, GEMM of the rows with many,
  * scatter of those); 4, 5, 6 the same for site 2; 7 R GEMM; 8 its K-split
- * reduction.  Algorithmic work counts only the quantum-number-allowed blocks
+ * reduction.  One-site products (tt_opts.one_site) use 0 (stage 1: L.x), 1 (light
+ * rows of the mix), 2 (GEMM of the heavy rows), 3 (their mix pass), 7 (the
+ * products with the stacked right environment) and 8 (their K-split reduction).  Algorithmic work counts only the quantum-number-allowed blocks
  * (block-sparse product) and each operand element moved once.  reset != 0
  * clears the accumulators after copying. */
 #define TT_KT_SLOTS 9

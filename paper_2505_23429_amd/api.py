@@ -196,6 +196,9 @@ class Context:
 
     KERNELS = ("gemm_Lx", "mix1_gather", "mix1_heavy_gemm", "mix1_heavy_scatter", "mix2_gather",
                "mix2_heavy_gemm", "mix2_heavy_scatter", "gemm_R", "gemm_R_reduce")
+    # the same timing slots as filled by one-site products (unused slots: "-")
+    KERNELS_ONE_SITE = ("env_s1_Lx", "env_mix_gather", "env_mix_heavy_gemm", "env_mix_heavy", "-", "-", "-",
+                        "gemm_R_stacked", "gemm_R_stacked_reduce")
 
     def kernel_timing(self, enable=True, reset=False):
         """Per-kernel stats of the products: one row per entry of KERNELS,

@@ -341,6 +341,7 @@ void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2
   u.nin4.assign(u.ngrp, 0);
   u.hw_off.assign(u.ngrp, 0);
   u.nnz = 0.0;
+  u.nent_light.assign(u.ngrp, 0.0);
   nrows.resize(u.ngrp, 0);
   std::vector<std::pair<int, double>> ent;
   for (int g = 0; g < u.ngrp; ++g) {
@@ -370,6 +371,7 @@ void bs_site_use(Engine& E, BsSiteUse& u, const SiteOp& op, const std::vector<Q2
         continue;
       }
       for (auto& pv : ent) { ocol.push_back(pv.first); oval.push_back(pv.second); }
+      u.nent_light[g] += (double)ent.size();
       optr.push_back((int)ocol.size());
       orow.push_back(ro);
     }
@@ -596,7 +598,11 @@ static bool env_tab(Engine& E, const BsSiteUse& u, const Labels& lP, const Label
 // staging buffer tmp (ntmp).  Ein: [nin][Pp][Qp]; ket: the ket core (nket elements).
 static void env_panel(Engine& E, const BsSiteUse& u, EnvTab& t, const double* Ein, long long nE, int Qp,
                       long long PQ, const double* ket, long long nket, long long bks, double* T1, double* panel,
-                      double* tmp, int* err) {
+                      double* tmp, int* err, bool timed = false) {
+  // timed: per-kernel events of a product (slots 0 stage 1, 1 light mix, 2 heavy GEMM, 3 heavy mix)
+  auto mark = [&](int slot) {
+    if (timed) E.kt_mark(slot);
+  };
   hipStream_t st = E.stream;
   // T1 entries whose ket sector Q_pi - d_K does not exist are never written
   fill(T1, sizeof(double) * t.n1, st);
@@ -606,6 +612,7 @@ static void env_panel(Engine& E, const BsSiteUse& u, EnvTab& t, const double* Ei
                        u.rin.as<int>(), t.d_goff.as<long long>(), t.d_gcols.as<int>(), t.d_specoff.as<long long>(),
                        t.d_nR.as<int>(), t.nRs, Ein, PQ, Qp, nE, ket, nket, bks, T1, t.n1, err);
     BECHECK(hipGetLastError());
+    mark(0);
   }
   if (!t.tm.empty()) {
     hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)t.tm.size()), dim3(MC), 0, st, t.d_tm.as<int4>(),
@@ -615,6 +622,7 @@ static void env_panel(Engine& E, const BsSiteUse& u, EnvTab& t, const double* Ei
                        u.d_cls_out.as<int>(), u.pos_out.as<int>(), t.d_nR.as<int>(), err,
                        (const long long*)nullptr, (const double*)nullptr);
     BECHECK(hipGetLastError());
+    mark(1);
   }
   if (!t.th.empty()) {
     if (t.gg_t1 != T1 || t.gg_tmp != tmp) {
@@ -638,6 +646,7 @@ static void env_panel(Engine& E, const BsSiteUse& u, EnvTab& t, const double* Ei
       t.gg_tmp = tmp;
     }
     gemm_grouped<double>(t.ggdev.as<GemmGroup<double>>(), t.gg, st);
+    mark(2);
     hipLaunchKernelGGL(env_mix_kernel, dim3((unsigned)t.th.size()), dim3(MC), 0, st, t.d_th.as<int4>(),
                        t.d_grp.as<EnvGrp>(), u.optr.as<int>(), u.ocol.as<int>(), u.oval.as<double>(),
                        u.hrow.as<int2>(), t.d_spec.as<int4>(), T1, t.n1, panel, t.npan, t.d_t3tau.as<int>(),
@@ -645,6 +654,7 @@ static void env_panel(Engine& E, const BsSiteUse& u, EnvTab& t, const double* Ei
                        u.d_cls_out.as<int>(), u.pos_out.as<int>(), t.d_nR.as<int>(), err, t.d_hbase.as<long long>(),
                        (const double*)tmp);
     BECHECK(hipGetLastError());
+    mark(3);
   }
 }
 
@@ -713,7 +723,8 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
 // bra sector tau of the right bond, the panel P_tau[(pi, s', i_p)][(B, i_r)] =
 // sum L W x.  The last stage multiplies it by the right environment stacked per
 // tau, Rs_tau[(B, i_r)][j] = R[B][o_tau + j][o_rho + i_r] (built once per local
-// problem), one GEMM per (pi, s') written straight into y.
+// problem): the split-K MFMA tiles of the two-site product's last stage over each
+// tau's whole panel, whose K chunks are summed and scattered into the rows of y.
 // ---------------------------------------------------------------------------
 namespace {
 struct R1Desc { long long dst; int cls0, cnt, nr, orho, ntau, otau, pad; };
@@ -743,9 +754,11 @@ struct BsHeff1Impl {
   int rlp = 0, rrp = 0, RAx = 0;
   DevMem t1, panel, tmp, Rs, err;
   std::vector<long long> rsoff;
-  std::vector<GemmGroup<double>> yg;
-  DevMem ygdev;
-  double* yg_y = nullptr;
+  // last stage: split-K tiles over the panels of every right sector, rows scattered into y
+  int ntiles = 0, nred = 0, nslots = 0;
+  long long nrs = 0;
+  DevMem tiles, red, rowdst, part;
+  double kfl[TT_KT_SLOTS] = {}, kby[TT_KT_SLOTS] = {};  // algorithmic flops and bytes per timing slot
 };
 
 bool bs_heff1_build(Engine& E, BsHeff1& h, std::shared_ptr<BsSiteUse> use, const Labels& ql, const Labels& qr, int RAx,
@@ -784,6 +797,7 @@ bool bs_heff1_build(Engine& E, BsHeff1& h, std::shared_ptr<BsSiteUse> use, const
     }
     nrs += (long long)t.Ntau[ta] * ntau;
   }
+  p->nrs = nrs;
   p->Rs.resize_zero(sizeof(double) * std::max<long long>(nrs, 1), st);
   if (!rd.empty()) {
     DevMem d_rd;
@@ -794,12 +808,58 @@ bool bs_heff1_build(Engine& E, BsHeff1& h, std::shared_ptr<BsSiteUse> use, const
     BECHECK(hipGetLastError());
     check_err(p->err, st, "one-site product set-up");
   }
-  // block-sparse flops of one product's two contractions (stage 1 and the last
-  // stage; the sparse mix between them is not counted)
-  double fl = 0.0;
-  for (const EnvS1& d : t.s1) fl += 2.0 * d.M * (double)d.N * d.K;
-  for (const EnvUP& e : t.ups) fl += 2.0 * t.SP.n[e.pi] * (double)t.Ntau[e.tau] * t.ST.n[e.tau];
-  h.flops = fl;
+  // last stage: one split-K segment per right sector tau (panel [Ktau][Ntau] x stacked
+  // R [Ntau][n_tau]); panel row koff(pi, s') + i_p is y row (o_pi + i_p, s'), columns o_tau..
+  std::vector<BsSplitSeg> segs;
+  std::vector<long long> rowdst;
+  std::vector<long long> row0(t.nTs, 0);
+  for (int ta = 0; ta < t.nTs; ++ta) {
+    row0[ta] = (long long)rowdst.size();
+    rowdst.resize(rowdst.size() + t.Ktau[ta], -1);
+    segs.push_back(BsSplitSeg{t.pbase[ta], p->rsoff[ta], t.Ktau[ta], t.ST.n[ta], t.Ntau[ta], (int)row0[ta]});
+  }
+  for (const EnvUP& e : t.ups)
+    for (int i = 0; i < t.SP.n[e.pi]; ++i)
+      rowdst[row0[e.tau] + e.koff + i] = (((long long)t.SP.off[e.pi] + i) * 4 + e.s) * p->rrp + t.ST.off[e.tau];
+  for (long long d : rowdst)
+    if (d < 0) throw std::runtime_error("one-site product: a panel row has no destination");
+  std::vector<BsS4Tile> tiles;
+  std::vector<BsRedTile> red;
+  double el_red = 0.0;
+  bs_splitk_tables(segs, tiles, red, p->nslots, el_red);
+  p->ntiles = (int)tiles.size();
+  p->nred = (int)red.size();
+  up(p->tiles, tiles, st);
+  up(p->red, red, st);
+  up(p->rowdst, rowdst, st);
+  p->part.ensure(sizeof(double) * (size_t)std::max(p->nslots, 1) * kBsSplitTile * kBsSplitTile);
+  // algorithmic work per timing slot (quantum-number-allowed blocks, each operand
+  // element moved once): 0 stage 1, 1 light mix, 2 heavy GEMM, 3 heavy mix, 7 last
+  // stage's products, 8 their K-split reduction
+  double* kf = p->kfl;
+  double* kb = p->kby;
+  for (const EnvS1& d : t.s1) {
+    kf[0] += 2.0 * d.M * (double)d.N * d.K;
+    kb[0] += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (double)d.M * d.N);
+  }
+  for (int g = 0; g < t.ng; ++g) {
+    const double cols = t.gcols[g];
+    const double nl = u.orow0[g + 1] - u.orow0[g], H = u.hrow0[g + 1] - u.hrow0[g], nin = u.nrows_in[g];
+    kf[1] += 2.0 * u.nent_light[g] * cols;
+    kb[1] += 8.0 * cols * ((nl > 0 ? nin : 0.0) + nl);
+    if (H > 0) {
+      kf[2] += 2.0 * H * nin * cols;
+      kb[2] += 8.0 * (H * nin + nin * cols + H * cols);
+      kb[3] += 8.0 * 2.0 * H * cols;
+    }
+  }
+  for (int ta = 0; ta < t.nTs; ++ta) {
+    const double M = t.Ktau[ta], K = t.Ntau[ta], N = t.ST.n[ta];
+    kf[7] += 2.0 * M * K * N;
+    kb[7] += 8.0 * (M * K + K * N + M * N);
+  }
+  kb[8] = 8.0 * el_red;
+  h.flops = kf[0] + kf[1] + kf[2] + kf[7];
   h.p = p;
   return true;
 }
@@ -811,27 +871,15 @@ void bs_heff1_apply(Engine& E, BsHeff1& h, const double* Lx, const double* x, do
   hipStream_t st = E.stream;
   const long long nx = (long long)p.rlp * 4 * p.rrp;
   fill(y, sizeof(double) * nx, st);
+  E.kt_begin();
   env_panel(E, u, t, Lx, (long long)p.RAx * p.rlp * p.rlp, p.rlp, (long long)p.rlp * p.rlp, x, nx, 4LL * p.rrp,
-            p.t1.as<double>(), p.panel.as<double>(), t.th.empty() ? nullptr : p.tmp.as<double>(), p.err.as<int>());
-  if (p.yg_y != y) {
-    p.yg.clear();
-    for (const EnvUP& e : t.ups) {
-      const int np = t.SP.n[e.pi], ntau = t.ST.n[e.tau], K = t.Ntau[e.tau];
-      if (np == 0 || ntau == 0 || K == 0) continue;
-      GemmGroup<double> G{};
-      G.g.M = np; G.g.N = ntau; G.g.K = K; G.g.batch = 1; G.g.kin = std::max(16, (K + 15) / 16 * 16);
-      G.g.sAm = K; G.g.sAkk = 1;
-      G.g.sBkk = ntau; G.g.sBn = 1;
-      G.g.sCm = 4LL * p.rrp; G.g.alpha = 1.0; G.g.beta = 0.0;
-      G.A = p.panel.as<double>() + t.t3base[e.pi * 4 + e.s];
-      G.B = p.Rs.as<double>() + p.rsoff[e.tau];
-      G.C = y + ((long long)t.SP.off[e.pi] * 4 + e.s) * p.rrp + t.ST.off[e.tau];
-      p.yg.push_back(G);
-    }
-    if (!p.yg.empty()) upload(p.ygdev, p.yg.data(), p.yg.size() * sizeof(GemmGroup<double>), st);
-    p.yg_y = y;
-  }
-  if (!p.yg.empty()) gemm_grouped<double>(p.ygdev.as<GemmGroup<double>>(), p.yg, st);
+            p.t1.as<double>(), p.panel.as<double>(), t.th.empty() ? nullptr : p.tmp.as<double>(), p.err.as<int>(),
+            true);
+  bs_splitk_run(E, p.ntiles, p.tiles.as<BsS4Tile>(), p.nred, p.red.as<BsRedTile>(), p.rowdst.as<long long>(),
+                p.panel.as<double>(), std::max<long long>(t.npan, 1), p.Rs.as<double>(), std::max<long long>(p.nrs, 1),
+                p.part.as<double>(), y, nx, p.err.as<int>(), 7, 8);
+  check_err(p.err, st, "one-site product");
+  E.kt_end(p.kfl, p.kby);
 }
 
 }  // namespace tt

@@ -105,6 +105,7 @@ struct BsSiteUse {
   std::map<Q2, int> gid;
   std::vector<int> orow0;                  // group -> first output row (size ngrp + 1)
   std::vector<int> nrows_in;               // input rows per group
+  std::vector<double> nent_light;          // operator entries of the light output rows per group
   double nnz = 0.0;                        // operator non-zeros (for flop counts)
   DevMem clist_in, clist_out, pos_out, d_cls_out, d_gidx_in, rin, optr, ocol, oval, orow;
   // heavy output rows (many entries) as a dense [H x rows_in] matrix per group
@@ -128,12 +129,24 @@ bool bs_env(Engine& E, const BsSiteUse& u, const double* Ein, const Core& bra, c
 // ---------------------------------------------------------------------------
 // One-site effective-Hamiltonian product (eq. mat_vec, one-site form, FP64):
 //   y[a'][s'][b'] = sum L[A][a'][a] W[A,s',s,B] x[a][s][b] R[B][b'][b]
-// through stage 1 and the mix of the left update (ket = x), then one GEMM per
-// (left sector, s') against the right environment stacked per right sector.
+// through stage 1 and the mix of the left update (ket = x), then split-K products
+// of each right sector's panel with the right environment stacked for that sector.
 // use: the left-update tables of the site (virtual input channels at a block site,
 // whose L then carries them); ql/qr: bond labels of x (grouped by charge);
 // R: [RB][rrp][rrp], read once by the build.  x, y: [rlp][4][rrp]; y is overwritten.
 // ---------------------------------------------------------------------------
+// Split-K products of row panels with stacked matrices whose rows are scattered into
+// y (the kernels of the two-site product's last stage): segment g multiplies the
+// panel [M][K] at abase by the stacked [K][N] at bbase, and its row m lands at
+// y[rowdst[row0 + m] + n].  part holds 64 x 64 doubles per slot.
+struct BsSplitSeg { long long abase, bbase; int M, N, K, row0; };
+void bs_splitk_tables(const std::vector<BsSplitSeg>& segs, std::vector<BsS4Tile>& tiles, std::vector<BsRedTile>& red,
+                      int& nslots, double& el_red);
+void bs_splitk_run(Engine& E, int ntiles, const BsS4Tile* tiles, int nred, const BsRedTile* red,
+                   const long long* rowdst, const double* A, long long nA, const double* B, long long nB, double* part,
+                   double* y, long long ny, int* err, int slot_gemm, int slot_red);
+constexpr int kBsSplitTile = 64;
+
 struct BsHeff1Impl;
 struct BsHeff1 {
   std::shared_ptr<BsHeff1Impl> p;

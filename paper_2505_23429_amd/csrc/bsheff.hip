@@ -1156,6 +1156,42 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   E.kt_end(fl, by);
 }
 
+// split-K panel x stacked-matrix products of the one-site product (same kernels as stage 4)
+void bs_splitk_tables(const std::vector<BsSplitSeg>& segs, std::vector<BsS4Tile>& tiles, std::vector<BsRedTile>& red,
+                      int& nslots, double& el_red) {
+  tiles.clear();
+  red.clear();
+  nslots = 0;
+  el_red = 0.0;
+  for (const BsSplitSeg& g : segs) {
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0) continue;
+    for (int m0 = 0; m0 < g.M; m0 += TILE)
+      for (int n0 = 0; n0 < g.N; n0 += TILE) {
+        BsRedTile r{g.M, g.N, m0, n0, nslots, 0, g.row0, 0};
+        for (int k0 = 0; k0 < g.K; k0 += KSPLIT) {
+          tiles.push_back(BsS4Tile{g.abase, g.bbase, g.M, g.N, g.K, m0, n0, k0, std::min(g.K, k0 + KSPLIT), nslots});
+          ++nslots;
+          ++r.nsplit;
+        }
+        el_red += (double)(r.nsplit + 1) * std::min(TILE, g.M - m0) * std::min(TILE, g.N - n0);
+        red.push_back(r);
+      }
+  }
+}
+
+void bs_splitk_run(Engine& E, int ntiles, const BsS4Tile* tiles, int nred, const BsRedTile* red,
+                   const long long* rowdst, const double* A, long long nA, const double* B, long long nB, double* part,
+                   double* y, long long ny, int* err, int slot_gemm, int slot_red) {
+  hipStream_t s = E.stream;
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL((stage4_mfma_kernel<double>), dim3(ntiles), dim3(256), 0, s, tiles, A, nA, B, nB, part, err);
+  BSCHECK(hipGetLastError());
+  if (slot_gemm >= 0) E.kt_mark(slot_gemm);
+  hipLaunchKernelGGL((reduce4_kernel<double>), dim3(nred), dim3(256), 0, s, red, part, rowdst, y, ny, err);
+  BSCHECK(hipGetLastError());
+  if (slot_red >= 0) E.kt_mark(slot_red);
+}
+
 template void bs_apply<double>(Engine&, BsPlan&, const double*, const double*, const double*, const double*, double*,
                                bool);
 template void bs_apply<float>(Engine&, BsPlan&, const float*, const float*, const float*, const float*, float*, bool);
