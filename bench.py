@@ -391,6 +391,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-product sweep after the timed steps")
     ap.add_argument("--matvec", choices=("f64", "f32", "bf16"), default=None,
                     help="product precision instead of the workload's own")
+    ap.add_argument("--linear", action="store_true",
+                    help="the linear-system functional 1/2 <X,AX> - <F,X> (A: the workload's Hamiltonian shifted "
+                         "to be positive definite, F: a random TT of bond dimension --chi-f; FP64 products)")
+    ap.add_argument("--chi-f", type=int, default=64)
     ap.add_argument("--one-site", action="store_true",
                     help="one-site micro-steps (Algorithm 2, one-site branch; FP64 products) instead of two-site")
     ap.add_argument("--coarse-k", type=int, default=1,
@@ -424,19 +428,27 @@ def main():
     w, lengths = workload(args.workload)
     chi = args.chi or w.chi
     t0 = time.perf_counter()
-    h, B = S.integrals(w.L, w.n_factors, w.seed)
+    if args.linear:
+        h, B, sigma, Fcores, Flabels = S.linear_system(w.L, w.n_elec, w.seed, args.chi_f)
+    else:
+        h, B = S.integrals(w.L, w.n_factors, w.seed)
     mpo = build_mpo(h, B)
     cores, labels = S.random_mps(w.L, w.n_elec, w.two_sz, chi, w.seed + 1)
+    if args.linear:
+        cores = S.unit_tt(cores)  # the linear functional depends on the iterate's norm
     log(f"setup: MPO R_mid={mpo.R[w.L // 2]} nnz={sum(mpo.nnz())} in {time.perf_counter() - t0:.1f}s")
-    prec = "f64" if args.one_site else (args.matvec or w.matvec_prec)
+    prec = "f64" if (args.one_site or args.linear) else (args.matvec or w.matvec_prec)
+    functional = "linear" if args.linear else "eig"
     tol, maxiter, refine = w.dav_tol, args.dav_maxiter or 4000, prec != "f64"
     if args.capped:
         tol, maxiter, refine = (w.dav_tol if prec == "f64" else 1e-5), args.dav_maxiter or 40, False
     ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                   refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=args.sub_workers,
-                  coarse_k=args.coarse_k, one_site=args.one_site)
+                  coarse_k=args.coarse_k, one_site=args.one_site, functional=functional)
     workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
+    if args.linear:
+        ctx.set_rhs(Fcores, Flabels)
     # host -> device hand-over (PCIe) and device left-orthogonalisation: outside the timed region
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -482,8 +494,10 @@ def main():
         ctx.close()
         ctx1 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                        refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1,
-                       coarse_k=args.coarse_k, one_site=args.one_site)
+                       coarse_k=args.coarse_k, one_site=args.one_site, functional=functional)
         ctx1.set_mpo(mpo)
+        if args.linear:
+            ctx1.set_rhs(Fcores, Flabels)
         ctx1.set_mps(cores, labels)
         ctx1.kernel_timing(enable=True, reset=True)
         t = time.perf_counter()
@@ -510,7 +524,9 @@ def main():
                    "lowprec_handover": args.lowprec_tol if refine else None,
                    "integrals_seed": w.seed, "mps_seed": w.seed + 1, "parallelism": "single-gpu",
                    "concurrent_subdomain_solves": workers, "coarse_k": args.coarse_k,
-                   "micro_step": "one-site" if args.one_site else "two-site"},
+                   "micro_step": "one-site" if args.one_site else "two-site",
+                   "functional": "linear (1/2 <X,AX> - <F,X>)" if args.linear else "eigenvalue (Rayleigh quotient)",
+                   **({"chi_f": args.chi_f, "shift_sigma": sigma} if args.linear else {})},
         "heff_tflops_block_sparse": round(float(stats[:, 2].sum()) / max(heff_ms * 1e-3, 1e-12) / 1e12, 3),
         "heff_block_sparse_flops_per_sweep": float(stats[:, 2].sum()) / args.steps,
         "heff_seconds_per_sweep": round(heff_ms * 1e-3 / args.steps, 3),

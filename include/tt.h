@@ -120,21 +120,33 @@ typedef struct tt_opts {
                          charge-block QR (the orthogonalization step of Algorithm 1), so bond
                          dimensions do not change in Step 2.  Needs matvec_prec = TT_F64 and
                          qn_skip = 1 (EINVAL otherwise). */
+  int functional;     /* 0: J(X) = <X,AX>/<X,X> (eq. energy_eig, the eigenvalue problem);
+                         1: J(X) = 1/2 <X,AX> - <F,X> (eq. energy_lin) with A the MPO operator,
+                         which must be symmetric positive definite on the sector, and F the
+                         TT given by tt_set_rhs.  The micro-steps then solve the projected
+                         linear systems P^T A P w = P^T F (preconditioned conjugate gradients
+                         to dav_tol relative to |P^T F|, at most dav_maxiter products) and
+                         Step 3 the coarse linear system (Section "The second-level
+                         minimization", last remark).  Needs matvec_prec = TT_F64, qn_skip = 1
+                         and coarse_k = 1 (EINVAL otherwise). */
 } tt_opts;
 
 #define TT_MAX_SUB 64
 
 typedef struct tt_sweep_report {
   int nsub;
-  double E_before;                 /* <U|H|U> of the input iterate */
-  double E_local[TT_MAX_SUB];      /* last Ritz value of each subdomain sweep */
+  double E_before;                 /* <U|H|U> of the input iterate (functional 1: J(X)) */
+  double E_local[TT_MAX_SUB];      /* last Ritz value of each subdomain sweep (functional 1: the
+                                      local minimum 1/2 w.Aw - b.w of its last micro-step) */
   int matvecs[TT_MAX_SUB];         /* effective-Hamiltonian products per subdomain */
   double S[(TT_MAX_SUB + 1) * (TT_MAX_SUB + 1)]; /* coarse overlap, row-major (nsub+1)^2 */
   double A[(TT_MAX_SUB + 1) * (TT_MAX_SUB + 1)]; /* coarse Hamiltonian, row-major */
-  double coef[TT_MAX_SUB + 1];     /* coarse coefficients, c^T S c = 1 */
-  double lambda;                   /* lowest coarse eigenvalue */
+  double coef[TT_MAX_SUB + 1];     /* coarse coefficients: c^T S c = 1 (functional 0), the coarse
+                                      minimiser (1); state 0 is the normalised iterate and every
+                                      update is normalised, so S has a unit diagonal */
+  double lambda;                   /* lowest coarse eigenvalue (functional 1: coarse minimum of J) */
   int rankS;                       /* numerical rank of S */
-  double E_after;                  /* <U|H|U> of the compressed next iterate */
+  double E_after;                  /* <U|H|U> of the compressed next iterate (functional 1: J) */
   double discarded;                /* total discarded weight of Step 4 */
   double seconds[4];               /* wall time of Steps 1..4 */
   double flops_heff;               /* dense-bond flops of all effective-Hamiltonian products */
@@ -146,6 +158,7 @@ typedef struct tt_sweep_report {
                                       the workers */
   int matvecs_f64[TT_MAX_SUB];     /* of matvecs[]: the products taken in FP64 */
   int nstates;                     /* coarse states n = nsub * coarse_k + 1: S, A are n x n, coef n */
+  double rhs[TT_MAX_SUB + 1];      /* functional = 1: coarse right-hand side b_j = <F|U^j> */
 } tt_sweep_report;
 
 void tt_default_opts(tt_opts* o);
@@ -170,11 +183,24 @@ int tt_set_mpo(void* ctx, int L, const int* R, const int* nnz, const int32_t* co
 int tt_set_mps(void* ctx, int L, const int* r, const double* const* U, const int32_t* const* q);
 
 /* Copy the current (left-orthogonal) iterate out.  If U is NULL only r[0..L] is
- * written; otherwise U[k] and q[k] must have room for the sizes in r. */
+ * written; otherwise U[k] and q[k] must have room for the sizes in r.  With
+ * functional = 1 the iterate keeps its norm (the last core carries it); with 0
+ * it is normalised. */
 int tt_get_mps(void* ctx, int* r, double* const* U, int32_t* const* q);
 
 /* <U|H|U> / <U|U> of the current iterate. */
 int tt_energy(void* ctx, double* E);
+
+/* Right-hand side F of the linear-system functional (eq. energy_lin) as a TT:
+ * r[0..L], cores F[k] host [r_k][4][r_{k+1}], labels q[k] host int32 [r_k][2]
+ * (same conventions and checks as tt_set_mps; the cores are kept as given, not
+ * orthogonalised or normalised).  Needs the MPO; F's sector must be the
+ * iterate's (right boundary label), else the sweep fails with EINVAL. */
+int tt_set_rhs(void* ctx, int L, const int* r, const double* const* F, const int32_t* const* q);
+
+/* J(X) of the current iterate for the context's functional: the Rayleigh
+ * quotient (functional 0) or 1/2 <X,AX> - <F,X> (functional 1). */
+int tt_functional(void* ctx, double* J);
 
 /* Keeps a device copy of the current iterate (op 0) or makes the kept copy the
  * current iterate again (op 1), without a host round trip: repeated global

@@ -28,6 +28,11 @@ contractions only, so it reaches the sizes of the bench workloads:
   L.x -> W -> R, subdomain j swept over sites s_j .. e_j with the
   orthogonalization step of Algorithm 1 (``oracle.tt.qr_left_core``) moving the
   centre right between micro-steps;
+* the linear-system functional (eq. energy_lin): the micro-steps solve
+  P^T A P w = P^T F by conjugate gradients on the same products, P^T F from the
+  overlap environments of the iterate with F's TT; the coarse linear system over
+  the normalised updates (``oracle.tt.coarse_solve_lin``), b_j = <U^j|F> by overlap
+  chains;
 * Algorithm 1 (two-site branch) with the same pieces.
 
 Every dense step is a library matrix product or factorisation on plain
@@ -119,6 +124,13 @@ def overlap_left(E, bra, ket):
     """E'[b', b] = sum E[a', a] bra[a', s, b'] ket[a, s, b]."""
     t = (E @ ket.reshape(ket.shape[0], -1)).reshape(bra.shape[0] * 4, ket.shape[2])
     return bra.reshape(bra.shape[0] * 4, bra.shape[2]).T @ t
+
+
+def overlap_right(E, bra, ket):
+    """E'[a', a] = sum bra[a', s, b'] ket[a, s, b] E[b', b]."""
+    t = ket.reshape(ket.shape[0] * 4, ket.shape[2]) @ E.T          # [a s, b']
+    t = t.reshape(ket.shape[0], 4 * bra.shape[2])
+    return bra.reshape(bra.shape[0], 4 * bra.shape[2]) @ t.T        # [a', a]
 
 
 def heff_apply(Lenv, W1: SiteOps, W2: SiteOps, Renv, x):
@@ -492,3 +504,144 @@ def a2dmrg_sweep(mpo, cores, labels, chi, lengths, eps=1e-8, tol=1e-11, cutoff=1
     E_new = chain_energy(mpo, ops, new_cores)
     return ChainReport(E_before, E_local, matvecs, S, A, lam, c, rank, E_new, new_cores, new_labels, states,
                        state_labels)
+
+
+# ---------------------------------------------------------------------------
+# linear-system functional (eq. energy_lin)
+# ---------------------------------------------------------------------------
+
+def conjugate_gradients(mv, b, x0, tol=1e-12, maxiter=1000):
+    """Plain conjugate gradients for a symmetric positive definite operator: from x0
+    until |b - A x| <= tol |b|.  Returns (x, products)."""
+    x = x0.copy()
+    r = b - mv(x)
+    n = 1
+    p = r.copy()
+    rr = r @ r
+    bn = np.linalg.norm(b)
+    while np.sqrt(rr) > tol * bn and n < maxiter:
+        q = mv(p)
+        n += 1
+        a = rr / (p @ q)
+        x += a * p
+        r -= a * q
+        rr2 = r @ r
+        p = r + (rr2 / rr) * p
+        rr = rr2
+    return x, n
+
+
+def a2dmrg_lin_sweep(mpo, cores, labels, chi, lengths, f_cores, eps=1e-8, tol=1e-12, cutoff=1e-12, tau=1e-10,
+                     sites=2, log=None):
+    """One global iteration of Algorithm 2 for the linear-system functional with A the
+    MPO operator: the readings of ``oracle.tt.a2dmrg_lin_sweep`` through environment
+    chains.  ``cores``: left-orthogonal, the last core carrying the iterate's norm."""
+    L = mpo.L
+    ops = [site_ops(mpo, k) for k in range(L)]
+    cores = [c.copy() for c in cores]
+
+    def J_of(st):
+        E = np.ones((1, 1, 1))
+        N = np.ones((1, 1))
+        G = np.ones((1, 1))
+        for k in range(L):
+            E = env_left(E, st[k], ops[k], st[k])
+            G = overlap_left(G, st[k], f_cores[k])
+        return float(0.5 * E[0, 0, 0] - G[0, 0])
+
+    J_before = J_of(cores)
+    V, W = T.lq_sweep(cores, labels)
+    starts = T.subdomain_starts(lengths)
+    Le = [np.ones((1, 1, 1))]
+    Fe = [np.ones((1, 1))]
+    for k in range(max(starts)):
+        Le.append(env_left(Le[k], cores[k], ops[k], cores[k]))
+        Fe.append(overlap_left(Fe[k], cores[k], f_cores[k]))
+    Re = [None] * (L + 1)
+    Fr = [None] * (L + 1)
+    Re[L] = np.ones((1, 1, 1))
+    Fr[L] = np.ones((1, 1))
+    for k in range(L - 1, 0, -1):
+        Re[k] = env_right(Re[k + 1], V[k], ops[k], V[k])
+        Fr[k] = overlap_right(Fr[k + 1], V[k], f_cores[k])
+    states, state_labels, E_local, matvecs = [cores], [labels], [], []
+    for j, s in enumerate(starts):
+        e = s + lengths[j] - 1
+        lab = [q.copy() for q in labels]
+        cur = cores[:s] + [W[s]] + [V[k] for k in range(s + 1, L)]
+        Lrun, Frun = Le[s], Fe[s]
+        theta, nmv = 0.0, 0
+        if sites == 1:
+            for k in range(s, e + 1):
+                m = T.x1_mask(lab[k], lab[k + 1])
+                rhs = np.einsum("ac,csd,bd->asb", Frun, f_cores[k], Fr[k + 1])[m]
+
+                def mv(v, k=k, m=m):
+                    z = np.zeros(m.shape)
+                    z[m] = v
+                    return heff1_apply(Lrun, ops[k], Re[k + 1], z)[m]
+
+                w, n = conjugate_gradients(mv, rhs, cur[k][m], tol)
+                nmv += n
+                theta = float(0.5 * w @ mv(w) - rhs @ w)
+                x = np.zeros(m.shape)
+                x[m] = w
+                if k < e:
+                    Q, R = T.qr_left_core(x, lab[k], lab[k + 1])
+                    cur[k], cur[k + 1] = Q, np.einsum("ab,bsc->asc", R, cur[k + 1])
+                    Lrun = env_left(Lrun, Q, ops[k], Q)
+                    Frun = overlap_left(Frun, Q, f_cores[k])
+                else:
+                    cur[k] = x
+                if log:
+                    log(f"subdomain {j} site {k}: J_loc={theta:.12f} products={n}")
+        else:
+            blast = min(e, L - 2)
+            for b in range(s, blast + 1):
+                m = T.x_mask(lab[b], lab[b + 2])
+                fw = np.einsum("asb,btc->astc", f_cores[b], f_cores[b + 1])
+                rhs = np.einsum("ac,cstd,bd->astb", Frun, fw, Fr[b + 2])[m]
+                x0 = np.einsum("asb,btc->astc", cur[b], cur[b + 1])
+
+                def mv(v, b=b, m=m):
+                    z = np.zeros(m.shape)
+                    z[m] = v
+                    return heff_apply(Lrun, ops[b], ops[b + 1], Re[b + 2], z)[m]
+
+                w, n = conjugate_gradients(mv, rhs, x0[m], tol)
+                nmv += n
+                theta = float(0.5 * w @ mv(w) - rhs @ w)
+                x = np.zeros(m.shape)
+                x[m] = w
+                A_, C_, qn, _, _ = T.split_two_site(x, lab[b], lab[b + 2], chi, True, cutoff, tau)
+                cur[b], cur[b + 1], lab[b + 1] = A_, C_, qn
+                if b < blast:
+                    Lrun = env_left(Lrun, A_, ops[b], A_)
+                    Frun = overlap_left(Frun, A_, f_cores[b])
+                if log:
+                    log(f"subdomain {j} bond {b}: J_loc={theta:.12f} products={n}")
+        states.append(cur)
+        state_labels.append(lab)
+        E_local.append(theta)
+        matvecs.append(nmv)
+    n = len(states)
+    S = np.zeros((n, n))
+    A = np.zeros((n, n))
+    b = np.zeros(n)
+    for i in range(n):
+        G = np.ones((1, 1))
+        for k in range(L):
+            G = overlap_left(G, states[i][k], f_cores[k])
+        b[i] = G[0, 0]
+        for jj in range(i, n):
+            A[i, jj], S[i, jj] = chain_sandwich(ops, states[i], states[jj])
+            A[jj, i], S[jj, i] = A[i, jj], S[i, jj]
+    d = 1.0 / np.sqrt(np.diag(S))
+    S, A, b = S * np.outer(d, d), A * np.outer(d, d), b * d
+    Jc, c, rank = T.coarse_solve_lin(S, A, b, eps)
+    sc, sl = tt_direct_sum(states, c * d, state_labels)
+    new_cores, new_labels = tt_round(sc, sl, chi, cutoff, tau)
+    J_new = J_of(new_cores)
+    rep = T.LinearReport(J_before, E_local, S, A, b, c, Jc, rank, J_new, new_cores, new_labels, states)
+    rep.matvecs = matvecs
+    return rep

@@ -29,6 +29,12 @@ state vectors restricted to one (N, Sz) sector, so it is limited to small
   rank-deficient branch eq. aux_eig_final_sym): coarse matrices from dense
   state vectors, eigen-decomposition of the overlap with relative threshold
   ``eps``, lowest eigenpair of the reduced pencil.
+* Linear-system functional (eq. energy_lin, J(X) = 1/2 <X,AX> - <F,X> with A
+  symmetric positive definite): the micro-step minimises J over the range of the
+  retraction, i.e. solves P^T A P w = P^T F; the second level minimises J over the
+  span of the updates, the linear system (X^T A X) y = X^T b with b_j = <F, U^j>
+  on the numerical range of the overlap matrix (the same canonical
+  orthogonalisation as the eigenvalue case).
 * Compression (Step 4 of Algorithm 2): TT-SVD of the dense coarse solution
   with the same per-block truncation rule, which equals TT rounding of any
   exact TT representation of that vector.
@@ -294,6 +300,18 @@ class Problem:
             out.append((float(w[q]), x))
         return out
 
+    def local_solve_lin(self, cores, k, ql, qr, f, sites=2):
+        """Micro-step of the linear-system functional: w = (P^T A P)^{-1} P^T f with the
+        two-site (or one-site) retraction; returns (1/2 w.P^T A P w - w.P^T f, w as a
+        tensor)."""
+        P, m = self.retraction(cores, k, ql, qr) if sites == 2 else self.retraction1(cores, k, ql, qr)
+        Ap = P.T @ self.H @ P
+        bp = P.T @ f
+        w = np.linalg.solve(0.5 * (Ap + Ap.T), bp)
+        x = np.zeros(m.shape)
+        x[m] = w
+        return float(0.5 * w @ Ap @ w - bp @ w), x
+
     def local_solve(self, cores, k, ql, qr, x0=None, tol=1e-12, dense_limit=3000):
         """Micro-iteration S_{k,k+1}: lowest eigenpair of P^T H P."""
         P, m = self.retraction(cores, k, ql, qr)
@@ -498,3 +516,85 @@ def a2dmrg_sweep(prob: Problem, cores, labels, chi, lengths, eps=1e-8, cutoff=1e
     new_cores[-1] = new_cores[-1] / nrm
     E_new = prob.energy(new_cores)
     return SweepReport(E_local, S, A, lam, c, rank, E_new, new_cores, new_labels, states)
+
+
+@dataclass
+class LinearReport:
+    J_before: float
+    E_local: list
+    S: np.ndarray
+    A: np.ndarray
+    b: np.ndarray
+    c: np.ndarray
+    J_coarse: float
+    rankS: int
+    J_new: float
+    cores: list
+    labels: list
+    states: list
+
+
+def coarse_solve_lin(S, A, b, eps=1e-8):
+    """Second level of the linear-system functional: minimise 1/2 c.Ac - b.c over the
+    numerical range of S (eigenvalues of S below eps*max dropped)."""
+    w, V = np.linalg.eigh(S)
+    keep = w >= eps * w.max()
+    X = V[:, keep] / np.sqrt(w[keep])[None, :]
+    At = X.T @ A @ X
+    y = np.linalg.solve(0.5 * (At + At.T), X.T @ b)
+    c = X @ y
+    return float(0.5 * c @ A @ c - b @ c), c, int(keep.sum())
+
+
+def a2dmrg_lin_sweep(prob: Problem, cores, labels, chi, lengths, f_cores, eps=1e-8, cutoff=1e-12, tau=1e-10,
+                     sites=2):
+    """One global iteration of Algorithm 2 for the linear-system functional, A = prob.H.
+
+    ``cores``: left-orthogonal (U_0..U_{L-2}, W_{L-1}), W_{L-1} carrying the norm of the
+    iterate X (not normalised: J depends on it); ``f_cores``: the TT of F.  The updates
+    are the TTs of the micro-step solutions (two-site: split by the truncated SVD with
+    the singular values on the right; one-site: QR moves); the coarse problem is posed
+    on the normalised states (S with unit diagonal; c refers to them), and the
+    combination is compressed by TT-SVD without normalisation."""
+    L = prob.L
+    f = prob.to_sector(contract_full(f_cores))
+    V, W = lq_sweep(cores, labels)
+    starts = subdomain_starts(lengths)
+    states = [[c.copy() for c in cores]]
+    E_local = []
+    for j, s in enumerate(starts):
+        e = s + lengths[j] - 1
+        lab = [q.copy() for q in labels]
+        cur = cores[:s] + [W[s]] + [V[k] for k in range(s + 1, L)]
+        if sites == 1:
+            for k in range(s, e + 1):
+                theta, x = prob.local_solve_lin(cur, k, lab[k], lab[k + 1], f, sites=1)
+                if k < e:
+                    cur[k], R = qr_left_core(x, lab[k], lab[k + 1])
+                    cur[k + 1] = np.einsum("ab,bsc->asc", R, cur[k + 1])
+                else:
+                    cur[k] = x
+        else:
+            blast = min(e, L - 2)
+            theta = 0.0
+            for b in range(s, blast + 1):
+                theta, x = prob.local_solve_lin(cur, b, lab[b], lab[b + 2], f)
+                A, C, qn, _, _ = split_two_site(x, lab[b], lab[b + 2], chi, True, cutoff, tau)
+                cur[b], cur[b + 1], lab[b + 1] = A, C, qn
+        states.append(cur)
+        E_local.append(theta)
+    Y = np.stack([prob.to_sector(contract_full(st)) for st in states], axis=1)
+    x0 = Y[:, 0]
+    J_before = float(0.5 * x0 @ prob.H @ x0 - f @ x0)
+    # the coarse states are normalised (the span is unchanged, and the eps threshold of
+    # the rank-deficient branch then does not depend on the states' scales)
+    Y = Y / np.linalg.norm(Y, axis=0)[None, :]
+    S = Y.T @ Y
+    A = Y.T @ prob.H @ Y
+    b = Y.T @ f
+    Jc, c, rank = coarse_solve_lin(S, A, b, eps)
+    y = Y @ c
+    new_cores, new_labels = tt_svd(prob, y, chi, cutoff, tau)
+    yn = prob.to_sector(contract_full(new_cores))
+    J_new = float(0.5 * yn @ prob.H @ yn - f @ yn)
+    return LinearReport(J_before, E_local, S, A, b, c, Jc, rank, J_new, new_cores, new_labels, states)

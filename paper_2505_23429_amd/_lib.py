@@ -21,7 +21,7 @@ EXPORTS = (
     "tt_default_opts", "tt_create", "tt_destroy", "tt_last_error", "tt_set_mpo", "tt_set_mps", "tt_get_mps",
     "tt_energy", "tt_local_solve", "tt_coarse_correct", "tt_sweep", "tt_dmrg2", "tt_heff_apply_dev",
     "tt_env_update_dev", "tt_heff_energy_grad_dev", "tt_energy_mpo_grad", "tt_gemm_dev", "tt_kernel_timing",
-    "tt_window_apply_dev", "tt_mps_checkpoint", "tt_heff_apply_dev_noalloc",
+    "tt_window_apply_dev", "tt_mps_checkpoint", "tt_heff_apply_dev_noalloc", "tt_set_rhs", "tt_functional",
 )
 TT_NOALLOC_SCRATCH_BYTES = 256 << 20
 
@@ -34,7 +34,7 @@ class Opts(C.Structure):
         ("sub_workers", C.c_int), ("mix_stage", C.c_int), ("svd_lds", C.c_int),
         ("worker_alloc_limit", C.c_longlong), ("stream", C.c_void_p), ("dev_alloc", C.c_void_p),
         ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p), ("coarse_k", C.c_int),
-        ("one_site", C.c_int),
+        ("one_site", C.c_int), ("functional", C.c_int),
     ]
 
 
@@ -53,7 +53,7 @@ class SweepReport(C.Structure):
         ("coef", C.c_double * (TT_MAX_SUB + 1)), ("lambda_", C.c_double), ("rankS", C.c_int),
         ("E_after", C.c_double), ("discarded", C.c_double), ("seconds", C.c_double * 4),
         ("flops_heff", C.c_double), ("seconds_heff", C.c_double), ("phase_seconds", C.c_double * 9),
-        ("matvecs_f64", C.c_int * TT_MAX_SUB), ("nstates", C.c_int),
+        ("matvecs_f64", C.c_int * TT_MAX_SUB), ("nstates", C.c_int), ("rhs", C.c_double * (TT_MAX_SUB + 1)),
     ]
 
 
@@ -86,6 +86,10 @@ def load():
     lib.tt_get_mps.restype = I
     lib.tt_energy.argtypes = [VP, P(D)]
     lib.tt_energy.restype = I
+    lib.tt_set_rhs.argtypes = [VP, I, P(I), P(P(D)), P(P(C.c_int32))]
+    lib.tt_set_rhs.restype = I
+    lib.tt_functional.argtypes = [VP, P(D)]
+    lib.tt_functional.restype = I
     lib.tt_local_solve.argtypes = [VP, I, P(I), P(D), P(I)]
     lib.tt_local_solve.restype = I
     lib.tt_coarse_correct.argtypes = [VP, P(D), P(D), P(D), P(D), P(D), P(I)]

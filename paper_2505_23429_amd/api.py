@@ -39,11 +39,13 @@ class Context:
     def __init__(self, chi=64, dav_tol=1e-8, dav_maxiter=200, dav_maxsub=24, coarse_eps=1e-8, svd_cutoff=1e-12,
                  tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True,
                  sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0, stream=None, torch_alloc=False,
-                 coarse_k=1, one_site=False):
+                 coarse_k=1, one_site=False, functional="eig"):
         """``stream``: a torch.cuda.Stream (or raw stream handle) every call runs on;
         ``torch_alloc``: take every device block of the context from the torch caching
         allocator (tt_opts.dev_alloc/dev_free) instead of the library's own pools;
-        ``one_site``: one-site micro-steps (FP64 products) instead of two-site ones."""
+        ``one_site``: one-site micro-steps (FP64 products) instead of two-site ones;
+        ``functional``: "eig" (Rayleigh quotient, the eigenvalue problem) or "linear"
+        (1/2 <X,AX> - <F,X> with F from ``set_rhs``; A must be positive definite)."""
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -66,6 +68,10 @@ class Context:
         o.coarse_k = int(coarse_k)
         self.coarse_k = int(coarse_k)
         o.one_site = int(bool(one_site))
+        if functional not in ("eig", "linear"):
+            raise ValueError("functional must be 'eig' or 'linear'")
+        o.functional = 1 if functional == "linear" else 0
+        self.functional = functional
         if stream is not None:
             o.stream = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
         self._callbacks = None
@@ -144,6 +150,20 @@ class Context:
         self._check(self.lib.tt_energy(self.h, C.byref(e)))
         return e.value
 
+    def set_rhs(self, cores, labels):
+        """Right-hand side F of the linear-system functional, as a TT (kept as given)."""
+        Lsites = len(cores)
+        r, rp = _iarr([c.shape[0] for c in cores] + [cores[-1].shape[2]])
+        F, kf = _ptr_array([c.reshape(-1) for c in cores], C.c_double)
+        q, kq = _ptr_array([np.asarray(l).reshape(-1) for l in labels], C.c_int32)
+        self._check(self.lib.tt_set_rhs(self.h, Lsites, rp, F, q))
+
+    def functional_value(self):
+        """J(X) of the current iterate for the context's functional."""
+        j = C.c_double()
+        self._check(self.lib.tt_functional(self.h, C.byref(j)))
+        return j.value
+
     # ---- the additive two-level iteration --------------------------------
     def local_solve(self, lengths):
         n = len(lengths)
@@ -182,7 +202,7 @@ class Context:
             "S": S, "A": A, "c": np.array(rep.coef[:m]),
             "lambda": rep.lambda_, "rankS": rep.rankS, "E_after": rep.E_after, "discarded": rep.discarded,
             "seconds": list(rep.seconds), "flops_heff": rep.flops_heff, "seconds_heff": rep.seconds_heff,
-            "phase_seconds": list(rep.phase_seconds),
+            "phase_seconds": list(rep.phase_seconds), "b": np.array(rep.rhs[:m]),
         }
 
     def checkpoint(self, restore=False):

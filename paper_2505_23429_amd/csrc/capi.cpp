@@ -153,6 +153,7 @@ void tt_default_opts(tt_opts* o) {
   o->alloc_user = nullptr;
   o->coarse_k = 1;
   o->one_site = 0;
+  o->functional = 0;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -163,7 +164,9 @@ int tt_create(const tt_opts* opts, void** out) {
       opts->mix_stage < 0 || opts->mix_stage > 2 || opts->svd_lds < 0 || opts->svd_lds > 1 ||
       opts->worker_alloc_limit < 0 || (!opts->dev_alloc) != (!opts->dev_free) || opts->coarse_k < 1 ||
       opts->coarse_k > 8 || opts->one_site < 0 || opts->one_site > 1 ||
-      (opts->one_site && (opts->matvec_prec != TT_F64 || !opts->qn_skip)))
+      (opts->one_site && (opts->matvec_prec != TT_F64 || !opts->qn_skip)) || opts->functional < 0 ||
+      opts->functional > 1 ||
+      (opts->functional == 1 && (opts->matvec_prec != TT_F64 || !opts->qn_skip || opts->coarse_k != 1)))
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);
@@ -213,6 +216,23 @@ int tt_energy(void* ctx, double* En) {
   });
 }
 
+int tt_set_rhs(void* ctx, int L, const int* r, const double* const* F, const int32_t* const* q) {
+  return guard(ctx, [&](Engine& E) {
+    if (!r || !F || !q) throw std::invalid_argument("bad TT arguments");
+    E.set_rhs(L, r, F, q);
+    return TT_OK;
+  });
+}
+
+int tt_functional(void* ctx, double* J) {
+  return guard(ctx, [&](Engine& E) {
+    if (!J) throw std::invalid_argument("J is NULL");
+    if (!E.have_mps) throw std::logic_error("no TT iterate");
+    *J = E.functional_value();
+    return TT_OK;
+  });
+}
+
 int tt_local_solve(void* ctx, int nsub, const int* lengths, double* E_local, int* matvecs) {
   return guard(ctx, [&](Engine& E) {
     if (!lengths) throw std::invalid_argument("lengths is NULL");
@@ -248,7 +268,7 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
     E.sec_heff = 0.0;
     for (double& v : E.ph) v = 0.0;
     auto t0 = std::chrono::steady_clock::now();
-    out->E_before = E.energy();
+    out->E_before = E.functional_value();
     auto t1 = std::chrono::steady_clock::now();
     E.local_solve(nsub, lengths, out->E_local, out->matvecs);
     for (int j = 0; j < nsub; ++j) out->matvecs_f64[j] = E.subs[E.sub_base[j]].matvecs64;
@@ -258,6 +278,8 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
     std::vector<double> S((size_t)n * n), A((size_t)n * n);
     int st = E.coarse_correct(S.data(), A.data(), out->coef, &out->lambda, &out->E_after, &out->rankS,
                               &out->discarded);
+    if (E.opts.functional == 1)
+      for (int i = 0; i < n && i < (int)E.coarse_b.size(); ++i) out->rhs[i] = E.coarse_b[i];
     auto t3 = std::chrono::steady_clock::now();
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) {

@@ -516,6 +516,8 @@ void Engine::free_caches() {
   Wc.clear();
   Lenv.clear();
   Renv.clear();
+  FL.clear();
+  FR.clear();
   subs.clear();
   have_local = false;
 }
@@ -1867,8 +1869,103 @@ void Engine::set_mps(int L_, const int* r, const double* const* Uh, const int32_
   scale(cores[L - 1].d.as<double>(), 1.0 / nrm, cores[L - 1].elems(), stream);
   HC(hipStreamSynchronize(stream));
   U = std::move(cores);
+  xscale = nrm;
   have_mps = true;
   free_caches();
+}
+
+// Right-hand side of the linear-system functional: kept as given (host layout checks as
+// for the iterate).
+void Engine::set_rhs(int L_, const int* r, const double* const* Fh, const int32_t* const* q) {
+  if (!have_mpo) throw std::logic_error("set the MPO before the right-hand side");
+  if (L_ != L) throw std::invalid_argument("right-hand side length differs from the MPO length");
+  if (r[0] != 1 || r[L] != 1) throw std::invalid_argument("TT boundary ranks must be 1");
+  std::vector<Labels> lab(L + 1);
+  for (int k = 0; k <= L; ++k) {
+    if (r[k] <= 0) throw std::invalid_argument("TT rank must be positive");
+    lab[k].resize(r[k]);
+    for (int a = 0; a < r[k]; ++a) lab[k][a] = {q[k][2 * a], q[k][2 * a + 1]};
+  }
+  if (lab[0][0] != Q2{0, 0}) throw std::invalid_argument("left boundary label must be (0,0)");
+  std::vector<Core> cores(L);
+  for (int k = 0; k < L; ++k) {
+    Core& c = cores[k];
+    c.rl = r[k]; c.rr = r[k + 1]; c.ql = lab[k]; c.qr = lab[k + 1];
+    const int rlp = c.rlp(), rrp = c.rrp();
+    std::vector<double> h((size_t)rlp * 4 * rrp, 0.0);
+    for (int a = 0; a < c.rl; ++a)
+      for (int s = 0; s < 4; ++s)
+        for (int b = 0; b < c.rr; ++b) {
+          double v = Fh[k][((size_t)a * 4 + s) * c.rr + b];
+          if (v != 0.0 && qadd(c.ql[a], SITE_Q[s]) != c.qr[b])
+            throw std::invalid_argument("right-hand side core " + std::to_string(k) + " violates its labels");
+          h[((size_t)a * 4 + s) * rrp + b] = v;
+        }
+    upload(c.d, h.data(), h.size() * sizeof(double), stream);
+  }
+  HC(hipStreamSynchronize(stream));
+  Fc = std::move(cores);
+  have_rhs = true;
+}
+
+// E'[b'][b] = sum E[a'][a] bra[a'][s][b'] ket[a][s][b]  (dense, padded bonds)
+void Engine::ov_left(const Env& in, const Core& bra, const Core& ket, Env& out) {
+  if (in.R != 1 || in.rb != bra.rl || in.rk != ket.rl) throw std::runtime_error("ov_left: shape mismatch");
+  const int rbp = padr(in.rb), rkp = padr(in.rk), rb2 = bra.rrp(), rk2 = ket.rrp();
+  Env o;
+  o.R = 1; o.rb = bra.rr; o.rk = ket.rr;
+  o.d.ensure(sizeof(double) * o.elems());
+  ws2.ensure(sizeof(double) * (size_t)rbp * 4 * rk2);
+  GemmArgs g{};
+  g.M = rbp; g.N = 4 * rk2; g.K = rkp; g.batch = 1; g.kin = rkp;
+  g.sAm = rkp; g.sAkk = 1; g.sBkk = 4LL * rk2; g.sBn = 1; g.sCm = 4LL * rk2; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, in.d.as<double>(), ket.d.as<double>(), ws2.as<double>(), true, true, stream);
+  GemmArgs h{};
+  h.M = rb2; h.N = rk2; h.K = 4 * rbp; h.batch = 1; h.kin = 4 * rbp;
+  h.sAm = 1; h.sAkk = rb2; h.sBkk = rk2; h.sBn = 1; h.sCm = rk2; h.alpha = 1.0; h.beta = 0.0;
+  gemm<double>(h, bra.d.as<double>(), ws2.as<double>(), o.d.as<double>(), false, true, stream);
+  out = std::move(o);
+}
+
+// E'[a'][a] = sum bra[a'][s][b'] ket[a][s][b] E[b'][b]  (dense, padded bonds)
+void Engine::ov_right(const Env& in, const Core& bra, const Core& ket, Env& out) {
+  if (in.R != 1 || in.rb != bra.rr || in.rk != ket.rr) throw std::runtime_error("ov_right: shape mismatch");
+  const int rb2 = padr(in.rb), rk2 = padr(in.rk), rbp = bra.rlp(), rkp = ket.rlp();
+  Env o;
+  o.R = 1; o.rb = bra.rl; o.rk = ket.rl;
+  o.d.ensure(sizeof(double) * o.elems());
+  ws2.ensure(sizeof(double) * (size_t)rkp * 4 * rb2);
+  GemmArgs g{};
+  g.M = 4 * rkp; g.N = rb2; g.K = rk2; g.batch = 1; g.kin = rk2;
+  g.sAm = rk2; g.sAkk = 1; g.sBkk = 1; g.sBn = rk2; g.sCm = rb2; g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, ket.d.as<double>(), in.d.as<double>(), ws2.as<double>(), true, false, stream);
+  GemmArgs h{};
+  h.M = rbp; h.N = rkp; h.K = 4 * rb2; h.batch = 1; h.kin = 4 * rb2;
+  h.sAm = 4LL * rb2; h.sAkk = 1; h.sBkk = 1; h.sBn = 4LL * rb2; h.sCm = rkp; h.alpha = 1.0; h.beta = 0.0;
+  gemm<double>(h, bra.d.as<double>(), ws2.as<double>(), o.d.as<double>(), true, false, stream);
+  out = std::move(o);
+}
+
+double Engine::overlap_with_rhs() {
+  if (!have_rhs) throw std::logic_error("the linear-system functional needs tt_set_rhs");
+  if (Fc.size() != (size_t)L || Fc[L - 1].qr != U[L - 1].qr)
+    throw std::invalid_argument("right-hand side and iterate are in different sectors");
+  Env e;
+  env_unit(e, 1);
+  for (int k = 0; k < L; ++k) {
+    Env o;
+    ov_left(e, U[k], Fc[k], o);
+    e = std::move(o);
+  }
+  double v;
+  d2h(&v, e.d.p, sizeof(double), stream);
+  return v;
+}
+
+double Engine::functional_value() {
+  if (opts.functional == 0) return energy();
+  const double a = energy();  // <U|A|U>, U of unit norm
+  return 0.5 * xscale * xscale * a - xscale * overlap_with_rhs();
 }
 
 void Engine::get_mps(int* r, double* const* Uh, int32_t* const* q) {
@@ -1881,9 +1978,10 @@ void Engine::get_mps(int* r, double* const* Uh, int32_t* const* q) {
     std::vector<double> h(c.elems());
     download(h.data(), c.d, h.size() * sizeof(double), stream);
     const int rrp = c.rrp();
+    const double f = (opts.functional == 1 && k == L - 1) ? xscale : 1.0;
     for (int a = 0; a < c.rl; ++a)
       for (int s = 0; s < 4; ++s)
-        for (int b = 0; b < c.rr; ++b) Uh[k][((size_t)a * 4 + s) * c.rr + b] = h[((size_t)a * 4 + s) * rrp + b];
+        for (int b = 0; b < c.rr; ++b) Uh[k][((size_t)a * 4 + s) * c.rr + b] = f * h[((size_t)a * 4 + s) * rrp + b];
   }
   if (q)
     for (int k = 0; k <= L; ++k) {
@@ -1911,10 +2009,12 @@ void Engine::checkpoint(int op) {
   if (op == 0) {
     if (!have_mps) throw std::logic_error("checkpoint: no iterate to keep");
     copy(U, Usaved);
+    xscale_saved = xscale;
   } else if (op == 1) {
     if (Usaved.empty()) throw std::logic_error("checkpoint: nothing kept");
     if ((int)Usaved.size() != L) throw std::logic_error("checkpoint: kept iterate does not fit the MPO");
     copy(Usaved, U);
+    xscale = xscale_saved;
     free_caches();
     have_mps = true;
   } else {
@@ -2703,6 +2803,139 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
 }
 
 // ---------------------------------------------------------------------------
+// linear-system functional: projected right-hand side and conjugate gradients
+// ---------------------------------------------------------------------------
+
+// P^T F of the window in its dense layout [rlp][nphys][rrp]: the overlap environments FLe
+// ([1][rl][rFl]) and FRe ([1][rr][rFr]) with F's cores of the window (one or two) between.
+static void local_rhs(Engine& E, const Window& w, const Env& FLe, const Env& FRe, const Core* F1, const Core* F2,
+                      double* b) {
+  const int rFl = F1->rlp(), rFr = (F2 ? F2 : F1)->rrp();
+  const int np = w.nphys;
+  if (FLe.rb != w.rl || FRe.rb != w.rr || FLe.rk != F1->rl || FRe.rk != (F2 ? F2 : F1)->rr)
+    throw std::runtime_error("projected right-hand side: shape mismatch");
+  DevMem T, Y1;
+  const double* Ft = F1->d.as<double>();
+  if (F2) {
+    // F1 F2 -> [rFl][4][4][rFr]
+    const int kp = F1->rrp();
+    T.ensure(sizeof(double) * (size_t)rFl * 16 * rFr);
+    GemmArgs g{};
+    g.M = 4 * rFl; g.N = 4 * rFr; g.K = kp; g.batch = 1; g.kin = kp;
+    g.sAm = kp; g.sAkk = 1; g.sBkk = 4LL * rFr; g.sBn = 1; g.sCm = 4LL * rFr; g.alpha = 1.0; g.beta = 0.0;
+    gemm<double>(g, F1->d.as<double>(), F2->d.as<double>(), T.as<double>(), true, true, E.stream);
+    Ft = T.as<double>();
+  }
+  // Y1[a][(s..)][bF] = sum_aF FL[a][aF] Ft[aF][(s..)][bF]
+  Y1.ensure(sizeof(double) * (size_t)w.rlp * np * rFr);
+  GemmArgs g{};
+  g.M = w.rlp; g.N = np * rFr; g.K = rFl; g.batch = 1; g.kin = rFl;
+  g.sAm = rFl; g.sAkk = 1; g.sBkk = (long long)np * rFr; g.sBn = 1; g.sCm = (long long)np * rFr;
+  g.alpha = 1.0; g.beta = 0.0;
+  gemm<double>(g, FLe.d.as<double>(), Ft, Y1.as<double>(), true, true, E.stream);
+  // b[(a s..)][b'] = sum_bF Y1[(a s..)][bF] FR[b'][bF]
+  GemmArgs h{};
+  h.M = w.rlp * np; h.N = w.rrp; h.K = rFr; h.batch = 1; h.kin = rFr;
+  h.sAm = rFr; h.sAkk = 1; h.sBkk = 1; h.sBn = rFr; h.sCm = w.rrp; h.alpha = 1.0; h.beta = 0.0;
+  gemm<double>(h, Y1.as<double>(), FRe.d.as<double>(), b, true, false, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+}
+
+// Micro-step of the linear-system functional: minimise 1/2 w.Aw - b.w over the allowed
+// entries, i.e. solve P^T A P w = P^T F (A symmetric positive definite), by conjugate
+// gradients preconditioned with the diagonal, from the warm start x, until the residual is
+// <= tol |b|.  theta returns the local minimum 1/2 w.Aw - b.w = -(w.b + w.r)/2.
+static Davidson pcg(Engine& E, Window& w, const QnIndex& qi, double* x, const double* bdense, double tol,
+                    int maxiter) {
+  Davidson res;
+  const size_t nd = (size_t)w.rlp * w.nphys * w.rrp;
+  const size_t n = qi.ncp;
+  const int* idx = qi.idx.as<int>();
+  E.dav_V.ensure(sizeof(double) * n * 4);
+  E.dav_AV.ensure(sizeof(double) * n * 2);
+  E.dav_xd.ensure(sizeof(double) * nd);
+  E.dav_yd.ensure(sizeof(double) * nd);
+  E.dav_dc.ensure(sizeof(double) * n);
+  E.dav_c.ensure(sizeof(double) * 8);
+  E.wsp.ensure(sizeof(double) * (size_t)kDotBlocks * 2);
+  double* xc = E.dav_V.as<double>();
+  double* r = xc + n;
+  double* z = xc + 2 * n;
+  double* pv = xc + 3 * n;
+  double* q = E.dav_AV.as<double>();
+  double* bc = q + n;
+  double* xd = E.dav_xd.as<double>();
+  double* yd = E.dav_yd.as<double>();
+  double* dg = E.dav_dc.as<double>();
+  double* cdev = E.dav_c.as<double>();
+  double* part = E.wsp.as<double>();
+  auto dot = [&](const double* a, const double* b2) {
+    multi_dot(a, n, 1, b2, n, cdev, part, kDotBlocks, E.stream);
+    double v;
+    d2h(&v, cdev, sizeof(double), E.stream);
+    return v;
+  };
+  auto product = [&](const double* v, double* av) {
+    scatter_idx(xd, v, idx, qi.nc, E.stream);
+    window_matvec(E, w, xd, yd, TT_F64);
+    gather_idx(av, yd, idx, qi.nc, n, E.stream);
+    res.matvecs++;
+    res.matvecs64++;
+  };
+  // z = r / diag (the kernel returns r / (theta - d))
+  auto prec = [&](const double* rv, double* zv) {
+    precond(zv, rv, dg, 0.0, nullptr, n, E.stream);
+    scale(zv, -1.0, n, E.stream);
+  };
+  fill(xd, sizeof(double) * nd, E.stream);
+  gather_idx(dg, w.diag.as<double>(), idx, qi.nc, n, E.stream);
+  gather_idx(bc, bdense, idx, qi.nc, n, E.stream);
+  gather_idx(xc, x, idx, qi.nc, n, E.stream);
+  const double bnorm = std::sqrt(std::max(dot(bc, bc), 0.0));
+  if (!(bnorm > 0.0)) {
+    // P^T F = 0: the minimiser is w = 0
+    fill(x, sizeof(double) * nd, E.stream);
+    res.converged = true;
+    res.theta = 0.0;
+    HC(hipStreamSynchronize(E.stream));
+    return res;
+  }
+  product(xc, q);
+  axpby(r, 1.0, bc, -1.0, q, n, E.stream);  // r = b - A x
+  double rn = std::sqrt(std::max(dot(r, r), 0.0));
+  prec(r, z);
+  HC(hipMemcpyAsync(pv, z, sizeof(double) * n, hipMemcpyDeviceToDevice, E.stream));
+  double rz = dot(r, z);
+  while (rn > tol * bnorm && res.matvecs < maxiter) {
+    product(pv, q);
+    const double pq = dot(pv, q);
+    if (!(pq > 0.0)) throw std::runtime_error("linear-system functional: the local operator is not positive definite");
+    const double alpha = rz / pq;
+    axpy(xc, alpha, pv, n, E.stream);
+    axpy(r, -alpha, q, n, E.stream);
+    rn = std::sqrt(std::max(dot(r, r), 0.0));
+    ++res.iters;
+    if (rn <= tol * bnorm) break;
+    prec(r, z);
+    const double rz2 = dot(r, z);
+    axpby(pv, 1.0, z, rz2 / rz, pv, n, E.stream);  // p = z + beta p
+    rz = rz2;
+  }
+  res.converged = rn <= tol * bnorm;
+  res.resid = rn / bnorm;
+  res.theta = -0.5 * (dot(xc, bc) + dot(xc, r));
+  fill(x, sizeof(double) * nd, E.stream);
+  scatter_idx(x, xc, idx, qi.nc, E.stream);
+  HC(hipStreamSynchronize(E.stream));
+  return res;
+}
+
+// Linear-system micro-step of the window at bond (b, b+1) (two-site: C, D the current
+// cores) or at site b (one-site: C the current core, D unused); x the warm start.
+static Davidson local_lin(Engine& E, const Env& Le, int b, const Env& Re, DevMem& x, const Core& C, const Core* D,
+                          const Env& FLe, const Env& FRe, const Core& F1, const Core* F2);
+
+// ---------------------------------------------------------------------------
 // one-site local problems (Algorithm 2, one-site branch)
 // ---------------------------------------------------------------------------
 
@@ -2793,6 +3026,25 @@ static Davidson local_eig1(Engine& E, const Env& Le, int k, const Env& Re, DevMe
   return r;
 }
 
+static Davidson local_lin(Engine& E, const Env& Le, int b, const Env& Re, DevMem& x, const Core& C, const Core* D,
+                          const Env& FLe, const Env& FRe, const Core& F1, const Core* F2) {
+  const bool one = D == nullptr;
+  QnIndex mask = one ? build_index1(E, C.rl, C.ql, C.rr, C.qr) : build_index(E, C.rl, C.ql, D->rr, D->qr);
+  Window w;
+  double tph = E.now();
+  if (one) prepare_window1(E, w, Le, b, Re, C.ql, C.qr);
+  else prepare_window(E, w, Le, b, Re, TT_F64, C.ql, D->qr);
+  DevMem bd;
+  bd.ensure(sizeof(double) * (size_t)w.rlp * w.nphys * w.rrp);
+  local_rhs(E, w, FLe, FRe, &F1, F2, bd.as<double>());
+  E.ph[2] += E.now() - tph;
+  tph = E.now();
+  Davidson r = pcg(E, w, mask, x.as<double>(), bd.as<double>(), E.opts.dav_tol, E.opts.dav_maxiter);
+  E.ph[3] += E.now() - tph;
+  if (!r.converged) E.warn = std::max(E.warn, (int)TT_WNOCONV);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Step 1 + Step 2
 // ---------------------------------------------------------------------------
@@ -2821,13 +3073,21 @@ void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
   HC(hipMemcpyAsync(center.d.p, src.Wc[s].d.p, src.Wc[s].d.n, hipMemcpyDeviceToDevice, stream));
   Env Lrun;
   const Env* Lcur = &src.Lenv[s];
+  // linear-system functional: the warm start carries the iterate's norm, and the overlap
+  // environment with F moves along with Lrun
+  const bool lin = opts.functional == 1;
+  Env FLrun;
+  const Env* FLcur = lin ? &src.FL[s] : nullptr;
+  if (lin) scale(center.d.as<double>(), src.xscale, center.elems(), stream);
   DevMem x;
   for (int b = s; b <= blast; ++b) {
     const Core& next = src.Vc[b + 1];
     two_site(*this, center, next, x);
     std::vector<DevMem> more;
-    Davidson r = local_eig(*this, *Lcur, b, src.Renv[b + 2], x, center, next,
-                           b == blast && opts.coarse_k > 1 ? &more : nullptr);
+    Davidson r = lin ? local_lin(*this, *Lcur, b, src.Renv[b + 2], x, center, &next, *FLcur, src.FR[b + 2],
+                                 src.Fc[b], &src.Fc[b + 1])
+                     : local_eig(*this, *Lcur, b, src.Renv[b + 2], x, center, next,
+                                 b == blast && opts.coarse_k > 1 ? &more : nullptr);
     S.matvecs += r.matvecs;
     S.matvecs64 += r.matvecs64;
     S.E = r.theta;
@@ -2863,6 +3123,12 @@ void Engine::solve_subdomain(const Engine& src, int j, int s, int e, Sub& S) {
       env_left(*Lcur, N, N, b, nl);
       Lrun = std::move(nl);
       Lcur = &Lrun;
+      if (lin) {
+        Env nf;
+        ov_left(*FLcur, N, src.Fc[b], nf);
+        FLrun = std::move(nf);
+        FLcur = &FLrun;
+      }
       ph[5] += now() - tph;
     } else {
       double nc = norm_dev(*this, C.d.as<double>(), C.elems());
@@ -2900,10 +3166,16 @@ void Engine::solve_subdomain1(const Engine& src, int j, int s, int e, Sub& S) {
   copy_core(src.Wc[s], center);
   Env Lrun;
   const Env* Lcur = &src.Lenv[s];
+  const bool lin = opts.functional == 1;
+  Env FLrun;
+  const Env* FLcur = lin ? &src.FL[s] : nullptr;
+  if (lin) scale(center.d.as<double>(), src.xscale, center.elems(), stream);
   for (int k = s; k <= e; ++k) {
     std::vector<DevMem> more;
-    Davidson r = local_eig1(*this, *Lcur, k, src.Renv[k + 1], center.d, center,
-                            k == e && opts.coarse_k > 1 ? &more : nullptr);
+    Davidson r = lin ? local_lin(*this, *Lcur, k, src.Renv[k + 1], center.d, center, nullptr, *FLcur, src.FR[k + 1],
+                                 src.Fc[k], nullptr)
+                     : local_eig1(*this, *Lcur, k, src.Renv[k + 1], center.d, center,
+                                  k == e && opts.coarse_k > 1 ? &more : nullptr);
     S.matvecs += r.matvecs;
     S.matvecs64 += r.matvecs64;
     S.E = r.theta;
@@ -2919,10 +3191,21 @@ void Engine::solve_subdomain1(const Engine& src, int j, int s, int e, Sub& S) {
       env_left(*Lcur, center, center, k, nl);
       Lrun = std::move(nl);
       Lcur = &Lrun;
+      if (lin) {
+        Env nf;
+        ov_left(*FLcur, center, src.Fc[k], nf);
+        FLrun = std::move(nf);
+        FLcur = &FLrun;
+      }
       ph[5] += now() - tph;
       S.mod.push_back(std::move(center));
       center = std::move(next);
     } else {
+      if (lin) {
+        // the coarse step only needs the direction of each update
+        const double nc = norm_dev(*this, center.d.as<double>(), center.elems());
+        if (nc > 0.0) scale(center.d.as<double>(), 1.0 / nc, center.elems(), stream);
+      }
       // Extension One: every further eigenvector of the last micro-step gives an update
       // of its own, sharing cores s..e-1 with this one
       for (size_t q = 0; q < more.size(); ++q) {
@@ -3142,6 +3425,36 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
   // (b, b + 1) Renv[b + 2]
   const int kmin = opts.one_site ? 1 : 2;
   for (int k = L - 1; k >= kmin; --k) env_right(Renv[k + 1], Vc[k], Vc[k], k, Renv[k]);
+  if (opts.functional == 1) {
+    // overlap environments with the right-hand side: FL at the subdomain starts (and the
+    // whole chain <tau(U)|F>), FR at every bond the local problems read
+    if (!have_rhs) throw std::logic_error("the linear-system functional needs tt_set_rhs");
+    if (Fc.size() != (size_t)L || Fc[L - 1].qr != U[L - 1].qr)
+      throw std::invalid_argument("right-hand side and iterate are in different sectors");
+    FL.clear(); FL.resize(L + 1);
+    FR.clear(); FR.resize(L + 1);
+    std::vector<char> need(L + 1, 0);
+    for (int j = 0, st = 0; j < nsub; ++j) {
+      need[st] = 1;
+      st += lengths[j];
+    }
+    Env cur;
+    env_unit(cur, 1);
+    for (int k = 0; k < L; ++k) {
+      if (need[k]) {
+        FL[k].R = cur.R; FL[k].rb = cur.rb; FL[k].rk = cur.rk;
+        FL[k].d.ensure(cur.d.n);
+        HC(hipMemcpyAsync(FL[k].d.p, cur.d.p, cur.d.n, hipMemcpyDeviceToDevice, stream));
+      }
+      Env nx;
+      ov_left(cur, U[k], Fc[k], nx);
+      cur = std::move(nx);
+    }
+    d2h(&uf, cur.d.p, sizeof(double), stream);
+    env_unit(FR[L], 1);
+    for (int k = L - 1; k >= 1; --k) ov_right(FR[k + 1], Vc[k], Fc[k], FR[k]);
+    HC(hipStreamSynchronize(stream));
+  }
   ph[1] += now() - tph;
   if (verbose)
     std::fprintf(stderr, "[tt] step 1 done: LQ sweep %.2fs, environments %.2fs\n", ph[0], ph[1]);
@@ -3205,7 +3518,21 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   double tph = now();
   const int P = (int)subs.size();
   const int n = P + 1;
-  std::vector<double> S((size_t)n * n, 0.0), A((size_t)n * n, 0.0);
+  const bool lin = opts.functional == 1;
+  std::vector<double> S((size_t)n * n, 0.0), A((size_t)n * n, 0.0), bvec(n, 0.0);
+  if (lin) bvec[0] = uf;
+  // sum over the valid block of El[a][f] Er[a][f] (two one-channel environments at one bond)
+  auto ov_close2 = [](Engine& W, const Env& El, const Env& Er) {
+    if (El.rb != Er.rb || El.rk != Er.rk) throw std::runtime_error("overlap closure: shape mismatch");
+    const int p = padr(El.rb), q = padr(El.rk);
+    std::vector<double> a((size_t)p * q), b((size_t)p * q);
+    download(a.data(), El.d, a.size() * sizeof(double), W.stream);
+    download(b.data(), Er.d, b.size() * sizeof(double), W.stream);
+    double t = 0.0;
+    for (int i = 0; i < El.rb; ++i)
+      for (int j = 0; j < El.rk; ++j) t += a[(size_t)i * q + j] * b[(size_t)i * q + j];
+    return t;
+  };
   // <U0|H|U0> and <U0|U0> = 1 (normalised iterate)
   {
     Env e;
@@ -3288,6 +3615,17 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
     }
     A[(size_t)j * n + j] = W.env_close(eH, Renv[Sj.t + 1]);
     S[(size_t)j * n + j] = ov_close(W, eS);
+    if (lin) {
+      // b_j = <U^j|F>: the overlap chain with F through the update's sites
+      Env ef, tf;
+      const Env* cf = &FL[Sj.s];
+      for (int k = Sj.s; k <= Sj.t; ++k) {
+        W.ov_left(*cf, Sj.mod[k - Sj.s], Fc[k], tf);
+        ef = std::move(tf);
+        cf = &ef;
+      }
+      bvec[j] = ov_close2(W, ef, FR[Sj.t + 1]);
+    }
   };
   // entries (i, j), j > i: one chain with bra Ũ^i and ket U from bond s_i,
   // branching into ket Ũ^j at every later subdomain
@@ -3391,18 +3729,43 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   std::vector<double> wa, Va;
   jacobi_eig(p, At, wa, Va);
   std::vector<double> c(n, 0.0);
-  for (int i = 0; i < n; ++i)
-    for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * Va[(size_t)a * p];
-  int imax = 0;
-  for (int i = 1; i < n; ++i)
-    if (std::fabs(c[i]) > std::fabs(c[imax])) imax = i;
-  if (c[imax] < 0)
-    for (double& v : c) v = -v;
+  double lam_out = 0.0;
+  if (!lin) {
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * Va[(size_t)a * p];
+    int imax = 0;
+    for (int i = 1; i < n; ++i)
+      if (std::fabs(c[i]) > std::fabs(c[imax])) imax = i;
+    if (c[imax] < 0)
+      for (double& v : c) v = -v;
+    lam_out = wa[0];
+  } else {
+    // coarse linear system (X^T A X) y = X^T b on the numerical range of S, c = X y;
+    // the coarse minimum of J is 1/2 c.Ac - b.c
+    if (!(wa[0] > 0.0)) throw std::runtime_error("linear-system functional: the coarse operator is not positive definite");
+    std::vector<double> rb(p, 0.0), y(p, 0.0);
+    for (int a = 0; a < p; ++a)
+      for (int i = 0; i < n; ++i) rb[a] += X[(size_t)i * p + a] * bvec[i];
+    for (int m = 0; m < p; ++m) {
+      double proj = 0.0;
+      for (int a = 0; a < p; ++a) proj += Va[(size_t)a * p + m] * rb[a];
+      for (int a = 0; a < p; ++a) y[a] += Va[(size_t)a * p + m] * proj / wa[m];
+    }
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * y[a];
+    double cAc = 0.0, bc = 0.0;
+    for (int i = 0; i < n; ++i) {
+      bc += bvec[i] * c[i];
+      for (int j = 0; j < n; ++j) cAc += c[i] * A[(size_t)i * n + j] * c[j];
+    }
+    lam_out = 0.5 * cAc - bc;
+  }
+  coarse_b = bvec;
   int status = (p < n) ? TT_WRANKDEF : TT_OK;
   if (Sout) std::copy(S.begin(), S.end(), Sout);
   if (Aout) std::copy(A.begin(), A.end(), Aout);
   if (cout) std::copy(c.begin(), c.end(), cout);
-  if (lam) *lam = wa[0];
+  if (lam) *lam = lam_out;
   if (rank) *rank = p;
 
   // ---- Step 4: block TT of sum_j c_j Ũ^j and TT rounding ----
@@ -3558,9 +3921,11 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   scale(T[L - 1].d.as<double>(), 1.0 / nr, T[L - 1].elems(), stream);
   HC(hipStreamSynchronize(stream));
   U = std::move(T);
+  // the linear-system functional keeps the norm of the compressed combination
+  if (lin) xscale = nr;
   free_caches();
   const double tc2 = now();
-  double En = energy();
+  double En = functional_value();
   ph[7] += now() - tph;
   if (verbose)
     std::fprintf(stderr,

@@ -171,7 +171,16 @@ class Engine {
   std::vector<int>& Rb;
   std::vector<Labels>& chan_q;
   std::vector<DevMem>& chan_q_dev;
-  std::vector<Core> U;                 // current left-orthogonal iterate
+  std::vector<Core> U;                 // current left-orthogonal iterate (unit norm)
+  // linear-system functional: the iterate is X = xscale * tau(U); F its right-hand side;
+  // FL[k] = <U_0..U_{k-1} | F_0..F_{k-1}> at subdomain starts, FR[k] = <V_k..V_{L-1} | F_k..>
+  // (one-channel environments [1][r_bra][r_F]); uf = <tau(U)|F>; coarse_b the coarse right-hand side
+  double xscale = 1.0, xscale_saved = 1.0;
+  std::vector<Core> Fc;
+  bool have_rhs = false;
+  std::vector<Env> FL, FR;
+  double uf = 0.0;
+  std::vector<double> coarse_b;
   std::vector<Core> Usaved;            // device copy kept by tt_mps_checkpoint
   bool have_mpo = false, have_mps = false;
 
@@ -237,6 +246,12 @@ class Engine {
   void set_mps(int L, const int* r, const double* const* Uh, const int32_t* const* q);
   void get_mps(int* r, double* const* Uh, int32_t* const* q);
   double energy();
+  double functional_value();  // J(X): Rayleigh quotient, or 1/2 <X,AX> - <F,X>
+  void set_rhs(int L, const int* r, const double* const* Fh, const int32_t* const* q);
+  double overlap_with_rhs();  // <tau(U)|F>
+  // one-channel overlap environments (bra, ket may differ in bond dimensions and labels)
+  void ov_left(const Env& in, const Core& bra, const Core& ket, Env& out);
+  void ov_right(const Env& in, const Core& bra, const Core& ket, Env& out);
   void checkpoint(int op);  // 0: keep a device copy of the iterate, 1: make it current again
 
   // algorithm

@@ -126,6 +126,10 @@ void gather2d(const double* src, long long lds, const int* rows, int nr, const i
 // tri: 0 full, 1 keep i <= j (upper), 2 keep j <= i (lower); other entries written as 0
 void scatter2d(const double* src, long long sr, long long sc, const int* rows, int nr, const int* cols, int nc,
                double* dst, long long ldd, double alpha, const double* rs, const double* cs, int tri, hipStream_t s);
+// Core with permuted bonds: out[a][s][b] = in[pl[a]][s][pr[b]] for a < rl, b < rr
+// (padded strides irp/orp of the right bonds); other entries of out are left alone.
+void permute_core(const double* in, int irp, const int* pl, const int* pr, int rl, int rr, double* out, int orp,
+                  hipStream_t s);
 // copy a strided 3-D block: dst[i*d0 + j*d1 + k] = alpha * src[i*s0 + j*s1 + k]
 // (accumulate: dst[...] += alpha * src[...])
 void copy3d(const double* src, long long s0, long long s1, double* dst, long long d0, long long d1, int n0, int n1,

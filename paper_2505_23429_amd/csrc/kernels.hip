@@ -1215,6 +1215,25 @@ void scatter2d(const double* src, long long sr, long long sc, const int* rows, i
   HIPCHECK(hipGetLastError());
 }
 
+__global__ void permute_core_kernel(const double* in, int irp, const int* pl, const int* pr, int rl, int rr,
+                                    double* out, int orp) {
+  const long long tot = (long long)rl * 4 * rr;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(t % rr);
+    const long long r = t / rr;
+    const int s = (int)(r % 4);
+    const int a = (int)(r / 4);
+    out[((long long)a * 4 + s) * orp + b] = in[((long long)pl[a] * 4 + s) * irp + pr[b]];
+  }
+}
+void permute_core(const double* in, int irp, const int* pl, const int* pr, int rl, int rr, double* out, int orp,
+                  hipStream_t s) {
+  if ((long long)rl * rr == 0) return;
+  hipLaunchKernelGGL(permute_core_kernel, dim3(nblocks((size_t)rl * 4 * rr)), dim3(256), 0, s, in, irp, pl, pr, rl, rr,
+                     out, orp);
+  HIPCHECK(hipGetLastError());
+}
+
 __global__ void copy3d_kernel(const double* src, long long s0, long long s1, double* dst, long long d0, long long d1,
                               int n0, int n1, int n2, double alpha, int acc) {
   const long long tot = (long long)n0 * n1 * n2;

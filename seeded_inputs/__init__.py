@@ -14,6 +14,18 @@ experiments, Section 4, which are not available here):
   (chemists' notation, 8-fold symmetric, positive semidefinite);
 * ``numpy.random.default_rng(seed)`` draws ``A`` first, then ``C_1..C_K``.
 
+Linear-system workload (eq. energy_lin needs a symmetric positive definite A and a
+right-hand side F): A is the Hamiltonian of the same recipe with the one-body
+integrals shifted by ``sigma / N`` on the diagonal, which adds ``sigma`` on the
+N-electron sector.  ``sigma = 1 + N * g`` with ``g`` the Gershgorin bound
+``max_p sum_q |M_pq|`` of ``M = h - 1/2 sum_k B_k B_k``: the two-electron part equals
+``1/2 sum_k (sum B_k[p,q] E_pq)^2 - 1/2 sum (B_k B_k)_ps E_ps``, whose first term is
+positive semidefinite, so ``H >= sum M_ps E_ps >= -N g`` and ``A >= 1`` there.  F and
+the initial iterate of this workload are random QN-consistent TTs of the same sector
+scaled to unit norm (``unit_tt``: the norm of a random TT grows geometrically with L).
+This bound and that norm are the only arithmetic of the module beyond draws and
+label structure (they define inputs).
+
 Local basis of one spatial orbital (one tensor-train site, ``n = 4``):
 ``|0>, |up>, |dn>, |updn>`` with charges ``(N, 2Sz) = (0,0), (1,1), (1,-1), (2,0)``.
 """
@@ -71,6 +83,34 @@ def integrals(L: int, n_factors: int, seed: int):
 def workload_integrals(idx: int):
     w = WORKLOADS[idx]
     return integrals(w.L, w.n_factors, w.seed)
+
+
+def linear_system(L: int, n_elec: int, seed: int, chi_f: int):
+    """Inputs of the linear-system functional: ``(h_shift, B, sigma, F_cores,
+    F_labels)``: the one-body integrals of ``integrals(L, L, seed)`` shifted so that
+    A = H(h_shift, B) >= 1 on the ``n_elec``-electron sector (module docstring), and a
+    random TT F of unit norm (bond dimension ``chi_f``, TT seed ``seed + 7``) of that
+    sector with Sz = 0.  The initial iterate is ``unit_tt(random_mps(...))``."""
+    h, B = integrals(L, L, seed)
+    M = h - 0.5 * np.einsum("kpq,kqs->ps", B, B)
+    g = float(np.max(np.sum(np.abs(M), axis=1)))
+    sigma = 1.0 + n_elec * g
+    h_shift = h + (sigma / n_elec) * np.eye(L)
+    F, Fl = random_mps(L, n_elec, 0, chi_f, seed + 7)
+    return h_shift, B, sigma, unit_tt(F), Fl
+
+
+def unit_tt(cores):
+    """The TT scaled to unit norm (last core divided by the norm, by transfer matrices)."""
+    E = np.ones((1, 1))
+    for U in cores:
+        r, n, r2 = U.shape
+        t = (E @ U.reshape(r, n * r2)).reshape(r * n, r2)   # [a s, d] = sum_b E[a, b] U[b, s, d]
+        E = U.reshape(r * n, r2).T @ t                      # [c, d] = sum_{a s} U[a, s, c] t[a s, d]
+    nrm = math.sqrt(float(E[0, 0]))
+    out = [c.copy() for c in cores]
+    out[-1] = out[-1] / nrm
+    return out
 
 
 # ---------------------------------------------------------------------------

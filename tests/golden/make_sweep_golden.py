@@ -6,6 +6,7 @@ Run from the repository root:
     python tests/golden/make_sweep_golden.py L16_chi128
     python tests/golden/make_sweep_golden.py L12_chi160_k2
     python tests/golden/make_sweep_golden.py L12_chi160_1s
+    python tests/golden/make_sweep_golden.py L12_chi160_lin
 
 Every value is computed by the environment-chain oracle (``oracle.chain``,
 with the oracle's own MPO ``oracle.mpo``) from the seeded inputs of
@@ -47,6 +48,42 @@ CASES = {
     # one-site micro-steps (Algorithm 2, one-site branch)
     "L12_chi160_1s": (12, 1012, 160, 23, (4, 4, 4), 1e-11, 1, 1),
 }
+
+
+# linear-system functional (inputs of seeded_inputs.linear_system):
+# name: (L, seed, chi, TT seed, subdomain lengths, CG tolerance, bond dimension of F, sites)
+CASES_LIN = {
+    "L12_chi160_lin": (12, 1012, 160, 23, (4, 4, 4), 1e-12, 32, 2),
+}
+
+
+def run_linear(name):
+    L, seed, chi, mps_seed, lengths, tol, chi_f, sites = CASES_LIN[name]
+    t0 = time.time()
+    hs, B, sigma, F, Fl = S.linear_system(L, L, seed, chi_f)
+    mpo = OM.build_mpo(hs, B)
+    cores, labels = S.random_mps(L, L, 0, chi, mps_seed)
+    cores = S.unit_tt(cores)
+    oc = T.left_orthogonalize(cores, labels)
+
+    def log(msg):
+        print(f"[{time.time() - t0:8.1f}s] {msg}", flush=True)
+
+    rep = CH.a2dmrg_lin_sweep(mpo, oc, labels, chi, lengths, F, tol=tol, sites=sites, log=log)
+    out = {
+        "case": name, "functional": "linear", "L": L, "n_elec": L, "two_sz": 0, "seed": seed, "sigma": sigma,
+        "chi": chi, "mps_seed": mps_seed, "chi_f": chi_f, "lengths": list(lengths), "cg_tol": tol, "sites": sites,
+        "coarse_eps": 1e-8, "svd_cutoff": 1e-12, "tie_rel": 1e-10,
+        "J_before": rep.J_before, "E_local": list(map(float, rep.E_local)), "oracle_products": rep.matvecs,
+        "S": rep.S.tolist(), "A": rep.A.tolist(), "b": rep.b.tolist(), "c": rep.c.tolist(),
+        "J_coarse": rep.J_coarse, "rankS": rep.rankS, "J_after": rep.J_new,
+        "bond_dims_after": [int(q.shape[0]) for q in rep.labels], "oracle_seconds": time.time() - t0,
+    }
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"sweep_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    log(f"wrote {path}: J_before={rep.J_before:.12f} J_coarse={rep.J_coarse:.12f} J_after={rep.J_new:.12f}")
 
 
 def gauge_fix(S_, A_, c):
@@ -93,5 +130,5 @@ def run(name):
 
 
 if __name__ == "__main__":
-    for n in sys.argv[1:] or sorted(CASES):
-        run(n)
+    for n in sys.argv[1:] or sorted(CASES) + sorted(CASES_LIN):
+        run_linear(n) if n in CASES_LIN else run(n)

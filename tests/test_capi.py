@@ -46,6 +46,7 @@ def test_default_options_and_invalid_create():
     ("chi_max", 0), ("dav_maxiter", 0), ("dav_maxsub", 3), ("matvec_prec", 3), ("matvec_prec", -1),
     ("sub_workers", -1), ("sub_workers", 65), ("mix_stage", 3), ("mix_stage", -1), ("svd_lds", 2),
     ("worker_alloc_limit", -1), ("coarse_k", 0), ("coarse_k", 9), ("one_site", 2), ("one_site", -1),
+    ("functional", 2), ("functional", -1),
 ])
 def test_create_rejects_each_invalid_option(field, value):
     """tt_create validates the options before it touches the device: every value outside
@@ -73,6 +74,23 @@ def test_one_site_needs_fp64_block_sparse_products(field, value):
     lib.tt_default_opts(C.byref(o))
     assert (o.one_site, o.coarse_k) == (0, 1)
     o.one_site = 1
+    setattr(o, field, value)
+    h = C.c_void_p()
+    assert lib.tt_create(C.byref(o), C.byref(h)) == _lib.TT_EINVAL
+    assert not h.value
+
+
+@pytest.mark.parametrize("field,value", [("matvec_prec", 1), ("matvec_prec", 2), ("qn_skip", 0), ("coarse_k", 2)])
+def test_linear_functional_needs_fp64_block_sparse_products(field, value):
+    """The linear-system functional solves its micro-steps by FP64 conjugate gradients
+    on the block-sparse product and has no several-eigenvector variant."""
+    from paper_2505_23429_amd import _lib
+
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.tt_default_opts(C.byref(o))
+    assert o.functional == 0
+    o.functional = 1
     setattr(o, field, value)
     h = C.c_void_p()
     assert lib.tt_create(C.byref(o), C.byref(h)) == _lib.TT_EINVAL
