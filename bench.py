@@ -395,6 +395,11 @@ def main():
                     help="the linear-system functional 1/2 <X,AX> - <F,X> (A: the workload's Hamiltonian shifted "
                          "to be positive definite, F: a random TT of bond dimension --chi-f; FP64 products)")
     ap.add_argument("--chi-f", type=int, default=64)
+    ap.add_argument("--lengths", default="",
+                    help="subdomain lengths instead of the workload's: comma-separated, or one integer m for "
+                         "subdomains of m sites")
+    ap.add_argument("--coarse-krylov", action="store_true",
+                    help="Step 3 by Lanczos without forming the coarse Hamiltonian matrix")
     ap.add_argument("--one-site", action="store_true",
                     help="one-site micro-steps (Algorithm 2, one-site branch; FP64 products) instead of two-site")
     ap.add_argument("--coarse-k", type=int, default=1,
@@ -426,6 +431,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w, lengths = workload(args.workload)
+    if args.lengths:
+        parts = [int(x) for x in args.lengths.split(",")]
+        if len(parts) == 1:
+            m = parts[0]
+            lengths = [m] * (w.L // m) + ([w.L % m] if w.L % m else [])
+        else:
+            lengths = parts
+        if sum(lengths) != w.L:
+            raise SystemExit(f"--lengths must sum to L = {w.L}")
     chi = args.chi or w.chi
     t0 = time.perf_counter()
     if args.linear:
@@ -444,7 +458,8 @@ def main():
         tol, maxiter, refine = (w.dav_tol if prec == "f64" else 1e-5), args.dav_maxiter or 40, False
     ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                   refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=args.sub_workers,
-                  coarse_k=args.coarse_k, one_site=args.one_site, functional=functional)
+                  coarse_k=args.coarse_k, one_site=args.one_site, functional=functional,
+                  coarse_krylov=args.coarse_krylov)
     workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
     if args.linear:
@@ -494,7 +509,8 @@ def main():
         ctx.close()
         ctx1 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                        refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1,
-                       coarse_k=args.coarse_k, one_site=args.one_site, functional=functional)
+                       coarse_k=args.coarse_k, one_site=args.one_site, functional=functional,
+                  coarse_krylov=args.coarse_krylov)
         ctx1.set_mpo(mpo)
         if args.linear:
             ctx1.set_rhs(Fcores, Flabels)
@@ -525,6 +541,7 @@ def main():
                    "integrals_seed": w.seed, "mps_seed": w.seed + 1, "parallelism": "single-gpu",
                    "concurrent_subdomain_solves": workers, "coarse_k": args.coarse_k,
                    "micro_step": "one-site" if args.one_site else "two-site",
+                   "coarse_solve": "krylov (no coarse matrix)" if args.coarse_krylov else "explicit matrices",
                    "functional": "linear (1/2 <X,AX> - <F,X>)" if args.linear else "eigenvalue (Rayleigh quotient)",
                    **({"chi_f": args.chi_f, "shift_sigma": sigma} if args.linear else {})},
         "heff_tflops_block_sparse": round(float(stats[:, 2].sum()) / max(heff_ms * 1e-3, 1e-12) / 1e12, 3),
@@ -539,6 +556,7 @@ def main():
              "step2_wall"))},
     }
     out["set_mps_s"] = round(t_upload, 3)
+    out["coarse_matvecs"] = int(reps[-1].get("coarse_matvecs", 0))
     out["statuses"] = sorted({int(r["status"]) for r in reps})
     if not args.no_fp64 and prec != "f64":
         # the same sweep with FP64 products on the same GPU (same input, same solver settings);

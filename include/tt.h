@@ -129,6 +129,14 @@ typedef struct tt_opts {
                          Step 3 the coarse linear system (Section "The second-level
                          minimization", last remark).  Needs matvec_prec = TT_F64, qn_skip = 1
                          and coarse_k = 1 (EINVAL otherwise). */
+  int coarse_krylov;  /* 1: Step 3 without forming the coarse Hamiltonian matrix (Appendix on
+                         the second-level problem, Krylov remark, eq. aux_mat-vec_prod): S is
+                         formed, then the lowest eigenpair of the reduced problem comes from
+                         Lanczos iterations whose products z_i = <U^i|H|W(v)> contract every
+                         coarse state with the structured combination W(v) = sum_j v_j U^j (the
+                         block TT of Step 4, bonds regrouped by charge) through one left and
+                         one right environment chain and a branch per update.  The report's A
+                         is then NaN.  functional = 0 only (EINVAL otherwise). */
 } tt_opts;
 
 #define TT_MAX_SUB 64
@@ -159,6 +167,7 @@ typedef struct tt_sweep_report {
   int matvecs_f64[TT_MAX_SUB];     /* of matvecs[]: the products taken in FP64 */
   int nstates;                     /* coarse states n = nsub * coarse_k + 1: S, A are n x n, coef n */
   double rhs[TT_MAX_SUB + 1];      /* functional = 1: coarse right-hand side b_j = <F|U^j> */
+  int coarse_matvecs;              /* coarse_krylov = 1: products with the coarse matrix */
 } tt_sweep_report;
 
 void tt_default_opts(tt_opts* o);

@@ -34,7 +34,7 @@ class Opts(C.Structure):
         ("sub_workers", C.c_int), ("mix_stage", C.c_int), ("svd_lds", C.c_int),
         ("worker_alloc_limit", C.c_longlong), ("stream", C.c_void_p), ("dev_alloc", C.c_void_p),
         ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p), ("coarse_k", C.c_int),
-        ("one_site", C.c_int), ("functional", C.c_int),
+        ("one_site", C.c_int), ("functional", C.c_int), ("coarse_krylov", C.c_int),
     ]
 
 
@@ -54,6 +54,7 @@ class SweepReport(C.Structure):
         ("E_after", C.c_double), ("discarded", C.c_double), ("seconds", C.c_double * 4),
         ("flops_heff", C.c_double), ("seconds_heff", C.c_double), ("phase_seconds", C.c_double * 9),
         ("matvecs_f64", C.c_int * TT_MAX_SUB), ("nstates", C.c_int), ("rhs", C.c_double * (TT_MAX_SUB + 1)),
+        ("coarse_matvecs", C.c_int),
     ]
 
 

@@ -154,6 +154,7 @@ void tt_default_opts(tt_opts* o) {
   o->coarse_k = 1;
   o->one_site = 0;
   o->functional = 0;
+  o->coarse_krylov = 0;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -166,7 +167,8 @@ int tt_create(const tt_opts* opts, void** out) {
       opts->coarse_k > 8 || opts->one_site < 0 || opts->one_site > 1 ||
       (opts->one_site && (opts->matvec_prec != TT_F64 || !opts->qn_skip)) || opts->functional < 0 ||
       opts->functional > 1 ||
-      (opts->functional == 1 && (opts->matvec_prec != TT_F64 || !opts->qn_skip || opts->coarse_k != 1)))
+      (opts->functional == 1 && (opts->matvec_prec != TT_F64 || !opts->qn_skip || opts->coarse_k != 1)) ||
+      opts->coarse_krylov < 0 || opts->coarse_krylov > 1 || (opts->coarse_krylov && opts->functional != 0))
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);
@@ -280,6 +282,7 @@ int tt_sweep(void* ctx, int nsub, const int* lengths, tt_sweep_report* out) {
                               &out->discarded);
     if (E.opts.functional == 1)
       for (int i = 0; i < n && i < (int)E.coarse_b.size(); ++i) out->rhs[i] = E.coarse_b[i];
+    out->coarse_matvecs = E.coarse_matvecs;
     auto t3 = std::chrono::steady_clock::now();
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) {

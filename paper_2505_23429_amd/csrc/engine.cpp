@@ -14,6 +14,8 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <limits>
+#include <map>
 #include <numeric>
 #include <atomic>
 #include <exception>
@@ -3503,286 +3505,29 @@ void Engine::local_solve(int nsub, const int* lengths, double* Eloc, int* mv) {
 // ---------------------------------------------------------------------------
 // Step 3 + Step 4
 // ---------------------------------------------------------------------------
-static const Core& core_of(const Engine& E, int j, int k, bool V_suffix) {
-  // Ũ^j (j >= 1): U_k for k < s_j, mod for s_j..t_j, V_k beyond
-  const Engine::Sub& S = E.subs[j - 1];
-  if (k < S.s) return E.U[k];
-  if (k <= S.t) return S.mod[k - S.s];
-  (void)V_suffix;
-  return E.Vc[k];
-}
+// ---------------------------------------------------------------------------
+// Step 4's block TT of sum_j c_j U^j (state 0 the iterate, then the updates)
+// ---------------------------------------------------------------------------
+// Bond k (1..L-1) blocks: U (r_k), V (r_k, if some state ended before site k), and one
+// block per state that straddles the bond (several when Extension One keeps more than
+// one update of a subdomain).  Labels are those of the blocks in this order, so they
+// are grouped by charge within each block only.
+namespace {
+struct BondLayout {
+  int offU = -1, offV = -1, dim = 0;
+  int rU = 0, rV = 0;
+  std::vector<std::pair<int, int>> str;  // (state j, block offset)
+  Labels q;
+  int off_of(int j) const {
+    for (const auto& p : str)
+      if (p.first == j) return p.second;
+    return -1;
+  }
+};
+}  // namespace
 
-int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam, double* Eout, int* rank,
-                           double* disc) {
-  if (!have_local) throw std::logic_error("coarse_correct needs a preceding local_solve");
-  double tph = now();
+void Engine::combination_tt(const std::vector<double>& c, std::vector<Core>& T) {
   const int P = (int)subs.size();
-  const int n = P + 1;
-  const bool lin = opts.functional == 1;
-  std::vector<double> S((size_t)n * n, 0.0), A((size_t)n * n, 0.0), bvec(n, 0.0);
-  if (lin) bvec[0] = uf;
-  // sum over the valid block of El[a][f] Er[a][f] (two one-channel environments at one bond)
-  auto ov_close2 = [](Engine& W, const Env& El, const Env& Er) {
-    if (El.rb != Er.rb || El.rk != Er.rk) throw std::runtime_error("overlap closure: shape mismatch");
-    const int p = padr(El.rb), q = padr(El.rk);
-    std::vector<double> a((size_t)p * q), b((size_t)p * q);
-    download(a.data(), El.d, a.size() * sizeof(double), W.stream);
-    download(b.data(), Er.d, b.size() * sizeof(double), W.stream);
-    double t = 0.0;
-    for (int i = 0; i < El.rb; ++i)
-      for (int j = 0; j < El.rk; ++j) t += a[(size_t)i * q + j] * b[(size_t)i * q + j];
-    return t;
-  };
-  // <U0|H|U0> and <U0|U0> = 1 (normalised iterate)
-  {
-    Env e;
-    env_left(Lenv[L - 1], U[L - 1], U[L - 1], L - 1, e);
-    double v;
-    d2h(&v, e.d.p, sizeof(double), stream);
-    A[0] = v;
-    S[0] = 1.0;
-  }
-  auto overlap_start = [](Engine& W, int rb, int rk, Env& e) {
-    // identity on the bra/ket bond (both left-orthonormal prefixes of U)
-    e.R = 1; e.rb = rb; e.rk = rk;
-    const int p = padr(rb), q = padr(rk);
-    std::vector<double> h((size_t)p * q, 0.0);
-    for (int i = 0; i < std::min(rb, rk); ++i) h[(size_t)i * q + i] = 1.0;
-    upload(e.d, h.data(), h.size() * sizeof(double), W.stream);
-  };
-  // overlap chains use a one-channel identity "MPO" through the same kernels
-  SiteOp ident;
-  {
-    std::vector<int> o{0}, i{0};
-    std::vector<double> op{1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
-    build_siteop(ident, 1, o, i, op, stream);
-  }
-  // the same chain through the block-sparse update (one neutral channel)
-  BsSiteUse ident_use;
-  if (opts.qn_skip) bs_site_use(*this, ident_use, ident, {Q2{0, 0}}, {Q2{0, 0}}, +1);
-  HC(hipStreamSynchronize(stream));
-  auto ov_left = [&](Engine& W, const Env& in, const Core& bra, const Core& ket, Env& out) {
-    ScopeTimer tm(W, W.t_ov, W.n_ov);
-    Env o;
-    o.R = 1; o.rb = bra.rr; o.rk = ket.rr;
-    o.d.ensure(sizeof(double) * o.elems());
-    if (opts.qn_skip && in.rb == bra.rl && in.rk == ket.rl &&
-        bs_env(W, ident_use, in.d.as<double>(), bra, ket, o.d.as<double>())) {
-      out = std::move(o);
-      return;
-    }
-    W.env_left_raw(padr(in.rb), padr(in.rk), bra.rrp(), ket.rrp(), 1, in.d.as<double>(), bra.d.as<double>(),
-                   ket.d.as<double>(), ident, 1, o.d.as<double>());
-    out = std::move(o);
-  };
-  auto ov_close = [](Engine& W, const Env& e) {
-    // trace over the bond (the V suffix is right-orthonormal)
-    const int p = padr(e.rb), q = padr(e.rk);
-    std::vector<double> h((size_t)p * q);
-    download(h.data(), e.d, h.size() * sizeof(double), W.stream);
-    double t = 0.0;
-    for (int i = 0; i < std::min(e.rb, e.rk); ++i) t += h[(size_t)i * q + i];
-    return t;
-  };
-  // entries (0, j) and (j, j) of subdomain j
-  auto column0_and_diag = [&](Engine& W, int j) {
-    const Sub& Sj = subs[j - 1];
-    // bra U^0 in the s_j-orthogonal gauge: W_{s_j}, V_{s_j+1}, ...
-    Env eH, eS, tH, tS;
-    const Env* cH = &Lenv[Sj.s];
-    overlap_start(W, Wc[Sj.s].rl, Sj.mod[0].rl, eS);
-    for (int k = Sj.s; k <= Sj.t; ++k) {
-      const Core& bra = (k == Sj.s) ? Wc[k] : Vc[k];
-      const Core& ket = Sj.mod[k - Sj.s];
-      W.env_left(*cH, bra, ket, k, tH);
-      eH = std::move(tH);
-      cH = &eH;
-      ov_left(W, eS, bra, ket, tS);
-      eS = std::move(tS);
-    }
-    A[j] = A[(size_t)j * n] = W.env_close(eH, Renv[Sj.t + 1]);
-    S[j] = S[(size_t)j * n] = ov_close(W, eS);
-    // diagonal
-    cH = &Lenv[Sj.s];
-    overlap_start(W, Sj.mod[0].rl, Sj.mod[0].rl, eS);
-    for (int k = Sj.s; k <= Sj.t; ++k) {
-      const Core& c = Sj.mod[k - Sj.s];
-      W.env_left(*cH, c, c, k, tH);
-      eH = std::move(tH);
-      cH = &eH;
-      ov_left(W, eS, c, c, tS);
-      eS = std::move(tS);
-    }
-    A[(size_t)j * n + j] = W.env_close(eH, Renv[Sj.t + 1]);
-    S[(size_t)j * n + j] = ov_close(W, eS);
-    if (lin) {
-      // b_j = <U^j|F>: the overlap chain with F through the update's sites
-      Env ef, tf;
-      const Env* cf = &FL[Sj.s];
-      for (int k = Sj.s; k <= Sj.t; ++k) {
-        W.ov_left(*cf, Sj.mod[k - Sj.s], Fc[k], tf);
-        ef = std::move(tf);
-        cf = &ef;
-      }
-      bvec[j] = ov_close2(W, ef, FR[Sj.t + 1]);
-    }
-  };
-  // entries (i, j), j > i: one chain with bra Ũ^i and ket U from bond s_i,
-  // branching into ket Ũ^j at every later subdomain
-  auto row = [&](Engine& W, int i) {
-    const Sub& Si = subs[i - 1];
-    Env cH, cS, tH, tS;
-    bool first = true;
-    int k = Si.s;
-    for (int j = i + 1; j <= P; ++j) {
-      const Sub& Sj = subs[j - 1];
-      // advance the common chain to bond s_j
-      for (; k < Sj.s; ++k) {
-        const Core& bra = core_of(*this, i, k, true);
-        const Core& ket = U[k];
-        if (first) {
-          W.env_left(Lenv[Si.s], bra, ket, k, tH);
-          Env s0;
-          overlap_start(W, bra.rl, ket.rl, s0);
-          ov_left(W, s0, bra, ket, tS);
-          first = false;
-        } else {
-          W.env_left(cH, bra, ket, k, tH);
-          ov_left(W, cS, bra, ket, tS);
-        }
-        cH = std::move(tH);
-        cS = std::move(tS);
-      }
-      // branch: sites s_j..t_j with ket = Ũ^j
-      Env bH, bS, s0;
-      const Env* pH = &cH;
-      const Env* pS = &cS;
-      if (first) {
-        // Ũ^j starts at the same site as Ũ^i (an alternative update of the same
-        // subdomain): the branch starts from the cached environment there
-        pH = &Lenv[Si.s];
-        overlap_start(W, core_of(*this, i, Sj.s, true).rl, Sj.mod[0].rl, s0);
-        pS = &s0;
-      }
-      for (int kk = Sj.s; kk <= Sj.t; ++kk) {
-        const Core& bra = core_of(*this, i, kk, true);
-        const Core& ket = Sj.mod[kk - Sj.s];
-        W.env_left(*pH, bra, ket, kk, tH);
-        ov_left(W, *pS, bra, ket, tS);
-        bH = std::move(tH);
-        bS = std::move(tS);
-        pH = &bH;
-        pS = &bS;
-      }
-      A[(size_t)i * n + j] = A[(size_t)j * n + i] = W.env_close(bH, Renv[Sj.t + 1]);
-      S[(size_t)i * n + j] = S[(size_t)j * n + i] = ov_close(W, bS);
-    }
-  };
-  // tasks: P columns/diagonals, then P - 1 rows; cost = environment updates
-  std::vector<double> cost;
-  for (int j = 1; j <= P; ++j) cost.push_back(2.0 * (subs[j - 1].t - subs[j - 1].s + 1));
-  for (int i = 1; i < P; ++i) {
-    double c = 0.0;
-    for (int j = i + 1; j <= P; ++j) c += subs[j - 1].t - subs[j - 1].s + 1;
-    cost.push_back(2.0 * (c + std::max(0, subs[P - 1].s - subs[i - 1].s)));
-  }
-  run_tasks((int)cost.size(), cost, [&](Engine& W, int t) {
-    if (t < P) column0_and_diag(W, t + 1);
-    else row(W, t - P + 1);
-  });
-  ph[6] += now() - tph;
-  tph = now();
-  if (verbose) {
-    const auto ps = pool().stats();
-    const auto as = arena().stats();
-    std::fprintf(stderr,
-                 "[tt] step 3: coarse matrices %.2fs (so far: %d block-sparse env updates %.2fs, %d dense %.2fs, "
-                 "%d overlap updates %.2fs; small blocks: %.0f allocations, %.1f GB, %.2fs; large-block chunks: "
-                 "%.0f, %.1f GB, %.2fs)\n",
-                 ph[6], n_env_bs, t_env_bs, n_env_dense, t_env_dense, n_ov, t_ov, ps[0], ps[1] / 1e9, ps[2], as[0],
-                 as[1] / 1e9, as[2]);
-  }
-  // coarse eigenproblem (host FP64): canonical orthogonalisation of S
-  std::vector<double> ws, Vs;
-  jacobi_eig(n, S, ws, Vs);
-  const double smax = ws[n - 1];
-  std::vector<int> keep;
-  for (int i = 0; i < n; ++i)
-    if (ws[i] >= opts.coarse_eps * smax) keep.push_back(i);
-  const int p = (int)keep.size();
-  std::vector<double> X((size_t)n * p);
-  for (int i = 0; i < n; ++i)
-    for (int a = 0; a < p; ++a) X[(size_t)i * p + a] = Vs[(size_t)i * n + keep[a]] / std::sqrt(ws[keep[a]]);
-  std::vector<double> At((size_t)p * p, 0.0);
-  for (int a = 0; a < p; ++a)
-    for (int b = 0; b < p; ++b) {
-      double v = 0.0;
-      for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) v += X[(size_t)i * p + a] * A[(size_t)i * n + j] * X[(size_t)j * p + b];
-      At[(size_t)a * p + b] = v;
-    }
-  for (int a = 0; a < p; ++a)
-    for (int b = a + 1; b < p; ++b) {
-      double v = 0.5 * (At[(size_t)a * p + b] + At[(size_t)b * p + a]);
-      At[(size_t)a * p + b] = At[(size_t)b * p + a] = v;
-    }
-  std::vector<double> wa, Va;
-  jacobi_eig(p, At, wa, Va);
-  std::vector<double> c(n, 0.0);
-  double lam_out = 0.0;
-  if (!lin) {
-    for (int i = 0; i < n; ++i)
-      for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * Va[(size_t)a * p];
-    int imax = 0;
-    for (int i = 1; i < n; ++i)
-      if (std::fabs(c[i]) > std::fabs(c[imax])) imax = i;
-    if (c[imax] < 0)
-      for (double& v : c) v = -v;
-    lam_out = wa[0];
-  } else {
-    // coarse linear system (X^T A X) y = X^T b on the numerical range of S, c = X y;
-    // the coarse minimum of J is 1/2 c.Ac - b.c
-    if (!(wa[0] > 0.0)) throw std::runtime_error("linear-system functional: the coarse operator is not positive definite");
-    std::vector<double> rb(p, 0.0), y(p, 0.0);
-    for (int a = 0; a < p; ++a)
-      for (int i = 0; i < n; ++i) rb[a] += X[(size_t)i * p + a] * bvec[i];
-    for (int m = 0; m < p; ++m) {
-      double proj = 0.0;
-      for (int a = 0; a < p; ++a) proj += Va[(size_t)a * p + m] * rb[a];
-      for (int a = 0; a < p; ++a) y[a] += Va[(size_t)a * p + m] * proj / wa[m];
-    }
-    for (int i = 0; i < n; ++i)
-      for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * y[a];
-    double cAc = 0.0, bc = 0.0;
-    for (int i = 0; i < n; ++i) {
-      bc += bvec[i] * c[i];
-      for (int j = 0; j < n; ++j) cAc += c[i] * A[(size_t)i * n + j] * c[j];
-    }
-    lam_out = 0.5 * cAc - bc;
-  }
-  coarse_b = bvec;
-  int status = (p < n) ? TT_WRANKDEF : TT_OK;
-  if (Sout) std::copy(S.begin(), S.end(), Sout);
-  if (Aout) std::copy(A.begin(), A.end(), Aout);
-  if (cout) std::copy(c.begin(), c.end(), cout);
-  if (lam) *lam = lam_out;
-  if (rank) *rank = p;
-
-  // ---- Step 4: block TT of sum_j c_j Ũ^j and TT rounding ----
-  // bond k (1..L-1) blocks: U (r_k), V (r_k, if some state ended before site k), and one
-  // block per state that straddles the bond (several when Extension One keeps more than
-  // one update of a subdomain)
-  struct BondLayout {
-    int offU = -1, offV = -1, dim = 0;
-    int rU = 0, rV = 0;
-    std::vector<std::pair<int, int>> str;  // (state j, block offset)
-    Labels q;
-    int off_of(int j) const {
-      for (const auto& p : str)
-        if (p.first == j) return p.second;
-      return -1;
-    }
-  };
   std::vector<BondLayout> bl(L + 1);
   bl[0].dim = 1;
   bl[0].q = {Q2{0, 0}};
@@ -3817,7 +3562,8 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
   if (!opts.one_site)
     for (int j = 1; j <= P; ++j)
       if (subs[j - 1].s == L - 1) c0 += c[j];
-  std::vector<Core> T(L);
+  T.clear();
+  T.resize(L);
   for (int k = 0; k < L; ++k) {
     Core& C = T[k];
     C.rl = bl[k].dim; C.rr = bl[k + 1].dim; C.ql = bl[k].q; C.qr = bl[k + 1].q;
@@ -3871,6 +3617,462 @@ int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam
       else put(Sj.mod[0], Bl.offU, Br.offV, c[j], true);  // a one-site update of site k alone
     }
   }
+  HC(hipStreamSynchronize(stream));
+}
+
+void Engine::grouped_combination(const std::vector<double>& v, std::vector<Core>& W) {
+  std::vector<Core> T;
+  combination_tt(v, T);
+  // stable permutation of every inner bond that groups its labels by charge
+  std::vector<std::vector<int>> perm(L + 1);
+  perm[0] = {0};
+  perm[L] = {0};
+  for (int k = 1; k < L; ++k) {
+    const Labels& q = T[k].ql;
+    perm[k].resize(q.size());
+    std::iota(perm[k].begin(), perm[k].end(), 0);
+    std::stable_sort(perm[k].begin(), perm[k].end(), [&](int a, int b) { return q[a] < q[b]; });
+  }
+  std::vector<DevMem> dperm(L + 1);
+  for (int k = 0; k <= L; ++k) upload(dperm[k], perm[k].data(), perm[k].size() * sizeof(int), stream);
+  W.clear();
+  W.resize(L);
+  for (int k = 0; k < L; ++k) {
+    const Core& C = T[k];
+    Core& D = W[k];
+    D.rl = C.rl; D.rr = C.rr;
+    D.ql.resize(C.rl);
+    D.qr.resize(C.rr);
+    for (int a = 0; a < C.rl; ++a) D.ql[a] = C.ql[perm[k][a]];
+    for (int b = 0; b < C.rr; ++b) D.qr[b] = C.qr[perm[k + 1][b]];
+    D.d.resize_zero(sizeof(double) * D.elems(), stream);
+    permute_core(C.d.as<double>(), C.rrp(), dperm[k].as<int>(), dperm[k + 1].as<int>(), C.rl, C.rr, D.d.as<double>(),
+                 D.rrp(), stream);
+  }
+  HC(hipStreamSynchronize(stream));
+}
+
+// z_i = <U^i|H|W(v)> for all coarse states i (eq. aux_mat-vec_prod with the structured
+// combination W(v) = sum_j v_j U^j): one right-to-left chain <V_{>=k}|H|W_{>=k}> kept at
+// the bonds where an update ends, one left-to-right chain <U_{<k}|H|W_{<k}> that every
+// update branches off at its first site, through its own cores.
+int Engine::coarse_apply(const std::vector<double>& v, std::vector<double>& z) {
+  const int P = (int)subs.size();
+  std::vector<Core> W;
+  grouped_combination(v, W);
+  int nupd = 0;
+  auto copy_env = [&](const Env& a, Env& b) {
+    b.R = a.R; b.rb = a.rb; b.rk = a.rk;
+    b.d.ensure(a.d.n);
+    HC(hipMemcpyAsync(b.d.p, a.d.p, a.d.n, hipMemcpyDeviceToDevice, stream));
+  };
+  std::vector<char> needR(L + 1, 0);
+  for (const Sub& Sj : subs) needR[Sj.t + 1] = 1;
+  std::map<int, Env> RW;
+  {
+    Env cur;
+    env_unit(cur, 1);
+    if (needR[L]) copy_env(cur, RW[L]);
+    for (int k = L - 1; k >= 1; --k) {
+      bool any = false;
+      for (int q = 1; q <= k; ++q) any = any || needR[q];
+      if (!any) break;
+      Env nx;
+      env_right(cur, Vc[k], W[k], k, nx);
+      ++nupd;
+      cur = std::move(nx);
+      if (needR[k]) copy_env(cur, RW[k]);
+    }
+  }
+  std::vector<int> order(P);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return subs[a].s < subs[b].s; });
+  z.assign(P + 1, 0.0);
+  Env lw;
+  env_unit(lw, 1);
+  int kpos = 0;
+  for (int i : order) {
+    const Sub& Si = subs[i];
+    for (; kpos < Si.s; ++kpos) {
+      Env nx;
+      env_left(lw, U[kpos], W[kpos], kpos, nx);
+      ++nupd;
+      lw = std::move(nx);
+    }
+    Env e, tmp;
+    const Env* cur = &lw;
+    for (int k = Si.s; k <= Si.t; ++k) {
+      env_left(*cur, Si.mod[k - Si.s], W[k], k, tmp);
+      ++nupd;
+      e = std::move(tmp);
+      cur = &e;
+    }
+    z[i + 1] = env_close(e, RW.at(Si.t + 1));
+  }
+  for (; kpos < L; ++kpos) {
+    Env nx;
+    env_left(lw, U[kpos], W[kpos], kpos, nx);
+    ++nupd;
+    lw = std::move(nx);
+  }
+  d2h(&z[0], lw.d.p, sizeof(double), stream);
+  return nupd;
+}
+
+static const Core& core_of(const Engine& E, int j, int k, bool V_suffix) {
+  // Ũ^j (j >= 1): U_k for k < s_j, mod for s_j..t_j, V_k beyond
+  const Engine::Sub& S = E.subs[j - 1];
+  if (k < S.s) return E.U[k];
+  if (k <= S.t) return S.mod[k - S.s];
+  (void)V_suffix;
+  return E.Vc[k];
+}
+
+int Engine::coarse_correct(double* Sout, double* Aout, double* cout, double* lam, double* Eout, int* rank,
+                           double* disc) {
+  if (!have_local) throw std::logic_error("coarse_correct needs a preceding local_solve");
+  double tph = now();
+  const int P = (int)subs.size();
+  const int n = P + 1;
+  const bool lin = opts.functional == 1;
+  // Krylov coarse solve: the Hamiltonian matrix is not formed, only S (its products
+  // with A go through coarse_apply)
+  const bool kry = opts.coarse_krylov != 0;
+  coarse_matvecs = 0;
+  std::vector<double> S((size_t)n * n, 0.0), A((size_t)n * n, 0.0), bvec(n, 0.0);
+  if (lin) bvec[0] = uf;
+  // sum over the valid block of El[a][f] Er[a][f] (two one-channel environments at one bond)
+  auto ov_close2 = [](Engine& W, const Env& El, const Env& Er) {
+    if (El.rb != Er.rb || El.rk != Er.rk) throw std::runtime_error("overlap closure: shape mismatch");
+    const int p = padr(El.rb), q = padr(El.rk);
+    std::vector<double> a((size_t)p * q), b((size_t)p * q);
+    download(a.data(), El.d, a.size() * sizeof(double), W.stream);
+    download(b.data(), Er.d, b.size() * sizeof(double), W.stream);
+    double t = 0.0;
+    for (int i = 0; i < El.rb; ++i)
+      for (int j = 0; j < El.rk; ++j) t += a[(size_t)i * q + j] * b[(size_t)i * q + j];
+    return t;
+  };
+  // <U0|H|U0> and <U0|U0> = 1 (normalised iterate)
+  if (!kry) {
+    Env e;
+    env_left(Lenv[L - 1], U[L - 1], U[L - 1], L - 1, e);
+    double v;
+    d2h(&v, e.d.p, sizeof(double), stream);
+    A[0] = v;
+  }
+  S[0] = 1.0;
+  auto overlap_start = [](Engine& W, int rb, int rk, Env& e) {
+    // identity on the bra/ket bond (both left-orthonormal prefixes of U)
+    e.R = 1; e.rb = rb; e.rk = rk;
+    const int p = padr(rb), q = padr(rk);
+    std::vector<double> h((size_t)p * q, 0.0);
+    for (int i = 0; i < std::min(rb, rk); ++i) h[(size_t)i * q + i] = 1.0;
+    upload(e.d, h.data(), h.size() * sizeof(double), W.stream);
+  };
+  // overlap chains use a one-channel identity "MPO" through the same kernels
+  SiteOp ident;
+  {
+    std::vector<int> o{0}, i{0};
+    std::vector<double> op{1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    build_siteop(ident, 1, o, i, op, stream);
+  }
+  // the same chain through the block-sparse update (one neutral channel)
+  BsSiteUse ident_use;
+  if (opts.qn_skip) bs_site_use(*this, ident_use, ident, {Q2{0, 0}}, {Q2{0, 0}}, +1);
+  HC(hipStreamSynchronize(stream));
+  auto ov_left = [&](Engine& W, const Env& in, const Core& bra, const Core& ket, Env& out) {
+    ScopeTimer tm(W, W.t_ov, W.n_ov);
+    Env o;
+    o.R = 1; o.rb = bra.rr; o.rk = ket.rr;
+    o.d.ensure(sizeof(double) * o.elems());
+    if (opts.qn_skip && in.rb == bra.rl && in.rk == ket.rl &&
+        bs_env(W, ident_use, in.d.as<double>(), bra, ket, o.d.as<double>())) {
+      out = std::move(o);
+      return;
+    }
+    W.env_left_raw(padr(in.rb), padr(in.rk), bra.rrp(), ket.rrp(), 1, in.d.as<double>(), bra.d.as<double>(),
+                   ket.d.as<double>(), ident, 1, o.d.as<double>());
+    out = std::move(o);
+  };
+  auto ov_close = [](Engine& W, const Env& e) {
+    // trace over the bond (the V suffix is right-orthonormal)
+    const int p = padr(e.rb), q = padr(e.rk);
+    std::vector<double> h((size_t)p * q);
+    download(h.data(), e.d, h.size() * sizeof(double), W.stream);
+    double t = 0.0;
+    for (int i = 0; i < std::min(e.rb, e.rk); ++i) t += h[(size_t)i * q + i];
+    return t;
+  };
+  // entries (0, j) and (j, j) of subdomain j
+  auto column0_and_diag = [&](Engine& W, int j) {
+    const Sub& Sj = subs[j - 1];
+    // bra U^0 in the s_j-orthogonal gauge: W_{s_j}, V_{s_j+1}, ...
+    Env eH, eS, tH, tS;
+    const Env* cH = &Lenv[Sj.s];
+    overlap_start(W, Wc[Sj.s].rl, Sj.mod[0].rl, eS);
+    for (int k = Sj.s; k <= Sj.t; ++k) {
+      const Core& bra = (k == Sj.s) ? Wc[k] : Vc[k];
+      const Core& ket = Sj.mod[k - Sj.s];
+      if (!kry) {
+        W.env_left(*cH, bra, ket, k, tH);
+        eH = std::move(tH);
+        cH = &eH;
+      }
+      ov_left(W, eS, bra, ket, tS);
+      eS = std::move(tS);
+    }
+    if (!kry) A[j] = A[(size_t)j * n] = W.env_close(eH, Renv[Sj.t + 1]);
+    S[j] = S[(size_t)j * n] = ov_close(W, eS);
+    // diagonal
+    cH = &Lenv[Sj.s];
+    overlap_start(W, Sj.mod[0].rl, Sj.mod[0].rl, eS);
+    for (int k = Sj.s; k <= Sj.t; ++k) {
+      const Core& c = Sj.mod[k - Sj.s];
+      if (!kry) {
+        W.env_left(*cH, c, c, k, tH);
+        eH = std::move(tH);
+        cH = &eH;
+      }
+      ov_left(W, eS, c, c, tS);
+      eS = std::move(tS);
+    }
+    if (!kry) A[(size_t)j * n + j] = W.env_close(eH, Renv[Sj.t + 1]);
+    S[(size_t)j * n + j] = ov_close(W, eS);
+    if (lin) {
+      // b_j = <U^j|F>: the overlap chain with F through the update's sites
+      Env ef, tf;
+      const Env* cf = &FL[Sj.s];
+      for (int k = Sj.s; k <= Sj.t; ++k) {
+        W.ov_left(*cf, Sj.mod[k - Sj.s], Fc[k], tf);
+        ef = std::move(tf);
+        cf = &ef;
+      }
+      bvec[j] = ov_close2(W, ef, FR[Sj.t + 1]);
+    }
+  };
+  // entries (i, j), j > i: one chain with bra Ũ^i and ket U from bond s_i,
+  // branching into ket Ũ^j at every later subdomain
+  auto row = [&](Engine& W, int i) {
+    const Sub& Si = subs[i - 1];
+    Env cH, cS, tH, tS;
+    bool first = true;
+    int k = Si.s;
+    for (int j = i + 1; j <= P; ++j) {
+      const Sub& Sj = subs[j - 1];
+      // advance the common chain to bond s_j
+      for (; k < Sj.s; ++k) {
+        const Core& bra = core_of(*this, i, k, true);
+        const Core& ket = U[k];
+        if (first) {
+          if (!kry) W.env_left(Lenv[Si.s], bra, ket, k, tH);
+          Env s0;
+          overlap_start(W, bra.rl, ket.rl, s0);
+          ov_left(W, s0, bra, ket, tS);
+          first = false;
+        } else {
+          if (!kry) W.env_left(cH, bra, ket, k, tH);
+          ov_left(W, cS, bra, ket, tS);
+        }
+        if (!kry) cH = std::move(tH);
+        cS = std::move(tS);
+      }
+      // branch: sites s_j..t_j with ket = Ũ^j
+      Env bH, bS, s0;
+      const Env* pH = &cH;
+      const Env* pS = &cS;
+      if (first) {
+        // Ũ^j starts at the same site as Ũ^i (an alternative update of the same
+        // subdomain): the branch starts from the cached environment there
+        pH = &Lenv[Si.s];
+        overlap_start(W, core_of(*this, i, Sj.s, true).rl, Sj.mod[0].rl, s0);
+        pS = &s0;
+      }
+      for (int kk = Sj.s; kk <= Sj.t; ++kk) {
+        const Core& bra = core_of(*this, i, kk, true);
+        const Core& ket = Sj.mod[kk - Sj.s];
+        if (!kry) {
+          W.env_left(*pH, bra, ket, kk, tH);
+          bH = std::move(tH);
+          pH = &bH;
+        }
+        ov_left(W, *pS, bra, ket, tS);
+        bS = std::move(tS);
+        pS = &bS;
+      }
+      if (!kry) A[(size_t)i * n + j] = A[(size_t)j * n + i] = W.env_close(bH, Renv[Sj.t + 1]);
+      S[(size_t)i * n + j] = S[(size_t)j * n + i] = ov_close(W, bS);
+    }
+  };
+  // tasks: P columns/diagonals, then P - 1 rows; cost = environment updates
+  std::vector<double> cost;
+  for (int j = 1; j <= P; ++j) cost.push_back(2.0 * (subs[j - 1].t - subs[j - 1].s + 1));
+  for (int i = 1; i < P; ++i) {
+    double c = 0.0;
+    for (int j = i + 1; j <= P; ++j) c += subs[j - 1].t - subs[j - 1].s + 1;
+    cost.push_back(2.0 * (c + std::max(0, subs[P - 1].s - subs[i - 1].s)));
+  }
+  run_tasks((int)cost.size(), cost, [&](Engine& W, int t) {
+    if (t < P) column0_and_diag(W, t + 1);
+    else row(W, t - P + 1);
+  });
+  ph[6] += now() - tph;
+  tph = now();
+  if (verbose) {
+    const auto ps = pool().stats();
+    const auto as = arena().stats();
+    std::fprintf(stderr,
+                 "[tt] step 3: coarse matrices %.2fs (so far: %d block-sparse env updates %.2fs, %d dense %.2fs, "
+                 "%d overlap updates %.2fs; small blocks: %.0f allocations, %.1f GB, %.2fs; large-block chunks: "
+                 "%.0f, %.1f GB, %.2fs)\n",
+                 ph[6], n_env_bs, t_env_bs, n_env_dense, t_env_dense, n_ov, t_ov, ps[0], ps[1] / 1e9, ps[2], as[0],
+                 as[1] / 1e9, as[2]);
+  }
+  // coarse eigenproblem (host FP64): canonical orthogonalisation of S
+  std::vector<double> ws, Vs;
+  jacobi_eig(n, S, ws, Vs);
+  const double smax = ws[n - 1];
+  std::vector<int> keep;
+  for (int i = 0; i < n; ++i)
+    if (ws[i] >= opts.coarse_eps * smax) keep.push_back(i);
+  const int p = (int)keep.size();
+  std::vector<double> X((size_t)n * p);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < p; ++a) X[(size_t)i * p + a] = Vs[(size_t)i * n + keep[a]] / std::sqrt(ws[keep[a]]);
+  std::vector<double> c(n, 0.0);
+  double lam_out = 0.0;
+  std::vector<double> wa, Va;
+  if (!kry) {
+    std::vector<double> At((size_t)p * p, 0.0);
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) {
+        double v = 0.0;
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) v += X[(size_t)i * p + a] * A[(size_t)i * n + j] * X[(size_t)j * p + b];
+        At[(size_t)a * p + b] = v;
+      }
+    for (int a = 0; a < p; ++a)
+      for (int b = a + 1; b < p; ++b) {
+        double v = 0.5 * (At[(size_t)a * p + b] + At[(size_t)b * p + a]);
+        At[(size_t)a * p + b] = At[(size_t)b * p + a] = v;
+      }
+    jacobi_eig(p, At, wa, Va);
+  }
+  if (kry) {
+    // Lanczos with full reorthogonalisation for the lowest eigenpair of X^T A X, started
+    // from the iterate's coordinates in the orthonormal basis X (y_a = sum_i X_ia S_i0);
+    // each product forms v = X y, z = A v through the combination TT, X^T z.  Stops when
+    // the Ritz residual is <= 1e-12 max(1, |theta|) or the Krylov space is the whole space.
+    auto red = [&](const std::vector<double>& y, std::vector<double>& out) {
+      std::vector<double> v(n, 0.0), z;
+      for (int i = 0; i < n; ++i)
+        for (int a = 0; a < p; ++a) v[i] += X[(size_t)i * p + a] * y[a];
+      coarse_apply(v, z);
+      ++coarse_matvecs;
+      out.assign(p, 0.0);
+      for (int a = 0; a < p; ++a)
+        for (int i = 0; i < n; ++i) out[a] += X[(size_t)i * p + a] * z[i];
+    };
+    std::vector<std::vector<double>> Q;
+    std::vector<double> al, be;
+    std::vector<double> q(p, 0.0);
+    for (int a = 0; a < p; ++a)
+      for (int i = 0; i < n; ++i) q[a] += X[(size_t)i * p + a] * S[(size_t)i * n];
+    double nq = 0.0;
+    for (double x : q) nq += x * x;
+    nq = std::sqrt(nq);
+    if (!(nq > 0.0)) {
+      std::fill(q.begin(), q.end(), 0.0);
+      q[0] = 1.0;
+      nq = 1.0;
+    }
+    for (double& x : q) x /= nq;
+    std::vector<double> ybest;
+    double theta = 0.0;
+    for (int m = 0; m < p; ++m) {
+      Q.push_back(q);
+      std::vector<double> w;
+      red(q, w);
+      double a_ = 0.0;
+      for (int a = 0; a < p; ++a) a_ += q[a] * w[a];
+      al.push_back(a_);
+      for (int pass = 0; pass < 2; ++pass)
+        for (const auto& qq : Q) {
+          double d = 0.0;
+          for (int a = 0; a < p; ++a) d += qq[a] * w[a];
+          for (int a = 0; a < p; ++a) w[a] -= d * qq[a];
+        }
+      double b_ = 0.0;
+      for (double x : w) b_ += x * x;
+      b_ = std::sqrt(b_);
+      // tridiagonal T_m and its lowest eigenpair
+      const int mm = m + 1;
+      std::vector<double> Tm((size_t)mm * mm, 0.0), wt, Vt;
+      for (int r = 0; r < mm; ++r) {
+        Tm[(size_t)r * mm + r] = al[r];
+        if (r + 1 < mm) Tm[(size_t)r * mm + r + 1] = Tm[(size_t)(r + 1) * mm + r] = be[r];
+      }
+      jacobi_eig(mm, Tm, wt, Vt);
+      theta = wt[0];
+      ybest.assign(p, 0.0);
+      for (int r = 0; r < mm; ++r)
+        for (int a = 0; a < p; ++a) ybest[a] += Vt[(size_t)r * mm] * Q[r][a];
+      const double res = b_ * std::fabs(Vt[(size_t)(mm - 1) * mm]);
+      if (res <= 1e-12 * std::max(1.0, std::fabs(theta)) || b_ <= 1e-14 * std::max(1.0, std::fabs(theta))) break;
+      be.push_back(b_);
+      for (int a = 0; a < p; ++a) q[a] = w[a] / b_;
+    }
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * ybest[a];
+    int imax = 0;
+    for (int i = 1; i < n; ++i)
+      if (std::fabs(c[i]) > std::fabs(c[imax])) imax = i;
+    if (c[imax] < 0)
+      for (double& v : c) v = -v;
+    lam_out = theta;
+    // the Hamiltonian matrix was not formed
+    std::fill(A.begin(), A.end(), std::numeric_limits<double>::quiet_NaN());
+  } else if (!lin) {
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * Va[(size_t)a * p];
+    int imax = 0;
+    for (int i = 1; i < n; ++i)
+      if (std::fabs(c[i]) > std::fabs(c[imax])) imax = i;
+    if (c[imax] < 0)
+      for (double& v : c) v = -v;
+    lam_out = wa[0];
+  } else {
+    // coarse linear system (X^T A X) y = X^T b on the numerical range of S, c = X y;
+    // the coarse minimum of J is 1/2 c.Ac - b.c
+    if (!(wa[0] > 0.0)) throw std::runtime_error("linear-system functional: the coarse operator is not positive definite");
+    std::vector<double> rb(p, 0.0), y(p, 0.0);
+    for (int a = 0; a < p; ++a)
+      for (int i = 0; i < n; ++i) rb[a] += X[(size_t)i * p + a] * bvec[i];
+    for (int m = 0; m < p; ++m) {
+      double proj = 0.0;
+      for (int a = 0; a < p; ++a) proj += Va[(size_t)a * p + m] * rb[a];
+      for (int a = 0; a < p; ++a) y[a] += Va[(size_t)a * p + m] * proj / wa[m];
+    }
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < p; ++a) c[i] += X[(size_t)i * p + a] * y[a];
+    double cAc = 0.0, bc = 0.0;
+    for (int i = 0; i < n; ++i) {
+      bc += bvec[i] * c[i];
+      for (int j = 0; j < n; ++j) cAc += c[i] * A[(size_t)i * n + j] * c[j];
+    }
+    lam_out = 0.5 * cAc - bc;
+  }
+  coarse_b = bvec;
+  int status = (p < n) ? TT_WRANKDEF : TT_OK;
+  if (Sout) std::copy(S.begin(), S.end(), Sout);
+  if (Aout) std::copy(A.begin(), A.end(), Aout);
+  if (cout) std::copy(c.begin(), c.end(), cout);
+  if (lam) *lam = lam_out;
+  if (rank) *rank = p;
+
+  // ---- Step 4: block TT of sum_j c_j Ũ^j and TT rounding ----
+  std::vector<Core> T;
+  combination_tt(c, T);
   HC(hipStreamSynchronize(stream));
   const double tc0 = now();
   // right-to-left orthogonalisation

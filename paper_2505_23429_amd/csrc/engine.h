@@ -267,6 +267,14 @@ class Engine {
   // fn reads shared state only and writes task-private outputs.
   void run_tasks(int ntask, const std::vector<double>& cost, const std::function<void(Engine&, int)>& fn);
   int coarse_correct(double* S, double* A, double* c, double* lam, double* Eout, int* rank, double* disc);
+  // Step 4's block TT of sum_j c_j U^j (labels grouped by charge within each block)
+  void combination_tt(const std::vector<double>& c, std::vector<Core>& T);
+  // the same TT with every bond's labels grouped by charge (a permutation of each bond)
+  void grouped_combination(const std::vector<double>& v, std::vector<Core>& W);
+  // z = A v with A_ij = <U^i|H|U^j>, through environment chains with the combination TT
+  // (the coarse matrix is not formed); returns the number of environment updates
+  int coarse_apply(const std::vector<double>& v, std::vector<double>& z);
+  int coarse_matvecs = 0;  // Krylov products of the last coarse step
   void dmrg2(int nsweeps, double* energies);
 
   // kernels on raw device pointers

@@ -46,7 +46,7 @@ def test_default_options_and_invalid_create():
     ("chi_max", 0), ("dav_maxiter", 0), ("dav_maxsub", 3), ("matvec_prec", 3), ("matvec_prec", -1),
     ("sub_workers", -1), ("sub_workers", 65), ("mix_stage", 3), ("mix_stage", -1), ("svd_lds", 2),
     ("worker_alloc_limit", -1), ("coarse_k", 0), ("coarse_k", 9), ("one_site", 2), ("one_site", -1),
-    ("functional", 2), ("functional", -1),
+    ("functional", 2), ("functional", -1), ("coarse_krylov", 2), ("coarse_krylov", -1),
 ])
 def test_create_rejects_each_invalid_option(field, value):
     """tt_create validates the options before it touches the device: every value outside
@@ -80,10 +80,11 @@ def test_one_site_needs_fp64_block_sparse_products(field, value):
     assert not h.value
 
 
-@pytest.mark.parametrize("field,value", [("matvec_prec", 1), ("matvec_prec", 2), ("qn_skip", 0), ("coarse_k", 2)])
+@pytest.mark.parametrize("field,value", [("matvec_prec", 1), ("matvec_prec", 2), ("qn_skip", 0), ("coarse_k", 2),
+                                         ("coarse_krylov", 1)])
 def test_linear_functional_needs_fp64_block_sparse_products(field, value):
     """The linear-system functional solves its micro-steps by FP64 conjugate gradients
-    on the block-sparse product and has no several-eigenvector variant."""
+    on the block-sparse product and has no several-eigenvector or Krylov-coarse variant."""
     from paper_2505_23429_amd import _lib
 
     lib = _lib.load()
