@@ -1044,9 +1044,21 @@ static std::vector<GemmGroup<T>> heavy_groups(Engine& E, const BsMix& m, const T
   return gg;
 }
 
+// The heavy-row GEMMs of one mix split by their row count: buckets 0..2 run on the
+// skinny streaming kernel (at most 16, 32, 64 rows), bucket 3 on the matrix-core tiles.
+template <typename T>
+static std::array<std::vector<GemmGroup<T>>, 4> split_heavy(const std::vector<GemmGroup<T>>& gg) {
+  std::array<std::vector<GemmGroup<T>>, 4> parts;
+  for (const GemmGroup<T>& G : gg) {
+    const int mr = skinny_rows(G.g.M);
+    parts[mr == 16 ? 0 : mr == 32 ? 1 : mr == 64 ? 2 : 3].push_back(G);
+  }
+  return parts;
+}
+
 template <typename T, int MODE>
 static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, long long nin, T* out, long long nout,
-                    int* err, bool rnd, const std::vector<GemmGroup<T>>& gg, const DevMem& gdev) {
+                    int* err, bool rnd, const std::array<std::vector<GemmGroup<T>>, 4>& gg, DevMem* gdev) {
   hipStream_t s = E.stream;
   const int slot0 = MODE == 1 ? 1 : 4;
   if (m.ntiles > 0) {
@@ -1061,7 +1073,10 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
   }
   if (m.nhtiles > 0) {
     T* tmp = E.bs_tmp.as<T>();
-    gemm_grouped<T>(gdev.template as<GemmGroup<T>>(), gg, s);
+    static const int kRows[3] = {16, 32, 64};
+    for (int b = 0; b < 3; ++b)
+      if (!gg[b].empty()) gemm_grouped_skinny<T>(gdev[b].template as<GemmGroup<T>>(), gg[b], kRows[b], s);
+    if (!gg[3].empty()) gemm_grouped<T>(gdev[3].template as<GemmGroup<T>>(), gg[3], s);
     E.kt_mark(slot0 + 1);
     hipLaunchKernelGGL((mix_kernel<T, MODE, true>), dim3(m.nhtiles), dim3(MIX_COLS), 0, s, m.htiles.as<MixTile>(),
                        m.groups.as<BsGroup>(), m.hrows.as<MixRow>(), m.ocol.as<int>(), mix_vals<T>(m).template as<T>(),
@@ -1107,13 +1122,15 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   fill(y, sizeof(T) * ny, s);
   // heavy-row GEMM descriptors uploaded before the timed kernels
   E.bs_tmp.ensure(sizeof(T) * std::max<long long>(std::max(p.m1.ntmp, p.m2.ntmp), 1));
-  const std::vector<GemmGroup<T>> gg1 = heavy_groups<T>(E, p.m1, E.bs_t1.as<T>(), p.n1);
-  const std::vector<GemmGroup<T>> gg2 = heavy_groups<T>(E, p.m2, E.bs_t2.as<T>(), p.n2);
+  const auto gg1 = split_heavy<T>(heavy_groups<T>(E, p.m1, E.bs_t1.as<T>(), p.n1));
+  const auto gg2 = split_heavy<T>(heavy_groups<T>(E, p.m2, E.bs_t2.as<T>(), p.n2));
   // the descriptors change only with the plan, the precision or the workspace addresses
   if (E.bs_gg_serial != p.serial || E.bs_gg_prec != prec || E.bs_gg_ptr[0] != E.bs_t1.p ||
       E.bs_gg_ptr[1] != E.bs_t2.p || E.bs_gg_ptr[2] != E.bs_tmp.p) {
-    if (!gg1.empty()) upload(E.bs_gg1, gg1.data(), gg1.size() * sizeof(GemmGroup<T>), s);
-    if (!gg2.empty()) upload(E.bs_gg2, gg2.data(), gg2.size() * sizeof(GemmGroup<T>), s);
+    for (int b = 0; b < 4; ++b) {
+      if (!gg1[b].empty()) upload(E.bs_gg1[b], gg1[b].data(), gg1[b].size() * sizeof(GemmGroup<T>), s);
+      if (!gg2[b].empty()) upload(E.bs_gg2[b], gg2[b].data(), gg2[b].size() * sizeof(GemmGroup<T>), s);
+    }
     E.bs_gg_serial = p.serial;
     E.bs_gg_prec = prec;
     E.bs_gg_ptr[0] = E.bs_t1.p;

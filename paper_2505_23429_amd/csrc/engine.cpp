@@ -504,8 +504,12 @@ Engine::~Engine() {
 void Engine::release_workspaces() {
   for (DevMem* m : {&ws0, &ws1, &ws2, &ws3, &wsd, &wsp, &dav_V, &dav_AV, &dav_t, &dav_u, &dav_Au, &dav_c, &dav_mask, &dav_xd, &dav_yd, &dav_dc, &dav_uk, &dav_tk,
                     &dav_t2, &dav_t3, &wlow_x, &wlow_y, &wlow_L, &wlow_R, &wlow_Rt, &envq_o, &envq_i, &bs_t1, &bs_t2,
-                    &bs_t3, &bs_part, &bs_tmp, &bs_gg1, &bs_gg2, &be_t1, &be_panel, &be_up, &be_tmp})
+                    &bs_t3, &bs_part, &bs_tmp, &be_t1, &be_panel, &be_up, &be_tmp})
     m->release();
+  for (int b = 0; b < 4; ++b) {
+    bs_gg1[b].release();
+    bs_gg2[b].release();
+  }
   bs_zero_serial = -1;
   bs_zero_prec = -1;
   bs_gg_serial = -1;

@@ -316,7 +316,8 @@ class Engine {
   DevMem wlow_x, wlow_y, wlow_L, wlow_R, wlow_Rt;
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)
-  DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp, bs_gg1, bs_gg2;
+  DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp;
+  DevMem bs_gg1[4], bs_gg2[4];  // heavy-row GEMM descriptors per row bucket (16, 32, 64, larger)
   DevMem be_t1, be_panel, be_up, be_tmp;  // block-sparse environment-update workspaces
   long long bs_zero_serial = -1;  // plan whose never-written T1 entries are zero in bs_t1
   // plan (serial, precision, workspace addresses) whose heavy-row GEMM descriptors bs_gg1/2 hold

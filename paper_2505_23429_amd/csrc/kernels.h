@@ -63,6 +63,17 @@ struct GemmGroup {
 template <typename T>
 void gemm_grouped(const GemmGroup<T>* dev_groups, const std::vector<GemmGroup<T>>& host_groups, hipStream_t s);
 
+// The same for problems with few rows (M <= kSkinnyMaxM), row-major, alpha = 1, beta = 0:
+// C = A B streamed over B's columns (each thread owns one to four columns and keeps all
+// M rows of its columns in registers; A is staged through LDS in K chunks).  Every
+// element of B is read once; the cost is B's bytes, not an M-row matrix-core tile.
+constexpr int kSkinnyMaxM = 64;
+// smallest supported row bucket that holds M rows (16, 32 or 64), 0 if none
+int skinny_rows(int M);
+template <typename T>
+void gemm_grouped_skinny(const GemmGroup<T>* dev_groups, const std::vector<GemmGroup<T>>& host_groups, int mr,
+                         hipStream_t s);
+
 // BF16 operands (uint16 storage), FP32 accumulation and FP32 output.
 void gemm_bf16(const GemmArgs& g, const uint16_t* A, const uint16_t* B, float* C, bool a_kcontig,
                bool b_ncontig, hipStream_t s);

@@ -331,6 +331,147 @@ void gemm_grouped(const GemmGroup<T>* dev_groups, const std::vector<GemmGroup<T>
     hipLaunchKernelGGL((gemm_grouped_kernel<T, true, true, false>), grid, dim3(256), 0, s, dev_groups);
   HIPCHECK(hipGetLastError());
 }
+// ---------------------------------------------------------------------------
+// skinny grouped GEMM: C[m][n] = sum_k A[m][k] B[k][n] for M <= 64 rows
+// ---------------------------------------------------------------------------
+template <typename T, int MB>
+__global__ __launch_bounds__(256) void skinny_mfma_kernel(const GemmGroup<T>* __restrict__ grp) {
+  constexpr int KS = sizeof(T) == 4 ? 16 : 8;  // K slice
+  constexpr int NB = 256;                      // columns per workgroup
+  constexpr int MRW = MB * 16;
+  constexpr int BPT = KS * NB / 256;           // B elements per thread per slice
+  __shared__ T As[2][KS][MRW + 4];
+  __shared__ T Bs[2][KS][NB + 4];
+  const GemmGroup<T> G = grp[blockIdx.y];
+  const int M = G.g.M, N = G.g.N, K = G.g.K;
+  const long long lda = G.g.sAm, ldb = G.g.sBkk, ldc = G.g.sCm;
+  const int n0 = (int)blockIdx.x * NB;
+  if (n0 >= N) return;  // uniform over the workgroup
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // B: thread -> row br, BPT consecutive columns from bc
+  constexpr int TPR = NB / BPT;  // threads per B row
+  const int br = tid / TPR, bc = (tid % TPR) * BPT;
+  const bool bvec = ((ldb * sizeof(T)) % 16 == 0) && ((reinterpret_cast<uintptr_t>(G.B) % 16) == 0);
+  T rb[BPT];
+  constexpr int AP = (MRW * KS + 255) / 256;  // A elements per thread per slice
+  T ra[AP];
+  auto fetch = [&](int k0) {
+    const int k = k0 + br;
+    const long long base = (long long)k * ldb + n0 + bc;
+    if (k < K && bvec && n0 + bc + BPT <= N) {
+#pragma unroll
+      for (int u = 0; u < BPT; u += 16 / (int)sizeof(T)) {
+        if constexpr (sizeof(T) == 4) {
+          const float4 v = *reinterpret_cast<const float4*>(G.B + base + u);
+          rb[u] = v.x; rb[u + 1] = v.y; rb[u + 2] = v.z; rb[u + 3] = v.w;
+        } else {
+          const double2 v = *reinterpret_cast<const double2*>(G.B + base + u);
+          rb[u] = v.x; rb[u + 1] = v.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < BPT; ++u) rb[u] = (k < K && n0 + bc + u < N) ? G.B[base + u] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < AP; ++u) {
+      const int e = tid + u * 256, ar = e / KS, ak = e - ar * KS;
+      ra[u] = (e < MRW * KS && ar < M && k0 + ak < K) ? G.A[(long long)ar * lda + k0 + ak] : T(0);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) Bs[buf][br][bc + u] = rb[u];
+#pragma unroll
+    for (int u = 0; u < AP; ++u) {
+      const int e = tid + u * 256, ar = e / KS, ak = e - ar * KS;
+      if (e < MRW * KS) As[buf][ak][ar] = ra[u];
+    }
+  };
+  T acc[MB][4][4];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+  int buf = 0;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += KS) {
+    const bool more = k0 + KS < K;
+    if (more) fetch(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      T b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk + (lane >> 4)][wv * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        const T a = As[buf][kk + (lane >> 4)][i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mfma_step<T>(a, b[j], acc[i][j]);
+      }
+    }
+    if (more) {
+      // buf ^ 1 was last read before the previous barrier
+      stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wv * 64 + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i * 16 + acc_row<T>(lane, v);
+        if (row < M) G.C[(long long)row * ldc + col] = acc[i][j][v];
+      }
+    }
+}
+
+int skinny_rows(int M) {
+  if (M <= 0) return 16;
+  if (M > kSkinnyMaxM) return 0;
+  return (M + 15) / 16 * 16;
+}
+
+template <typename T>
+void gemm_grouped_skinny(const GemmGroup<T>* dev_groups, const std::vector<GemmGroup<T>>& host_groups, int mr,
+                         hipStream_t s) {
+  if (host_groups.empty()) return;
+  int nmax = 0;
+  for (const GemmGroup<T>& G : host_groups) {
+    const GemmArgs& g = G.g;
+    check_args(g);
+    if (g.batch != 1 || g.kmode != 0 || g.skip) throw std::runtime_error("gemm_grouped_skinny: dense problems only");
+    if (g.M > mr) throw std::runtime_error("gemm_grouped_skinny: more rows than the bucket");
+    if (g.sAkk != 1 || g.sBn != 1) throw std::runtime_error("gemm_grouped_skinny: row-major operands only");
+    if (g.alpha != 1.0 || g.beta != 0.0) throw std::runtime_error("gemm_grouped_skinny: C = A B only");
+    if (g.K > g.kin) throw std::runtime_error("gemm_grouped_skinny: one inner K block only");
+    if (g.M > 0 && g.N > 0 && g.K > 0 && (!G.A || !G.B || !G.C)) throw std::runtime_error("gemm_grouped_skinny: null operand");
+    nmax = std::max(nmax, g.N);
+  }
+  if (nmax == 0) return;
+  dim3 grid((nmax + 255) / 256, (unsigned)host_groups.size(), 1);
+  if (grid.y > 65535) throw std::runtime_error("gemm_grouped_skinny: too many problems");
+  if (mr == 16) hipLaunchKernelGGL((skinny_mfma_kernel<T, 1>), grid, dim3(256), 0, s, dev_groups);
+  else if (mr == 32) hipLaunchKernelGGL((skinny_mfma_kernel<T, 2>), grid, dim3(256), 0, s, dev_groups);
+  else if (mr == 48) hipLaunchKernelGGL((skinny_mfma_kernel<T, 3>), grid, dim3(256), 0, s, dev_groups);
+  else if (mr == 64) hipLaunchKernelGGL((skinny_mfma_kernel<T, 4>), grid, dim3(256), 0, s, dev_groups);
+  else throw std::runtime_error("gemm_grouped_skinny: row bucket must be 16, 32, 48 or 64");
+  HIPCHECK(hipGetLastError());
+}
+template void gemm_grouped_skinny<double>(const GemmGroup<double>*, const std::vector<GemmGroup<double>>&, int,
+                                          hipStream_t);
+template void gemm_grouped_skinny<float>(const GemmGroup<float>*, const std::vector<GemmGroup<float>>&, int,
+                                         hipStream_t);
+
 template void gemm_grouped<double>(const GemmGroup<double>*, const std::vector<GemmGroup<double>>&, hipStream_t);
 template void gemm_grouped<float>(const GemmGroup<float>*, const std::vector<GemmGroup<float>>&, hipStream_t);
 
