@@ -398,6 +398,8 @@ def main():
     ap.add_argument("--lengths", default="",
                     help="subdomain lengths instead of the workload's: comma-separated, or one integer m for "
                          "subdomains of m sites")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each local problem's products from a HIP graph of their launches")
     ap.add_argument("--coarse-krylov", action="store_true",
                     help="Step 3 by Lanczos without forming the coarse Hamiltonian matrix")
     ap.add_argument("--one-site", action="store_true",
@@ -459,7 +461,7 @@ def main():
     ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                   refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=args.sub_workers,
                   coarse_k=args.coarse_k, one_site=args.one_site, functional=functional,
-                  coarse_krylov=args.coarse_krylov)
+                  coarse_krylov=args.coarse_krylov, graph_products=args.graphs)
     workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
     if args.linear:
@@ -510,7 +512,7 @@ def main():
         ctx1 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                        refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1,
                        coarse_k=args.coarse_k, one_site=args.one_site, functional=functional,
-                  coarse_krylov=args.coarse_krylov)
+                  coarse_krylov=args.coarse_krylov, graph_products=args.graphs)
         ctx1.set_mpo(mpo)
         if args.linear:
             ctx1.set_rhs(Fcores, Flabels)
@@ -542,6 +544,7 @@ def main():
                    "concurrent_subdomain_solves": workers, "coarse_k": args.coarse_k,
                    "micro_step": "one-site" if args.one_site else "two-site",
                    "coarse_solve": "krylov (no coarse matrix)" if args.coarse_krylov else "explicit matrices",
+                   "graph_products": bool(args.graphs),
                    "functional": "linear (1/2 <X,AX> - <F,X>)" if args.linear else "eigenvalue (Rayleigh quotient)",
                    **({"chi_f": args.chi_f, "shift_sigma": sigma} if args.linear else {})},
         "heff_tflops_block_sparse": round(float(stats[:, 2].sum()) / max(heff_ms * 1e-3, 1e-12) / 1e12, 3),

@@ -137,6 +137,10 @@ typedef struct tt_opts {
                          block TT of Step 4, bonds regrouped by charge) through one left and
                          one right environment chain and a branch per update.  The report's A
                          is then NaN.  functional = 0 only (EINVAL otherwise). */
+  int graph_products; /* 1: each local problem's block-sparse two-site products replay a HIP
+                         graph of their launches (captured at the second product; the first
+                         runs eagerly), saving the per-kernel launch cost; results are bit for
+                         bit those of eager launches.  Off while tt_kernel_timing records. */
 } tt_opts;
 
 #define TT_MAX_SUB 64

@@ -39,14 +39,16 @@ class Context:
     def __init__(self, chi=64, dav_tol=1e-8, dav_maxiter=200, dav_maxsub=24, coarse_eps=1e-8, svd_cutoff=1e-12,
                  tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True,
                  sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0, stream=None, torch_alloc=False,
-                 coarse_k=1, one_site=False, functional="eig", coarse_krylov=False):
+                 coarse_k=1, one_site=False, functional="eig", coarse_krylov=False,
+                 graph_products=False):
         """``stream``: a torch.cuda.Stream (or raw stream handle) every call runs on;
         ``torch_alloc``: take every device block of the context from the torch caching
         allocator (tt_opts.dev_alloc/dev_free) instead of the library's own pools;
         ``one_site``: one-site micro-steps (FP64 products) instead of two-site ones;
         ``functional``: "eig" (Rayleigh quotient, the eigenvalue problem) or "linear"
         (1/2 <X,AX> - <F,X> with F from ``set_rhs``; A must be positive definite);
-        ``coarse_krylov``: Step 3 by Lanczos without forming the coarse matrix."""
+        ``coarse_krylov``: Step 3 by Lanczos without forming the coarse matrix;
+        ``graph_products``: replay the block-sparse products from HIP graphs."""
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -73,6 +75,7 @@ class Context:
             raise ValueError("functional must be 'eig' or 'linear'")
         o.functional = 1 if functional == "linear" else 0
         o.coarse_krylov = int(bool(coarse_krylov))
+        o.graph_products = int(bool(graph_products))
         self.functional = functional
         if stream is not None:
             o.stream = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))

@@ -83,8 +83,11 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
 // y = H_eff x.  L: [RAx][rlp][rlp] (virtual channels included), R: [RC][rrp][rrp],
 // Rt: [RCx - RC][rrp][rrp] (second-site block channels), x, y: [rlp][4][4][rrp].
 // bf16_t3 rounds the mix-2 output to bfloat16 before the last contraction.
+// check = false: launches only (graph capture); bs_check then reads the plan's index check.
 template <typename T>
-void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3);
+void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3,
+              bool check = true);
+void bs_check(Engine& E, BsPlan& p);
 
 // ---------------------------------------------------------------------------
 // Block-sparse environment update through one site (FP64).

@@ -1089,7 +1089,8 @@ static void run_mix(Engine& E, const BsPlan& p, const BsMix& m, const T* in, lon
 }
 
 template <typename T>
-void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3) {
+void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3,
+              bool check) {
   if (!p.ok) throw std::runtime_error("block-sparse plan not built");
   hipStream_t s = E.stream;
   const int prec = sizeof(T) == 8 ? 0 : 1;
@@ -1159,11 +1160,7 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
     BSCHECK(hipGetLastError());
     E.kt_mark(8);
   }
-  int herr = 0;
-  BSCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
-  BSCHECK(hipStreamSynchronize(s));
-  if (herr != 0)
-    throw std::runtime_error("block-sparse product: index outside its buffer (check " + std::to_string(herr) + ")");
+  if (check) bs_check(E, p);
   const double el = (double)sizeof(T);
   const double fl[Engine::KT_SLOTS] = {p.flops1, p.m1.fl_light, p.m1.fl_heavy, 0.0, p.m2.fl_light, p.m2.fl_heavy,
                                        0.0, p.flops4, 0.0};
@@ -1209,8 +1206,17 @@ void bs_splitk_run(Engine& E, int ntiles, const BsS4Tile* tiles, int nred, const
   if (slot_red >= 0) E.kt_mark(slot_red);
 }
 
+void bs_check(Engine& E, BsPlan& p) {
+  int herr = 0;
+  BSCHECK(hipMemcpyAsync(&herr, p.err.as<int>(), sizeof(int), hipMemcpyDeviceToHost, E.stream));
+  BSCHECK(hipStreamSynchronize(E.stream));
+  if (herr != 0)
+    throw std::runtime_error("block-sparse product: index outside its buffer (check " + std::to_string(herr) + ")");
+}
+
 template void bs_apply<double>(Engine&, BsPlan&, const double*, const double*, const double*, const double*, double*,
-                               bool);
-template void bs_apply<float>(Engine&, BsPlan&, const float*, const float*, const float*, const float*, float*, bool);
+                               bool, bool);
+template void bs_apply<float>(Engine&, BsPlan&, const float*, const float*, const float*, const float*, float*, bool,
+                              bool);
 
 }  // namespace tt

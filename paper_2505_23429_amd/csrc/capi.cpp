@@ -155,6 +155,7 @@ void tt_default_opts(tt_opts* o) {
   o->one_site = 0;
   o->functional = 0;
   o->coarse_krylov = 0;
+  o->graph_products = 0;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -168,7 +169,8 @@ int tt_create(const tt_opts* opts, void** out) {
       (opts->one_site && (opts->matvec_prec != TT_F64 || !opts->qn_skip)) || opts->functional < 0 ||
       opts->functional > 1 ||
       (opts->functional == 1 && (opts->matvec_prec != TT_F64 || !opts->qn_skip || opts->coarse_k != 1)) ||
-      opts->coarse_krylov < 0 || opts->coarse_krylov > 1 || (opts->coarse_krylov && opts->functional != 0))
+      opts->coarse_krylov < 0 || opts->coarse_krylov > 1 || (opts->coarse_krylov && opts->functional != 0) ||
+      opts->graph_products < 0 || opts->graph_products > 1)
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);

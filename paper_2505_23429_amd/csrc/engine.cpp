@@ -2066,6 +2066,24 @@ struct Window {
   int nphys = 16;         // local states of the window: 16 (two sites) or 4 (one site)
   bool one = false;       // one-site window (FP64 block-sparse product bs1, L in Lx, R in R64)
   BsHeff1 bs1;
+  // HIP graphs of the block-sparse product's launches (tt_opts.graph_products), one per
+  // product precision: captured at the second product with the same x and y, replayed
+  // while they stay
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  const double* gx[3] = {nullptr, nullptr, nullptr};
+  double* gy[3] = {nullptr, nullptr, nullptr};
+  // the engine workspaces a captured graph addresses (checked before every replay), the
+  // precision the window's products have used, and whether graphs are off for it
+  std::array<const void*, 16> gsig[3] = {};
+  int gprec_used = -1;
+  bool graph_off = false;
+  Window() = default;
+  Window(const Window&) = delete;
+  Window& operator=(const Window&) = delete;
+  ~Window() {
+    for (hipGraphExec_t g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+  }
 };
 
 // diag[a][s1][s2][b] = sum_B (sum_A W1[A,s1,s1,B] L_A[a][a]) (sum_C W2[B,s2,s2,C] R_C[b][b])
@@ -2334,6 +2352,85 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
   window_diag(E, w, Le, b, Re);
 }
 
+// the launches of one block-sparse two-site product (no host synchronisation)
+static void bs_launch(Engine& E, Window& w, const double* x, double* y, int prec) {
+  const size_t n = (size_t)w.rlp * 16 * w.rrp;
+  if (prec == TT_F64) {
+    bs_apply<double>(E, w.bs, w.Lx.as<double>(), w.R64, w.nP ? w.Rt.as<double>() : nullptr, x, y, false, false);
+  } else {
+    E.wlow_x.ensure(sizeof(float) * n);
+    E.wlow_y.ensure(sizeof(float) * n);
+    if (prec == TT_BF16) convert_f64_bf16f32(x, E.wlow_x.as<float>(), n, E.stream);
+    else convert_f64_f32(x, E.wlow_x.as<float>(), n, E.stream);
+    bs_apply<float>(E, w.bs, w.L32.as<float>(), w.R32.as<float>(), w.nP ? w.Rt32.as<float>() : nullptr,
+                    E.wlow_x.as<float>(), E.wlow_y.as<float>(), prec == TT_BF16, false);
+    convert_f32_f64(E.wlow_y.as<float>(), y, n, E.stream);
+  }
+}
+
+// Block-sparse product through a HIP graph: the first product with (x, y, prec) runs
+// eagerly (it makes the plan's one-time uploads and fills), the second is captured and
+// every later one replays the captured launches.  Returns false when the product was not
+// launched here (capture not possible): the caller then launches it eagerly.
+static std::array<const void*, 16> bs_workspace_sig(const Engine& E) {
+  std::array<const void*, 16> s{};
+  int i = 0;
+  for (const DevMem* m : {&E.bs_t1, &E.bs_t2, &E.bs_t3, &E.bs_part, &E.bs_tmp, &E.wlow_x, &E.wlow_y}) s[i++] = m->p;
+  for (int b = 0; b < 4; ++b) {
+    s[i++] = E.bs_gg1[b].p;
+    s[i++] = E.bs_gg2[b].p;
+  }
+  return s;
+}
+
+// A graph replays launches whose operands include engine workspaces (intermediates, the
+// heavy-row GEMM descriptors, T1's never-written entries, which an eager product zeroes
+// when the precision changes).  Products of another precision on the same engine rewrite
+// or reallocate them, so graphs are used only while a window's products keep one
+// precision (the FP64-anchored refinement alternates: its windows run eagerly) and only
+// while the workspaces are where they were at capture.
+static bool bs_graph_product(Engine& E, Window& w, const double* x, double* y, int prec) {
+  if (prec < 0 || prec > 2 || w.graph_off) return false;
+  if (w.gprec_used >= 0 && w.gprec_used != prec) {
+    for (hipGraphExec_t& g : w.gexec)
+      if (g) {
+        HC(hipGraphExecDestroy(g));
+        g = nullptr;
+      }
+    w.graph_off = true;
+    return false;
+  }
+  w.gprec_used = prec;
+  hipGraphExec_t& ge = w.gexec[prec];
+  if (ge && (w.gx[prec] != x || w.gy[prec] != y || w.gsig[prec] != bs_workspace_sig(E))) {
+    HC(hipGraphExecDestroy(ge));
+    ge = nullptr;
+    w.gx[prec] = nullptr;  // the next product runs eagerly, the one after is captured
+  }
+  if (!ge) {
+    const bool second = w.gx[prec] == x && w.gy[prec] == y;
+    w.gx[prec] = x;
+    w.gy[prec] = y;
+    if (!second) return false;
+    hipGraph_t g = nullptr;
+    HC(hipStreamBeginCapture(E.stream, hipStreamCaptureModeThreadLocal));
+    bool ok = true;
+    try {
+      bs_launch(E, w, x, y, prec);
+    } catch (...) {
+      ok = false;
+    }
+    const hipError_t ec = hipStreamEndCapture(E.stream, &g);
+    if (ok && ec == hipSuccess && g && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) ge = nullptr;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!ge) return false;
+    w.gsig[prec] = bs_workspace_sig(E);
+  }
+  HC(hipGraphLaunch(ge, E.stream));
+  return true;
+}
+
 static void window_matvec(Engine& E, Window& w, const double* x, double* y, int prec) {
   const size_t n = (size_t)w.rlp * 16 * w.rrp;
   E.cur_rl = w.rl; E.cur_rr = w.rr; E.cur_RA = w.RA; E.cur_RC = w.RC;
@@ -2343,17 +2440,10 @@ static void window_matvec(Engine& E, Window& w, const double* x, double* y, int 
     if (prec != TT_F64) throw std::logic_error("one-site products run in FP64 only");
     bs_heff1_apply(E, w.bs1, w.Lx.as<double>(), x, y);
   } else if (w.use_bs) {
-    if (prec == TT_F64) {
-      bs_apply<double>(E, w.bs, w.Lx.as<double>(), w.R64, w.nP ? w.Rt.as<double>() : nullptr, x, y, false);
-    } else {
-      E.wlow_x.ensure(sizeof(float) * n);
-      E.wlow_y.ensure(sizeof(float) * n);
-      if (prec == TT_BF16) convert_f64_bf16f32(x, E.wlow_x.as<float>(), n, E.stream);
-      else convert_f64_f32(x, E.wlow_x.as<float>(), n, E.stream);
-      bs_apply<float>(E, w.bs, w.L32.as<float>(), w.R32.as<float>(), w.nP ? w.Rt32.as<float>() : nullptr,
-                      E.wlow_x.as<float>(), E.wlow_y.as<float>(), prec == TT_BF16);
-      convert_f32_f64(E.wlow_y.as<float>(), y, n, E.stream);
-    }
+    // kernel timing records events between the launches: always eager
+    const bool graphed = E.opts.graph_products && !E.kt_on && bs_graph_product(E, w, x, y, prec);
+    if (!graphed) bs_launch(E, w, x, y, prec);
+    bs_check(E, w.bs);
   } else if (prec == TT_F64) {
     E.heff<double>(w.rlp, w.rrp, w.RAx, w.Lx.as<double>(), *w.w1, w.RB, *w.w2, w.RC, w.R64, x, y,
                    w.nP ? w.Rt.as<double>() : nullptr, w.P0, w.nP, tabs);
