@@ -184,7 +184,8 @@ def mfma_summary(pmc_csv, bench_json, command):
                    "dispatches; MfmaFlops: counted matrix-core flops per dispatch (including the zero padding of "
                    "partial tiles); algorithmic flops: block-sparse flops per launch from the same run",
            "kernels": {}}
-    for slot, sym in list(KERNEL_SYMBOLS.items()) + [("mix1_heavy_gemm", "gemm_grouped_kernel<float")]:
+    extra = [("mix1_heavy_gemm", "gemm_grouped_kernel<float"), ("heavy_skinny", "skinny_mfma_kernel<float")]
+    for slot, sym in list(KERNEL_SYMBOLS.items()) + extra:
         ds = [d for d, n in names.items() if sym in n and "MfmaUtil" in per[d]]
         if not ds:
             continue
@@ -192,10 +193,12 @@ def mfma_summary(pmc_csv, bench_json, command):
         mf = sum(per[d].get("MfmaFlops", 0.0) for d in ds) / len(ds)
         k = run["kernels"].get(slot, {})
         alg = k["tflops"] * 1e12 * k["ms"] * 1e-3 / k["launches"] if k.get("launches") else None
-        out["kernels"][slot if slot != "mix1_heavy_gemm" else "heavy_gemm_grouped"] = {
+        heavy = slot in ("mix1_heavy_gemm", "heavy_skinny")
+        key = {"mix1_heavy_gemm": "heavy_gemm_grouped (more than 64 rows)",
+               "heavy_skinny": "heavy_gemm_skinny (at most 64 rows)"}.get(slot, slot)
+        out["kernels"][key] = {
             "symbol": sym, "dispatches": len(ds), "mfma_util_percent": round(util, 2),
-            "mfma_flops_per_dispatch": mf,
-            "algorithmic_flops_per_launch": alg if slot != "mix1_heavy_gemm" else None}
+            "mfma_flops_per_dispatch": mf, "algorithmic_flops_per_launch": None if heavy else alg}
     return out
 
 
