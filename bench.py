@@ -48,6 +48,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_a2dmrg_L32_chi512.txt")
 KERNEL_SOURCES = ("paper_2505_23429_amd/csrc/bsheff.hip", "paper_2505_23429_amd/csrc/bsheff.h")
 # timing slots of the product and the kernel symbols they stand for (FP32 products)
 KERNEL_SYMBOLS = {
+    "gemm_LWx_panels": "lw_gemm_kernel<float, 2>",
+    "gemm_panels_WR": "stage4_mfma_kernel<float>",
+    "gemm_panels_WR_reduce": "reduce4_kernel<float>",
+    "gemm_LWx": "lw_gemm_kernel<float, 1>",
     "gemm_Lx": "stage1_mfma_kernel<float>",
     "mix1_gather": "mix_kernel<float, 1, false>",
     "mix1_heavy_scatter": "mix_kernel<float, 1, true>",
@@ -401,6 +405,8 @@ def main():
     ap.add_argument("--lengths", default="",
                     help="subdomain lengths instead of the workload's: comma-separated, or one integer m for "
                          "subdomains of m sites")
+    ap.add_argument("--precontract", type=int, default=2, choices=(0, 1, 2),
+                    help="site tensors contracted with their environment once per window: 2 both, 1 left, 0 none")
     ap.add_argument("--graphs", action="store_true",
                     help="replay each local problem's products from a HIP graph of their launches")
     ap.add_argument("--coarse-krylov", action="store_true",
@@ -464,7 +470,8 @@ def main():
     ctx = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                   refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=args.sub_workers,
                   coarse_k=args.coarse_k, one_site=args.one_site, functional=functional,
-                  coarse_krylov=args.coarse_krylov, graph_products=args.graphs)
+                  coarse_krylov=args.coarse_krylov, graph_products=args.graphs,
+                  precontract=args.precontract)
     workers = min(args.sub_workers or 4, len(lengths))
     ctx.set_mpo(mpo)
     if args.linear:
@@ -502,7 +509,8 @@ def main():
     stats = ctx.kernel_timing(enable=False, reset=True)
     sec = (te - ts) / args.steps
     fl = sum(r["flops_heff"] for r in reps)
-    names = Context.KERNELS_ONE_SITE if args.one_site else Context.KERNELS
+    names = (Context.KERNELS_ONE_SITE if args.one_site else
+             (Context.KERNELS, Context.KERNELS_LEFT_OPERATOR, Context.KERNELS_PRECONTRACTED)[args.precontract])
     kernels_timed = breakdown_of(names, stats)
     iso_note = "timed region (one solve at a time)"
     if workers > 1:
@@ -515,7 +523,8 @@ def main():
         ctx1 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24, matvec_prec=prec,
                        refine_fp64=refine, lowprec_tol=args.lowprec_tol, sub_workers=1,
                        coarse_k=args.coarse_k, one_site=args.one_site, functional=functional,
-                  coarse_krylov=args.coarse_krylov, graph_products=args.graphs)
+                  coarse_krylov=args.coarse_krylov, graph_products=args.graphs,
+                  precontract=args.precontract)
         ctx1.set_mpo(mpo)
         if args.linear:
             ctx1.set_rhs(Fcores, Flabels)
@@ -550,6 +559,9 @@ def main():
                    "micro_step": "one-site" if args.one_site else "two-site",
                    "coarse_solve": "krylov (no coarse matrix)" if args.coarse_krylov else "explicit matrices",
                    "graph_products": bool(args.graphs),
+                   "precontracted": ("none (L x, sparse W1 and W2 mixes, R in every product)",
+                                     "left (L W1 once per window)",
+                                     "left and right (L W1, W2 R once per window)")[args.precontract],
                    "functional": "linear (1/2 <X,AX> - <F,X>)" if args.linear else "eigenvalue (Rayleigh quotient)",
                    **({"chi_f": args.chi_f, "shift_sigma": sigma} if args.linear else {})},
         "heff_tflops_block_sparse": round(heff_fl_sweep / max(heff_s_sweep, 1e-12) / 1e12, 3),
@@ -572,7 +584,7 @@ def main():
         ctx.close()
         ctx64 = Context(chi=chi, dav_tol=tol, dav_maxiter=maxiter, dav_maxsub=24,
                         matvec_prec="f64", refine_fp64=False, sub_workers=args.sub_workers,
-                        coarse_k=args.coarse_k)
+                        coarse_k=args.coarse_k, precontract=args.precontract)
         ctx64.set_mpo(mpo)
         ctx64.set_mps(cores, labels)
         ctx64.checkpoint()

@@ -141,6 +141,17 @@ typedef struct tt_opts {
                          graph of their launches (captured at the second product; the first
                          runs eagerly), saving the per-kernel launch cost; results are bit for
                          bit those of eager launches.  Off while tt_kernel_timing records. */
+  int precontract;    /* block-sparse two-site products (eq. mat_vec): which MPO site tensors are
+                         contracted with their environment once per window instead of in every
+                         product.  0 = none: every product forms L_A x for all left channels,
+                         applies W1 and then W2 as sparse combinations of rows, and contracts
+                         with R.  1 = the left operator LW[B] = sum_A W1[A, s1', s1, B] L_A
+                         (formed in FP64): every product applies it to x in one grouped
+                         matrix-core GEMM, then W2 and R as for 0.  2 (default) = the left and
+                         the right operator WR[B] = sum_C W2[B, s2', s2, C] R_C: every product
+                         is one GEMM with LW into panels of the bra's left half and one split-K
+                         GEMM of the panels with WR.  Same contraction, different summation
+                         order. */
 } tt_opts;
 
 #define TT_MAX_SUB 64
@@ -325,7 +336,11 @@ int tt_energy_mpo_grad(void* ctx, double* E, double* const* gops);
  * flops, algorithmic bytes] for the kernels: 0 L.x GEMM; 1, 2, 3 site-1 mix
  * (gather of the rows with few operator entries, GEMM of the rows with many,
  * scatter of those); 4, 5, 6 the same for site 2; 7 R GEMM; 8 its K-split
- * reduction.  One-site products (tt_opts.one_site) use 0 (stage 1: L.x), 1 (light
+ * reduction.  With tt_opts.precontract = 1, slot 0 is the GEMM with the left operator
+ * (slots 1-3 unused); with precontract = 2, slot 0 is that GEMM into the panels, 7 the
+ * panels x right-operator GEMM and 8 its reduction (slots 1-6 unused).  The forming of
+ * the operators (once per window) is not in the stats.  One-site products
+ * (tt_opts.one_site) use 0 (stage 1: L.x), 1 (light
  * rows of the mix), 2 (GEMM of the heavy rows), 3 (their mix pass), 7 (the
  * products with the stacked right environment) and 8 (their K-split reduction).  Algorithmic work counts only the quantum-number-allowed blocks
  * (block-sparse product) and each operand element moved once.  reset != 0

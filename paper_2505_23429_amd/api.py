@@ -40,7 +40,7 @@ class Context:
                  tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True,
                  sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0, stream=None, torch_alloc=False,
                  coarse_k=1, one_site=False, functional="eig", coarse_krylov=False,
-                 graph_products=False):
+                 graph_products=False, precontract=2):
         """``stream``: a torch.cuda.Stream (or raw stream handle) every call runs on;
         ``torch_alloc``: take every device block of the context from the torch caching
         allocator (tt_opts.dev_alloc/dev_free) instead of the library's own pools;
@@ -48,7 +48,10 @@ class Context:
         ``functional``: "eig" (Rayleigh quotient, the eigenvalue problem) or "linear"
         (1/2 <X,AX> - <F,X> with F from ``set_rhs``; A must be positive definite);
         ``coarse_krylov``: Step 3 by Lanczos without forming the coarse matrix;
-        ``graph_products``: replay the block-sparse products from HIP graphs."""
+        ``graph_products``: replay the block-sparse products from HIP graphs;
+        ``precontract``: 2 = contract each environment with its site's MPO tensor once
+        per window (every product is then two GEMMs), 1 = only the left one, 0 = none
+        (every product forms L x and applies both site tensors as sparse mixes)."""
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -76,6 +79,9 @@ class Context:
         o.functional = 1 if functional == "linear" else 0
         o.coarse_krylov = int(bool(coarse_krylov))
         o.graph_products = int(bool(graph_products))
+        if precontract not in (0, 1, 2):
+            raise ValueError("precontract must be 0, 1 or 2")
+        o.precontract = int(precontract)
         self.functional = functional
         if stream is not None:
             o.stream = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
@@ -222,7 +228,12 @@ class Context:
 
     KERNELS = ("gemm_Lx", "mix1_gather", "mix1_heavy_gemm", "mix1_heavy_scatter", "mix2_gather",
                "mix2_heavy_gemm", "mix2_heavy_scatter", "gemm_R", "gemm_R_reduce")
-    # the same timing slots as filled by one-site products (unused slots: "-")
+    # the same timing slots as filled by two-site products with the precontracted left
+    # operator (its GEMM takes the place of stage 1 and the first mix), with both
+    # precontracted operators, and by one-site products (unused slots: "-")
+    KERNELS_LEFT_OPERATOR = ("gemm_LWx", "-", "-", "-", "mix2_gather", "mix2_heavy_gemm", "mix2_heavy_scatter",
+                             "gemm_R", "gemm_R_reduce")
+    KERNELS_PRECONTRACTED = ("gemm_LWx_panels", "-", "-", "-", "-", "-", "-", "gemm_panels_WR", "gemm_panels_WR_reduce")
     KERNELS_ONE_SITE = ("env_s1_Lx", "env_mix_gather", "env_mix_heavy_gemm", "env_mix_heavy", "-", "-", "-",
                         "gemm_R_stacked", "gemm_R_stacked_reduce")
 

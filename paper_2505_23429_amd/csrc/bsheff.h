@@ -14,6 +14,26 @@
 //   stage 4  y  = sum_C T3 R_C^T  grouped split-K GEMM per right sector beta'
 // store and touch only the structurally non-zero entries.  The environments
 // stay dense; x and y are the dense padded vectors [rlp][4][4][rrp].
+//
+// Stage 1 and mix 1 can instead run as one GEMM on a precontracted left operator
+//   LW[(B, s1', alpha', i')][(s1, a)] = sum_A W1[A, s1', s1, B] L_A[alpha' + i'][alpha + a]
+// (alpha' = alpha + d_A), which depends on the window only and is formed once per
+// window.  Its rows are grouped by the charge gamma = alpha + q(s1) = alpha' + q(s1')
+// - d_B of the ket's left half and by the set of site states s1 with a non-zero
+// operator entry in row s1' of channel B (the mask); per group
+//   T2[(B, s2)][spec(alpha', s1', beta) + i' n_beta + j] = sum_(s1, a) LW x[a][s1][s2][j],
+// beta = gamma + q(s2): T1 is never formed, and the heavy rows of W1 (the
+// accumulating channels) are summed once per window instead of once per product.
+//
+// With the right operator precontracted as well,
+//   WR[(B, s2, b)][j'] = sum_C W2[B, s2', s2, C] R_C[beta' + j'][beta + b]
+// (also formed once per window), the rest of the product is one split-K GEMM per
+// panel (zeta, s2'): zeta = alpha' + q(s1') is the charge of the bra's left half, the
+// panel's rows are (s1', alpha' = zeta - q(s1'), i') and its K runs over the chunks
+// (B, s2, b) whose operator entries reach s2' (beta = zeta - d_B + q(s2),
+// beta' = zeta + q(s2')); the left-operator GEMM writes each of its outputs into the
+// panels that use it, and y[alpha', s1', s2', beta'] = panel x WR.  T2 as rows (B, s2),
+// the second mix and T3 are then never formed either.
 #pragma once
 #include "engine.h"
 
@@ -36,6 +56,29 @@ struct MixTile { int g, c0, r0, r1, s0, ns, pad0, pad1; };
 struct BsS4Tile { long long abase, bbase; int M, N, K, m0, n0, k0, k1, slot; };
 struct BsRedTile { int M, N, m0, n0, slot0, nsplit, row0, pad; };
 struct BsPair { int C, beta, koff, bprime; };
+// One GEMM of the precontracted left operator: rows [0, M) (row blocks [rb0, rb0 + nrb)),
+// LW rows at a0 with stride K4 (K rounded up to 4; the padding is zero), K entries of the
+// x-row table from k0 (pieces: site state ps, first k pk, length pn, ket sector pa), N
+// columns of the column table from n0 ({x offset, s2 << 20 | j}), right sector be[s2].
+struct BsLwGroup {
+  long long a0;
+  int M, K, K4, N, k0, n0, rb0, nrb, np, pad;
+  int be[4], ps[4], pk[4], pn[4], pa[4];
+};
+// rows [r0, r0 + n) of group g: output channel and bra state bs = B * 4 + s1', bra sector
+// ap; with the right operator, zi indexes the panels of the block's zeta and kci the chunk
+// table (entries [kci * 16 + s2 * 4 + s2']: the chunk's first panel column, -1 none)
+struct BsLwBlock { int g, r0, n, bs, ap, zi, kci, pad; };
+// panels of one zeta: M rows (s1', alpha', i') from row0[s1'] (-1: no alpha'); per s2' the
+// panel at pbase[s2'] with K[s2'] columns (-1: no panel)
+struct BsZeta { long long pbase[4]; int K[4]; int row0[4]; int M, pad; };
+// one panel: rows M, K (the chunks (B, s2) at columns [kc, kc + n_beta)), N = n_beta';
+// A at pbase is [M][K] row-major, WR at wbase is [K][N]
+struct BsPanel { long long pbase, wbase; int M, K, N, zi, s2p, bep, pad0, pad1; };
+// one block of WR: panel P, chunk (B, s2) = bs2 / 4, bs2 % 4 at column kc, right sector be
+struct BsWrItem { int P, bs2, kc, be; };
+// one workgroup: rows [m0, m0 + 128) of group g, overlapped by row blocks [rb0, rb0 + nrb)
+struct BsLwTile { int g, m0, rb0, nrb; };
 
 // One sparse x dense mix.  Output rows with few operator entries ("light",
 // nearly all of them) are gathered entry by entry; the few rows with many
@@ -73,6 +116,23 @@ struct BsPlan {
   DevMem tiles4, red, rowdst, pairs, rbase;
   DevMem rstack64, rstack32;
   bool have64 = false, have32 = false;
+  // precontracted left operator (lw): replaces stage 1 and mix 1
+  bool lw = false;
+  int nlw_groups = 0, nlw_tiles = 0, nlw_blocks = 0;
+  long long nlw = 0;                       // elements of LW
+  double flops_lw = 0.0, bytes_lw = 0.0;   // per product: flops; elements of LW, x read and T2 written
+  double build_lw = 0.0;                   // multiply-adds of forming LW (once per window)
+  DevMem lw_groups, lw_tiles, lw_blocks, lw_krow, lw_col, lw_tptr, lw_tA, lw_tv, rowbase2, aoff;
+  DevMem lw64, lw32;
+  bool have_lw64 = false;
+  int lw32_state = 0;                      // LW in FP32: 0 not formed, 1 rounded to FP32, 2 to bfloat16
+  // precontracted right operator (wr, with lw): panels replace T2, mix 2, T3 and stage 4's panels
+  bool wr = false;
+  int nwr_items = 0, npanels = 0;
+  long long nwr = 0;                       // elements of WR (n2: elements of the panels)
+  double build_wr = 0.0;                   // multiply-adds of forming WR
+  DevMem lw_zeta, lw_kc, wr_items, wr_panels, wr_tptr, wr_tC, wr_tv, wr64, wr32;
+  int wr32_state = 0;
   DevMem err;  // set by a kernel when an index would leave its buffer (the access is skipped)
 };
 
@@ -88,6 +148,10 @@ template <typename T>
 void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T* x, T* y, bool bf16_t3,
               bool check = true);
 void bs_check(Engine& E, BsPlan& p);
+// Forms the precontracted operators of a plan with p.lw (FP64): LW from the environment
+// L [RAx][rlp][rlp] (nL elements) and, with p.wr, WR from R [RC][rrp][rrp] and the block
+// channels Rt [RCx - RC][rrp][rrp]; the FP32 copies follow on first use.
+void bs_lw_build(Engine& E, BsPlan& p, const double* L, long long nL, const double* R, const double* Rt);
 
 // ---------------------------------------------------------------------------
 // Block-sparse environment update through one site (FP64).

@@ -26,6 +26,7 @@ inline Q2 add(Q2 a, Q2 b) { return {a[0] + b[0], a[1] + b[1]}; }
 inline Q2 sub(Q2 a, Q2 b) { return {a[0] - b[0], a[1] - b[1]}; }
 
 constexpr int TILE = 64;       // output tile edge of the stage-1 and stage-4 kernels
+constexpr int LW_ROWS = 128;   // rows per workgroup of the left-operator GEMM
 constexpr int KT = 32;         // K slice staged in LDS
 constexpr int MIX_COLS = 256;  // spectator columns per mix workgroup (one per thread)
 constexpr int MIX_ROWS = 64;   // output rows per mix workgroup
@@ -57,6 +58,30 @@ bool make_sectors(const Labels& lab, Sectors& s) {
   }
   return true;
 }
+
+// sector index of a charge by table lookup (-1: none); the plan tables query it millions of times
+struct QLook {
+  int lo0 = 0, lo1 = 0, w0 = 0, w1 = 0;
+  std::vector<int> t;
+  explicit QLook(const Sectors& S) {
+    if (S.q.empty()) return;
+    int hi0 = S.q[0][0], hi1 = S.q[0][1];
+    lo0 = hi0;
+    lo1 = hi1;
+    for (const Q2& q : S.q) {
+      lo0 = std::min(lo0, q[0]); hi0 = std::max(hi0, q[0]);
+      lo1 = std::min(lo1, q[1]); hi1 = std::max(hi1, q[1]);
+    }
+    w0 = hi0 - lo0 + 1;
+    w1 = hi1 - lo1 + 1;
+    t.assign((size_t)w0 * w1, -1);
+    for (int i = 0; i < (int)S.q.size(); ++i) t[(size_t)(S.q[i][0] - lo0) * w1 + (S.q[i][1] - lo1)] = i;
+  }
+  int operator()(Q2 q) const {
+    const int a = q[0] - lo0, b = q[1] - lo1;
+    return (a < 0 || b < 0 || a >= w0 || b >= w1) ? -1 : t[(size_t)a * w1 + b];
+  }
+};
 
 template <class V>
 void up(DevMem& d, const std::vector<V>& v, hipStream_t s) {
@@ -185,6 +210,266 @@ __global__ __launch_bounds__(256) void stage1_mfma_kernel(
     const long long d = rp + so + (long long)R.y * nb[c] + Cc.w;
     if (rp < 0 || so < 0 || d >= nout) { err[0] = 3; continue; }
     out[d] = Cs[r][c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// precontracted left operator
+// ---------------------------------------------------------------------------
+// LW of one row block (output channel B, bra state s1', bra sector alpha'): element
+// (i', k) with k in piece p (site state s1, ket sector alpha) sums the operator
+// entries of (B, s1', s1) times L_A[alpha' + i'][alpha + k - pk]; the K padding is
+// written as zero.  Consecutive threads take consecutive k (consecutive L columns).
+__global__ __launch_bounds__(256) void lw_build_kernel(const BsLwBlock* __restrict__ blocks,
+                                                       const BsLwGroup* __restrict__ groups,
+                                                       const int* __restrict__ tptr, const int* __restrict__ tA,
+                                                       const double* __restrict__ tv, const int* __restrict__ aoff,
+                                                       const double* __restrict__ L, long long nL, int rlp,
+                                                       double* __restrict__ lw, long long nlw, int* __restrict__ err) {
+  const BsLwBlock b = blocks[blockIdx.x];
+  const BsLwGroup& G = groups[b.g];  // read in place: its piece arrays are indexed at run time
+  const long long rl2 = (long long)rlp * rlp;
+  const int tot = b.n * G.K4;
+  for (int e = threadIdx.x; e < tot; e += 256) {
+    const int ip = e / G.K4, k = e - ip * G.K4;
+    double acc = 0.0;
+    if (k < G.K) {
+      int p = 0;
+      while (p + 1 < G.np && k >= G.pk[p + 1]) ++p;
+      const int s1 = G.ps[p];
+      const long long rc = (long long)(aoff[b.ap] + ip) * rlp + aoff[G.pa[p]] + (k - G.pk[p]);
+      for (int t = tptr[b.bs * 4 + s1]; t < tptr[b.bs * 4 + s1 + 1]; ++t) {
+        const long long q = (long long)tA[t] * rl2 + rc;
+        if (q >= 0 && q < nL) acc += tv[t] * L[q]; else err[0] = 11;
+      }
+    }
+    const long long d = G.a0 + (long long)(b.r0 + ip) * G.K4 + k;
+    if (d >= 0 && d < nlw) lw[d] = acc; else err[0] = 11;
+  }
+}
+
+// WR block of one panel chunk (B, s2): element (b, j') sums the operator entries of
+// (B, s2', s2) times R_C[beta' + j'][beta + b] (C >= RC: the block channels Rt); rows
+// b of the panel's [K][N] matrix from the chunk's column.  Consecutive threads take
+// consecutive b (consecutive R columns).
+__global__ __launch_bounds__(256) void wr_build_kernel(const BsWrItem* __restrict__ items,
+                                                       const BsPanel* __restrict__ panels,
+                                                       const int* __restrict__ tptr, const int* __restrict__ tC,
+                                                       const double* __restrict__ tv, const int* __restrict__ boff,
+                                                       const int* __restrict__ nbeta, const double* __restrict__ R,
+                                                       long long nR, const double* __restrict__ Rt, long long nRt,
+                                                       int RC, int rrp, double* __restrict__ wr, long long nwr,
+                                                       int* __restrict__ err) {
+  const BsWrItem it = items[blockIdx.x];
+  const BsPanel P = panels[it.P];
+  const int B = it.bs2 >> 2, s2 = it.bs2 & 3;
+  const int nb = nbeta[it.be], np = P.N;
+  const long long rr2 = (long long)rrp * rrp;
+  const int ti = (B * 4 + P.s2p) * 4 + s2;
+  const int t0 = tptr[ti], t1 = tptr[ti + 1];
+  for (int e = threadIdx.x; e < nb * np; e += 256) {
+    const int jp = e / nb, b = e - jp * nb;
+    const long long rc = (long long)(boff[P.bep] + jp) * rrp + boff[it.be] + b;
+    double acc = 0.0;
+    for (int t = t0; t < t1; ++t) {
+      const int C = tC[t];
+      if (C < RC) {
+        const long long q = (long long)C * rr2 + rc;
+        if (q >= 0 && q < nR) acc += tv[t] * R[q]; else err[0] = 16;
+      } else {
+        const long long q = (long long)(C - RC) * rr2 + rc;
+        if (q >= 0 && q < nRt) acc += tv[t] * Rt[q]; else err[0] = 16;
+      }
+    }
+    const long long d = P.wbase + (long long)(it.kc + b) * np + jp;
+    if (d >= 0 && d < nwr) wr[d] = acc; else err[0] = 16;
+  }
+}
+
+// T2 = LW x for one tile of LW_ROWS rows of a group, all its columns (in passes of NC):
+// four waves of two 16-row blocks, 16 x 16 x 4 MFMA blocks over K in slices of KS.  The
+// x slice (shared by the waves) is staged in LDS with all threads loading; every lane
+// reads its A fragments (one LW row, four consecutive k per MFMA step) straight from
+// memory.  Results go from the accumulators to T2, where the columns of one s2 of a
+// row are contiguous and the rows of one row block follow each other.
+// MODE 1 writes T2 (rows (B, s2)); MODE 2 writes every panel (zeta, s2') that uses the
+// output (rounded to bfloat16 when rnd is set).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void lw_gemm_kernel(
+    const BsLwTile* __restrict__ tiles, const BsLwGroup* __restrict__ groups, const BsLwBlock* __restrict__ blocks,
+    const int* __restrict__ krow, const int2* __restrict__ col,
+    const T* __restrict__ lw, long long nlw, const T* __restrict__ x, long long nx,
+    const long long* __restrict__ rowbase2, const long long* __restrict__ specoff, const int* __restrict__ nbeta,
+    int nbe, const BsZeta* __restrict__ zetas,
+    const int* __restrict__ kctab, int rnd, T* __restrict__ out, long long nout, int* __restrict__ err) {
+  constexpr int ND = MODE == 2 ? 16 : 4;  // destinations per row: per s2 (and s2')
+  constexpr int KS = sizeof(T) == 4 ? 32 : 16;  // K slice
+  constexpr int NB = sizeof(T) == 4 ? 8 : 4;    // 16-column blocks per pass
+  constexpr int NC = NB * 16;
+  constexpr int MB = LW_ROWS / 64;              // 16-row blocks per wave
+  const BsLwTile t = tiles[blockIdx.x];
+  const BsLwGroup G = groups[t.g];
+  __shared__ T Bs[KS][NC + 4];
+  __shared__ long long rd[LW_ROWS][ND];
+  __shared__ int2 cl[NC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int mrows = min(LW_ROWS, G.M - t.m0);
+  if (MODE == 2 && tid < LW_ROWS) {
+    // panel offsets of row (B, s1', alpha', i') for each (s2, s2'): panel (zeta, s2') row
+    // (s1', alpha', i'), column of the chunk (B, s2); -1 where no panel uses it
+#pragma unroll
+    for (int i = 0; i < 16; ++i) rd[tid][i % ND] = -1;
+    if (tid < mrows) {
+      const int r = t.m0 + tid;
+      int q = -1, ip = 0;
+      for (int i = 0; i < t.nrb; ++i) {
+        const BsLwBlock b = blocks[t.rb0 + i];
+        if (r >= b.r0 && r < b.r0 + b.n) {
+          q = t.rb0 + i;
+          ip = r - b.r0;
+          break;
+        }
+      }
+      if (q < 0 || blocks[q].kci < 0) {
+        err[0] = 12;
+      } else {
+        const BsLwBlock b = blocks[q];
+        const BsZeta& Z = zetas[b.zi];
+        const int row = Z.row0[b.bs & 3] + ip;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int kc = kctab[(long long)b.kci * 16 + i], z = i & 3, be = G.be[i >> 2];
+          if (kc >= 0 && be >= 0) rd[tid][i % ND] = Z.pbase[z] + (long long)row * Z.K[z] + kc;
+          else if (kc >= 0) err[0] = 12;
+        }
+      }
+    }
+  }
+  if (MODE == 1 && tid < LW_ROWS) {
+    // T2 offset of row (B, s1', alpha', i') for each s2: row (B, s2), spectator (alpha', s1', beta), i' n_beta
+    long long d4[4] = {-1, -1, -1, -1};
+    if (tid < mrows) {
+      const int r = t.m0 + tid;
+      int q = -1, ip = 0;
+      for (int i = 0; i < t.nrb; ++i) {
+        const BsLwBlock b = blocks[t.rb0 + i];
+        if (r >= b.r0 && r < b.r0 + b.n) {
+          q = t.rb0 + i;
+          ip = r - b.r0;
+          break;
+        }
+      }
+      if (q < 0) {
+        err[0] = 12;
+      } else {
+        const BsLwBlock b = blocks[q];
+        const int ch = b.bs >> 2, s1p = b.bs & 3;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int be = G.be[s2];
+          if (be < 0) continue;
+          const long long rb = rowbase2[ch * 4 + s2];
+          const long long so = specoff[((long long)b.ap * 4 + s1p) * nbe + be];
+          if (rb < 0 || so < 0) err[0] = 12;
+          else d4[s2] = rb + so + (long long)ip * nbeta[be];
+        }
+      }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) rd[tid][s2 % ND] = d4[s2];
+  }
+  // this lane's A rows (row lane % 16 of each of the wave's row blocks)
+  const T* arow[MB];
+  bool aok[MB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int r = wv * (16 * MB) + m * 16 + (lane & 15);
+    const long long a = G.a0 + (long long)(t.m0 + r) * G.K4;
+    aok[m] = r < mrows && a >= 0 && a + G.K4 <= nlw;
+    if (r < mrows && !aok[m]) err[0] = 13;
+    arow[m] = lw + (aok[m] ? a : 0);
+  }
+  for (int c0 = 0; c0 < G.N; c0 += NC) {
+    const int nc = min(NC, G.N - c0), nblk = (nc + 15) >> 4;
+    __syncthreads();  // rd written; the previous pass is done with cl
+    for (int c = tid; c < NC; c += 256) cl[c] = c < nc ? col[G.n0 + c0 + c] : make_int2(0, -1);
+    T acc[MB][NB][4];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[m][j][v] = T(0);
+    for (int k0 = 0; k0 < G.K4; k0 += KS) {
+      __syncthreads();  // cl written; the previous slice consumed
+#pragma unroll 4
+      for (int e = tid; e < KS * NC; e += 256) {
+        const int u = e / NC, c = e % NC, k = k0 + u;
+        T v = T(0);
+        if (c < nc && k < G.K) {
+          const long long q = (long long)krow[G.k0 + k] + cl[c].x;
+          if (q >= 0 && q < nx) v = x[q]; else err[0] = 14;
+        }
+        Bs[u][c] = v;
+      }
+      T af[MB][KS / 4];
+#pragma unroll
+      for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int s = 0; s < KS / 4; ++s) {
+          const int k = k0 + 4 * s + (lane >> 4);
+          af[m][s] = aok[m] && k < G.K4 ? arow[m][k] : T(0);
+        }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < KS / 4; ++s) {
+        if (k0 + 4 * s < G.K4) {
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            if (j < nblk) {
+              const T bv = Bs[4 * s + (lane >> 4)][j * 16 + (lane & 15)];
+#pragma unroll
+              for (int m = 0; m < MB; ++m) s1_mfma<T>(af[m][s], bv, acc[m][j]);
+            }
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < nblk) {
+          const int cc = j * 16 + (lane & 15);
+          const int2 ci = cl[cc];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = wv * (16 * MB) + m * 16 + (sizeof(T) == 4 ? 4 * (lane >> 4) + v : 4 * v + (lane >> 4));
+            if (row >= mrows || cc >= nc) continue;
+            if (MODE == 1) {
+              const long long d0 = rd[row][(ci.y >> 20) % ND];
+              const long long d = d0 + (ci.y & 0xfffff);
+              if (d0 < 0 || d >= nout) { err[0] = 15; continue; }
+              out[d] = acc[m][j][v];
+            } else {
+              const T val = rnd ? (T)bf16_round((float)acc[m][j][v]) : acc[m][j][v];
+#pragma unroll 1
+              for (int z = 0; z < 4; ++z) {
+                const long long d0 = rd[row][((ci.y >> 20) * 4 + z) % ND];
+                if (d0 < 0) continue;
+                const long long d = d0 + (ci.y & 0xfffff);
+                if (d >= nout) { err[0] = 15; continue; }
+                out[d] = val;
+              }
+            }
+          }
+        }
+  }
+}
+
+__global__ void lw_round_kernel(const double* __restrict__ in, float* __restrict__ out, long long n, int bf16) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float v = (float)in[i];
+    out[i] = bf16 ? bf16_round(v) : v;
   }
 }
 
@@ -836,6 +1121,280 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   p.n1 = n1;
   p.n2 = n2;
 
+  // precontracted left operator: row blocks (B, s1', alpha') grouped by (gamma, mask)
+  p.lw = E.opts.precontract >= 1 && (long long)rlp * 16 * rrp < (1LL << 31);
+  p.wr = p.lw && E.opts.precontract == 2;
+  p.have_lw64 = false;
+  p.lw32_state = p.wr32_state = 0;
+  // panel GEMM tables (right operator)
+  std::vector<BsS4Tile> wtiles4;
+  std::vector<BsRedTile> wred;
+  std::vector<long long> wrowdst;
+  int wslots = 0;
+  double wflops = 0.0, wbytes = 0.0, wel_red = 0.0;
+  if (p.lw) {
+    p.n1 = 0;
+    // operator entries of (B, s1', s1): channel A and value; the charge of A is fixed by them
+    std::vector<int> tptr((size_t)RB * 16 + 1, 0), tA;
+    std::vector<double> tv;
+    for (int B = 0; B < RB; ++B)
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s1_ = 0; s1_ < 4; ++s1_) {
+          tptr[(size_t)(B * 4 + sp) * 4 + s1_] = (int)tA.size();
+          const Q2 want = add(sub(dB[B], kSiteQ[sp]), kSiteQ[s1_]);  // d_A = d_B + q(s1) - q(s1')
+          for (int e = w1.hptr[B]; e < w1.hptr[B + 1]; ++e) {
+            const double v = w1.hop[(size_t)e * 16 + sp * 4 + s1_];
+            if (v == 0.0) continue;
+            if (dA[w1.hsrc[e]] != want)
+              throw std::runtime_error("block-sparse plan: MPO entry breaks the charge grouping");
+            tA.push_back(w1.hsrc[e]);
+            tv.push_back(v);
+          }
+        }
+    tptr[(size_t)RB * 16] = (int)tA.size();
+    const QLook fa(SA), fb(SB);
+    // right operator: panels (zeta, s2') and their chunks (B, s2), WR blocks, chunk table
+    std::map<Q2, int> zid;
+    std::vector<Q2> zq;
+    std::vector<BsZeta> zetas;
+    std::vector<BsPanel> panels;
+    std::vector<BsWrItem> items;
+    std::vector<int> kctab, bzk, t2ptr, t2C;
+    std::vector<double> t2v;
+    if (p.wr) {
+      // operator entries of the second site by (B, s2', s2): channel C and value
+      std::vector<std::vector<std::pair<int, double>>> lst((size_t)RB * 16);
+      for (int C = 0; C < RCx; ++C)
+        for (int e = w2.hptr[C]; e < w2.hptr[C + 1]; ++e) {
+          const int B = w2.hsrc[e];
+          for (int s2p = 0; s2p < 4; ++s2p)
+            for (int s2_ = 0; s2_ < 4; ++s2_) {
+              const double v = w2.hop[(size_t)e * 16 + s2p * 4 + s2_];
+              if (v == 0.0) continue;
+              if (dC[C] != add(sub(dB[B], kSiteQ[s2_]), kSiteQ[s2p]))  // d_C = d_B + q(s2') - q(s2)
+                throw std::runtime_error("block-sparse plan: MPO entry breaks the charge grouping");
+              lst[(size_t)(B * 4 + s2p) * 4 + s2_].emplace_back(C, v);
+            }
+        }
+      std::vector<int> rel((size_t)RB * 4, 0);  // s2' reached by the entries of (B, s2)
+      t2ptr.assign((size_t)RB * 16 + 1, 0);
+      for (size_t i = 0; i < lst.size(); ++i) {
+        t2ptr[i] = (int)t2C.size();
+        for (auto& cv : lst[i]) {
+          t2C.push_back(cv.first);
+          t2v.push_back(cv.second);
+        }
+        if (!lst[i].empty()) rel[(i / 16) * 4 + (i % 4)] |= 1 << ((i / 4) % 4);
+      }
+      t2ptr[(size_t)RB * 16] = (int)t2C.size();
+      for (int ap = 0; ap < nal; ++ap)
+        for (int sp = 0; sp < 4; ++sp) {
+          const Q2 z = add(SA.q[ap], kSiteQ[sp]);
+          if (!zid.count(z)) {
+            zid[z] = (int)zq.size();
+            zq.push_back(z);
+          }
+        }
+      const int nz = (int)zq.size();
+      zetas.resize(nz);
+      bzk.assign((size_t)RB * nz, -1);
+      long long npan = 0, nw = 0;
+      for (int zi = 0; zi < nz; ++zi) {
+        BsZeta& Z = zetas[zi];
+        int M = 0;
+        for (int sp = 0; sp < 4; ++sp) {
+          const int ap = fa(sub(zq[zi], kSiteQ[sp]));
+          Z.row0[sp] = ap >= 0 ? M : -1;
+          if (ap >= 0) M += SA.n[ap];
+        }
+        Z.M = M;
+        for (int s2p = 0; s2p < 4; ++s2p) {
+          Z.pbase[s2p] = -1;
+          Z.K[s2p] = -1;
+          const int bep = fb(add(zq[zi], kSiteQ[s2p]));
+          if (bep < 0 || M == 0) continue;
+          const int P = (int)panels.size();
+          const size_t it0 = items.size();
+          int K = 0;
+          for (int s2_ = 0; s2_ < 4; ++s2_)
+            for (int B = 0; B < RB; ++B) {
+              if (!(rel[(size_t)B * 4 + s2_] >> s2p & 1)) continue;
+              const int be = fb(add(sub(zq[zi], dB[B]), kSiteQ[s2_]));
+              if (be < 0) continue;
+              items.push_back(BsWrItem{P, B * 4 + s2_, K, be});
+              int& kci = bzk[(size_t)B * nz + zi];
+              if (kci < 0) {
+                kci = (int)(kctab.size() / 16);
+                kctab.resize(kctab.size() + 16, -1);
+              }
+              kctab[(size_t)kci * 16 + s2_ * 4 + s2p] = K;
+              K += SB.n[be];
+            }
+          if (K == 0) continue;
+          const int N = SB.n[bep];
+          Z.pbase[s2p] = npan;
+          Z.K[s2p] = K;
+          const int row0 = (int)wrowdst.size();
+          for (int sp = 0; sp < 4; ++sp) {
+            const int ap = fa(sub(zq[zi], kSiteQ[sp]));
+            if (ap < 0) continue;
+            for (int i = 0; i < SA.n[ap]; ++i)
+              wrowdst.push_back((long long)(SA.off[ap] + i) * 16 * rrp + (long long)(sp * 4 + s2p) * rrp + SB.off[bep]);
+          }
+          panels.push_back(BsPanel{npan, nw, M, K, N, zi, s2p, bep, 0, 0});
+          for (size_t i = it0; i < items.size(); ++i) {
+            const int B = items[i].bs2 >> 2, s2_ = items[i].bs2 & 3, ti = (B * 4 + s2p) * 4 + s2_;
+            p.build_wr += (double)SB.n[items[i].be] * N * (t2ptr[ti + 1] - t2ptr[ti]);
+          }
+          // split-K tiles of the panel product (the stage-4 kernels), rows scattered into y
+          for (int m0 = 0; m0 < M; m0 += TILE)
+            for (int n0 = 0; n0 < N; n0 += TILE) {
+              BsRedTile r{M, N, m0, n0, wslots, 0, row0, 0};
+              for (int k0 = 0; k0 < K; k0 += KSPLIT) {
+                wtiles4.push_back(BsS4Tile{npan, nw, M, N, K, m0, n0, k0, std::min(K, k0 + KSPLIT), wslots});
+                ++wslots;
+                ++r.nsplit;
+              }
+              wel_red += (double)(r.nsplit + 1) * std::min(TILE, M - m0) * std::min(TILE, N - n0);
+              wred.push_back(r);
+            }
+          wflops += 2.0 * M * (double)K * N;
+          wbytes += (double)M * K + (double)K * N + (double)M * N;
+          npan += (long long)M * K;
+          nw += (long long)K * N;
+        }
+      }
+      p.n2 = npan;
+      p.nwr = nw;
+      p.npanels = (int)panels.size();
+      p.nwr_items = (int)items.size();
+    }
+    struct LwKey {
+      Q2 g;
+      int mask, cmask;
+      bool operator<(const LwKey& o) const {
+        return g != o.g ? g < o.g : (mask != o.mask ? mask < o.mask : cmask < o.cmask);
+      }
+    };
+    std::map<LwKey, std::vector<BsLwBlock>> byg;
+    for (int B = 0; B < RB; ++B)
+      for (int sp = 0; sp < 4; ++sp)
+        for (int ap = 0; ap < nal; ++ap) {
+          const Q2 gam = sub(add(SA.q[ap], kSiteQ[sp]), dB[B]);
+          // columns: the s2 whose right sector exists (and, with panels, that a panel uses)
+          int cmask = 0, zi = -1, kci = -1;
+          if (p.wr) {
+            zi = zid.at(add(SA.q[ap], kSiteQ[sp]));
+            kci = bzk[(size_t)B * zq.size() + zi];
+            if (kci < 0) continue;
+            for (int i = 0; i < 16; ++i)
+              if (kctab[(size_t)kci * 16 + i] >= 0) cmask |= 1 << (i / 4);
+          } else {
+            for (int s2_ = 0; s2_ < 4; ++s2_)
+              if (fb(add(gam, kSiteQ[s2_])) >= 0) cmask |= 1 << s2_;
+          }
+          if (cmask == 0) continue;
+          int mask = 0;
+          for (int s1_ = 0; s1_ < 4; ++s1_) {
+            const size_t ti = (size_t)(B * 4 + sp) * 4 + s1_;
+            if (fa(sub(gam, kSiteQ[s1_])) >= 0 && tptr[ti + 1] > tptr[ti]) mask |= 1 << s1_;
+          }
+          // no operator entry: these outputs stay zero
+          if (mask == 0) continue;
+          byg[LwKey{gam, mask, cmask}].push_back(BsLwBlock{0, 0, SA.n[ap], B * 4 + sp, ap, zi, kci, 0});
+        }
+    std::vector<BsLwGroup> lgroups;
+    std::vector<BsLwBlock> blocks;
+    std::vector<BsLwTile> ltiles;
+    std::vector<int> krow;
+    std::vector<int2> lcol;
+    long long a0 = 0;
+    p.flops_lw = p.bytes_lw = p.build_lw = 0.0;
+    for (auto& kv : byg) {
+      const Q2 gam = kv.first.g;
+      BsLwGroup G{};
+      G.a0 = a0;
+      G.k0 = (int)krow.size();
+      G.n0 = (int)lcol.size();
+      G.np = 0;
+      for (int s1_ = 0; s1_ < 4; ++s1_) {
+        if (!(kv.first.mask >> s1_ & 1)) continue;
+        const int al = fa(sub(gam, kSiteQ[s1_]));
+        G.ps[G.np] = s1_;
+        G.pk[G.np] = G.K;
+        G.pn[G.np] = SA.n[al];
+        G.pa[G.np] = al;
+        ++G.np;
+        for (int a = 0; a < SA.n[al]; ++a) krow.push_back((SA.off[al] + a) * 16 * rrp + s1_ * 4 * rrp);
+        G.K += SA.n[al];
+      }
+      G.K4 = (G.K + 3) / 4 * 4;
+      for (int s2_ = 0; s2_ < 4; ++s2_) {
+        const int be = kv.first.cmask >> s2_ & 1 ? fb(add(gam, kSiteQ[s2_])) : -1;
+        G.be[s2_] = be;
+        if (be < 0) continue;
+        for (int j = 0; j < SB.n[be]; ++j) lcol.push_back(make_int2(s2_ * rrp + SB.off[be] + j, (s2_ << 20) | j));
+        G.N += SB.n[be];
+      }
+      G.rb0 = (int)blocks.size();
+      const int g = (int)lgroups.size();
+      for (BsLwBlock& b : kv.second) {
+        b.g = g;
+        b.r0 = G.M;
+        G.M += b.n;
+        // forming LW: one multiply-add per element of the block and operator entry
+        for (int q = 0; q < G.np; ++q) {
+          const size_t ti = (size_t)b.bs * 4 + G.ps[q];
+          p.build_lw += (double)b.n * G.pn[q] * (tptr[ti + 1] - tptr[ti]);
+        }
+        blocks.push_back(b);
+      }
+      G.nrb = (int)blocks.size() - G.rb0;
+      for (int m0 = 0, i = G.rb0; m0 < G.M; m0 += LW_ROWS) {
+        while (blocks[i].r0 + blocks[i].n <= m0) ++i;
+        int j = i;
+        while (j < G.rb0 + G.nrb && blocks[j].r0 < m0 + LW_ROWS) ++j;
+        ltiles.push_back(BsLwTile{g, m0, i, j - i});
+      }
+      a0 += (long long)G.M * G.K4;
+      p.flops_lw += 2.0 * G.M * (double)G.K * G.N;
+      p.bytes_lw += (double)G.M * G.K + (double)G.K * G.N + (double)G.M * G.N;
+      lgroups.push_back(G);
+    }
+    p.nlw = a0;
+    p.nlw_groups = (int)lgroups.size();
+    p.nlw_blocks = (int)blocks.size();
+    p.nlw_tiles = (int)ltiles.size();
+    if (krow.empty()) krow.push_back(0);
+    if (lcol.empty()) lcol.push_back(make_int2(0, 0));
+    if (tA.empty()) { tA.push_back(0); tv.push_back(0.0); }
+    hipStream_t s0 = E.stream;
+    up(p.lw_groups, lgroups, s0);
+    up(p.lw_blocks, blocks, s0);
+    up(p.lw_tiles, ltiles, s0);
+    up(p.lw_krow, krow, s0);
+    up(p.lw_col, lcol, s0);
+    up(p.lw_tptr, tptr, s0);
+    up(p.lw_tA, tA, s0);
+    up(p.lw_tv, tv, s0);
+    up(p.rowbase2, rowbase2, s0);
+    up(p.aoff, SA.off, s0);
+    if (p.wr) {
+      if (zetas.empty()) zetas.push_back(BsZeta{});
+      if (kctab.empty()) kctab.assign(16, -1);
+      if (panels.empty()) panels.push_back(BsPanel{});
+      if (items.empty()) items.push_back(BsWrItem{});
+      if (t2C.empty()) { t2C.push_back(0); t2v.push_back(0.0); }
+      up(p.lw_zeta, zetas, s0);
+      up(p.lw_kc, kctab, s0);
+      up(p.wr_panels, panels, s0);
+      up(p.wr_items, items, s0);
+      up(p.wr_tptr, t2ptr, s0);
+      up(p.wr_tC, t2C, s0);
+      up(p.wr_tv, t2v, s0);
+    }
+  }
+
   // stage 1 tables
   std::vector<BsAlpha> alpha(nal);
   std::vector<long long> rsrc;
@@ -843,7 +1402,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   const long long rl2 = (long long)rlp * rlp;
   p.flops1 = 0.0;
   p.bytes1 = 0.0;
-  for (int a = 0; a < nal; ++a) {
+  for (int a = 0; a < (p.lw ? 0 : nal); ++a) {
     BsAlpha& A_ = alpha[a];
     A_.row0 = (int)rinfo.size();
     A_.col0 = (int)cinfo.size();
@@ -897,7 +1456,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   std::vector<BsPair> pairs;
   std::vector<long long> rbase(nbe, 0);
   long long nrs = 0;
-  for (int bp = 0; bp < nbe; ++bp) {
+  for (int bp = 0; bp < (p.wr ? 0 : nbe); ++bp) {
     rbase[bp] = nrs;
     for (int be = 0; be < nbe; ++be) {
       auto it = dcls.find(sub(SB.q[bp], SB.q[be]));
@@ -920,7 +1479,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   p.flops4 = 0.0;
   p.bytes4 = 0.0;
   p.el_red = 0.0;
-  for (int bp = 0; bp < nbe; ++bp) {
+  for (int bp = 0; bp < (p.wr ? 0 : nbe); ++bp) {
     const int row0 = (int)rowdst.size();
     int M = 0;
     for (int a = 0; a < nal; ++a)
@@ -951,6 +1510,15 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
     n3 += (long long)M * K;
   }
   p.n3 = n3;
+  if (p.wr) {
+    tiles4.swap(wtiles4);
+    red.swap(wred);
+    rowdst.swap(wrowdst);
+    slots = wslots;
+    p.flops4 = wflops;
+    p.bytes4 = wbytes;
+    p.el_red = wel_red;
+  }
   p.ntiles4 = (int)tiles4.size();
   p.nred = (int)red.size();
   p.nslots = slots;
@@ -983,10 +1551,26 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
       gcls[g][z] = it == dcls.end() ? -1 : it->second;
     }
   std::vector<std::array<int, 4>> nocls(ng, std::array<int, 4>{-1, -1, -1, -1});
-  build_mix(E, p.m1, 1, w1, dB, RB, idx1, grp1, gid, gq, cols, ldg, off1, nr1, ns1, spec0, nspec, rowbase2, crank,
-            nocls);
-  build_mix(E, p.m2, 2, w2, dC, RCx, idx2, grp2, gid, gq, cols, ldg, off2, nr2, ns2, spec0, nspec, rowbase2, crank,
-            gcls);
+  if (!p.lw) {
+    build_mix(E, p.m1, 1, w1, dB, RB, idx1, grp1, gid, gq, cols, ldg, off1, nr1, ns1, spec0, nspec, rowbase2, crank,
+              nocls);
+  } else {
+    BsMix& m = p.m1;
+    m.ntiles = m.nhtiles = m.nstage = m.noloc = m.nstaged = 0;
+    m.flops = m.nin = m.nout = m.fl_light = m.el_light = m.fl_heavy = m.el_heavy = m.el_scatter = 0.0;
+    m.ntmp = 0;
+    m.heavy.clear();
+  }
+  if (!p.wr) {
+    build_mix(E, p.m2, 2, w2, dC, RCx, idx2, grp2, gid, gq, cols, ldg, off2, nr2, ns2, spec0, nspec, rowbase2, crank,
+              gcls);
+  } else {
+    BsMix& m = p.m2;
+    m.ntiles = m.nhtiles = m.nstage = m.noloc = m.nstaged = 0;
+    m.flops = m.nin = m.nout = m.fl_light = m.el_light = m.fl_heavy = m.el_heavy = m.el_scatter = 0.0;
+    m.ntmp = 0;
+    m.heavy.clear();
+  }
   up(p.m1.spec, spec, s);
   up(p.m2.spec, spec, s);
   if (E.verbose_level >= 2) {
@@ -997,6 +1581,9 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
       std::fprintf(stderr, "; heavy GEMMs of mix %d (H x cols x Nin):", mi + 1);
       for (const BsHeavy& h : m.heavy) std::fprintf(stderr, " %dx%dx%d", h.H, h.cols, h.Nin);
     }
+    if (p.lw)
+      std::fprintf(stderr, "; left operator: %d groups, %d tiles, %lld elements, %.3g multiply-adds to form",
+                   p.nlw_groups, p.nlw_tiles, p.nlw, p.build_lw);
     std::fprintf(stderr, "\n");
   }
   p.have64 = p.have32 = false;
@@ -1097,15 +1684,37 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   const size_t ny = (size_t)p.rlp * 16 * p.rrp;
   if (!p.err.p) p.err.resize_zero(sizeof(int), s);
   int* err = p.err.as<int>();
-  E.bs_t1.ensure(sizeof(T) * std::max<long long>(p.n1, 1));
+  if (!p.lw) E.bs_t1.ensure(sizeof(T) * std::max<long long>(p.n1, 1));
   E.bs_t2.ensure(sizeof(T) * std::max<long long>(p.n2, 1));
   E.bs_t3.ensure(sizeof(T) * std::max<long long>(p.n3, 1));
   E.bs_part.ensure(sizeof(T) * (size_t)std::max(p.nslots, 1) * TILE * TILE);
   if (E.bs_zero_serial != p.serial || E.bs_zero_prec != prec) {
-    // T1 entries whose left sector alpha' - d_A does not exist are never written
-    fill(E.bs_t1.p, sizeof(T) * p.n1, s);
+    // entries that are never written: T1's where the left sector alpha' - d_A does not
+    // exist; with the left operator T2's of the rows (B, s1') without operator entries
+    if (p.lw) fill(E.bs_t2.p, sizeof(T) * p.n2, s);
+    else fill(E.bs_t1.p, sizeof(T) * p.n1, s);
     E.bs_zero_serial = p.serial;
     E.bs_zero_prec = prec;
+  }
+  const T* lwop = nullptr;
+  if (p.lw) {
+    if (!p.have_lw64) throw std::logic_error("block-sparse product: left operator not formed");
+    if (sizeof(T) == 8) {
+      lwop = reinterpret_cast<const T*>(p.lw64.p);
+    } else {
+      const int want = bf16_t3 ? 2 : 1;
+      if (p.lw32_state != want) {
+        p.lw32.ensure(sizeof(float) * (size_t)std::max<long long>(p.nlw, 1));
+        if (p.nlw > 0) {
+          const int nb = (int)std::min<long long>((p.nlw + 255) / 256, 8192);
+          hipLaunchKernelGGL(lw_round_kernel, dim3(nb), dim3(256), 0, s, p.lw64.as<double>(), p.lw32.as<float>(),
+                             p.nlw, want == 2 ? 1 : 0);
+          BSCHECK(hipGetLastError());
+        }
+        p.lw32_state = want;
+      }
+      lwop = reinterpret_cast<const T*>(p.lw32.p);
+    }
   }
   DevMem& rs = prec == 0 ? p.rstack64 : p.rstack32;
   bool& have = prec == 0 ? p.have64 : p.have32;
@@ -1138,21 +1747,64 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
     E.bs_gg_ptr[1] = E.bs_t2.p;
     E.bs_gg_ptr[2] = E.bs_tmp.p;
   }
-  E.kt_begin();
-  if (p.ntiles1 > 0) {
-    hipLaunchKernelGGL((stage1_mfma_kernel<T>), dim3(p.ntiles1), dim3(256), 0, s, p.tiles1.as<int4>(),
-                       p.alpha.as<BsAlpha>(), p.rsrc.as<long long>(), p.rinfo.as<int4>(), p.cinfo.as<int4>(),
-                       p.rowpart1.as<long long>(), p.specoff.as<long long>(), p.nbeta.as<int>(), p.nbe, L,
-                       (long long)p.RAx * p.rlp * p.rlp, x, (long long)ny, (long long)16 * p.rrp, E.bs_t1.as<T>(),
-                       p.n1, err);
-    BSCHECK(hipGetLastError());
+  const T* wrop = nullptr;
+  if (p.wr) {
+    if (sizeof(T) == 8) {
+      wrop = reinterpret_cast<const T*>(p.wr64.p);
+    } else {
+      const int want = bf16_t3 ? 2 : 1;
+      if (p.wr32_state != want) {
+        p.wr32.ensure(sizeof(float) * (size_t)std::max<long long>(p.nwr, 1));
+        if (p.nwr > 0) {
+          const int nb = (int)std::min<long long>((p.nwr + 255) / 256, 8192);
+          hipLaunchKernelGGL(lw_round_kernel, dim3(nb), dim3(256), 0, s, p.wr64.as<double>(), p.wr32.as<float>(),
+                             p.nwr, want == 2 ? 1 : 0);
+          BSCHECK(hipGetLastError());
+        }
+        p.wr32_state = want;
+      }
+      wrop = reinterpret_cast<const T*>(p.wr32.p);
+    }
   }
-  if (p.ntiles1 > 0) E.kt_mark(0);
-  run_mix<T, 1>(E, p, p.m1, E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2, err, false, gg1, E.bs_gg1);
-  run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3, gg2, E.bs_gg2);
+  E.kt_begin();
+  if (p.lw) {
+    if (p.nlw_tiles > 0) {
+      if (p.wr)
+        hipLaunchKernelGGL((lw_gemm_kernel<T, 2>), dim3(p.nlw_tiles), dim3(256), 0, s, p.lw_tiles.as<BsLwTile>(),
+                           p.lw_groups.as<BsLwGroup>(), p.lw_blocks.as<BsLwBlock>(),
+                           p.lw_krow.as<int>(), p.lw_col.as<int2>(), lwop, p.nlw, x, (long long)ny, (const long long*)nullptr,
+                           (const long long*)nullptr, p.nbeta.as<int>(), p.nbe, p.lw_zeta.as<BsZeta>(),
+                           p.lw_kc.as<int>(), bf16_t3 ? 1 : 0, E.bs_t2.as<T>(), p.n2, err);
+      else
+        hipLaunchKernelGGL((lw_gemm_kernel<T, 1>), dim3(p.nlw_tiles), dim3(256), 0, s, p.lw_tiles.as<BsLwTile>(),
+                           p.lw_groups.as<BsLwGroup>(), p.lw_blocks.as<BsLwBlock>(),
+                           p.lw_krow.as<int>(), p.lw_col.as<int2>(), lwop, p.nlw, x, (long long)ny, p.rowbase2.as<long long>(),
+                           p.specoff.as<long long>(), p.nbeta.as<int>(), p.nbe, (const BsZeta*)nullptr,
+                           (const int*)nullptr, 0, E.bs_t2.as<T>(), p.n2, err);
+      BSCHECK(hipGetLastError());
+      E.kt_mark(0);
+    }
+  } else {
+    if (p.ntiles1 > 0) {
+      hipLaunchKernelGGL((stage1_mfma_kernel<T>), dim3(p.ntiles1), dim3(256), 0, s, p.tiles1.as<int4>(),
+                         p.alpha.as<BsAlpha>(), p.rsrc.as<long long>(), p.rinfo.as<int4>(), p.cinfo.as<int4>(),
+                         p.rowpart1.as<long long>(), p.specoff.as<long long>(), p.nbeta.as<int>(), p.nbe, L,
+                         (long long)p.RAx * p.rlp * p.rlp, x, (long long)ny, (long long)16 * p.rrp, E.bs_t1.as<T>(),
+                         p.n1, err);
+      BSCHECK(hipGetLastError());
+    }
+    if (p.ntiles1 > 0) E.kt_mark(0);
+    run_mix<T, 1>(E, p, p.m1, E.bs_t1.as<T>(), p.n1, E.bs_t2.as<T>(), p.n2, err, false, gg1, E.bs_gg1);
+  }
+  if (!p.wr) run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3, gg2, E.bs_gg2);
   if (p.ntiles4 > 0) {
-    hipLaunchKernelGGL((stage4_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
-                       E.bs_t3.as<T>(), p.n3, rs.as<T>(), p.nrs, E.bs_part.as<T>(), err);
+    // panels x WR (right operator), or stage-4 panels x stacked R
+    if (p.wr)
+      hipLaunchKernelGGL((stage4_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
+                         E.bs_t2.as<T>(), p.n2, wrop, p.nwr, E.bs_part.as<T>(), err);
+    else
+      hipLaunchKernelGGL((stage4_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
+                         E.bs_t3.as<T>(), p.n3, rs.as<T>(), p.nrs, E.bs_part.as<T>(), err);
     BSCHECK(hipGetLastError());
     E.kt_mark(7);
     hipLaunchKernelGGL((reduce4_kernel<T>), dim3(p.nred), dim3(256), 0, s, p.red.as<BsRedTile>(),
@@ -1162,9 +1814,10 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   }
   if (check) bs_check(E, p);
   const double el = (double)sizeof(T);
-  const double fl[Engine::KT_SLOTS] = {p.flops1, p.m1.fl_light, p.m1.fl_heavy, 0.0, p.m2.fl_light, p.m2.fl_heavy,
-                                       0.0, p.flops4, 0.0};
-  const double by[Engine::KT_SLOTS] = {el * p.bytes1, el * p.m1.el_light, el * p.m1.el_heavy, el * p.m1.el_scatter,
+  const double fl[Engine::KT_SLOTS] = {p.lw ? p.flops_lw : p.flops1, p.m1.fl_light, p.m1.fl_heavy, 0.0,
+                                       p.m2.fl_light, p.m2.fl_heavy, 0.0, p.flops4, 0.0};
+  const double by[Engine::KT_SLOTS] = {el * (p.lw ? p.bytes_lw : p.bytes1), el * p.m1.el_light, el * p.m1.el_heavy,
+                                       el * p.m1.el_scatter,
                                        el * p.m2.el_light, el * p.m2.el_heavy, el * p.m2.el_scatter, el * p.bytes4,
                                        el * p.el_red};
   E.kt_end(fl, by);
@@ -1204,6 +1857,34 @@ void bs_splitk_run(Engine& E, int ntiles, const BsS4Tile* tiles, int nred, const
   hipLaunchKernelGGL((reduce4_kernel<double>), dim3(nred), dim3(256), 0, s, red, part, rowdst, y, ny, err);
   BSCHECK(hipGetLastError());
   if (slot_red >= 0) E.kt_mark(slot_red);
+}
+
+void bs_lw_build(Engine& E, BsPlan& p, const double* L, long long nL, const double* R, const double* Rt) {
+  if (!p.ok || !p.lw) throw std::logic_error("bs_lw_build: plan without a left operator");
+  if (p.wr && (!R || (p.RCx > p.RC && !Rt))) throw std::logic_error("bs_lw_build: missing right environment");
+  hipStream_t s = E.stream;
+  if (!p.err.p) p.err.resize_zero(sizeof(int), s);
+  p.lw64.ensure(sizeof(double) * (size_t)std::max<long long>(p.nlw, 1));
+  if (p.nlw_blocks > 0) {
+    hipLaunchKernelGGL(lw_build_kernel, dim3(p.nlw_blocks), dim3(256), 0, s, p.lw_blocks.as<BsLwBlock>(),
+                       p.lw_groups.as<BsLwGroup>(), p.lw_tptr.as<int>(), p.lw_tA.as<int>(), p.lw_tv.as<double>(),
+                       p.aoff.as<int>(), L, nL, p.rlp, p.lw64.as<double>(), p.nlw, p.err.as<int>());
+    BSCHECK(hipGetLastError());
+  }
+  if (p.wr) {
+    p.wr64.ensure(sizeof(double) * (size_t)std::max<long long>(p.nwr, 1));
+    if (p.nwr_items > 0) {
+      const long long rr2 = (long long)p.rrp * p.rrp;
+      hipLaunchKernelGGL(wr_build_kernel, dim3(p.nwr_items), dim3(256), 0, s, p.wr_items.as<BsWrItem>(),
+                         p.wr_panels.as<BsPanel>(), p.wr_tptr.as<int>(), p.wr_tC.as<int>(), p.wr_tv.as<double>(),
+                         p.boff.as<int>(), p.nbeta.as<int>(), R, (long long)p.RC * rr2, Rt,
+                         (long long)(p.RCx - p.RC) * rr2, p.RC, p.rrp, p.wr64.as<double>(), p.nwr, p.err.as<int>());
+      BSCHECK(hipGetLastError());
+    }
+  }
+  p.have_lw64 = true;
+  p.lw32_state = p.wr32_state = 0;
+  bs_check(E, p);
 }
 
 void bs_check(Engine& E, BsPlan& p) {

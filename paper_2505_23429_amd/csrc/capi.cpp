@@ -156,6 +156,7 @@ void tt_default_opts(tt_opts* o) {
   o->functional = 0;
   o->coarse_krylov = 0;
   o->graph_products = 0;
+  o->precontract = 2;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -170,7 +171,7 @@ int tt_create(const tt_opts* opts, void** out) {
       opts->functional > 1 ||
       (opts->functional == 1 && (opts->matvec_prec != TT_F64 || !opts->qn_skip || opts->coarse_k != 1)) ||
       opts->coarse_krylov < 0 || opts->coarse_krylov > 1 || (opts->coarse_krylov && opts->functional != 0) ||
-      opts->graph_products < 0 || opts->graph_products > 1)
+      opts->graph_products < 0 || opts->graph_products > 1 || opts->precontract < 0 || opts->precontract > 2)
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);

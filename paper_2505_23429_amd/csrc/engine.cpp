@@ -2317,6 +2317,8 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
   w.prec = prec;
   w.use_bs = E.opts.qn_skip != 0 && bs_build(E, w.bs, b, ql, qr, w.rlp, w.rrp, w.RAx, w.nP);
   w.use_tabs = E.opts.qn_skip != 0 && !w.use_bs;
+  if (w.use_bs && w.bs.lw)
+    bs_lw_build(E, w.bs, w.Lx.as<double>(), sl * w.RAx, w.R64, w.nP ? w.Rt.as<double>() : nullptr);
   if (prec == TT_BF16 && w.use_bs) {
     // block-sparse product in FP32 arithmetic on operands rounded to bfloat16
     w.L32.ensure(sizeof(float) * sl * w.RAx);
@@ -2868,6 +2870,7 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
           convert_f64_f32(w.Lx.as<double>(), w.L32.as<float>(), sl * w.RAx, E.stream);
           convert_f64_f32(w.R64, w.R32.as<float>(), sr * w.RC, E.stream);
           if (w.nP) convert_f64_f32(w.Rt.as<double>(), w.Rt32.as<float>(), sr * w.nP, E.stream);
+          w.bs.have32 = false;  // the stacked right environment follows the new operands
           inner = TT_F32;
         } else {
           inner = -1;

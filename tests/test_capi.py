@@ -47,7 +47,7 @@ def test_default_options_and_invalid_create():
     ("sub_workers", -1), ("sub_workers", 65), ("mix_stage", 3), ("mix_stage", -1), ("svd_lds", 2),
     ("worker_alloc_limit", -1), ("coarse_k", 0), ("coarse_k", 9), ("one_site", 2), ("one_site", -1),
     ("functional", 2), ("functional", -1), ("coarse_krylov", 2), ("coarse_krylov", -1),
-    ("graph_products", 2), ("graph_products", -1),
+    ("graph_products", 2), ("graph_products", -1), ("precontract", 3), ("precontract", -1),
 ])
 def test_create_rejects_each_invalid_option(field, value):
     """tt_create validates the options before it touches the device: every value outside

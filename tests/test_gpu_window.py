@@ -4,7 +4,10 @@ solves, eq. mat_vec) against the oracle's dense einsum definition.
 Operands carry the charge structure of a real iterate: environments
 E[K][bra][ket] are random where q(bra) - q(ket) equals the channel charge of K
 and zero elsewhere, x is random on its allowed blocks.  Windows with and
-without the coefficient block of the MPO are covered.  Tolerances relative to
+without the coefficient block of the MPO are covered, and the three forms of the
+product: both environments precontracted with their site tensors (default), only
+the left one, and none (L x, then both site tensors as sparse mixes).  Tolerances
+relative to
 max|y|: 1e-12 (FP64), 1e-5 (FP32), 2e-2 (bfloat16-rounded operands).
 """
 import numpy as np
@@ -90,6 +93,29 @@ def small_modes(small):
 def test_window_product_staging_modes(small_modes, b, prec, mode):
     ctxs, mpo, labels = small_modes
     _window_case(ctxs[mode], mpo, labels, b, prec)
+
+
+@pytest.fixture(scope="module")
+def small_forms(small):
+    """Contexts with the other two forms of the product: only the left operator
+    precontracted (1), and none (0: L x, both site tensors as sparse mixes)."""
+    from paper_2505_23429_amd.api import Context
+
+    _, mpo, labels = small
+    out = {}
+    for form in (0, 1):
+        c = Context(chi=48, precontract=form)
+        c.set_mpo(mpo)
+        out[form] = c
+    return out, mpo, labels
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("b", [1, 3, 4, 5])
+def test_window_product_other_forms(small_forms, b, prec, form):
+    ctxs, mpo, labels = small_forms
+    _window_case(ctxs[form], mpo, labels, b, prec)
 
 
 def _window_case(ctx, mpo, labels, b, prec):
