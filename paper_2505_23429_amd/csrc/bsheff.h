@@ -66,15 +66,22 @@ struct BsLwGroup {
   int be[4], ps[4], pk[4], pn[4], pa[4];
 };
 // rows [r0, r0 + n) of group g: output channel and bra state bs = B * 4 + s1', bra sector
-// ap; with the right operator, zi indexes the panels of the block's zeta and kci the chunk
-// table (entries [kci * 16 + s2 * 4 + s2']: the chunk's first panel column, -1 none)
+// ap; with the right operator, zi indexes the block's zeta and kci the chunk table
+// (entries [kci * 4 + s2]: the first column of the chunk (B, s2) in the zeta's store, -1 none)
 struct BsLwBlock { int g, r0, n, bs, ap, zi, kci, pad; };
-// panels of one zeta: M rows (s1', alpha', i') from row0[s1'] (-1: no alpha'); per s2' the
-// panel at pbase[s2'] with K[s2'] columns (-1: no panel)
-struct BsZeta { long long pbase[4]; int K[4]; int row0[4]; int M, pad; };
-// one panel: rows M, K (the chunks (B, s2) at columns [kc, kc + n_beta)), N = n_beta';
-// A at pbase is [M][K] row-major, WR at wbase is [K][N]
+// the chunks of one zeta: M rows (s1', alpha', i') from row0[s1'] (-1: no alpha'); every
+// chunk (B, s2) that a panel of this zeta uses is stored once, at zbase + kc M as the
+// row-major block [M][nb8] (nb8 = n_beta rounded up to 8, the padding zero), so that an
+// output block of the left-operator GEMM is contiguous and written once
+struct BsZeta { long long zbase; int M, row0[4], pad; };
+// one panel (zeta, s2'): rows M, K columns (its chunks, each padded to 8), N = n_beta'; its
+// A operand is read from the zeta's chunks through the column table, WR at wbase is [K][N]
 struct BsPanel { long long pbase, wbase; int M, K, N, zi, s2p, bep, pad0, pad1; };
+// per 8 panel columns: the offset of their chunk columns from zbase for row 0, and the
+// chunk's row stride
+struct BsK8 { int off, nb8; };
+// one workgroup of the panel GEMM (the stage-4 tile with the panel's column table at t8)
+struct BsPTile { long long abase, bbase, t8; int M, N, K, m0, n0, k0, k1, slot; };
 // one block of WR: panel P, chunk (B, s2) = bs2 / 4, bs2 % 4 at column kc, right sector be
 struct BsWrItem { int P, bs2, kc, be; };
 // one workgroup: rows [m0, m0 + 128) of group g, overlapped by row blocks [rb0, rb0 + nrb)
@@ -129,9 +136,11 @@ struct BsPlan {
   // precontracted right operator (wr, with lw): panels replace T2, mix 2, T3 and stage 4's panels
   bool wr = false;
   int nwr_items = 0, npanels = 0;
-  long long nwr = 0;                       // elements of WR (n2: elements of the panels)
+  long long nwr = 0;                       // elements of WR (n2: elements of the chunk stores)
   double build_wr = 0.0;                   // multiply-adds of forming WR
-  DevMem lw_zeta, lw_kc, wr_items, wr_panels, wr_tptr, wr_tC, wr_tv, wr64, wr32;
+  DevMem lw_zeta, lw_kc, wr_items, wr_panels, wr_tptr, wr_tC, wr_tv, wr64, wr32, wr_k8, wr_ptiles;
+  int nptiles = 0;
+  long long nk8 = 0;
   int wr32_state = 0;
   DevMem err;  // set by a kernel when an index would leave its buffer (the access is skipped)
 };

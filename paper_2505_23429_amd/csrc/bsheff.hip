@@ -292,8 +292,8 @@ __global__ __launch_bounds__(256) void wr_build_kernel(const BsWrItem* __restric
 // reads its A fragments (one LW row, four consecutive k per MFMA step) straight from
 // memory.  Results go from the accumulators to T2, where the columns of one s2 of a
 // row are contiguous and the rows of one row block follow each other.
-// MODE 1 writes T2 (rows (B, s2)); MODE 2 writes every panel (zeta, s2') that uses the
-// output (rounded to bfloat16 when rnd is set).
+// MODE 1 writes T2 (rows (B, s2)); MODE 2 writes the chunk stores of the panels (rounded
+// to bfloat16 when rnd is set).
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void lw_gemm_kernel(
     const BsLwTile* __restrict__ tiles, const BsLwGroup* __restrict__ groups, const BsLwBlock* __restrict__ blocks,
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const long long* __restrict__ rowbase2, const long long* __restrict__ specoff, const int* __restrict__ nbeta,
     int nbe, const BsZeta* __restrict__ zetas,
     const int* __restrict__ kctab, int rnd, T* __restrict__ out, long long nout, int* __restrict__ err) {
-  constexpr int ND = MODE == 2 ? 16 : 4;  // destinations per row: per s2 (and s2')
+  constexpr int ND = 4;  // destinations per row: one per s2
   constexpr int KS = sizeof(T) == 4 ? 32 : 16;  // K slice
   constexpr int NB = sizeof(T) == 4 ? 8 : 4;    // 16-column blocks per pass
   constexpr int NC = NB * 16;
@@ -315,10 +315,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int mrows = min(LW_ROWS, G.M - t.m0);
   if (MODE == 2 && tid < LW_ROWS) {
-    // panel offsets of row (B, s1', alpha', i') for each (s2, s2'): panel (zeta, s2') row
-    // (s1', alpha', i'), column of the chunk (B, s2); -1 where no panel uses it
+    // chunk-store offset of row (B, s1', alpha', i') for each s2: the chunk (B, s2) of the
+    // zeta alpha' + q(s1'), its row (s1', alpha', i'); -1 where no panel uses the chunk
 #pragma unroll
-    for (int i = 0; i < 16; ++i) rd[tid][i % ND] = -1;
+    for (int s2 = 0; s2 < 4; ++s2) rd[tid][s2] = -1;
     if (tid < mrows) {
       const int r = t.m0 + tid;
       int q = -1, ip = 0;
@@ -336,11 +336,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const BsLwBlock b = blocks[q];
         const BsZeta& Z = zetas[b.zi];
         const int row = Z.row0[b.bs & 3] + ip;
+        const int4 k4 = reinterpret_cast<const int4*>(kctab)[b.kci];
+        const int kcs[4] = {k4.x, k4.y, k4.z, k4.w};
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int kc = kctab[(long long)b.kci * 16 + i], z = i & 3, be = G.be[i >> 2];
-          if (kc >= 0 && be >= 0) rd[tid][i % ND] = Z.pbase[z] + (long long)row * Z.K[z] + kc;
-          else if (kc >= 0) err[0] = 12;
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int kc = kcs[s2], be = G.be[s2];
+          if (kc >= 0 && be >= 0) rd[tid][s2] = Z.zbase + (long long)kc * Z.M + (long long)row * ((nbeta[be] + 7) & ~7);
+          else if (be >= 0) err[0] = 12;
         }
       }
     }
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       }
     }
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) rd[tid][s2 % ND] = d4[s2];
+    for (int s2 = 0; s2 < 4; ++s2) rd[tid][s2] = d4[s2];
   }
   // this lane's A rows (row lane % 16 of each of the wave's row blocks)
   const T* arow[MB];
@@ -445,22 +447,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
           for (int v = 0; v < 4; ++v) {
             const int row = wv * (16 * MB) + m * 16 + (sizeof(T) == 4 ? 4 * (lane >> 4) + v : 4 * v + (lane >> 4));
             if (row >= mrows || cc >= nc) continue;
-            if (MODE == 1) {
-              const long long d0 = rd[row][(ci.y >> 20) % ND];
-              const long long d = d0 + (ci.y & 0xfffff);
-              if (d0 < 0 || d >= nout) { err[0] = 15; continue; }
-              out[d] = acc[m][j][v];
-            } else {
-              const T val = rnd ? (T)bf16_round((float)acc[m][j][v]) : acc[m][j][v];
-#pragma unroll 1
-              for (int z = 0; z < 4; ++z) {
-                const long long d0 = rd[row][((ci.y >> 20) * 4 + z) % ND];
-                if (d0 < 0) continue;
-                const long long d = d0 + (ci.y & 0xfffff);
-                if (d >= nout) { err[0] = 15; continue; }
-                out[d] = val;
-              }
-            }
+            const long long d0 = rd[row][(ci.y >> 20) % ND];
+            const long long d = d0 + (ci.y & 0xfffff);
+            if (d0 < 0 || d >= nout) { err[0] = 15; continue; }
+            out[d] = MODE == 2 && rnd ? (T)bf16_round((float)acc[m][j][v]) : acc[m][j][v];
           }
         }
   }
@@ -728,13 +718,105 @@ __global__ __launch_bounds__(256) void stage4_mfma_kernel(const BsS4Tile* __rest
       buf ^= 1;
     }
   }
+  // only the tile's valid rows and columns (the reduction reads no others)
   T* P = part + (long long)t.slot * (TILE * TILE);
+  const int mvalid = min(TILE, t.M - t.m0);
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = sizeof(T) == 4 ? 4 * (lane >> 4) + v : 4 * v + (lane >> 4);
-      P[(wv * 16 + row) * TILE + j * 16 + (lane & 15)] = acc[j][v];
+      if (wv * 16 + row < mvalid && j * 16 + (lane & 15) < nvalid)
+        P[(wv * 16 + row) * TILE + j * 16 + (lane & 15)] = acc[j][v];
+    }
+}
+
+// Panel x right operator: the stage-4 tile whose A operand, the panel (zeta, s2'), is read
+// from the zeta's chunk store through the panel's column table (offset and row stride per
+// aligned block of 8 columns; a thread's RUNL columns lie in one such block).
+template <typename T>
+__global__ __launch_bounds__(256) void panel_mfma_kernel(const BsPTile* __restrict__ tiles, const BsK8* __restrict__ k8,
+                                                         long long nk8, const T* __restrict__ A,
+                                                          long long nA, const T* __restrict__ B, long long nB,
+                                                          T* __restrict__ part, int* __restrict__ err) {
+  const BsPTile t = tiles[blockIdx.x];
+  if (t.abase < 0 || t.abase >= nA || t.bbase < 0 || t.bbase + (long long)t.K * t.N > nB) {
+    if (threadIdx.x == 0) err[0] = 8;
+    return;
+  }
+  constexpr int KS = sizeof(T) == 4 ? 32 : 16;  // K slice (two LDS buffers stay under 64 KB)
+  constexpr int RUNL = KS / 4;                   // elements per thread per operand slice
+  __shared__ T As[2][KS][TILE + 4];
+  __shared__ T Bs[2][KS][TILE + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nvalid = min(TILE, t.N - t.n0);
+  const int nblk = (nvalid + 15) >> 4;
+  // global -> register runs: A (64 rows x KS: row tid/4, RUNL consecutive k), B (KS x 64: k tid*RUNL/64, RUNL columns)
+  const int ar = tid >> 2, ak = (tid & 3) * RUNL;
+  const int bk = tid / (TILE / RUNL), bn = (tid % (TILE / RUNL)) * RUNL;
+  T ra[RUNL], rb[RUNL];
+  auto fetch = [&](int k0) {
+    // this thread's RUNL columns lie in one aligned block of 8 of one chunk
+    const int ka = k0 + ak;
+    bool rowok = t.m0 + ar < t.M && ka < t.k1;
+    long long arow = 0;
+    if (rowok) {
+      const long long ti = t.t8 + (ka >> 3);
+      const BsK8 e = ti >= 0 && ti < nk8 ? k8[ti] : BsK8{-1, 0};
+      arow = t.abase + e.off + (long long)(t.m0 + ar) * e.nb8 + (ka & 7);
+      if (e.off < 0 || arow < 0 || arow + RUNL > nA) {
+        err[0] = 8;
+        rowok = false;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) ra[u] = (rowok && ka + u < t.k1) ? A[arow + u] : T(0);
+    const int kb = k0 + bk;
+    const long long brow = t.bbase + (long long)kb * t.N + t.n0;
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) rb[u] = (kb < t.k1 && bn + u < nvalid) ? B[brow + bn + u] : T(0);
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) As[buf][ak + u][ar] = ra[u];
+#pragma unroll
+    for (int u = 0; u < RUNL; ++u) Bs[buf][bk][bn + u] = rb[u];
+  };
+  T acc[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[j][v] = T(0);
+  int buf = 0;
+  fetch(t.k0);
+  stash(0);
+  __syncthreads();
+  for (int k0 = t.k0; k0 < t.k1; k0 += KS) {
+    const bool more = k0 + KS < t.k1;
+    if (more) fetch(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      const T a = As[buf][kk + (lane >> 4)][wv * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < nblk) s4_mfma<T>(a, Bs[buf][kk + (lane >> 4)][j * 16 + (lane & 15)], acc[j]);
+    }
+    if (more) {
+      stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  // only the tile's valid rows and columns (the reduction reads no others)
+  T* P = part + (long long)t.slot * (TILE * TILE);
+  const int mvalid = min(TILE, t.M - t.m0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = sizeof(T) == 4 ? 4 * (lane >> 4) + v : 4 * v + (lane >> 4);
+      if (wv * 16 + row < mvalid && j * 16 + (lane & 15) < nvalid)
+        P[(wv * 16 + row) * TILE + j * 16 + (lane & 15)] = acc[j][v];
     }
 }
 
@@ -1127,7 +1209,8 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   p.have_lw64 = false;
   p.lw32_state = p.wr32_state = 0;
   // panel GEMM tables (right operator)
-  std::vector<BsS4Tile> wtiles4;
+  std::vector<BsPTile> wptiles;
+  std::vector<BsK8> wk8;
   std::vector<BsRedTile> wred;
   std::vector<long long> wrowdst;
   int wslots = 0;
@@ -1199,6 +1282,8 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
       zetas.resize(nz);
       bzk.assign((size_t)RB * nz, -1);
       long long npan = 0, nw = 0;
+      std::vector<int> ckc;  // chunk-store column of each chunk of the current zeta
+      std::vector<int2> cch;  // its (B * 4 + s2, right sector)
       for (int zi = 0; zi < nz; ++zi) {
         BsZeta& Z = zetas[zi];
         int M = 0;
@@ -1208,32 +1293,50 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
           if (ap >= 0) M += SA.n[ap];
         }
         Z.M = M;
+        Z.zbase = npan;
+        if (M == 0) continue;
+        // the zeta's store: every chunk (B, s2) that reaches some s2' with a right sector
+        ckc.clear();
+        cch.clear();
+        int KU = 0;
+        for (int s2_ = 0; s2_ < 4; ++s2_)
+          for (int B = 0; B < RB; ++B) {
+            int reach = rel[(size_t)B * 4 + s2_];
+            for (int s2p = 0; s2p < 4; ++s2p)
+              if (fb(add(zq[zi], kSiteQ[s2p])) < 0) reach &= ~(1 << s2p);
+            if (reach == 0) continue;
+            const int be = fb(add(sub(zq[zi], dB[B]), kSiteQ[s2_]));
+            if (be < 0) continue;
+            int& kci = bzk[(size_t)B * nz + zi];
+            if (kci < 0) {
+              kci = (int)(kctab.size() / 4);
+              kctab.resize(kctab.size() + 4, -1);
+            }
+            kctab[(size_t)kci * 4 + s2_] = KU;
+            ckc.push_back(KU);
+            cch.push_back(make_int2(B * 4 + s2_, be));
+            KU += (SB.n[be] + 7) & ~7;
+          }
+        if ((long long)M * KU >= (1LL << 31))
+          throw std::runtime_error("block-sparse plan: chunk store larger than 2^31 elements");
         for (int s2p = 0; s2p < 4; ++s2p) {
-          Z.pbase[s2p] = -1;
-          Z.K[s2p] = -1;
           const int bep = fb(add(zq[zi], kSiteQ[s2p]));
-          if (bep < 0 || M == 0) continue;
+          if (bep < 0) continue;
           const int P = (int)panels.size();
           const size_t it0 = items.size();
-          int K = 0;
-          for (int s2_ = 0; s2_ < 4; ++s2_)
-            for (int B = 0; B < RB; ++B) {
-              if (!(rel[(size_t)B * 4 + s2_] >> s2p & 1)) continue;
-              const int be = fb(add(sub(zq[zi], dB[B]), kSiteQ[s2_]));
-              if (be < 0) continue;
-              items.push_back(BsWrItem{P, B * 4 + s2_, K, be});
-              int& kci = bzk[(size_t)B * nz + zi];
-              if (kci < 0) {
-                kci = (int)(kctab.size() / 16);
-                kctab.resize(kctab.size() + 16, -1);
-              }
-              kctab[(size_t)kci * 16 + s2_ * 4 + s2p] = K;
-              K += SB.n[be];
-            }
+          const long long t8 = (long long)wk8.size();
+          int K = 0, Kr = 0;  // panel columns with and without the padding of the chunks
+          for (size_t c = 0; c < ckc.size(); ++c) {
+            const int bs2 = cch[c].x, be = cch[c].y;
+            if (!(rel[(size_t)bs2] >> s2p & 1)) continue;
+            const int nb8 = (SB.n[be] + 7) & ~7;
+            items.push_back(BsWrItem{P, bs2, K, be});
+            for (int c8 = 0; c8 < nb8; c8 += 8) wk8.push_back(BsK8{ckc[c] * M + c8, nb8});
+            K += nb8;
+            Kr += SB.n[be];
+          }
           if (K == 0) continue;
           const int N = SB.n[bep];
-          Z.pbase[s2p] = npan;
-          Z.K[s2p] = K;
           const int row0 = (int)wrowdst.size();
           for (int sp = 0; sp < 4; ++sp) {
             const int ap = fa(sub(zq[zi], kSiteQ[sp]));
@@ -1251,23 +1354,24 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
             for (int n0 = 0; n0 < N; n0 += TILE) {
               BsRedTile r{M, N, m0, n0, wslots, 0, row0, 0};
               for (int k0 = 0; k0 < K; k0 += KSPLIT) {
-                wtiles4.push_back(BsS4Tile{npan, nw, M, N, K, m0, n0, k0, std::min(K, k0 + KSPLIT), wslots});
+                wptiles.push_back(BsPTile{npan, nw, t8, M, N, K, m0, n0, k0, std::min(K, k0 + KSPLIT), wslots});
                 ++wslots;
                 ++r.nsplit;
               }
               wel_red += (double)(r.nsplit + 1) * std::min(TILE, M - m0) * std::min(TILE, N - n0);
               wred.push_back(r);
             }
-          wflops += 2.0 * M * (double)K * N;
-          wbytes += (double)M * K + (double)K * N + (double)M * N;
-          npan += (long long)M * K;
+          wflops += 2.0 * M * (double)Kr * N;
+          wbytes += (double)M * Kr + (double)Kr * N + (double)M * N;
           nw += (long long)K * N;
         }
+        npan += (long long)M * KU;
       }
       p.n2 = npan;
       p.nwr = nw;
       p.npanels = (int)panels.size();
       p.nwr_items = (int)items.size();
+      p.nptiles = (int)wptiles.size();
     }
     struct LwKey {
       Q2 g;
@@ -1287,8 +1391,8 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
             zi = zid.at(add(SA.q[ap], kSiteQ[sp]));
             kci = bzk[(size_t)B * zq.size() + zi];
             if (kci < 0) continue;
-            for (int i = 0; i < 16; ++i)
-              if (kctab[(size_t)kci * 16 + i] >= 0) cmask |= 1 << (i / 4);
+            for (int s2_ = 0; s2_ < 4; ++s2_)
+              if (kctab[(size_t)kci * 4 + s2_] >= 0) cmask |= 1 << s2_;
           } else {
             for (int s2_ = 0; s2_ < 4; ++s2_)
               if (fb(add(gam, kSiteQ[s2_])) >= 0) cmask |= 1 << s2_;
@@ -1381,7 +1485,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
     up(p.aoff, SA.off, s0);
     if (p.wr) {
       if (zetas.empty()) zetas.push_back(BsZeta{});
-      if (kctab.empty()) kctab.assign(16, -1);
+      if (kctab.empty()) kctab.assign(4, -1);
       if (panels.empty()) panels.push_back(BsPanel{});
       if (items.empty()) items.push_back(BsWrItem{});
       if (t2C.empty()) { t2C.push_back(0); t2v.push_back(0.0); }
@@ -1392,6 +1496,11 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
       up(p.wr_tptr, t2ptr, s0);
       up(p.wr_tC, t2C, s0);
       up(p.wr_tv, t2v, s0);
+      if (wk8.empty()) wk8.push_back(BsK8{0, 8});
+      if (wptiles.empty()) wptiles.push_back(BsPTile{});
+      p.nk8 = (long long)wk8.size();
+      up(p.wr_k8, wk8, s0);
+      up(p.wr_ptiles, wptiles, s0);
     }
   }
 
@@ -1511,7 +1620,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   }
   p.n3 = n3;
   if (p.wr) {
-    tiles4.swap(wtiles4);
+    tiles4.clear();
     red.swap(wred);
     rowdst.swap(wrowdst);
     slots = wslots;
@@ -1519,7 +1628,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
     p.bytes4 = wbytes;
     p.el_red = wel_red;
   }
-  p.ntiles4 = (int)tiles4.size();
+  p.ntiles4 = p.wr ? p.nptiles : (int)tiles4.size();
   p.nred = (int)red.size();
   p.nslots = slots;
 
@@ -1800,8 +1909,8 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   if (p.ntiles4 > 0) {
     // panels x WR (right operator), or stage-4 panels x stacked R
     if (p.wr)
-      hipLaunchKernelGGL((stage4_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
-                         E.bs_t2.as<T>(), p.n2, wrop, p.nwr, E.bs_part.as<T>(), err);
+      hipLaunchKernelGGL((panel_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.wr_ptiles.as<BsPTile>(),
+                         p.wr_k8.as<BsK8>(), p.nk8, E.bs_t2.as<T>(), p.n2, wrop, p.nwr, E.bs_part.as<T>(), err);
     else
       hipLaunchKernelGGL((stage4_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
                          E.bs_t3.as<T>(), p.n3, rs.as<T>(), p.nrs, E.bs_part.as<T>(), err);
@@ -1873,6 +1982,7 @@ void bs_lw_build(Engine& E, BsPlan& p, const double* L, long long nL, const doub
   }
   if (p.wr) {
     p.wr64.ensure(sizeof(double) * (size_t)std::max<long long>(p.nwr, 1));
+    fill(p.wr64.p, sizeof(double) * (size_t)p.nwr, s);  // rows of the chunk padding stay zero
     if (p.nwr_items > 0) {
       const long long rr2 = (long long)p.rrp * p.rrp;
       hipLaunchKernelGGL(wr_build_kernel, dim3(p.nwr_items), dim3(256), 0, s, p.wr_items.as<BsWrItem>(),
