@@ -49,7 +49,7 @@ KERNEL_SOURCES = ("paper_2505_23429_amd/csrc/bsheff.hip", "paper_2505_23429_amd/
 # timing slots of the product and the kernel symbols they stand for (FP32 products)
 KERNEL_SYMBOLS = {
     "gemm_LWx_panels": "lw_gemm_kernel<float, 2>",
-    "gemm_panels_WR": "stage4_mfma_kernel<float>",
+    "gemm_panels_WR": "panel_mfma_kernel<float>",
     "gemm_panels_WR_reduce": "reduce4_kernel<float>",
     "gemm_LWx": "lw_gemm_kernel<float, 1>",
     "gemm_Lx": "stage1_mfma_kernel<float>",

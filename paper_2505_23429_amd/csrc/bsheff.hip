@@ -828,8 +828,18 @@ __global__ __launch_bounds__(256) void reduce4_kernel(const BsRedTile* __restric
   for (int e = threadIdx.x; e < TILE * TILE; e += 256) {
     const int r = e / TILE, c = e % TILE;
     if (t.m0 + r >= t.M || t.n0 + c >= t.N) continue;
-    T s = T(0);
-    for (int q = 0; q < t.nsplit; ++q) s += part[(long long)(t.slot0 + q) * (TILE * TILE) + e];
+    // four partial sums in flight, combined in a fixed order (deterministic)
+    const T* pp = part + (long long)t.slot0 * (TILE * TILE) + e;
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int q = 0;
+    for (; q + 4 <= t.nsplit; q += 4) {
+      s0 += pp[(long long)q * (TILE * TILE)];
+      s1 += pp[(long long)(q + 1) * (TILE * TILE)];
+      s2 += pp[(long long)(q + 2) * (TILE * TILE)];
+      s3 += pp[(long long)(q + 3) * (TILE * TILE)];
+    }
+    for (; q < t.nsplit; ++q) s0 += pp[(long long)q * (TILE * TILE)];
+    const T s = (s0 + s1) + (s2 + s3);
     const long long d = rowdst[t.row0 + t.m0 + r] + t.n0 + c;
     if (d < 0 || d >= ny) { err[0] = 9; continue; }
     y[d] = s;
