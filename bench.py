@@ -191,13 +191,13 @@ def mfma_summary(pmc_csv, bench_json, command):
     extra = [("mix1_heavy_gemm", "gemm_grouped_kernel<float"), ("heavy_skinny", "skinny_mfma_kernel<float")]
     for slot, sym in list(KERNEL_SYMBOLS.items()) + extra:
         ds = [d for d, n in names.items() if sym in n and "MfmaUtil" in per[d]]
-        if not ds:
+        heavy = slot in ("mix1_heavy_gemm", "heavy_skinny")
+        if not ds or (not heavy and slot not in run["kernels"]):
             continue
         util = sum(per[d]["MfmaUtil"] for d in ds) / len(ds)
         mf = sum(per[d].get("MfmaFlops", 0.0) for d in ds) / len(ds)
         k = run["kernels"].get(slot, {})
         alg = k["tflops"] * 1e12 * k["ms"] * 1e-3 / k["launches"] if k.get("launches") else None
-        heavy = slot in ("mix1_heavy_gemm", "heavy_skinny")
         key = {"mix1_heavy_gemm": "heavy_gemm_grouped (more than 64 rows)",
                "heavy_skinny": "heavy_gemm_skinny (at most 64 rows)"}.get(slot, slot)
         out["kernels"][key] = {
