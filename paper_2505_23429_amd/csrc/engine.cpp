@@ -2319,7 +2319,13 @@ static void prepare_window(Engine& E, Window& w, const Env& Le, int b, const Env
   w.use_tabs = E.opts.qn_skip != 0 && !w.use_bs;
   if (w.use_bs && w.bs.lw)
     bs_lw_build(E, w.bs, w.Lx.as<double>(), sl * w.RAx, w.R64, w.nP ? w.Rt.as<double>() : nullptr);
-  if (prec == TT_BF16 && w.use_bs) {
+  if (w.use_bs && w.bs.wr) {
+    // with both operators precontracted the products read only LW and WR: the window's
+    // copies of the environments were needed to form them, and no low-precision copies are
+    // made (the diagonal preconditioner reads the environments themselves)
+    w.Lx.release();
+    w.Rt.release();
+  } else if (prec == TT_BF16 && w.use_bs) {
     // block-sparse product in FP32 arithmetic on operands rounded to bfloat16
     w.L32.ensure(sizeof(float) * sl * w.RAx);
     convert_f64_bf16f32(w.Lx.as<double>(), w.L32.as<float>(), sl * w.RAx, E.stream);
@@ -2865,7 +2871,9 @@ static Davidson local_eig(Engine& E, const Env& Le, int b, const Env& Re, DevMem
       // storage), and a dense bfloat16 window continues with FP64 products.
       int inner = prec;
       if (prec == TT_BF16) {
-        if (w.use_bs) {
+        if (w.use_bs && w.bs.wr) {
+          inner = TT_F32;  // the FP32 copies of LW and WR follow the product precision
+        } else if (w.use_bs) {
           const long long sl = (long long)w.rlp * w.rlp, sr = (long long)w.rrp * w.rrp;
           convert_f64_f32(w.Lx.as<double>(), w.L32.as<float>(), sl * w.RAx, E.stream);
           convert_f64_f32(w.R64, w.R32.as<float>(), sr * w.RC, E.stream);

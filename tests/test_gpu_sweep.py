@@ -96,6 +96,26 @@ def test_a2dmrg_sweep_matches_oracle(L, seed, chi, lengths):
     assert max(q.shape[0] for q in l2) <= chi
 
 
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_a2dmrg_sweep_product_forms_match_oracle(form, prec):
+    """The sweep with the other two forms of the two-site product (only the left
+    operator precontracted, or none) against the dense-vector oracle, in FP64 and with
+    FP32 products and the FP64 refinement."""
+    L, seed, chi, lengths = 8, 1008, 24, (2, 3, 3)
+    mpo, cores, labels, prob, oc = _setup(L, seed, chi, 3 + chi)
+    kw = dict(matvec_prec=prec, refine_fp64=True) if prec == "f32" else {}
+    ctx = _ctx(mpo, cores, labels, chi=chi, dav_tol=1e-10, precontract=form, **kw)
+    rep = ctx.sweep(list(lengths))
+    ro = T.a2dmrg_sweep(prob, oc, labels, chi, lengths)
+    tol = 1e-8 if prec == "f64" else 1e-6
+    assert np.abs(rep["E_local"] - np.array(ro.E_local)).max() < tol
+    assert abs(rep["lambda"] - ro.lam) < tol
+    assert abs(rep["E_after"] - ro.E_new) < tol
+    c2, _ = ctx.get_mps()
+    assert abs(prob.energy(c2) - ro.E_new) < tol
+
+
 def test_a2dmrg_sweep_global_memory_svd_matches_oracle():
     """The same sweep with every sector SVD block factored by the global-memory path of
     the Jacobi kernel (at these sizes the blocks would otherwise all fit in LDS)."""
