@@ -31,9 +31,9 @@
 // panel (zeta, s2'): zeta = alpha' + q(s1') is the charge of the bra's left half, the
 // panel's rows are (s1', alpha' = zeta - q(s1'), i') and its K runs over the chunks
 // (B, s2, b) whose operator entries reach s2' (beta = zeta - d_B + q(s2),
-// beta' = zeta + q(s2')); the left-operator GEMM writes each of its outputs into the
-// panels that use it, and y[alpha', s1', s2', beta'] = panel x WR.  T2 as rows (B, s2),
-// the second mix and T3 are then never formed either.
+// beta' = zeta + q(s2')); the left-operator GEMM writes each of its outputs once, into
+// the chunk store of its zeta that the panels read, and y[alpha', s1', s2', beta'] =
+// panel x WR.  T2 as rows (B, s2), the second mix and T3 are then never formed either.
 #pragma once
 #include "engine.h"
 
@@ -75,7 +75,8 @@ struct BsLwBlock { int g, r0, n, bs, ap, zi, kci, pad; };
 // output block of the left-operator GEMM is contiguous and written once
 struct BsZeta { long long zbase; int M, row0[4], pad; };
 // one panel (zeta, s2'): rows M, K columns (its chunks, each padded to 8), N = n_beta'; its
-// A operand is read from the zeta's chunks through the column table, WR at wbase is [K][N]
+// A operand is read from the zeta's chunks (from pbase, the zeta's store) through the
+// column table, WR at wbase is [K][N]
 struct BsPanel { long long pbase, wbase; int M, K, N, zi, s2p, bep, pad0, pad1; };
 // per 8 panel columns: the offset of their chunk columns from zbase for row 0, and the
 // chunk's row stride

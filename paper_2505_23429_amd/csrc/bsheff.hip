@@ -456,7 +456,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
 }
 
-__global__ void lw_round_kernel(const double* __restrict__ in, float* __restrict__ out, long long n, int bf16) {
+// the FP32 copy of a precontracted operator (rounded further to bfloat16 when bf16 is set)
+__global__ void operator_f32_kernel(const double* __restrict__ in, float* __restrict__ out, long long n, int bf16) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const float v = (float)in[i];
     out[i] = bf16 ? bf16_round(v) : v;
@@ -1216,6 +1217,9 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   // precontracted left operator: row blocks (B, s1', alpha') grouped by (gamma, mask)
   p.lw = E.opts.precontract >= 1 && (long long)rlp * 16 * rrp < (1LL << 31);
   p.wr = p.lw && E.opts.precontract == 2;
+  p.build_wr = 0.0;
+  p.nwr = p.nk8 = 0;
+  p.npanels = p.nwr_items = p.nptiles = 0;
   p.have_lw64 = false;
   p.lw32_state = p.wr32_state = 0;
   // panel GEMM tables (right operator)
@@ -1703,6 +1707,9 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
     if (p.lw)
       std::fprintf(stderr, "; left operator: %d groups, %d tiles, %lld elements, %.3g multiply-adds to form",
                    p.nlw_groups, p.nlw_tiles, p.nlw, p.build_lw);
+    if (p.wr)
+      std::fprintf(stderr, "; right operator: %d panels, %d chunks, %lld elements, %.3g multiply-adds to form",
+                   p.npanels, p.nwr_items, p.nwr, p.build_wr);
     std::fprintf(stderr, "\n");
   }
   p.have64 = p.have32 = false;
@@ -1826,7 +1833,7 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
         p.lw32.ensure(sizeof(float) * (size_t)std::max<long long>(p.nlw, 1));
         if (p.nlw > 0) {
           const int nb = (int)std::min<long long>((p.nlw + 255) / 256, 8192);
-          hipLaunchKernelGGL(lw_round_kernel, dim3(nb), dim3(256), 0, s, p.lw64.as<double>(), p.lw32.as<float>(),
+          hipLaunchKernelGGL(operator_f32_kernel, dim3(nb), dim3(256), 0, s, p.lw64.as<double>(), p.lw32.as<float>(),
                              p.nlw, want == 2 ? 1 : 0);
           BSCHECK(hipGetLastError());
         }
@@ -1876,7 +1883,7 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
         p.wr32.ensure(sizeof(float) * (size_t)std::max<long long>(p.nwr, 1));
         if (p.nwr > 0) {
           const int nb = (int)std::min<long long>((p.nwr + 255) / 256, 8192);
-          hipLaunchKernelGGL(lw_round_kernel, dim3(nb), dim3(256), 0, s, p.wr64.as<double>(), p.wr32.as<float>(),
+          hipLaunchKernelGGL(operator_f32_kernel, dim3(nb), dim3(256), 0, s, p.wr64.as<double>(), p.wr32.as<float>(),
                              p.nwr, want == 2 ? 1 : 0);
           BSCHECK(hipGetLastError());
         }
