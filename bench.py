@@ -48,10 +48,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_a2dmrg_L32_chi512.txt")
 KERNEL_SOURCES = ("paper_2505_23429_amd/csrc/bsheff.hip", "paper_2505_23429_amd/csrc/bsheff.h")
 # timing slots of the product and the kernel symbols they stand for (FP32 products)
 KERNEL_SYMBOLS = {
-    "gemm_LWx_panels": "lw_gemm_kernel<float, 2>",
-    "gemm_panels_WR": "panel_mfma_kernel<float>",
+    "gemm_LWx_panels": "lw_gemm_kernel<float, 2, float>",
+    "gemm_panels_WR": "panel_mfma_kernel<float, float>",
     "gemm_panels_WR_reduce": "reduce4_kernel<float>",
-    "gemm_LWx": "lw_gemm_kernel<float, 1>",
+    "gemm_LWx": "lw_gemm_kernel<float, 1, float>",
     "gemm_Lx": "stage1_mfma_kernel<float>",
     "mix1_gather": "mix_kernel<float, 1, false>",
     "mix1_heavy_scatter": "mix_kernel<float, 1, true>",

@@ -57,7 +57,7 @@ struct BsS4Tile { long long abase, bbase; int M, N, K, m0, n0, k0, k1, slot; };
 struct BsRedTile { int M, N, m0, n0, slot0, nsplit, row0, pad; };
 struct BsPair { int C, beta, koff, bprime; };
 // One GEMM of the precontracted left operator: rows [0, M) (row blocks [rb0, rb0 + nrb)),
-// LW rows at a0 with stride K4 (K rounded up to 4; the padding is zero), K entries of the
+// LW rows at a0 with stride K4 (K rounded up to 8; the padding is zero), K entries of the
 // x-row table from k0 (pieces: site state ps, first k pk, length pn, ket sector pa), N
 // columns of the column table from n0 ({x offset, s2 << 20 | j}), right sector be[s2].
 struct BsLwGroup {
@@ -140,6 +140,8 @@ struct BsPlan {
   long long nwr = 0;                       // elements of WR (n2: elements of the chunk stores)
   double build_wr = 0.0;                   // multiply-adds of forming WR
   DevMem lw_zeta, lw_kc, wr_items, wr_panels, wr_tptr, wr_tC, wr_tv, wr64, wr32, wr_k8, wr_ptiles;
+  DevMem lw16, wr16;                       // bfloat16 copies of LW and WR (bf16 products)
+  bool have_lw16 = false, have_wr16 = false;
   int nptiles = 0;
   long long nk8 = 0;
   int wr32_state = 0;

@@ -94,6 +94,45 @@ __device__ inline float bf16_round(float v) {
   return __uint_as_float(u & 0xffff0000u);
 }
 
+// element loads and stores of the two precontracted-operator GEMMs: FP64, FP32, or
+// bfloat16 storage (uint16_t bit patterns, FP32 arithmetic, round to nearest even)
+__device__ inline double ldv(const double* p, long long i) { return p[i]; }
+__device__ inline float ldv(const float* p, long long i) { return p[i]; }
+__device__ inline float ldv(const uint16_t* p, long long i) { return __uint_as_float((uint32_t)p[i] << 16); }
+__device__ inline void stv(double* p, long long i, double v) { p[i] = v; }
+__device__ inline void stv(float* p, long long i, float v) { p[i] = v; }
+__device__ inline void stv(uint16_t* p, long long i, float v) { p[i] = (uint16_t)(__float_as_uint(bf16_round(v)) >> 16); }
+// a run of N consecutive elements from a 16-byte aligned address, as vector loads
+template <int N>
+__device__ inline void ldrun(const float* p, float (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N / 4; ++i) {
+    const float4 q = reinterpret_cast<const float4*>(p)[i];
+    v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
+  }
+}
+template <int N>
+__device__ inline void ldrun(const double* p, double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const double2 q = reinterpret_cast<const double2*>(p)[i];
+    v[2 * i] = q.x; v[2 * i + 1] = q.y;
+  }
+}
+template <int N>
+__device__ inline void ldrun(const uint16_t* p, float (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N / 8; ++i) {
+    const uint4 q = reinterpret_cast<const uint4*>(p)[i];
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      v[8 * i + 2 * h] = __uint_as_float(w[h] << 16);
+      v[8 * i + 2 * h + 1] = __uint_as_float(w[h] & 0xffff0000u);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // stage 1: T1[(A, s1)][spec(a', s2, b) + i' n_b + j] = sum_a L_A[a'][a] x[a][s1][s2][b]
 // for each left sector alpha (rows (A, i') with a' in alpha + d_A, columns
@@ -292,16 +331,15 @@ __global__ __launch_bounds__(256) void wr_build_kernel(const BsWrItem* __restric
 // reads its A fragments (one LW row, four consecutive k per MFMA step) straight from
 // memory.  Results go from the accumulators to T2, where the columns of one s2 of a
 // row are contiguous and the rows of one row block follow each other.
-// MODE 1 writes T2 (rows (B, s2)); MODE 2 writes the chunk stores of the panels (rounded
-// to bfloat16 when rnd is set).
-template <typename T, int MODE>
+// MODE 1 writes T2 (rows (B, s2)); MODE 2 writes the chunk stores of the panels.  S is
+// the storage type of LW, x and the output (T, or bfloat16 with T = float).
+template <typename T, int MODE, typename S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void lw_gemm_kernel(
     const BsLwTile* __restrict__ tiles, const BsLwGroup* __restrict__ groups, const BsLwBlock* __restrict__ blocks,
-    const int* __restrict__ krow, const int2* __restrict__ col,
-    const T* __restrict__ lw, long long nlw, const T* __restrict__ x, long long nx,
-    const long long* __restrict__ rowbase2, const long long* __restrict__ specoff, const int* __restrict__ nbeta,
-    int nbe, const BsZeta* __restrict__ zetas,
-    const int* __restrict__ kctab, int rnd, T* __restrict__ out, long long nout, int* __restrict__ err) {
+    const int* __restrict__ krow, const int2* __restrict__ col, const S* __restrict__ lw, long long nlw,
+    const S* __restrict__ x, long long nx, const long long* __restrict__ rowbase2,
+    const long long* __restrict__ specoff, const int* __restrict__ nbeta, int nbe, const BsZeta* __restrict__ zetas,
+    const int* __restrict__ kctab, S* __restrict__ out, long long nout, int* __restrict__ err) {
   constexpr int ND = 4;  // destinations per row: one per s2
   constexpr int KS = sizeof(T) == 4 ? 32 : 16;  // K slice
   constexpr int NB = sizeof(T) == 4 ? 8 : 4;    // 16-column blocks per pass
@@ -381,7 +419,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     for (int s2 = 0; s2 < 4; ++s2) rd[tid][s2] = d4[s2];
   }
   // this lane's A rows (row lane % 16 of each of the wave's row blocks)
-  const T* arow[MB];
+  const S* arow[MB];
   bool aok[MB];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
@@ -410,30 +448,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         T v = T(0);
         if (c < nc && k < G.K) {
           const long long q = (long long)krow[G.k0 + k] + cl[c].x;
-          if (q >= 0 && q < nx) v = x[q]; else err[0] = 14;
+          if (q >= 0 && q < nx) v = (T)ldv(x, q); else err[0] = 14;
         }
         Bs[u][c] = v;
       }
+      // The slice's K order is permuted for the matrix cores: MFMA step s sums k = g KS/4 + s
+      // over the lane groups g = lane / 16, so a lane's A values for the KS/4 steps are one
+      // run of consecutive k (a vector load; rows are padded to a multiple of 8, so a run is
+      // either inside a row or past its end) and B reads the same permutation from LDS.
       T af[MB][KS / 4];
+      const int kl = k0 + (lane >> 4) * (KS / 4);
 #pragma unroll
-      for (int m = 0; m < MB; ++m)
+      for (int m = 0; m < MB; ++m) {
+        if (aok[m] && kl < G.K4) {
+          ldrun<KS / 4>(arow[m] + kl, af[m]);
+        } else {
 #pragma unroll
-        for (int s = 0; s < KS / 4; ++s) {
-          const int k = k0 + 4 * s + (lane >> 4);
-          af[m][s] = aok[m] && k < G.K4 ? arow[m][k] : T(0);
+          for (int s = 0; s < KS / 4; ++s) af[m][s] = T(0);
         }
+      }
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < KS / 4; ++s) {
-        if (k0 + 4 * s < G.K4) {
 #pragma unroll
-          for (int j = 0; j < NB; ++j)
-            if (j < nblk) {
-              const T bv = Bs[4 * s + (lane >> 4)][j * 16 + (lane & 15)];
+        for (int j = 0; j < NB; ++j)
+          if (j < nblk) {
+            const T bv = Bs[(lane >> 4) * (KS / 4) + s][j * 16 + (lane & 15)];
 #pragma unroll
-              for (int m = 0; m < MB; ++m) s1_mfma<T>(af[m][s], bv, acc[m][j]);
-            }
-        }
+            for (int m = 0; m < MB; ++m) s1_mfma<T>(af[m][s], bv, acc[m][j]);
+          }
       }
     }
 #pragma unroll
@@ -450,10 +493,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             const long long d0 = rd[row][(ci.y >> 20) % ND];
             const long long d = d0 + (ci.y & 0xfffff);
             if (d0 < 0 || d >= nout) { err[0] = 15; continue; }
-            out[d] = MODE == 2 && rnd ? (T)bf16_round((float)acc[m][j][v]) : acc[m][j][v];
+            stv(out, d, acc[m][j][v]);
           }
         }
   }
+}
+
+// the bfloat16 copy of a float array (operators from FP64, x from FP32)
+template <typename F>
+__global__ void to_bf16_kernel(const F* __restrict__ in, uint16_t* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    stv(out, i, (float)in[i]);
 }
 
 // the FP32 copy of a precontracted operator (rounded further to bfloat16 when bf16 is set)
@@ -735,11 +785,11 @@ __global__ __launch_bounds__(256) void stage4_mfma_kernel(const BsS4Tile* __rest
 // Panel x right operator: the stage-4 tile whose A operand, the panel (zeta, s2'), is read
 // from the zeta's chunk store through the panel's column table (offset and row stride per
 // aligned block of 8 columns; a thread's RUNL columns lie in one such block).
-template <typename T>
+template <typename T, typename S>
 __global__ __launch_bounds__(256) void panel_mfma_kernel(const BsPTile* __restrict__ tiles, const BsK8* __restrict__ k8,
-                                                         long long nk8, const T* __restrict__ A,
-                                                          long long nA, const T* __restrict__ B, long long nB,
-                                                          T* __restrict__ part, int* __restrict__ err) {
+                                                         long long nk8, const S* __restrict__ A, long long nA,
+                                                         const S* __restrict__ B, long long nB, T* __restrict__ part,
+                                                         int* __restrict__ err) {
   const BsPTile t = tiles[blockIdx.x];
   if (t.abase < 0 || t.abase >= nA || t.bbase < 0 || t.bbase + (long long)t.K * t.N > nB) {
     if (threadIdx.x == 0) err[0] = 8;
@@ -770,12 +820,18 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(const BsPTile* __restri
         rowok = false;
       }
     }
+    // the run is 16-byte aligned and lies inside [k0, k1) or past it (chunk columns and the
+    // K split are multiples of 8)
+    if (rowok) {
+      ldrun<RUNL>(A + arow, ra);
+    } else {
 #pragma unroll
-    for (int u = 0; u < RUNL; ++u) ra[u] = (rowok && ka + u < t.k1) ? A[arow + u] : T(0);
+      for (int u = 0; u < RUNL; ++u) ra[u] = T(0);
+    }
     const int kb = k0 + bk;
     const long long brow = t.bbase + (long long)kb * t.N + t.n0;
 #pragma unroll
-    for (int u = 0; u < RUNL; ++u) rb[u] = (kb < t.k1 && bn + u < nvalid) ? B[brow + bn + u] : T(0);
+    for (int u = 0; u < RUNL; ++u) rb[u] = (kb < t.k1 && bn + u < nvalid) ? (T)ldv(B, brow + bn + u) : T(0);
   };
   auto stash = [&](int buf) {
 #pragma unroll
@@ -1220,7 +1276,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
   p.build_wr = 0.0;
   p.nwr = p.nk8 = 0;
   p.npanels = p.nwr_items = p.nptiles = 0;
-  p.have_lw64 = false;
+  p.have_lw64 = p.have_lw16 = p.have_wr16 = false;
   p.lw32_state = p.wr32_state = 0;
   // panel GEMM tables (right operator)
   std::vector<BsPTile> wptiles;
@@ -1446,7 +1502,7 @@ bool bs_build(Engine& E, BsPlan& p, int b, const Labels& ql, const Labels& qr, i
         for (int a = 0; a < SA.n[al]; ++a) krow.push_back((SA.off[al] + a) * 16 * rrp + s1_ * 4 * rrp);
         G.K += SA.n[al];
       }
-      G.K4 = (G.K + 3) / 4 * 4;
+      G.K4 = (G.K + 7) / 8 * 8;  // row stride: K rounded up to 8 (runs of 8 consecutive k per lane)
       for (int s2_ = 0; s2_ < 4; ++s2_) {
         const int be = kv.first.cmask >> s2_ & 1 ? fb(add(gam, kSiteQ[s2_])) : -1;
         G.be[s2_] = be;
@@ -1806,24 +1862,46 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
               bool check) {
   if (!p.ok) throw std::runtime_error("block-sparse plan not built");
   hipStream_t s = E.stream;
-  const int prec = sizeof(T) == 8 ? 0 : 1;
+  // bfloat16 with both operators precontracted: LW, WR, x and the chunk stores are held in
+  // bfloat16 (FP32 arithmetic); otherwise every operand has the type T
+  const bool b16 = sizeof(T) == 4 && bf16_t3 && p.wr;
+  const int prec = sizeof(T) == 8 ? 0 : (b16 ? 2 : 1);
+  const size_t es2 = b16 ? sizeof(uint16_t) : sizeof(T);  // element of the chunk stores / T2
   const size_t ny = (size_t)p.rlp * 16 * p.rrp;
   if (!p.err.p) p.err.resize_zero(sizeof(int), s);
   int* err = p.err.as<int>();
   if (!p.lw) E.bs_t1.ensure(sizeof(T) * std::max<long long>(p.n1, 1));
-  E.bs_t2.ensure(sizeof(T) * std::max<long long>(p.n2, 1));
+  E.bs_t2.ensure(es2 * std::max<long long>(p.n2, 1));
   E.bs_t3.ensure(sizeof(T) * std::max<long long>(p.n3, 1));
   E.bs_part.ensure(sizeof(T) * (size_t)std::max(p.nslots, 1) * TILE * TILE);
   if (E.bs_zero_serial != p.serial || E.bs_zero_prec != prec) {
     // entries that are never written: T1's where the left sector alpha' - d_A does not
     // exist; with the left operator T2's of the rows (B, s1') without operator entries
-    if (p.lw) fill(E.bs_t2.p, sizeof(T) * p.n2, s);
+    if (p.lw) fill(E.bs_t2.p, es2 * p.n2, s);
     else fill(E.bs_t1.p, sizeof(T) * p.n1, s);
     E.bs_zero_serial = p.serial;
     E.bs_zero_prec = prec;
   }
   const T* lwop = nullptr;
-  if (p.lw) {
+  auto bf16_copy = [&](const DevMem& from, DevMem& to, long long n, bool& have) {
+    if (have) return;
+    to.ensure(sizeof(uint16_t) * (size_t)std::max<long long>(n, 1));
+    if (n > 0) {
+      const int nb = (int)std::min<long long>((n + 255) / 256, 8192);
+      hipLaunchKernelGGL((to_bf16_kernel<double>), dim3(nb), dim3(256), 0, s, from.as<double>(), to.as<uint16_t>(), n);
+      BSCHECK(hipGetLastError());
+    }
+    have = true;
+  };
+  if (b16) {
+    if (!p.have_lw64) throw std::logic_error("block-sparse product: left operator not formed");
+    bf16_copy(p.lw64, p.lw16, p.nlw, p.have_lw16);
+    bf16_copy(p.wr64, p.wr16, p.nwr, p.have_wr16);
+    E.bs_x16.ensure(sizeof(uint16_t) * ny);
+    const int nb = (int)std::min<long long>(((long long)ny + 255) / 256, 8192);
+    hipLaunchKernelGGL((to_bf16_kernel<T>), dim3(nb), dim3(256), 0, s, x, E.bs_x16.as<uint16_t>(), (long long)ny);
+    BSCHECK(hipGetLastError());
+  } else if (p.lw) {
     if (!p.have_lw64) throw std::logic_error("block-sparse product: left operator not formed");
     if (sizeof(T) == 8) {
       lwop = reinterpret_cast<const T*>(p.lw64.p);
@@ -1874,7 +1952,7 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
     E.bs_gg_ptr[2] = E.bs_tmp.p;
   }
   const T* wrop = nullptr;
-  if (p.wr) {
+  if (p.wr && !b16) {
     if (sizeof(T) == 8) {
       wrop = reinterpret_cast<const T*>(p.wr64.p);
     } else {
@@ -1895,18 +1973,27 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   E.kt_begin();
   if (p.lw) {
     if (p.nlw_tiles > 0) {
-      if (p.wr)
-        hipLaunchKernelGGL((lw_gemm_kernel<T, 2>), dim3(p.nlw_tiles), dim3(256), 0, s, p.lw_tiles.as<BsLwTile>(),
+      if (b16) {
+        if constexpr (sizeof(T) == 4)
+          hipLaunchKernelGGL((lw_gemm_kernel<float, 2, uint16_t>), dim3(p.nlw_tiles), dim3(256), 0, s,
+                             p.lw_tiles.as<BsLwTile>(), p.lw_groups.as<BsLwGroup>(), p.lw_blocks.as<BsLwBlock>(),
+                             p.lw_krow.as<int>(), p.lw_col.as<int2>(), p.lw16.as<uint16_t>(), p.nlw,
+                             E.bs_x16.as<uint16_t>(), (long long)ny, (const long long*)nullptr,
+                             (const long long*)nullptr, p.nbeta.as<int>(), p.nbe, p.lw_zeta.as<BsZeta>(),
+                             p.lw_kc.as<int>(), E.bs_t2.as<uint16_t>(), p.n2, err);
+      } else if (p.wr) {
+        hipLaunchKernelGGL((lw_gemm_kernel<T, 2, T>), dim3(p.nlw_tiles), dim3(256), 0, s, p.lw_tiles.as<BsLwTile>(),
                            p.lw_groups.as<BsLwGroup>(), p.lw_blocks.as<BsLwBlock>(),
                            p.lw_krow.as<int>(), p.lw_col.as<int2>(), lwop, p.nlw, x, (long long)ny, (const long long*)nullptr,
                            (const long long*)nullptr, p.nbeta.as<int>(), p.nbe, p.lw_zeta.as<BsZeta>(),
-                           p.lw_kc.as<int>(), bf16_t3 ? 1 : 0, E.bs_t2.as<T>(), p.n2, err);
-      else
-        hipLaunchKernelGGL((lw_gemm_kernel<T, 1>), dim3(p.nlw_tiles), dim3(256), 0, s, p.lw_tiles.as<BsLwTile>(),
+                           p.lw_kc.as<int>(), E.bs_t2.as<T>(), p.n2, err);
+      } else {
+        hipLaunchKernelGGL((lw_gemm_kernel<T, 1, T>), dim3(p.nlw_tiles), dim3(256), 0, s, p.lw_tiles.as<BsLwTile>(),
                            p.lw_groups.as<BsLwGroup>(), p.lw_blocks.as<BsLwBlock>(),
                            p.lw_krow.as<int>(), p.lw_col.as<int2>(), lwop, p.nlw, x, (long long)ny, p.rowbase2.as<long long>(),
                            p.specoff.as<long long>(), p.nbeta.as<int>(), p.nbe, (const BsZeta*)nullptr,
-                           (const int*)nullptr, 0, E.bs_t2.as<T>(), p.n2, err);
+                           (const int*)nullptr, E.bs_t2.as<T>(), p.n2, err);
+      }
       BSCHECK(hipGetLastError());
       E.kt_mark(0);
     }
@@ -1925,8 +2012,13 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
   if (!p.wr) run_mix<T, 2>(E, p, p.m2, E.bs_t2.as<T>(), p.n2, E.bs_t3.as<T>(), p.n3, err, bf16_t3, gg2, E.bs_gg2);
   if (p.ntiles4 > 0) {
     // panels x WR (right operator), or stage-4 panels x stacked R
-    if (p.wr)
-      hipLaunchKernelGGL((panel_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.wr_ptiles.as<BsPTile>(),
+    if (b16) {
+      if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((panel_mfma_kernel<float, uint16_t>), dim3(p.ntiles4), dim3(256), 0, s,
+                           p.wr_ptiles.as<BsPTile>(), p.wr_k8.as<BsK8>(), p.nk8, E.bs_t2.as<uint16_t>(), p.n2,
+                           p.wr16.as<uint16_t>(), p.nwr, E.bs_part.as<float>(), err);
+    } else if (p.wr)
+      hipLaunchKernelGGL((panel_mfma_kernel<T, T>), dim3(p.ntiles4), dim3(256), 0, s, p.wr_ptiles.as<BsPTile>(),
                          p.wr_k8.as<BsK8>(), p.nk8, E.bs_t2.as<T>(), p.n2, wrop, p.nwr, E.bs_part.as<T>(), err);
     else
       hipLaunchKernelGGL((stage4_mfma_kernel<T>), dim3(p.ntiles4), dim3(256), 0, s, p.tiles4.as<BsS4Tile>(),
@@ -1939,12 +2031,12 @@ void bs_apply(Engine& E, BsPlan& p, const T* L, const T* R, const T* Rt, const T
     E.kt_mark(8);
   }
   if (check) bs_check(E, p);
-  const double el = (double)sizeof(T);
+  const double el = (double)sizeof(T), elw = b16 ? (double)sizeof(uint16_t) : el;
   const double fl[Engine::KT_SLOTS] = {p.lw ? p.flops_lw : p.flops1, p.m1.fl_light, p.m1.fl_heavy, 0.0,
                                        p.m2.fl_light, p.m2.fl_heavy, 0.0, p.flops4, 0.0};
-  const double by[Engine::KT_SLOTS] = {el * (p.lw ? p.bytes_lw : p.bytes1), el * p.m1.el_light, el * p.m1.el_heavy,
+  const double by[Engine::KT_SLOTS] = {elw * (p.lw ? p.bytes_lw : p.bytes1), el * p.m1.el_light, el * p.m1.el_heavy,
                                        el * p.m1.el_scatter,
-                                       el * p.m2.el_light, el * p.m2.el_heavy, el * p.m2.el_scatter, el * p.bytes4,
+                                       el * p.m2.el_light, el * p.m2.el_heavy, el * p.m2.el_scatter, elw * p.bytes4,
                                        el * p.el_red};
   E.kt_end(fl, by);
 }
@@ -2011,6 +2103,7 @@ void bs_lw_build(Engine& E, BsPlan& p, const double* L, long long nL, const doub
   }
   p.have_lw64 = true;
   p.lw32_state = p.wr32_state = 0;
+  p.have_lw16 = p.have_wr16 = false;
   bs_check(E, p);
 }
 

@@ -2383,7 +2383,8 @@ static void bs_launch(Engine& E, Window& w, const double* x, double* y, int prec
 static std::array<const void*, 16> bs_workspace_sig(const Engine& E) {
   std::array<const void*, 16> s{};
   int i = 0;
-  for (const DevMem* m : {&E.bs_t1, &E.bs_t2, &E.bs_t3, &E.bs_part, &E.bs_tmp, &E.wlow_x, &E.wlow_y}) s[i++] = m->p;
+  for (const DevMem* m : {&E.bs_t1, &E.bs_t2, &E.bs_t3, &E.bs_part, &E.bs_tmp, &E.wlow_x, &E.wlow_y, &E.bs_x16})
+    s[i++] = m->p;
   for (int b = 0; b < 4; ++b) {
     s[i++] = E.bs_gg1[b].p;
     s[i++] = E.bs_gg2[b].p;

@@ -317,6 +317,7 @@ class Engine {
   DevMem envq_o, envq_i;  // charge arrays of the environment-update mix
   // block-sparse product workspaces (T1, T2, stage-4 panels, split-K partials)
   DevMem bs_t1, bs_t2, bs_t3, bs_part, bs_tmp;
+  DevMem bs_x16;  // x in bfloat16 for the bf16 products with both operators precontracted
   DevMem bs_gg1[4], bs_gg2[4];  // heavy-row GEMM descriptors per row bucket (16, 32, 64, larger)
   DevMem be_t1, be_panel, be_up, be_tmp;  // block-sparse environment-update workspaces
   long long bs_zero_serial = -1;  // plan whose never-written T1 entries are zero in bs_t1
