@@ -67,7 +67,9 @@ typedef struct tt_opts {
   int dav_maxsub;     /* subspace size before a restart */
   double coarse_eps;  /* keep overlap eigenvalues >= coarse_eps * max (rank-deficient branch) */
   int matvec_prec;    /* tt_prec of the effective-Hamiltonian product */
-  int refine_fp64;    /* 1: after a low-precision solve, continue with FP64 products to dav_tol */
+  int refine_fp64;    /* 1: after the low-precision phase, an FP64-anchored refinement to
+                         dav_tol: residuals from FP64 products, correction directions from
+                         low-precision ones (FP32; a bfloat16 solve continues in FP32) */
   double lowprec_tol; /* with refine_fp64: the low-precision phase ends when the residual is
                          <= lowprec_tol * |Ritz value| (or has stalled at the rounding floor
                          of the low-precision product); FP64 products then reach dav_tol */
@@ -150,8 +152,9 @@ typedef struct tt_opts {
                          matrix-core GEMM, then W2 and R as for 0.  2 (default) = the left and
                          the right operator WR[B] = sum_C W2[B, s2', s2, C] R_C: every product
                          is one GEMM with LW into panels of the bra's left half and one split-K
-                         GEMM of the panels with WR.  Same contraction, different summation
-                         order. */
+                         GEMM of the panels with WR; with matvec_prec = TT_BF16, LW, WR, x and
+                         the panels are held in bfloat16 (FP32 arithmetic).  Same contraction,
+                         different summation order. */
 } tt_opts;
 
 #define TT_MAX_SUB 64
