@@ -96,3 +96,11 @@ def test_heff_energy_grad_rejects_bad_operands():
     W2 = (np.array([0, 4]), np.array([1, 2]), np.zeros((2, 4, 4)))  # right channel 2 >= RC = 2
     with pytest.raises(ValueError, match="channel index"):
         api.heff_energy_grad(None, L, _w(3, 5), W2, R, x.double(), 5)
+
+
+@pytest.mark.parametrize("kw", [{"precontract": 3}, {"precontract": -1}, {"functional": "min"}])
+def test_context_rejects_bad_options_before_create(kw):
+    """Options the binding can check itself are refused before tt_create runs, so no
+    device is touched (the library is only loaded)."""
+    with pytest.raises(ValueError):
+        api.Context(chi=16, **kw)
