@@ -155,6 +155,14 @@ typedef struct tt_opts {
                          GEMM of the panels with WR; with matvec_prec = TT_BF16, LW, WR, x and
                          the panels are held in bfloat16 (FP32 arithmetic).  Same contraction,
                          different summation order. */
+  int svd_blocked;    /* sector SVDs: 1 (default) = a block of at least 48 columns (and rows +
+                         columns <= 1152) is factored by the blocked Jacobi kernels, spread
+                         over many workgroups (two 8-column blocks of its columns per
+                         workgroup); 0 = never; 2 = every block of 2 or more columns they take;
+                         3 and 4 = as 2 with the rows per lane of their pair kernels pinned (0:
+                         loops over LDS, 9: registers) instead of chosen by size (2-4 are for
+                         testing).  Same rotations, visited in another order: results agree to
+                         rounding. */
 } tt_opts;
 
 #define TT_MAX_SUB 64

@@ -35,7 +35,7 @@ class Opts(C.Structure):
         ("worker_alloc_limit", C.c_longlong), ("stream", C.c_void_p), ("dev_alloc", C.c_void_p),
         ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p), ("coarse_k", C.c_int),
         ("one_site", C.c_int), ("functional", C.c_int), ("coarse_krylov", C.c_int),
-        ("graph_products", C.c_int), ("precontract", C.c_int),
+        ("graph_products", C.c_int), ("precontract", C.c_int), ("svd_blocked", C.c_int),
     ]
 
 

@@ -40,7 +40,7 @@ class Context:
                  tie_rel=1e-10, matvec_prec="f64", refine_fp64=False, lowprec_tol=1e-5, device=0, qn_skip=True,
                  sub_workers=0, mix_stage=0, svd_lds=True, worker_alloc_limit=0, stream=None, torch_alloc=False,
                  coarse_k=1, one_site=False, functional="eig", coarse_krylov=False,
-                 graph_products=False, precontract=2):
+                 graph_products=False, precontract=2, svd_blocked=1):
         """``stream``: a torch.cuda.Stream (or raw stream handle) every call runs on;
         ``torch_alloc``: take every device block of the context from the torch caching
         allocator (tt_opts.dev_alloc/dev_free) instead of the library's own pools;
@@ -51,7 +51,10 @@ class Context:
         ``graph_products``: replay the block-sparse products from HIP graphs;
         ``precontract``: 2 = contract each environment with its site's MPO tensor once
         per window (every product is then two GEMMs), 1 = only the left one, 0 = none
-        (every product forms L x and applies both site tensors as sparse mixes)."""
+        (every product forms L x and applies both site tensors as sparse mixes);
+        ``svd_blocked``: 1 = sector SVD blocks of 48 or more columns by the blocked Jacobi
+        kernels (many workgroups per block), 0 = never, 2 = every block they take, 3 and 4 =
+        as 2 with the pair kernels' rows per lane pinned to 0 (loops) or 9 (for testing)."""
         self.lib = L.load()
         o = L.Opts()
         self.lib.tt_default_opts(C.byref(o))
@@ -82,6 +85,9 @@ class Context:
         if precontract not in (0, 1, 2):
             raise ValueError("precontract must be 0, 1 or 2")
         o.precontract = int(precontract)
+        if svd_blocked not in (0, 1, 2, 3, 4):
+            raise ValueError("svd_blocked must be 0, 1, 2, 3 or 4")
+        o.svd_blocked = int(svd_blocked)
         self.functional = functional
         if stream is not None:
             o.stream = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))

@@ -157,6 +157,7 @@ void tt_default_opts(tt_opts* o) {
   o->coarse_krylov = 0;
   o->graph_products = 0;
   o->precontract = 2;
+  o->svd_blocked = 1;
 }
 
 int tt_create(const tt_opts* opts, void** out) {
@@ -171,7 +172,8 @@ int tt_create(const tt_opts* opts, void** out) {
       opts->functional > 1 ||
       (opts->functional == 1 && (opts->matvec_prec != TT_F64 || !opts->qn_skip || opts->coarse_k != 1)) ||
       opts->coarse_krylov < 0 || opts->coarse_krylov > 1 || (opts->coarse_krylov && opts->functional != 0) ||
-      opts->graph_products < 0 || opts->graph_products > 1 || opts->precontract < 0 || opts->precontract > 2)
+      opts->graph_products < 0 || opts->graph_products > 1 || opts->precontract < 0 || opts->precontract > 2 ||
+      opts->svd_blocked < 0 || opts->svd_blocked > 4)
     return TT_EINVAL;
   try {
     *out = new Engine(*opts);

@@ -1268,6 +1268,8 @@ struct SvdOut {
 // sweep limit of the Jacobi SVD kernel (a sweep visits every column pair once; the
 // factorisations here converge in about ten)
 constexpr int kJacobiSweeps = 40;
+// blocks of at least this many columns go to the blocked Jacobi kernels (svd_blocked = 1)
+constexpr int kJacobiBlockedMinN = 48;
 
 class SectorSVD {
  public:
@@ -1352,16 +1354,22 @@ class SectorSVD {
     };
     const double tb0 = E.verbose ? E.now() : 0.0;
     {
-      std::vector<SvdJob> jobs[2];
+      // the one-workgroup kernel (global memory, or LDS where the block fits) or, for wide
+      // blocks, the blocked kernels
+      auto blocked = [&](int m, int n) {
+        const int mode = E.opts.svd_blocked;
+        return mode != 0 && n >= (mode == 1 ? kJacobiBlockedMinN : 2) && jacobi_blocked_fits(m, n);
+      };
+      std::vector<SvdJob> jobs[2], bjobs;
       long long vtot = 0;
       for (size_t bi = 0; bi < bins.size(); ++bi) {
         if (bins[bi].N > kJacobiMaxN) continue;
         for (int t : *members[bi]) {
           const long long m = std::max(blocks[t].m, blocks[t].n), n = std::min(blocks[t].m, blocks[t].n);
-          if (!E.opts.svd_lds || (m + n) * n > kJacobiLds) vtot += n * n;
+          if (blocked((int)m, (int)n) || !E.opts.svd_lds || (m + n) * n > kJacobiLds) vtot += n * n;
         }
       }
-      DevMem Vs, jdev[2];
+      DevMem Vs, jdev[2], bdev, bscr;
       Vs.ensure(sizeof(double) * (size_t)std::max<long long>(vtot, 1));
       long long voff = 0;
       for (size_t bi = 0; bi < bins.size(); ++bi) {
@@ -1371,11 +1379,14 @@ class SectorSVD {
         for (int i = 0; i < B.cnt; ++i) {
           const Blk& b = blocks[mem[i]];
           const int m = std::max(b.m, b.n), n = std::min(b.m, b.n);
-          const int in_lds = E.opts.svd_lds && (long long)(m + n) * n <= kJacobiLds ? 1 : 0;
-          jobs[in_lds].push_back(SvdJob{B.A.as<double>() + (size_t)B.M * B.N * i, in_lds ? nullptr : Vs.as<double>() + voff,
-                                        B.U.as<double>() + (size_t)B.M * B.K * i, B.S.as<double>() + (size_t)B.K * i,
-                                        B.Vt.as<double>() + (size_t)B.K * B.N * i, B.info.as<int>() + i, m, n, B.M, B.M,
-                                        B.K, 0});
+          const bool bj = blocked(m, n);
+          const int in_lds = !bj && E.opts.svd_lds && (long long)(m + n) * n <= kJacobiLds ? 1 : 0;
+          const SvdJob job{B.A.as<double>() + (size_t)B.M * B.N * i, in_lds ? nullptr : Vs.as<double>() + voff,
+                           B.U.as<double>() + (size_t)B.M * B.K * i, B.S.as<double>() + (size_t)B.K * i,
+                           B.Vt.as<double>() + (size_t)B.K * B.N * i, B.info.as<int>() + i, m, n, B.M, B.M,
+                           B.K, 0};
+          if (bj) bjobs.push_back(job);
+          else jobs[in_lds].push_back(job);
           if (!in_lds) voff += (long long)n * n;
         }
       }
@@ -1384,6 +1395,18 @@ class SectorSVD {
           upload(jdev[v], jobs[v].data(), jobs[v].size() * sizeof(SvdJob), E.stream);
           jacobi_svd(jdev[v].as<SvdJob>(), (int)jobs[v].size(), kJacobiSweeps, v == 1, E.stream);
         }
+      if (!bjobs.empty()) {
+        const size_t nj = bjobs.size();
+        upload(bdev, bjobs.data(), nj * sizeof(SvdJob), E.stream);
+        // per matrix: |A|_F^2 (double), rotation count and active index (int)
+        bscr.ensure(nj * (sizeof(double) + 2 * sizeof(int)));
+        double* fro2 = bscr.as<double>();
+        int* rot = reinterpret_cast<int*>(fro2 + nj);
+        // svd_blocked 3 and 4 pin the pair kernels' rows per lane (loops over LDS, or 9)
+        const int rows = E.opts.svd_blocked == 3 ? 0 : E.opts.svd_blocked == 4 ? 9 : -1;
+        jacobi_svd_blocked(bdev.as<SvdJob>(), bjobs.data(), (int)nj, rows, kJacobiSweeps, fro2, rot, rot + nj,
+                           E.stream);
+      }
       for (Bin& B : bins)
         if (B.N > kJacobiMaxN) factor(B, E.blas);
       HC(hipStreamSynchronize(E.stream));

@@ -122,6 +122,17 @@ struct SvdJob { double* A; double* V; double* U; double* S; double* Vt; int* inf
 constexpr int kJacobiMaxN = 1024;
 constexpr int kJacobiLds = 17920;  // doubles of A and V held in LDS (140 KiB)
 void jacobi_svd(const SvdJob* jobs, int njobs, int max_sweeps, bool in_lds, hipStream_t s);
+// Blocked Jacobi SVD of the same matrices (same outputs and info), each spread over many
+// workgroups: columns in blocks of 8, one launch for the pairs inside the blocks and one per
+// round of a tournament over the blocks, every column pair once per sweep; the host reads
+// the per-matrix rotation counts after each sweep (one stream synchronisation per sweep).
+// V must be an N x N scratch.  jacobi_blocked_fits: the launches can hold two blocks'
+// columns of A and V in LDS (M + N <= 1152).  rows: rows per lane the pair kernels hold in
+// registers (4 or 9; 0 = loops over LDS; -1 = the fewest that cover the largest M).  fro2,
+// rot and act_dev are device scratch of njobs entries each.
+bool jacobi_blocked_fits(int M, int N);
+void jacobi_svd_blocked(const SvdJob* jobs, const SvdJob* jobs_host, int njobs, int rows, int max_sweeps,
+                        double* fro2, int* rot, int* act_dev, hipStream_t s);
 // out[n] = sum_i c[i] V[i*ldv+n]  (c on device)
 void lincomb(const double* V, size_t ldv, int m, const double* c_dev, double* out, size_t n, hipStream_t s);
 void convert_f64_f32(const double* a, float* b, size_t n, hipStream_t s);

@@ -1067,6 +1067,370 @@ void jacobi_svd(const SvdJob* jobs, int njobs, int max_sweeps, bool in_lds, hipS
   HIPCHECK(hipGetLastError());
 }
 
+// Blocked one-sided Jacobi SVD: one tall matrix spread over many workgroups.  The N
+// columns are cut into blocks of BJ = 8 (the last one narrower).  A sweep is one launch in
+// which each workgroup rotates the pairs inside one block (the tournament of the
+// one-workgroup kernel over the block's columns), then one launch per round of a
+// round-robin tournament over the blocks, in which each workgroup takes two blocks and
+// visits their cross pairs in BJ rounds: column k of the first block against column
+// (k + t) mod BJ of the second in round t, so a round's pairs are disjoint and each
+// of the BJ waves takes one.  Every column pair is thus visited once per sweep, with the
+// pair test, rotation and zero-column rule of the one-workgroup kernel; the host ends a
+// matrix's sweeps after one without a rotation.  A launch holds its blocks' columns of A
+// and V in LDS.  A round's latency (the dot products, three wave sums and the rotation's
+// square roots and divisions, one after another) bounds these kernels, not the issue
+// rate: blocks of 8 columns (two waves per SIMD) measured faster than blocks of 16.
+constexpr int kBJLds = 18432;  // doubles of LDS per workgroup (144 KiB)
+constexpr int kBJ = 8;         // columns per block
+bool jacobi_blocked_fits(int M, int N) {
+  return N >= 2 && M >= N && N <= kJacobiMaxN && (long long)(M + N) * 2 * kBJ <= kBJLds;
+}
+// rotation of a column pair: cosine and sine from |a_p|^2, |a_q|^2 and a_p . a_q
+__device__ __forceinline__ void bj_coeffs(double al, double be, double ga, double& c, double& sn) {
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  sn = c * t;
+}
+// one Jacobi rotation of the column pair (p, q) held in LDS, by one wave (wave-uniform
+// arguments); returns whether it rotated.  With R > 0 (M, N <= 64 R) a lane loads its R
+// rows of both columns at once; R = 0 walks the columns in a loop (same sums: a lane adds
+// its rows in increasing order either way).
+template <int R>
+__device__ __forceinline__ bool bj_rotate(double* ap, double* aq, double* vp, double* vq, int M, int N, int lane,
+                                          double tol, double zero2) {
+  double al = 0.0, be = 0.0, ga = 0.0, c, sn;
+  if constexpr (R > 0) {
+    double x[R], y[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = lane + 64 * u;
+      x[u] = i < M ? ap[i] : 0.0;
+      y[u] = i < M ? aq[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      al = fma(x[u], x[u], al);
+      be = fma(y[u], y[u], be);
+      ga = fma(x[u], y[u], ga);
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    if (!(fabs(ga) > tol * sqrt(al * be)) || !(fmin(al, be) > zero2)) return false;
+    bj_coeffs(al, be, ga, c, sn);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = lane + 64 * u;
+      if (i < M) {
+        ap[i] = c * x[u] - sn * y[u];
+        aq[i] = sn * x[u] + c * y[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = lane + 64 * u;
+      x[u] = i < N ? vp[i] : 0.0;
+      y[u] = i < N ? vq[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = lane + 64 * u;
+      if (i < N) {
+        vp[i] = c * x[u] - sn * y[u];
+        vq[i] = sn * x[u] + c * y[u];
+      }
+    }
+  } else {
+    for (int i = lane; i < M; i += 64) {
+      const double x = ap[i], y = aq[i];
+      al = fma(x, x, al);
+      be = fma(y, y, be);
+      ga = fma(x, y, ga);
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    if (!(fabs(ga) > tol * sqrt(al * be)) || !(fmin(al, be) > zero2)) return false;
+    bj_coeffs(al, be, ga, c, sn);
+    for (int i = lane; i < M; i += 64) {
+      const double x = ap[i], y = aq[i];
+      ap[i] = c * x - sn * y;
+      aq[i] = sn * x + c * y;
+    }
+    for (int i = lane; i < N; i += 64) {
+      const double x = vp[i], y = vq[i];
+      vp[i] = c * x - sn * y;
+      vq[i] = sn * x + c * y;
+    }
+  }
+  return true;
+}
+// V = identity and |A|_F^2 of each matrix (one workgroup per matrix)
+__global__ __launch_bounds__(64 * JW) void bj_init_kernel(const SvdJob* __restrict__ jobs, double* __restrict__ fro2) {
+  const SvdJob J = jobs[blockIdx.x];
+  const int M = J.M, N = J.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NT = 64 * JW;
+  for (long long i = tid; i < (long long)N * N; i += NT) J.V[i] = (i % (N + 1) == 0) ? 1.0 : 0.0;
+  __shared__ double fro_w[JW];
+  double s2 = 0.0;
+  for (int j = wave; j < N; j += JW)
+    for (int i = lane; i < M; i += 64) s2 = fma(J.A[(size_t)j * J.lda + i], J.A[(size_t)j * J.lda + i], s2);
+  s2 = wave_sum(s2);
+  if (lane == 0) fro_w[wave] = s2;
+  __syncthreads();
+  if (tid == 0) {
+    double f = 0.0;
+    for (int w = 0; w < JW; ++w) f += fro_w[w];
+    fro2[blockIdx.x] = f;
+  }
+}
+// pairs inside block blockIdx.x of matrix act[blockIdx.y]
+template <int BJ, int R>
+__global__ __launch_bounds__(64 * BJ) void bj_within_kernel(const SvdJob* __restrict__ jobs,
+                                                            const int* __restrict__ act,
+                                                            const double* __restrict__ fro2, int* __restrict__ rot) {
+  __shared__ double lds[kBJLds / 2];
+  const int jb = act[blockIdx.y];
+  const SvdJob J = jobs[jb];
+  const int M = J.M, N = J.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NT = 64 * BJ;
+  const int c0 = blockIdx.x * BJ;
+  if (c0 >= N) return;
+  const int w = min(BJ, N - c0);
+  double* a = lds;                   // column k of the block at a + k M
+  double* v = lds + (size_t)M * BJ;  // its column of V at v + k N
+  for (int i = tid; i < M * w; i += NT) a[i] = J.A[(size_t)(c0 + i / M) * J.lda + i % M];
+  for (int i = tid; i < N * w; i += NT) v[i] = J.V[(size_t)(c0 + i / N) * N + i % N];
+  __syncthreads();
+  const double tol = 2.2e-16 * (double)M, zero2 = tol * tol * fro2[jb];
+  const int wp = w + (w & 1);
+  bool any = false;
+  for (int r = 0; r < wp - 1; ++r) {
+    if (wave < wp / 2) {
+      int p, q;
+      if (wave == 0) { p = wp - 1; q = r; }
+      else { p = (r + wave) % (wp - 1); q = (r - wave + wp - 1) % (wp - 1); }
+      if (p < w && q < w)
+        any |= bj_rotate<R>(a + (size_t)p * M, a + (size_t)q * M, v + (size_t)p * N, v + (size_t)q * N, M, N, lane,
+                            tol, zero2);
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < M * w; i += NT) J.A[(size_t)(c0 + i / M) * J.lda + i % M] = a[i];
+  for (int i = tid; i < N * w; i += NT) J.V[(size_t)(c0 + i / N) * N + i % N] = v[i];
+  if (any && lane == 0) atomicAdd(rot + jb, 1);
+}
+// cross pairs of the two blocks that workgroup blockIdx.x meets in tournament round r.
+// Wave k pairs column k of the first block with column (k + t) mod BJ of the second in
+// round t.  With R > 0 (M, N <= 64 R) wave k keeps its column of the first block and of V
+// in registers for the whole launch and only the second block is held in LDS; with R = 0
+// both blocks are held in LDS.
+template <int BJ, int R>
+__global__ __launch_bounds__(64 * BJ) void bj_cross_kernel(const SvdJob* __restrict__ jobs,
+                                                           const int* __restrict__ act,
+                                                           const double* __restrict__ fro2, int* __restrict__ rot,
+                                                           int r) {
+  __shared__ double lds[R > 0 ? kBJLds / 2 : kBJLds];
+  const int jb = act[blockIdx.y];
+  const SvdJob J = jobs[jb];
+  const int M = J.M, N = J.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NT = 64 * BJ;
+  const int nb = (N + BJ - 1) / BJ, nbp = nb + (nb & 1);
+  const int k = blockIdx.x;
+  if (r >= nbp - 1 || k >= nbp / 2) return;
+  int bi, bk;
+  if (k == 0) { bi = nbp - 1; bk = r; }
+  else { bi = (r + k) % (nbp - 1); bk = (r - k + nbp - 1) % (nbp - 1); }
+  if (bi >= nb || bk >= nb) return;
+  const int ci = bi * BJ, ck = bk * BJ, wi = min(BJ, N - ci), wk = min(BJ, N - ck);
+  const double tol = 2.2e-16 * (double)M, zero2 = tol * tol * fro2[jb];
+  bool any = false;
+  if constexpr (R > 0) {
+    // the second block's columns at a + j M and v + j N (j < wk)
+    double* a = lds;
+    double* v = lds + (size_t)M * BJ;
+    for (int i = tid; i < M * wk; i += NT) a[i] = J.A[(size_t)(ck + i / M) * J.lda + i % M];
+    for (int i = tid; i < N * wk; i += NT) v[i] = J.V[(size_t)(ck + i / N) * N + i % N];
+    const int p = wave;
+    const bool own = p < wi;
+    double* gA = J.A + (size_t)(ci + (own ? p : 0)) * J.lda;
+    double* gV = J.V + (size_t)(ci + (own ? p : 0)) * N;
+    double x[R], vx[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = lane + 64 * u;
+      x[u] = own && i < M ? gA[i] : 0.0;
+      vx[u] = own && i < N ? gV[i] : 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < BJ; ++t) {
+      const int q = (p + t) % BJ;
+      if (own && q < wk) {
+        double* ay = a + (size_t)q * M;
+        double* vy = v + (size_t)q * N;
+        double y[R];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int i = lane + 64 * u;
+          y[u] = i < M ? ay[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          al = fma(x[u], x[u], al);
+          be = fma(y[u], y[u], be);
+          ga = fma(x[u], y[u], ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (fabs(ga) > tol * sqrt(al * be) && fmin(al, be) > zero2) {
+          double c, sn;
+          bj_coeffs(al, be, ga, c, sn);
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const int i = lane + 64 * u;
+            const double xn = c * x[u] - sn * y[u], yn = sn * x[u] + c * y[u];
+            x[u] = xn;
+            if (i < M) ay[i] = yn;
+          }
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const int i = lane + 64 * u;
+            y[u] = i < N ? vy[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const int i = lane + 64 * u;
+            const double xn = c * vx[u] - sn * y[u], yn = sn * vx[u] + c * y[u];
+            vx[u] = xn;
+            if (i < N) vy[i] = yn;
+          }
+          any = true;
+        }
+      }
+      __syncthreads();
+    }
+    if (own) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int i = lane + 64 * u;
+        if (i < M) gA[i] = x[u];
+        if (i < N) gV[i] = vx[u];
+      }
+    }
+    for (int i = tid; i < M * wk; i += NT) J.A[(size_t)(ck + i / M) * J.lda + i % M] = a[i];
+    for (int i = tid; i < N * wk; i += NT) J.V[(size_t)(ck + i / N) * N + i % N] = v[i];
+  } else {
+    // columns of the first block at a + j M (j < wi), of the second at a + (BJ + j) M; V alike
+    double* a = lds;
+    double* v = lds + (size_t)M * 2 * BJ;
+    for (int i = tid; i < M * wi; i += NT) a[i] = J.A[(size_t)(ci + i / M) * J.lda + i % M];
+    for (int i = tid; i < M * wk; i += NT) a[(size_t)M * BJ + i] = J.A[(size_t)(ck + i / M) * J.lda + i % M];
+    for (int i = tid; i < N * wi; i += NT) v[i] = J.V[(size_t)(ci + i / N) * N + i % N];
+    for (int i = tid; i < N * wk; i += NT) v[(size_t)N * BJ + i] = J.V[(size_t)(ck + i / N) * N + i % N];
+    __syncthreads();
+    for (int t = 0; t < BJ; ++t) {
+      const int p = wave, q = (wave + t) % BJ;
+      if (p < wi && q < wk)
+        any |= bj_rotate<0>(a + (size_t)p * M, a + (size_t)(BJ + q) * M, v + (size_t)p * N,
+                            v + (size_t)(BJ + q) * N, M, N, lane, tol, zero2);
+      __syncthreads();
+    }
+    for (int i = tid; i < M * wi; i += NT) J.A[(size_t)(ci + i / M) * J.lda + i % M] = a[i];
+    for (int i = tid; i < M * wk; i += NT) J.A[(size_t)(ck + i / M) * J.lda + i % M] = a[(size_t)M * BJ + i];
+    for (int i = tid; i < N * wi; i += NT) J.V[(size_t)(ci + i / N) * N + i % N] = v[i];
+    for (int i = tid; i < N * wk; i += NT) J.V[(size_t)(ck + i / N) * N + i % N] = v[(size_t)N * BJ + i];
+  }
+  if (any && lane == 0) atomicAdd(rot + jb, 1);
+}
+// one sweep: the pairs inside every block, then the tournament rounds over the blocks
+template <int BJ, int R>
+void bj_sweep(const SvdJob* jobs, const int* act, const double* fro2, int* rot, int nbmax, int nact, hipStream_t s) {
+  const int nbpmax = nbmax + (nbmax & 1);
+  hipLaunchKernelGGL((bj_within_kernel<BJ, R>), dim3(nbmax, nact), dim3(64 * BJ), 0, s, jobs, act, fro2, rot);
+  HIPCHECK(hipGetLastError());
+  for (int r = 0; r < nbpmax - 1; ++r) {
+    hipLaunchKernelGGL((bj_cross_kernel<BJ, R>), dim3(nbpmax / 2, nact), dim3(64 * BJ), 0, s, jobs, act, fro2, rot,
+                       r);
+    HIPCHECK(hipGetLastError());
+  }
+}
+// singular triplets in decreasing order of sigma (ties by column index), as the
+// one-workgroup kernel writes them; info = 1 for a matrix still rotating in its last sweep
+__global__ __launch_bounds__(64 * JW) void bj_finish_kernel(const SvdJob* __restrict__ jobs,
+                                                            const int* __restrict__ rot) {
+  __shared__ double sig[kJacobiMaxN];
+  __shared__ int rnk[kJacobiMaxN];
+  const SvdJob J = jobs[blockIdx.x];
+  const int M = J.M, N = J.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NT = 64 * JW;
+  for (int j = wave; j < N; j += JW) {
+    const double* aj = J.A + (size_t)j * J.lda;
+    double s2 = 0.0;
+    for (int i = lane; i < M; i += 64) s2 = fma(aj[i], aj[i], s2);
+    s2 = wave_sum(s2);
+    if (lane == 0) sig[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < N; j += NT) {
+    const double sj = sig[j];
+    int rk = 0;
+    for (int i = 0; i < N; ++i) rk += (sig[i] > sj) || (sig[i] == sj && i < j);
+    rnk[j] = rk;
+  }
+  __syncthreads();
+  for (int j = wave; j < N; j += JW) {
+    const int rk = rnk[j];
+    const double sj = sig[j];
+    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    const double* aj = J.A + (size_t)j * J.lda;
+    double* uo = J.U + (size_t)rk * J.ldu;
+    for (int i = lane; i < M; i += 64) uo[i] = aj[i] * inv;
+    const double* vj = J.V + (size_t)j * N;
+    for (int i = lane; i < N; i += 64) J.Vt[rk + (size_t)i * J.ldvt] = vj[i];
+    if (lane == 0) J.S[rk] = sj;
+  }
+  if (tid == 0) J.info[0] = rot[blockIdx.x] > 0 ? 1 : 0;
+}
+void jacobi_svd_blocked(const SvdJob* jobs, const SvdJob* jobs_host, int njobs, int rows, int max_sweeps,
+                        double* fro2, int* rot, int* act_dev, hipStream_t s) {
+  if (njobs <= 0) return;
+  int nbmax = 1, mmax = 1;
+  for (int j = 0; j < njobs; ++j) {
+    const SvdJob& J = jobs_host[j];
+    if (!jacobi_blocked_fits(J.M, J.N) || J.V == nullptr || J.lda < J.M || J.ldu < J.M || J.ldvt < J.N)
+      throw std::logic_error("jacobi_svd_blocked: a matrix shape the blocked kernels do not take");
+    nbmax = std::max(nbmax, (J.N + kBJ - 1) / kBJ);
+    mmax = std::max(mmax, J.M);
+  }
+  // rows per lane held in registers by the pair kernels: 4 or 9, or 0 (loops over LDS)
+  const int R = rows >= 0 ? rows : mmax <= 256 ? 4 : mmax <= 576 ? 9 : 0;
+  if ((R != 0 && R != 4 && R != 9) || (R != 0 && mmax > 64 * R))
+    throw std::logic_error("jacobi_svd_blocked: rows per lane must be 0, 4 or 9 and cover every matrix");
+  hipLaunchKernelGGL(bj_init_kernel, dim3(njobs), dim3(64 * JW), 0, s, jobs, fro2);
+  HIPCHECK(hipGetLastError());
+  std::vector<int> act(njobs), rh(njobs);
+  for (int j = 0; j < njobs; ++j) act[j] = j;
+  for (int sweep = 0; sweep < max_sweeps && !act.empty(); ++sweep) {
+    const int nact = (int)act.size();
+    HIPCHECK(hipMemcpyAsync(act_dev, act.data(), sizeof(int) * nact, hipMemcpyHostToDevice, s));
+    fill(rot, sizeof(int) * njobs, s);
+    if (R == 4) bj_sweep<kBJ, 4>(jobs, act_dev, fro2, rot, nbmax, nact, s);
+    else if (R == 9) bj_sweep<kBJ, 9>(jobs, act_dev, fro2, rot, nbmax, nact, s);
+    else bj_sweep<kBJ, 0>(jobs, act_dev, fro2, rot, nbmax, nact, s);
+    HIPCHECK(hipMemcpyAsync(rh.data(), rot, sizeof(int) * njobs, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    std::vector<int> next;
+    for (int j : act)
+      if (rh[j] > 0) next.push_back(j);
+    act.swap(next);
+  }
+  hipLaunchKernelGGL(bj_finish_kernel, dim3(njobs), dim3(64 * JW), 0, s, jobs, rot);
+  HIPCHECK(hipGetLastError());
+}
+
 // out = sum_i c[i] V_i; with VEC = 2 a thread produces two adjacent entries from 16-byte
 // loads, and the vectors are taken four at a time so that four loads are in flight
 template <int VEC>

@@ -98,7 +98,7 @@ def test_heff_energy_grad_rejects_bad_operands():
         api.heff_energy_grad(None, L, _w(3, 5), W2, R, x.double(), 5)
 
 
-@pytest.mark.parametrize("kw", [{"precontract": 3}, {"precontract": -1}, {"functional": "min"}])
+@pytest.mark.parametrize("kw", [{"precontract": 3}, {"precontract": -1}, {"functional": "min"}, {"svd_blocked": 5}])
 def test_context_rejects_bad_options_before_create(kw):
     """Options the binding can check itself are refused before tt_create runs, so no
     device is touched (the library is only loaded)."""

@@ -48,6 +48,7 @@ def test_default_options_and_invalid_create():
     ("worker_alloc_limit", -1), ("coarse_k", 0), ("coarse_k", 9), ("one_site", 2), ("one_site", -1),
     ("functional", 2), ("functional", -1), ("coarse_krylov", 2), ("coarse_krylov", -1),
     ("graph_products", 2), ("graph_products", -1), ("precontract", 3), ("precontract", -1),
+    ("svd_blocked", 5), ("svd_blocked", -1),
 ])
 def test_create_rejects_each_invalid_option(field, value):
     """tt_create validates the options before it touches the device: every value outside
@@ -57,7 +58,7 @@ def test_create_rejects_each_invalid_option(field, value):
     lib = _lib.load()
     o = _lib.Opts()
     lib.tt_default_opts(C.byref(o))
-    assert (o.mix_stage, o.svd_lds, o.worker_alloc_limit, o.sub_workers) == (0, 1, 0, 0)
+    assert (o.mix_stage, o.svd_lds, o.worker_alloc_limit, o.sub_workers, o.svd_blocked) == (0, 1, 0, 0, 1)
     setattr(o, field, value)
     h = C.c_void_p()
     assert lib.tt_create(C.byref(o), C.byref(h)) == _lib.TT_EINVAL
