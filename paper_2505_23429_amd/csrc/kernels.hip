@@ -1566,33 +1566,37 @@ void scatter_factors(const ScatterBlk* blks, int nblk, const int* rows, const in
 }
 
 // ---------------------------------------------------------------------------
-// Householder LQ of sector blocks (one 256-thread workgroup per block): the
+// Householder LQ of sector blocks (one workgroup of HHW waves per block): the
 // unblocked algorithm, each reflector from one row, the trailing rows updated
 // one wave per row; then Q formed by applying the reflectors in reverse order
 // to the first k rows of the identity.  The block lives in global memory (L2),
-// the current reflector in LDS.
+// the current reflector in LDS.  A row's update waits on its loads from L2, so the
+// rows a workgroup updates at once set the pace: 16 waves rather than 4.
 // ---------------------------------------------------------------------------
 __device__ inline double hh_wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
+constexpr int HHW = 16;       // waves per workgroup
+constexpr int HHT = 64 * HHW;  // threads per workgroup
 __device__ inline double hh_block_sum(double x, double* red) {
   x = hh_wave_sum(x);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
   __syncthreads();
-  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  double t = 0.0;
+  for (int w = 0; w < HHW; ++w) t += red[w];
   __syncthreads();
   return t;
 }
-__global__ __launch_bounds__(256) void householder_lq_kernel(const double* __restrict__ W, long long sWr, long long sWc,
+__global__ __launch_bounds__(HHT) void householder_lq_kernel(const double* __restrict__ W, long long sWr, long long sWc,
                                                              const int* __restrict__ rows, const int* __restrict__ cols,
                                                              const int* __restrict__ nmap, const HhBlk* __restrict__ blks,
                                                              double* __restrict__ ws,
                                                              double* __restrict__ Lout, long long sLr, long long sLc,
                                                              double* __restrict__ Qout, long long sQr, long long sQc) {
   __shared__ double v[HH_MAXN];
-  __shared__ double red[4];
+  __shared__ double red[HHW];
   const HhBlk b = blks[blockIdx.x];
   const int m = b.m, n = b.n, k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1602,7 +1606,7 @@ __global__ __launch_bounds__(256) void householder_lq_kernel(const double* __res
   const int* rw = rows + b.roff;
   const int* cl = cols + b.coff;
   const int* nw = nmap + b.noff;
-  for (long long e = tid; e < (long long)m * n; e += 256) {
+  for (long long e = tid; e < (long long)m * n; e += HHT) {
     const int r = (int)(e / n), c = (int)(e - (long long)r * n);
     A[e] = W[(long long)rw[r] * sWr + (long long)cl[c] * sWc];
   }
@@ -1611,7 +1615,7 @@ __global__ __launch_bounds__(256) void householder_lq_kernel(const double* __res
   for (int i = 0; i < k; ++i) {
     double* Ai = A + (long long)i * n;
     double part = 0.0;
-    for (int c = i + 1 + tid; c < n; c += 256) part += Ai[c] * Ai[c];
+    for (int c = i + 1 + tid; c < n; c += HHT) part += Ai[c] * Ai[c];
     const double sig = hh_block_sum(part, red);
     const double alpha = Ai[i];
     double t = 0.0, beta = alpha, scl = 0.0;
@@ -1620,10 +1624,10 @@ __global__ __launch_bounds__(256) void householder_lq_kernel(const double* __res
       t = (beta - alpha) / beta;
       scl = 1.0 / (alpha - beta);
     }
-    for (int c = i + tid; c < n; c += 256) v[c - i] = c == i ? 1.0 : Ai[c] * scl;
+    for (int c = i + tid; c < n; c += HHT) v[c - i] = c == i ? 1.0 : Ai[c] * scl;
     __syncthreads();
     if (t != 0.0) {
-      for (int r = i + 1 + wv; r < m; r += 4) {
+      for (int r = i + 1 + wv; r < m; r += HHW) {
         double* Ar = A + (long long)r * n;
         double d = 0.0;
         for (int c = i + lane; c < n; c += 64) d += Ar[c] * v[c - i];
@@ -1631,7 +1635,7 @@ __global__ __launch_bounds__(256) void householder_lq_kernel(const double* __res
         for (int c = i + lane; c < n; c += 64) Ar[c] -= d * v[c - i];
       }
     }
-    for (int c = i + 1 + tid; c < n; c += 256) Ai[c] = v[c - i];
+    for (int c = i + 1 + tid; c < n; c += HHT) Ai[c] = v[c - i];
     if (tid == 0) {
       Ai[i] = beta;
       tau[i] = t;
@@ -1639,7 +1643,7 @@ __global__ __launch_bounds__(256) void householder_lq_kernel(const double* __res
     __syncthreads();
   }
   // Q = [I_k 0] H(k-1) ... H(0): when H(i) is applied only rows >= i and columns >= i change
-  for (long long e = tid; e < (long long)k * n; e += 256) {
+  for (long long e = tid; e < (long long)k * n; e += HHT) {
     const int r = (int)(e / n), c = (int)(e - (long long)r * n);
     X[e] = r == c ? 1.0 : 0.0;
   }
@@ -1648,9 +1652,9 @@ __global__ __launch_bounds__(256) void householder_lq_kernel(const double* __res
     const double t = tau[i];
     if (t == 0.0) continue;
     const double* Ai = A + (long long)i * n;
-    for (int c = i + tid; c < n; c += 256) v[c - i] = c == i ? 1.0 : Ai[c];
+    for (int c = i + tid; c < n; c += HHT) v[c - i] = c == i ? 1.0 : Ai[c];
     __syncthreads();
-    for (int r = i + wv; r < k; r += 4) {
+    for (int r = i + wv; r < k; r += HHW) {
       double* Xr = X + (long long)r * n;
       double d = 0.0;
       for (int c = i + lane; c < n; c += 64) d += Xr[c] * v[c - i];
@@ -1659,11 +1663,11 @@ __global__ __launch_bounds__(256) void householder_lq_kernel(const double* __res
     }
     __syncthreads();
   }
-  for (long long e = tid; e < (long long)m * k; e += 256) {
+  for (long long e = tid; e < (long long)m * k; e += HHT) {
     const int r = (int)(e / k), c = (int)(e - (long long)r * k);
     if (c <= r) Lout[(long long)rw[r] * sLr + (long long)nw[c] * sLc] = A[(long long)r * n + c];
   }
-  for (long long e = tid; e < (long long)k * n; e += 256) {
+  for (long long e = tid; e < (long long)k * n; e += HHT) {
     const int r = (int)(e / n), c = (int)(e - (long long)r * n);
     Qout[(long long)nw[r] * sQr + (long long)cl[c] * sQc] = X[e];
   }
@@ -1672,7 +1676,7 @@ void householder_lq(const double* W, long long sWr, long long sWc, const int* ro
                     const HhBlk* blks, int nblk, double* ws, double* Lout, long long sLr, long long sLc, double* Qout,
                     long long sQr, long long sQc, hipStream_t s) {
   if (nblk <= 0) return;
-  hipLaunchKernelGGL(householder_lq_kernel, dim3(nblk), dim3(256), 0, s, W, sWr, sWc, rows, cols, nmap, blks, ws, Lout,
+  hipLaunchKernelGGL(householder_lq_kernel, dim3(nblk), dim3(HHT), 0, s, W, sWr, sWc, rows, cols, nmap, blks, ws, Lout,
                      sLr, sLc, Qout, sQr, sQc);
   HIPCHECK(hipGetLastError());
 }
