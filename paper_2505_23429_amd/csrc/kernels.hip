@@ -1411,6 +1411,7 @@ void jacobi_svd_blocked(const SvdJob* jobs, const SvdJob* jobs_host, int njobs, 
     throw std::logic_error("jacobi_svd_blocked: rows per lane must be 0, 4 or 9 and cover every matrix");
   hipLaunchKernelGGL(bj_init_kernel, dim3(njobs), dim3(64 * JW), 0, s, jobs, fro2);
   HIPCHECK(hipGetLastError());
+  fill(rot, sizeof(int) * njobs, s);  // read by the finish kernel even if no sweep runs
   std::vector<int> act(njobs), rh(njobs);
   for (int j = 0; j < njobs; ++j) act[j] = j;
   for (int sweep = 0; sweep < max_sweeps && !act.empty(); ++sweep) {
