@@ -1077,7 +1077,8 @@ void jacobi_svd(const SvdJob* jobs, int njobs, int max_sweeps, bool in_lds, hipS
 // of the BJ waves takes one.  Every column pair is thus visited once per sweep, with the
 // pair test, rotation and zero-column rule of the one-workgroup kernel; the host ends a
 // matrix's sweeps after one without a rotation.  A launch holds its blocks' columns of A
-// and V in LDS.  A round's latency (the dot products, three wave sums and the rotation's
+// and V in LDS, or in a cross launch the first block's in registers (one column per
+// wave) and only the second block's in LDS.  A round's latency (the dot products, three wave sums and the rotation's
 // square roots and divisions, one after another) bounds these kernels, not the issue
 // rate: blocks of 8 columns (two waves per SIMD) measured faster than blocks of 16.
 constexpr int kBJLds = 18432;  // doubles of LDS per workgroup (144 KiB)
